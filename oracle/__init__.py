@@ -1,0 +1,258 @@
+"""ctypes wrapper of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY. The oracle is the plain reference the GPU grasp
+step is checked against. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import it; the product path never does. It shares no
+code with the GPU library and imports nothing from it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC = [os.path.join(_HERE, "oracle.cpp")]
+
+OBJ_GRID, OBJ_SPHERE, OBJ_PLANE, OBJ_BOX = 0, 1, 2, 3
+M_SIMS = 7
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with g++ (C++17, OpenMP)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", LIB_PATH + ".tmp"] + SRC
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class _Hand(C.Structure):
+    _fields_ = [("n_links", C.c_int), ("parent", C.POINTER(C.c_int)),
+                ("joint_origin", C.POINTER(C.c_double)), ("joint_axis", C.POINTER(C.c_double)),
+                ("q_low", C.POINTER(C.c_double)), ("q_up", C.POINTER(C.c_double)),
+                ("n_contacts", C.c_int), ("contact_local", C.POINTER(C.c_double)),
+                ("contact_link", C.POINTER(C.c_int))]
+
+
+class _Obj(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("lo", C.c_double * 3), ("h", C.c_double),
+                ("values", C.POINTER(C.c_float)), ("center", C.c_double * 3), ("radius", C.c_double),
+                ("half", C.c_double * 3), ("normal", C.c_double * 3), ("offset", C.c_double),
+                ("inertia_over_mass", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("v0", C.c_double), ("K", C.c_int), ("omega", C.c_double),
+                ("r_dil", C.c_double), ("alpha_leak", C.c_double), ("w_stable", C.c_double),
+                ("w_pen", C.c_double), ("w_range", C.c_double), ("w_limit", C.c_double),
+                ("w_min", C.c_double)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Step parameters (Sec. III-C, Sec. IV-A; unstated values are readings)."""
+    dt: float = 1e-3
+    v0: float = 1.0
+    K: int = 1
+    omega: float = 1.0
+    r_dil: float = 0.0
+    alpha_leak: float = 0.1
+    w_stable: float = 1.0
+    w_pen: float = 1e4
+    w_range: float = 1e-2
+    w_limit: float = 1.0
+    w_min: float = 1e-12
+
+    def _c(self):
+        return _Params(self.dt, self.v0, self.K, self.omega, self.r_dil, self.alpha_leak,
+                       self.w_stable, self.w_pen, self.w_range, self.w_limit, self.w_min)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+        hp, op, pp = C.POINTER(_Hand), C.POINTER(_Obj), C.POINTER(_Params)
+        L.oracle_fk.argtypes = [hp, C.c_int, dp, dp, dp]
+        L.oracle_sample.argtypes = [op, C.c_int, dp, dp, dp, dp, dp]
+        L.oracle_inertia_over_mass.argtypes = [op]
+        L.oracle_inertia_over_mass.restype = C.c_double
+        L.oracle_step.argtypes = [hp, op, pp, C.c_int, dp, dp, dp, dp, dp, C.c_int]
+        L.oracle_trace.argtypes = [hp, op, pp, dp, dp, dp, dp]
+        L.oracle_fd_grad.argtypes = [hp, op, pp, C.c_int, dp, C.c_double, dp, ip, C.c_int]
+        L.oracle_adam.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, C.c_double]
+        L.oracle_rank.argtypes = [C.c_int, dp, ip]
+        L.oracle_optimize.argtypes = [hp, op, pp, C.c_int, dp, C.c_int, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, ip, dp,
+                                      C.c_int]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+class Hand:
+    """Oracle view of a hand (any object with the synth.Hand fields)."""
+
+    def __init__(self, h):
+        self.parent = np.ascontiguousarray(h.parent, dtype=np.int32)
+        self.joint_origin = _d(h.joint_origin)
+        self.joint_axis = _d(h.joint_axis)
+        self.q_low = _d(h.q_low)
+        self.q_up = _d(h.q_up)
+        self.contact_local = _d(h.contact_local)
+        self.contact_link = np.ascontiguousarray(h.contact_link, dtype=np.int32)
+        self.n_links = int(self.parent.shape[0])
+        self.n_dof = 6 + self.n_links - 1
+        self.n_contacts = int(self.contact_link.shape[0])
+        self.c = _Hand(self.n_links, _ptr(self.parent, C.c_int), _ptr(self.joint_origin),
+                       _ptr(self.joint_axis), _ptr(self.q_low), _ptr(self.q_up), self.n_contacts,
+                       _ptr(self.contact_local), _ptr(self.contact_link, C.c_int))
+
+
+class Obj:
+    """Oracle view of an object: a grid (synth.Grid) or an analytic shape."""
+
+    def __init__(self, grid=None, kind=OBJ_GRID, center=(0, 0, 0), radius=0.0, half=(0, 0, 0),
+                 normal=(0, 0, 1), offset=0.0, inertia_over_mass=0.0):
+        self.values = None
+        c = _Obj()
+        c.kind = kind
+        if grid is not None:
+            self.values = np.ascontiguousarray(grid.values, dtype=np.float32)
+            c.kind = OBJ_GRID
+            c.n = int(grid.n)
+            c.lo = (C.c_double * 3)(*[float(x) for x in grid.lo])
+            c.h = float(grid.h)
+            c.values = _ptr(self.values, C.c_float)
+        c.center = (C.c_double * 3)(*center)
+        c.radius = radius
+        c.half = (C.c_double * 3)(*half)
+        n = np.asarray(normal, dtype=np.float64)
+        n = n / np.linalg.norm(n)
+        c.normal = (C.c_double * 3)(*n)
+        c.offset = offset
+        c.inertia_over_mass = inertia_over_mass
+        self.c = c
+
+    def inertia_over_mass(self) -> float:
+        return float(lib().oracle_inertia_over_mass(C.byref(self.c)))
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"{name} failed with code {rc}")
+
+
+def fk(hand: Hand, q, frames: bool = False):
+    q = _d(q).reshape(-1, hand.n_dof)
+    B = q.shape[0]
+    p = np.zeros((B, hand.n_contacts, 3))
+    T = np.zeros((B, hand.n_links, 12)) if frames else None
+    _check(lib().oracle_fk(C.byref(hand.c), B, _ptr(q), _ptr(p), _ptr(T)), "oracle_fk")
+    return (p, T) if frames else p
+
+
+def sample(obj: Obj, r, hess: bool = False):
+    r = _d(r).reshape(-1, 3)
+    n = r.shape[0]
+    phi = np.zeros(n)
+    g = np.zeros((n, 3))
+    H = np.zeros((n, 3, 3)) if hess else None
+    margin = np.zeros(n)
+    _check(lib().oracle_sample(C.byref(obj.c), n, _ptr(r), _ptr(phi), _ptr(g), _ptr(H), _ptr(margin)),
+           "oracle_sample")
+    return (phi, g, H, margin) if hess else (phi, g, margin)
+
+
+def step(hand: Hand, obj: Obj, prm: Params, q, grad: bool = True, margins: bool = False,
+         threads: int = 0):
+    q = _d(q).reshape(-1, hand.n_dof)
+    B = q.shape[0]
+    loss = np.zeros(B)
+    terms = np.zeros((B, 4))
+    g = np.zeros((B, hand.n_dof)) if grad else None
+    mg = np.zeros((B, 2)) if margins else None
+    pc = prm._c()
+    _check(lib().oracle_step(C.byref(hand.c), C.byref(obj.c), C.byref(pc), B, _ptr(q), _ptr(loss),
+                             _ptr(terms), _ptr(g), _ptr(mg), threads), "oracle_step")
+    out = {"loss": loss, "terms": terms}
+    if grad:
+        out["grad"] = g
+    if margins:
+        out["min_abs_d"] = mg[:, 0]
+        out["min_face"] = mg[:, 1]
+    return out
+
+
+def trace(hand: Hand, obj: Obj, prm: Params, q, samples: bool = True):
+    q = _d(q).reshape(hand.n_dof)
+    poses = np.zeros((M_SIMS, prm.K + 1, 6))
+    smp = np.zeros((M_SIMS, prm.K, hand.n_contacts, 6)) if samples else None
+    p = np.zeros((hand.n_contacts, 3))
+    pc = prm._c()
+    _check(lib().oracle_trace(C.byref(hand.c), C.byref(obj.c), C.byref(pc), _ptr(q), _ptr(poses),
+                              _ptr(smp), _ptr(p)), "oracle_trace")
+    return {"poses": poses, "samples": smp, "p": p}
+
+
+def fd_grad(hand: Hand, obj: Obj, prm: Params, q, h: float = 1e-4, threads: int = 0):
+    q = _d(q).reshape(-1, hand.n_dof)
+    B = q.shape[0]
+    g = np.zeros((B, hand.n_dof))
+    ex = np.zeros((B, hand.n_dof), np.int32)
+    pc = prm._c()
+    _check(lib().oracle_fd_grad(C.byref(hand.c), C.byref(obj.c), C.byref(pc), B, _ptr(q), h, _ptr(g),
+                                _ptr(ex, C.c_int), threads), "oracle_fd_grad")
+    return g, ex.astype(bool)
+
+
+def adam(q, m, v, g, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    q, m, v, g = (_d(a).copy() for a in (q, m, v, g))
+    _check(lib().oracle_adam(q.size, _ptr(q), _ptr(m), _ptr(v), _ptr(g), t, lr, b1, b2, eps), "oracle_adam")
+    return q, m, v
+
+
+def rank(loss):
+    loss = _d(loss)
+    r = np.zeros(loss.shape[0], np.int32)
+    _check(lib().oracle_rank(loss.shape[0], _ptr(loss), _ptr(r, C.c_int)), "oracle_rank")
+    return r
+
+
+def optimize(hand: Hand, obj: Obj, prm: Params, q0, T: int, r0: float = 0.01, lr=1e-3, b1=0.9,
+             b2=0.999, eps=1e-8, use_gd=False, history=False, threads: int = 0):
+    q = _d(q0).reshape(-1, hand.n_dof).copy()
+    B = q.shape[0]
+    fl = np.zeros(B)
+    ft = np.zeros((B, 4))
+    rk = np.zeros(B, np.int32)
+    hist = np.zeros((T, B)) if history else None
+    pc = prm._c()
+    _check(lib().oracle_optimize(C.byref(hand.c), C.byref(obj.c), C.byref(pc), B, _ptr(q), T, r0, lr, b1,
+                                 b2, eps, int(use_gd), _ptr(fl), _ptr(ft), _ptr(rk, C.c_int), _ptr(hist),
+                                 threads), "oracle_optimize")
+    out = {"q": q, "loss": fl, "terms": ft, "rank": rk}
+    if history:
+        out["history"] = hist
+    return out

@@ -1,0 +1,716 @@
+// FP64 CPU oracle for the grid-SDF Fast-Grasp'D grasp step.
+//
+// TEST INFRASTRUCTURE ONLY: the plain reference the GPU path is checked
+// against. Shares no code with the GPU library. Every step follows the paper's
+// order and notation (Fast-Grasp'D, Sec. III-C "Position-based dynamics" and
+// Sec. IV-A "Gradient-based grasp optimization"); the grid sampler follows the
+// trilinear grid SDF the paper describes for its predecessor (Sec. III-A).
+//
+// Gradients: forward-mode dual numbers, one tangent per degree of freedom.
+// The leaky contact gradient (Sec. III-C, "Leaky gradient") is a derivative
+// rule on C = max(0, -d): its tangent is -dd where d < 0 and -alpha dd
+// elsewhere, while its value is unchanged.
+//
+// Readings where the paper is silent (each listed in the design notes):
+//  * object representation: dense grid, trilinear value, analytic gradient;
+//    outside the box, clamp to the box and add the Euclidean distance to it;
+//  * constraints are projected as a Jacobi sum (all corrections computed at
+//    the same pose, then added with relaxation omega), K times in one step;
+//  * mass matrix: isotropic, mass 1 and inertia I/m; orientation is a
+//    rotation vector updated additively; gravity is absent;
+//  * the test velocities are +-v0 along each axis plus zero; angular 0;
+//  * penetration loss L_pen = 1/2 sum C^2 at the rest pose; L_range over
+//    finger joints; L_limit summed over finger joints;
+//  * derivatives at kinks (|.| at 0, max at 0, clamp) are 0; at d = 0 the
+//    leaky branch is taken.
+#include "oracle_api.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+constexpr int kSims = 7;  // M = 7 simulations (Sec. IV-A)
+
+// ---------------------------------------------------------------------------
+// scalars: double, or a dual number carrying N tangents
+// ---------------------------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0.0) { std::fill(d, d + N, 0.0); }
+  Dual(double x) : v(x) { std::fill(d, d + N, 0.0); }  // NOLINT: implicit constant
+};
+
+template <int N> inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r;
+}
+template <int N> inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v * b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+template <int N> inline Dual<N> operator*(double a, const Dual<N>& b) {
+  Dual<N> r; r.v = a * b.v; for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator*(const Dual<N>& b, double a) { return a * b; }
+template <int N> inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v / b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+  return r;
+}
+template <int N> inline Dual<N> operator/(const Dual<N>& a, double b) {
+  Dual<N> r; r.v = a.v / b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / b; return r;
+}
+template <int N> inline Dual<N> operator+(const Dual<N>& a, double b) { Dual<N> r = a; r.v += b; return r; }
+template <int N> inline Dual<N> operator+(double b, const Dual<N>& a) { Dual<N> r = a; r.v += b; return r; }
+template <int N> inline Dual<N> operator-(const Dual<N>& a, double b) { Dual<N> r = a; r.v -= b; return r; }
+template <int N> inline Dual<N> operator-(double b, const Dual<N>& a) { return -(a - b); }
+template <int N> inline Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
+
+template <int N> inline double val(const Dual<N>& a) { return a.v; }
+inline double val(double a) { return a; }
+
+template <int N> inline Dual<N> sqrt_(const Dual<N>& a) {
+  Dual<N> r; r.v = std::sqrt(a.v);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * r.v);
+  return r;
+}
+inline double sqrt_(double a) { return std::sqrt(a); }
+template <int N> inline Dual<N> sin_(const Dual<N>& a) {
+  Dual<N> r; r.v = std::sin(a.v); double c = std::cos(a.v);
+  for (int i = 0; i < N; ++i) r.d[i] = c * a.d[i];
+  return r;
+}
+inline double sin_(double a) { return std::sin(a); }
+template <int N> inline Dual<N> cos_(const Dual<N>& a) {
+  Dual<N> r; r.v = std::cos(a.v); double s = std::sin(a.v);
+  for (int i = 0; i < N; ++i) r.d[i] = -s * a.d[i];
+  return r;
+}
+inline double cos_(double a) { return std::cos(a); }
+
+// A value with a zero tangent.
+template <class S> inline S konst(double x) { return S(x); }
+
+// Euclidean norm, derivative 0 at the origin (a kink).
+template <class S> inline S norm3(const S v[3]) {
+  S s = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  if (val(s) > 0.0) return sqrt_(s);
+  return konst<S>(0.0);
+}
+
+// ---------------------------------------------------------------------------
+// rigid transforms (row-major 3x3 rotation + translation)
+// ---------------------------------------------------------------------------
+template <class S>
+struct Xf {
+  S R[9];
+  S t[3];
+};
+
+template <class S> Xf<S> identity_xf() {
+  Xf<S> x;
+  for (int i = 0; i < 9; ++i) x.R[i] = konst<S>((i % 4 == 0) ? 1.0 : 0.0);
+  for (int i = 0; i < 3; ++i) x.t[i] = konst<S>(0.0);
+  return x;
+}
+
+template <class S> Xf<S> compose(const Xf<S>& A, const Xf<S>& B) {
+  Xf<S> C;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      C.R[3 * i + j] = A.R[3 * i] * B.R[j] + A.R[3 * i + 1] * B.R[3 + j] + A.R[3 * i + 2] * B.R[6 + j];
+    C.t[i] = A.R[3 * i] * B.t[0] + A.R[3 * i + 1] * B.t[1] + A.R[3 * i + 2] * B.t[2] + A.t[i];
+  }
+  return C;
+}
+
+template <class S> void apply_xf(const Xf<S>& A, const double c[3], S out[3]) {
+  for (int i = 0; i < 3; ++i)
+    out[i] = A.R[3 * i] * c[0] + A.R[3 * i + 1] * c[1] + A.R[3 * i + 2] * c[2] + A.t[i];
+}
+
+// Rotation by angle a about a fixed unit axis k: I + sin a [k]x + (1 - cos a) [k]x^2.
+template <class S> Xf<S> axis_angle(const double k[3], const S& a) {
+  S s = sin_(a), c1 = 1.0 - cos_(a);
+  double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  Xf<S> x;
+  for (int i = 0; i < 9; ++i) x.R[i] = ((i % 4 == 0) ? 1.0 : 0.0) + s * K[i] + c1 * K2[i];
+  for (int i = 0; i < 3; ++i) x.t[i] = konst<S>(0.0);
+  return x;
+}
+
+template <class S> Xf<S> const_xf(const double* m12) {
+  Xf<S> x;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) x.R[3 * i + j] = konst<S>(m12[4 * i + j]);
+    x.t[i] = konst<S>(m12[4 * i + 3]);
+  }
+  return x;
+}
+
+// Forward kinematics p = FK(q) (Sec. III-C): the wrist is
+// Trans(q0, q1, q2) Rz(q3) Ry(q4) Rx(q5); each further link l hangs from its
+// parent through the fixed joint origin O_l and a revolute joint about axis_l
+// by angle q_{5+l}: T_l = T_parent O_l Rot(axis_l, q_{5+l}).
+template <class S> void forward_kinematics(const ohand& h, const S* q, std::vector<Xf<S>>& T) {
+  const int L = h.n_links;
+  T.assign(L, identity_xf<S>());
+  const double ez[3] = {0, 0, 1}, ey[3] = {0, 1, 0}, ex[3] = {1, 0, 0};
+  Xf<S> root = identity_xf<S>();
+  for (int i = 0; i < 3; ++i) root.t[i] = q[i];
+  root = compose(root, axis_angle(ez, q[3]));
+  root = compose(root, axis_angle(ey, q[4]));
+  root = compose(root, axis_angle(ex, q[5]));
+  T[0] = root;
+  for (int l = 1; l < L; ++l) {
+    Xf<S> J = compose(T[h.parent[l]], const_xf<S>(h.joint_origin + 12 * l));
+    T[l] = compose(J, axis_angle(h.joint_axis + 3 * l, q[5 + l]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// object SDF sample: value and gradient at a point in the object frame
+// ---------------------------------------------------------------------------
+struct SampleInfo {
+  int cell[3] = {0, 0, 0};
+  int clamped[3] = {0, 0, 0};
+  double face_margin = 1e30;
+};
+
+// Grid: trilinear interpolation of a vertex-centred grid (Sec. III-A). Per
+// axis u = (r - lo)/h, clamped to [0, N-1]; the cell is floor(u) capped at
+// N-2 and f = u - cell. The gradient is the analytic derivative of the
+// trilinear blend, zero along clamped axes. Outside the box the distance e
+// from the clamped point is added to the value and e/|e| to the gradient.
+template <class S>
+void sample_grid(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
+  const int N = o.n;
+  S f[3];
+  S e[3];
+  int c[3];
+  bool cl[3];
+  double margin = 1e30;
+  for (int a = 0; a < 3; ++a) {
+    S u = (r[a] - o.lo[a]) / o.h;
+    S ub;
+    if (val(u) < 0.0) { ub = konst<S>(0.0); cl[a] = true; }
+    else if (val(u) > N - 1.0) { ub = konst<S>(N - 1.0); cl[a] = true; }
+    else { ub = u; cl[a] = false; }
+    c[a] = std::min(static_cast<int>(std::floor(val(ub))), N - 2);
+    f[a] = ub - static_cast<double>(c[a]);
+    e[a] = cl[a] ? (u - ub) * o.h : konst<S>(0.0);
+    double k = std::min(std::max(std::round(val(u)), 0.0), N - 1.0);
+    margin = std::min(margin, std::fabs(val(u) - k));
+  }
+  auto V = [&](int i, int j, int k) -> double {
+    return static_cast<double>(o.values[(static_cast<int64_t>(c[2] + k) * N + (c[1] + j)) * N + (c[0] + i)]);
+  };
+  S w0[3], w1[3];
+  for (int a = 0; a < 3; ++a) { w1[a] = f[a]; w0[a] = 1.0 - f[a]; }
+  S val_tri = konst<S>(0.0);
+  S df[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+  for (int k = 0; k < 2; ++k)
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) {
+        double v = V(i, j, k);
+        const S& wx = i ? w1[0] : w0[0];
+        const S& wy = j ? w1[1] : w0[1];
+        const S& wz = k ? w1[2] : w0[2];
+        val_tri += v * (wx * wy * wz);
+        df[0] += (i ? v : -v) * (wy * wz);
+        df[1] += (j ? v : -v) * (wx * wz);
+        df[2] += (k ? v : -v) * (wx * wy);
+      }
+  for (int a = 0; a < 3; ++a) n[a] = cl[a] ? konst<S>(0.0) : df[a] / o.h;
+  phi = val_tri;
+  S ne = norm3(e);
+  if (val(ne) > 0.0) {
+    phi = phi + ne;
+    for (int a = 0; a < 3; ++a) n[a] = n[a] + e[a] / ne;
+  }
+  if (info) {
+    for (int a = 0; a < 3; ++a) { info->cell[a] = c[a]; info->clamped[a] = cl[a]; }
+    info->face_margin = margin;
+  }
+}
+
+template <class S>
+void sample_object(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
+  switch (o.kind) {
+    case OBJ_GRID:
+      sample_grid(o, r, phi, n, info);
+      return;
+    case OBJ_SPHERE: {
+      S a[3];
+      for (int i = 0; i < 3; ++i) a[i] = r[i] - o.center[i];
+      S l = norm3(a);
+      phi = l - o.radius;
+      for (int i = 0; i < 3; ++i) n[i] = (val(l) > 0.0) ? a[i] / l : konst<S>(0.0);
+      return;
+    }
+    case OBJ_PLANE: {
+      phi = r[0] * o.normal[0] + r[1] * o.normal[1] + r[2] * o.normal[2] - o.offset;
+      for (int i = 0; i < 3; ++i) n[i] = konst<S>(o.normal[i]);
+      return;
+    }
+    case OBJ_BOX: {
+      // exact box SDF: outside |max(q, 0)|, inside max_i q_i, q = |y| - half
+      S y[3], qv[3];
+      double sg[3];
+      for (int i = 0; i < 3; ++i) {
+        y[i] = r[i] - o.center[i];
+        sg[i] = val(y[i]) >= 0.0 ? 1.0 : -1.0;
+        qv[i] = sg[i] * y[i] - o.half[i];
+      }
+      S pos[3];
+      bool any_out = false;
+      for (int i = 0; i < 3; ++i) {
+        pos[i] = val(qv[i]) > 0.0 ? qv[i] : konst<S>(0.0);
+        any_out = any_out || val(qv[i]) > 0.0;
+      }
+      if (any_out) {
+        S l = norm3(pos);
+        phi = l;
+        for (int i = 0; i < 3; ++i) n[i] = sg[i] * (pos[i] / l);
+      } else {
+        int m = 0;
+        for (int i = 1; i < 3; ++i) if (val(qv[i]) > val(qv[m])) m = i;
+        phi = qv[m];
+        for (int i = 0; i < 3; ++i) n[i] = konst<S>(i == m ? sg[i] : 0.0);
+      }
+      return;
+    }
+    default:
+      phi = konst<S>(0.0);
+      for (int i = 0; i < 3; ++i) n[i] = konst<S>(0.0);
+  }
+}
+
+double inertia_over_mass(const oobject& o) {
+  if (o.inertia_over_mass > 0.0 || o.kind != OBJ_GRID) return o.inertia_over_mass;
+  // isotropic inertia of a uniform ball of the object's volume:
+  // I/m = 2/5 R_eq^2, V = h^3 * (number of vertices with phi < 0)
+  const int64_t n3 = static_cast<int64_t>(o.n) * o.n * o.n;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n3; ++i) cnt += (o.values[i] < 0.0f) ? 1 : 0;
+  const double V = o.h * o.h * o.h * static_cast<double>(cnt);
+  const double Req = std::cbrt(3.0 * V / (4.0 * M_PI));
+  return 0.4 * Req * Req;
+}
+
+// ---------------------------------------------------------------------------
+// object orientation: rotation vector theta, R = I + A [t]x + B [t]x^2 with
+// A = sin|t|/|t| and B = (1 - cos|t|)/|t|^2; power series below |t| = 0.5
+// ---------------------------------------------------------------------------
+template <class S> void rotation_matrix(const S th[3], S R[9]) {
+  S s = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+  S A, B;
+  if (val(s) < 0.25) {
+    S s2 = s * s, s3 = s2 * s, s4 = s3 * s;
+    A = 1.0 - s / 6.0 + s2 / 120.0 - s3 / 5040.0 + s4 / 362880.0;
+    B = 0.5 - s / 24.0 + s2 / 720.0 - s3 / 40320.0 + s4 / 3628800.0;
+  } else {
+    S t = sqrt_(s);
+    A = sin_(t) / t;
+    B = (1.0 - cos_(t)) / s;
+  }
+  S K[9] = {konst<S>(0.0), -th[2], th[1], th[2], konst<S>(0.0), -th[0], -th[1], th[0], konst<S>(0.0)};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      S k2 = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+      R[3 * i + j] = ((i == j) ? 1.0 : 0.0) + A * K[3 * i + j] + B * k2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one grasp step for one candidate
+// ---------------------------------------------------------------------------
+struct Trace {
+  double* poses = nullptr;    // [M][K+1][6]
+  double* samples = nullptr;  // [M][K][Nc][6]
+  double* p_world = nullptr;  // [Nc][3]
+  double min_abs_d = 1e30;
+  double min_face = 1e30;
+  uint64_t signature = 1469598103934665603ull;  // FNV-1a over discrete decisions
+  void mix(uint64_t x) {
+    for (int i = 0; i < 8; ++i) { signature ^= (x >> (8 * i)) & 0xff; signature *= 1099511628211ull; }
+  }
+};
+
+// C = max(0, -d) with the leaky derivative rule (Sec. III-C, "Leaky
+// gradient"): value max(0, -d); tangent -dd where d < 0, -alpha dd otherwise.
+template <class S> S leaky_penetration(const S& d, double alpha) {
+  if (val(d) < 0.0) return -d;
+  S c = -alpha * d;
+  c.v = 0.0;
+  return c;
+}
+template <> double leaky_penetration<double>(const double& d, double) { return d < 0.0 ? -d : 0.0; }
+
+template <class S>
+void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& P, const S* q,
+                    S& loss, S terms[4], Trace* tr) {
+  const int Nc = h.n_contacts;
+  const int nd = 6 + h.n_links - 1;
+  // 1. forward kinematics: hand points p_i (the hand is static during the step)
+  std::vector<Xf<S>> T;
+  forward_kinematics(h, q, T);
+  std::vector<S> p(3 * static_cast<size_t>(Nc));
+  for (int i = 0; i < Nc; ++i) apply_xf(T[h.contact_link[i]], h.contact_local + 3 * i, &p[3 * i]);
+  if (tr && tr->p_world)
+    for (int i = 0; i < 3 * Nc; ++i) tr->p_world[i] = val(p[i]);
+
+  // 2. penetration of the hand at the object's rest pose, with dilation:
+  //    C0_i = max(0, -(phi(p_i) - r)); L_pen = 1/2 sum C0_i^2
+  S Lpen = konst<S>(0.0);
+  for (int i = 0; i < Nc; ++i) {
+    S phi, n[3];
+    sample_object(o, &p[3 * i], phi, n, nullptr);
+    S d = phi - P.r_dil;
+    if (val(d) < 0.0) Lpen += 0.5 * (d * d);
+  }
+
+  // 3. M velocity-test simulations (Sec. IV-A), each one PBD step (Sec. III-C)
+  const double dirs[kSims][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                 {0, 0, 1}, {0, 0, -1}, {0, 0, 0}};
+  S Lstable = konst<S>(0.0);
+  for (int m = 0; m < kSims; ++m) {
+    // symplectic-Euler prediction from the canonical pose with velocity v0_m
+    S x[3], th[3];
+    for (int a = 0; a < 3; ++a) { x[a] = konst<S>(P.dt * P.v0 * dirs[m][a]); th[a] = konst<S>(0.0); }
+    for (int k = 0; k < P.K; ++k) {
+      if (tr && tr->poses)
+        for (int a = 0; a < 3; ++a) {
+          tr->poses[(m * (P.K + 1) + k) * 6 + a] = val(x[a]);
+          tr->poses[(m * (P.K + 1) + k) * 6 + 3 + a] = val(th[a]);
+        }
+      S R[9];
+      rotation_matrix(th, R);
+      S Wl[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+      S Wa[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+      for (int i = 0; i < Nc; ++i) {
+        // hand point in the object frame: r_i = R(theta)^-1 (p_i - x)
+        S a[3], r[3];
+        for (int j = 0; j < 3; ++j) a[j] = p[3 * i + j] - x[j];
+        for (int j = 0; j < 3; ++j) r[j] = R[j] * a[0] + R[3 + j] * a[1] + R[6 + j] * a[2];
+        S phi, nrm[3];
+        SampleInfo info;
+        sample_object(o, r, phi, nrm, &info);
+        // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
+        S d = phi - P.r_dil;
+        S C = leaky_penetration(d, P.alpha_leak);
+        // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
+        S g[3], u[3];
+        for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
+        u[0] = a[1] * g[2] - a[2] * g[1];
+        u[1] = a[2] * g[0] - a[0] * g[2];
+        u[2] = a[0] * g[1] - a[1] * g[0];
+        // Eq. (1) with M = diag(1, 1, 1, I/m, I/m, I/m):
+        // [dx; dtheta] = -M^-1 J^T (J M^-1 J^T)^-1 C = lambda (g, u / (I/m)), lambda = -C / w
+        S w = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / Im;
+        S lam = konst<S>(0.0);
+        const bool active = val(w) > P.w_min;
+        if (active) {
+          lam = -C / w;
+          for (int j = 0; j < 3; ++j) { Wl[j] += lam * g[j]; Wa[j] += lam * u[j]; }
+        }
+        if (tr) {
+          if (tr->samples) {
+            double* s = tr->samples + ((static_cast<size_t>(m) * P.K + k) * Nc + i) * 6;
+            s[0] = val(d); s[1] = val(g[0]); s[2] = val(g[1]); s[3] = val(g[2]);
+            s[4] = val(w); s[5] = val(lam);
+          }
+          if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
+          tr->min_face = std::min(tr->min_face, info.face_margin);
+          tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
+                  (static_cast<uint64_t>(info.cell[2]) << 32) |
+                  (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
+                  (static_cast<uint64_t>(val(d) < 0.0) << 52) | (static_cast<uint64_t>(active) << 53));
+        }
+      }
+      // Jacobi: all corrections at the same pose, summed, relaxed by omega
+      for (int j = 0; j < 3; ++j) {
+        x[j] = x[j] + P.omega * Wl[j];
+        th[j] = th[j] + (P.omega / Im) * Wa[j];
+      }
+    }
+    if (tr && tr->poses)
+      for (int a = 0; a < 3; ++a) {
+        tr->poses[(m * (P.K + 1) + P.K) * 6 + a] = val(x[a]);
+        tr->poses[(m * (P.K + 1) + P.K) * 6 + 3 + a] = val(th[a]);
+      }
+    // velocities from positions: x' = (x+ - x-)/dt with x- = 0 (Sec. III-C)
+    S v[3], wv[3];
+    for (int a = 0; a < 3; ++a) { v[a] = x[a] / P.dt; wv[a] = th[a] / P.dt; }
+    // L_stable = sum_m (|x'_m| + |theta'_m|) / M (Sec. IV-A)
+    Lstable += (norm3(v) + norm3(wv)) / static_cast<double>(kSims);
+  }
+
+  // 4. joint losses over finger joints (Sec. IV-A)
+  S rs = konst<S>(0.0);
+  S Llimit = konst<S>(0.0);
+  for (int j = 6; j < nd; ++j) {
+    S dm = q[j] - 0.5 * (h.q_up[j] + h.q_low[j]);
+    rs += dm * dm;
+    if (val(q[j]) > h.q_up[j]) Llimit += q[j] - h.q_up[j];
+    if (val(q[j]) < h.q_low[j]) Llimit += h.q_low[j] - q[j];
+    if (tr) tr->mix(static_cast<uint64_t>(j) << 8 | (val(q[j]) > h.q_up[j]) | (val(q[j]) < h.q_low[j]) << 1);
+  }
+  S Lrange = (val(rs) > 0.0) ? sqrt_(rs) : konst<S>(0.0);
+
+  terms[0] = Lstable;
+  terms[1] = Lpen;
+  terms[2] = Lrange;
+  terms[3] = Llimit;
+  loss = P.w_stable * Lstable + P.w_pen * Lpen + P.w_range * Lrange + P.w_limit * Llimit;
+}
+
+bool valid_hand(const ohand* h) {
+  if (!h || h->n_links < 1 || h->n_contacts < 0 || !h->parent || !h->joint_origin || !h->joint_axis ||
+      !h->q_low || !h->q_up || (h->n_contacts > 0 && (!h->contact_local || !h->contact_link)))
+    return false;
+  if (h->parent[0] != -1) return false;
+  for (int l = 1; l < h->n_links; ++l)
+    if (h->parent[l] < 0 || h->parent[l] >= l) return false;
+  for (int i = 0; i < h->n_contacts; ++i)
+    if (h->contact_link[i] < 0 || h->contact_link[i] >= h->n_links) return false;
+  return true;
+}
+
+bool valid_obj(const oobject* o) {
+  if (!o) return false;
+  if (o->kind == OBJ_GRID) return o->n >= 2 && o->h > 0.0 && o->values;
+  return o->kind >= OBJ_SPHERE && o->kind <= OBJ_BOX;
+}
+
+template <int N>
+void step_dual(const ohand& h, const oobject& o, double Im, const oparams& P, const double* q,
+               double* loss, double* terms, double* grad, double* margins) {
+  const int nd = 6 + h.n_links - 1;
+  std::vector<Dual<N>> qd(nd);
+  for (int j = 0; j < nd; ++j) { qd[j] = Dual<N>(q[j]); qd[j].d[j] = 1.0; }
+  Dual<N> L, t4[4];
+  Trace tr;
+  candidate_step(h, o, Im, P, qd.data(), L, t4, margins ? &tr : nullptr);
+  *loss = L.v;
+  if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i].v;
+  for (int j = 0; j < nd; ++j) grad[j] = L.d[j];
+  if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; }
+}
+
+void step_one(const ohand& h, const oobject& o, double Im, const oparams& P, const double* q,
+              double* loss, double* terms, double* grad, double* margins) {
+  const int nd = 6 + h.n_links - 1;
+  if (!grad) {
+    double L, t4[4];
+    Trace tr;
+    candidate_step(h, o, Im, P, q, L, t4, margins ? &tr : nullptr);
+    *loss = L;
+    if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i];
+    if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; }
+    return;
+  }
+  if (nd <= 8) step_dual<8>(h, o, Im, P, q, loss, terms, grad, margins);
+  else if (nd <= 16) step_dual<16>(h, o, Im, P, q, loss, terms, grad, margins);
+  else if (nd <= 24) step_dual<24>(h, o, Im, P, q, loss, terms, grad, margins);
+  else if (nd <= 32) step_dual<32>(h, o, Im, P, q, loss, terms, grad, margins);
+  else step_dual<40>(h, o, Im, P, q, loss, terms, grad, margins);
+}
+
+int set_threads(int n) {
+#ifdef _OPENMP
+  return n > 0 ? n : omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_fk(const ohand* hand, int B, const double* q, double* p_out, double* frames_out) {
+  if (!valid_hand(hand) || B < 0 || (B > 0 && (!q || !p_out))) return -1;
+  const int nd = 6 + hand->n_links - 1, L = hand->n_links, Nc = hand->n_contacts;
+  for (int b = 0; b < B; ++b) {
+    std::vector<Xf<double>> T;
+    forward_kinematics(*hand, q + static_cast<size_t>(b) * nd, T);
+    for (int i = 0; i < Nc; ++i)
+      apply_xf(T[hand->contact_link[i]], hand->contact_local + 3 * i, p_out + (static_cast<size_t>(b) * Nc + i) * 3);
+    if (frames_out)
+      for (int l = 0; l < L; ++l)
+        for (int i = 0; i < 3; ++i) {
+          for (int j = 0; j < 3; ++j) frames_out[(static_cast<size_t>(b) * L + l) * 12 + 4 * i + j] = T[l].R[3 * i + j];
+          frames_out[(static_cast<size_t>(b) * L + l) * 12 + 4 * i + 3] = T[l].t[i];
+        }
+  }
+  return 0;
+}
+
+int oracle_sample(const oobject* obj, int n, const double* r, double* phi, double* grad, double* hess,
+                  double* face_margin) {
+  if (!valid_obj(obj) || n < 0 || (n > 0 && (!r || !phi || !grad))) return -1;
+  for (int i = 0; i < n; ++i) {
+    SampleInfo info;
+    if (hess) {
+      Dual<3> rd[3], ph, nr[3];
+      for (int a = 0; a < 3; ++a) { rd[a] = Dual<3>(r[3 * i + a]); rd[a].d[a] = 1.0; }
+      sample_object(*obj, rd, ph, nr, &info);
+      phi[i] = ph.v;
+      for (int a = 0; a < 3; ++a) {
+        grad[3 * i + a] = nr[a].v;
+        for (int b = 0; b < 3; ++b) hess[9 * i + 3 * a + b] = nr[a].d[b];
+      }
+    } else {
+      double n3[3];
+      sample_object(*obj, r + 3 * i, phi[i], n3, &info);
+      for (int a = 0; a < 3; ++a) grad[3 * i + a] = n3[a];
+    }
+    if (face_margin) face_margin[i] = info.face_margin;
+  }
+  return 0;
+}
+
+double oracle_inertia_over_mass(const oobject* obj) {
+  if (!valid_obj(obj)) return -1.0;
+  return inertia_over_mass(*obj);
+}
+
+int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B, const double* q,
+                double* loss, double* terms, double* grad, double* margins, int n_threads) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !prm || B < 0 || (B > 0 && (!q || !loss)) || prm->K < 1)
+    return -1;
+  const double Im = inertia_over_mass(*obj);
+  if (!(Im > 0.0)) return -2;
+  const int nd = 6 + hand->n_links - 1;
+  const int nt = set_threads(n_threads);
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int b = 0; b < B; ++b)
+    step_one(*hand, *obj, Im, *prm, q + static_cast<size_t>(b) * nd, loss + b, terms ? terms + 4 * b : nullptr,
+             grad ? grad + static_cast<size_t>(b) * nd : nullptr, margins ? margins + 2 * b : nullptr);
+  return 0;
+}
+
+int oracle_trace(const ohand* hand, const oobject* obj, const oparams* prm, const double* q, double* poses,
+                 double* samples, double* p_world) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !prm || !q || prm->K < 1) return -1;
+  const double Im = inertia_over_mass(*obj);
+  if (!(Im > 0.0)) return -2;
+  Trace tr;
+  tr.poses = poses;
+  tr.samples = samples;
+  tr.p_world = p_world;
+  double L, t4[4];
+  candidate_step(*hand, *obj, Im, *prm, q, L, t4, &tr);
+  return 0;
+}
+
+int oracle_fd_grad(const ohand* hand, const oobject* obj, const oparams* prm, int B, const double* q,
+                   double fd_h, double* grad, int* excluded, int n_threads) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !prm || B < 0 || (B > 0 && (!q || !grad)) || !(fd_h > 0.0))
+    return -1;
+  const double Im = inertia_over_mass(*obj);
+  if (!(Im > 0.0)) return -2;
+  const int nd = 6 + hand->n_links - 1;
+  const int nt = set_threads(n_threads);
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int b = 0; b < B; ++b) {
+    std::vector<double> qq(q + static_cast<size_t>(b) * nd, q + static_cast<size_t>(b + 1) * nd);
+    double L0, t4[4];
+    Trace t0;
+    candidate_step(*hand, *obj, Im, *prm, qq.data(), L0, t4, &t0);
+    for (int j = 0; j < nd; ++j) {
+      const double q0 = qq[j];
+      double Lp, Lm;
+      Trace tp, tm;
+      qq[j] = q0 + fd_h;
+      candidate_step(*hand, *obj, Im, *prm, qq.data(), Lp, t4, &tp);
+      qq[j] = q0 - fd_h;
+      candidate_step(*hand, *obj, Im, *prm, qq.data(), Lm, t4, &tm);
+      qq[j] = q0;
+      grad[static_cast<size_t>(b) * nd + j] = (Lp - Lm) / (2.0 * fd_h);
+      if (excluded)
+        excluded[static_cast<size_t>(b) * nd + j] = (tp.signature != t0.signature) || (tm.signature != t0.signature);
+    }
+  }
+  return 0;
+}
+
+// Adam (Kingma & Ba): bias-corrected first and second moments, t >= 1.
+int oracle_adam(int n, double* q, double* m, double* v, const double* g, int t, double lr, double b1, double b2,
+                double eps) {
+  if (n < 0 || t < 1 || (n > 0 && (!q || !m || !v || !g))) return -1;
+  const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+  for (int i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    const double mh = m[i] / c1, vh = v[i] / c2;
+    q[i] -= lr * mh / (std::sqrt(vh) + eps);
+  }
+  return 0;
+}
+
+int oracle_rank(int B, const double* loss, int* rank) {
+  if (B < 0 || (B > 0 && (!loss || !rank))) return -1;
+  std::vector<int> idx(B);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return loss[a] < loss[b]; });
+  std::copy(idx.begin(), idx.end(), rank);
+  return 0;
+}
+
+int oracle_optimize(const ohand* hand, const oobject* obj, const oparams* prm, int B, double* q, int T, double r0,
+                    double lr, double b1, double b2, double eps, int use_gd, double* final_loss, double* final_terms,
+                    int* rank, double* loss_hist, int n_threads) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !prm || B < 0 || T < 1 || (B > 0 && !q)) return -1;
+  const int nd = 6 + hand->n_links - 1;
+  std::vector<double> m(static_cast<size_t>(B) * nd, 0.0), v(static_cast<size_t>(B) * nd, 0.0);
+  std::vector<double> g(static_cast<size_t>(B) * nd), L(B);
+  oparams P = *prm;
+  for (int t = 0; t < T; ++t) {
+    // linear dilation schedule down to 0 at the last step (Sec. III-B)
+    P.r_dil = (T > 1) ? r0 * (1.0 - static_cast<double>(t) / (T - 1)) : 0.0;
+    int rc = oracle_step(hand, obj, &P, B, q, L.data(), nullptr, g.data(), nullptr, n_threads);
+    if (rc) return rc;
+    if (loss_hist) std::copy(L.begin(), L.end(), loss_hist + static_cast<size_t>(t) * B);
+    if (use_gd) {
+      for (size_t i = 0; i < g.size(); ++i) q[i] -= lr * g[i];
+    } else {
+      oracle_adam(B * nd, q, m.data(), v.data(), g.data(), t + 1, lr, b1, b2, eps);
+    }
+  }
+  P.r_dil = 0.0;
+  std::vector<double> terms(4 * static_cast<size_t>(B));
+  int rc = oracle_step(hand, obj, &P, B, q, L.data(), terms.data(), nullptr, nullptr, n_threads);
+  if (rc) return rc;
+  if (final_loss) std::copy(L.begin(), L.end(), final_loss);
+  if (final_terms) std::copy(terms.begin(), terms.end(), final_terms);
+  if (rank) oracle_rank(B, L.data(), rank);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+/*
+ * FP64 CPU oracle for the grid-SDF Fast-Grasp'D grasp step.
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the slow, plain reference that
+ * the GPU path is checked against. Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it. It shares no code, header,
+ * table or constant with the GPU library; inputs arrive as plain arrays.
+ *
+ * Method (Fast-Grasp'D, Sec. III-C and Sec. IV-A): forward kinematics of the
+ * hand, penetration constraints of hand points against the object SDF,
+ * position-based-dynamics corrections of the object pose (Eq. (1)) summed
+ * over constraints, the velocity-test stability loss over M = 7 simulations,
+ * joint range/limit losses, the leaky contact gradient, and the optimizer.
+ * The object is a dense vertex-centred SDF grid sampled trilinearly (the
+ * representation of the paper's predecessor, Sec. III-A), or an analytic
+ * sphere / plane / box for checks.
+ *
+ * The gradient is computed by forward-mode dual numbers (one tangent per
+ * degree of freedom), a mechanism independent of the GPU's hand-written
+ * reverse-mode adjoint.
+ *
+ * All functions return 0 on success and a negative value on bad arguments.
+ */
+#ifndef GRASP_ORACLE_API_H
+#define GRASP_ORACLE_API_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n_links;                 /* link 0 is the palm (root) */
+  const int* parent;           /* [n_links]; parent[0] = -1, parent[l] < l */
+  const double* joint_origin;  /* [n_links][12] row-major 3x4: parent frame -> joint l at q = 0 */
+  const double* joint_axis;    /* [n_links][3] unit axis in the joint frame */
+  const double* q_low;         /* [n_dof]; entries 0..5 (wrist) unused */
+  const double* q_up;          /* [n_dof] */
+  int n_contacts;
+  const double* contact_local; /* [n_contacts][3] in the frame of contact_link[i] */
+  const int* contact_link;     /* [n_contacts] */
+} ohand;
+
+enum { OBJ_GRID = 0, OBJ_SPHERE = 1, OBJ_PLANE = 2, OBJ_BOX = 3 };
+
+typedef struct {
+  int kind;
+  /* grid: vertex (i,j,k) at lo + (i,j,k) h, value index (k*n + j)*n + i */
+  int n;
+  double lo[3];
+  double h;
+  const float* values;
+  /* sphere: |r - center| - radius; box: axis-aligned, centred at center */
+  double center[3];
+  double radius;
+  double half[3];
+  /* plane: normal . r - offset (normal unit) */
+  double normal[3];
+  double offset;
+  /* I/m of the isotropic object; <= 0 for a grid means 0.4 R_eq^2 with
+     R_eq^3 = 3 V / (4 pi), V = h^3 * #{vertices with value < 0} */
+  double inertia_over_mass;
+} oobject;
+
+typedef struct {
+  double dt;          /* time step (1e-3 s) */
+  double v0;          /* test speed (m/s); velocities +x,-x,+y,-y,+z,-z,0 */
+  int K;              /* projection iterations inside the one step */
+  double omega;       /* relaxation of the summed corrections */
+  double r_dil;       /* SDF dilation radius for this step */
+  double alpha_leak;  /* leaky gradient factor */
+  double w_stable, w_pen, w_range, w_limit;
+  double w_min;       /* a constraint with J M^-1 J^T <= w_min is skipped */
+} oparams;
+
+/* Forward kinematics. p_out [B][Nc][3]; frames_out [B][L][12] or NULL. */
+int oracle_fk(const ohand* hand, int B, const double* q, double* p_out, double* frames_out);
+
+/* SDF sample at n points r [n][3]: phi [n], grad [n][3], hess [n][9] or NULL,
+   face_margin [n] or NULL = distance (cell units) of the nearest coordinate to
+   a cell face or the box boundary (grids only). */
+int oracle_sample(const oobject* obj, int n, const double* r, double* phi, double* grad,
+                  double* hess, double* face_margin);
+
+double oracle_inertia_over_mass(const oobject* obj);
+
+/* One grasp step for B candidates q [B][n_dof].
+   loss [B]; terms [B][4] = (L_stable, L_pen, L_range, L_limit) or NULL;
+   grad [B][n_dof] or NULL; margins [B][2] = (min |d| over samples,
+   min face margin over samples) or NULL. */
+int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B,
+                const double* q, double* loss, double* terms, double* grad, double* margins,
+                int n_threads);
+
+/* One candidate in detail. poses [M][K+1][6] = (x, theta) before each
+   iteration and after the last; samples [M][K][Nc][6] = (d, g, w, lambda) or NULL;
+   p_world [Nc][3] or NULL. */
+int oracle_trace(const ohand* hand, const oobject* obj, const oparams* prm, const double* q,
+                 double* poses, double* samples, double* p_world);
+
+/* Central finite differences of the loss, step fd_h. excluded [B][n_dof] is
+   set where the discrete state (cells, clamps, penetration and limit
+   branches) differs between q - h e_j, q and q + h e_j. */
+int oracle_fd_grad(const ohand* hand, const oobject* obj, const oparams* prm, int B,
+                   const double* q, double fd_h, double* grad, int* excluded, int n_threads);
+
+/* Bias-corrected Adam step (t >= 1) on n values, in place. */
+int oracle_adam(int n, double* q, double* m, double* v, const double* g, int t, double lr,
+                double b1, double b2, double eps);
+
+/* rank[k] = index of the k-th smallest loss; ties keep index order. */
+int oracle_rank(int B, const double* loss, int* rank);
+
+/* T optimizer steps with the linear dilation schedule r(t) = r0 (1 - t/(T-1)),
+   then one forward at r = 0 for the final loss and the ranking.
+   q [B][n_dof] in/out; loss_hist [T][B] or NULL. use_gd selects plain
+   gradient descent q -= lr g instead of Adam. */
+int oracle_optimize(const ohand* hand, const oobject* obj, const oparams* prm, int B, double* q,
+                    int T, double r0, double lr, double b1, double b2, double eps, int use_gd,
+                    double* final_loss, double* final_terms, int* rank, double* loss_hist,
+                    int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
