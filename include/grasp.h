@@ -1,0 +1,211 @@
+/*
+ * grasp.h - C ABI of the MI355X (gfx950) grid-SDF grasp-step library.
+ *
+ * The library computes the data-parallel hot path of Fast-Grasp'D's
+ * gradient-based grasp synthesis (Sec. III-C "Position-based dynamics",
+ * Sec. IV-A "Gradient-based grasp optimization"): for a batch of candidate
+ * hand configurations q_h (a base pose plus joint angles, Sec. III), it runs
+ * forward kinematics of the hand's contact points, samples the object's
+ * signed-distance grid at every point in each of M = 7 velocity-test
+ * simulations, turns penetration into position-based-dynamics corrections of
+ * the object pose (Eq. (1)), forms the stability loss from the resulting
+ * object velocities plus penetration and joint range/limit losses, and
+ * back-propagates that loss to q_h with the leaky contact gradient, followed
+ * by an Adam step.
+ *
+ * Object representation: a dense vertex-centred FP32 SDF grid sampled
+ * trilinearly (the representation the paper describes for its predecessor,
+ * Sec. III-A), with the analytic gradient of the trilinear blend.
+ *
+ * Conventions
+ *  - Every call returns grasp_status (0 = GRASP_OK, negative = error) and
+ *    never throws. grasp_last_error() describes the last failure of the
+ *    calling thread.
+ *  - "dev" pointers are device memory of the context's GPU, owned by the
+ *    caller, and must stay valid until the work queued on the given stream
+ *    has run. "host" pointers are read (or written) before the call returns.
+ *  - hip_stream is a hipStream_t (NULL = the default stream). Step calls are
+ *    asynchronous in stream order; argument errors are reported at once.
+ *  - Units are SI: metres, seconds, radians.
+ *  - A HIP runtime failure returns GRASP_EDEVICE and poisons the context:
+ *    every later call on it returns GRASP_EDEVICE.
+ */
+#ifndef GRASP_H
+#define GRASP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t grasp_status;
+enum {
+  GRASP_OK = 0,
+  GRASP_EINVAL = -1,     /* bad argument: NULL, shape, id, value */
+  GRASP_ENOMEM = -2,     /* arena or workspace too small */
+  GRASP_EDEVICE = -3,    /* HIP runtime failure; the context is poisoned */
+  GRASP_EBUSY = -4,      /* object still used by a live job */
+  GRASP_EAGAIN = -5,     /* job not finished yet */
+  GRASP_ENONFINITE = -6, /* a loss or configuration became NaN/Inf */
+  GRASP_ECANCELED = -7   /* job was cancelled */
+};
+
+typedef struct grasp_ctx grasp_ctx; /* opaque */
+typedef uint64_t grasp_hand_id;
+typedef uint64_t grasp_sdf_id;
+typedef uint64_t grasp_job_id;
+
+/* ---------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`. Hands, SDF grids and serving
+ * state are sub-allocated from an arena of arena_bytes: arena_dev (dev,
+ * caller-owned, 256-byte aligned) or, when arena_dev is NULL, device memory
+ * the library allocates and frees itself. arena_bytes is also the HBM budget
+ * that job admission respects. */
+grasp_status grasp_init(int device, void* arena_dev, size_t arena_bytes, grasp_ctx** out);
+
+/* Waits for the context's work, stops its scheduler and frees what it owns.
+ * NULL is ignored. */
+void grasp_shutdown(grasp_ctx* ctx);
+
+/* Thread-local description of the calling thread's last error; valid until
+ * that thread's next grasp_* call. Never NULL. */
+const char* grasp_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Hands: an articulation chain with contact points on its links (Sec. III:
+ * "a mesh and an articulation chain"; every hand vertex is a constraint,
+ * Sec. III-C).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_links;             /* 1..32; link 0 = palm; n_dof = 6 + (n_links - 1) */
+  const int32_t* parent;       /* host [n_links]; parent[0] = -1, 0 <= parent[l] < l;
+                                  at most 8 links on any root-to-leaf path below the palm */
+  const float* joint_origin;   /* host [n_links][12], row-major 3x4 rigid transform from the
+                                  parent link frame to joint l at q = 0 (entry 0 ignored) */
+  const float* joint_axis;     /* host [n_links][3], unit revolute axis in the joint frame;
+                                  link l turns by q[5 + l] (entry 0 ignored) */
+  const float* q_low;          /* host [n_dof] joint limits; entries 0..5 (wrist) unused */
+  const float* q_up;           /* host [n_dof] */
+  int32_t n_contacts;          /* >= 1 */
+  const float* contact_local;  /* host [n_contacts][3], in the frame of contact_link[i] */
+  const int32_t* contact_link; /* host [n_contacts], 0 <= link < n_links */
+} grasp_hand_desc;
+
+/* The wrist is Trans(q0, q1, q2) Rz(q3) Ry(q4) Rx(q5); link l >= 1 has pose
+ * T_parent * joint_origin[l] * Rot(joint_axis[l], q[5 + l]). The library
+ * copies the description, re-lays the contacts out sorted by link, and
+ * returns results indexed by contact in the caller's order.
+ * EINVAL on a malformed description (e.g. a non-unit axis, |1 - |a|| > 1e-3). */
+grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* desc, grasp_hand_id* out);
+/* EBUSY while a live job uses the hand. */
+grasp_status grasp_destroy_hand(grasp_ctx* ctx, grasp_hand_id hand);
+
+/* Writes host out[n_contacts]: the link of each contact in caller order, as
+ * the device holds it (exact copy of the description's contact_link). */
+grasp_status grasp_hand_contact_links(grasp_ctx* ctx, grasp_hand_id hand, int32_t* out);
+
+/* ---------------------------------------------------------------------------
+ * Objects: a signed-distance grid (Sec. III-A/B)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n;                 /* vertices per axis, 2..1024 (cubic grid) */
+  float lo[3];               /* position of vertex (0,0,0) */
+  float h;                   /* vertex spacing, > 0: vertex (i,j,k) at lo + (i,j,k) h */
+  const float* values;       /* host [n][n][n], x fastest: index (k n + j) n + i; negative inside */
+  float inertia_over_mass;   /* I/m of the isotropic object; <= 0 selects 2/5 R_eq^2 with
+                                R_eq^3 = 3 V / (4 pi), V = h^3 #{vertices with value < 0} */
+} grasp_sdf_desc;
+
+/* Copies the grid to the device (and a corner-packed copy for gathers).
+ * EINVAL when the object has no interior and inertia_over_mass <= 0. */
+grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* desc, grasp_sdf_id* out);
+/* EBUSY while a live job uses the grid. */
+grasp_status grasp_unload_sdf(grasp_ctx* ctx, grasp_sdf_id sdf);
+/* Host out: the I/m the library uses for this grid. */
+grasp_status grasp_sdf_inertia(grasp_ctx* ctx, grasp_sdf_id sdf, float* out);
+
+/* ---------------------------------------------------------------------------
+ * The step (Sec. III-C, Sec. IV-A)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  float dt;          /* PBD time step, 1e-3 s in the paper */
+  float v0;          /* test speed (m/s): initial object velocities +x,-x,+y,-y,+z,-z,0 times v0 */
+  int32_t K;         /* projection iterations inside the one step, >= 1 */
+  int32_t ckpt_every;/* pose checkpoint interval for the backward, divides K (1 = keep all) */
+  float omega;       /* relaxation of the summed (Jacobi) corrections, default 1 */
+  float r_dil;       /* SDF dilation radius of this step (Sec. III-B), >= 0 */
+  float alpha_leak;  /* leaky-gradient factor (Sec. III-C), 0.1 in the paper; 0 = exact */
+  float w_stable, w_pen, w_range, w_limit; /* loss weights */
+  float w_min;       /* constraints with J M^-1 J^T <= w_min are skipped (1e-12) */
+  int32_t mode;      /* GRASP_MODE_*: how grasp_step_fwd/bwd share state */
+} grasp_step_params;
+
+enum {
+  GRASP_MODE_AUTO = 0,      /* SAVE when a workspace is given, else RECOMPUTE */
+  GRASP_MODE_SAVE = 1,      /* fwd stores pose checkpoints in the workspace, bwd reads them */
+  GRASP_MODE_RECOMPUTE = 2  /* bwd recomputes the forward (FK, samples, corrections) */
+};
+
+/* Fills p with the defaults above (dt 1e-3, v0 1, K 1, ckpt 1, omega 1, r_dil 0,
+ * alpha 0.1, weights 1 / 1e4 / 1e-2 / 1, w_min 1e-12, AUTO). */
+void grasp_default_params(grasp_step_params* p);
+
+/* Host out: workspace bytes grasp_step_fwd/bwd need for B candidates in SAVE
+ * mode (pose checkpoints, 168 (K/ckpt + 1) bytes per candidate). */
+grasp_status grasp_step_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                        const grasp_step_params* p, int32_t B, size_t* out);
+
+/* Forward: loss (dev [B]) and terms (dev [B][4] = L_stable, L_pen, L_range,
+ * L_limit, or NULL) for configurations q (dev [B][n_dof]). In SAVE mode ws
+ * (dev, ws_bytes from grasp_step_workspace_bytes) receives the pose
+ * checkpoints the backward reads; otherwise ws may be NULL.
+ * ENOMEM if ws_bytes is too small for SAVE. */
+grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                            const grasp_step_params* p, int32_t B, const float* q, float* loss,
+                            float* terms, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Backward: dq (dev [B][n_dof]) = dloss[b] * dL_b/dq_b with the leaky rule,
+ * for dloss dev [B] (NULL = all ones). Same q, p, ws as the forward. */
+grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                            const grasp_step_params* p, int32_t B, const float* q, const float* dloss,
+                            float* dq, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Bias-corrected Adam on n values in place (dev q, m, v; dev g), step t >= 1. */
+grasp_status grasp_adam_step(grasp_ctx* ctx, int32_t n, float* q, float* m, float* v, const float* g,
+                             int32_t t, float lr, float b1, float b2, float eps, void* hip_stream);
+
+/* One fused optimizer step in a single launch: forward, backward and Adam
+ * for B candidates. q, m, v (dev [B][n_dof]) are updated in place; loss,
+ * terms, dq (dev) are written when not NULL (loss/terms before the update).
+ * t >= 1 is the Adam step number. */
+grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                              const grasp_step_params* p, int32_t B, float* q, float* m, float* v,
+                              int32_t t, float lr, float b1, float b2, float eps, float* loss,
+                              float* terms, float* dq, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Parity introspection (tests)
+ * ------------------------------------------------------------------------- */
+
+/* Samples the grid at n points r (dev [n][3], object frame): out (dev [n][4] =
+ * phi, grad phi) and hess (dev [n][9] row-major d grad/dr, or NULL). */
+grasp_status grasp_debug_sdf_sample(grasp_ctx* ctx, grasp_sdf_id sdf, int32_t n, const float* r,
+                                    float* out, float* hess, void* hip_stream);
+
+/* Forward trace of the step, caller contact order: p_world (dev [B][Nc][3]
+ * or NULL), poses (dev [B][7][K+1][6] = x, theta before each iteration and
+ * after the last, or NULL), samples (dev [B][7][K][Nc][6] = d, g, w, lambda,
+ * or NULL). */
+grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                               const grasp_step_params* p, int32_t B, const float* q, float* p_world,
+                               float* poses, float* samples, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRASP_H */

@@ -1,0 +1,126 @@
+"""ctypes binding of libgrasp.so (the C ABI in include/grasp.h).
+
+Argument marshalling only: every step of the grasp path runs in the HIP
+library. If the library is missing this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrasp.so")
+
+GRASP_OK, GRASP_EINVAL, GRASP_ENOMEM, GRASP_EDEVICE = 0, -1, -2, -3
+GRASP_EBUSY, GRASP_EAGAIN, GRASP_ENONFINITE, GRASP_ECANCELED = -4, -5, -6, -7
+MODE_AUTO, MODE_SAVE, MODE_RECOMPUTE = 0, 1, 2
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY", -5: "EAGAIN",
+                -6: "ENONFINITE", -7: "ECANCELED"}
+
+
+class GraspError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HandDesc(C.Structure):
+    _fields_ = [("n_links", C.c_int32), ("parent", C.POINTER(C.c_int32)),
+                ("joint_origin", C.POINTER(C.c_float)), ("joint_axis", C.POINTER(C.c_float)),
+                ("q_low", C.POINTER(C.c_float)), ("q_up", C.POINTER(C.c_float)),
+                ("n_contacts", C.c_int32), ("contact_local", C.POINTER(C.c_float)),
+                ("contact_link", C.POINTER(C.c_int32))]
+
+
+class SdfDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("lo", C.c_float * 3), ("h", C.c_float),
+                ("values", C.POINTER(C.c_float)), ("inertia_over_mass", C.c_float)]
+
+
+class StepParamsC(C.Structure):
+    _fields_ = [("dt", C.c_float), ("v0", C.c_float), ("K", C.c_int32), ("ckpt_every", C.c_int32),
+                ("omega", C.c_float), ("r_dil", C.c_float), ("alpha_leak", C.c_float),
+                ("w_stable", C.c_float), ("w_pen", C.c_float), ("w_range", C.c_float),
+                ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32)]
+
+
+@dataclasses.dataclass
+class StepParams:
+    """Mirror of grasp_step_params (defaults of grasp_default_params)."""
+    dt: float = 1e-3
+    v0: float = 1.0
+    K: int = 1
+    ckpt_every: int = 1
+    omega: float = 1.0
+    r_dil: float = 0.0
+    alpha_leak: float = 0.1
+    w_stable: float = 1.0
+    w_pen: float = 1e4
+    w_range: float = 1e-2
+    w_limit: float = 1.0
+    w_min: float = 1e-12
+    mode: int = MODE_AUTO
+
+    def c(self) -> StepParamsC:
+        return StepParamsC(self.dt, self.v0, self.K, self.ckpt_every, self.omega, self.r_dil,
+                           self.alpha_leak, self.w_stable, self.w_pen, self.w_range, self.w_limit,
+                           self.w_min, self.mode)
+
+
+# (name, restype, argtypes) of every exported entry point in include/grasp.h
+_VP, _SZ, _I32, _U64, _F = C.c_void_p, C.c_size_t, C.c_int32, C.c_uint64, C.c_float
+_FP, _IP = C.POINTER(C.c_float), C.POINTER(C.c_int32)
+SIGNATURES = [
+    ("grasp_init", _I32, [C.c_int, _VP, _SZ, C.POINTER(_VP)]),
+    ("grasp_shutdown", None, [_VP]),
+    ("grasp_last_error", C.c_char_p, []),
+    ("grasp_create_hand", _I32, [_VP, C.POINTER(HandDesc), C.POINTER(_U64)]),
+    ("grasp_destroy_hand", _I32, [_VP, _U64]),
+    ("grasp_hand_contact_links", _I32, [_VP, _U64, _IP]),
+    ("grasp_load_sdf", _I32, [_VP, C.POINTER(SdfDesc), C.POINTER(_U64)]),
+    ("grasp_unload_sdf", _I32, [_VP, _U64]),
+    ("grasp_sdf_inertia", _I32, [_VP, _U64, _FP]),
+    ("grasp_default_params", None, [C.POINTER(StepParamsC)]),
+    ("grasp_step_workspace_bytes", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(_SZ)]),
+    ("grasp_step_fwd", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("grasp_step_bwd", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("grasp_adam_step", _I32, [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _F, _F, _F, _F, _VP]),
+    ("grasp_step_fused", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F,
+                                _F, _VP, _VP, _VP, _VP]),
+    ("grasp_debug_sdf_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP, _VP]),
+    ("grasp_debug_trace", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _VP]),
+]
+
+
+class Library:
+    """The loaded libgrasp.so with typed entry points."""
+    _inst = None
+
+    def __init__(self, path: str = LIB_PATH):
+        if not os.path.exists(path):
+            raise RuntimeError(f"libgrasp.so not built at {path}; run paper_2306_08132_amd.build.build()")
+        self.path = path
+        self.dll = C.CDLL(path)
+        for name, res, args in SIGNATURES:
+            f = getattr(self.dll, name)
+            f.restype = res
+            f.argtypes = args
+
+    @classmethod
+    def get(cls) -> "Library":
+        if cls._inst is None:
+            cls._inst = cls()
+        return cls._inst
+
+    def __getattr__(self, name):
+        return getattr(self.dll, name)
+
+    def check(self, code: int, where: str):
+        if code != GRASP_OK:
+            msg = self.dll.grasp_last_error()
+            raise GraspError(code, where, msg.decode() if msg else "")
+        return code
+
+    def call(self, name: str, *args):
+        return self.check(getattr(self.dll, name)(*args), name)

@@ -1,0 +1,197 @@
+"""Python front end of the grasp library: contexts, resident hands and SDF
+grids, the step calls on torch tensors, and a torch.autograd.Function.
+
+PyTorch supplies device memory and streams only; every computation runs in
+the HIP kernels of libgrasp.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import (HandDesc, Library, SdfDesc, StepParams, MODE_AUTO, MODE_RECOMPUTE, MODE_SAVE,
+                   GraspError)
+
+__all__ = ["Context", "Hand", "Sdf", "StepParams", "GraspStep", "GraspError", "MODE_AUTO",
+           "MODE_SAVE", "MODE_RECOMPUTE"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Context:
+    """A grasp context on one GPU; its arena is a torch uint8 tensor."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 1 << 30, arena: torch.Tensor | None = None):
+        self.lib = Library.get()
+        self.device = device
+        if arena is None:
+            arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.arena = arena
+        h = C.c_void_p()
+        self.lib.call("grasp_init", device, C.c_void_p(arena.data_ptr()), arena.numel(), C.byref(h))
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            self.lib.grasp_shutdown(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- resident objects ---------------------------------------------------
+    def hand(self, hand) -> "Hand":
+        return Hand(self, hand)
+
+    def sdf(self, grid, inertia_over_mass: float = 0.0) -> "Sdf":
+        return Sdf(self, grid, inertia_over_mass)
+
+    # -- steps -----------------------------------------------------------------
+    def workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
+        out = C.c_size_t()
+        pc = prm.c()
+        self.lib.call("grasp_step_workspace_bytes", self.h, hand.id, sdf.id, C.byref(pc), B, C.byref(out))
+        return out.value
+
+    def step_fwd(self, hand, sdf, prm: StepParams, q, loss, terms=None, ws=None, stream=None):
+        pc = prm.c()
+        nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+        self.lib.call("grasp_step_fwd", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(loss),
+                      _ptr(terms), _ptr(ws), nbytes, _stream(stream))
+
+    def step_bwd(self, hand, sdf, prm: StepParams, q, dq, dloss=None, ws=None, stream=None):
+        pc = prm.c()
+        nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+        self.lib.call("grasp_step_bwd", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(dloss),
+                      _ptr(dq), _ptr(ws), nbytes, _stream(stream))
+
+    def adam(self, q, m, v, g, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.lib.call("grasp_adam_step", self.h, q.numel(), _ptr(q), _ptr(m), _ptr(v), _ptr(g), t, lr, b1, b2, eps,
+                      _stream(stream))
+
+    def step_fused(self, hand, sdf, prm: StepParams, q, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
+                   loss=None, terms=None, dq=None, stream=None):
+        pc = prm.c()
+        self.lib.call("grasp_step_fused", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
+                      _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
+
+    def debug_sdf_sample(self, sdf, r, hess: bool = False, stream=None):
+        n = r.shape[0]
+        out = torch.empty((n, 4), dtype=torch.float32, device=r.device)
+        H = torch.empty((n, 9), dtype=torch.float32, device=r.device) if hess else None
+        self.lib.call("grasp_debug_sdf_sample", self.h, sdf.id, n, _ptr(r), _ptr(out), _ptr(H), _stream(stream))
+        return (out, H) if hess else out
+
+    def debug_trace(self, hand, sdf, prm: StepParams, q, p_world=True, poses=True, samples=True, stream=None):
+        B, dev = q.shape[0], q.device
+        pw = torch.empty((B, hand.n_contacts, 3), dtype=torch.float32, device=dev) if p_world else None
+        ps = torch.empty((B, 7, prm.K + 1, 6), dtype=torch.float32, device=dev) if poses else None
+        sm = torch.empty((B, 7, prm.K, hand.n_contacts, 6), dtype=torch.float32, device=dev) if samples else None
+        pc = prm.c()
+        self.lib.call("grasp_debug_trace", self.h, hand.id, sdf.id, C.byref(pc), B, _ptr(q), _ptr(pw), _ptr(ps),
+                      _ptr(sm), _stream(stream))
+        return {"p": pw, "poses": ps, "samples": sm}
+
+
+class Hand:
+    """A hand resident in a context (grasp_create_hand)."""
+
+    def __init__(self, ctx: Context, hand):
+        self.ctx = ctx
+        parent = _i32(hand.parent)
+        origin = _f32(hand.joint_origin)
+        axis = _f32(hand.joint_axis)
+        lo, up = _f32(hand.q_low), _f32(hand.q_up)
+        cl, lk = _f32(hand.contact_local), _i32(hand.contact_link)
+        fp, ip = C.POINTER(C.c_float), C.POINTER(C.c_int32)
+        d = HandDesc(parent.shape[0], parent.ctypes.data_as(ip), origin.ctypes.data_as(fp),
+                     axis.ctypes.data_as(fp), lo.ctypes.data_as(fp), up.ctypes.data_as(fp), lk.shape[0],
+                     cl.ctypes.data_as(fp), lk.ctypes.data_as(ip))
+        hid = C.c_uint64()
+        ctx.lib.call("grasp_create_hand", ctx.h, C.byref(d), C.byref(hid))
+        self.id = hid.value
+        self.n_links = int(parent.shape[0])
+        self.n_dof = 6 + self.n_links - 1
+        self.n_contacts = int(lk.shape[0])
+
+    def contact_links(self) -> np.ndarray:
+        out = np.zeros(self.n_contacts, np.int32)
+        self.ctx.lib.call("grasp_hand_contact_links", self.ctx.h, self.id, out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out
+
+    def destroy(self):
+        self.ctx.lib.call("grasp_destroy_hand", self.ctx.h, self.id)
+
+
+class Sdf:
+    """An SDF grid resident in a context (grasp_load_sdf)."""
+
+    def __init__(self, ctx: Context, grid, inertia_over_mass: float = 0.0):
+        self.ctx = ctx
+        vals = _f32(grid.values)
+        d = SdfDesc(int(grid.n), (C.c_float * 3)(*[float(x) for x in grid.lo]), float(grid.h),
+                    vals.ctypes.data_as(C.POINTER(C.c_float)), float(inertia_over_mass))
+        sid = C.c_uint64()
+        ctx.lib.call("grasp_load_sdf", ctx.h, C.byref(d), C.byref(sid))
+        self.id = sid.value
+        self.n = int(grid.n)
+
+    def inertia_over_mass(self) -> float:
+        out = C.c_float()
+        self.ctx.lib.call("grasp_sdf_inertia", self.ctx.h, self.id, C.byref(out))
+        return out.value
+
+    def unload(self):
+        self.ctx.lib.call("grasp_unload_sdf", self.ctx.h, self.id)
+
+
+class GraspStep(torch.autograd.Function):
+    """loss = GraspStep.apply(q, ctx, hand, sdf, params): the grasp loss of
+    each candidate (grasp_step_fwd); backward is the hand-written adjoint
+    (grasp_step_bwd). In SAVE/AUTO mode a workspace tensor carries the pose
+    checkpoints from forward to backward; RECOMPUTE needs none."""
+
+    @staticmethod
+    def forward(fctx, q, ctx: Context, hand: Hand, sdf: Sdf, prm: StepParams):
+        q = q.detach().contiguous()
+        if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != hand.n_dof:
+            raise ValueError("q must be float32 [B][n_dof]")
+        B = q.shape[0]
+        loss = torch.empty(B, dtype=torch.float32, device=q.device)
+        ws = None
+        if prm.mode != MODE_RECOMPUTE:
+            nb = ctx.workspace_bytes(hand, sdf, prm, B)
+            ws = torch.empty(max(nb, 4), dtype=torch.uint8, device=q.device)
+        ctx.step_fwd(hand, sdf, prm, q, loss, ws=ws)
+        fctx.save_for_backward(q)
+        fctx.extra = (ctx, hand, sdf, prm, ws)
+        return loss
+
+    @staticmethod
+    def backward(fctx, dloss):
+        (q,) = fctx.saved_tensors
+        ctx, hand, sdf, prm, ws = fctx.extra
+        dq = torch.empty_like(q)
+        ctx.step_bwd(hand, sdf, prm, q, dq, dloss=dloss.contiguous().to(torch.float32), ws=ws)
+        return dq, None, None, None, None

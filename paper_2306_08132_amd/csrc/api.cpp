@@ -1,0 +1,672 @@
+// C-ABI entry points of the grasp-step library: context, arena, resident
+// hands and SDF grids, and the step calls. Argument checking happens here so
+// that kernels only ever see shapes they were written for.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "context.h"
+
+namespace grasp {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr size_t kGranule = 256;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+bool finite(float x) { return std::isfinite(x); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+grasp_status fail(grasp_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+void Arena::reset(char* base, size_t bytes) {
+  base_ = base;
+  bytes_ = bytes / kGranule * kGranule;
+  free_.clear();
+  used_.clear();
+  if (bytes_) free_[0] = bytes_;
+}
+
+void* Arena::alloc(size_t bytes) {
+  const size_t need = round_up(std::max<size_t>(bytes, 1), kGranule);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < need) continue;
+    const size_t off = it->first, sz = it->second;
+    free_.erase(it);
+    if (sz > need) free_[off + need] = sz - need;
+    used_[off] = need;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Arena::free(void* p) {
+  if (!p) return;
+  const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t start = off, sz = u->second;
+  used_.erase(u);
+  auto nx = free_.lower_bound(start);
+  if (nx != free_.end() && nx->first == start + sz) {
+    sz += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(start);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      sz += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = sz;
+}
+
+size_t Arena::used() const {
+  size_t s = 0;
+  for (auto& kv : used_) s += kv.second;
+  return s;
+}
+
+size_t Arena::largest_free() const {
+  size_t s = 0;
+  for (auto& kv : free_) s = std::max(s, kv.second);
+  return s;
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+  ok_ = (prev_ == dev) || (hipSetDevice(dev) == hipSuccess);
+}
+
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+}
+
+grasp_status device_fail(grasp_ctx* ctx, hipError_t e, const char* where) {
+  if (ctx) ctx->poisoned = true;
+  return fail(GRASP_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+DevHand* find_hand(grasp_ctx* ctx, grasp_hand_id id) {
+  auto it = ctx->hands.find(id);
+  return it == ctx->hands.end() ? nullptr : it->second.get();
+}
+
+DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id) {
+  auto it = ctx->sdfs.find(id);
+  return it == ctx->sdfs.end() ? nullptr : it->second.get();
+}
+
+grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
+  if (!p) return fail(GRASP_EINVAL, "params is NULL");
+  if (!(p->dt > 0.0f) || !finite(p->dt)) return fail(GRASP_EINVAL, "dt must be finite and > 0");
+  if (!finite(p->v0)) return fail(GRASP_EINVAL, "v0 must be finite");
+  if (p->K < 1 || p->K > 1024) return fail(GRASP_EINVAL, "K must be in [1, 1024]");
+  if (p->ckpt_every < 1 || p->K % p->ckpt_every != 0)
+    return fail(GRASP_EINVAL, "ckpt_every must be >= 1 and divide K");
+  if (!finite(p->omega) || !finite(p->r_dil) || p->r_dil < 0.0f || !finite(p->alpha_leak) ||
+      !finite(p->w_stable) || !finite(p->w_pen) || !finite(p->w_range) || !finite(p->w_limit) ||
+      !finite(p->w_min) || p->w_min < 0.0f)
+    return fail(GRASP_EINVAL, "params must be finite (r_dil, w_min >= 0)");
+  if (p->mode < GRASP_MODE_AUTO || p->mode > GRASP_MODE_RECOMPUTE) return fail(GRASP_EINVAL, "bad mode");
+  // LDS of one wave must fit comfortably: K/ckpt + 1 + ckpt pose slots
+  if (wave_lds_floats(p->K, p->ckpt_every) * sizeof(float) > 16 * 1024)
+    return fail(GRASP_EINVAL, "K / ckpt_every too large for the pose checkpoint buffer");
+  if (out) {
+    out->dt = p->dt;
+    out->v0 = p->v0;
+    out->omega = p->omega;
+    out->r_dil = p->r_dil;
+    out->alpha = p->alpha_leak;
+    out->w_stable = p->w_stable;
+    out->w_pen = p->w_pen;
+    out->w_range = p->w_range;
+    out->w_limit = p->w_limit;
+    out->w_min = p->w_min;
+    out->K = p->K;
+    out->ckpt = p->ckpt_every;
+  }
+  return GRASP_OK;
+}
+
+}  // namespace grasp
+
+using namespace grasp;
+
+namespace {
+
+#define GRASP_CHECK_CTX(ctx)                                                        \
+  do {                                                                              \
+    if (!(ctx)) return fail(GRASP_EINVAL, "context is NULL");                       \
+    if ((ctx)->poisoned) return fail(GRASP_EDEVICE, "context poisoned by an earlier device error"); \
+  } while (0)
+
+// Waves per workgroup of the step kernel (independent waves share nothing).
+constexpr int kStepWaves = 4;
+
+}  // namespace
+
+extern "C" {
+
+const char* grasp_last_error(void) { return g_last_error.c_str(); }
+
+grasp_status grasp_init(int device, void* arena_dev, size_t arena_bytes, grasp_ctx** out) {
+  set_error("");
+  if (!out) return fail(GRASP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return fail(GRASP_EDEVICE, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+  if (device < 0 || device >= n) return fail(GRASP_EINVAL, "no such device");
+  if (arena_bytes < kGranule) return fail(GRASP_EINVAL, "arena_bytes too small");
+  if (arena_dev && (reinterpret_cast<uintptr_t>(arena_dev) % kGranule) != 0)
+    return fail(GRASP_EINVAL, "arena must be 256-byte aligned");
+  DeviceGuard g(device);
+  if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
+  auto* ctx = new grasp_ctx();
+  ctx->device = device;
+  if (arena_dev) {
+    ctx->arena_base = static_cast<char*>(arena_dev);
+  } else {
+    void* p = nullptr;
+    e = hipMalloc(&p, arena_bytes);
+    if (e != hipSuccess) {
+      delete ctx;
+      return fail(GRASP_ENOMEM, std::string("hipMalloc arena: ") + hipGetErrorString(e));
+    }
+    ctx->arena_base = static_cast<char*>(p);
+    ctx->arena_owned = true;
+  }
+  ctx->arena.reset(ctx->arena_base, arena_bytes);
+  *out = ctx;
+  return GRASP_OK;
+}
+
+void grasp_shutdown_scheduler(grasp_ctx* ctx);  // sched.cpp
+
+void grasp_shutdown(grasp_ctx* ctx) {
+  if (!ctx) return;
+  grasp_shutdown_scheduler(ctx);
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->arena_owned) (void)hipFree(ctx->arena_base);
+  }
+  delete ctx;
+}
+
+void grasp_default_params(grasp_step_params* p) {
+  if (!p) return;
+  p->dt = 1e-3f;
+  p->v0 = 1.0f;
+  p->K = 1;
+  p->ckpt_every = 1;
+  p->omega = 1.0f;
+  p->r_dil = 0.0f;
+  p->alpha_leak = 0.1f;
+  p->w_stable = 1.0f;
+  p->w_pen = 1e4f;
+  p->w_range = 1e-2f;
+  p->w_limit = 1.0f;
+  p->w_min = 1e-12f;
+  p->mode = GRASP_MODE_AUTO;
+}
+
+// ---------------------------------------------------------------------------
+// hands
+// ---------------------------------------------------------------------------
+grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_hand_id* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!d || !out) return fail(GRASP_EINVAL, "desc/out is NULL");
+  const int L = d->n_links, Nc = d->n_contacts;
+  if (L < 1 || L > kMaxLinks) return fail(GRASP_EINVAL, "n_links must be in [1, 32]");
+  if (Nc < 1 || Nc > (1 << 24)) return fail(GRASP_EINVAL, "n_contacts must be in [1, 2^24]");
+  if (!d->parent || !d->joint_origin || !d->joint_axis || !d->q_low || !d->q_up || !d->contact_local ||
+      !d->contact_link)
+    return fail(GRASP_EINVAL, "hand description has a NULL array");
+  const int nd = 6 + L - 1;
+  if (d->parent[0] != -1) return fail(GRASP_EINVAL, "parent[0] must be -1");
+  std::vector<int> depth(L, 0), chain(static_cast<size_t>(L) * kMaxDepth, -1);
+  for (int l = 1; l < L; ++l) {
+    if (d->parent[l] < 0 || d->parent[l] >= l) return fail(GRASP_EINVAL, "parent[l] must be in [0, l)");
+    depth[l] = depth[d->parent[l]] + 1;
+    if (depth[l] > kMaxDepth) return fail(GRASP_EINVAL, "chain deeper than 8 links");
+    for (int s = 0; s < depth[l] - 1; ++s) chain[l * kMaxDepth + s] = chain[d->parent[l] * kMaxDepth + s];
+    chain[l * kMaxDepth + depth[l] - 1] = l;
+    const float* a = d->joint_axis + 3 * l;
+    const float n = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (!(std::fabs(n - 1.0f) <= 1e-3f)) return fail(GRASP_EINVAL, "joint_axis must be unit length");
+    for (int j = 0; j < 12; ++j)
+      if (!finite(d->joint_origin[12 * l + j])) return fail(GRASP_EINVAL, "joint_origin not finite");
+  }
+  for (int j = 6; j < nd; ++j)
+    if (!finite(d->q_low[j]) || !finite(d->q_up[j]) || d->q_low[j] > d->q_up[j])
+      return fail(GRASP_EINVAL, "joint limits must be finite with q_low <= q_up");
+  for (int i = 0; i < Nc; ++i) {
+    if (d->contact_link[i] < 0 || d->contact_link[i] >= L) return fail(GRASP_EINVAL, "contact_link out of range");
+    for (int j = 0; j < 3; ++j)
+      if (!finite(d->contact_local[3 * i + j])) return fail(GRASP_EINVAL, "contact_local not finite");
+  }
+  // stable sort of contacts by link: slot -> caller index
+  std::vector<int> perm(Nc);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d->contact_link[a] < d->contact_link[b]; });
+  const int nch = (Nc + kWave - 1) / kWave;
+  const int npad = nch * kWave;
+  std::vector<float> cx(npad, 0.0f), cy(npad, 0.0f), cz(npad, 0.0f);
+  std::vector<int> clink(npad, 0), chunk(nch, 0);
+  for (int s = 0; s < Nc; ++s) {
+    const int i = perm[s];
+    cx[s] = d->contact_local[3 * i];
+    cy[s] = d->contact_local[3 * i + 1];
+    cz[s] = d->contact_local[3 * i + 2];
+    clink[s] = d->contact_link[i];
+  }
+  for (int c = 0; c < nch; ++c) {
+    const int first = clink[c * kWave];
+    const int last = clink[std::min(Nc, (c + 1) * kWave) - 1];
+    chunk[c] = first | (last << 16);
+  }
+  std::vector<float> origin(static_cast<size_t>(L) * 12), axis(static_cast<size_t>(L) * 3), qlo(nd), qup(nd);
+  std::memcpy(origin.data(), d->joint_origin, origin.size() * sizeof(float));
+  std::memcpy(axis.data(), d->joint_axis, axis.size() * sizeof(float));
+  std::memcpy(qlo.data(), d->q_low, nd * sizeof(float));
+  std::memcpy(qup.data(), d->q_up, nd * sizeof(float));
+  for (int j = 0; j < 6; ++j) { qlo[j] = 0.0f; qup[j] = 0.0f; }
+  std::vector<int> parent(d->parent, d->parent + L);
+
+  // one device block: floats, then ints
+  struct Part { const void* src; size_t bytes; size_t off; };
+  std::vector<Part> parts = {
+      {origin.data(), origin.size() * 4, 0}, {axis.data(), axis.size() * 4, 0}, {qlo.data(), qlo.size() * 4, 0},
+      {qup.data(), qup.size() * 4, 0},       {cx.data(), cx.size() * 4, 0},     {cy.data(), cy.size() * 4, 0},
+      {cz.data(), cz.size() * 4, 0},         {parent.data(), parent.size() * 4, 0},
+      {chain.data(), chain.size() * 4, 0},   {depth.data(), depth.size() * 4, 0},
+      {clink.data(), clink.size() * 4, 0},   {chunk.data(), chunk.size() * 4, 0},
+      {perm.data(), perm.size() * 4, 0}};
+  size_t total = 0;
+  for (auto& p : parts) { p.off = total; total += round_up(p.bytes, 256); }
+  std::vector<char> host(total, 0);
+  for (auto& p : parts) std::memcpy(host.data() + p.off, p.src, p.bytes);
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  void* blk = ctx->arena.alloc(total);
+  if (!blk) return fail(GRASP_ENOMEM, "arena full (hand)");
+  hipError_t e = hipMemcpy(blk, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ctx->arena.free(blk);
+    return device_fail(ctx, e, "hipMemcpy hand");
+  }
+  auto h = std::make_unique<DevHand>();
+  char* b = static_cast<char*>(blk);
+  auto F = [&](int k) { return reinterpret_cast<const float*>(b + parts[k].off); };
+  auto I = [&](int k) { return reinterpret_cast<const int*>(b + parts[k].off); };
+  h->view.L = L;
+  h->view.n_dof = nd;
+  h->view.Nc = Nc;
+  h->view.n_chunks = nch;
+  h->view.origin = F(0);
+  h->view.axis = F(1);
+  h->view.qlo = F(2);
+  h->view.qup = F(3);
+  h->view.cx = F(4);
+  h->view.cy = F(5);
+  h->view.cz = F(6);
+  h->view.parent = I(7);
+  h->view.chain = I(8);
+  h->view.depth = I(9);
+  h->view.clink = I(10);
+  h->view.chunk_lk = I(11);
+  h->view.perm = I(12);
+  h->block = blk;
+  h->bytes = total;
+  h->contact_link.assign(d->contact_link, d->contact_link + Nc);
+  const uint64_t id = ctx->next_id++;
+  ctx->hands[id] = std::move(h);
+  *out = id;
+  return GRASP_OK;
+}
+
+grasp_status grasp_destroy_hand(grasp_ctx* ctx, grasp_hand_id id) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DevHand* h = find_hand(ctx, id);
+  if (!h) return fail(GRASP_EINVAL, "unknown hand id");
+  if (h->live_jobs > 0) return fail(GRASP_EBUSY, "hand in use by a live job");
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->arena.free(h->block);
+  ctx->hands.erase(id);
+  return GRASP_OK;
+}
+
+grasp_status grasp_hand_contact_links(grasp_ctx* ctx, grasp_hand_id id, int32_t* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!out) return fail(GRASP_EINVAL, "out is NULL");
+  HandView v;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DevHand* h = find_hand(ctx, id);
+    if (!h) return fail(GRASP_EINVAL, "unknown hand id");
+    v = h->view;
+  }
+  DeviceGuard g(ctx->device);
+  std::vector<int> clink(v.Nc), perm(v.Nc);
+  hipError_t e = hipMemcpy(clink.data(), v.clink, v.Nc * sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(perm.data(), v.perm, v.Nc * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpy contact links");
+  for (int s = 0; s < v.Nc; ++s) {
+    if (perm[s] < 0 || perm[s] >= v.Nc) return fail(GRASP_EINVAL, "corrupt contact permutation");
+    out[perm[s]] = clink[s];
+  }
+  return GRASP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SDF grids
+// ---------------------------------------------------------------------------
+grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_id* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!d || !out || !d->values) return fail(GRASP_EINVAL, "desc/out/values is NULL");
+  if (d->n < 2 || d->n > 1024) return fail(GRASP_EINVAL, "n must be in [2, 1024]");
+  if (!(d->h > 0.0f) || !finite(d->h) || !finite(d->lo[0]) || !finite(d->lo[1]) || !finite(d->lo[2]))
+    return fail(GRASP_EINVAL, "h must be > 0 and lo finite");
+  const size_t n = static_cast<size_t>(d->n);
+  const size_t n3 = n * n * n;
+  size_t neg = 0;
+  for (size_t i = 0; i < n3; ++i) {
+    if (!finite(d->values[i])) return fail(GRASP_EINVAL, "SDF values must be finite");
+    neg += d->values[i] < 0.0f;
+  }
+  double Im = d->inertia_over_mass;
+  if (!(Im > 0.0)) {
+    // isotropic inertia of a uniform ball of the object's volume
+    const double hh = d->h;
+    const double V = hh * hh * hh * static_cast<double>(neg);
+    if (neg == 0) return fail(GRASP_EINVAL, "object has no interior vertex; give inertia_over_mass");
+    const double Req = std::cbrt(3.0 * V / (4.0 * M_PI));
+    Im = 0.4 * Req * Req;
+  }
+  const size_t nc = n - 1;
+  const size_t vbytes = round_up(n3 * sizeof(float), 256);
+  const size_t cbytes = nc * nc * nc * 8 * sizeof(float);
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  void* blk = ctx->arena.alloc(vbytes + cbytes);
+  if (!blk) return fail(GRASP_ENOMEM, "arena full (SDF grid)");
+  char* b = static_cast<char*>(blk);
+  hipError_t e = hipMemcpy(b, d->values, n3 * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, reinterpret_cast<float4*>(b + vbytes), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ctx->arena.free(blk);
+    return device_fail(ctx, e, "SDF upload");
+  }
+  auto s = std::make_unique<DevSdf>();
+  s->view.n = d->n;
+  s->view.lo[0] = d->lo[0];
+  s->view.lo[1] = d->lo[1];
+  s->view.lo[2] = d->lo[2];
+  s->view.h = d->h;
+  s->view.inv_h = 1.0f / d->h;
+  s->view.inv_Im = static_cast<float>(1.0 / Im);
+  s->view.values = reinterpret_cast<const float*>(b);
+  s->view.cells = reinterpret_cast<const float4*>(b + vbytes);
+  s->block = blk;
+  s->bytes = vbytes + cbytes;
+  s->inertia_over_mass = static_cast<float>(Im);
+  const uint64_t id = ctx->next_id++;
+  ctx->sdfs[id] = std::move(s);
+  *out = id;
+  return GRASP_OK;
+}
+
+grasp_status grasp_unload_sdf(grasp_ctx* ctx, grasp_sdf_id id) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DevSdf* s = find_sdf(ctx, id);
+  if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
+  if (s->live_jobs > 0) return fail(GRASP_EBUSY, "SDF in use by a live job");
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->arena.free(s->block);
+  ctx->sdfs.erase(id);
+  return GRASP_OK;
+}
+
+grasp_status grasp_sdf_inertia(grasp_ctx* ctx, grasp_sdf_id id, float* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!out) return fail(GRASP_EINVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DevSdf* s = find_sdf(ctx, id);
+  if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
+  *out = s->inertia_over_mass;
+  return GRASP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// steps
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct Resolved {
+  HandView hand;
+  SdfView sdf;
+  StepConsts prm;
+};
+
+grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const grasp_step_params* p, int32_t B,
+                     Resolved* r) {
+  if (B < 0) return fail(GRASP_EINVAL, "B must be >= 0");
+  grasp_status st = check_params(p, &r->prm);
+  if (st != GRASP_OK) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DevHand* h = find_hand(ctx, hid);
+  if (!h) return fail(GRASP_EINVAL, "unknown hand id");
+  DevSdf* s = find_sdf(ctx, sid);
+  if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
+  r->hand = h->view;
+  r->sdf = s->view;
+  return GRASP_OK;
+}
+
+size_t pose_ws_bytes(const StepConsts& c, int32_t B) {
+  return static_cast<size_t>(B) * kSims * pose_slots(c.K, c.ckpt) * 6 * sizeof(float);
+}
+
+StepArgs base_args(const Resolved& r, int32_t B) {
+  StepArgs a{};
+  a.hand = r.hand;
+  a.sdf = r.sdf;
+  a.prm = r.prm;
+  a.B = B;
+  return a;
+}
+
+AdamConsts adam_consts(int32_t t, float lr, float b1, float b2, float eps) {
+  AdamConsts c;
+  c.lr = lr;
+  c.b1 = b1;
+  c.b2 = b2;
+  c.eps = eps;
+  c.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(b1), t));
+  c.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), t));
+  return c;
+}
+
+grasp_status check_adam(int32_t t, float lr, float b1, float b2, float eps) {
+  if (t < 1) return fail(GRASP_EINVAL, "Adam step t must be >= 1");
+  if (!std::isfinite(lr) || !(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f) || !(eps >= 0.0f) ||
+      !std::isfinite(eps))
+    return fail(GRASP_EINVAL, "bad Adam hyper-parameters");
+  return GRASP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+grasp_status grasp_step_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                        const grasp_step_params* p, int32_t B, size_t* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!out) return fail(GRASP_EINVAL, "out is NULL");
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  *out = pose_ws_bytes(r.prm, B);
+  return GRASP_OK;
+}
+
+grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                            int32_t B, const float* q, float* loss, float* terms, void* ws, size_t ws_bytes,
+                            void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && (!q || !loss)) return fail(GRASP_EINVAL, "q/loss is NULL");
+  const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
+  if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
+    return fail(GRASP_ENOMEM, "workspace too small for SAVE mode");
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.loss = loss;
+  a.terms = terms;
+  a.poses = save ? static_cast<float*>(ws) : nullptr;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_step(a, STEP_FWD, false, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fwd launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                            int32_t B, const float* q, const float* dloss, float* dq, void* ws, size_t ws_bytes,
+                            void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && (!q || !dq)) return fail(GRASP_EINVAL, "q/dq is NULL");
+  const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
+  if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
+    return fail(GRASP_ENOMEM, "workspace too small for SAVE mode");
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.dloss = dloss;
+  a.dq = dq;
+  a.poses = save ? static_cast<float*>(ws) : nullptr;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_step(a, STEP_BWD, false, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_bwd launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_adam_step(grasp_ctx* ctx, int32_t n, float* q, float* m, float* v, const float* g, int32_t t,
+                             float lr, float b1, float b2, float eps, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (n < 0) return fail(GRASP_EINVAL, "n must be >= 0");
+  if (n > 0 && (!q || !m || !v || !g)) return fail(GRASP_EINVAL, "q/m/v/g is NULL");
+  grasp_status st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  DeviceGuard gd(ctx->device);
+  hipError_t e = launch_adam(n, q, m, v, g, adam_consts(t, lr, b1, b2, eps), static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_adam_step launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                              int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2,
+                              float eps, float* loss, float* terms, float* dq, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && (!q || !m || !v)) return fail(GRASP_EINVAL, "q/m/v is NULL");
+  st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.q_out = q;
+  a.m = m;
+  a.v = v;
+  a.loss = loss;
+  a.terms = terms;
+  a.dq = dq;
+  a.adam = adam_consts(t, lr, b1, b2, eps);
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_step(a, STEP_FUSED, true, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_debug_sdf_sample(grasp_ctx* ctx, grasp_sdf_id sdf, int32_t n, const float* r, float* out,
+                                    float* hess, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (n < 0 || (n > 0 && (!r || !out))) return fail(GRASP_EINVAL, "bad n / NULL r or out");
+  SdfView sv;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DevSdf* s = find_sdf(ctx, sdf);
+    if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
+    sv = s->view;
+  }
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_sample_points(sv, n, r, out, hess, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_sdf_sample launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                               int32_t B, const float* q, float* p_world, float* poses, float* samples,
+                               void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && !q) return fail(GRASP_EINVAL, "q is NULL");
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.trace_p = p_world;
+  a.trace_poses = poses;
+  a.trace_samples = samples;
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_step(a, STEP_FWD, false, 1, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_trace launch");
+  return GRASP_OK;
+}
+
+}  // extern "C"

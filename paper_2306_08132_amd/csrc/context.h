@@ -1,0 +1,99 @@
+// Host-side state of a grasp context: device arena, resident hands and SDF
+// grids, error reporting. Shared by the C-ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/grasp.h"
+#include "internal.h"
+
+namespace grasp {
+
+// Thread-local last-error text.
+void set_error(const std::string& msg);
+grasp_status fail(grasp_status code, const std::string& msg);
+
+// First-fit sub-allocator over one device range (256-byte granules).
+class Arena {
+ public:
+  void reset(char* base, size_t bytes);
+  void* alloc(size_t bytes);   // nullptr when no block fits
+  void free(void* p);
+  size_t capacity() const { return bytes_; }
+  size_t used() const;
+  size_t largest_free() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t bytes_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> size
+  std::map<size_t, size_t> used_;   // offset -> size
+};
+
+struct DevHand {
+  HandView view{};
+  void* block = nullptr;       // one arena block holding every array
+  size_t bytes = 0;
+  std::vector<int32_t> contact_link;  // caller order (host copy for validation)
+  int live_jobs = 0;
+};
+
+struct DevSdf {
+  SdfView view{};
+  void* block = nullptr;
+  size_t bytes = 0;
+  float inertia_over_mass = 0.0f;
+  int live_jobs = 0;
+};
+
+struct Scheduler;  // serving loop (sched.cpp)
+
+}  // namespace grasp
+
+struct grasp_ctx {
+  int device = 0;
+  char* arena_base = nullptr;
+  bool arena_owned = false;
+  grasp::Arena arena;
+  std::mutex mu;  // guards the arena and the object tables
+  std::map<uint64_t, std::unique_ptr<grasp::DevHand>> hands;
+  std::map<uint64_t, std::unique_ptr<grasp::DevSdf>> sdfs;
+  uint64_t next_id = 1;
+  std::atomic<bool> poisoned{false};
+  grasp::Scheduler* sched = nullptr;  // owned; created and destroyed in sched.cpp
+};
+
+namespace grasp {
+
+// Makes the context's device current for the scope and restores the
+// caller's device afterwards.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = -1;
+  bool ok_ = false;
+};
+
+// HIP failure: poison the context and report EDEVICE.
+grasp_status device_fail(grasp_ctx* ctx, hipError_t e, const char* where);
+
+// Looks up resident objects (caller holds ctx->mu).
+DevHand* find_hand(grasp_ctx* ctx, grasp_hand_id id);
+DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id);
+
+// Checks step parameters and fills the device constants.
+grasp_status check_params(const grasp_step_params* p, StepConsts* out);
+
+}  // namespace grasp

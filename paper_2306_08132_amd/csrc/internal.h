@@ -1,0 +1,118 @@
+// Internal declarations shared by the host library and the gfx950 kernels of
+// the grasp step. Not part of the public interface (see include/grasp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace grasp {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kSims = 7;         // M velocity tests: +x, -x, +y, -y, +z, -z, 0
+constexpr int kMaxLinks = 32;    // n_dof = 6 + (L - 1) <= 37 fits one wavefront
+constexpr int kMaxDof = kMaxLinks + 5;
+constexpr int kMaxDepth = 8;     // links on the path root -> leaf (root excluded)
+constexpr int kLinkStride = 16;  // floats per link transform slot in LDS (3x4 + pad)
+
+// A hand resident on the device. Contacts are re-laid out sorted by link, in
+// structure-of-arrays form, padded to whole 64-contact chunks.
+struct HandView {
+  int L;            // links; link 0 = palm
+  int n_dof;        // 6 + L - 1
+  int Nc;           // contacts
+  int n_chunks;     // ceil(Nc / 64)
+  const float* origin;    // [L][12] row-major 3x4: parent frame -> joint, at q = 0
+  const float* axis;      // [L][3] unit joint axis in the joint frame
+  const int* parent;      // [L]; parent[0] = -1
+  const int* chain;       // [L][kMaxDepth] links from the root's child down to l; -1 padded
+  const int* depth;       // [L] number of valid chain entries
+  const float* qlo;       // [n_dof]
+  const float* qup;       // [n_dof]
+  const float* cx;        // [n_chunks * 64] link-local contact coordinates, sorted by link
+  const float* cy;
+  const float* cz;
+  const int* clink;       // [n_chunks * 64] link of each sorted contact (0 in padding)
+  const int* chunk_lk;    // [n_chunks] first link | (last link << 16) of the chunk's valid contacts
+  const int* perm;        // [Nc] sorted slot -> caller index
+};
+
+// An object SDF resident on the device: vertex-centred N^3 grid, and the
+// same values re-laid out with each cell's 8 corners contiguous (32 B).
+struct SdfView {
+  int n;
+  float lo[3];
+  float h;
+  float inv_h;
+  float inv_Im;            // 1 / (I/m)
+  const float* values;     // [N^3], x fastest
+  const float4* cells;     // [(N-1)^3][2]: corners (000,100,010,110), (001,101,011,111)
+};
+
+// Device copy of the step parameters.
+struct StepConsts {
+  float dt, v0, omega, r_dil, alpha, w_stable, w_pen, w_range, w_limit, w_min;
+  int K;        // projection iterations
+  int ckpt;     // pose checkpoint interval (1 = every iteration kept)
+};
+
+struct AdamConsts {
+  float lr, b1, b2, eps;
+  float c1, c2;  // bias corrections 1 - b1^t, 1 - b2^t
+};
+
+// Per-wave LDS layout of the step kernel (floats): link transforms, joint
+// frames, link wrench adjoints, per-test constants, then pose checkpoints
+// (K/ckpt + 1 slots) and a replay buffer (ckpt slots), each slot 7 x 6.
+constexpr int kOffT = 0;                       // [kMaxLinks][12]
+constexpr int kOffJ = kOffT + kMaxLinks * 12;  // [kMaxLinks][6] joint world origin, world axis
+constexpr int kOffW = kOffJ + kMaxLinks * 6;   // [kMaxLinks][6] link force, torque adjoints
+constexpr int kUStride = 32;
+constexpr int kOffU = kOffW + kMaxLinks * 6;   // [7][32] per-test constants
+constexpr int kOffPose = kOffU + kSims * kUStride;
+
+__host__ __device__ inline int pose_slots(int K, int ckpt) { return K / ckpt + 1; }
+__host__ __device__ inline size_t wave_lds_floats(int K, int ckpt) {
+  const size_t f = static_cast<size_t>(kOffPose) + static_cast<size_t>(K / ckpt + 1 + ckpt) * kSims * 6;
+  return (f + 31) / 32 * 32;  // keep every wave's region 128-byte aligned
+}
+
+// What one launch of the step kernel does.
+enum StepKind : int {
+  STEP_FWD = 0,        // loss/terms; pose checkpoints to the workspace if given
+  STEP_BWD = 1,        // dq from saved checkpoints (or recomputed forward)
+  STEP_FUSED = 2,      // forward + backward (+ Adam) in one launch
+};
+
+struct StepArgs {
+  HandView hand;
+  SdfView sdf;
+  StepConsts prm;
+  AdamConsts adam;
+  int B;
+  const float* q;       // [B][n_dof]
+  float* q_out;         // Adam: updated q (may alias q)
+  float* m;             // Adam state [B][n_dof] (or null)
+  float* v;
+  float* loss;          // [B] (or null)
+  float* terms;         // [B][4] (or null)
+  float* dq;            // [B][n_dof] (or null)
+  const float* dloss;   // [B] (or null: 1)
+  float* poses;         // [B][7][slots][6] checkpoints (or null)
+  int* nonfinite;       // [1] set when any loss is not finite (or null)
+  // debug trace (caller order), all optional
+  float* trace_p;       // [B][Nc][3]
+  float* trace_poses;   // [B][7][K+1][6]
+  float* trace_samples; // [B][7][K][Nc][6] = d, g, w, lambda
+};
+
+hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, int waves_per_block,
+                       hipStream_t stream);
+hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
+                       hipStream_t stream);
+hipError_t launch_build_cells(const float* values, int n, float4* cells, hipStream_t stream);
+hipError_t launch_sample_points(const SdfView& s, int n, const float* r, float* out4, float* hess9,
+                                hipStream_t stream);
+
+}  // namespace grasp

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs. Tolerances: relative 1e-5 on SDF samples and contact
+positions, 1e-4 on losses, 1e-3 on gradients; exact on contact-to-link
+indexing and ranking. A sample within 2.5e-7 m of d = 0 (about five times
+the FP32 error of d at these coordinates) may take the other branch of the
+leaky rule in FP32; candidates holding one are reported and may not exceed a
+small fraction."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2306_08132_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+KINK_D = 2.5e-7  # metres: a sample this close to d = 0 may flip branch in FP32
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2306_08132_amd.api import Context
+    c = Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def f32(x):
+    """A parameter as the GPU receives it (FP32), widened for the oracle."""
+    return float(np.float32(x)) if isinstance(x, float) else x
+
+
+def prm_pair(**kw):
+    """(GPU params, oracle params) holding the same FP32 values."""
+    from paper_2306_08132_amd.api import StepParams
+    sp = StepParams(**kw)
+    op = O.Params()
+    for k in vars(op):
+        setattr(op, k, f32(getattr(sp, k)))
+    return sp, op
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    hand, grid, q = S.config_workload("tiny")
+    return hand, grid, q
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def ohand(hand):
+    return O.Hand(hand.rounded())
+
+
+@pytest.mark.parametrize("fj", [(3, 3, 512, 0), (4, 4, 1000, 1), (5, 4, 4096, 2), (2, 3, 70, 3)])
+def test_contact_links_exact(ctx, fj):
+    F, J, n, s = fj
+    say("contact links", fj)
+    hand = S.make_hand(F, J, n, seed=s)
+    h = ctx.hand(hand)
+    assert np.array_equal(h.contact_links(), hand.contact_link)
+
+
+@pytest.mark.parametrize("which", ["sphere64", "ellipsoids48", "mixed33"])
+def test_sdf_sampler_parity(ctx, which):
+    say("sampler", which)
+    if which == "sphere64":
+        g = S.make_grid(S.make_object("sphere", seed=0), 64)
+    elif which == "ellipsoids48":
+        g = S.make_grid(S.make_object("ellipsoids", seed=2), 48)
+    else:
+        g = S.make_grid(S.make_object("mixed", seed=3, n_prims=5), 33)
+    sd = ctx.sdf(g)
+    r = S.random_points(g, 20000, seed=7).astype(np.float32)
+    out, H = ctx.debug_sdf_sample(sd, dev(r), hess=True)
+    torch.cuda.synchronize()
+    out, H = out.cpu().numpy().astype(np.float64), H.cpu().numpy().astype(np.float64).reshape(-1, 3, 3)
+    phi, grad, Ho, margin = O.sample(O.Obj(g), r.astype(np.float64), hess=True)
+    tol_phi = 1e-5 * np.maximum(np.abs(phi), g.h)
+    assert np.all(np.abs(out[:, 0] - phi) <= tol_phi), np.max(np.abs(out[:, 0] - phi) / tol_phi)
+    ok = margin > 1e-4  # away from cell faces and the box boundary
+    gn = np.linalg.norm(grad, axis=1)
+    err = np.abs(out[:, 1:] - grad).max(axis=1)
+    assert np.all(err[ok] <= 1e-5 * np.maximum(gn[ok], 1.0)), np.max(err[ok])
+    scale = np.maximum(np.abs(Ho).reshape(-1, 9).max(axis=1), 1.0 / g.h)
+    herr = np.abs(H - Ho).reshape(-1, 9).max(axis=1)
+    assert np.all(herr[ok] <= 1e-4 * scale[ok]), np.max(herr[ok] / scale[ok])
+    say("  flagged near faces:", (~ok).mean())
+    assert inertia_close(ctx, sd, g)
+
+
+def inertia_close(ctx, sd, g):
+    return abs(sd.inertia_over_mass() - O.Obj(g).inertia_over_mass()) <= 1e-6 * O.Obj(g).inertia_over_mass()
+
+
+def test_fk_and_trace_parity(ctx, tiny):
+    hand, grid, q = tiny
+    say("fk/trace tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.004)
+    tr = ctx.debug_trace(h, sd, sp, dev(q[:16]))
+    torch.cuda.synchronize()
+    Hh, ob = ohand(hand), O.Obj(grid)
+    q32 = q[:16].astype(np.float32).astype(np.float64)
+    p_or = O.fk(Hh, q32)
+    p = tr["p"].cpu().numpy()
+    scale = np.maximum(np.abs(p_or).max(axis=(1, 2)), 0.01)
+    assert np.all(np.abs(p - p_or).max(axis=(1, 2)) <= 1e-5 * scale)
+    for b in range(4):
+        t = O.trace(Hh, ob, op, q32[b])
+        s_gpu = tr["samples"][b].cpu().numpy()
+        d_gpu, d_or = s_gpu[..., 0], t["samples"][..., 0]
+        assert np.all(np.abs(d_gpu - d_or) <= 1e-5 * np.maximum(np.abs(d_or), grid.h))
+        # non-penetrating samples contribute exactly zero
+        assert np.all(s_gpu[..., 5][d_gpu >= 0] == 0.0)
+        # pose components are sums over contacts that can cancel: the tolerance
+        # scales with the sum of the summands' magnitudes
+        pg = tr["poses"][b].cpu().numpy()
+        lam = np.abs(t["samples"][:, 0, :, 5])                      # [7][Nc]
+        gn = np.linalg.norm(t["samples"][:, 0, :, 1:4], axis=-1)
+        an = np.linalg.norm(p_or[b][None] - t["poses"][:, 0, None, :3], axis=-1)
+        Im = ob.inertia_over_mass()
+        lin = (lam * gn).sum(1)[:, None] + np.abs(t["poses"][:, 0, :3]).max()
+        ang = (lam * gn * an).sum(1)[:, None] / Im
+        err = np.abs(pg - t["poses"])[:, 1]
+        assert np.all(err[:, :3] <= 1e-5 * lin + 1e-9) and np.all(err[:, 3:] <= 1e-5 * ang + 1e-9)
+
+
+def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05):
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    B = q.shape[0]
+    qd = dev(q)
+    loss = torch.empty(B, device=DEV)
+    terms = torch.empty((B, 4), device=DEV)
+    nb = ctx.workspace_bytes(h, sd, sp, B)
+    ws = torch.empty(max(nb, 4), dtype=torch.uint8, device=DEV)
+    ctx.step_fwd(h, sd, sp, qd, loss, terms, ws=ws)
+    dq = torch.empty_like(qd)
+    ctx.step_bwd(h, sd, sp, qd, dq, ws=ws)
+    torch.cuda.synchronize()
+    loss, terms, dq = loss.cpu().numpy(), terms.cpu().numpy(), dq.cpu().numpy()
+    q32 = q.astype(np.float32).astype(np.float64)
+    ref = O.step(ohand(hand), O.Obj(grid), op, q32, grad=True, margins=True)
+    floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
+    lerr = np.abs(loss - ref["loss"]) / floor
+    gscale = np.abs(ref["grad"]).max(axis=1)
+    gerr = np.abs(dq - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30)
+    flagged = ref["min_abs_d"] < KINK_D
+    say(f"{label}: B={B} max loss rel err {lerr.max():.2e}, grad rel err max(unflagged) "
+        f"{gerr[~flagged].max() if (~flagged).any() else 0:.2e}, median {np.median(gerr):.2e}, "
+        f"flagged {flagged.mean():.3f} (their grad errs {np.round(gerr[flagged], 5).tolist()})")
+    assert np.all(lerr <= 1e-4), (np.argmax(lerr), lerr.max())
+    assert np.all(gerr[~flagged] <= 1e-3), (np.nonzero(~flagged)[0][np.argmax(gerr[~flagged])], gerr[~flagged].max())
+    assert flagged.mean() <= max_flagged
+    return loss, dq, ref
+
+
+def test_step_parity_tiny(ctx, tiny):
+    hand, grid, q = tiny
+    sp, op = prm_pair(r_dil=0.005)
+    compare_step(ctx, hand, grid, q, sp, op, "tiny r=5mm")
+    sp, op = prm_pair(r_dil=0.0, alpha_leak=0.0)
+    compare_step(ctx, hand, grid, q, sp, op, "tiny exact")
+
+
+def test_step_parity_ragged_and_small(ctx):
+    """Contact counts off the 64-lane chunk size, one-link hand, tiny grid."""
+    for F, J, n, N, B in [(3, 3, 65, 16, 5), (4, 4, 1000, 40, 9), (5, 4, 777, 33, 7)]:
+        hand = S.make_hand(F, J, n, seed=F + n)
+        grid = S.make_grid(S.make_object("ellipsoids", seed=n), N)
+        q = S.make_candidates(hand, B, seed=n, shell_radius=grid.bound_radius + 0.06)
+        sp, op = prm_pair(r_dil=0.003)
+        compare_step(ctx, hand, grid, q, sp, op, f"ragged {F}x{J} Nc={n}", max_flagged=0.2)
+
+
+def test_step_parity_iterations(ctx, tiny):
+    """K > 1 projection iterations, with and without pose checkpoints."""
+    hand, grid, q = tiny
+    outs = []
+    for K, ck in [(4, 1), (4, 2), (4, 4)]:
+        sp, op = prm_pair(K=K, ckpt_every=ck, r_dil=0.004)
+        loss, dq, _ = compare_step(ctx, hand, grid, q[:24], sp, op, f"K={K} ckpt={ck}", max_flagged=0.2)
+        outs.append((loss, dq))
+    for loss, dq in outs[1:]:
+        assert np.array_equal(loss, outs[0][0]) and np.array_equal(dq, outs[0][1])
+
+
+def test_save_recompute_and_fused_identical(ctx, tiny):
+    from paper_2306_08132_amd.api import MODE_RECOMPUTE, MODE_SAVE
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    B = 32
+    res = {}
+    for mode in (MODE_SAVE, MODE_RECOMPUTE):
+        sp, _ = prm_pair(r_dil=0.004, mode=mode)
+        qd = dev(q[:B])
+        loss = torch.empty(B, device=DEV)
+        ws = None
+        if mode == MODE_SAVE:
+            ws = torch.empty(ctx.workspace_bytes(h, sd, sp, B), dtype=torch.uint8, device=DEV)
+        ctx.step_fwd(h, sd, sp, qd, loss, ws=ws)
+        dq = torch.empty_like(qd)
+        ctx.step_bwd(h, sd, sp, qd, dq, ws=ws)
+        res[mode] = (loss.cpu().numpy(), dq.cpu().numpy())
+    assert np.array_equal(res[MODE_SAVE][0], res[MODE_RECOMPUTE][0])
+    assert np.array_equal(res[MODE_SAVE][1], res[MODE_RECOMPUTE][1])
+    # fused forward + backward + Adam equals the separate calls bit for bit
+    sp, _ = prm_pair(r_dil=0.004)
+    qf = dev(q[:B])
+    m = torch.zeros_like(qf)
+    v = torch.zeros_like(qf)
+    lf = torch.empty(B, device=DEV)
+    dqf = torch.empty_like(qf)
+    ctx.step_fused(h, sd, sp, qf, m, v, 1, loss=lf, dq=dqf)
+    qs = dev(q[:B])
+    ms, vs = torch.zeros_like(qs), torch.zeros_like(qs)
+    g = torch.tensor(res[MODE_SAVE][1], device=DEV)
+    ctx.adam(qs, ms, vs, g, 1)
+    torch.cuda.synchronize()
+    assert np.array_equal(lf.cpu().numpy(), res[MODE_SAVE][0])
+    assert np.array_equal(dqf.cpu().numpy(), res[MODE_SAVE][1])
+    assert torch.equal(qf, qs) and torch.equal(m, ms) and torch.equal(v, vs)
+
+
+def test_adam_parity(ctx):
+    q, m, v, g = S.adam_state(64, 22, seed=5)
+    for t in (1, 7, 300):
+        qd, md, vd, gd = (dev(a) for a in (q, m, v, g))
+        ctx.adam(qd, md, vd, gd, t)
+        torch.cuda.synchronize()
+        r = O.adam(*(a.astype(np.float32).astype(np.float64) for a in (q, m, v, g)), t,
+                   lr=f32(1e-3), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+        for got, want in zip((qd, md, vd), r):
+            np.testing.assert_allclose(got.cpu().numpy(), want, rtol=1e-6, atol=1e-7)
+
+
+def test_autograd_function(ctx, tiny):
+    from paper_2306_08132_amd.api import GraspStep
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.004)
+    qd = dev(q[:8]).requires_grad_(True)
+    w = torch.linspace(0.5, 2.0, 8, device=DEV)
+    (GraspStep.apply(qd, ctx, h, sd, sp) * w).sum().backward()
+    ref = O.step(ohand(hand), O.Obj(grid), op, q[:8].astype(np.float32).astype(np.float64))
+    want = ref["grad"] * w.cpu().numpy()[:, None]
+    err = np.abs(qd.grad.cpu().numpy() - want).max(axis=1) / np.abs(want).max(axis=1)
+    assert np.all(err <= 1e-3)
+
+
+def test_gradient_matches_finite_differences(ctx, tiny):
+    """The GPU adjoint against FP64 central differences of the oracle loss
+    (exact gradient, alpha = 0), outside kinks."""
+    hand, grid, q = tiny
+    sp, op = prm_pair(alpha_leak=0.0, r_dil=0.004)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    B = 8
+    qd = dev(q[:B])
+    loss = torch.empty(B, device=DEV)
+    dq = torch.empty_like(qd)
+    ctx.step_fwd(h, sd, sp, qd, loss)
+    ctx.step_bwd(h, sd, sp, qd, dq)
+    torch.cuda.synchronize()
+    fd, ex = O.fd_grad(ohand(hand), O.Obj(grid), op, q[:B].astype(np.float32).astype(np.float64), h=1e-6)
+    g = dq.cpu().numpy()
+    scale = np.abs(fd).max(axis=1, keepdims=True)
+    bad = (np.abs(g - fd) > 1e-3 * scale) & ~ex
+    say("fd excluded fraction", ex.mean())
+    assert not bad.any()
+
+
+def test_nonfinite_input_stays_in_bounds(ctx, tiny):
+    """NaN/Inf configurations give non-finite losses, never a bad access."""
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, _ = prm_pair()
+    qq = q[:4].copy()
+    qq[0, 0] = np.nan
+    qq[1, 7] = np.inf
+    qq[2, 3] = -np.inf
+    loss = torch.empty(4, device=DEV)
+    qd = dev(qq)
+    ctx.step_fwd(h, sd, sp, qd, loss)
+    dq = torch.empty_like(qd)
+    ctx.step_bwd(h, sd, sp, qd, dq)
+    torch.cuda.synchronize()
+    l = loss.cpu().numpy()
+    assert not np.isfinite(l[:3]).all() and np.isfinite(l[3])
+
+
+def test_full_size_diff_sampled(ctx):
+    """Full differentiable-step workload (4096 candidates, 2048 contacts,
+    128^3): fused launch as benchmarked, 8 sampled candidates vs the oracle."""
+    hand, grid, q = S.config_workload("diff")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.005)
+    B = q.shape[0]
+    qd = dev(q)
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    loss = torch.empty(B, device=DEV)
+    dq = torch.empty_like(qd)
+    ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(0).choice(B, 8, replace=False)
+    ref = O.step(ohand(hand), O.Obj(grid), op, q[idx].astype(np.float32).astype(np.float64), margins=True)
+    l, g = loss.cpu().numpy()[idx], dq.cpu().numpy()[idx]
+    lerr = np.abs(l - ref["loss"]) / np.maximum(np.abs(ref["loss"]), 1.0)
+    gerr = np.abs(g - ref["grad"]).max(axis=1) / np.abs(ref["grad"]).max(axis=1)
+    flagged = ref["min_abs_d"] < KINK_D
+    say("diff full: loss err", lerr.max(), "grad err", gerr, "flagged", flagged)
+    assert np.all(lerr <= 1e-4)
+    assert np.all(gerr[~flagged] <= 1e-3)
