@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-job form")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
+                         "the reference that scales HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the grasp step shards by "
@@ -100,6 +103,13 @@ def main():
     if not os.path.exists(_lib.LIB_PATH):
         from __graft_entry__ import build
         build()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print("bench: building the workload", file=sys.stderr, flush=True)
     hand, grid, q0 = S.config_workload("diff")
     B, Nc, nd, K = q0.shape[0], hand.n_contacts, hand.n_dof, 1
@@ -115,6 +125,9 @@ def main():
         prm = StepParams(K=K, r_dil=r0 * (1.0 - min(t, T_sched - 1) / (T_sched - 1)))
         ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
 
+    print("bench: tuning the launch tile", file=sys.stderr, flush=True)
+    tile, tile_ms = ctx.tune(h, sd, StepParams(K=K, r_dil=r0), q, reps=3)
+    print(f"bench: tile {tile} at {tile_ms:.3f} ms", file=sys.stderr, flush=True)
     print("bench: warmup", file=sys.stderr, flush=True)
     for t in range(args.warmup):
         step(t)
@@ -139,8 +152,29 @@ def main():
     print(f"bench: fused step {avg_ms:.3f} ms/launch, {value:.3e} contact-evals/s", file=sys.stderr, flush=True)
 
     plain = None
-    if not args.no_plain and hasattr(ctx, "plain_step"):
-        plain = ctx.plain_step_throughput(h, sd, q0, steps=max(3, args.steps // 5))
+    if not args.no_plain:
+        # the plain per-job form on the same candidates: unfused stages, HBM
+        # intermediates, one launch per stage per step, no graph
+        print("bench: plain per-job form", file=sys.stderr, flush=True)
+        qp = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
+        mp, vp = torch.zeros_like(qp), torch.zeros_like(qp)
+        prm0 = StepParams(K=K, r_dil=r0)
+        ws = ctx.plain_workspace(h, sd, prm0, B)
+        n_plain = max(3, args.steps // 5)
+        for t in range(2):
+            ctx.plain_step(h, sd, prm0, qp, mp, vp, t + 1, ws, loss=loss, stream=stream)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for t in range(n_plain):
+            prm = StepParams(K=K, r_dil=r0 * (1.0 - min(t, T_sched - 1) / (T_sched - 1)))
+            ctx.plain_step(h, sd, prm, qp, mp, vp, t + 3, ws, loss=loss, stream=stream)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - tp0) / n_plain
+        plain = {"value": evals / tp, "unit": "contact-evals/s", "ms_per_step": tp * 1e3, "steps": n_plain,
+                 "workspace_bytes": ws.numel(), "fused_over_plain": value / (evals / tp)}
+        del ws
+        print(f"bench: plain {tp * 1e3:.3f} ms/step, fused/plain {value / (evals / tp):.2f}x", file=sys.stderr,
+              flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -167,6 +201,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step<K=1> (fused)", "avg_launch_ms": avg_ms,
+                     "tile": {"waves_per_block": tile[0], "min_waves_per_simd": tile[1]},
                      "algorithmic_bytes_per_launch": abytes},
         "plain": plain,
         "cpu_baseline": cpu,

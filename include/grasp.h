@@ -39,6 +39,7 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+#pragma GCC visibility push(default)
 
 typedef int32_t grasp_status;
 enum {
@@ -189,6 +190,90 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
                               float* terms, float* dq, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * The plain per-job form: the same step (K = 1) as one unfused kernel per
+ * stage (link transforms, contact points, SDF samples, summed corrections,
+ * losses, contact adjoints, link sums, tree sweep, Adam) with every
+ * intermediate in the workspace. It is the baseline the fused and batched
+ * forms are measured against.
+ * ------------------------------------------------------------------------- */
+
+/* Host out: workspace bytes of grasp_plain_step for B candidates (EINVAL unless K = 1). */
+grasp_status grasp_plain_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                         const grasp_step_params* p, int32_t B, size_t* out);
+
+/* One optimizer step of B candidates: loss (dev [B]) and terms (dev [B][4]
+ * or NULL) at q, then Adam on q, m, v (dev [B][n_dof], in place) with step
+ * number t. ws: dev, 64-byte aligned, ws_bytes from grasp_plain_workspace_bytes
+ * (ENOMEM if smaller). */
+grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                              int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2,
+                              float eps, float* loss, float* terms, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Launch-shape tuning. A tile is the step kernel's launch shape; every tile
+ * computes bit-identical results, only speed differs.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t waves_per_block;     /* candidates per workgroup: 1, 2 or 4 */
+  int32_t min_waves_per_simd;  /* register budget: 1 (compiler's choice) .. 4 */
+} grasp_tile;
+
+/* Times every tile on a private copy of q (dev [B][n_dof]) with reps fused
+ * steps each, keeps the fastest for this shape (hand, grid, K, B) in the
+ * context, and returns it (host best, best_ms = ms per fused step). q is not
+ * modified. Tiles are also persisted to the file named by the environment
+ * variable GRASP_TUNE_CACHE when it is set. */
+grasp_status grasp_tune(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                        int32_t B, const float* q, int32_t reps, grasp_tile* best, float* best_ms);
+
+/* Pins a tile for this shape (overrides the tuner). EINVAL on a bad tile. */
+grasp_status grasp_set_tile(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                            int32_t B, const grasp_tile* tile);
+
+/* ---------------------------------------------------------------------------
+ * The batched form: many jobs, each its own hand, grid, candidate count and
+ * schedule position, advance one optimizer step in a single launch over a
+ * device job table (batching amortizes launch and tail cost, Sec. V-C reports
+ * the amortized time per grasp). On a non-default stream the launch is
+ * captured once per launch shape in a hipGraph and replayed every step.
+ * Each candidate is computed exactly as grasp_step_fused computes it, so a
+ * job's results do not depend on the other jobs in the step.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  grasp_hand_id hand;
+  grasp_sdf_id sdf;
+  grasp_step_params p;   /* p.r_dil is replaced by the schedule r0 (1 - t/(T-1)) */
+  int32_t B;             /* candidates, >= 1 */
+  float* q;              /* dev [B][n_dof], updated in place */
+  float* m;              /* dev [B][n_dof] Adam moments, updated in place */
+  float* v;
+  float* loss;           /* dev [B] or NULL: loss at the start of the step */
+  float* terms;          /* dev [B][4] or NULL */
+  int32_t t;             /* optimizer steps already taken; the call runs Adam step t + 1
+                            and increments t */
+  int32_t T;             /* schedule length (dilation reaches 0 at t = T - 1) */
+  float r0;              /* initial dilation radius */
+  float lr, b1, b2, eps; /* Adam */
+} grasp_batch_job;
+
+typedef struct grasp_batch grasp_batch; /* opaque */
+
+/* A batch able to hold up to capacity candidates in max_jobs jobs per step.
+ * use_graph = 0 launches eagerly. Allocates its job table in the arena. */
+grasp_status grasp_batch_create(grasp_ctx* ctx, int32_t capacity, int32_t max_jobs, int32_t use_graph,
+                                grasp_batch** out);
+grasp_status grasp_batch_destroy(grasp_batch* batch);
+/* Launch shape of the batched kernel (see grasp_tile). */
+grasp_status grasp_batch_set_tile(grasp_batch* batch, const grasp_tile* tile);
+/* One optimizer step for every job (host array jobs[n]; each job's t is
+ * incremented). The call waits for the previous step of this batch before
+ * rewriting the table, then queues the step on hip_stream. */
+grasp_status grasp_batch_step(grasp_batch* batch, grasp_batch_job* jobs, int32_t n, void* hip_stream);
+/* Host out[n]: per job (in the order of the last step's array) whether a loss
+ * was not finite since the previous call; clears the flags. Synchronous. */
+grasp_status grasp_batch_flags(grasp_batch* batch, int32_t n, int32_t* out);
+
+/* ---------------------------------------------------------------------------
  * Parity introspection (tests)
  * ------------------------------------------------------------------------- */
 
@@ -205,6 +290,7 @@ grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id 
                                const grasp_step_params* p, int32_t B, const float* q, float* p_world,
                                float* poses, float* samples, void* hip_stream);
 
+#pragma GCC visibility pop
 #ifdef __cplusplus
 }
 #endif

@@ -38,11 +38,22 @@ class SdfDesc(C.Structure):
                 ("values", C.POINTER(C.c_float)), ("inertia_over_mass", C.c_float)]
 
 
+class TileC(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("min_waves_per_simd", C.c_int32)]
+
+
 class StepParamsC(C.Structure):
     _fields_ = [("dt", C.c_float), ("v0", C.c_float), ("K", C.c_int32), ("ckpt_every", C.c_int32),
                 ("omega", C.c_float), ("r_dil", C.c_float), ("alpha_leak", C.c_float),
                 ("w_stable", C.c_float), ("w_pen", C.c_float), ("w_range", C.c_float),
                 ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32)]
+
+
+class BatchJobC(C.Structure):
+    _fields_ = [("hand", C.c_uint64), ("sdf", C.c_uint64), ("p", StepParamsC), ("B", C.c_int32),
+                ("q", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("loss", C.c_void_p),
+                ("terms", C.c_void_p), ("t", C.c_int32), ("T", C.c_int32), ("r0", C.c_float),
+                ("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float)]
 
 
 @dataclasses.dataclass
@@ -88,6 +99,16 @@ SIGNATURES = [
     ("grasp_adam_step", _I32, [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _F, _F, _F, _F, _VP]),
     ("grasp_step_fused", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F,
                                 _F, _VP, _VP, _VP, _VP]),
+    ("grasp_plain_workspace_bytes", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(_SZ)]),
+    ("grasp_plain_step", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F, _F,
+                                _VP, _VP, _VP, _SZ, _VP]),
+    ("grasp_tune", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _I32, C.POINTER(TileC), _FP]),
+    ("grasp_set_tile", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(TileC)]),
+    ("grasp_batch_create", _I32, [_VP, _I32, _I32, _I32, C.POINTER(_VP)]),
+    ("grasp_batch_destroy", _I32, [_VP]),
+    ("grasp_batch_set_tile", _I32, [_VP, C.POINTER(TileC)]),
+    ("grasp_batch_step", _I32, [_VP, _VP, _I32, _VP]),
+    ("grasp_batch_flags", _I32, [_VP, _I32, _IP]),
     ("grasp_debug_sdf_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP, _VP]),
     ("grasp_debug_trace", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _VP]),
 ]

@@ -11,11 +11,11 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (HandDesc, Library, SdfDesc, StepParams, MODE_AUTO, MODE_RECOMPUTE, MODE_SAVE,
-                   GraspError)
+from ._lib import (BatchJobC, HandDesc, Library, SdfDesc, StepParams, TileC, MODE_AUTO, MODE_RECOMPUTE,
+                   MODE_SAVE, GraspError)
 
-__all__ = ["Context", "Hand", "Sdf", "StepParams", "GraspStep", "GraspError", "MODE_AUTO",
-           "MODE_SAVE", "MODE_RECOMPUTE"]
+__all__ = ["Context", "Hand", "Sdf", "StepParams", "GraspStep", "GraspError", "Batch", "BatchJob",
+           "MODE_AUTO", "MODE_SAVE", "MODE_RECOMPUTE"]
 
 
 def _ptr(t):
@@ -95,6 +95,33 @@ class Context:
         pc = prm.c()
         self.lib.call("grasp_step_fused", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
                       _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
+
+    def plain_workspace(self, hand, sdf, prm: StepParams, B: int) -> torch.Tensor:
+        out = C.c_size_t()
+        pc = prm.c()
+        self.lib.call("grasp_plain_workspace_bytes", self.h, hand.id, sdf.id, C.byref(pc), B, C.byref(out))
+        return torch.empty(out.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def plain_step(self, hand, sdf, prm: StepParams, q, m, v, t: int, ws, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
+                   loss=None, terms=None, stream=None):
+        """The unfused per-job form: loss at q, then Adam on q, m, v in place."""
+        pc = prm.c()
+        self.lib.call("grasp_plain_step", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
+                      _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(ws), ws.numel(), _stream(stream))
+
+    def tune(self, hand, sdf, prm: StepParams, q, reps: int = 3):
+        """Times every launch tile on a copy of q; returns ((wpb, occ), ms per step)."""
+        pc = prm.c()
+        best = TileC()
+        ms = C.c_float()
+        self.lib.call("grasp_tune", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), reps, C.byref(best),
+                      C.byref(ms))
+        return (best.waves_per_block, best.min_waves_per_simd), ms.value
+
+    def set_tile(self, hand, sdf, prm: StepParams, B: int, wpb: int, occ: int):
+        pc = prm.c()
+        t = TileC(wpb, occ)
+        self.lib.call("grasp_set_tile", self.h, hand.id, sdf.id, C.byref(pc), B, C.byref(t))
 
     def debug_sdf_sample(self, sdf, r, hess: bool = False, stream=None):
         n = r.shape[0]
@@ -195,3 +222,55 @@ class GraspStep(torch.autograd.Function):
         dq = torch.empty_like(q)
         ctx.step_bwd(hand, sdf, prm, q, dq, dloss=dloss.contiguous().to(torch.float32), ws=ws)
         return dq, None, None, None, None
+
+
+class BatchJob:
+    """One job of a batched step: its resident hand and grid, parameters,
+    device tensors q, m, v (updated in place) and schedule position."""
+
+    def __init__(self, hand: Hand, sdf: Sdf, prm: StepParams, q, m=None, v=None, loss=None, terms=None,
+                 t: int = 0, T: int = 300, r0: float = 0.01, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.hand, self.sdf, self.prm = hand, sdf, prm
+        self.q = q
+        self.m = torch.zeros_like(q) if m is None else m
+        self.v = torch.zeros_like(q) if v is None else v
+        self.loss = torch.empty(q.shape[0], dtype=torch.float32, device=q.device) if loss is None else loss
+        self.terms = terms
+        self.t, self.T, self.r0 = t, T, r0
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+
+    def c(self) -> BatchJobC:
+        return BatchJobC(self.hand.id, self.sdf.id, self.prm.c(), self.q.shape[0], self.q.data_ptr(),
+                         self.m.data_ptr(), self.v.data_ptr(), self.loss.data_ptr(),
+                         None if self.terms is None else self.terms.data_ptr(), self.t, self.T, self.r0,
+                         self.lr, self.b1, self.b2, self.eps)
+
+
+class Batch:
+    """grasp_batch: one launch per optimizer step over many jobs."""
+
+    def __init__(self, ctx: Context, capacity: int, max_jobs: int = 64, use_graph: bool = True):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.lib.call("grasp_batch_create", ctx.h, capacity, max_jobs, int(use_graph), C.byref(h))
+        self.h = h
+
+    def set_tile(self, wpb: int, occ: int):
+        t = TileC(wpb, occ)
+        self.ctx.lib.call("grasp_batch_set_tile", self.h, C.byref(t))
+
+    def step(self, jobs, stream=None):
+        arr = (BatchJobC * len(jobs))(*[j.c() for j in jobs])
+        self.ctx.lib.call("grasp_batch_step", self.h, C.cast(arr, C.c_void_p), len(jobs), _stream(stream))
+        for j, c in zip(jobs, arr):
+            j.t = c.t
+
+    def flags(self, n: int) -> np.ndarray:
+        out = np.zeros(n, np.int32)
+        self.ctx.lib.call("grasp_batch_flags", self.h, n, out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.grasp_batch_destroy(self.h)
+            self.h = None

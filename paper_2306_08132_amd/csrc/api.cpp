@@ -3,7 +3,10 @@
 // that kernels only ever see shapes they were written for.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -149,6 +152,7 @@ grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
 using namespace grasp;
 
 namespace {
+void load_tile_cache(grasp_ctx* ctx);
 
 #define GRASP_CHECK_CTX(ctx)                                                        \
   do {                                                                              \
@@ -156,8 +160,6 @@ namespace {
     if ((ctx)->poisoned) return fail(GRASP_EDEVICE, "context poisoned by an earlier device error"); \
   } while (0)
 
-// Waves per workgroup of the step kernel (independent waves share nothing).
-constexpr int kStepWaves = 4;
 
 }  // namespace
 
@@ -193,6 +195,7 @@ grasp_status grasp_init(int device, void* arena_dev, size_t arena_bytes, grasp_c
     ctx->arena_owned = true;
   }
   ctx->arena.reset(ctx->arena_base, arena_bytes);
+  load_tile_cache(ctx);
   *out = ctx;
   return GRASP_OK;
 }
@@ -270,7 +273,7 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
   const int nch = (Nc + kWave - 1) / kWave;
   const int npad = nch * kWave;
   std::vector<float> cx(npad, 0.0f), cy(npad, 0.0f), cz(npad, 0.0f);
-  std::vector<int> clink(npad, 0), chunk(nch, 0);
+  std::vector<int> clink(npad, 0), chunk(nch, 0), link_start(L + 1, 0);
   for (int s = 0; s < Nc; ++s) {
     const int i = perm[s];
     cx[s] = d->contact_local[3 * i];
@@ -278,6 +281,8 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
     cz[s] = d->contact_local[3 * i + 2];
     clink[s] = d->contact_link[i];
   }
+  for (int s = 0; s < Nc; ++s) link_start[clink[s] + 1] = s + 1;
+  for (int l = 1; l <= L; ++l) link_start[l] = std::max(link_start[l], link_start[l - 1]);
   for (int c = 0; c < nch; ++c) {
     const int first = clink[c * kWave];
     const int last = clink[std::min(Nc, (c + 1) * kWave) - 1];
@@ -299,7 +304,7 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
       {cz.data(), cz.size() * 4, 0},         {parent.data(), parent.size() * 4, 0},
       {chain.data(), chain.size() * 4, 0},   {depth.data(), depth.size() * 4, 0},
       {clink.data(), clink.size() * 4, 0},   {chunk.data(), chunk.size() * 4, 0},
-      {perm.data(), perm.size() * 4, 0}};
+      {perm.data(), perm.size() * 4, 0},     {link_start.data(), link_start.size() * 4, 0}};
   size_t total = 0;
   for (auto& p : parts) { p.off = total; total += round_up(p.bytes, 256); }
   std::vector<char> host(total, 0);
@@ -336,6 +341,7 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
   h->view.clink = I(10);
   h->view.chunk_lk = I(11);
   h->view.perm = I(12);
+  h->view.link_start = I(13);
   h->block = blk;
   h->bytes = total;
   h->contact_link.assign(d->contact_link, d->contact_link + Nc);
@@ -497,6 +503,39 @@ grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const 
   return GRASP_OK;
 }
 
+// Problem shape that a tuned tile belongs to: iteration structure, hand and
+// grid sizes, and the candidate count rounded to a power of two.
+std::string shape_key(const Resolved& r, int32_t B) {
+  int bb = 1;
+  while (bb < B) bb <<= 1;
+  std::ostringstream os;
+  os << "K" << r.prm.K << "c" << r.prm.ckpt << "L" << r.hand.L << "N" << r.hand.Nc << "g" << r.sdf.n << "B" << bb;
+  return os.str();
+}
+
+TileCfg tile_for(grasp_ctx* ctx, const Resolved& r, int32_t B) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->tiles.find(shape_key(r, B));
+  return it == ctx->tiles.end() ? TileCfg{} : it->second;
+}
+
+void load_tile_cache(grasp_ctx* ctx) {
+  const char* path = std::getenv("GRASP_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string key;
+  TileCfg c;
+  while (f >> key >> c.wpb >> c.occ)
+    if (valid_tile(c)) ctx->tiles[key] = c;
+}
+
+void save_tile(const std::string& key, TileCfg c) {
+  const char* path = std::getenv("GRASP_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << c.wpb << " " << c.occ << "\n";
+}
+
 size_t pose_ws_bytes(const StepConsts& c, int32_t B) {
   return static_cast<size_t>(B) * kSims * pose_slots(c.K, c.ckpt) * 6 * sizeof(float);
 }
@@ -562,8 +601,9 @@ grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   a.loss = loss;
   a.terms = terms;
   a.poses = save ? static_cast<float*>(ws) : nullptr;
+  const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_FWD, false, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_step(a, STEP_FWD, false, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fwd launch");
   return GRASP_OK;
 }
@@ -585,8 +625,9 @@ grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   a.dloss = dloss;
   a.dq = dq;
   a.poses = save ? static_cast<float*>(ws) : nullptr;
+  const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_BWD, false, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_step(a, STEP_BWD, false, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_bwd launch");
   return GRASP_OK;
 }
@@ -625,9 +666,152 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   a.terms = terms;
   a.dq = dq;
   a.adam = adam_consts(t, lr, b1, b2, eps);
+  const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_FUSED, true, kStepWaves, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_step(a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_plain_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                         const grasp_step_params* p, int32_t B, size_t* out) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!out) return fail(GRASP_EINVAL, "out is NULL");
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (r.prm.K != 1) return fail(GRASP_EINVAL, "the plain form runs one projection iteration (K = 1)");
+  *out = plain_workspace_floats(r.hand, B) * sizeof(float);
+  return GRASP_OK;
+}
+
+grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                              int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2,
+                              float eps, float* loss, float* terms, void* ws, size_t ws_bytes, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (r.prm.K != 1) return fail(GRASP_EINVAL, "the plain form runs one projection iteration (K = 1)");
+  if (B > 0 && (!q || !m || !v || !loss || !ws)) return fail(GRASP_EINVAL, "q/m/v/loss/ws is NULL");
+  st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  if (ws_bytes < plain_workspace_floats(r.hand, B) * sizeof(float))
+    return fail(GRASP_ENOMEM, "workspace too small for the plain form");
+  if (reinterpret_cast<uintptr_t>(ws) % 64 != 0) return fail(GRASP_EINVAL, "workspace must be 64-byte aligned");
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  float* dq = nullptr;
+  hipError_t e = launch_plain_step(r.hand, r.sdf, r.prm, B, q, loss, terms, static_cast<float*>(ws), &dq, s);
+  if (e == hipSuccess) e = launch_adam(B * r.hand.n_dof, q, m, v, dq, adam_consts(t, lr, b1, b2, eps), s);
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_plain_step launch");
+  return GRASP_OK;
+}
+
+}  // extern "C"
+
+namespace grasp {
+// Checks one batch job and resolves its hand and grid (used by batch.cpp).
+grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c) {
+  if (j.B < 1 || !j.q || !j.m || !j.v) return fail(GRASP_EINVAL, "batch job needs B >= 1 and q, m, v");
+  if (j.t < 0 || j.T < 1 || !(j.r0 >= 0.0f) || !std::isfinite(j.r0)) return fail(GRASP_EINVAL, "bad job schedule");
+  grasp_status st = check_adam(j.t + 1, j.lr, j.b1, j.b2, j.eps);
+  if (st != GRASP_OK) return st;
+  Resolved r;
+  st = resolve(ctx, j.hand, j.sdf, &j.p, j.B, &r);
+  if (st != GRASP_OK) return st;
+  *h = r.hand;
+  *s = r.sdf;
+  *c = r.prm;
+  return GRASP_OK;
+}
+}  // namespace grasp
+
+extern "C" {
+
+grasp_status grasp_set_tile(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                            int32_t B, const grasp_tile* tile) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  if (!tile) return fail(GRASP_EINVAL, "tile is NULL");
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  const TileCfg c{tile->waves_per_block, tile->min_waves_per_simd};
+  if (!valid_tile(c)) return fail(GRASP_EINVAL, "tile must have waves_per_block in {1,2,4} and min_waves_per_simd in 1..4");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->tiles[shape_key(r, B)] = c;
+  return GRASP_OK;
+}
+
+grasp_status grasp_tune(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                        int32_t B, const float* q, int32_t reps, grasp_tile* best, float* best_ms) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (B < 1 || !q || reps < 1) return fail(GRASP_EINVAL, "tune needs B >= 1, q and reps >= 1");
+  const size_t nq = static_cast<size_t>(B) * r.hand.n_dof * sizeof(float);
+  void* blk = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    blk = ctx->arena.alloc(3 * nq + 256);
+  }
+  if (!blk) return fail(GRASP_ENOMEM, "arena full (tuning scratch)");
+  char* b = static_cast<char*>(blk);
+  float* sq = reinterpret_cast<float*>(b);
+  float* sm = reinterpret_cast<float*>(b + nq);
+  float* sv = reinterpret_cast<float*>(b + 2 * nq);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipStreamCreate(&s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  StepArgs a = base_args(r, B);
+  a.q = sq;
+  a.q_out = sq;
+  a.m = sm;
+  a.v = sv;
+  a.adam = adam_consts(1, 1e-3f, 0.9f, 0.999f, 1e-8f);
+  TileCfg bestc{};
+  float bestt = 1e30f;
+  for (int wpb : {1, 2, 4}) {
+    for (int occ = 1; occ <= 4 && e == hipSuccess; ++occ) {
+      const TileCfg c{wpb, occ};
+      e = hipMemcpyAsync(sq, q, nq, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemsetAsync(sm, 0, 2 * nq, s);
+      if (e == hipSuccess) e = launch_step(a, STEP_FUSED, true, c, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_step(a, STEP_FUSED, true, c, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms / reps < bestt) {
+        bestt = ms / reps;
+        bestc = c;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->arena.free(blk);
+    if (e == hipSuccess) ctx->tiles[shape_key(r, B)] = bestc;
+  }
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_tune");
+  save_tile(shape_key(r, B), bestc);
+  if (best) {
+    best->waves_per_block = bestc.wpb;
+    best->min_waves_per_simd = bestc.occ;
+  }
+  if (best_ms) *best_ms = bestt;
   return GRASP_OK;
 }
 
@@ -664,7 +848,7 @@ grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id 
   a.trace_poses = poses;
   a.trace_samples = samples;
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_FWD, false, 1, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_step(a, STEP_FWD, false, TileCfg{1, 1}, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_trace launch");
   return GRASP_OK;
 }

@@ -68,6 +68,7 @@ struct grasp_ctx {
   std::map<uint64_t, std::unique_ptr<grasp::DevSdf>> sdfs;
   uint64_t next_id = 1;
   std::atomic<bool> poisoned{false};
+  std::map<std::string, grasp::TileCfg> tiles;  // tuned launch shapes per problem shape
   grasp::Scheduler* sched = nullptr;  // owned; created and destroyed in sched.cpp
 };
 

@@ -1,0 +1,314 @@
+// Device-side building blocks shared by the fused and the plain grasp-step
+// kernels: wavefront reductions, small vector algebra, the SDF grid sample
+// with its second derivative, and the object-rotation exponential with its
+// vector-Jacobian product.
+#pragma once
+
+#include "internal.h"
+
+// Every multiply-add that is fused is written as fmaf: the arithmetic of a
+// candidate is then the same in every tile variant and launch form, so a
+// candidate's result does not depend on how it was scheduled.
+#pragma clang fp contract(off)
+
+namespace grasp {
+namespace dev {
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Butterfly sum over the 64 lanes: pairwise within quads, then mirrored
+// half-rows and rows (DPP), then across rows. Every lane ends with the
+// same bits (each step adds a value and its partner's, which commute).
+__device__ __forceinline__ float wave_sum(float x) {
+  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);  // row_half_mirror
+  x += dpp_f<0x140>(x);  // row_mirror
+  x += __shfl_xor(x, 16);
+  x += __shfl_xor(x, 32);
+  return x;
+}
+
+// Makes this wave's earlier LDS writes visible to its later LDS reads from
+// other lanes, and keeps the compiler from moving memory operations across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return {fmaf(a.y, b.z, -(a.z * b.y)), fmaf(a.z, b.x, -(a.x * b.z)), fmaf(a.x, b.y, -(a.y * b.x))};
+}
+// s a + b
+__device__ __forceinline__ V3 axpy(float s, V3 a, V3 b) { return {fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
+// y = M x and y = M^T x for a row-major 3x3 M
+__device__ __forceinline__ V3 mul(const float* M, V3 v) {
+  return {fmaf(M[0], v.x, fmaf(M[1], v.y, M[2] * v.z)), fmaf(M[3], v.x, fmaf(M[4], v.y, M[5] * v.z)),
+          fmaf(M[6], v.x, fmaf(M[7], v.y, M[8] * v.z))};
+}
+__device__ __forceinline__ V3 mul_t(const float* M, V3 v) {
+  return {fmaf(M[0], v.x, fmaf(M[3], v.y, M[6] * v.z)), fmaf(M[1], v.x, fmaf(M[4], v.y, M[7] * v.z)),
+          fmaf(M[2], v.x, fmaf(M[5], v.y, M[8] * v.z))};
+}
+// hardware reciprocal and reciprocal square root (about 1 ulp)
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// ---------------------------------------------------------------------------
+// SDF sample: trilinear value and analytic gradient of the vertex-centred
+// grid; outside the box, the clamped sample plus the distance to the box.
+// ---------------------------------------------------------------------------
+struct Sample {
+  float phi;
+  V3 n;          // gradient of phi in the object frame
+  // kept for the second derivative (penetrating samples in the adjoint)
+  float dx00, dx10, dx01, dx11;    // x-differences of the 4 corner rows
+  float dyx0, dyx1;                 // (v011-v001)-(v010-v000), (v111-v101)-(v110-v100)
+  float fx, fy, fz;
+  V3 e;          // offset from the clamped point (0 inside)
+  float inv_ne;  // 1/|e| (0 inside)
+  bool clx, cly, clz;
+};
+
+__device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
+  const float top = static_cast<float>(S.n - 1);
+  // u stays a rounded product: contracting it into the clamp residual below
+  // would turn an interior point's exact zero offset into a rounding residue
+  const float ux = __fmul_rn(r.x - S.lo[0], S.inv_h);
+  const float uy = __fmul_rn(r.y - S.lo[1], S.inv_h);
+  const float uz = __fmul_rn(r.z - S.lo[2], S.inv_h);
+  const float bx = fminf(fmaxf(ux, 0.0f), top);
+  const float by = fminf(fmaxf(uy, 0.0f), top);
+  const float bz = fminf(fmaxf(uz, 0.0f), top);
+  const int cm = S.n - 2;
+  const int ix = min(max(static_cast<int>(floorf(bx)), 0), cm);
+  const int iy = min(max(static_cast<int>(floorf(by)), 0), cm);
+  const int iz = min(max(static_cast<int>(floorf(bz)), 0), cm);
+  s.fx = bx - static_cast<float>(ix);
+  s.fy = by - static_cast<float>(iy);
+  s.fz = bz - static_cast<float>(iz);
+  const int nc = S.n - 1;
+  const int cell = (iz * nc + iy) * nc + ix;
+  const float4 lo4 = S.cells[2 * cell];
+  const float4 hi4 = S.cells[2 * cell + 1];
+  // corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
+  s.dx00 = lo4.y - lo4.x;
+  s.dx10 = lo4.w - lo4.z;
+  s.dx01 = hi4.y - hi4.x;
+  s.dx11 = hi4.w - hi4.z;
+  const float c00 = fmaf(s.fx, s.dx00, lo4.x);
+  const float c10 = fmaf(s.fx, s.dx10, lo4.z);
+  const float c01 = fmaf(s.fx, s.dx01, hi4.x);
+  const float c11 = fmaf(s.fx, s.dx11, hi4.z);
+  const float dy0 = c10 - c00, dy1 = c11 - c01;
+  const float c0 = fmaf(s.fy, dy0, c00), c1 = fmaf(s.fy, dy1, c01);
+  const float gz = c1 - c0;
+  const float gy = fmaf(s.fz, dy1 - dy0, dy0);
+  const float gx0 = fmaf(s.fy, s.dx10 - s.dx00, s.dx00);
+  const float gx1 = fmaf(s.fy, s.dx11 - s.dx01, s.dx01);
+  const float gx = fmaf(s.fz, gx1 - gx0, gx0);
+  s.dyx0 = (hi4.z - hi4.x) - (lo4.z - lo4.x);
+  s.dyx1 = (hi4.w - hi4.y) - (lo4.w - lo4.y);
+  s.clx = ux != bx;
+  s.cly = uy != by;
+  s.clz = uz != bz;
+  s.phi = fmaf(s.fz, gz, c0);
+  s.n = v3(s.clx ? 0.0f : gx * S.inv_h, s.cly ? 0.0f : gy * S.inv_h, s.clz ? 0.0f : gz * S.inv_h);
+  s.e = v3(s.clx ? (ux - bx) * S.h : 0.0f, s.cly ? (uy - by) * S.h : 0.0f, s.clz ? (uz - bz) * S.h : 0.0f);
+  const float ee = dot(s.e, s.e);
+  s.inv_ne = 0.0f;
+  if (ee > 0.0f) {
+    s.inv_ne = rsq(ee);
+    s.phi += ee * s.inv_ne;
+    s.n = axpy(s.inv_ne, s.e, s.n);
+  }
+}
+
+// H v with H = d(grad phi)/dr of the sample: mixed partials of the trilinear
+// blend on unclamped axes, plus (I - e e^T/|e|^2)/|e| on clamped axes.
+__device__ __forceinline__ V3 hess_mul(const SdfView& S, const Sample& s, V3 v) {
+  const float ih2 = S.inv_h * S.inv_h;
+  float hxy = fmaf(s.fz, (s.dx11 - s.dx01) - (s.dx10 - s.dx00), s.dx10 - s.dx00) * ih2;
+  float hxz = fmaf(s.fy, (s.dx11 - s.dx10) - (s.dx01 - s.dx00), s.dx01 - s.dx00) * ih2;
+  float hyz = fmaf(s.fx, s.dyx1 - s.dyx0, s.dyx0) * ih2;
+  if (s.clx || s.cly) hxy = 0.0f;
+  if (s.clx || s.clz) hxz = 0.0f;
+  if (s.cly || s.clz) hyz = 0.0f;
+  V3 out = v3(fmaf(hxy, v.y, hxz * v.z), fmaf(hxy, v.x, hyz * v.z), fmaf(hxz, v.x, hyz * v.y));
+  if (s.inv_ne > 0.0f) {
+    const V3 eh = s.inv_ne * s.e;
+    const float ev = dot(eh, v);
+    out.x += s.clx ? fmaf(-eh.x, ev, v.x) * s.inv_ne : 0.0f;
+    out.y += s.cly ? fmaf(-eh.y, ev, v.y) * s.inv_ne : 0.0f;
+    out.z += s.clz ? fmaf(-eh.z, ev, v.z) * s.inv_ne : 0.0f;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// object orientation: R(theta) = I + A [t]x + B [t]x^2 and the derivatives
+// A' = dA/ds, B' = dB/ds with s = |t|^2; power series below |t| = 0.5
+// ---------------------------------------------------------------------------
+struct Rot {
+  float R[9];
+  V3 th;
+  float A, B, Ap, Bp;
+};
+
+__device__ __forceinline__ void make_rot(V3 th, Rot& o) {
+  const float s = dot(th, th);
+  if (s < 0.25f) {
+    o.A = 1.0f + s * (-1.0f / 6 + s * (1.0f / 120 + s * (-1.0f / 5040 + s * (1.0f / 362880))));
+    o.B = 0.5f + s * (-1.0f / 24 + s * (1.0f / 720 + s * (-1.0f / 40320 + s * (1.0f / 3628800))));
+    o.Ap = -1.0f / 6 + s * (1.0f / 60 + s * (-1.0f / 1680 + s * (1.0f / 90720)));
+    o.Bp = -1.0f / 24 + s * (1.0f / 360 + s * (-1.0f / 13440 + s * (1.0f / 907200)));
+  } else {
+    const float t = sqrtf(s);
+    float sn, cs;
+    sincosf(t, &sn, &cs);
+    o.A = sn / t;
+    o.B = (1.0f - cs) / s;
+    o.Ap = (t * cs - sn) / (2.0f * s * t);
+    o.Bp = (t * sn - 2.0f * (1.0f - cs)) / (2.0f * s * s);
+  }
+  o.th = th;
+  const float x = th.x, y = th.y, z = th.z;
+  // [t]x^2 = t t^T - s I
+  o.R[0] = 1.0f + o.B * (x * x - s);
+  o.R[1] = -o.A * z + o.B * x * y;
+  o.R[2] = o.A * y + o.B * x * z;
+  o.R[3] = o.A * z + o.B * x * y;
+  o.R[4] = 1.0f + o.B * (y * y - s);
+  o.R[5] = -o.A * x + o.B * y * z;
+  o.R[6] = -o.A * y + o.B * x * z;
+  o.R[7] = o.A * x + o.B * y * z;
+  o.R[8] = 1.0f + o.B * (z * z - s);
+}
+
+// d/dphi of y = R(phi) v contracted with yb, at phi = sgn * theta.
+__device__ __forceinline__ V3 rot_vjp(const Rot& o, float sgn, V3 v, V3 yb) {
+  const V3 ph = sgn * o.th;
+  const V3 tv = cross(ph, v);
+  const V3 ttv = cross(ph, tv);
+  const float c = 2.0f * o.Ap * dot(yb, tv) + 2.0f * o.Bp * dot(yb, ttv);
+  const V3 a = cross(v, yb);
+  const float pv = dot(ph, v), py = dot(ph, yb), vy = dot(v, yb);
+  return v3(c * ph.x + o.A * a.x + o.B * (pv * yb.x + v.x * py - 2.0f * ph.x * vy),
+            c * ph.y + o.A * a.y + o.B * (pv * yb.y + v.y * py - 2.0f * ph.y * vy),
+            c * ph.z + o.A * a.z + o.B * (pv * yb.z + v.z * py - 2.0f * ph.z * vy));
+}
+
+// Test point of velocity test m before any correction (a = p - dt v0 dir_m):
+// exactly one coordinate moves, so the other two (and their grid
+// coordinates) are shared by the tests of one contact.
+__device__ __forceinline__ V3 test_point(V3 p, int m, float dv) {
+  V3 a = p;
+  if (m == 0) a.x = p.x - dv;
+  else if (m == 1) a.x = p.x + dv;
+  else if (m == 2) a.y = p.y - dv;
+  else if (m == 3) a.y = p.y + dv;
+  else if (m == 4) a.z = p.z - dv;
+  else if (m == 5) a.z = p.z + dv;
+  return a;
+}
+
+__device__ __forceinline__ V3 sim_dir(int m) {
+  return v3(m == 0 ? 1.0f : (m == 1 ? -1.0f : 0.0f), m == 2 ? 1.0f : (m == 3 ? -1.0f : 0.0f),
+            m == 4 ? 1.0f : (m == 5 ? -1.0f : 0.0f));
+}
+
+// Pose of link l for configuration qb (Sec. III-C, p = FK(q)), composed along
+// its chain from the wrist: T_0 = Trans(q0..2) Rz(q3) Ry(q4) Rx(q5), then
+// T_a = T_parent(a) O_a Rot(axis_a, q_{5+a}) for each link a down to l.
+// Writes T (row-major 3x4) and Jw = (world origin, world axis) of joint l
+// (for the palm: the wrist origin and a zero axis).
+__device__ __forceinline__ void link_transform(const HandView& H, const float* qb, int l, float* T, float* Jw) {
+  float R[9], t[3];
+  {
+    float s3, c3, s4, c4, s5, c5;
+    sincosf(qb[3], &s3, &c3);
+    sincosf(qb[4], &s4, &c4);
+    sincosf(qb[5], &s5, &c5);
+    R[0] = c3 * c4; R[1] = fmaf(c3 * s4, s5, -(s3 * c5)); R[2] = fmaf(c3 * s4, c5, s3 * s5);
+    R[3] = s3 * c4; R[4] = fmaf(s3 * s4, s5, c3 * c5);    R[5] = fmaf(s3 * s4, c5, -(c3 * s5));
+    R[6] = -s4;     R[7] = c4 * s5;                        R[8] = c4 * c5;
+    t[0] = qb[0]; t[1] = qb[1]; t[2] = qb[2];
+  }
+  if (l == 0) {
+    Jw[0] = t[0]; Jw[1] = t[1]; Jw[2] = t[2]; Jw[3] = 0.0f; Jw[4] = 0.0f; Jw[5] = 0.0f;
+  }
+  const int dep = H.depth[l];
+  for (int s = 0; s < dep; ++s) {
+    const int a = H.chain[l * kMaxDepth + s];
+    const float* O = H.origin + 12 * a;
+    float JR[9], Jt[3];
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j)
+        JR[3 * i + j] = fmaf(R[3 * i], O[j], fmaf(R[3 * i + 1], O[4 + j], R[3 * i + 2] * O[8 + j]));
+      Jt[i] = fmaf(R[3 * i], O[3], fmaf(R[3 * i + 1], O[7], fmaf(R[3 * i + 2], O[11], t[i])));
+    }
+    const V3 k = v3(H.axis[3 * a], H.axis[3 * a + 1], H.axis[3 * a + 2]);
+    float sn, cs;
+    sincosf(qb[5 + a], &sn, &cs);
+    const float oc = 1.0f - cs;
+    // Rodrigues: I + sin [k]x + (1 - cos) [k]x^2, with [k]x^2 = k k^T - I
+    const float Q[9] = {fmaf(oc, fmaf(k.x, k.x, -1.0f), 1.0f), fmaf(oc, k.x * k.y, -(sn * k.z)),
+                        fmaf(oc, k.x * k.z, sn * k.y),         fmaf(oc, k.x * k.y, sn * k.z),
+                        fmaf(oc, fmaf(k.y, k.y, -1.0f), 1.0f), fmaf(oc, k.y * k.z, -(sn * k.x)),
+                        fmaf(oc, k.x * k.z, -(sn * k.y)),      fmaf(oc, k.y * k.z, sn * k.x),
+                        fmaf(oc, fmaf(k.z, k.z, -1.0f), 1.0f)};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        R[3 * i + j] = fmaf(JR[3 * i], Q[j], fmaf(JR[3 * i + 1], Q[3 + j], JR[3 * i + 2] * Q[6 + j]));
+    t[0] = Jt[0]; t[1] = Jt[1]; t[2] = Jt[2];
+    if (s == dep - 1) {
+      const V3 kw = mul(JR, k);
+      Jw[0] = Jt[0]; Jw[1] = Jt[1]; Jw[2] = Jt[2]; Jw[3] = kw.x; Jw[4] = kw.y; Jw[5] = kw.z;
+    }
+  }
+  T[0] = R[0]; T[1] = R[1]; T[2] = R[2];  T[3] = t[0];
+  T[4] = R[3]; T[5] = R[4]; T[6] = R[5];  T[7] = t[1];
+  T[8] = R[6]; T[9] = R[7]; T[10] = R[8]; T[11] = t[2];
+}
+
+// World position of a link-local point under a row-major 3x4 transform.
+__device__ __forceinline__ V3 xform_point(float4 r0, float4 r1, float4 r2, float lx, float ly, float lz) {
+  return v3(fmaf(r0.x, lx, fmaf(r0.y, ly, fmaf(r0.z, lz, r0.w))),
+            fmaf(r1.x, lx, fmaf(r1.y, ly, fmaf(r1.z, lz, r1.w))),
+            fmaf(r2.x, lx, fmaf(r2.y, ly, fmaf(r2.z, lz, r2.w))));
+}
+
+// Gradient of the loss w.r.t. joint j from the subtree wrench (f, tau about
+// the world origin) of the link it drives: revolute joints turn about their
+// world axis through their world origin o, tau_o = tau - o x f. Wrist joints
+// 0..2 translate; 3..5 turn about z, Rz y and Rz Ry x through the wrist origin.
+__device__ __forceinline__ float joint_torque(int j, const float* qb, V3 f, V3 tau, V3 o, V3 ax) {
+  if (j < 3) return j == 0 ? f.x : (j == 1 ? f.y : f.z);
+  const V3 tq = tau - cross(o, f);
+  if (j >= 6) return dot(ax, tq);
+  float s3, c3, s4, c4;
+  sincosf(qb[3], &s3, &c3);
+  sincosf(qb[4], &s4, &c4);
+  V3 w;
+  if (j == 3) w = v3(0.0f, 0.0f, 1.0f);
+  else if (j == 4) w = v3(-s3, c3, 0.0f);
+  else w = v3(c3 * c4, s3 * c4, -s4);
+  return dot(w, tq);
+}
+
+}  // namespace dev
+}  // namespace grasp

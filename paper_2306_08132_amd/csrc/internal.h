@@ -35,6 +35,7 @@ struct HandView {
   const float* cz;
   const int* clink;       // [n_chunks * 64] link of each sorted contact (0 in padding)
   const int* chunk_lk;    // [n_chunks] first link | (last link << 16) of the chunk's valid contacts
+  const int* link_start;  // [L + 1] first sorted contact of each link
   const int* perm;        // [Nc] sorted slot -> caller index
 };
 
@@ -107,8 +108,40 @@ struct StepArgs {
   float* trace_samples; // [B][7][K][Nc][6] = d, g, w, lambda
 };
 
-hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, int waves_per_block,
-                       hipStream_t stream);
+// Launch shape of the step kernel: waves (candidates) per workgroup and the
+// minimum waves per SIMD its registers must allow. Every shape computes the
+// same bits; only speed differs.
+struct TileCfg {
+  int wpb = 4;
+  int occ = 1;
+};
+bool valid_tile(TileCfg c);
+
+hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream);
+// The plain per-job form (one projection iteration): workspace floats and
+// the unfused stage kernels; *dq_out receives the workspace slot holding dq.
+size_t plain_workspace_floats(const HandView& H, int B);
+hipError_t launch_plain_step(const HandView& H, const SdfView& S, const StepConsts& P, int B, const float* q,
+                             float* loss, float* terms, float* ws, float** dq_out, hipStream_t stream);
+
+// Batched form: a device table of jobs, each one StepArgs for a fused step of
+// its B candidates; items [begin, begin + B) of the shared work range.
+struct BatchJob {
+  StepArgs args;
+  int begin;
+  int pad[3];
+};
+struct BatchHeader {
+  int n_jobs;
+  int total;  // sum of B over the table
+  int pad[2];
+};
+// Launches `blocks` workgroups over the table's items (waves past the total
+// exit); kone selects the one-iteration kernel (every job in the table must
+// agree on it).
+hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
+                        int lds_floats, hipStream_t stream);
+
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);
 hipError_t launch_build_cells(const float* values, int n, float4* cells, hipStream_t stream);

@@ -9,220 +9,13 @@
 // losses) is a wavefront reduction in a fixed order, so a candidate's result
 // is bit-identical whatever else runs on the GPU. No workgroup barrier is
 // used: waves never wait on each other.
-#include "internal.h"
+#include "device_common.h"
 
 namespace grasp {
 
 namespace {
+using namespace dev;
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// Butterfly sum over the 64 lanes: pairwise within quads, then mirrored
-// half-rows and rows (DPP), then across rows. Every lane ends with the
-// same bits (each step adds a value and its partner's, which commute).
-__device__ __forceinline__ float wave_sum(float x) {
-  x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp_f<0x141>(x);  // row_half_mirror
-  x += dpp_f<0x140>(x);  // row_mirror
-  x += __shfl_xor(x, 16);
-  x += __shfl_xor(x, 32);
-  return x;
-}
-
-// Makes this wave's earlier LDS writes visible to its later LDS reads from
-// other lanes, and keeps the compiler from moving memory operations across.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-struct V3 {
-  float x, y, z;
-};
-__device__ __forceinline__ V3 v3(float x, float y, float z) { return {x, y, z}; }
-__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ V3 cross(V3 a, V3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-// y = M x and y = M^T x for a row-major 3x3 M
-__device__ __forceinline__ V3 mul(const float* M, V3 v) {
-  return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
-          M[6] * v.x + M[7] * v.y + M[8] * v.z};
-}
-__device__ __forceinline__ V3 mul_t(const float* M, V3 v) {
-  return {M[0] * v.x + M[3] * v.y + M[6] * v.z, M[1] * v.x + M[4] * v.y + M[7] * v.z,
-          M[2] * v.x + M[5] * v.y + M[8] * v.z};
-}
-
-// ---------------------------------------------------------------------------
-// SDF sample: trilinear value and analytic gradient of the vertex-centred
-// grid; outside the box, the clamped sample plus the distance to the box.
-// ---------------------------------------------------------------------------
-struct Sample {
-  float phi;
-  V3 n;          // gradient of phi in the object frame
-  // kept for the second derivative (penetrating samples in the adjoint)
-  float dx00, dx10, dx01, dx11;    // x-differences of the 4 corner rows
-  float dyx0, dyx1;                 // (v011-v001)-(v010-v000), (v111-v101)-(v110-v100)
-  float fx, fy, fz;
-  V3 e;          // offset from the clamped point (0 inside)
-  float inv_ne;  // 1/|e| (0 inside)
-  bool clx, cly, clz;
-};
-
-__device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
-  const float top = static_cast<float>(S.n - 1);
-  // u stays a rounded product: contracting it into the clamp residual below
-  // would turn an interior point's exact zero offset into a rounding residue
-  const float ux = __fmul_rn(r.x - S.lo[0], S.inv_h);
-  const float uy = __fmul_rn(r.y - S.lo[1], S.inv_h);
-  const float uz = __fmul_rn(r.z - S.lo[2], S.inv_h);
-  const float bx = fminf(fmaxf(ux, 0.0f), top);
-  const float by = fminf(fmaxf(uy, 0.0f), top);
-  const float bz = fminf(fmaxf(uz, 0.0f), top);
-  const int cm = S.n - 2;
-  const int ix = min(max(static_cast<int>(floorf(bx)), 0), cm);
-  const int iy = min(max(static_cast<int>(floorf(by)), 0), cm);
-  const int iz = min(max(static_cast<int>(floorf(bz)), 0), cm);
-  s.fx = bx - static_cast<float>(ix);
-  s.fy = by - static_cast<float>(iy);
-  s.fz = bz - static_cast<float>(iz);
-  const int nc = S.n - 1;
-  const int cell = (iz * nc + iy) * nc + ix;
-  const float4 lo4 = S.cells[2 * cell];
-  const float4 hi4 = S.cells[2 * cell + 1];
-  // corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
-  s.dx00 = lo4.y - lo4.x;
-  s.dx10 = lo4.w - lo4.z;
-  s.dx01 = hi4.y - hi4.x;
-  s.dx11 = hi4.w - hi4.z;
-  const float c00 = fmaf(s.fx, s.dx00, lo4.x);
-  const float c10 = fmaf(s.fx, s.dx10, lo4.z);
-  const float c01 = fmaf(s.fx, s.dx01, hi4.x);
-  const float c11 = fmaf(s.fx, s.dx11, hi4.z);
-  const float dy0 = c10 - c00, dy1 = c11 - c01;
-  const float c0 = fmaf(s.fy, dy0, c00), c1 = fmaf(s.fy, dy1, c01);
-  const float gz = c1 - c0;
-  const float gy = fmaf(s.fz, dy1 - dy0, dy0);
-  const float gx0 = fmaf(s.fy, s.dx10 - s.dx00, s.dx00);
-  const float gx1 = fmaf(s.fy, s.dx11 - s.dx01, s.dx01);
-  const float gx = fmaf(s.fz, gx1 - gx0, gx0);
-  s.dyx0 = (hi4.z - hi4.x) - (lo4.z - lo4.x);
-  s.dyx1 = (hi4.w - hi4.y) - (lo4.w - lo4.y);
-  s.clx = ux != bx;
-  s.cly = uy != by;
-  s.clz = uz != bz;
-  s.phi = fmaf(s.fz, gz, c0);
-  s.n = v3(s.clx ? 0.0f : gx * S.inv_h, s.cly ? 0.0f : gy * S.inv_h, s.clz ? 0.0f : gz * S.inv_h);
-  s.e = v3(s.clx ? (ux - bx) * S.h : 0.0f, s.cly ? (uy - by) * S.h : 0.0f, s.clz ? (uz - bz) * S.h : 0.0f);
-  const float ee = dot(s.e, s.e);
-  s.inv_ne = 0.0f;
-  if (ee > 0.0f) {
-    const float ne = sqrtf(ee);
-    s.inv_ne = 1.0f / ne;
-    s.phi += ne;
-    s.n = s.n + s.inv_ne * s.e;
-  }
-}
-
-// H v with H = d(grad phi)/dr of the sample: mixed partials of the trilinear
-// blend on unclamped axes, plus (I - e e^T/|e|^2)/|e| on clamped axes.
-__device__ __forceinline__ V3 hess_mul(const SdfView& S, const Sample& s, V3 v) {
-  const float ih2 = S.inv_h * S.inv_h;
-  float hxy = fmaf(s.fz, (s.dx11 - s.dx01) - (s.dx10 - s.dx00), s.dx10 - s.dx00) * ih2;
-  float hxz = fmaf(s.fy, (s.dx11 - s.dx10) - (s.dx01 - s.dx00), s.dx01 - s.dx00) * ih2;
-  float hyz = fmaf(s.fx, s.dyx1 - s.dyx0, s.dyx0) * ih2;
-  if (s.clx || s.cly) hxy = 0.0f;
-  if (s.clx || s.clz) hxz = 0.0f;
-  if (s.cly || s.clz) hyz = 0.0f;
-  V3 out = v3(hxy * v.y + hxz * v.z, hxy * v.x + hyz * v.z, hxz * v.x + hyz * v.y);
-  if (s.inv_ne > 0.0f) {
-    const V3 eh = s.inv_ne * s.e;
-    const float ev = dot(eh, v);
-    out.x += s.clx ? (v.x - eh.x * ev) * s.inv_ne : 0.0f;
-    out.y += s.cly ? (v.y - eh.y * ev) * s.inv_ne : 0.0f;
-    out.z += s.clz ? (v.z - eh.z * ev) * s.inv_ne : 0.0f;
-  }
-  return out;
-}
-
-// ---------------------------------------------------------------------------
-// object orientation: R(theta) = I + A [t]x + B [t]x^2 and the derivatives
-// A' = dA/ds, B' = dB/ds with s = |t|^2; power series below |t| = 0.5
-// ---------------------------------------------------------------------------
-struct Rot {
-  float R[9];
-  V3 th;
-  float A, B, Ap, Bp;
-};
-
-__device__ __forceinline__ void make_rot(V3 th, Rot& o) {
-  const float s = dot(th, th);
-  if (s < 0.25f) {
-    o.A = 1.0f + s * (-1.0f / 6 + s * (1.0f / 120 + s * (-1.0f / 5040 + s * (1.0f / 362880))));
-    o.B = 0.5f + s * (-1.0f / 24 + s * (1.0f / 720 + s * (-1.0f / 40320 + s * (1.0f / 3628800))));
-    o.Ap = -1.0f / 6 + s * (1.0f / 60 + s * (-1.0f / 1680 + s * (1.0f / 90720)));
-    o.Bp = -1.0f / 24 + s * (1.0f / 360 + s * (-1.0f / 13440 + s * (1.0f / 907200)));
-  } else {
-    const float t = sqrtf(s);
-    float sn, cs;
-    sincosf(t, &sn, &cs);
-    o.A = sn / t;
-    o.B = (1.0f - cs) / s;
-    o.Ap = (t * cs - sn) / (2.0f * s * t);
-    o.Bp = (t * sn - 2.0f * (1.0f - cs)) / (2.0f * s * s);
-  }
-  o.th = th;
-  const float x = th.x, y = th.y, z = th.z;
-  // [t]x^2 = t t^T - s I
-  o.R[0] = 1.0f + o.B * (x * x - s);
-  o.R[1] = -o.A * z + o.B * x * y;
-  o.R[2] = o.A * y + o.B * x * z;
-  o.R[3] = o.A * z + o.B * x * y;
-  o.R[4] = 1.0f + o.B * (y * y - s);
-  o.R[5] = -o.A * x + o.B * y * z;
-  o.R[6] = -o.A * y + o.B * x * z;
-  o.R[7] = o.A * x + o.B * y * z;
-  o.R[8] = 1.0f + o.B * (z * z - s);
-}
-
-// d/dphi of y = R(phi) v contracted with yb, at phi = sgn * theta.
-__device__ __forceinline__ V3 rot_vjp(const Rot& o, float sgn, V3 v, V3 yb) {
-  const V3 ph = sgn * o.th;
-  const V3 tv = cross(ph, v);
-  const V3 ttv = cross(ph, tv);
-  const float c = 2.0f * o.Ap * dot(yb, tv) + 2.0f * o.Bp * dot(yb, ttv);
-  const V3 a = cross(v, yb);
-  const float pv = dot(ph, v), py = dot(ph, yb), vy = dot(v, yb);
-  return v3(c * ph.x + o.A * a.x + o.B * (pv * yb.x + v.x * py - 2.0f * ph.x * vy),
-            c * ph.y + o.A * a.y + o.B * (pv * yb.y + v.y * py - 2.0f * ph.y * vy),
-            c * ph.z + o.A * a.z + o.B * (pv * yb.z + v.z * py - 2.0f * ph.z * vy));
-}
-
-__device__ __forceinline__ V3 sim_dir(int m) {
-  return v3(m == 0 ? 1.0f : (m == 1 ? -1.0f : 0.0f), m == 2 ? 1.0f : (m == 3 ? -1.0f : 0.0f),
-            m == 4 ? 1.0f : (m == 5 ? -1.0f : 0.0f));
-}
-
-// ---------------------------------------------------------------------------
-// per-wave LDS layout (floats)
-// ---------------------------------------------------------------------------
-constexpr int kOffT = 0;                                // [kMaxLinks][12] link transforms
-constexpr int kOffJ = kOffT + kMaxLinks * 12;           // [kMaxLinks][6] joint origin, world axis
-constexpr int kOffW = kOffJ + kMaxLinks * 6;            // [kMaxLinks][6] link force, torque (adjoint)
-constexpr int kOffU = kOffW + kMaxLinks * 6;            // [7][32] per-test pose constants
-constexpr int kOffPose = kOffU + kSims * 32;            // [slots][7][6] pose checkpoints
-constexpr int kUStride = 32;
 // per-test constants: 0..2 x, 3..11 R, 12..14 theta, 15..18 A B A' B', 19..24 Wl_bar Wa_bar
 
 struct Ctx {
@@ -233,61 +26,11 @@ struct Ctx {
   int lane;
 };
 
-// Link transforms T_l (Sec. III-C, p = FK(q)). Each lane l composes its own
-// chain from the wrist: T_0 = Trans(q0..2) Rz(q3) Ry(q4) Rx(q5), then
-// T_a = T_parent(a) O_a Rot(axis_a, q_{5+a}) down to link l. Also stores each
-// joint's world origin and world axis for the adjoint.
+// Link transforms T_l (Sec. III-C, p = FK(q)): lane l composes its own
+// chain (link_transform) and leaves T_l and joint l's world frame in LDS.
 __device__ void forward_kinematics(const Ctx& c, const float* qb) {
-  const HandView& H = c.H;
   const int l = c.lane;
-  float R[9], t[3];
-  {
-    float s3, c3, s4, c4, s5, c5;
-    sincosf(qb[3], &s3, &c3);
-    sincosf(qb[4], &s4, &c4);
-    sincosf(qb[5], &s5, &c5);
-    R[0] = c3 * c4; R[1] = c3 * s4 * s5 - s3 * c5; R[2] = c3 * s4 * c5 + s3 * s5;
-    R[3] = s3 * c4; R[4] = s3 * s4 * s5 + c3 * c5; R[5] = s3 * s4 * c5 - c3 * s5;
-    R[6] = -s4;     R[7] = c4 * s5;                R[8] = c4 * c5;
-    t[0] = qb[0]; t[1] = qb[1]; t[2] = qb[2];
-  }
-  if (l < H.L) {
-    float* Jw = c.lds + kOffJ + 6 * l;
-    if (l == 0) {
-      Jw[0] = t[0]; Jw[1] = t[1]; Jw[2] = t[2]; Jw[3] = 0.0f; Jw[4] = 0.0f; Jw[5] = 0.0f;
-    }
-    const int dep = H.depth[l];
-    for (int s = 0; s < dep; ++s) {
-      const int a = H.chain[l * kMaxDepth + s];
-      const float* O = H.origin + 12 * a;
-      float JR[9], Jt[3];
-      for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 3; ++j)
-          JR[3 * i + j] = R[3 * i] * O[j] + R[3 * i + 1] * O[4 + j] + R[3 * i + 2] * O[8 + j];
-        Jt[i] = R[3 * i] * O[3] + R[3 * i + 1] * O[7] + R[3 * i + 2] * O[11] + t[i];
-      }
-      const V3 k = v3(H.axis[3 * a], H.axis[3 * a + 1], H.axis[3 * a + 2]);
-      float sn, cs;
-      sincosf(qb[5 + a], &sn, &cs);
-      const float oc = 1.0f - cs;
-      // Rodrigues: I + sin [k]x + (1 - cos) [k]x^2, [k]x^2 = k k^T - I
-      const float Q[9] = {1.0f + oc * (k.x * k.x - 1.0f), -sn * k.z + oc * k.x * k.y, sn * k.y + oc * k.x * k.z,
-                          sn * k.z + oc * k.x * k.y, 1.0f + oc * (k.y * k.y - 1.0f), -sn * k.x + oc * k.y * k.z,
-                          -sn * k.y + oc * k.x * k.z, sn * k.x + oc * k.y * k.z, 1.0f + oc * (k.z * k.z - 1.0f)};
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          R[3 * i + j] = JR[3 * i] * Q[j] + JR[3 * i + 1] * Q[3 + j] + JR[3 * i + 2] * Q[6 + j];
-      t[0] = Jt[0]; t[1] = Jt[1]; t[2] = Jt[2];
-      if (s == dep - 1) {
-        const V3 kw = mul(JR, k);
-        Jw[0] = Jt[0]; Jw[1] = Jt[1]; Jw[2] = Jt[2]; Jw[3] = kw.x; Jw[4] = kw.y; Jw[5] = kw.z;
-      }
-    }
-    float* T = c.lds + kOffT + 12 * l;
-    T[0] = R[0]; T[1] = R[1]; T[2] = R[2]; T[3] = t[0];
-    T[4] = R[3]; T[5] = R[4]; T[6] = R[5]; T[7] = t[1];
-    T[8] = R[6]; T[9] = R[7]; T[10] = R[8]; T[11] = t[2];
-  }
+  if (l < c.H.L) link_transform(c.H, qb, l, c.lds + kOffT + 12 * l, c.lds + kOffJ + 6 * l);
   wave_lds_sync();
 }
 
@@ -298,9 +41,7 @@ __device__ __forceinline__ V3 contact_point(const Ctx& c, int i, int& link) {
   link = H.clink[i];
   const float4* T4 = reinterpret_cast<const float4*>(c.lds + kOffT + 12 * link);
   const float4 r0 = T4[0], r1 = T4[1], r2 = T4[2];
-  return v3(fmaf(r0.x, lx, fmaf(r0.y, ly, fmaf(r0.z, lz, r0.w))),
-            fmaf(r1.x, lx, fmaf(r1.y, ly, fmaf(r1.z, lz, r1.w))),
-            fmaf(r2.x, lx, fmaf(r2.y, ly, fmaf(r2.z, lz, r2.w))));
+  return xform_point(r0, r1, r2, lx, ly, lz);
 }
 
 // Per-test constants of iteration k into LDS: pose (x, theta), R(theta) and
@@ -349,7 +90,7 @@ __device__ void forward_pass(const Ctx& c, bool first, float W[kSims][6], float&
       V3 a, r;
       Rot o;
       if constexpr (KONE) {
-        a = p - dv * sim_dir(m);
+        a = test_point(p, m, dv);
         r = a;
       } else {
         const float* U = c.lds + kOffU + kUStride * m;
@@ -365,9 +106,9 @@ __device__ void forward_pass(const Ctx& c, bool first, float W[kSims][6], float&
       float lam = 0.0f, w = 0.0f;
       if (valid && (d < 0.0f || trace_s)) {
         const V3 u = cross(a, g);
-        w = dot(g, g) + dot(u, u) * S.inv_Im;
+        w = fmaf(dot(u, u), S.inv_Im, dot(g, g));
         if (d < 0.0f && w > wmin) {
-          lam = d / w;
+          lam = d * rcp(w);
           W[m][0] = fmaf(lam, g.x, W[m][0]);
           W[m][1] = fmaf(lam, g.y, W[m][1]);
           W[m][2] = fmaf(lam, g.z, W[m][2]);
@@ -425,7 +166,7 @@ __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pos
       V3 a, r;
       Rot o;
       if constexpr (KONE) {
-        a = p - dv * sim_dir(m);
+        a = test_point(p, m, dv);
         r = a;
       } else {
         load_rot(U, o);
@@ -437,23 +178,23 @@ __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pos
       const V3 g = KONE ? s.n : mul(o.R, s.n);
       const float d = s.phi - rd;
       const V3 u = cross(a, g);
-      const float w = dot(g, g) + dot(u, u) * inv_Im;
+      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
       const V3 WlB = v3(U[19], U[20], U[21]);
       const V3 WaB = v3(U[22], U[23], U[24]);
-      const float lb = dot(WlB, g) + dot(WaB, u);
+      const float lb = fmaf(WlB.x, g.x, fmaf(WlB.y, g.y, fmaf(WlB.z, g.z, dot(WaB, u))));
       float dbar = 0.0f;
       V3 gbar = v3(0.0f, 0.0f, 0.0f), abar = v3(0.0f, 0.0f, 0.0f);
       bool pen = false;
       if (valid && w > wmin) {
-        const float iw = 1.0f / w;
+        const float iw = rcp(w);
         if (d < 0.0f) {
           // lambda = d / w: full derivative through d, g and u
           pen = true;
           const float lam = d * iw;
           dbar = lb * iw;
           const float wbar2 = -2.0f * lb * lam * iw;
-          V3 ubar = lam * WaB + (wbar2 * inv_Im) * u;
-          gbar = lam * WlB + wbar2 * g;
+          const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
+          gbar = axpy(lam, WlB, wbar2 * g);
           abar = cross(g, ubar);
           gbar = gbar + cross(ubar, a);
         } else {
@@ -700,35 +441,18 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
     }
   wave_lds_sync();
   float gq = 0.0f;
-  {
-    const float* W0 = lds + kOffW;
-    const float* J0 = lds + kOffJ;
-    if (lane < 3) {
-      gq = W0[lane];
-    } else if (lane < 6) {
-      // wrist rotations about the axes through the wrist origin t0
-      const V3 f = v3(W0[0], W0[1], W0[2]), tau = v3(W0[3], W0[4], W0[5]);
-      const V3 t0 = v3(J0[0], J0[1], J0[2]);
-      const V3 tq = tau - cross(t0, f);
-      float s3, c3, s4, c4;
-      sincosf(qb[3], &s3, &c3);
-      sincosf(qb[4], &s4, &c4);
-      V3 ax;
-      if (lane == 3) ax = v3(0.0f, 0.0f, 1.0f);
-      else if (lane == 4) ax = v3(-s3, c3, 0.0f);
-      else ax = v3(c3 * c4, s3 * c4, -s4);
-      gq = dot(ax, tq);
-    } else if (lane < nd) {
-      const int l = lane - 5;
-      const float* Wl = lds + kOffW + 6 * l;
-      const float* Jl = lds + kOffJ + 6 * l;
-      const V3 f = v3(Wl[0], Wl[1], Wl[2]), tau = v3(Wl[3], Wl[4], Wl[5]);
-      const V3 o = v3(Jl[0], Jl[1], Jl[2]), ax = v3(Jl[3], Jl[4], Jl[5]);
-      gq = dot(ax, tau - cross(o, f));
+  if (lane < nd) {
+    // joint j = lane drives link l: the wrist (j < 6) drives the palm
+    const int l = lane < 6 ? 0 : lane - 5;
+    const float* Wl = lds + kOffW + 6 * l;
+    const float* Jl = lds + kOffJ + 6 * l;
+    gq = joint_torque(lane, qb, v3(Wl[0], Wl[1], Wl[2]), v3(Wl[3], Wl[4], Wl[5]), v3(Jl[0], Jl[1], Jl[2]),
+                      v3(Jl[3], Jl[4], Jl[5]));
+    if (lane >= 6) {
       // joint losses
       const float rg = Lrange > 0.0f ? P.w_range * dm / Lrange : 0.0f;
       const float lg = qj > up ? P.w_limit : (qj < lo ? -P.w_limit : 0.0f);
-      gq += sL * (rg + lg);
+      gq = fmaf(sL, rg + lg, gq);
     }
   }
   if (lane < nd) {
@@ -745,15 +469,48 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
   }
 }
 
-template <bool KONE>
-__global__ void __launch_bounds__(256) k_step(StepArgs A, int kind, int adam) {
+// OCC is the minimum number of waves per SIMD the register allocation must
+// allow (1 = the compiler's choice); it is the occupancy knob of the tuner.
+template <bool KONE, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(OCC, 8)))
+k_step(StepArgs A, int kind, int adam) {
   extern __shared__ float smem[];
   const int wpb = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
-  const int b = blockIdx.x * wpb + w;
+  const int b = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
   if (b >= A.B) return;
   float* lds = smem + static_cast<size_t>(w) * wave_lds_floats(A.prm.K, A.prm.ckpt);
   candidate_step<KONE>(A, b, kind, adam != 0, lds);
+}
+
+// Batched step: one launch covers every job of a device table. Wave w of the
+// grid takes work item w; items [begin, begin + B) of a job are its
+// candidates, each one fused forward, backward and Adam computed exactly as
+// the single-job launch computes it. Jobs are ordered most expensive first
+// so the dispatcher starts the long candidates early. The header and table
+// are read from device memory, so a graph captured for a grid of `capacity`
+// waves serves any job set up to that many candidates; waves past the
+// table's total exit at once.
+template <bool KONE, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(OCC, 8)))
+k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, int lds_per_wave) {
+  extern __shared__ float smem[];
+  const int wpb = blockDim.x / kWave;
+  const int w = threadIdx.x / kWave;
+  // wave-uniform by construction; readfirstlane lets the compiler see it
+  const int item = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
+  const int n_jobs = hdr->n_jobs;
+  if (item >= hdr->total) return;
+  int lo = 0, hi = n_jobs - 1;  // last job with begin <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  float* lds = smem + static_cast<size_t>(w) * lds_per_wave;
+  const StepArgs A = jobs[lo].args;  // one uniform copy, like a kernel argument
+  candidate_step<KONE>(A, item - jobs[lo].begin, STEP_FUSED, true, lds);
 }
 
 __global__ void k_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c) {
@@ -803,16 +560,61 @@ __global__ void k_sample_points(SdfView S, int n, const float* __restrict__ r, f
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, int wpb, hipStream_t stream) {
-  if (a.B <= 0) return hipSuccess;
+namespace {
+template <bool KONE, int OCC>
+void launch_variant(const StepArgs& a, int kind, bool adam, int wpb, size_t lds, hipStream_t stream) {
   const int blocks = (a.B + wpb - 1) / wpb;
-  const size_t lds = wave_lds_floats(a.prm.K, a.prm.ckpt) * wpb * sizeof(float);
+  hipLaunchKernelGGL((k_step<KONE, OCC>), dim3(blocks), dim3(wpb * kWave), lds, stream, a, kind, adam ? 1 : 0);
+}
+template <bool KONE>
+void launch_occ(const StepArgs& a, int kind, bool adam, TileCfg cfg, size_t lds, hipStream_t stream) {
+  switch (cfg.occ) {
+    case 2: launch_variant<KONE, 2>(a, kind, adam, cfg.wpb, lds, stream); break;
+    case 3: launch_variant<KONE, 3>(a, kind, adam, cfg.wpb, lds, stream); break;
+    case 4: launch_variant<KONE, 4>(a, kind, adam, cfg.wpb, lds, stream); break;
+    default: launch_variant<KONE, 1>(a, kind, adam, cfg.wpb, lds, stream); break;
+  }
+}
+}  // namespace
+
+bool valid_tile(TileCfg c) {
+  return (c.wpb == 1 || c.wpb == 2 || c.wpb == 4) && (c.occ >= 1 && c.occ <= 4);
+}
+
+hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream) {
+  if (a.B <= 0) return hipSuccess;
+  if (!valid_tile(cfg)) cfg = TileCfg{};
+  const size_t lds = wave_lds_floats(a.prm.K, a.prm.ckpt) * cfg.wpb * sizeof(float);
   if (a.prm.K == 1)
-    hipLaunchKernelGGL(k_step<true>, dim3(blocks), dim3(wpb * kWave), lds, stream, a, static_cast<int>(kind),
-                       adam ? 1 : 0);
+    launch_occ<true>(a, static_cast<int>(kind), adam, cfg, lds, stream);
   else
-    hipLaunchKernelGGL(k_step<false>, dim3(blocks), dim3(wpb * kWave), lds, stream, a, static_cast<int>(kind),
-                       adam ? 1 : 0);
+    launch_occ<false>(a, static_cast<int>(kind), adam, cfg, lds, stream);
+  return hipGetLastError();
+}
+
+namespace {
+template <bool KONE, int OCC>
+void launch_batch_variant(const BatchHeader* hdr, const BatchJob* jobs, int blocks, int wpb, int lds_floats,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL((k_batch<KONE, OCC>), dim3(blocks), dim3(wpb * kWave),
+                     static_cast<size_t>(lds_floats) * wpb * sizeof(float), stream, hdr, jobs, lds_floats);
+}
+}  // namespace
+
+hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
+                        int lds_floats, hipStream_t stream) {
+  if (!valid_tile(cfg)) cfg = TileCfg{};
+  switch ((kone ? 10 : 0) + cfg.occ) {
+    case 12: launch_batch_variant<true, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 13: launch_batch_variant<true, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 14: launch_batch_variant<true, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 2: launch_batch_variant<false, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 3: launch_batch_variant<false, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 4: launch_batch_variant<false, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    default:
+      if (kone) launch_batch_variant<true, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);
+      else launch_batch_variant<false, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);
+  }
   return hipGetLastError();
 }
 

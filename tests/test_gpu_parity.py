@@ -317,3 +317,64 @@ def test_full_size_diff_sampled(ctx):
     say("diff full: loss err", lerr.max(), "grad err", gerr, "flagged", flagged)
     assert np.all(lerr <= 1e-4)
     assert np.all(gerr[~flagged] <= 1e-3)
+
+
+def test_every_tile_bit_identical(ctx, tiny):
+    """Launch tiles change speed only: every tile gives the same bits."""
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    res = []
+    for K in (1, 2):
+        sp, _ = prm_pair(r_dil=0.004, K=K)
+        B = 40
+        for wpb in (1, 2, 4):
+            for occ in (1, 2, 3, 4):
+                ctx.set_tile(h, sd, sp, B, wpb, occ)
+                qd = dev(q[:B])
+                m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+                loss = torch.empty(B, device=DEV)
+                dq = torch.empty_like(qd)
+                ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+                res.append((K, loss.cpu().numpy(), dq.cpu().numpy(), qd.cpu().numpy()))
+        (best, ms) = ctx.tune(h, sd, sp, dev(q[:B]), reps=1)
+        say("K", K, "tuned tile", best, ms)
+    for K in (1, 2):
+        rk = [r for r in res if r[0] == K]
+        for r in rk[1:]:
+            assert all(np.array_equal(x, y) for x, y in zip(r[1:], rk[0][1:]))
+
+
+def test_plain_form_parity(ctx, tiny):
+    """The unfused per-job form against the oracle, and against the fused
+    step (same formulas, different summation order)."""
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.005)
+    B = q.shape[0]
+    ws = ctx.plain_workspace(h, sd, sp, B)
+    qp = dev(q)
+    m, v = torch.zeros_like(qp), torch.zeros_like(qp)
+    loss = torch.empty(B, device=DEV)
+    ctx.plain_step(h, sd, sp, qp, m, v, 1, ws, loss=loss)
+    qf = dev(q)
+    mf, vf = torch.zeros_like(qf), torch.zeros_like(qf)
+    lf = torch.empty(B, device=DEV)
+    dqf = torch.empty_like(qf)
+    ctx.step_fused(h, sd, sp, qf, mf, vf, 1, loss=lf, dq=dqf)
+    torch.cuda.synchronize()
+    ref = O.step(ohand(hand), O.Obj(grid), op, q.astype(np.float32).astype(np.float64), margins=True)
+    lp = loss.cpu().numpy()
+    assert np.all(np.abs(lp - ref["loss"]) <= 1e-4 * np.maximum(np.abs(ref["loss"]), 1.0))
+    # Adam's first step is -lr sign(g): compare the update direction where |g| is not tiny
+    g = ref["grad"]
+    big = np.abs(g) > 1e-3 * np.abs(g).max(axis=1, keepdims=True)
+    upd = (qp.cpu().numpy() - q.astype(np.float32))
+    flagged = ref["min_abs_d"] < KINK_D
+    ok = big & ~flagged[:, None]
+    assert np.all(np.sign(upd[ok]) == -np.sign(g[ok]))
+    # m after one step is (1 - b1) dq: the plain gradient against the oracle
+    dq_plain = m.cpu().numpy() / np.float32(1 - np.float32(0.9))
+    err = np.abs(dq_plain - g).max(axis=1) / np.abs(g).max(axis=1)
+    say("plain grad rel err max(unflagged)", err[~flagged].max())
+    assert np.all(err[~flagged] <= 1e-3)
+    assert np.allclose(lp, lf.cpu().numpy(), rtol=1e-5, atol=1e-6)
