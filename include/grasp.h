@@ -274,6 +274,58 @@ grasp_status grasp_batch_step(grasp_batch* batch, grasp_batch_job* jobs, int32_t
 grasp_status grasp_batch_flags(grasp_batch* batch, int32_t n, int32_t* out);
 
 /* ---------------------------------------------------------------------------
+ * Serving: continuous batching of grasp jobs (Sec. V-C contrasts the online
+ * and the amortized time per grasp). A scheduler thread owned by the context
+ * admits queued jobs at step boundaries, first come first served, when their
+ * device footprint (q, m, v, loss, terms: 12 B n_dof + 20 B per candidate)
+ * fits the arena and the candidate capacity; advances every resident job by
+ * one optimizer step per batched launch; and retires a job after its T steps
+ * with one forward at r_dil = 0 (final loss, terms) and the ranking, freeing
+ * its memory. Hands and grids stay resident and are shared between jobs.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  grasp_hand_id hand;
+  grasp_sdf_id sdf;
+  int32_t B;             /* candidates, >= 1 */
+  const float* q0;       /* host [B][n_dof] initial configurations, copied by grasp_submit */
+  int32_t T;             /* optimizer steps, >= 1 */
+  float r0;              /* initial dilation; r(t) = r0 (1 - t/(T-1)) */
+  grasp_step_params p;   /* p.r_dil is ignored */
+  float lr, b1, b2, eps; /* Adam */
+} grasp_job_desc;
+
+typedef struct {
+  grasp_status status;   /* GRASP_OK, GRASP_ENONFINITE or GRASP_ECANCELED */
+  float* q;              /* host [B][n_dof] final configurations, caller-owned, or NULL */
+  float* loss;           /* host [B] final loss at r_dil = 0, or NULL */
+  float* terms;          /* host [B][4], or NULL */
+  int32_t* rank;         /* host [B]: candidate indices by ascending final loss (ties by index), or NULL */
+  double t_submit, t_admit, t_done; /* seconds since grasp_init */
+  int32_t steps;         /* optimizer steps the job took */
+} grasp_job_result;
+
+/* Sets the scheduler's candidate capacity per step (default 65536) and job
+ * limit (default 256); only before the first grasp_submit. */
+grasp_status grasp_serve_config(grasp_ctx* ctx, int32_t capacity, int32_t max_jobs);
+/* Queues a job (thread-safe, non-blocking). ENOMEM if the job can never fit
+ * (footprint > arena or B > capacity); EINVAL on bad ids or parameters. */
+grasp_status grasp_submit(grasp_ctx* ctx, const grasp_job_desc* job, grasp_job_id* out);
+/* GRASP_EAGAIN while the job is queued or running. Once it has ended, copies
+ * its results into the caller's buffers in *inout, returns its final status
+ * and forgets the job (a second poll returns EINVAL). Thread-safe. */
+grasp_status grasp_poll(grasp_ctx* ctx, grasp_job_id job, grasp_job_result* inout);
+/* Asks the scheduler to stop a job at the next step boundary (it then ends
+ * with GRASP_ECANCELED). EINVAL for an unknown or already polled job. */
+grasp_status grasp_cancel(grasp_ctx* ctx, grasp_job_id job);
+
+typedef struct {
+  int64_t steps;          /* batched launches so far */
+  int64_t contact_evals;  /* sum over steps of resident candidates x contacts x 7 x K */
+  int32_t queued, resident, finished;
+} grasp_serve_stats;
+grasp_status grasp_serve_stats_get(grasp_ctx* ctx, grasp_serve_stats* out);
+
+/* ---------------------------------------------------------------------------
  * Parity introspection (tests)
  * ------------------------------------------------------------------------- */
 

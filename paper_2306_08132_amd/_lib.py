@@ -56,6 +56,23 @@ class BatchJobC(C.Structure):
                 ("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float)]
 
 
+class JobDescC(C.Structure):
+    _fields_ = [("hand", C.c_uint64), ("sdf", C.c_uint64), ("B", C.c_int32), ("q0", C.c_void_p),
+                ("T", C.c_int32), ("r0", C.c_float), ("p", StepParamsC), ("lr", C.c_float), ("b1", C.c_float),
+                ("b2", C.c_float), ("eps", C.c_float)]
+
+
+class JobResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("q", C.c_void_p), ("loss", C.c_void_p), ("terms", C.c_void_p),
+                ("rank", C.c_void_p), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("steps", C.c_int32)]
+
+
+class ServeStatsC(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("contact_evals", C.c_int64), ("queued", C.c_int32),
+                ("resident", C.c_int32), ("finished", C.c_int32)]
+
+
 @dataclasses.dataclass
 class StepParams:
     """Mirror of grasp_step_params (defaults of grasp_default_params)."""
@@ -109,6 +126,11 @@ SIGNATURES = [
     ("grasp_batch_set_tile", _I32, [_VP, C.POINTER(TileC)]),
     ("grasp_batch_step", _I32, [_VP, _VP, _I32, _VP]),
     ("grasp_batch_flags", _I32, [_VP, _I32, _IP]),
+    ("grasp_serve_config", _I32, [_VP, _I32, _I32]),
+    ("grasp_submit", _I32, [_VP, C.POINTER(JobDescC), C.POINTER(_U64)]),
+    ("grasp_poll", _I32, [_VP, _U64, C.POINTER(JobResultC)]),
+    ("grasp_cancel", _I32, [_VP, _U64]),
+    ("grasp_serve_stats_get", _I32, [_VP, C.POINTER(ServeStatsC)]),
     ("grasp_debug_sdf_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP, _VP]),
     ("grasp_debug_trace", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _VP]),
 ]

@@ -11,8 +11,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (BatchJobC, HandDesc, Library, SdfDesc, StepParams, TileC, MODE_AUTO, MODE_RECOMPUTE,
-                   MODE_SAVE, GraspError)
+from ._lib import (BatchJobC, HandDesc, JobDescC, JobResultC, Library, SdfDesc, ServeStatsC, StepParams,
+                   TileC, GRASP_EAGAIN, MODE_AUTO, MODE_RECOMPUTE, MODE_SAVE, GraspError)
 
 __all__ = ["Context", "Hand", "Sdf", "StepParams", "GraspStep", "GraspError", "Batch", "BatchJob",
            "MODE_AUTO", "MODE_SAVE", "MODE_RECOMPUTE"]
@@ -122,6 +122,44 @@ class Context:
         pc = prm.c()
         t = TileC(wpb, occ)
         self.lib.call("grasp_set_tile", self.h, hand.id, sdf.id, C.byref(pc), B, C.byref(t))
+
+    # -- serving ---------------------------------------------------------------
+    def serve_config(self, capacity: int = 65536, max_jobs: int = 256):
+        self.lib.call("grasp_serve_config", self.h, capacity, max_jobs)
+
+    def submit(self, hand, sdf, q0, T: int, r0: float = 0.01, prm: StepParams | None = None, lr=1e-3, b1=0.9,
+               b2=0.999, eps=1e-8) -> int:
+        """Queues a grasp job (host q0 [B][n_dof]); returns its id."""
+        q0 = _f32(q0)
+        prm = prm or StepParams()
+        d = JobDescC(hand.id, sdf.id, q0.shape[0], q0.ctypes.data, T, r0, prm.c(), lr, b1, b2, eps)
+        out = C.c_uint64()
+        self.lib.call("grasp_submit", self.h, C.byref(d), C.byref(out))
+        return out.value
+
+    def poll(self, job: int, B: int, n_dof: int):
+        """None while the job runs; then a dict of its results (status, q, loss, terms, rank, times)."""
+        q = np.zeros((B, n_dof), np.float32)
+        loss = np.zeros(B, np.float32)
+        terms = np.zeros((B, 4), np.float32)
+        rank = np.zeros(B, np.int32)
+        r = JobResultC(0, q.ctypes.data, loss.ctypes.data, terms.ctypes.data, rank.ctypes.data, 0, 0, 0, 0)
+        code = self.lib.grasp_poll(self.h, job, C.byref(r))
+        if code == GRASP_EAGAIN:
+            return None
+        if code not in (0, -6, -7):
+            self.lib.check(code, "grasp_poll")
+        return {"status": r.status, "q": q, "loss": loss, "terms": terms, "rank": rank, "t_submit": r.t_submit,
+                "t_admit": r.t_admit, "t_done": r.t_done, "steps": r.steps}
+
+    def cancel(self, job: int):
+        self.lib.call("grasp_cancel", self.h, job)
+
+    def serve_stats(self) -> dict:
+        st = ServeStatsC()
+        self.lib.call("grasp_serve_stats_get", self.h, C.byref(st))
+        return {"steps": st.steps, "contact_evals": st.contact_evals, "queued": st.queued,
+                "resident": st.resident, "finished": st.finished}
 
     def debug_sdf_sample(self, sdf, r, hess: bool = False, stream=None):
         n = r.shape[0]

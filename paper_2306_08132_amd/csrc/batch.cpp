@@ -16,8 +16,6 @@ using namespace grasp;
 
 namespace grasp {
 
-grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c);
-
 namespace {
 
 AdamConsts adam_for(int32_t t, float lr, float b1, float b2, float eps) {

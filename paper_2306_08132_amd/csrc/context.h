@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -70,6 +71,7 @@ struct grasp_ctx {
   std::atomic<bool> poisoned{false};
   std::map<std::string, grasp::TileCfg> tiles;  // tuned launch shapes per problem shape
   grasp::Scheduler* sched = nullptr;  // owned; created and destroyed in sched.cpp
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 
 namespace grasp {
@@ -93,6 +95,9 @@ grasp_status device_fail(grasp_ctx* ctx, hipError_t e, const char* where);
 // Looks up resident objects (caller holds ctx->mu).
 DevHand* find_hand(grasp_ctx* ctx, grasp_hand_id id);
 DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id);
+
+// Checks one batch job and resolves its hand, grid and constants.
+grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c);
 
 // Checks step parameters and fills the device constants.
 grasp_status check_params(const grasp_step_params* p, StepConsts* out);

@@ -1,0 +1,111 @@
+"""GPU: the serving loop. A job's results are the same alone and in a mix
+of overlapping jobs (bit-exact), cancelled and non-finite jobs end without
+disturbing the others, and jobs that can never fit are refused."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2306_08132_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup(gpu):
+    from paper_2306_08132_amd.api import Context
+    ctx = Context(0, arena_bytes=512 << 20)
+    ctx.serve_config(capacity=4096, max_jobs=16)
+    objs = []
+    for k, (F, J, nc, N, B) in enumerate([(3, 3, 256, 24, 40), (4, 4, 512, 32, 64), (5, 4, 700, 28, 24)]):
+        hand = S.make_hand(F, J, nc, seed=40 + k)
+        grid = S.make_grid(S.make_object("ellipsoids", seed=50 + k, n_range=(2, 3)), N)
+        q = S.make_candidates(hand, B, seed=60 + k, shell_radius=grid.bound_radius + 0.06).astype(np.float32)
+        objs.append((ctx.hand(hand), ctx.sdf(grid), q))
+    yield ctx, objs
+    ctx.close()
+
+
+def wait(ctx, jid, B, nd, timeout=120.0):
+    t0 = time.time()
+    while time.time() - t0 < timeout:
+        r = ctx.poll(jid, B, nd)
+        if r is not None:
+            return r
+        time.sleep(0.005)
+    raise TimeoutError(f"job {jid} did not finish")
+
+
+def test_alone_equals_in_mix(setup):
+    ctx, objs = setup
+    h, sd, q = objs[1]
+    say("serving: job alone")
+    a = ctx.submit(h, sd, q, T=8)
+    alone = wait(ctx, a, q.shape[0], h.n_dof)
+    assert alone["status"] == 0 and alone["steps"] == 8
+    say("serving: job in a mix of overlapping jobs")
+    ids = []
+    ids.append((ctx.submit(objs[0][0], objs[0][1], objs[0][2], T=12), objs[0]))
+    time.sleep(0.01)
+    mid = ctx.submit(h, sd, q, T=8)
+    time.sleep(0.005)
+    ids.append((ctx.submit(objs[2][0], objs[2][1], objs[2][2], T=5), objs[2]))
+    mixed = wait(ctx, mid, q.shape[0], h.n_dof)
+    for jid, (hh, _, qq) in ids:
+        assert wait(ctx, jid, qq.shape[0], hh.n_dof)["status"] == 0
+    for k in ("q", "loss", "terms", "rank"):
+        assert np.array_equal(alone[k], mixed[k]), k
+    assert mixed["t_submit"] <= mixed["t_admit"] <= mixed["t_done"]
+    # ranking: stable sort of the final losses
+    assert mixed["rank"].tolist() == np.argsort(mixed["loss"], kind="stable").tolist()
+
+
+def test_final_loss_is_forward_at_zero_dilation(setup):
+    from paper_2306_08132_amd.api import StepParams
+    ctx, objs = setup
+    h, sd, q = objs[0]
+    r = wait(ctx, ctx.submit(h, sd, q, T=3), q.shape[0], h.n_dof)
+    qd = torch.tensor(r["q"], device="cuda:0")
+    loss = torch.empty(q.shape[0], device="cuda:0")
+    ctx.step_fwd(h, sd, StepParams(r_dil=0.0), qd, loss)
+    torch.cuda.synchronize()
+    assert np.array_equal(loss.cpu().numpy(), r["loss"])
+
+
+def test_cancel_and_nonfinite_leave_others_intact(setup):
+    ctx, objs = setup
+    h0, sd0, q0 = objs[0]
+    h2, sd2, q2 = objs[2]
+    ref = wait(ctx, ctx.submit(h2, sd2, q2, T=6), q2.shape[0], h2.n_dof)
+    bad = q0.copy()
+    bad[3, 0] = np.nan
+    j_bad = ctx.submit(h0, sd0, bad, T=20)
+    j_long = ctx.submit(h0, sd0, q0, T=10000)
+    j_ok = ctx.submit(h2, sd2, q2, T=6)
+    time.sleep(0.05)
+    ctx.cancel(j_long)
+    rb = wait(ctx, j_bad, q0.shape[0], h0.n_dof)
+    rl = wait(ctx, j_long, q0.shape[0], h0.n_dof)
+    ro = wait(ctx, j_ok, q2.shape[0], h2.n_dof)
+    say("statuses", rb["status"], rl["status"], ro["status"])
+    assert rb["status"] == -6 and rb["steps"] == 1
+    assert rl["status"] == -7
+    assert ro["status"] == 0 and np.array_equal(ro["q"], ref["q"])
+
+
+def test_refusals(setup):
+    from paper_2306_08132_amd.api import GraspError
+    ctx, objs = setup
+    h, sd, q = objs[0]
+    big = np.zeros((5000, h.n_dof), np.float32)  # more than the 4096-candidate capacity
+    with pytest.raises(GraspError):
+        ctx.submit(h, sd, big, T=2)
+    with pytest.raises(GraspError):
+        ctx.poll(123456789, 1, h.n_dof)
+    st = ctx.serve_stats()
+    assert st["steps"] > 0 and st["contact_evals"] > 0
