@@ -77,6 +77,135 @@ def cpu_baseline(hand, grid, q, prm_kw, budget_s=12.0):
             "sample": f"{done} of {q.shape[0]} candidates, 1 step, forward + gradient, FP64, {dt:.1f} s"}
 
 
+def serving_pool(S, device):
+    """A few hands and objects for the served jobs (geometry is built once
+    and stays resident; jobs draw from it)."""
+    import numpy as np
+    hands = {F: S.make_hand(F, 4 if F > 3 else 3, 2048, seed=200 + F) for F in (3, 4, 5)}
+    objs = []
+    for k, n in enumerate((64, 96, 128)):
+        prims = S.make_object("mixed", seed=300 + k, n_range=(3, 6))
+        objs.append(S.make_grid(prims, n, device=device))
+    return hands, objs
+
+
+def serving_run(ctx, S, n_jobs, rate, steps):
+    """Poisson stream of grasp jobs through the serving loop: p50/p99 of
+    submit-to-result latency and served contact-evaluations per second."""
+    import numpy as np
+    from paper_2306_08132_amd.api import StepParams
+    hands, objs = serving_pool(S, "cuda:0")
+    rh = {F: ctx.hand(h) for F, h in hands.items()}
+    ro = [ctx.sdf(g) for g in objs]
+    stream = S.make_job_stream(n_jobs, rate, seed=3, B_range=(256, 2048), steps=steps)
+    rng = np.random.default_rng(3)
+    jobs = []
+    for j in stream:
+        F = int(rng.integers(3, 6))
+        g = int(rng.integers(0, len(objs)))
+        q = S.make_candidates(hands[F], j["B"], seed=j["hand_seed"] % 100000,
+                              shell_radius=objs[g].bound_radius + 0.06).astype(np.float32)
+        jobs.append((j["arrival"], F, g, q))
+    st0 = ctx.serve_stats()
+    t0 = time.perf_counter()
+    ids = []
+    for arr, F, g, q in jobs:
+        while time.perf_counter() - t0 < arr:
+            time.sleep(0.0005)
+        ids.append((ctx.submit(rh[F], ro[g], q, T=steps, prm=StepParams()), F, q.shape[0]))
+    lat, status = [], []
+    for jid, F, B in ids:
+        while True:
+            r = ctx.poll(jid, B, hands[F].n_dof)
+            if r is not None:
+                break
+            time.sleep(0.001)
+        lat.append(r["t_done"] - r["t_submit"])
+        status.append(r["status"])
+    wall = time.perf_counter() - t0
+    st1 = ctx.serve_stats()
+    lat = np.array(lat)
+    evals = st1["contact_evals"] - st0["contact_evals"]
+    return {"jobs": n_jobs, "rate_per_s": rate, "steps_per_job": steps, "candidates": "U[256, 2048]",
+            "contacts": 2048, "grids": [g.n for g in objs], "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "jobs_per_s": n_jobs / wall,
+            "contact_evals_per_s": evals / wall, "batched_steps": st1["steps"] - st0["steps"],
+            "all_ok": bool(all(s_ == 0 for s_ in status))}
+
+
+def batched_run(ctx, S, args):
+    """16 uneven jobs (a 5-finger 26-DOF hand with 4096 contacts; unions of
+    3-8 ellipsoids/boxes at 64..256^3; 256..4096 candidates each) advanced
+    one step per launch, against the same jobs stepped one launch per job."""
+    import numpy as np
+    import torch
+    from paper_2306_08132_amd.api import Batch, BatchJob, StepParams
+    rng = np.random.default_rng(2)
+    hand = S.make_hand(5, 4, 4096, seed=2)
+    h = ctx.hand(hand)
+    jobs, evals = [], 0
+    for k in range(16):
+        n = int(rng.choice([64, 96, 128, 192, 256]))
+        grid = S.make_grid(S.make_object("mixed", seed=400 + k, n_range=(3, 8)), n, device="cuda:0")
+        B = int(rng.integers(256, 4097))
+        q = S.make_candidates(hand, B, seed=500 + k, shell_radius=grid.bound_radius + 0.06)
+        jobs.append((ctx.sdf(grid), torch.tensor(q, dtype=torch.float32, device="cuda:0")))
+        evals += B * hand.n_contacts * M_SIMS
+    cap = sum(q.shape[0] for _, q in jobs)
+    stream = torch.cuda.Stream()
+    bj = [BatchJob(h, sd, StepParams(), q.clone(), T=300) for sd, q in jobs]
+    b = Batch(ctx, capacity=cap, max_jobs=16)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            b.step(bj, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps // 5 + 3):
+            b.step(bj, stream=stream)
+        stream.synchronize()
+        tb = (time.perf_counter() - t0) / (args.steps // 5 + 3)
+    # the same jobs, one fused launch per job per step
+    sj = [(sd, q.clone(), torch.zeros_like(q), torch.zeros_like(q)) for sd, q in jobs]
+    for sd, q, m, v in sj:
+        ctx.step_fused(h, sd, StepParams(r_dil=0.01), q, m, v, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps // 5 + 3):
+        for sd, q, m, v in sj:
+            ctx.step_fused(h, sd, StepParams(r_dil=0.01), q, m, v, t + 2)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / (args.steps // 5 + 3)
+    b.close()
+    return {"jobs": 16, "candidates": cap, "contact_evals_per_step": evals, "ms_per_step": tb * 1e3,
+            "contact_evals_per_s": evals / tb, "per_job_launches_ms_per_step": ts * 1e3,
+            "batched_over_per_job": ts / tb}
+
+
+def large_run(ctx, S, args):
+    """K = 16 projection iterations, 65536 candidates, 8192 contacts, 256^3
+    grid; pose checkpoints every 4 iterations with replay in the backward."""
+    import torch
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q0 = S.config_workload("large", device="cuda:0")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
+    m, v = torch.zeros_like(q), torch.zeros_like(q)
+    out = {}
+    for ck in (4, 1):
+        prm = StepParams(K=16, ckpt_every=ck, r_dil=0.01)
+        ctx.step_fused(h, sd, prm, q, m, v, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(2):
+            ctx.step_fused(h, sd, prm, q, m, v, t + 2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        evals = q.shape[0] * hand.n_contacts * M_SIMS * 16
+        out[f"ckpt{ck}"] = {"s_per_iteration": dt, "contact_evals_per_s": evals / dt}
+    out["contact_evals_per_iteration"] = q.shape[0] * hand.n_contacts * M_SIMS * 16
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +213,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-job form")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-steps", type=int, default=60, help="optimizer steps per served job")
+    ap.add_argument("--batched", action="store_true", help="also run 16 uneven jobs in one launch per step")
+    ap.add_argument("--large", action="store_true", help="also run the K = 16 workload (65536 candidates)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
                          "the reference that scales HBM counters")
@@ -111,10 +246,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print("bench: building the workload", file=sys.stderr, flush=True)
-    hand, grid, q0 = S.config_workload("diff")
+    hand, grid, q0 = S.config_workload("diff", device="cuda:0")
     B, Nc, nd, K = q0.shape[0], hand.n_contacts, hand.n_dof, 1
     T_sched, r0 = 500, 0.01
-    ctx = Context(0, arena_bytes=1 << 30)
+    ctx = Context(0, arena_bytes=8 << 30)
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     stream = torch.cuda.current_stream()
     q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
@@ -176,6 +311,13 @@ def main():
         print(f"bench: plain {tp * 1e3:.3f} ms/step, fused/plain {value / (evals / tp):.2f}x", file=sys.stderr,
               flush=True)
 
+    serving = None
+    if not args.no_serving:
+        print("bench: serving stream", file=sys.stderr, flush=True)
+        serving = serving_run(ctx, S, n_jobs=args.serve_jobs, rate=args.serve_rate, steps=args.serve_steps)
+    batched = batched_run(ctx, S, args) if args.batched else None
+    large = large_run(ctx, S, args) if args.large else None
+
     cpu = None
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
@@ -204,6 +346,9 @@ def main():
                      "tile": {"waves_per_block": tile[0], "min_waves_per_simd": tile[1]},
                      "algorithmic_bytes_per_launch": abytes},
         "plain": plain,
+        "serving": serving,
+        "batched": batched,
+        "large": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

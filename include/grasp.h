@@ -114,7 +114,7 @@ grasp_status grasp_hand_contact_links(grasp_ctx* ctx, grasp_hand_id hand, int32_
  * Objects: a signed-distance grid (Sec. III-A/B)
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int32_t n;                 /* vertices per axis, 2..1024 (cubic grid) */
+  int32_t n;                 /* vertices per axis, 2..512 (cubic grid) */
   float lo[3];               /* position of vertex (0,0,0) */
   float h;                   /* vertex spacing, > 0: vertex (i,j,k) at lo + (i,j,k) h */
   const float* values;       /* host [n][n][n], x fastest: index (k n + j) n + i; negative inside */
@@ -215,7 +215,7 @@ grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t waves_per_block;     /* candidates per workgroup: 1, 2 or 4 */
-  int32_t min_waves_per_simd;  /* register budget: 1 (compiler's choice) .. 4 */
+  int32_t min_waves_per_simd;  /* register budget: 1 (compiler's choice) .. 6 */
 } grasp_tile;
 
 /* Times every tile on a private copy of q (dev [B][n_dof]) with reps fused

@@ -17,7 +17,6 @@ namespace grasp {
 
 namespace {
 thread_local std::string g_last_error;
-constexpr size_t kGranule = 256;
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 bool finite(float x) { return std::isfinite(x); }
@@ -28,66 +27,6 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 grasp_status fail(grasp_status code, const std::string& msg) {
   set_error(msg);
   return code;
-}
-
-// ---------------------------------------------------------------------------
-// arena
-// ---------------------------------------------------------------------------
-void Arena::reset(char* base, size_t bytes) {
-  base_ = base;
-  bytes_ = bytes / kGranule * kGranule;
-  free_.clear();
-  used_.clear();
-  if (bytes_) free_[0] = bytes_;
-}
-
-void* Arena::alloc(size_t bytes) {
-  const size_t need = round_up(std::max<size_t>(bytes, 1), kGranule);
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second < need) continue;
-    const size_t off = it->first, sz = it->second;
-    free_.erase(it);
-    if (sz > need) free_[off + need] = sz - need;
-    used_[off] = need;
-    return base_ + off;
-  }
-  return nullptr;
-}
-
-void Arena::free(void* p) {
-  if (!p) return;
-  const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
-  auto u = used_.find(off);
-  if (u == used_.end()) return;
-  size_t start = off, sz = u->second;
-  used_.erase(u);
-  auto nx = free_.lower_bound(start);
-  if (nx != free_.end() && nx->first == start + sz) {
-    sz += nx->second;
-    free_.erase(nx);
-  }
-  auto pv = free_.lower_bound(start);
-  if (pv != free_.begin()) {
-    --pv;
-    if (pv->first + pv->second == start) {
-      start = pv->first;
-      sz += pv->second;
-      free_.erase(pv);
-    }
-  }
-  free_[start] = sz;
-}
-
-size_t Arena::used() const {
-  size_t s = 0;
-  for (auto& kv : used_) s += kv.second;
-  return s;
-}
-
-size_t Arena::largest_free() const {
-  size_t s = 0;
-  for (auto& kv : free_) s = std::max(s, kv.second);
-  return s;
 }
 
 DeviceGuard::DeviceGuard(int dev) {
@@ -395,7 +334,7 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   set_error("");
   GRASP_CHECK_CTX(ctx);
   if (!d || !out || !d->values) return fail(GRASP_EINVAL, "desc/out/values is NULL");
-  if (d->n < 2 || d->n > 1024) return fail(GRASP_EINVAL, "n must be in [2, 1024]");
+  if (d->n < 2 || d->n > 512) return fail(GRASP_EINVAL, "n must be in [2, 512]");
   if (!(d->h > 0.0f) || !finite(d->h) || !finite(d->lo[0]) || !finite(d->lo[1]) || !finite(d->lo[2]))
     return fail(GRASP_EINVAL, "h must be > 0 and lo finite");
   const size_t n = static_cast<size_t>(d->n);
@@ -441,6 +380,7 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   s->view.inv_Im = static_cast<float>(1.0 / Im);
   s->view.values = reinterpret_cast<const float*>(b);
   s->view.cells = reinterpret_cast<const float4*>(b + vbytes);
+  s->view.cells_bytes = static_cast<uint32_t>(cbytes);
   s->block = blk;
   s->bytes = vbytes + cbytes;
   s->inertia_over_mass = static_cast<float>(Im);
@@ -740,7 +680,7 @@ grasp_status grasp_set_tile(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
   if (st != GRASP_OK) return st;
   const TileCfg c{tile->waves_per_block, tile->min_waves_per_simd};
-  if (!valid_tile(c)) return fail(GRASP_EINVAL, "tile must have waves_per_block in {1,2,4} and min_waves_per_simd in 1..4");
+  if (!valid_tile(c)) return fail(GRASP_EINVAL, "tile must have waves_per_block in {1,2,4} and min_waves_per_simd in 1..6");
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tiles[shape_key(r, B)] = c;
   return GRASP_OK;
@@ -780,7 +720,7 @@ grasp_status grasp_tune(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, co
   TileCfg bestc{};
   float bestt = 1e30f;
   for (int wpb : {1, 2, 4}) {
-    for (int occ = 1; occ <= 4 && e == hipSuccess; ++occ) {
+    for (int occ = 1; occ <= 6 && e == hipSuccess; ++occ) {
       const TileCfg c{wpb, occ};
       e = hipMemcpyAsync(sq, q, nq, hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess) e = hipMemsetAsync(sm, 0, 2 * nq, s);

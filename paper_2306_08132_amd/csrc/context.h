@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/grasp.h"
+#include "arena.h"
 #include "internal.h"
 
 namespace grasp {
@@ -21,23 +22,6 @@ namespace grasp {
 // Thread-local last-error text.
 void set_error(const std::string& msg);
 grasp_status fail(grasp_status code, const std::string& msg);
-
-// First-fit sub-allocator over one device range (256-byte granules).
-class Arena {
- public:
-  void reset(char* base, size_t bytes);
-  void* alloc(size_t bytes);   // nullptr when no block fits
-  void free(void* p);
-  size_t capacity() const { return bytes_; }
-  size_t used() const;
-  size_t largest_free() const;
-
- private:
-  char* base_ = nullptr;
-  size_t bytes_ = 0;
-  std::map<size_t, size_t> free_;   // offset -> size
-  std::map<size_t, size_t> used_;   // offset -> size
-};
 
 struct DevHand {
   HandView view{};

@@ -103,8 +103,13 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   s.fz = bz - static_cast<float>(iz);
   const int nc = S.n - 1;
   const int cell = (iz * nc + iy) * nc + ix;
-  const float4 lo4 = S.cells[2 * cell];
-  const float4 hi4 = S.cells[2 * cell + 1];
+  // two 16-byte buffer loads of the cell's corners (32-bit offsets; an offset
+  // past cells_bytes would read zeros, never fault)
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(S.cells), static_cast<short>(0),
+                                        static_cast<int>(S.cells_bytes), 0x00020000);
+  const float4 lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 32, 0, 0));
+  const float4 hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 32 + 16, 0, 0));
   // corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
   s.dx00 = lo4.y - lo4.x;
   s.dx10 = lo4.w - lo4.z;

@@ -49,6 +49,7 @@ struct SdfView {
   float inv_Im;            // 1 / (I/m)
   const float* values;     // [N^3], x fastest
   const float4* cells;     // [(N-1)^3][2]: corners (000,100,010,110), (001,101,011,111)
+  uint32_t cells_bytes;    // size of cells (< 4 GiB: buffer loads use 32-bit offsets)
 };
 
 // Device copy of the step parameters.
@@ -71,7 +72,8 @@ constexpr int kOffJ = kOffT + kMaxLinks * 12;  // [kMaxLinks][6] joint world ori
 constexpr int kOffW = kOffJ + kMaxLinks * 6;   // [kMaxLinks][6] link force, torque adjoints
 constexpr int kUStride = 32;
 constexpr int kOffU = kOffW + kMaxLinks * 6;   // [7][32] per-test constants
-constexpr int kOffPose = kOffU + kSims * kUStride;
+constexpr int kOffWS = kOffU + kSims * kUStride;   // [7][6] summed corrections of the last pass (+6 pad)
+constexpr int kOffPose = kOffWS + 48;
 
 __host__ __device__ inline int pose_slots(int K, int ckpt) { return K / ckpt + 1; }
 __host__ __device__ inline size_t wave_lds_floats(int K, int ckpt) {

@@ -67,26 +67,25 @@ __device__ __forceinline__ void load_rot(const float* U, Rot& o) {
   o.A = U[15]; o.B = U[16]; o.Ap = U[17]; o.Bp = U[18];
 }
 
-// One forward projection iteration over all contacts: the 7 x 6 correction
-// sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
-// on the rest test of the first iteration, the penetration energy.
-template <bool KONE>
-__device__ void forward_pass(const Ctx& c, bool first, float W[kSims][6], float& lpen,
-                             float* trace_s /*caller-order samples for this k, or null*/,
-                             int K, int k) {
+// Tests [M0, M1) of one pass: with all 7 in one group the tests of a contact
+// share its point and unchanged coordinates; a group per test keeps only 6
+// sums live (the K > 1 path, whose samples carry rotations).
+template <bool KONE, int M0, int M1>
+__device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, dv = c.P.dt * c.P.v0;
-  for (int m = 0; m < kSims; ++m)
+  float W[kSims][6];
+  for (int m = M0; m < M1; ++m)
     for (int j = 0; j < 6; ++j) W[m][j] = 0.0f;
-  lpen = 0.0f;
+  float lp = 0.0f;
   for (int ch = 0; ch < H.n_chunks; ++ch) {
     const int i = ch * kWave + c.lane;
     const bool valid = i < H.Nc;
     int link;
     const V3 p = contact_point(c, i, link);
 #pragma unroll
-    for (int m = 0; m < kSims; ++m) {
+    for (int m = M0; m < M1; ++m) {
       V3 a, r;
       Rot o;
       if constexpr (KONE) {
@@ -102,7 +101,7 @@ __device__ void forward_pass(const Ctx& c, bool first, float W[kSims][6], float&
       sample_sdf(S, r, s);
       const V3 g = KONE ? s.n : mul(o.R, s.n);
       const float d = s.phi - rd;
-      if (first && m == kSims - 1 && valid && d < 0.0f) lpen = fmaf(0.5f * d, d, lpen);
+      if (first && m == kSims - 1 && valid && d < 0.0f) lp = fmaf(0.5f * d, d, lp);
       float lam = 0.0f, w = 0.0f;
       if (valid && (d < 0.0f || trace_s)) {
         const V3 u = cross(a, g);
@@ -123,9 +122,33 @@ __device__ void forward_pass(const Ctx& c, bool first, float W[kSims][6], float&
       }
     }
   }
-  for (int m = 0; m < kSims; ++m)
-    for (int j = 0; j < 6; ++j) W[m][j] = wave_sum(W[m][j]);
-  lpen = wave_sum(lpen);
+  // the sums are wave-uniform: park them in LDS rather than in registers
+  for (int m = M0; m < M1; ++m)
+    for (int j = 0; j < 6; ++j) {
+      const float t = wave_sum(W[m][j]);
+      if (c.lane == 0) c.lds[kOffWS + 6 * m + j] = t;
+    }
+  if (M1 == kSims) lpen = wave_sum(lp);
+}
+
+// One forward projection iteration over all contacts: the 7 x 6 correction
+// sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
+// on the rest test of the first iteration, the penetration energy.
+template <bool KONE>
+__device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
+  lpen = 0.0f;
+  if constexpr (KONE) {
+    forward_tests<true, 0, kSims>(c, first, lpen, trace_s, K, k);
+  } else {
+    forward_tests<false, 0, 1>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 1, 2>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 2, 3>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 3, 4>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 4, 5>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 5, 6>(c, first, lpen, trace_s, K, k);
+    forward_tests<false, 6, 7>(c, first, lpen, trace_s, K, k);
+  }
+  wave_lds_sync();
 }
 
 // Adds the 6 per-lane values of link l (wave sum) into the link wrench table.
@@ -142,15 +165,15 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
 // iteration k). The per-test seeds Wl_bar, Wa_bar (adjoints of the summed
 // corrections) are in LDS. Adds p_bar x p and p_bar to the link wrench table
 // and, when pose_adj, returns the pose adjoint sums (-sum a_bar, sum theta_bar).
-template <bool KONE>
-__device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj,
-                              float XB[kSims][6]) {
+template <bool KONE, int M0, int M1>
+__device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, dv = c.P.dt * c.P.v0;
   const float inv_Im = S.inv_Im;
+  float XB[kSims][6];
   if (pose_adj)
-    for (int m = 0; m < kSims; ++m)
+    for (int m = M0; m < M1; ++m)
       for (int j = 0; j < 6; ++j) XB[m][j] = 0.0f;
   float acc[6] = {0, 0, 0, 0, 0, 0};
   int cur = -1;
@@ -161,7 +184,7 @@ __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pos
     const V3 p = contact_point(c, i, link);
     V3 pbar = v3(0.0f, 0.0f, 0.0f);
 #pragma unroll
-    for (int m = 0; m < kSims; ++m) {
+    for (int m = M0; m < M1; ++m) {
       const float* U = c.lds + kOffU + kUStride * m;
       V3 a, r;
       Rot o;
@@ -203,15 +226,26 @@ __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pos
         }
       }
       if (first && m == kSims - 1 && valid && d < 0.0f) dbar = fmaf(pen_seed, d, dbar);
+      // second derivative only for penetrating samples: their cell is
+      // gathered again (from cache) instead of keeping every sample's
+      // corners live across the unrolled tests
       V3 rbar;
       if constexpr (KONE) {
         rbar = dbar * s.n;
-        if (pen) rbar = rbar + hess_mul(S, s, gbar);
+        if (pen) {
+          Sample s2;
+          sample_sdf(S, r, s2);
+          rbar = rbar + hess_mul(S, s2, gbar);
+        }
         abar = abar + rbar;
       } else {
         const V3 nbar = mul_t(o.R, gbar);
         rbar = dbar * s.n;
-        if (pen) rbar = rbar + hess_mul(S, s, nbar);
+        if (pen) {
+          Sample s2;
+          sample_sdf(S, r, s2);
+          rbar = rbar + hess_mul(S, s2, nbar);
+        }
         abar = abar + mul(o.R, rbar);
         if (pose_adj && valid) {
           V3 thb = v3(0.0f, 0.0f, 0.0f);
@@ -247,20 +281,45 @@ __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pos
     }
   }
   if (cur >= 0) flush_link(c, cur, acc);
+  // pose adjoint of the previous iteration: running adjoint += this pass's sums
   if (pose_adj)
-    for (int m = 0; m < kSims; ++m)
-      for (int j = 0; j < 6; ++j) XB[m][j] = wave_sum(XB[m][j]);
+    for (int m = M0; m < M1; ++m)
+      for (int j = 0; j < 6; ++j) {
+        const float t = wave_sum(XB[m][j]);
+        if (c.lane == 0) c.lds[kOffU + kUStride * m + 25 + j] += t;
+      }
   wave_lds_sync();
+}
+
+// One backward iteration over all contacts (the adjoint of forward_pass at
+// iteration k). The per-test seeds (adjoints of the summed corrections) are
+// in LDS. Adds p_bar and p x p_bar to the link wrench table and, when
+// pose_adj, returns the pose adjoint sums (-sum a_bar, sum theta_bar).
+template <bool KONE>
+__device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
+  if constexpr (KONE) {
+    backward_tests<true, 0, kSims>(c, first, pen_seed, pose_adj);
+  } else {
+    backward_tests<false, 0, 1>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 1, 2>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 2, 3>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 3, 4>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 4, 5>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 5, 6>(c, first, pen_seed, pose_adj);
+    backward_tests<false, 6, 7>(c, first, pen_seed, pose_adj);
+  }
 }
 
 __device__ __forceinline__ float* pose_slot(float* lds, int s) { return lds + kOffPose + s * kSims * 6; }
 
-// Writes pose_new = pose_old + (omega W_lin, omega/(I/m) W_ang) for all tests.
-__device__ __forceinline__ void advance_pose(const Ctx& c, const float* pold, float* pnew, const float W[kSims][6]) {
+// Writes pose_new = pose_old + (omega W_lin, omega/(I/m) W_ang) for all tests
+// from the last forward pass's sums (in LDS).
+__device__ __forceinline__ void advance_pose(const Ctx& c, const float* pold, float* pnew) {
   const float om = c.P.omega, omi = c.P.omega * c.S.inv_Im;
-  if (c.lane == 0)
-    for (int m = 0; m < kSims; ++m)
-      for (int j = 0; j < 6; ++j) pnew[6 * m + j] = fmaf(j < 3 ? om : omi, W[m][j], pold[6 * m + j]);
+  if (c.lane < kSims * 6) {
+    const int j = c.lane % 6;
+    pnew[c.lane] = fmaf(j < 3 ? om : omi, c.lds[kOffWS + c.lane], pold[c.lane]);
+  }
   wave_lds_sync();
 }
 
@@ -306,7 +365,6 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
     }
 
   float lpen = 0.0f;
-  float W[kSims][6];
   // ---- forward: K projection iterations, checkpoints every ck ----
   if (do_fwd) {
     init_pose(c, pose_slot(lds, 0));
@@ -320,9 +378,9 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
       if constexpr (!KONE) load_test_consts(c, cur);
       float lp;
       float* ts = A.trace_samples ? A.trace_samples + static_cast<size_t>(b) * kSims * K * H.Nc * 6 : nullptr;
-      forward_pass<KONE>(c, k == 0, W, lp, ts, K, k);
+      forward_pass<KONE>(c, k == 0, lp, ts, K, k);
       if (k == 0) lpen = lp;
-      advance_pose(c, cur, cur, W);
+      advance_pose(c, cur, cur);
       if ((k + 1) % ck == 0) {
         float* dst = pose_slot(lds, (k + 1) / ck);
         if (lane < kSims * 6) dst[lane] = cur[lane];
@@ -376,58 +434,49 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
   // ---- backward ----
   const float sL = A.dloss ? A.dloss[b] : 1.0f;
   for (int t = lane; t < kMaxLinks * 6; t += kWave) lds[kOffW + t] = 0.0f;
-  // seeds: d L / d x^K_m and d L / d theta^K_m
-  float XB[kSims][6];
-  {
+  // seeds: lane m < 7 keeps dL/dx and dL/dtheta of test m after the last
+  // iteration in its LDS slot U[25..30] (the running pose adjoint)
+  if (lane < kSims) {
     const float cst = sL * P.w_stable / (kSims * P.dt);
-    for (int m = 0; m < kSims; ++m) {
-      const float* pm = fin + 6 * m;
-      const V3 x = v3(pm[0], pm[1], pm[2]), th = v3(pm[3], pm[4], pm[5]);
-      const float nx = sqrtf(dot(x, x)), nt = sqrtf(dot(th, th));
-      // |v| = |x|/dt; its derivative is x/|x| / dt (0 at the origin)
-      const float fx = nx > 0.0f ? cst / nx : 0.0f;
-      const float ft = nt > 0.0f ? cst / nt : 0.0f;
-      XB[m][0] = fx * x.x; XB[m][1] = fx * x.y; XB[m][2] = fx * x.z;
-      XB[m][3] = ft * th.x; XB[m][4] = ft * th.y; XB[m][5] = ft * th.z;
-    }
+    const float* pm = fin + 6 * lane;
+    const V3 x = v3(pm[0], pm[1], pm[2]), th = v3(pm[3], pm[4], pm[5]);
+    const float nx = sqrtf(dot(x, x)), nt = sqrtf(dot(th, th));
+    // |v| = |x|/dt; its derivative is x/|x| / dt (0 at the origin)
+    const float fx = nx > 0.0f ? cst / nx : 0.0f;
+    const float ft = nt > 0.0f ? cst / nt : 0.0f;
+    float* U = lds + kOffU + kUStride * lane;
+    U[25] = fx * x.x; U[26] = fx * x.y; U[27] = fx * x.z;
+    U[28] = ft * th.x; U[29] = ft * th.y; U[30] = ft * th.z;
   }
   const float pen_seed = sL * P.w_pen;
   const int nseg = K / ck;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     // replay the segment's iterations from its checkpoint (none when ck = 1)
     float* segbuf = pose_slot(lds, nslots);  // ck slots: poses seg*ck .. seg*ck+ck-1
-    {
+    if constexpr (!KONE) {
       const float* ckp = pose_slot(lds, seg);
       if (lane < kSims * 6) segbuf[lane] = ckp[lane];
       wave_lds_sync();
       for (int j = 1; j < ck; ++j) {
-        if constexpr (!KONE) load_test_consts(c, segbuf + (j - 1) * kSims * 6);
+        load_test_consts(c, segbuf + (j - 1) * kSims * 6);
         float lp;
-        forward_pass<KONE>(c, false, W, lp, nullptr, K, seg * ck + j - 1);
-        advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6, W);
+        forward_pass<KONE>(c, false, lp, nullptr, K, seg * ck + j - 1);
+        advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6);
       }
     }
     for (int j = ck - 1; j >= 0; --j) {
       const int k = seg * ck + j;
       if constexpr (!KONE) load_test_consts(c, segbuf + j * kSims * 6);
-      // seeds of this iteration's correction sums
+      // seeds of this iteration's correction sums from the running adjoint
       if (lane < kSims) {
         float* U = lds + kOffU + kUStride * lane;
         const float om = P.omega, omi = P.omega * c.S.inv_Im;
-        float xb[6];
-        for (int m = 0; m < kSims; ++m)
-          if (m == lane)
-            for (int t = 0; t < 6; ++t) xb[t] = XB[m][t];
-        U[19] = om * xb[0]; U[20] = om * xb[1]; U[21] = om * xb[2];
-        U[22] = omi * xb[3]; U[23] = omi * xb[4]; U[24] = omi * xb[5];
+        U[19] = om * U[25]; U[20] = om * U[26]; U[21] = om * U[27];
+        U[22] = omi * U[28]; U[23] = omi * U[29]; U[24] = omi * U[30];
       }
       wave_lds_sync();
-      float D[kSims][6];
-      const bool need_pose = !KONE && k > 0;
-      backward_pass<KONE>(c, k == 0, pen_seed, need_pose, D);
-      if (need_pose)
-        for (int m = 0; m < kSims; ++m)
-          for (int t = 0; t < 6; ++t) XB[m][t] += D[m][t];
+      if constexpr (KONE) backward_pass<KONE>(c, true, pen_seed, false);
+      else backward_pass<KONE>(c, k == 0, pen_seed, k > 0);
     }
   }
 
@@ -572,13 +621,15 @@ void launch_occ(const StepArgs& a, int kind, bool adam, TileCfg cfg, size_t lds,
     case 2: launch_variant<KONE, 2>(a, kind, adam, cfg.wpb, lds, stream); break;
     case 3: launch_variant<KONE, 3>(a, kind, adam, cfg.wpb, lds, stream); break;
     case 4: launch_variant<KONE, 4>(a, kind, adam, cfg.wpb, lds, stream); break;
+    case 5: launch_variant<KONE, 5>(a, kind, adam, cfg.wpb, lds, stream); break;
+    case 6: launch_variant<KONE, 6>(a, kind, adam, cfg.wpb, lds, stream); break;
     default: launch_variant<KONE, 1>(a, kind, adam, cfg.wpb, lds, stream); break;
   }
 }
 }  // namespace
 
 bool valid_tile(TileCfg c) {
-  return (c.wpb == 1 || c.wpb == 2 || c.wpb == 4) && (c.occ >= 1 && c.occ <= 4);
+  return (c.wpb == 1 || c.wpb == 2 || c.wpb == 4) && (c.occ >= 1 && c.occ <= 6);
 }
 
 hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream) {
@@ -608,9 +659,13 @@ hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone,
     case 12: launch_batch_variant<true, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     case 13: launch_batch_variant<true, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     case 14: launch_batch_variant<true, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 15: launch_batch_variant<true, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 16: launch_batch_variant<true, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     case 2: launch_batch_variant<false, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     case 3: launch_batch_variant<false, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     case 4: launch_batch_variant<false, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 5: launch_batch_variant<false, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 6: launch_batch_variant<false, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
     default:
       if (kone) launch_batch_variant<true, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);
       else launch_batch_variant<false, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);

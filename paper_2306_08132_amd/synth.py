@@ -342,11 +342,13 @@ def bound_radius(prims) -> float:
 
 
 def make_grid(prims, n: int, margin: float = 2.0 * CM, side: float | None = None,
-              lo=None, chunk: int = 1 << 17) -> Grid:
+              lo=None, chunk: int = 1 << 17, device: str | None = None) -> Grid:
     """FP32 vertex-centred SDF grid of the union of ``prims``.
 
     The cube is centred on the origin with side 2 (R_bound + margin), where
     R_bound is the largest |centre| + semi-axis; a 4 cm sphere gives 12 cm.
+    With ``device`` (a torch device) the same FP64 distances are evaluated
+    with torch there, which large grids need to be built in seconds.
     """
     rb = bound_radius(prims)
     if side is None:
@@ -354,12 +356,69 @@ def make_grid(prims, n: int, margin: float = 2.0 * CM, side: float | None = None
     lo = np.full(3, -0.5 * side) if lo is None else np.asarray(lo, np.float64)
     h = side / (n - 1)
     g = Grid(n=n, lo=lo, h=h, values=np.empty(0, np.float32), prims=prims, bound_radius=rb)
+    if device is not None:
+        g.values = _grid_values_torch(prims, n, lo, h, device)
+        return g
     pos = g.vertex_positions()
     vals = np.empty(pos.shape[0], np.float64)
     for s in range(0, pos.shape[0], chunk):
         vals[s:s + chunk] = object_sdf(prims, pos[s:s + chunk])
     g.values = vals.astype(np.float32)
     return g
+
+
+def _grid_values_torch(prims, n, lo, h, device, chunk=1 << 22):
+    """Vertex values of the union in FP64 with torch (same formulas as the
+    numpy path: exact sphere/box distances, ellipsoid by the Newton root)."""
+    import torch
+    i = torch.arange(n, dtype=torch.float64, device=device) * h
+    out = torch.empty(n ** 3, dtype=torch.float64, device=device)
+    z, y, x = torch.meshgrid(i + lo[2], i + lo[1], i + lo[0], indexing="ij")
+    P = torch.stack([x, y, z], dim=-1).reshape(-1, 3)
+    del x, y, z
+    for s in range(0, P.shape[0], chunk):
+        p = P[s:s + chunk]
+        best = None
+        for pr in prims:
+            if pr[0] == "sphere":
+                d = torch.linalg.norm(p - torch.as_tensor(pr[1], device=device), dim=-1) - pr[2]
+            elif pr[0] == "box":
+                yb = (p - torch.as_tensor(pr[1], device=device)) @ torch.as_tensor(pr[2], device=device)
+                q = yb.abs() - torch.as_tensor(pr[3], device=device)
+                d = torch.linalg.norm(q.clamp(min=0.0), dim=-1) + q.max(dim=-1).values.clamp(max=0.0)
+            else:
+                d = _ellipsoid_torch(p, pr[1], pr[2], pr[3], device)
+            best = d if best is None else torch.minimum(best, d)
+        out[s:s + chunk] = best
+    return out.to(torch.float32).cpu().numpy()
+
+
+def _ellipsoid_torch(p, center, rotation, semi, device, iters=16):
+    import torch
+    e = torch.as_tensor(semi, dtype=torch.float64, device=device)
+    y = ((p - torch.as_tensor(center, device=device)) @ torch.as_tensor(rotation, device=device)).abs()
+    y = torch.where(y == 0.0, torch.full_like(y, 1e-30), y)
+    e2 = e * e
+    ey = e * y
+    lo = (ey - e2).max(dim=-1).values
+    lo = torch.clamp(lo, min=float(-e2.min()) + 1e-300)
+    hi = torch.maximum(torch.sqrt((ey * ey).sum(dim=-1)), lo)
+    t = lo.clone()
+    for _ in range(iters):
+        den = t[:, None] + e2
+        rat = ey / den
+        Fv = (rat * rat).sum(dim=-1) - 1.0
+        dF = -2.0 * (rat * rat / den).sum(dim=-1)
+        step = torch.where(dF < 0.0, -Fv / dF, torch.zeros_like(Fv))
+        tn = t + step
+        lo = torch.where(Fv >= 0.0, t, lo)
+        hi = torch.where(Fv < 0.0, t, hi)
+        bad = ~((tn >= lo) & (tn <= hi))
+        t = torch.where(bad, 0.5 * (lo + hi), tn)
+    x = e2 * y / (t[:, None] + e2)
+    dist = torch.linalg.norm(x - y, dim=-1)
+    inside = ((y / e) ** 2).sum(dim=-1) < 1.0
+    return torch.where(inside, -dist, dist)
 
 
 def random_points(grid: Grid, n: int, seed: int, outside_frac: float = 0.25):
@@ -422,7 +481,7 @@ def adam_state(B: int, n_dof: int, seed: int, scale: float = 1.0):
 # the workloads
 # ----------------------------------------------------------------------------
 def config_workload(name: str, seed: int | None = None, B: int | None = None,
-                    n: int | None = None, n_contacts: int | None = None):
+                    n: int | None = None, n_contacts: int | None = None, device: str | None = None):
     """(hand, grid, q0) for a named workload, optionally shrunk for tests.
 
     tiny  : 3 fingers x 3 joints (15 DOF), 512 contacts, 4 cm sphere, 64^3 grid
@@ -442,13 +501,13 @@ def config_workload(name: str, seed: int | None = None, B: int | None = None,
         s = 1 if seed is None else seed
         hand = make_hand(4, 4, n_contacts or 2048, seed=s)
         prims = make_object("ellipsoids", seed=s, n_range=(3, 6))
-        grid = make_grid(prims, n or 128)
+        grid = make_grid(prims, n or 128, device=device)
         q = make_candidates(hand, B or 4096, seed=s + 100, shell_radius=grid.bound_radius + 6.0 * CM)
     elif name == "large":
         s = 4 if seed is None else seed
         hand = make_hand(5, 4, n_contacts or 8192, seed=s)
         prims = make_object("mixed", seed=s, n_prims=8)
-        grid = make_grid(prims, n or 256)
+        grid = make_grid(prims, n or 256, device=device)
         q = make_candidates(hand, B or 65536, seed=s + 100, shell_radius=grid.bound_radius + 6.0 * CM)
     else:
         raise ValueError(name)

@@ -328,7 +328,7 @@ def test_every_tile_bit_identical(ctx, tiny):
         sp, _ = prm_pair(r_dil=0.004, K=K)
         B = 40
         for wpb in (1, 2, 4):
-            for occ in (1, 2, 3, 4):
+            for occ in (1, 2, 3, 4, 5, 6):
                 ctx.set_tile(h, sd, sp, B, wpb, occ)
                 qd = dev(q[:B])
                 m, v = torch.zeros_like(qd), torch.zeros_like(qd)

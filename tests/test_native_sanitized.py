@@ -1,0 +1,33 @@
+"""Host code under AddressSanitizer and UBSan (CPU only): the context arena
+allocator against a byte-map model, and the oracle on a small problem."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all", "-g", "-O1"]
+
+
+def build_and_run(tmp_path, name, srcs, incs, extra=()):
+    exe = str(tmp_path / name)
+    cmd = ["g++", "-std=c++17"] + SAN + list(extra) + [f"-I{i}" for i in incs] + srcs + ["-o", exe]
+    subprocess.run(cmd, check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
+    out = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    return out.stdout
+
+
+def test_arena_under_sanitizers(tmp_path):
+    csrc = os.path.join(ROOT, "paper_2306_08132_amd", "csrc")
+    out = build_and_run(tmp_path, "arena_check", [os.path.join(ROOT, "tests", "native", "arena_check.cpp"),
+                                                   os.path.join(csrc, "arena.cpp")], [csrc])
+    assert "arena ok" in out
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    od = os.path.join(ROOT, "oracle")
+    out = build_and_run(tmp_path, "oracle_check", [os.path.join(ROOT, "tests", "native", "oracle_check.cpp"),
+                                                    os.path.join(od, "oracle.cpp")], [od], extra=["-fopenmp"])
+    assert "oracle ok" in out
