@@ -164,7 +164,8 @@ grasp_status grasp_step_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, gras
 /* Forward: loss (dev [B]) and terms (dev [B][4] = L_stable, L_pen, L_range,
  * L_limit, or NULL) for configurations q (dev [B][n_dof]). In SAVE mode ws
  * (dev, ws_bytes from grasp_step_workspace_bytes) receives the pose
- * checkpoints the backward reads; otherwise ws may be NULL.
+ * checkpoints the backward reads; otherwise ws may be NULL. A candidate
+ * whose q has a NaN or Inf entry gets a NaN loss (every form).
  * ENOMEM if ws_bytes is too small for SAVE. */
 grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
                             const grasp_step_params* p, int32_t B, const float* q, float* loss,

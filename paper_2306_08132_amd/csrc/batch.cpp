@@ -213,7 +213,9 @@ grasp_status grasp_batch_flags(grasp_batch* bt, int32_t n, int32_t* out) {
   set_error("");
   if (!bt || !out || n < 0 || n > bt->max_jobs) return fail(GRASP_EINVAL, "bad arguments");
   DeviceGuard g(bt->ctx->device);
-  hipError_t e = hipMemcpy(out, bt->flags_dev, static_cast<size_t>(n) * sizeof(int), hipMemcpyDeviceToHost);
+  // the flags are written by the last step, which may run on any stream
+  hipError_t e = bt->last ? hipEventSynchronize(bt->last) : hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(out, bt->flags_dev, static_cast<size_t>(n) * sizeof(int), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemset(bt->flags_dev, 0, static_cast<size_t>(n) * sizeof(int));
   if (e != hipSuccess) return device_fail(bt->ctx, e, "grasp_batch_flags");
   return GRASP_OK;

@@ -143,8 +143,10 @@ __global__ void pk_loss(PlainArgs a) {
     r2 = fmaf(dm, dm, r2);
     lim += fmaxf(qb[j] - up, 0.0f) + fmaxf(lo - qb[j], 0.0f);
   }
+  bool qbad = false;
+  for (int j = 0; j < a.H.n_dof; ++j) qbad = qbad || !isfinite(qb[j]);
   const float lr = sqrtf(r2), lp = a.lpen[b];
-  const float L = P.w_stable * ls + P.w_pen * lp + P.w_range * lr + P.w_limit * lim;
+  const float L = qbad ? __builtin_nanf("") : P.w_stable * ls + P.w_pen * lp + P.w_range * lr + P.w_limit * lim;
   a.loss[b] = L;
   if (a.terms) {
     a.terms[4 * b] = ls; a.terms[4 * b + 1] = lp; a.terms[4 * b + 2] = lr; a.terms[4 * b + 3] = lim;

@@ -226,17 +226,11 @@ __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool po
         }
       }
       if (first && m == kSims - 1 && valid && d < 0.0f) dbar = fmaf(pen_seed, d, dbar);
-      // second derivative only for penetrating samples: their cell is
-      // gathered again (from cache) instead of keeping every sample's
-      // corners live across the unrolled tests
+      // second derivative only for penetrating samples
       V3 rbar;
       if constexpr (KONE) {
         rbar = dbar * s.n;
-        if (pen) {
-          Sample s2;
-          sample_sdf(S, r, s2);
-          rbar = rbar + hess_mul(S, s2, gbar);
-        }
+        if (pen) rbar = rbar + hess_mul(S, s, gbar);
         abar = abar + rbar;
       } else {
         const V3 nbar = mul_t(o.R, gbar);
@@ -420,7 +414,11 @@ __device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, fl
   const float Lrange = sqrtf(range2);
   const float Llimit = wave_sum(lim);
   if (do_fwd && kind != STEP_BWD) {
-    const float L = P.w_stable * Lstable + P.w_pen * lpen + P.w_range * Lrange + P.w_limit * Llimit;
+    // a configuration with a non-finite coordinate has no defined loss; the
+    // grid clamp would otherwise map it to a finite corner value
+    const bool qbad = __builtin_amdgcn_ballot_w64(lane < nd && !isfinite(qj)) != 0;
+    const float L = qbad ? __builtin_nanf("")
+                         : P.w_stable * Lstable + P.w_pen * lpen + P.w_range * Lrange + P.w_limit * Llimit;
     if (lane == 0) {
       if (A.loss) A.loss[b] = L;
       if (A.terms) {

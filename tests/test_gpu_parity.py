@@ -3,8 +3,10 @@ same seeded inputs. Tolerances: relative 1e-5 on SDF samples and contact
 positions, 1e-4 on losses, 1e-3 on gradients; exact on contact-to-link
 indexing and ranking. A sample within 2.5e-7 m of d = 0 (about five times
 the FP32 error of d at these coordinates) may take the other branch of the
-leaky rule in FP32; candidates holding one are reported and may not exceed a
-small fraction."""
+leaky rule in FP32; candidates holding one are reported and may not exceed
+a small fraction. Where the FP64 gradient itself moves by more than a
+quarter of the tolerance under FP32-resolution changes of q (|v| near zero),
+the gradient tolerance is four times that movement."""
 import numpy as np
 import pytest
 import torch
@@ -152,12 +154,25 @@ def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05):
     lerr = np.abs(loss - ref["loss"]) / floor
     gscale = np.abs(ref["grad"]).max(axis=1)
     gerr = np.abs(dq - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30)
+    # conditioning: how far the FP64 gradient itself moves when q is perturbed
+    # at FP32 resolution (2^-24 relative). Near |v| = 0 the stable term's
+    # gradient v/|v| is ill-conditioned, and more so after several projection
+    # iterations; there the tolerance widens to four times that movement.
+    cond = np.zeros(B)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        qp = q32 * (1.0 + rng.normal(size=q32.shape) * 6e-8)
+        gp = O.step(ohand(hand), O.Obj(grid), op, qp)["grad"]
+        cond = np.maximum(cond, np.abs(gp - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30))
+    gtol = np.maximum(1e-3, 4.0 * cond)
     flagged = ref["min_abs_d"] < KINK_D
     say(f"{label}: B={B} max loss rel err {lerr.max():.2e}, grad rel err max(unflagged) "
         f"{gerr[~flagged].max() if (~flagged).any() else 0:.2e}, median {np.median(gerr):.2e}, "
+        f"widened tol {(gtol > 1e-3).sum()} (max {gtol.max():.2e}), "
         f"flagged {flagged.mean():.3f} (their grad errs {np.round(gerr[flagged], 5).tolist()})")
     assert np.all(lerr <= 1e-4), (np.argmax(lerr), lerr.max())
-    assert np.all(gerr[~flagged] <= 1e-3), (np.nonzero(~flagged)[0][np.argmax(gerr[~flagged])], gerr[~flagged].max())
+    bad = ~flagged & (gerr > gtol)
+    assert not bad.any(), (np.nonzero(bad)[0], gerr[bad], gtol[bad])
     assert flagged.mean() <= max_flagged
     return loss, dq, ref
 
@@ -277,7 +292,7 @@ def test_gradient_matches_finite_differences(ctx, tiny):
 
 
 def test_nonfinite_input_stays_in_bounds(ctx, tiny):
-    """NaN/Inf configurations give non-finite losses, never a bad access."""
+    """A NaN/Inf coordinate (wrist or finger) gives a NaN loss, never a bad access."""
     hand, grid, q = tiny
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     sp, _ = prm_pair()
@@ -292,7 +307,7 @@ def test_nonfinite_input_stays_in_bounds(ctx, tiny):
     ctx.step_bwd(h, sd, sp, qd, dq)
     torch.cuda.synchronize()
     l = loss.cpu().numpy()
-    assert not np.isfinite(l[:3]).all() and np.isfinite(l[3])
+    assert not np.isfinite(l[:3]).any() and np.isfinite(l[3])
 
 
 def test_full_size_diff_sampled(ctx):
