@@ -331,7 +331,7 @@ __device__ __forceinline__ void init_pose(const Ctx& c, float* p0) {
 // the per-candidate step
 // ---------------------------------------------------------------------------
 template <bool KONE>
-__device__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
+__device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
   const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id()};
