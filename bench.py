@@ -37,7 +37,7 @@ def algorithmic_bytes(B, Nc, K, n_dof, n):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("step_kernels.hip", "internal.h"):
+    for f in ("step_kernels.hip", "device_common.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2306_08132_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -225,7 +225,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the grasp step shards by "
-              "candidates with no exchange inside a step, so this build measures one GPU's share.",
+              "candidates with no exchange inside a step, so one GPU's share is what it measures.",
               file=sys.stderr)
         sys.exit(2)
 

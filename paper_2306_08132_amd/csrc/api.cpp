@@ -147,6 +147,7 @@ void grasp_shutdown(grasp_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
     if (ctx->arena_owned) (void)hipFree(ctx->arena_base);
   }
   delete ctx;
@@ -508,6 +509,36 @@ grasp_status check_adam(int32_t t, float lr, float b1, float b2, float eps) {
   return GRASP_OK;
 }
 
+// One single-job step launch with the candidate locality order (B >= kOrderMinB,
+// not under stream capture): the order kernel and the step run on stream s
+// after the previous user of the context's order buffer, on any stream, has
+// finished with it. Without memory for the buffer the step runs unordered.
+hipError_t launch_ordered_step(grasp_ctx* ctx, StepArgs a, StepKind kind, bool adam, TileCfg tc, hipStream_t s) {
+  a.order = nullptr;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return e;
+  if (a.B < kOrderMinB || cap != hipStreamCaptureStatusNone) return launch_step(a, kind, adam, tc, s);
+  std::lock_guard<std::mutex> lk(ctx->order_mu);
+  if (ctx->order_cap < a.B) {
+    // the old buffer may still be read by a launch on another stream
+    if (ctx->order_ev) e = hipEventSynchronize(ctx->order_ev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lka(ctx->mu);
+    if (ctx->order_buf) ctx->arena.free(ctx->order_buf);
+    ctx->order_buf = static_cast<int*>(ctx->arena.alloc(static_cast<size_t>(a.B) * sizeof(int)));
+    ctx->order_cap = ctx->order_buf ? a.B : 0;
+  }
+  if (!ctx->order_buf) return launch_step(a, kind, adam, tc, s);
+  if (!ctx->order_ev) e = hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming);
+  else e = hipStreamWaitEvent(s, ctx->order_ev, 0);
+  if (e == hipSuccess) e = launch_order(a.q, a.hand.n_dof, a.B, a.sdf, ctx->order_buf, s);
+  a.order = ctx->order_buf;
+  if (e == hipSuccess) e = launch_step(a, kind, adam, tc, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->order_ev, s);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -543,7 +574,7 @@ grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   a.poses = save ? static_cast<float*>(ws) : nullptr;
   const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_FWD, false, tc, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_ordered_step(ctx, a, STEP_FWD, false, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fwd launch");
   return GRASP_OK;
 }
@@ -567,7 +598,7 @@ grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   a.poses = save ? static_cast<float*>(ws) : nullptr;
   const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_BWD, false, tc, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_ordered_step(ctx, a, STEP_BWD, false, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_bwd launch");
   return GRASP_OK;
 }
@@ -608,7 +639,7 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   a.adam = adam_consts(t, lr, b1, b2, eps);
   const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_step(a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
   return GRASP_OK;
 }
@@ -724,9 +755,9 @@ grasp_status grasp_tune(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, co
       const TileCfg c{wpb, occ};
       e = hipMemcpyAsync(sq, q, nq, hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess) e = hipMemsetAsync(sm, 0, 2 * nq, s);
-      if (e == hipSuccess) e = launch_step(a, STEP_FUSED, true, c, s);  // warm-up
+      if (e == hipSuccess) e = launch_ordered_step(ctx, a, STEP_FUSED, true, c, s);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, s);
-      for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_step(a, STEP_FUSED, true, c, s);
+      for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_ordered_step(ctx, a, STEP_FUSED, true, c, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;

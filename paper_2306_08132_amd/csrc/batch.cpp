@@ -69,6 +69,7 @@ grasp_status batch_fill(grasp_batch* bt, const grasp_batch_job* jobs, int32_t n,
     e.args.loss = j.loss;
     e.args.terms = j.terms;
     e.args.nonfinite = bt->flags_dev + i;
+    e.args.order = j.B >= kOrderMinB ? bt->order_dev + total : nullptr;
     e.begin = total;
     total += j.B;
     lds = std::max<int>(lds, static_cast<int>(wave_lds_floats(e.args.prm.K, e.args.prm.ckpt)));
@@ -97,7 +98,9 @@ grasp_status grasp_batch_create(grasp_ctx* ctx, int32_t capacity, int32_t max_jo
   bt->max_jobs = max_jobs;
   bt->use_graph = use_graph != 0;
   bt->half = (sizeof(BatchHeader) + static_cast<size_t>(max_jobs) * sizeof(BatchJob) + 255) / 256 * 256;
-  const size_t bytes = 2 * bt->half + static_cast<size_t>(max_jobs) * sizeof(int);
+  // [K=1 table][K>1 table][per-job flags][candidate order, capacity ints]
+  const size_t flags_bytes = (static_cast<size_t>(max_jobs) * sizeof(int) + 255) / 256 * 256;
+  const size_t bytes = 2 * bt->half + flags_bytes + static_cast<size_t>(capacity) * sizeof(int);
   DeviceGuard g(ctx->device);
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -108,6 +111,7 @@ grasp_status grasp_batch_create(grasp_ctx* ctx, int32_t capacity, int32_t max_jo
     return fail(GRASP_ENOMEM, "arena full (batch table)");
   }
   bt->flags_dev = reinterpret_cast<int*>(bt->dev + 2 * bt->half);
+  bt->order_dev = reinterpret_cast<int*>(bt->dev + 2 * bt->half + flags_bytes);
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&bt->host), 2 * bt->half, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemset(bt->flags_dev, 0, static_cast<size_t>(max_jobs) * sizeof(int));
   if (e != hipSuccess) {
@@ -183,7 +187,8 @@ grasp_status grasp_batch_step(grasp_batch* bt, grasp_batch_job* jobs, int32_t n,
     const TileCfg tc = bt->tile;
     const int blocks = (bt->capacity + tc.wpb - 1) / tc.wpb;
     if (!bt->use_graph || s == nullptr) {
-      e = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
+      e = launch_order_batch(hdr, tab, bt->max_jobs, s);
+      if (e == hipSuccess) e = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
       continue;
     }
     const auto key = std::make_tuple(group, tc.wpb, tc.occ, lds);
@@ -192,7 +197,8 @@ grasp_status grasp_batch_step(grasp_batch* bt, grasp_batch_job* jobs, int32_t n,
       BatchGraph bg{};
       e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
       if (e == hipSuccess) {
-        const hipError_t le = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
+        hipError_t le = launch_order_batch(hdr, tab, bt->max_jobs, s);
+        if (le == hipSuccess) le = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
         e = hipStreamEndCapture(s, &bg.graph);
         if (e == hipSuccess) e = le;
       }

@@ -30,9 +30,10 @@ struct grasp_batch {
   int32_t max_jobs = 0;
   bool use_graph = true;
   size_t half = 0;            // bytes of one table (header + jobs), 256-aligned
-  char* dev = nullptr;        // [K=1 table][K>1 table][per-job non-finite flags]
+  char* dev = nullptr;        // [K=1 table][K>1 table][per-job non-finite flags][orders]
   char* host = nullptr;       // pinned staging of both tables
   int* flags_dev = nullptr;
+  int* order_dev = nullptr;   // per-job candidate locality orders, capacity ints
   grasp::TileCfg tile{};
   std::vector<grasp::BatchView> views;
   std::map<std::tuple<int, int, int, int>, grasp::BatchGraph> graphs;  // (group, wpb, occ, lds)

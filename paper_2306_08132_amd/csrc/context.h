@@ -55,6 +55,12 @@ struct grasp_ctx {
   std::atomic<bool> poisoned{false};
   std::map<std::string, grasp::TileCfg> tiles;  // tuned launch shapes per problem shape
   grasp::Scheduler* sched = nullptr;  // owned; created and destroyed in sched.cpp
+  // candidate locality order of single-job launches: one arena buffer shared
+  // by every stream, each use waiting (on the device) for the previous one
+  std::mutex order_mu;
+  int* order_buf = nullptr;
+  int order_cap = 0;
+  hipEvent_t order_ev = nullptr;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 

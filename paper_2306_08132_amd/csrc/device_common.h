@@ -84,7 +84,35 @@ struct Sample {
   bool clx, cly, clz;
 };
 
-__device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
+// Byte offset of the 32-byte corner record of the cell holding r.
+__device__ __forceinline__ int sdf_cell_byte(const SdfView& S, V3 r) {
+  const float top = static_cast<float>(S.n - 1);
+  const float ux = __fmul_rn(r.x - S.lo[0], S.inv_h);
+  const float uy = __fmul_rn(r.y - S.lo[1], S.inv_h);
+  const float uz = __fmul_rn(r.z - S.lo[2], S.inv_h);
+  const float bx = fminf(fmaxf(ux, 0.0f), top);
+  const float by = fminf(fmaxf(uy, 0.0f), top);
+  const float bz = fminf(fmaxf(uz, 0.0f), top);
+  const int cm = S.n - 2;
+  const int ix = min(max(static_cast<int>(floorf(bx)), 0), cm);
+  const int iy = min(max(static_cast<int>(floorf(by)), 0), cm);
+  const int iz = min(max(static_cast<int>(floorf(bz)), 0), cm);
+  const int nc = S.n - 1;
+  return ((iz * nc + iy) * nc + ix) * 32;
+}
+
+// The cell's 8 corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
+// (32-bit buffer offsets; an offset past cells_bytes reads zeros, never faults).
+__device__ __forceinline__ void sdf_corners(const SdfView& S, int off, float4& lo4, float4& hi4) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(S.cells), static_cast<short>(0),
+                                        static_cast<int>(S.cells_bytes), 0x00020000);
+  lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+}
+
+// Trilinear value and analytic gradient at r from its cell's corners.
+__device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 lo4, float4 hi4, Sample& s) {
   const float top = static_cast<float>(S.n - 1);
   // u stays a rounded product: contracting it into the clamp residual below
   // would turn an interior point's exact zero offset into a rounding residue
@@ -101,16 +129,6 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   s.fx = bx - static_cast<float>(ix);
   s.fy = by - static_cast<float>(iy);
   s.fz = bz - static_cast<float>(iz);
-  const int nc = S.n - 1;
-  const int cell = (iz * nc + iy) * nc + ix;
-  // two 16-byte buffer loads of the cell's corners (32-bit offsets; an offset
-  // past cells_bytes would read zeros, never fault)
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(S.cells), static_cast<short>(0),
-                                        static_cast<int>(S.cells_bytes), 0x00020000);
-  const float4 lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 32, 0, 0));
-  const float4 hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 32 + 16, 0, 0));
-  // corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
   s.dx00 = lo4.y - lo4.x;
   s.dx10 = lo4.w - lo4.z;
   s.dx01 = hi4.y - hi4.x;
@@ -134,13 +152,21 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   s.phi = fmaf(s.fz, gz, c0);
   s.n = v3(s.clx ? 0.0f : gx * S.inv_h, s.cly ? 0.0f : gy * S.inv_h, s.clz ? 0.0f : gz * S.inv_h);
   s.e = v3(s.clx ? (ux - bx) * S.h : 0.0f, s.cly ? (uy - by) * S.h : 0.0f, s.clz ? (uz - bz) * S.h : 0.0f);
+  // outside the box: add the distance to the clamped point and its direction
+  // (selects rather than a branch keep the sample one basic block)
   const float ee = dot(s.e, s.e);
-  s.inv_ne = 0.0f;
-  if (ee > 0.0f) {
-    s.inv_ne = rsq(ee);
-    s.phi += ee * s.inv_ne;
-    s.n = axpy(s.inv_ne, s.e, s.n);
-  }
+  const bool outside = ee > 0.0f;
+  const float ine = rsq(ee);
+  s.inv_ne = outside ? ine : 0.0f;
+  s.phi = outside ? s.phi + ee * ine : s.phi;
+  const V3 nn = axpy(ine, s.e, s.n);
+  s.n = v3(outside ? nn.x : s.n.x, outside ? nn.y : s.n.y, outside ? nn.z : s.n.z);
+}
+
+__device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
+  float4 lo4, hi4;
+  sdf_corners(S, sdf_cell_byte(S, r), lo4, hi4);
+  sample_sdf_from(S, r, lo4, hi4, s);
 }
 
 // H v with H = d(grad phi)/dr of the sample: mixed partials of the trilinear

@@ -104,6 +104,7 @@ struct StepArgs {
   const float* dloss;   // [B] (or null: 1)
   float* poses;         // [B][7][slots][6] checkpoints (or null)
   int* nonfinite;       // [1] set when any loss is not finite (or null)
+  const int* order;     // [B] candidate taken by work item i (or null: i itself)
   // debug trace (caller order), all optional
   float* trace_p;       // [B][Nc][3]
   float* trace_poses;   // [B][7][K+1][6]
@@ -120,6 +121,13 @@ struct TileCfg {
 bool valid_tile(TileCfg c);
 
 hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream);
+
+// Candidates of at least this many get a locality order before the step.
+constexpr int kOrderMinB = 256;
+// Writes order[0..B) = a permutation of the candidates grouped by the
+// direction of the wrist from the grid's centre (one workgroup).
+hipError_t launch_order(const float* q, int n_dof, int B, const SdfView& S, int* order, hipStream_t stream);
+
 // The plain per-job form (one projection iteration): workspace floats and
 // the unfused stage kernels; *dq_out receives the workspace slot holding dq.
 size_t plain_workspace_floats(const HandView& H, int B);
@@ -143,6 +151,9 @@ struct BatchHeader {
 // agree on it).
 hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
                         int lds_floats, hipStream_t stream);
+
+// The same for every job of a batch table whose order pointer is set.
+hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int max_jobs, hipStream_t stream);
 
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);

@@ -67,14 +67,13 @@ __device__ __forceinline__ void load_rot(const float* U, Rot& o) {
   o.A = U[15]; o.B = U[16]; o.Ap = U[17]; o.Bp = U[18];
 }
 
-// Tests [M0, M1) of one pass: with all 7 in one group the tests of a contact
-// share its point and unchanged coordinates; a group per test keeps only 6
-// sums live (the K > 1 path, whose samples carry rotations).
-template <bool KONE, int M0, int M1>
+// Tests [M0, M1) of one pass at a general object pose (x, theta): the
+// samples carry the rotation R(theta). One test per group keeps 6 sums live.
+template <int M0, int M1>
 __device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min, dv = c.P.dt * c.P.v0;
+  const float rd = c.P.r_dil, wmin = c.P.w_min;
   float W[kSims][6];
   for (int m = M0; m < M1; ++m)
     for (int j = 0; j < 6; ++j) W[m][j] = 0.0f;
@@ -86,20 +85,14 @@ __device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trac
     const V3 p = contact_point(c, i, link);
 #pragma unroll
     for (int m = M0; m < M1; ++m) {
-      V3 a, r;
       Rot o;
-      if constexpr (KONE) {
-        a = test_point(p, m, dv);
-        r = a;
-      } else {
-        const float* U = c.lds + kOffU + kUStride * m;
-        load_rot(U, o);
-        a = p - v3(U[0], U[1], U[2]);
-        r = mul_t(o.R, a);
-      }
+      const float* U = c.lds + kOffU + kUStride * m;
+      load_rot(U, o);
+      const V3 a = p - v3(U[0], U[1], U[2]);
+      const V3 r = mul_t(o.R, a);
       Sample s;
       sample_sdf(S, r, s);
-      const V3 g = KONE ? s.n : mul(o.R, s.n);
+      const V3 g = mul(o.R, s.n);
       const float d = s.phi - rd;
       if (first && m == kSims - 1 && valid && d < 0.0f) lp = fmaf(0.5f * d, d, lp);
       float lam = 0.0f, w = 0.0f;
@@ -131,6 +124,61 @@ __device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trac
   if (M1 == kSims) lpen = wave_sum(lp);
 }
 
+// K = 1 forward: the object is at its predicted pose, unrotated, so the 7
+// test points of a contact are p minus the test displacements. The next
+// test's corners are requested before the current one is blended, and the
+// per-test work is branch-free so the gathers stay in flight.
+template <bool TRACE>
+__device__ void forward_kone(const Ctx& c, bool first, float& lpen, float* trace_s) {
+  const HandView& H = c.H;
+  const SdfView& S = c.S;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, dv = c.P.dt * c.P.v0, inv_Im = S.inv_Im;
+  float W[kSims][6];
+  for (int m = 0; m < kSims; ++m)
+    for (int j = 0; j < 6; ++j) W[m][j] = 0.0f;
+  float lp = 0.0f;
+  for (int ch = 0; ch < H.n_chunks; ++ch) {
+    const int i = ch * kWave + c.lane;
+    const bool valid = i < H.Nc;
+    int link;
+    const V3 p = contact_point(c, i, link);
+    float4 lo[2], hi[2];
+    sdf_corners(S, sdf_cell_byte(S, test_point(p, 0, dv)), lo[0], hi[0]);
+#pragma unroll
+    for (int m = 0; m < kSims; ++m) {
+      if (m + 1 < kSims) sdf_corners(S, sdf_cell_byte(S, test_point(p, m + 1, dv)), lo[(m + 1) & 1], hi[(m + 1) & 1]);
+      const V3 a = test_point(p, m, dv);
+      Sample s;
+      sample_sdf_from(S, a, lo[m & 1], hi[m & 1], s);
+      const V3 g = s.n;
+      const float d = s.phi - rd;
+      const bool act = valid && d < 0.0f;
+      if (m == kSims - 1) lp = (first && act) ? fmaf(0.5f * d, d, lp) : lp;
+      const V3 u = cross(a, g);
+      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
+      const float lam = (act && w > wmin) ? d * rcp(w) : 0.0f;
+      W[m][0] = fmaf(lam, g.x, W[m][0]);
+      W[m][1] = fmaf(lam, g.y, W[m][1]);
+      W[m][2] = fmaf(lam, g.z, W[m][2]);
+      W[m][3] = fmaf(lam, u.x, W[m][3]);
+      W[m][4] = fmaf(lam, u.y, W[m][4]);
+      W[m][5] = fmaf(lam, u.z, W[m][5]);
+      if constexpr (TRACE) {
+        if (valid) {
+          float* o6 = trace_s + (static_cast<size_t>(m) * H.Nc + H.perm[i]) * 6;
+          o6[0] = d; o6[1] = g.x; o6[2] = g.y; o6[3] = g.z; o6[4] = w; o6[5] = lam;
+        }
+      }
+    }
+  }
+  for (int m = 0; m < kSims; ++m)
+    for (int j = 0; j < 6; ++j) {
+      const float t = wave_sum(W[m][j]);
+      if (c.lane == 0) c.lds[kOffWS + 6 * m + j] = t;
+    }
+  lpen = wave_sum(lp);
+}
+
 // One forward projection iteration over all contacts: the 7 x 6 correction
 // sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
 // on the rest test of the first iteration, the penetration energy.
@@ -138,15 +186,16 @@ template <bool KONE>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
   if constexpr (KONE) {
-    forward_tests<true, 0, kSims>(c, first, lpen, trace_s, K, k);
+    if (trace_s) forward_kone<true>(c, first, lpen, trace_s);
+    else forward_kone<false>(c, first, lpen, nullptr);
   } else {
-    forward_tests<false, 0, 1>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 1, 2>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 2, 3>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 3, 4>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 4, 5>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 5, 6>(c, first, lpen, trace_s, K, k);
-    forward_tests<false, 6, 7>(c, first, lpen, trace_s, K, k);
+    forward_tests<0, 1>(c, first, lpen, trace_s, K, k);
+    forward_tests<1, 2>(c, first, lpen, trace_s, K, k);
+    forward_tests<2, 3>(c, first, lpen, trace_s, K, k);
+    forward_tests<3, 4>(c, first, lpen, trace_s, K, k);
+    forward_tests<4, 5>(c, first, lpen, trace_s, K, k);
+    forward_tests<5, 6>(c, first, lpen, trace_s, K, k);
+    forward_tests<6, 7>(c, first, lpen, trace_s, K, k);
   }
   wave_lds_sync();
 }
@@ -161,15 +210,93 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
   }
 }
 
+// K = 1 backward (the adjoint of forward_kone). Corners are requested one
+// test ahead; the full adjoint (through g, u and the trilinear Hessian) runs
+// under a lane mask for penetrating samples only.
+__device__ void backward_kone(const Ctx& c, float pen_seed) {
+  const HandView& H = c.H;
+  const SdfView& S = c.S;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, dv = c.P.dt * c.P.v0;
+  const float inv_Im = S.inv_Im;
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  int cur = -1;
+  for (int ch = 0; ch < H.n_chunks; ++ch) {
+    const int i = ch * kWave + c.lane;
+    const bool valid = i < H.Nc;
+    int link;
+    const V3 p = contact_point(c, i, link);
+    V3 pbar = v3(0.0f, 0.0f, 0.0f);
+    float4 lo[2], hi[2];
+    sdf_corners(S, sdf_cell_byte(S, test_point(p, 0, dv)), lo[0], hi[0]);
+#pragma unroll
+    for (int m = 0; m < kSims; ++m) {
+      if (m + 1 < kSims) sdf_corners(S, sdf_cell_byte(S, test_point(p, m + 1, dv)), lo[(m + 1) & 1], hi[(m + 1) & 1]);
+      const float* U = c.lds + kOffU + kUStride * m;
+      const V3 a = test_point(p, m, dv);
+      Sample s;
+      sample_sdf_from(S, a, lo[m & 1], hi[m & 1], s);
+      const V3 g = s.n;
+      const float d = s.phi - rd;
+      const V3 u = cross(a, g);
+      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
+      const V3 WlB = v3(U[19], U[20], U[21]);
+      const V3 WaB = v3(U[22], U[23], U[24]);
+      const float lb = fmaf(WlB.x, g.x, fmaf(WlB.y, g.y, fmaf(WlB.z, g.z, dot(WaB, u))));
+      const bool okw = valid && w > wmin;
+      const bool pen = okw && d < 0.0f;
+      const float iw = rcp(w);
+      // lambda = d / w where d < 0 (full derivative); dC/dd = -alpha elsewhere
+      float dbar = okw ? (pen ? lb * iw : alpha * lb * iw) : 0.0f;
+      if (m == kSims - 1) dbar = (valid && d < 0.0f) ? fmaf(pen_seed, d, dbar) : dbar;
+      V3 ab = v3(0.0f, 0.0f, 0.0f);
+      V3 rbar = dbar * s.n;
+      if (pen) {
+        const float lam = d * iw;
+        const float wbar2 = -2.0f * lb * lam * iw;
+        const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
+        V3 gbar = axpy(lam, WlB, wbar2 * g);
+        ab = cross(g, ubar);
+        gbar = gbar + cross(ubar, a);
+        rbar = rbar + hess_mul(S, s, gbar);
+      }
+      pbar = pbar + (ab + rbar);
+    }
+    // scatter p_bar into link wrenches (force, torque about the world origin)
+    const V3 tau = cross(p, pbar);
+    const float v6[6] = {pbar.x, pbar.y, pbar.z, tau.x, tau.y, tau.z};
+    const int lk = H.chunk_lk[ch];
+    const int lf = lk & 0xffff, ll = lk >> 16;
+    if (lf == ll) {
+      if (lf != cur) {
+        if (cur >= 0) flush_link(c, cur, acc);
+        for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
+        cur = lf;
+      }
+      for (int j = 0; j < 6; ++j) acc[j] += v6[j];
+    } else {
+      if (cur >= 0) flush_link(c, cur, acc);
+      for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
+      cur = -1;
+      for (int l = lf; l <= ll; ++l) {
+        float mv[6];
+        for (int j = 0; j < 6; ++j) mv[j] = (link == l && valid) ? v6[j] : 0.0f;
+        flush_link(c, l, mv);
+      }
+    }
+  }
+  if (cur >= 0) flush_link(c, cur, acc);
+  wave_lds_sync();
+}
+
 // One backward iteration over all contacts (the adjoint of forward_pass at
 // iteration k). The per-test seeds Wl_bar, Wa_bar (adjoints of the summed
 // corrections) are in LDS. Adds p_bar x p and p_bar to the link wrench table
 // and, when pose_adj, returns the pose adjoint sums (-sum a_bar, sum theta_bar).
-template <bool KONE, int M0, int M1>
+template <int M0, int M1>
 __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, dv = c.P.dt * c.P.v0;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha;
   const float inv_Im = S.inv_Im;
   float XB[kSims][6];
   if (pose_adj)
@@ -186,19 +313,13 @@ __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool po
 #pragma unroll
     for (int m = M0; m < M1; ++m) {
       const float* U = c.lds + kOffU + kUStride * m;
-      V3 a, r;
       Rot o;
-      if constexpr (KONE) {
-        a = test_point(p, m, dv);
-        r = a;
-      } else {
-        load_rot(U, o);
-        a = p - v3(U[0], U[1], U[2]);
-        r = mul_t(o.R, a);
-      }
+      load_rot(U, o);
+      const V3 a = p - v3(U[0], U[1], U[2]);
+      const V3 r = mul_t(o.R, a);
       Sample s;
       sample_sdf(S, r, s);
-      const V3 g = KONE ? s.n : mul(o.R, s.n);
+      const V3 g = mul(o.R, s.n);
       const float d = s.phi - rd;
       const V3 u = cross(a, g);
       const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
@@ -228,18 +349,10 @@ __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool po
       if (first && m == kSims - 1 && valid && d < 0.0f) dbar = fmaf(pen_seed, d, dbar);
       // second derivative only for penetrating samples
       V3 rbar;
-      if constexpr (KONE) {
-        rbar = dbar * s.n;
-        if (pen) rbar = rbar + hess_mul(S, s, gbar);
-        abar = abar + rbar;
-      } else {
+      {
         const V3 nbar = mul_t(o.R, gbar);
         rbar = dbar * s.n;
-        if (pen) {
-          Sample s2;
-          sample_sdf(S, r, s2);
-          rbar = rbar + hess_mul(S, s2, nbar);
-        }
+        if (pen) rbar = rbar + hess_mul(S, s, nbar);
         abar = abar + mul(o.R, rbar);
         if (pose_adj && valid) {
           V3 thb = v3(0.0f, 0.0f, 0.0f);
@@ -292,15 +405,15 @@ __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool po
 template <bool KONE>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   if constexpr (KONE) {
-    backward_tests<true, 0, kSims>(c, first, pen_seed, pose_adj);
+    backward_kone(c, pen_seed);
   } else {
-    backward_tests<false, 0, 1>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 1, 2>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 2, 3>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 3, 4>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 4, 5>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 5, 6>(c, first, pen_seed, pose_adj);
-    backward_tests<false, 6, 7>(c, first, pen_seed, pose_adj);
+    backward_tests<0, 1>(c, first, pen_seed, pose_adj);
+    backward_tests<1, 2>(c, first, pen_seed, pose_adj);
+    backward_tests<2, 3>(c, first, pen_seed, pose_adj);
+    backward_tests<3, 4>(c, first, pen_seed, pose_adj);
+    backward_tests<4, 5>(c, first, pen_seed, pose_adj);
+    backward_tests<5, 6>(c, first, pen_seed, pose_adj);
+    backward_tests<6, 7>(c, first, pen_seed, pose_adj);
   }
 }
 
@@ -516,6 +629,94 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block i to XCD i mod
+// 8). This maps them so that each XCD works on one contiguous range of work
+// items, and with a locality order on candidates whose contacts touch
+// neighbouring grid cells: each XCD's L2 then holds a compact part of the
+// grid. A bijection on [0, nblk) for the first nblk blocks (those holding
+// work); blocks past nblk keep their index. Results never depend on it.
+__device__ __forceinline__ int xcd_block(int nblk) {
+  const int blk = static_cast<int>(blockIdx.x);
+  if (blk >= nblk) return blk;
+  const int per = nblk >> 3, rem = nblk & 7, x = blk & 7;
+  return x * per + min(x, rem) + (blk >> 3);
+}
+
+// Locality order: candidates bucketed by the direction of the wrist from
+// the grid's centre (a 4-bit-per-axis Morton code of the unit direction),
+// by a counting sort in one workgroup. Order within a bucket is whatever
+// the LDS atomics produce; no result depends on it.
+constexpr int kOrderAxisBits = 4;
+constexpr int kOrderBins = 1 << (3 * kOrderAxisBits);
+constexpr int kOrderThreads = 1024;
+static_assert(kOrderBins % kOrderThreads == 0, "bins split evenly over the threads");
+
+__device__ __forceinline__ int order_key(const float* qb, V3 c) {
+  const float x = qb[0] - c.x, y = qb[1] - c.y, z = qb[2] - c.z;
+  const float n2 = fmaf(x, x, fmaf(y, y, z * z));
+  const float s = n2 > 0.0f ? rsq(n2) : 0.0f;
+  const float half = 0.5f * static_cast<float>(1 << kOrderAxisBits), top = static_cast<float>((1 << kOrderAxisBits) - 1);
+  // fmaxf maps NaN to 0, so every key is a valid bucket
+  const int ix = static_cast<int>(fminf(fmaxf(fmaf(x * s, half, half), 0.0f), top));
+  const int iy = static_cast<int>(fminf(fmaxf(fmaf(y * s, half, half), 0.0f), top));
+  const int iz = static_cast<int>(fminf(fmaxf(fmaf(z * s, half, half), 0.0f), top));
+  int key = 0;
+  for (int bit = 0; bit < kOrderAxisBits; ++bit)
+    key |= (((ix >> bit) & 1) << (3 * bit)) | (((iy >> bit) & 1) << (3 * bit + 1)) | (((iz >> bit) & 1) << (3 * bit + 2));
+  return key;
+}
+
+__device__ __forceinline__ V3 grid_centre(const SdfView& S) {
+  const float hw = 0.5f * static_cast<float>(S.n - 1) * S.h;
+  return v3(S.lo[0] + hw, S.lo[1] + hw, S.lo[2] + hw);
+}
+
+// One workgroup of kOrderThreads writes out[0..B) (a permutation of 0..B-1).
+__device__ void order_block(const float* q, int nd, int B, V3 centre, int* out) {
+  __shared__ int cnt[kOrderBins];
+  __shared__ int part[kOrderThreads];
+  const int tid = static_cast<int>(threadIdx.x);
+  constexpr int kPer = kOrderBins / kOrderThreads;
+  for (int i = tid; i < kOrderBins; i += kOrderThreads) cnt[i] = 0;
+  __syncthreads();
+  for (int b = tid; b < B; b += kOrderThreads) atomicAdd(&cnt[order_key(q + static_cast<size_t>(b) * nd, centre)], 1);
+  __syncthreads();
+  // exclusive prefix sum over the bins: per-thread runs, then a scan of the run totals
+  int run = 0;
+  for (int k = 0; k < kPer; ++k) run += cnt[tid * kPer + k];
+  part[tid] = run;
+  __syncthreads();
+  for (int off = 1; off < kOrderThreads; off <<= 1) {
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int base = part[tid] - run;
+  for (int k = 0; k < kPer; ++k) {
+    const int c = cnt[tid * kPer + k];
+    cnt[tid * kPer + k] = base;
+    base += c;
+  }
+  __syncthreads();
+  for (int b = tid; b < B; b += kOrderThreads) {
+    const int pos = atomicAdd(&cnt[order_key(q + static_cast<size_t>(b) * nd, centre)], 1);
+    out[pos] = b;
+  }
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_order(const float* q, int nd, int B, SdfView S, int* out) {
+  order_block(q, nd, B, grid_centre(S), out);
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_order_batch(const BatchHeader* hdr, const BatchJob* jobs) {
+  const int j = static_cast<int>(blockIdx.x);
+  if (j >= hdr->n_jobs) return;
+  const StepArgs& A = jobs[j].args;
+  if (!A.order) return;
+  order_block(A.q, A.hand.n_dof, A.B, grid_centre(A.sdf), const_cast<int*>(A.order));
+}
+
 // OCC is the minimum number of waves per SIMD the register allocation must
 // allow (1 = the compiler's choice); it is the occupancy knob of the tuner.
 template <bool KONE, int OCC>
@@ -524,8 +725,9 @@ k_step(StepArgs A, int kind, int adam) {
   extern __shared__ float smem[];
   const int wpb = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
-  const int b = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
-  if (b >= A.B) return;
+  const int item = __builtin_amdgcn_readfirstlane(xcd_block(static_cast<int>(gridDim.x)) * wpb + w);
+  if (item >= A.B) return;
+  const int b = A.order ? __builtin_amdgcn_readfirstlane(A.order[item]) : item;
   float* lds = smem + static_cast<size_t>(w) * wave_lds_floats(A.prm.K, A.prm.ckpt);
   candidate_step<KONE>(A, b, kind, adam != 0, lds);
 }
@@ -545,9 +747,11 @@ k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, 
   const int wpb = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
   // wave-uniform by construction; readfirstlane lets the compiler see it
-  const int item = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
+  // the grid is sized for the batch capacity: spread only the blocks that hold items
+  const int total = hdr->total;
+  const int item = __builtin_amdgcn_readfirstlane(xcd_block((total + wpb - 1) / wpb) * wpb + w);
   const int n_jobs = hdr->n_jobs;
-  if (item >= hdr->total) return;
+  if (item >= total) return;
   int lo = 0, hi = n_jobs - 1;  // last job with begin <= item
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -557,7 +761,9 @@ k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, 
   lo = __builtin_amdgcn_readfirstlane(lo);
   float* lds = smem + static_cast<size_t>(w) * lds_per_wave;
   const StepArgs A = jobs[lo].args;  // one uniform copy, like a kernel argument
-  candidate_step<KONE>(A, item - jobs[lo].begin, STEP_FUSED, true, lds);
+  const int local = item - jobs[lo].begin;
+  const int b = A.order ? __builtin_amdgcn_readfirstlane(A.order[local]) : local;
+  candidate_step<KONE>(A, b, STEP_FUSED, true, lds);
 }
 
 __global__ void k_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c) {
@@ -638,6 +844,18 @@ hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg,
     launch_occ<true>(a, static_cast<int>(kind), adam, cfg, lds, stream);
   else
     launch_occ<false>(a, static_cast<int>(kind), adam, cfg, lds, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const float* q, int n_dof, int B, const SdfView& S, int* order, hipStream_t stream) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderThreads), 0, stream, q, n_dof, B, S, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int max_jobs, hipStream_t stream) {
+  if (max_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order_batch, dim3(max_jobs), dim3(kOrderThreads), 0, stream, hdr, jobs);
   return hipGetLastError();
 }
 

@@ -25,9 +25,11 @@ def ctx(gpu):
 
 @pytest.fixture(scope="module")
 def objects(ctx):
-    """Three jobs' geometry: different hands, grid resolutions and sizes."""
+    """Four jobs' geometry: different hands, grid resolutions and sizes (the
+    last one large enough to run in the candidate locality order)."""
     out = []
-    for k, (F, J, nc, N, B) in enumerate([(3, 3, 300, 24, 7), (4, 4, 700, 40, 13), (5, 4, 1000, 33, 5)]):
+    for k, (F, J, nc, N, B) in enumerate([(3, 3, 300, 24, 7), (4, 4, 700, 40, 13), (5, 4, 1000, 33, 5),
+                                          (3, 3, 300, 24, 300)]):
         hand = S.make_hand(F, J, nc, seed=10 + k)
         grid = S.make_grid(S.make_object("mixed", seed=20 + k, n_prims=3), N)
         q = S.make_candidates(hand, B, seed=30 + k, shell_radius=grid.bound_radius + 0.06)
@@ -83,6 +85,24 @@ def test_batch_equals_single_job_steps(ctx, objects, use_graph):
         assert np.array_equal(j.m.cpu().numpy(), m) and np.array_equal(j.v.cpu().numpy(), v)
         assert np.array_equal(j.loss.cpu().numpy(), loss)
         assert j.t == 3
+    b.close()
+
+
+def test_batch_with_ordered_job(ctx, objects):
+    """A job of 300 candidates runs in its locality order inside the batch
+    and in single-job launches; both equal bit for bit."""
+    from paper_2306_08132_amd.api import Batch
+    stream = torch.cuda.Stream()
+    b = Batch(ctx, capacity=512, max_jobs=4, use_graph=True)
+    jobs = make_jobs(objects, [3, 1])
+    with torch.cuda.stream(stream):
+        for s in range(3):
+            b.step(jobs, stream=stream)
+    stream.synchronize()
+    for j, i in zip(jobs, [3, 1]):
+        q, m, v, loss = run_single(ctx, objects, i, 3)
+        say("ordered job", i, "max |dq|", float(np.abs(j.q.cpu().numpy() - q).max()))
+        assert np.array_equal(j.q.cpu().numpy(), q) and np.array_equal(j.loss.cpu().numpy(), loss)
     b.close()
 
 

@@ -359,6 +359,31 @@ def test_every_tile_bit_identical(ctx, tiny):
             assert all(np.array_equal(x, y) for x, y in zip(r[1:], rk[0][1:]))
 
 
+def test_locality_order_changes_nothing(ctx, tiny):
+    """Launches of at least 256 candidates run them in a locality order (by
+    wrist direction, XCD-contiguous); the bits equal those of unordered
+    launches of the same candidates in slices of 100."""
+    hand, grid, _ = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    B = 600
+    q = S.make_candidates(hand, B, seed=77, shell_radius=grid.bound_radius + 0.06)
+    for K in (1, 2):
+        sp, _ = prm_pair(r_dil=0.004, K=K)
+        outs = []
+        for sl in ((0, B),) + tuple((i, i + 100) for i in range(0, B, 100)):
+            n = sl[1] - sl[0]
+            qd = dev(q[sl[0]:sl[1]])
+            m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+            loss = torch.empty(n, device=DEV)
+            dq = torch.empty_like(qd)
+            ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+            outs.append((loss.cpu().numpy(), dq.cpu().numpy(), qd.cpu().numpy()))
+        whole = outs[0]
+        parts = [np.concatenate([o[k] for o in outs[1:]]) for k in range(3)]
+        say("K", K, "ordered vs sliced max |diff| loss", float(np.nanmax(np.abs(whole[0] - parts[0]))))
+        assert all(np.array_equal(a, b) for a, b in zip(whole, parts))
+
+
 def test_plain_form_parity(ctx, tiny):
     """The unfused per-job form against the oracle, and against the fused
     step (same formulas, different summation order)."""
