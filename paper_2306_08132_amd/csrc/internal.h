@@ -65,7 +65,8 @@ struct AdamConsts {
 };
 
 // Per-wave LDS layout of the step kernel (floats): link transforms, joint
-// frames, link wrench adjoints, per-test constants, then pose checkpoints
+// frames, link wrench adjoints, per-test constants, a chunk's contact
+// points, then pose checkpoints
 // (K/ckpt + 1 slots) and a replay buffer (ckpt slots), each slot 7 x 6.
 constexpr int kOffT = 0;                       // [kMaxLinks][12]
 constexpr int kOffJ = kOffT + kMaxLinks * 12;  // [kMaxLinks][6] joint world origin, world axis
@@ -73,7 +74,8 @@ constexpr int kOffW = kOffJ + kMaxLinks * 6;   // [kMaxLinks][6] link force, tor
 constexpr int kUStride = 32;
 constexpr int kOffU = kOffW + kMaxLinks * 6;   // [7][32] per-test constants
 constexpr int kOffWS = kOffU + kSims * kUStride;   // [7][6] summed corrections of the last pass (+6 pad)
-constexpr int kOffPose = kOffWS + 48;
+constexpr int kOffP = kOffWS + 48;             // [64][4] world contact points of a chunk (x, y, z, link)
+constexpr int kOffPose = kOffP + kWave * 4;
 
 __host__ __device__ inline int pose_slots(int K, int ckpt) { return K / ckpt + 1; }
 __host__ __device__ inline size_t wave_lds_floats(int K, int ckpt) {

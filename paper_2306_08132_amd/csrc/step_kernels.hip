@@ -4,11 +4,14 @@
 // the hand-written adjoint with the leaky contact gradient, and Adam.
 //
 // Execution model: one 64-lane wavefront owns one candidate grasp from start
-// to end. Lanes stride over the link-sorted contacts in 64-contact chunks;
-// every per-candidate reduction (the 7 x 6 correction sums, link wrenches,
-// losses) is a wavefront reduction in a fixed order, so a candidate's result
-// is bit-identical whatever else runs on the GPU. No workgroup barrier is
-// used: waves never wait on each other.
+// to end and walks the link-sorted contacts in 64-contact chunks. With one
+// projection iteration a lane takes one (contact, test) pair, eight contacts
+// per instruction, so the seven nearby gathers of a contact share cache
+// lines; with several iterations a lane takes one contact and the tests run
+// one after another. Every per-candidate reduction (the 7 x 6 correction
+// sums, link wrenches, losses) is a wavefront reduction in a fixed order, so
+// a candidate's result is bit-identical whatever else runs on the GPU. No
+// workgroup barrier is used: waves never wait on each other.
 #include "device_common.h"
 
 namespace grasp {
@@ -124,58 +127,102 @@ __device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trac
   if (M1 == kSims) lpen = wave_sum(lp);
 }
 
-// K = 1 forward: the object is at its predicted pose, unrotated, so the 7
-// test points of a contact are p minus the test displacements. The next
-// test's corners are requested before the current one is blended, and the
-// per-test work is branch-free so the gathers stay in flight.
+// ---------------------------------------------------------------------------
+// K = 1 (one projection iteration at the predicted, unrotated pose). Lanes
+// take (contact, test) pairs: lane = 8 * contact + test, test 7 idle, eight
+// contacts per group and eight groups per 64-contact chunk. The seven test
+// points of a contact lie within about a cell of each other, so one gather
+// instruction touches about half as many cache lines as with one contact
+// per lane, and each lane keeps the sums of its own test only.
+// ---------------------------------------------------------------------------
+struct LaneTest {
+  int m;        // test of this lane (7: idle)
+  V3 off;       // test displacement: test_point(p, m, dv) = p + off
+};
+
+__device__ __forceinline__ LaneTest lane_test(int lane, float dv) {
+  LaneTest t;
+  t.m = lane & 7;
+  const float sx = t.m == 0 ? -dv : (t.m == 1 ? dv : 0.0f);
+  const float sy = t.m == 2 ? -dv : (t.m == 3 ? dv : 0.0f);
+  const float sz = t.m == 4 ? -dv : (t.m == 5 ? dv : 0.0f);
+  t.off = v3(sx, sy, sz);
+  return t;
+}
+
+// World points of contacts [64 ch, 64 ch + 64) into the chunk area of LDS;
+// link -1 marks padding past the last contact.
+__device__ __forceinline__ void stage_chunk(const Ctx& c, int ch) {
+  const int i = ch * kWave + c.lane;
+  int link;
+  const V3 p = contact_point(c, i, link);
+  float4* P = reinterpret_cast<float4*>(c.lds + kOffP);
+  P[c.lane] = make_float4(p.x, p.y, p.z, __int_as_float(i < c.H.Nc ? link : -1));
+  wave_lds_sync();
+}
+
+// Sum over the eight lanes holding the same test (lane bits 3..5).
+__device__ __forceinline__ float test_sum(float v) {
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 template <bool TRACE>
-__device__ void forward_kone(const Ctx& c, bool first, float& lpen, float* trace_s) {
+__device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min, dv = c.P.dt * c.P.v0, inv_Im = S.inv_Im;
-  float W[kSims][6];
-  for (int m = 0; m < kSims; ++m)
-    for (int j = 0; j < 6; ++j) W[m][j] = 0.0f;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
+  const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
+  const int sub = c.lane >> 3;
+  const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  float W[6] = {0, 0, 0, 0, 0, 0};
   float lp = 0.0f;
   for (int ch = 0; ch < H.n_chunks; ++ch) {
-    const int i = ch * kWave + c.lane;
-    const bool valid = i < H.Nc;
-    int link;
-    const V3 p = contact_point(c, i, link);
+    stage_chunk(c, ch);
     float4 lo[2], hi[2];
-    sdf_corners(S, sdf_cell_byte(S, test_point(p, 0, dv)), lo[0], hi[0]);
+    {
+      const float4 P4 = P[sub];
+      sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
+    }
 #pragma unroll
-    for (int m = 0; m < kSims; ++m) {
-      if (m + 1 < kSims) sdf_corners(S, sdf_cell_byte(S, test_point(p, m + 1, dv)), lo[(m + 1) & 1], hi[(m + 1) & 1]);
-      const V3 a = test_point(p, m, dv);
+    for (int g = 0; g < 8; ++g) {
+      if (g + 1 < 8) {
+        const float4 Pn = P[8 * (g + 1) + sub];
+        sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
+      }
+      const float4 P4 = P[8 * g + sub];
+      const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
+      const V3 a = v3(P4.x, P4.y, P4.z) + lt.off;
       Sample s;
-      sample_sdf_from(S, a, lo[m & 1], hi[m & 1], s);
-      const V3 g = s.n;
+      sample_sdf_from(S, a, lo[g & 1], hi[g & 1], s);
+      const V3 gn = s.n;
       const float d = s.phi - rd;
       const bool act = valid && d < 0.0f;
-      if (m == kSims - 1) lp = (first && act) ? fmaf(0.5f * d, d, lp) : lp;
-      const V3 u = cross(a, g);
-      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
+      lp = (act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      const V3 u = cross(a, gn);
+      const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
       const float lam = (act && w > wmin) ? d * rcp(w) : 0.0f;
-      W[m][0] = fmaf(lam, g.x, W[m][0]);
-      W[m][1] = fmaf(lam, g.y, W[m][1]);
-      W[m][2] = fmaf(lam, g.z, W[m][2]);
-      W[m][3] = fmaf(lam, u.x, W[m][3]);
-      W[m][4] = fmaf(lam, u.y, W[m][4]);
-      W[m][5] = fmaf(lam, u.z, W[m][5]);
+      W[0] = fmaf(lam, gn.x, W[0]);
+      W[1] = fmaf(lam, gn.y, W[1]);
+      W[2] = fmaf(lam, gn.z, W[2]);
+      W[3] = fmaf(lam, u.x, W[3]);
+      W[4] = fmaf(lam, u.y, W[4]);
+      W[5] = fmaf(lam, u.z, W[5]);
       if constexpr (TRACE) {
         if (valid) {
-          float* o6 = trace_s + (static_cast<size_t>(m) * H.Nc + H.perm[i]) * 6;
-          o6[0] = d; o6[1] = g.x; o6[2] = g.y; o6[3] = g.z; o6[4] = w; o6[5] = lam;
+          const int i = ch * kWave + 8 * g + sub;
+          float* o6 = trace_s + (static_cast<size_t>(lt.m) * H.Nc + H.perm[i]) * 6;
+          o6[0] = d; o6[1] = gn.x; o6[2] = gn.y; o6[3] = gn.z; o6[4] = w; o6[5] = lam;
         }
       }
     }
   }
-  for (int m = 0; m < kSims; ++m)
-    for (int j = 0; j < 6; ++j) {
-      const float t = wave_sum(W[m][j]);
-      if (c.lane == 0) c.lds[kOffWS + 6 * m + j] = t;
-    }
+  for (int j = 0; j < 6; ++j) {
+    const float t = test_sum(W[j]);
+    if (c.lane < kSims) c.lds[kOffWS + 6 * c.lane + j] = t;
+  }
   lpen = wave_sum(lp);
 }
 
@@ -186,8 +233,8 @@ template <bool KONE>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
   if constexpr (KONE) {
-    if (trace_s) forward_kone<true>(c, first, lpen, trace_s);
-    else forward_kone<false>(c, first, lpen, nullptr);
+    if (trace_s) forward_k1<true>(c, lpen, trace_s);
+    else forward_k1<false>(c, lpen, nullptr);
   } else {
     forward_tests<0, 1>(c, first, lpen, trace_s, K, k);
     forward_tests<1, 2>(c, first, lpen, trace_s, K, k);
@@ -210,77 +257,92 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
   }
 }
 
-// K = 1 backward (the adjoint of forward_kone). Corners are requested one
-// test ahead; the full adjoint (through g, u and the trilinear Hessian) runs
-// under a lane mask for penetrating samples only.
-__device__ void backward_kone(const Ctx& c, float pen_seed) {
+// K = 1 backward (the adjoint of forward_k1), same lane layout. Each lane
+// adds its sample's p_bar and p x p_bar to per-lane running sums of the
+// current link; sums are flushed (wave reductions) where the link changes.
+__device__ void backward_k1(const Ctx& c, float pen_seed) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, dv = c.P.dt * c.P.v0;
-  const float inv_Im = S.inv_Im;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, inv_Im = S.inv_Im;
+  const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
+  const int sub = c.lane >> 3;
+  const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  // seeds of this lane's test (adjoints of its summed corrections)
+  const float* U = c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
+  const V3 WlB = v3(U[19], U[20], U[21]);
+  const V3 WaB = v3(U[22], U[23], U[24]);
+  const float pseed = lt.m == kSims - 1 ? pen_seed : 0.0f;
   float acc[6] = {0, 0, 0, 0, 0, 0};
   int cur = -1;
   for (int ch = 0; ch < H.n_chunks; ++ch) {
-    const int i = ch * kWave + c.lane;
-    const bool valid = i < H.Nc;
-    int link;
-    const V3 p = contact_point(c, i, link);
-    V3 pbar = v3(0.0f, 0.0f, 0.0f);
+    stage_chunk(c, ch);
+    const int lk = H.chunk_lk[ch];
+    const int chunk_last = lk >> 16;
     float4 lo[2], hi[2];
-    sdf_corners(S, sdf_cell_byte(S, test_point(p, 0, dv)), lo[0], hi[0]);
+    {
+      const float4 P4 = P[sub];
+      sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
+    }
 #pragma unroll
-    for (int m = 0; m < kSims; ++m) {
-      if (m + 1 < kSims) sdf_corners(S, sdf_cell_byte(S, test_point(p, m + 1, dv)), lo[(m + 1) & 1], hi[(m + 1) & 1]);
-      const float* U = c.lds + kOffU + kUStride * m;
-      const V3 a = test_point(p, m, dv);
+    for (int g = 0; g < 8; ++g) {
+      if (g + 1 < 8) {
+        const float4 Pn = P[8 * (g + 1) + sub];
+        sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
+      }
+      const float4 P4 = P[8 * g + sub];
+      const int link = __float_as_int(P4.w);
+      const bool valid = link >= 0 && lt.m < kSims;
+      const V3 p = v3(P4.x, P4.y, P4.z);
+      const V3 a = p + lt.off;
       Sample s;
-      sample_sdf_from(S, a, lo[m & 1], hi[m & 1], s);
-      const V3 g = s.n;
+      sample_sdf_from(S, a, lo[g & 1], hi[g & 1], s);
+      const V3 gn = s.n;
       const float d = s.phi - rd;
-      const V3 u = cross(a, g);
-      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
-      const V3 WlB = v3(U[19], U[20], U[21]);
-      const V3 WaB = v3(U[22], U[23], U[24]);
-      const float lb = fmaf(WlB.x, g.x, fmaf(WlB.y, g.y, fmaf(WlB.z, g.z, dot(WaB, u))));
+      const V3 u = cross(a, gn);
+      const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
+      const float lb = fmaf(WlB.x, gn.x, fmaf(WlB.y, gn.y, fmaf(WlB.z, gn.z, dot(WaB, u))));
       const bool okw = valid && w > wmin;
       const bool pen = okw && d < 0.0f;
       const float iw = rcp(w);
       // lambda = d / w where d < 0 (full derivative); dC/dd = -alpha elsewhere
       float dbar = okw ? (pen ? lb * iw : alpha * lb * iw) : 0.0f;
-      if (m == kSims - 1) dbar = (valid && d < 0.0f) ? fmaf(pen_seed, d, dbar) : dbar;
+      dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
       V3 ab = v3(0.0f, 0.0f, 0.0f);
       V3 rbar = dbar * s.n;
       if (pen) {
         const float lam = d * iw;
         const float wbar2 = -2.0f * lb * lam * iw;
         const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
-        V3 gbar = axpy(lam, WlB, wbar2 * g);
-        ab = cross(g, ubar);
+        V3 gbar = axpy(lam, WlB, wbar2 * gn);
+        ab = cross(gn, ubar);
         gbar = gbar + cross(ubar, a);
         rbar = rbar + hess_mul(S, s, gbar);
       }
-      pbar = pbar + (ab + rbar);
-    }
-    // scatter p_bar into link wrenches (force, torque about the world origin)
-    const V3 tau = cross(p, pbar);
-    const float v6[6] = {pbar.x, pbar.y, pbar.z, tau.x, tau.y, tau.z};
-    const int lk = H.chunk_lk[ch];
-    const int lf = lk & 0xffff, ll = lk >> 16;
-    if (lf == ll) {
-      if (lf != cur) {
+      const V3 pb = ab + rbar;
+      const V3 tau = cross(p, pb);
+      const float v6[6] = {valid ? pb.x : 0.0f, valid ? pb.y : 0.0f, valid ? pb.z : 0.0f,
+                           valid ? tau.x : 0.0f, valid ? tau.y : 0.0f, valid ? tau.z : 0.0f};
+      // links of the group's first and last contacts (wave-uniform)
+      const int lf = __builtin_amdgcn_readfirstlane(__float_as_int(P[8 * g].w));
+      const int lz = __builtin_amdgcn_readfirstlane(__float_as_int(P[8 * g + 7].w));
+      if (lf < 0) continue;  // padding only
+      const int ll = lz >= 0 ? lz : chunk_last;
+      if (lf == ll) {
+        if (lf != cur) {
+          if (cur >= 0) flush_link(c, cur, acc);
+          for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
+          cur = lf;
+        }
+        for (int j = 0; j < 6; ++j) acc[j] += v6[j];
+      } else {
         if (cur >= 0) flush_link(c, cur, acc);
         for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
-        cur = lf;
-      }
-      for (int j = 0; j < 6; ++j) acc[j] += v6[j];
-    } else {
-      if (cur >= 0) flush_link(c, cur, acc);
-      for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
-      cur = -1;
-      for (int l = lf; l <= ll; ++l) {
-        float mv[6];
-        for (int j = 0; j < 6; ++j) mv[j] = (link == l && valid) ? v6[j] : 0.0f;
-        flush_link(c, l, mv);
+        cur = -1;
+        for (int l = lf; l <= ll; ++l) {
+          float mv[6];
+          for (int j = 0; j < 6; ++j) mv[j] = link == l ? v6[j] : 0.0f;
+          flush_link(c, l, mv);
+        }
       }
     }
   }
@@ -405,7 +467,7 @@ __device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool po
 template <bool KONE>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   if constexpr (KONE) {
-    backward_kone(c, pen_seed);
+    backward_k1(c, pen_seed);
   } else {
     backward_tests<0, 1>(c, first, pen_seed, pose_adj);
     backward_tests<1, 2>(c, first, pen_seed, pose_adj);
