@@ -84,21 +84,27 @@ struct Sample {
   bool clx, cly, clz;
 };
 
+// Grid coordinate of r along one axis: u = (r - lo) / h, its clamp b to
+// [0, N-1] and the cell's lower vertex index, as a float, min(floor(b), N-2).
+// u stays a rounded product: contracting it into the clamp residual of the
+// outside term would turn an interior point's exact zero into a residue.
+struct Axis {
+  float u, b, i;
+};
+
+__device__ __forceinline__ Axis grid_axis(float r, float lo, const SdfView& S) {
+  Axis a;
+  a.u = __fmul_rn(r - lo, S.inv_h);
+  a.b = __builtin_amdgcn_fmed3f(a.u, 0.0f, static_cast<float>(S.n - 1));
+  a.i = fminf(floorf(a.b), static_cast<float>(S.n - 2));
+  return a;
+}
+
 // Byte offset of the 32-byte corner record of the cell holding r.
 __device__ __forceinline__ int sdf_cell_byte(const SdfView& S, V3 r) {
-  const float top = static_cast<float>(S.n - 1);
-  const float ux = __fmul_rn(r.x - S.lo[0], S.inv_h);
-  const float uy = __fmul_rn(r.y - S.lo[1], S.inv_h);
-  const float uz = __fmul_rn(r.z - S.lo[2], S.inv_h);
-  const float bx = fminf(fmaxf(ux, 0.0f), top);
-  const float by = fminf(fmaxf(uy, 0.0f), top);
-  const float bz = fminf(fmaxf(uz, 0.0f), top);
-  const int cm = S.n - 2;
-  const int ix = min(max(static_cast<int>(floorf(bx)), 0), cm);
-  const int iy = min(max(static_cast<int>(floorf(by)), 0), cm);
-  const int iz = min(max(static_cast<int>(floorf(bz)), 0), cm);
+  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
   const int nc = S.n - 1;
-  return ((iz * nc + iy) * nc + ix) * 32;
+  return ((static_cast<int>(az.i) * nc + static_cast<int>(ay.i)) * nc + static_cast<int>(ax.i)) * 32;
 }
 
 // The cell's 8 corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
@@ -113,22 +119,10 @@ __device__ __forceinline__ void sdf_corners(const SdfView& S, int off, float4& l
 
 // Trilinear value and analytic gradient at r from its cell's corners.
 __device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 lo4, float4 hi4, Sample& s) {
-  const float top = static_cast<float>(S.n - 1);
-  // u stays a rounded product: contracting it into the clamp residual below
-  // would turn an interior point's exact zero offset into a rounding residue
-  const float ux = __fmul_rn(r.x - S.lo[0], S.inv_h);
-  const float uy = __fmul_rn(r.y - S.lo[1], S.inv_h);
-  const float uz = __fmul_rn(r.z - S.lo[2], S.inv_h);
-  const float bx = fminf(fmaxf(ux, 0.0f), top);
-  const float by = fminf(fmaxf(uy, 0.0f), top);
-  const float bz = fminf(fmaxf(uz, 0.0f), top);
-  const int cm = S.n - 2;
-  const int ix = min(max(static_cast<int>(floorf(bx)), 0), cm);
-  const int iy = min(max(static_cast<int>(floorf(by)), 0), cm);
-  const int iz = min(max(static_cast<int>(floorf(bz)), 0), cm);
-  s.fx = bx - static_cast<float>(ix);
-  s.fy = by - static_cast<float>(iy);
-  s.fz = bz - static_cast<float>(iz);
+  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
+  s.fx = ax.b - ax.i;
+  s.fy = ay.b - ay.i;
+  s.fz = az.b - az.i;
   s.dx00 = lo4.y - lo4.x;
   s.dx10 = lo4.w - lo4.z;
   s.dx01 = hi4.y - hi4.x;
@@ -146,12 +140,13 @@ __device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 l
   const float gx = fmaf(s.fz, gx1 - gx0, gx0);
   s.dyx0 = (hi4.z - hi4.x) - (lo4.z - lo4.x);
   s.dyx1 = (hi4.w - hi4.y) - (lo4.w - lo4.y);
-  s.clx = ux != bx;
-  s.cly = uy != by;
-  s.clz = uz != bz;
+  s.clx = ax.u != ax.b;
+  s.cly = ay.u != ay.b;
+  s.clz = az.u != az.b;
   s.phi = fmaf(s.fz, gz, c0);
   s.n = v3(s.clx ? 0.0f : gx * S.inv_h, s.cly ? 0.0f : gy * S.inv_h, s.clz ? 0.0f : gz * S.inv_h);
-  s.e = v3(s.clx ? (ux - bx) * S.h : 0.0f, s.cly ? (uy - by) * S.h : 0.0f, s.clz ? (uz - bz) * S.h : 0.0f);
+  // offset from the clamped point, exactly 0 on unclamped axes
+  s.e = v3((ax.u - ax.b) * S.h, (ay.u - ay.b) * S.h, (az.u - az.b) * S.h);
   // outside the box: add the distance to the clamped point and its direction
   // (selects rather than a branch keep the sample one basic block)
   const float ee = dot(s.e, s.e);

@@ -74,8 +74,9 @@ constexpr int kOffW = kOffJ + kMaxLinks * 6;   // [kMaxLinks][6] link force, tor
 constexpr int kUStride = 32;
 constexpr int kOffU = kOffW + kMaxLinks * 6;   // [7][32] per-test constants
 constexpr int kOffWS = kOffU + kSims * kUStride;   // [7][6] summed corrections of the last pass (+6 pad)
-constexpr int kOffP = kOffWS + 48;             // [64][4] world contact points of a chunk (x, y, z, link)
-constexpr int kOffPose = kOffP + kWave * 4;
+constexpr int kOffP = kOffWS + 48;             // [64][4] world contact points of a chunk (x, y, z, link);
+                                               // [6][64] per-lane sums at the end of a pass
+constexpr int kOffPose = kOffP + kWave * 6;
 
 __host__ __device__ inline int pose_slots(int K, int ckpt) { return K / ckpt + 1; }
 __host__ __device__ inline size_t wave_lds_floats(int K, int ckpt) {

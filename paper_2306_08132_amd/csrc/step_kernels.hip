@@ -129,20 +129,26 @@ __device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trac
 
 // ---------------------------------------------------------------------------
 // K = 1 (one projection iteration at the predicted, unrotated pose). Lanes
-// take (contact, test) pairs: lane = 8 * contact + test, test 7 idle, eight
-// contacts per group and eight groups per 64-contact chunk. The seven test
-// points of a contact lie within about a cell of each other, so one gather
-// instruction touches about half as many cache lines as with one contact
-// per lane, and each lane keeps the sums of its own test only.
+// take (contact, test) pairs: lane = 7 * contact + test for lanes 0..62 (lane
+// 63 idle), nine contacts per group and seven groups per 63-contact chunk.
+// The seven test points of a contact lie within about a cell of each other,
+// so one gather instruction touches about half as many cache lines as with
+// one contact per lane, and each lane keeps the sums of its own test only.
 // ---------------------------------------------------------------------------
+constexpr int kGroup = 9;                 // contacts per instruction
+constexpr int kGroups = 7;                // groups per chunk
+constexpr int kChunk = kGroup * kGroups;  // contacts per chunk (63)
+
 struct LaneTest {
-  int m;        // test of this lane (7: idle)
+  int m;        // test of this lane (kSims: idle)
+  int sub;      // contact within the group
   V3 off;       // test displacement: test_point(p, m, dv) = p + off
 };
 
 __device__ __forceinline__ LaneTest lane_test(int lane, float dv) {
   LaneTest t;
-  t.m = lane & 7;
+  t.sub = lane < kChunk ? lane / kSims : kGroup - 1;
+  t.m = lane < kChunk ? lane - kSims * t.sub : kSims;
   const float sx = t.m == 0 ? -dv : (t.m == 1 ? dv : 0.0f);
   const float sy = t.m == 2 ? -dv : (t.m == 3 ? dv : 0.0f);
   const float sz = t.m == 4 ? -dv : (t.m == 5 ? dv : 0.0f);
@@ -150,23 +156,31 @@ __device__ __forceinline__ LaneTest lane_test(int lane, float dv) {
   return t;
 }
 
-// World points of contacts [64 ch, 64 ch + 64) into the chunk area of LDS;
-// link -1 marks padding past the last contact.
+// World points of contacts [63 ch, 63 ch + 63) into the chunk area of LDS;
+// link -1 marks entries past the last contact.
 __device__ __forceinline__ void stage_chunk(const Ctx& c, int ch) {
-  const int i = ch * kWave + c.lane;
-  int link;
-  const V3 p = contact_point(c, i, link);
+  const int i = ch * kChunk + c.lane;
+  V3 p = v3(0.0f, 0.0f, 0.0f);
+  int link = -1;
+  if (c.lane < kChunk && i < c.H.Nc) p = contact_point(c, i, link);
   float4* P = reinterpret_cast<float4*>(c.lds + kOffP);
-  P[c.lane] = make_float4(p.x, p.y, p.z, __int_as_float(i < c.H.Nc ? link : -1));
+  P[c.lane] = make_float4(p.x, p.y, p.z, __int_as_float(link));
   wave_lds_sync();
 }
 
-// Sum over the eight lanes holding the same test (lane bits 3..5).
-__device__ __forceinline__ float test_sum(float v) {
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+// Per-test sums of six per-lane values: lanes m, m + 7, ..., m + 56 hold test
+// m; added in lane order through LDS, written to the 7 x 6 sums table.
+__device__ __forceinline__ void test_sums(const Ctx& c, const float v[6]) {
+  float* T = c.lds + kOffP;  // [6][64]
+  for (int j = 0; j < 6; ++j) T[j * kWave + c.lane] = v[j];
+  wave_lds_sync();
+  if (c.lane < kSims)
+    for (int j = 0; j < 6; ++j) {
+      float t = 0.0f;
+      for (int k = 0; k < kGroup; ++k) t += T[j * kWave + c.lane + kSims * k];
+      c.lds[kOffWS + 6 * c.lane + j] = t;
+    }
+  wave_lds_sync();
 }
 
 template <bool TRACE>
@@ -175,24 +189,24 @@ __device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
-  const int sub = c.lane >> 3;
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
   float W[6] = {0, 0, 0, 0, 0, 0};
   float lp = 0.0f;
-  for (int ch = 0; ch < H.n_chunks; ++ch) {
+  for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     float4 lo[2], hi[2];
     {
-      const float4 P4 = P[sub];
+      const float4 P4 = P[lt.sub];
       sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
     }
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      if (g + 1 < 8) {
-        const float4 Pn = P[8 * (g + 1) + sub];
+    for (int g = 0; g < kGroups; ++g) {
+      if (g + 1 < kGroups) {
+        const float4 Pn = P[kGroup * (g + 1) + lt.sub];
         sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
       }
-      const float4 P4 = P[8 * g + sub];
+      const float4 P4 = P[kGroup * g + lt.sub];
       const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
       const V3 a = v3(P4.x, P4.y, P4.z) + lt.off;
       Sample s;
@@ -212,17 +226,14 @@ __device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
       W[5] = fmaf(lam, u.z, W[5]);
       if constexpr (TRACE) {
         if (valid) {
-          const int i = ch * kWave + 8 * g + sub;
+          const int i = ch * kChunk + kGroup * g + lt.sub;
           float* o6 = trace_s + (static_cast<size_t>(lt.m) * H.Nc + H.perm[i]) * 6;
           o6[0] = d; o6[1] = gn.x; o6[2] = gn.y; o6[3] = gn.z; o6[4] = w; o6[5] = lam;
         }
       }
     }
   }
-  for (int j = 0; j < 6; ++j) {
-    const float t = test_sum(W[j]);
-    if (c.lane < kSims) c.lds[kOffWS + 6 * c.lane + j] = t;
-  }
+  test_sums(c, W);
   lpen = wave_sum(lp);
 }
 
@@ -265,8 +276,10 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, inv_Im = S.inv_Im;
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
-  const int sub = c.lane >> 3;
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
+  // link of the last contact (contacts are sorted by link)
+  const int last_link = H.clink[H.Nc - 1];
   // seeds of this lane's test (adjoints of its summed corrections)
   const float* U = c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
   const V3 WlB = v3(U[19], U[20], U[21]);
@@ -274,22 +287,20 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
   const float pseed = lt.m == kSims - 1 ? pen_seed : 0.0f;
   float acc[6] = {0, 0, 0, 0, 0, 0};
   int cur = -1;
-  for (int ch = 0; ch < H.n_chunks; ++ch) {
+  for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
-    const int lk = H.chunk_lk[ch];
-    const int chunk_last = lk >> 16;
     float4 lo[2], hi[2];
     {
-      const float4 P4 = P[sub];
+      const float4 P4 = P[lt.sub];
       sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
     }
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      if (g + 1 < 8) {
-        const float4 Pn = P[8 * (g + 1) + sub];
+    for (int g = 0; g < kGroups; ++g) {
+      if (g + 1 < kGroups) {
+        const float4 Pn = P[kGroup * (g + 1) + lt.sub];
         sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
       }
-      const float4 P4 = P[8 * g + sub];
+      const float4 P4 = P[kGroup * g + lt.sub];
       const int link = __float_as_int(P4.w);
       const bool valid = link >= 0 && lt.m < kSims;
       const V3 p = v3(P4.x, P4.y, P4.z);
@@ -318,15 +329,15 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
         gbar = gbar + cross(ubar, a);
         rbar = rbar + hess_mul(S, s, gbar);
       }
+      // p_bar of the sample (exactly 0 on invalid lanes: dbar = 0, no penetration)
       const V3 pb = ab + rbar;
       const V3 tau = cross(p, pb);
-      const float v6[6] = {valid ? pb.x : 0.0f, valid ? pb.y : 0.0f, valid ? pb.z : 0.0f,
-                           valid ? tau.x : 0.0f, valid ? tau.y : 0.0f, valid ? tau.z : 0.0f};
+      const float v6[6] = {pb.x, pb.y, pb.z, tau.x, tau.y, tau.z};
       // links of the group's first and last contacts (wave-uniform)
-      const int lf = __builtin_amdgcn_readfirstlane(__float_as_int(P[8 * g].w));
-      const int lz = __builtin_amdgcn_readfirstlane(__float_as_int(P[8 * g + 7].w));
-      if (lf < 0) continue;  // padding only
-      const int ll = lz >= 0 ? lz : chunk_last;
+      const int lf = __builtin_amdgcn_readfirstlane(__float_as_int(P[kGroup * g].w));
+      const int lz = __builtin_amdgcn_readfirstlane(__float_as_int(P[kGroup * g + kGroup - 1].w));
+      if (lf < 0) continue;  // past the last contact
+      const int ll = lz >= 0 ? lz : last_link;
       if (lf == ll) {
         if (lf != cur) {
           if (cur >= 0) flush_link(c, cur, acc);
