@@ -14,8 +14,14 @@
 // Readings where the paper is silent (each listed in the design notes):
 //  * object representation: dense grid, trilinear value, analytic gradient;
 //    outside the box, clamp to the box and add the Euclidean distance to it;
-//  * constraints are projected as a Jacobi sum (all corrections computed at
-//    the same pose, then added with relaxation omega), K times in one step;
+//  * the paper's Gauss-Seidel step over the contact constraints (Sec. III-C)
+//    is replaced by its parallel form with constraint averaging: every
+//    correction of Eq. (1) is computed at the same pose and their sum is
+//    divided by the number n of active (penetrating, w > w_min) constraints
+//    of that test, then added with relaxation omega; K such iterations in one
+//    step. One active constraint gives exactly the Gauss-Seidel update; n
+//    aligned constraints are resolved once instead of n times. n is piecewise
+//    constant in q, so it carries no derivative;
 //  * mass matrix: isotropic, mass 1 and inertia I/m; orientation is a
 //    rotation vector updated additively; gravity is absent;
 //  * the test velocities are +-v0 along each axis plus zero; angular 0;
@@ -358,15 +364,28 @@ struct Trace {
   }
 };
 
+// The part of d's tangent that comes from the hand point p alone:
+// dd/dp = (R grad(phi))^T = g^T, so d_hand = g . dp (value d).
+inline double hand_part(const double& d, const double*, const double*) { return d; }
+template <int N> Dual<N> hand_part(const Dual<N>& d, const Dual<N>* g, const Dual<N>* p) {
+  Dual<N> r(d.v);
+  for (int t = 0; t < N; ++t) r.d[t] = g[0].v * p[0].d[t] + g[1].v * p[1].d[t] + g[2].v * p[2].d[t];
+  return r;
+}
+
 // C = max(0, -d) with the leaky derivative rule (Sec. III-C, "Leaky
-// gradient"): value max(0, -d); tangent -dd where d < 0, -alpha dd otherwise.
-template <class S> S leaky_penetration(const S& d, double alpha) {
+// gradient"): value max(0, -d); tangent -dd where d < 0, and -alpha times
+// the hand-point part of dd otherwise. The leak is a surrogate derivative
+// for hand points that do not touch the object; along the object's pose
+// from one projection iteration to the next the derivative stays exact
+// (with one iteration the pose carries no tangent and the two coincide).
+template <class S> S leaky_penetration(const S& d, const S& d_hand, double alpha) {
   if (val(d) < 0.0) return -d;
-  S c = -alpha * d;
+  S c = -alpha * d_hand;
   c.v = 0.0;
   return c;
 }
-template <> double leaky_penetration<double>(const double& d, double) { return d < 0.0 ? -d : 0.0; }
+template <> double leaky_penetration<double>(const double& d, const double&, double) { return d < 0.0 ? -d : 0.0; }
 
 template <class S>
 void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& P, const S* q,
@@ -409,6 +428,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
       rotation_matrix(th, R);
       S Wl[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
       S Wa[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+      int n_active = 0;
       for (int i = 0; i < Nc; ++i) {
         // hand point in the object frame: r_i = R(theta)^-1 (p_i - x)
         S a[3], r[3];
@@ -419,10 +439,10 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         sample_object(o, r, phi, nrm, &info);
         // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
         S d = phi - P.r_dil;
-        S C = leaky_penetration(d, P.alpha_leak);
         // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
         S g[3], u[3];
         for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
+        S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak);
         u[0] = a[1] * g[2] - a[2] * g[1];
         u[1] = a[2] * g[0] - a[0] * g[2];
         u[2] = a[0] * g[1] - a[1] * g[0];
@@ -434,6 +454,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         if (active) {
           lam = -C / w;
           for (int j = 0; j < 3; ++j) { Wl[j] += lam * g[j]; Wa[j] += lam * u[j]; }
+          if (val(d) < 0.0) ++n_active;
         }
         if (tr) {
           if (tr->samples) {
@@ -449,10 +470,12 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
                   (static_cast<uint64_t>(val(d) < 0.0) << 52) | (static_cast<uint64_t>(active) << 53));
         }
       }
-      // Jacobi: all corrections at the same pose, summed, relaxed by omega
+      // all corrections at the same pose, averaged over the active constraints,
+      // relaxed by omega
+      const double avg = P.omega / static_cast<double>(std::max(n_active, 1));
       for (int j = 0; j < 3; ++j) {
-        x[j] = x[j] + P.omega * Wl[j];
-        th[j] = th[j] + (P.omega / Im) * Wa[j];
+        x[j] = x[j] + avg * Wl[j];
+        th[j] = th[j] + (avg / Im) * Wa[j];
       }
     }
     if (tr && tr->poses)

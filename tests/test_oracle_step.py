@@ -34,9 +34,11 @@ def _phi_np(kind, r, center=None, R=None, normal=None, offset=None):
 
 
 def eq1_correction(points, x, theta, Im, r_dil, phi):
-    """Sum over constraints of -M^-1 J^T (J M^-1 J^T)^-1 C (Eq. (1)), where
-    C(x, R) = max(0, -(phi(R^T (p - x)) - r_dil)) and J is taken by central
-    differences over x and over a world-frame rotation exp([e]x) R."""
+    """Average over the active (C > 0) constraints of -M^-1 J^T (J M^-1 J^T)^-1 C
+    (Eq. (1)), where C(x, R) = max(0, -(phi(R^T (p - x)) - r_dil)) and J is
+    taken by central differences over x and over a world-frame rotation
+    exp([e]x) R. The average is the parallel stand-in for the paper's
+    Gauss-Seidel step over the constraints."""
     R0 = rotvec_matrix(theta)
     Minv = np.diag([1, 1, 1, 1 / Im, 1 / Im, 1 / Im])
     total = np.zeros(6)
@@ -46,10 +48,12 @@ def eq1_correction(points, x, theta, Im, r_dil, phi):
         return max(0.0, -(phi(R.T @ (p - (x + dx))) - r_dil))
 
     eps = 1e-7
+    n_active = 0
     for p in points:
         c0 = C(p, np.zeros(3), np.zeros(3))
         if c0 <= 0.0:
             continue
+        n_active += 1
         J = np.zeros(6)
         for a in range(3):
             e = np.zeros(3)
@@ -57,7 +61,7 @@ def eq1_correction(points, x, theta, Im, r_dil, phi):
             J[a] = (C(p, e, np.zeros(3)) - C(p, -e, np.zeros(3))) / (2 * eps)
             J[3 + a] = (C(p, np.zeros(3), e) - C(p, np.zeros(3), -e)) / (2 * eps)
         total += -Minv @ J * c0 / (J @ Minv @ J)
-    return total
+    return total / max(n_active, 1)
 
 
 @pytest.mark.parametrize("K", [1, 3])
@@ -131,6 +135,39 @@ def test_linear_constraint_resolved_in_one_iteration(oracle_lib):
         np.testing.assert_array_equal(tr["poses"][m, 1, 3:], 0.0)
         assert abs(tr["samples"][m, 1, 0, 0]) <= 1e-18
         assert tr["samples"][m, 1, 0, 5] == 0.0 or abs(tr["samples"][m, 1, 0, 5]) < 1e-18
+
+
+def test_aligned_contacts_resolve_once(oracle_lib):
+    """Three contacts at the same depth below a plane, lever arms along the
+    normal: the averaged update is the single-contact one (-C n), not three
+    times it, and the next iteration sees no penetration."""
+    O = oracle_lib
+    delta = 0.002
+    ob = plane_obj(O, normal=(0, 0, 1), offset=0.0)
+    P = O.Params(K=2)
+    pts = [[0.0, 0.0, -delta], [0.0, 0.0, -delta], [0.0, 0.0, -delta]]
+    tr = O.trace(O.Hand(point_hand(pts)), ob, P, q_wrist())
+    for m in (4, 5, 6):
+        x0 = tr["poses"][m, 0, :3]
+        C = delta + x0[2]
+        np.testing.assert_allclose(tr["poses"][m, 1, :3] - x0, [0, 0, -C], atol=1e-18)
+        assert np.all(np.abs(tr["samples"][m, 1, :, 0]) <= 1e-18)
+
+
+def test_many_iterations_stay_bounded(oracle_lib):
+    """Sixteen projection iterations on a grid with many penetrating contacts:
+    the averaged iteration keeps the poses bounded (the summed form overshoots
+    by the contact count each iteration), and the leak confined to hand
+    points keeps the gradient within a small factor of the one-iteration
+    gradient (leaking along the pose chain compounds it to ~1e25)."""
+    O = oracle_lib
+    hand, grid, q = S.config_workload("tiny", B=6)
+    P = O.Params(K=16, r_dil=0.01)
+    r = O.step(O.Hand(hand.rounded()), O.Obj(grid), P, q)
+    assert np.isfinite(r["loss"]).all() and np.isfinite(r["grad"]).all()
+    assert np.abs(r["grad"]).max() < 1e7
+    tr = O.trace(O.Hand(hand.rounded()), O.Obj(grid), P, q[0])
+    assert np.abs(tr["poses"]).max() < 0.1  # metres / radians
 
 
 def test_nonpenetrating_contacts_contribute_exactly_zero(oracle_lib):
@@ -234,6 +271,22 @@ def test_leaky_gradient_zero_without_leak_and_linear_in_alpha(oracle_lib):
     np.testing.assert_array_equal(g0, 0.0)
     assert np.abs(g1).max() > 0
     np.testing.assert_allclose(ga, 0.1 * g1, rtol=1e-12, atol=1e-12 * np.abs(g1).max())
+
+
+def test_leak_is_affine_in_alpha_over_iterations(oracle_lib):
+    """With several projection iterations and penetrating contacts, the
+    gradient is affine in alpha: the leak acts on hand points only and its
+    tangent then travels through the exact iteration map. (Leaking along the
+    object-pose chain too would add alpha^2, alpha^3, ... terms.)"""
+    O = oracle_lib
+    hand, grid, q = S.config_workload("tiny", B=3)
+    H, ob = O.Hand(hand), O.Obj(grid)
+    g = {a: O.step(H, ob, O.Params(K=3, r_dil=0.01, alpha_leak=a), q)["grad"] for a in (0.0, 0.1, 0.2, 0.4)}
+    d1 = g[0.1] - g[0.0]
+    assert np.abs(d1).max() > 1e-6 * np.abs(g[0.0]).max()  # the leak matters here
+    scale = np.abs(g[0.4]).max()
+    np.testing.assert_allclose(g[0.2] - g[0.0], 2.0 * d1, atol=1e-9 * scale)
+    np.testing.assert_allclose(g[0.4] - g[0.0], 4.0 * d1, atol=1e-9 * scale)
 
 
 @pytest.mark.parametrize("h", [1e-4, 1e-6])
