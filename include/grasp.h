@@ -157,7 +157,8 @@ enum {
 void grasp_default_params(grasp_step_params* p);
 
 /* Host out: workspace bytes grasp_step_fwd/bwd need for B candidates in SAVE
- * mode (pose checkpoints, 168 (K/ckpt + 1) bytes per candidate). */
+ * mode (pose checkpoints and per-iteration active-constraint counts,
+ * 168 (K/ckpt + 1) + 28 K bytes per candidate). */
 grasp_status grasp_step_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
                                         const grasp_step_params* p, int32_t B, size_t* out);
 

@@ -478,7 +478,8 @@ void save_tile(const std::string& key, TileCfg c) {
 }
 
 size_t pose_ws_bytes(const StepConsts& c, int32_t B) {
-  return static_cast<size_t>(B) * kSims * pose_slots(c.K, c.ckpt) * 6 * sizeof(float);
+  // pose checkpoints [B][7][slots][6], then active-constraint counts [B][K][7]
+  return static_cast<size_t>(B) * kSims * (pose_slots(c.K, c.ckpt) * 6 + c.K) * sizeof(float);
 }
 
 StepArgs base_args(const Resolved& r, int32_t B) {

@@ -73,14 +73,21 @@ constexpr int kOffJ = kOffT + kMaxLinks * 12;  // [kMaxLinks][6] joint world ori
 constexpr int kOffW = kOffJ + kMaxLinks * 6;   // [kMaxLinks][6] link force, torque adjoints
 constexpr int kUStride = 32;
 constexpr int kOffU = kOffW + kMaxLinks * 6;   // [7][32] per-test constants
-constexpr int kOffWS = kOffU + kSims * kUStride;   // [7][6] summed corrections of the last pass (+6 pad)
-constexpr int kOffP = kOffWS + 48;             // [64][4] world contact points of a chunk (x, y, z, link);
+constexpr int kOffWS = kOffU + kSims * kUStride;   // [7][6] summed corrections of the last pass,
+                                                   // then [7] active-constraint counts (+7 pad)
+constexpr int kOffCnt = kOffWS + kSims * 6;
+constexpr int kOffP = kOffWS + 56;             // [64][4] world contact points of a chunk (x, y, z, link);
                                                // [6][64] per-lane sums at the end of a pass
 constexpr int kOffPose = kOffP + kWave * 6;
 
+// After the pose slots: the active-constraint count of every (iteration, test),
+// [K][7], which sets the average of that iteration's corrections.
 __host__ __device__ inline int pose_slots(int K, int ckpt) { return K / ckpt + 1; }
+__host__ __device__ inline size_t counts_offset(int K, int ckpt) {
+  return static_cast<size_t>(kOffPose) + static_cast<size_t>(K / ckpt + 1 + ckpt) * kSims * 6;
+}
 __host__ __device__ inline size_t wave_lds_floats(int K, int ckpt) {
-  const size_t f = static_cast<size_t>(kOffPose) + static_cast<size_t>(K / ckpt + 1 + ckpt) * kSims * 6;
+  const size_t f = counts_offset(K, ckpt) + static_cast<size_t>(K) * kSims;
   return (f + 31) / 32 * 32;  // keep every wave's region 128-byte aligned
 }
 
@@ -105,7 +112,7 @@ struct StepArgs {
   float* terms;         // [B][4] (or null)
   float* dq;            // [B][n_dof] (or null)
   const float* dloss;   // [B] (or null: 1)
-  float* poses;         // [B][7][slots][6] checkpoints (or null)
+  float* poses;         // [B][7][slots][6] checkpoints, then [B][K][7] counts (or null)
   int* nonfinite;       // [1] set when any loss is not finite (or null)
   const int* order;     // [B] candidate taken by work item i (or null: i itself)
   // debug trace (caller order), all optional

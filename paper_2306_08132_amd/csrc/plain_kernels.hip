@@ -27,6 +27,7 @@ struct PlainArgs {
   float* Pw;          // [B][Nc][3] contact points (sorted order)
   float* Sm;          // [B][7][Nc][4] samples: d, g
   float* W;           // [B][7][6] summed corrections
+  float* NA;          // [B][7] active-constraint counts
   float* lpen;        // [B]
   float* seeds;       // [B][7][6] adjoints of the summed corrections
   float* PB;          // [B][Nc][3] adjoint of each contact point
@@ -68,28 +69,29 @@ __global__ void pk_sample(PlainArgs a) {
   reinterpret_cast<float4*>(a.Sm)[t] = make_float4(s.phi - a.P.r_dil, s.n.x, s.n.y, s.n.z);
 }
 
-// Block sum of 6 values (plus one) in a fixed order: waves, then the 4 wave totals.
-__device__ void block_sum7(float v[7], float* sh) {
+// Block sum of N values in a fixed order: waves, then the 4 wave totals.
+template <int N>
+__device__ void block_sum(float v[N], float* sh) {
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  for (int j = 0; j < 7; ++j) v[j] = wave_sum(v[j]);
+  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
   if (lane == 0)
-    for (int j = 0; j < 7; ++j) sh[w * 7 + j] = v[j];
+    for (int j = 0; j < N; ++j) sh[w * N + j] = v[j];
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int j = 0; j < 7; ++j) {
+    for (int j = 0; j < N; ++j) {
       float s = sh[j];
-      for (int k = 1; k < kBlock / kWave; ++k) s += sh[k * 7 + j];
+      for (int k = 1; k < kBlock / kWave; ++k) s += sh[k * N + j];
       v[j] = s;
     }
 }
 
 // One block per (candidate, test): W = sum_i lambda_i (g_i, a_i x g_i) over
-// penetrating contacts, and the penetration energy on the rest test.
+// penetrating contacts, their count, and the penetration energy on the rest test.
 __global__ void __launch_bounds__(kBlock) pk_reduce(PlainArgs a) {
-  __shared__ float sh[(kBlock / kWave) * 7];
+  __shared__ float sh[(kBlock / kWave) * 8];
   const int bm = blockIdx.x, b = bm / kSims, m = bm % kSims;
   const float dv = a.P.dt * a.P.v0;
-  float acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < a.H.Nc; i += kBlock) {
     const float4 sm = reinterpret_cast<const float4*>(a.Sm)[static_cast<size_t>(bm) * a.H.Nc + i];
     const float d = sm.x;
@@ -103,13 +105,15 @@ __global__ void __launch_bounds__(kBlock) pk_reduce(PlainArgs a) {
         const float lam = d * rcp(w);
         acc[0] = fmaf(lam, g.x, acc[0]); acc[1] = fmaf(lam, g.y, acc[1]); acc[2] = fmaf(lam, g.z, acc[2]);
         acc[3] = fmaf(lam, u.x, acc[3]); acc[4] = fmaf(lam, u.y, acc[4]); acc[5] = fmaf(lam, u.z, acc[5]);
+        acc[7] += 1.0f;
       }
       if (m == kSims - 1) acc[6] = fmaf(0.5f * d, d, acc[6]);
     }
   }
-  block_sum7(acc, sh);
+  block_sum<8>(acc, sh);
   if (threadIdx.x == 0) {
     for (int j = 0; j < 6; ++j) a.W[static_cast<size_t>(bm) * 6 + j] = acc[j];
+    a.NA[bm] = acc[7];
     if (m == kSims - 1) a.lpen[b] = acc[6];
   }
 }
@@ -120,19 +124,21 @@ __global__ void pk_loss(PlainArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.B) return;
   const StepConsts& P = a.P;
-  const float dv = P.dt * P.v0, idt = 1.0f / P.dt, omi = P.omega * a.S.inv_Im;
+  const float dv = P.dt * P.v0, idt = 1.0f / P.dt;
   const float cst = P.w_stable / (kSims * P.dt);
   float ls = 0.0f;
   for (int m = 0; m < kSims; ++m) {
     const float* Wm = a.W + (static_cast<size_t>(b) * kSims + m) * 6;
+    // corrections averaged over the test's active constraints, relaxed by omega
+    const float om = P.omega / fmaxf(a.NA[static_cast<size_t>(b) * kSims + m], 1.0f), omi = om * a.S.inv_Im;
     const V3 d = sim_dir(m);
-    const V3 x = v3(fmaf(P.omega, Wm[0], dv * d.x), fmaf(P.omega, Wm[1], dv * d.y), fmaf(P.omega, Wm[2], dv * d.z));
+    const V3 x = v3(fmaf(om, Wm[0], dv * d.x), fmaf(om, Wm[1], dv * d.y), fmaf(om, Wm[2], dv * d.z));
     const V3 th = v3(omi * Wm[3], omi * Wm[4], omi * Wm[5]);
     const float nx = sqrtf(dot(x, x)), nt = sqrtf(dot(th, th));
     ls += nx * idt + nt * idt;
     const float fx = nx > 0.0f ? cst / nx : 0.0f, ft = nt > 0.0f ? cst / nt : 0.0f;
     float* sd = a.seeds + (static_cast<size_t>(b) * kSims + m) * 6;
-    sd[0] = P.omega * fx * x.x; sd[1] = P.omega * fx * x.y; sd[2] = P.omega * fx * x.z;
+    sd[0] = om * fx * x.x; sd[1] = om * fx * x.y; sd[2] = om * fx * x.z;
     sd[3] = omi * ft * th.x; sd[4] = omi * ft * th.y; sd[5] = omi * ft * th.z;
   }
   ls *= 1.0f / kSims;
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) pk_link_sum(PlainArgs a) {
     const V3 tau = cross(p, pb);
     acc[0] += pb.x; acc[1] += pb.y; acc[2] += pb.z; acc[3] += tau.x; acc[4] += tau.y; acc[5] += tau.z;
   }
-  block_sum7(acc, sh);
+  block_sum<7>(acc, sh);
   if (threadIdx.x == 0)
     for (int j = 0; j < 6; ++j) a.LW[static_cast<size_t>(blockIdx.x) * 6 + j] = acc[j];
 }
@@ -270,6 +276,7 @@ size_t layout(PlainArgs& a, const HandView& H, int B, float* ws) {
   a.Pw = take(b * Nc * 3);
   a.Sm = take(b * kSims * Nc * 4);
   a.W = take(b * kSims * 6);
+  a.NA = take(b * kSims);
   a.lpen = take(b);
   a.seeds = take(b * kSims * 6);
   a.PB = take(b * Nc * 3);

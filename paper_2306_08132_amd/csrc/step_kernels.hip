@@ -70,70 +70,16 @@ __device__ __forceinline__ void load_rot(const float* U, Rot& o) {
   o.A = U[15]; o.B = U[16]; o.Ap = U[17]; o.Bp = U[18];
 }
 
-// Tests [M0, M1) of one pass at a general object pose (x, theta): the
-// samples carry the rotation R(theta). One test per group keeps 6 sums live.
-template <int M0, int M1>
-__device__ void forward_tests(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
-  const HandView& H = c.H;
-  const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min;
-  float W[kSims][6];
-  for (int m = M0; m < M1; ++m)
-    for (int j = 0; j < 6; ++j) W[m][j] = 0.0f;
-  float lp = 0.0f;
-  for (int ch = 0; ch < H.n_chunks; ++ch) {
-    const int i = ch * kWave + c.lane;
-    const bool valid = i < H.Nc;
-    int link;
-    const V3 p = contact_point(c, i, link);
-#pragma unroll
-    for (int m = M0; m < M1; ++m) {
-      Rot o;
-      const float* U = c.lds + kOffU + kUStride * m;
-      load_rot(U, o);
-      const V3 a = p - v3(U[0], U[1], U[2]);
-      const V3 r = mul_t(o.R, a);
-      Sample s;
-      sample_sdf(S, r, s);
-      const V3 g = mul(o.R, s.n);
-      const float d = s.phi - rd;
-      if (first && m == kSims - 1 && valid && d < 0.0f) lp = fmaf(0.5f * d, d, lp);
-      float lam = 0.0f, w = 0.0f;
-      if (valid && (d < 0.0f || trace_s)) {
-        const V3 u = cross(a, g);
-        w = fmaf(dot(u, u), S.inv_Im, dot(g, g));
-        if (d < 0.0f && w > wmin) {
-          lam = d * rcp(w);
-          W[m][0] = fmaf(lam, g.x, W[m][0]);
-          W[m][1] = fmaf(lam, g.y, W[m][1]);
-          W[m][2] = fmaf(lam, g.z, W[m][2]);
-          W[m][3] = fmaf(lam, u.x, W[m][3]);
-          W[m][4] = fmaf(lam, u.y, W[m][4]);
-          W[m][5] = fmaf(lam, u.z, W[m][5]);
-        }
-      }
-      if (trace_s && valid) {
-        float* o6 = trace_s + ((static_cast<size_t>(m) * K + k) * H.Nc + H.perm[i]) * 6;
-        o6[0] = d; o6[1] = g.x; o6[2] = g.y; o6[3] = g.z; o6[4] = w; o6[5] = lam;
-      }
-    }
-  }
-  // the sums are wave-uniform: park them in LDS rather than in registers
-  for (int m = M0; m < M1; ++m)
-    for (int j = 0; j < 6; ++j) {
-      const float t = wave_sum(W[m][j]);
-      if (c.lane == 0) c.lds[kOffWS + 6 * m + j] = t;
-    }
-  if (M1 == kSims) lpen = wave_sum(lp);
-}
-
 // ---------------------------------------------------------------------------
-// K = 1 (one projection iteration at the predicted, unrotated pose). Lanes
-// take (contact, test) pairs: lane = 7 * contact + test for lanes 0..62 (lane
-// 63 idle), nine contacts per group and seven groups per 63-contact chunk.
-// The seven test points of a contact lie within about a cell of each other,
-// so one gather instruction touches about half as many cache lines as with
-// one contact per lane, and each lane keeps the sums of its own test only.
+// Projection passes. Lanes take (contact, test) pairs: lane = 7 * contact +
+// test for lanes 0..62 (lane 63 idle), nine contacts per group and seven
+// groups per 63-contact chunk. The seven test points of a contact lie close
+// together (within about a cell at the predicted pose), so one gather
+// instruction touches about half as many cache lines as with one contact per
+// lane, and each lane keeps the sums of its own test only. ROT selects the
+// general pose: sample at R(theta)^T (p - x) with the test's (x, theta) from
+// LDS; without it (one iteration) the object is at its predicted, unrotated
+// pose and the test point is p minus the test's displacement.
 // ---------------------------------------------------------------------------
 constexpr int kGroup = 9;                 // contacts per instruction
 constexpr int kGroups = 7;                // groups per chunk
@@ -168,56 +114,78 @@ __device__ __forceinline__ void stage_chunk(const Ctx& c, int ch) {
   wave_lds_sync();
 }
 
-// Per-test sums of six per-lane values: lanes m, m + 7, ..., m + 56 hold test
-// m; added in lane order through LDS, written to the 7 x 6 sums table.
-__device__ __forceinline__ void test_sums(const Ctx& c, const float v[6]) {
-  float* T = c.lds + kOffP;  // [6][64]
-  for (int j = 0; j < 6; ++j) T[j * kWave + c.lane] = v[j];
+// Per-test sums of N per-lane values: lanes m, m + 7, ..., m + 56 hold test m;
+// added in lane order through LDS. Lane m < 7 then stores (or adds) its N
+// sums at dst + stride * m.
+template <int N>
+__device__ __forceinline__ void test_sums(const Ctx& c, const float v[N], float* dst, int stride, bool add) {
+  float* T = c.lds + kOffP;  // [N][64], N <= 6
+  for (int j = 0; j < N; ++j) T[j * kWave + c.lane] = v[j];
   wave_lds_sync();
   if (c.lane < kSims)
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < N; ++j) {
       float t = 0.0f;
       for (int k = 0; k < kGroup; ++k) t += T[j * kWave + c.lane + kSims * k];
-      c.lds[kOffWS + 6 * c.lane + j] = t;
+      float* o = dst + stride * c.lane + j;
+      *o = add ? *o + t : t;
     }
   wave_lds_sync();
 }
 
-template <bool TRACE>
-__device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
+// The test's object pose of this pass for ROT lanes (LDS per-test constants;
+// the idle lane borrows test 6's).
+__device__ __forceinline__ const float* test_consts(const Ctx& c, const LaneTest& lt) {
+  return c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
+}
+
+template <bool ROT, bool TRACE>
+__device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
   const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
+  // object pose of this lane's test: a = p - x, r = R^T a
+  float R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  V3 x = v3(0.0f, 0.0f, 0.0f);
+  if constexpr (ROT) {
+    const float* U = test_consts(c, lt);
+    x = v3(U[0], U[1], U[2]);
+    for (int j = 0; j < 9; ++j) R[j] = U[3 + j];
+  }
+  auto test_pt = [&](V3 p) { return ROT ? p - x : p + lt.off; };
+  auto frame_pt = [&](V3 a) { return ROT ? mul_t(R, a) : a; };
   float W[6] = {0, 0, 0, 0, 0, 0};
-  float lp = 0.0f;
+  float lp = 0.0f, na = 0.0f;
   for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     float4 lo[2], hi[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
+      sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
+        sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
+                    hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
       const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
-      const V3 a = v3(P4.x, P4.y, P4.z) + lt.off;
+      const V3 a = test_pt(v3(P4.x, P4.y, P4.z));
       Sample s;
-      sample_sdf_from(S, a, lo[g & 1], hi[g & 1], s);
-      const V3 gn = s.n;
+      sample_sdf_from(S, frame_pt(a), lo[g & 1], hi[g & 1], s);
+      const V3 gn = ROT ? mul(R, s.n) : s.n;
       const float d = s.phi - rd;
       const bool act = valid && d < 0.0f;
-      lp = (act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      lp = (first && act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
       const V3 u = cross(a, gn);
       const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
-      const float lam = (act && w > wmin) ? d * rcp(w) : 0.0f;
+      const bool on = act && w > wmin;
+      const float lam = on ? d * rcp(w) : 0.0f;
+      na += on ? 1.0f : 0.0f;
       W[0] = fmaf(lam, gn.x, W[0]);
       W[1] = fmaf(lam, gn.y, W[1]);
       W[2] = fmaf(lam, gn.z, W[2]);
@@ -227,13 +195,14 @@ __device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
       if constexpr (TRACE) {
         if (valid) {
           const int i = ch * kChunk + kGroup * g + lt.sub;
-          float* o6 = trace_s + (static_cast<size_t>(lt.m) * H.Nc + H.perm[i]) * 6;
+          float* o6 = trace_s + ((static_cast<size_t>(lt.m) * K + k) * H.Nc + H.perm[i]) * 6;
           o6[0] = d; o6[1] = gn.x; o6[2] = gn.y; o6[3] = gn.z; o6[4] = w; o6[5] = lam;
         }
       }
     }
   }
-  test_sums(c, W);
+  test_sums<6>(c, W, c.lds + kOffWS, 6, false);
+  test_sums<1>(c, &na, c.lds + kOffCnt, 1, false);
   lpen = wave_sum(lp);
 }
 
@@ -243,18 +212,8 @@ __device__ void forward_k1(const Ctx& c, float& lpen, float* trace_s) {
 template <bool KONE>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
-  if constexpr (KONE) {
-    if (trace_s) forward_k1<true>(c, lpen, trace_s);
-    else forward_k1<false>(c, lpen, nullptr);
-  } else {
-    forward_tests<0, 1>(c, first, lpen, trace_s, K, k);
-    forward_tests<1, 2>(c, first, lpen, trace_s, K, k);
-    forward_tests<2, 3>(c, first, lpen, trace_s, K, k);
-    forward_tests<3, 4>(c, first, lpen, trace_s, K, k);
-    forward_tests<4, 5>(c, first, lpen, trace_s, K, k);
-    forward_tests<5, 6>(c, first, lpen, trace_s, K, k);
-    forward_tests<6, 7>(c, first, lpen, trace_s, K, k);
-  }
+  if (trace_s) forward_lanes<!KONE, true>(c, first, lpen, trace_s, K, k);
+  else forward_lanes<!KONE, false>(c, first, lpen, nullptr, K, k);
   wave_lds_sync();
 }
 
@@ -268,10 +227,14 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
   }
 }
 
-// K = 1 backward (the adjoint of forward_k1), same lane layout. Each lane
-// adds its sample's p_bar and p x p_bar to per-lane running sums of the
-// current link; sums are flushed (wave reductions) where the link changes.
-__device__ void backward_k1(const Ctx& c, float pen_seed) {
+// One backward iteration (the adjoint of forward_lanes at iteration k), same
+// lane layout. The per-test seeds (adjoints of the summed corrections) are in
+// LDS. Each lane adds its sample's p_bar and p x p_bar to per-lane running
+// sums of the current link, flushed (wave reductions) where the link changes;
+// with pose_adj the lanes also sum the adjoint of their test's pose (-sum
+// a_bar, sum theta_bar), which is added to the running pose adjoint.
+template <bool ROT>
+__device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, inv_Im = S.inv_Im;
@@ -280,34 +243,44 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
   const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
   // link of the last contact (contacts are sorted by link)
   const int last_link = H.clink[H.Nc - 1];
-  // seeds of this lane's test (adjoints of its summed corrections)
-  const float* U = c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
+  const float* U = test_consts(c, lt);
+  // seeds of this lane's test
   const V3 WlB = v3(U[19], U[20], U[21]);
   const V3 WaB = v3(U[22], U[23], U[24]);
-  const float pseed = lt.m == kSims - 1 ? pen_seed : 0.0f;
+  const float pseed = (first && lt.m == kSims - 1) ? pen_seed : 0.0f;
+  Rot o;
+  V3 x = v3(0.0f, 0.0f, 0.0f);
+  if constexpr (ROT) {
+    load_rot(U, o);
+    x = v3(U[0], U[1], U[2]);
+  }
+  auto test_pt = [&](V3 p) { return ROT ? p - x : p + lt.off; };
+  auto frame_pt = [&](V3 a) { return ROT ? mul_t(o.R, a) : a; };
   float acc[6] = {0, 0, 0, 0, 0, 0};
+  float XB[6] = {0, 0, 0, 0, 0, 0};
   int cur = -1;
   for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     float4 lo[2], hi[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners(S, sdf_cell_byte(S, v3(P4.x, P4.y, P4.z) + lt.off), lo[0], hi[0]);
+      sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners(S, sdf_cell_byte(S, v3(Pn.x, Pn.y, Pn.z) + lt.off), lo[(g + 1) & 1], hi[(g + 1) & 1]);
+        sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
+                    hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
       const int link = __float_as_int(P4.w);
       const bool valid = link >= 0 && lt.m < kSims;
       const V3 p = v3(P4.x, P4.y, P4.z);
-      const V3 a = p + lt.off;
+      const V3 a = test_pt(p);
       Sample s;
-      sample_sdf_from(S, a, lo[g & 1], hi[g & 1], s);
-      const V3 gn = s.n;
+      sample_sdf_from(S, frame_pt(a), lo[g & 1], hi[g & 1], s);
+      const V3 gn = ROT ? mul(o.R, s.n) : s.n;
       const float d = s.phi - rd;
       const V3 u = cross(a, gn);
       const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
@@ -319,18 +292,30 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
       float dbar = okw ? (pen ? lb * iw : alpha * lb * iw) : 0.0f;
       dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
       V3 ab = v3(0.0f, 0.0f, 0.0f);
+      V3 gbar = v3(0.0f, 0.0f, 0.0f);
       V3 rbar = dbar * s.n;
       if (pen) {
         const float lam = d * iw;
         const float wbar2 = -2.0f * lb * lam * iw;
         const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
-        V3 gbar = axpy(lam, WlB, wbar2 * gn);
+        gbar = axpy(lam, WlB, wbar2 * gn);
         ab = cross(gn, ubar);
         gbar = gbar + cross(ubar, a);
-        rbar = rbar + hess_mul(S, s, gbar);
+        rbar = rbar + hess_mul(S, s, ROT ? mul_t(o.R, gbar) : gbar);
       }
-      // p_bar of the sample (exactly 0 on invalid lanes: dbar = 0, no penetration)
-      const V3 pb = ab + rbar;
+      // a_bar of the sample (exactly 0 on invalid lanes: dbar = 0, no penetration)
+      const V3 pb = ab + (ROT ? mul(o.R, rbar) : rbar);
+      if constexpr (ROT) {
+        // the leak acts on the hand point only: a non-penetrating sample adds
+        // nothing to the adjoint of the object's pose
+        if (pose_adj && pen) {
+          V3 thb = v3(0.0f, 0.0f, 0.0f);
+          if (pen) thb = rot_vjp(o, 1.0f, s.n, gbar);
+          thb = thb - rot_vjp(o, -1.0f, a, rbar);
+          XB[0] -= pb.x; XB[1] -= pb.y; XB[2] -= pb.z;
+          XB[3] += thb.x; XB[4] += thb.y; XB[5] += thb.z;
+        }
+      }
       const V3 tau = cross(p, pb);
       const float v6[6] = {pb.x, pb.y, pb.z, tau.x, tau.y, tau.z};
       // links of the group's first and last contacts (wave-uniform)
@@ -358,147 +343,35 @@ __device__ void backward_k1(const Ctx& c, float pen_seed) {
     }
   }
   if (cur >= 0) flush_link(c, cur, acc);
-  wave_lds_sync();
-}
-
-// One backward iteration over all contacts (the adjoint of forward_pass at
-// iteration k). The per-test seeds Wl_bar, Wa_bar (adjoints of the summed
-// corrections) are in LDS. Adds p_bar x p and p_bar to the link wrench table
-// and, when pose_adj, returns the pose adjoint sums (-sum a_bar, sum theta_bar).
-template <int M0, int M1>
-__device__ void backward_tests(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
-  const HandView& H = c.H;
-  const SdfView& S = c.S;
-  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha;
-  const float inv_Im = S.inv_Im;
-  float XB[kSims][6];
-  if (pose_adj)
-    for (int m = M0; m < M1; ++m)
-      for (int j = 0; j < 6; ++j) XB[m][j] = 0.0f;
-  float acc[6] = {0, 0, 0, 0, 0, 0};
-  int cur = -1;
-  for (int ch = 0; ch < H.n_chunks; ++ch) {
-    const int i = ch * kWave + c.lane;
-    const bool valid = i < H.Nc;
-    int link;
-    const V3 p = contact_point(c, i, link);
-    V3 pbar = v3(0.0f, 0.0f, 0.0f);
-#pragma unroll
-    for (int m = M0; m < M1; ++m) {
-      const float* U = c.lds + kOffU + kUStride * m;
-      Rot o;
-      load_rot(U, o);
-      const V3 a = p - v3(U[0], U[1], U[2]);
-      const V3 r = mul_t(o.R, a);
-      Sample s;
-      sample_sdf(S, r, s);
-      const V3 g = mul(o.R, s.n);
-      const float d = s.phi - rd;
-      const V3 u = cross(a, g);
-      const float w = fmaf(dot(u, u), inv_Im, dot(g, g));
-      const V3 WlB = v3(U[19], U[20], U[21]);
-      const V3 WaB = v3(U[22], U[23], U[24]);
-      const float lb = fmaf(WlB.x, g.x, fmaf(WlB.y, g.y, fmaf(WlB.z, g.z, dot(WaB, u))));
-      float dbar = 0.0f;
-      V3 gbar = v3(0.0f, 0.0f, 0.0f), abar = v3(0.0f, 0.0f, 0.0f);
-      bool pen = false;
-      if (valid && w > wmin) {
-        const float iw = rcp(w);
-        if (d < 0.0f) {
-          // lambda = d / w: full derivative through d, g and u
-          pen = true;
-          const float lam = d * iw;
-          dbar = lb * iw;
-          const float wbar2 = -2.0f * lb * lam * iw;
-          const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
-          gbar = axpy(lam, WlB, wbar2 * g);
-          abar = cross(g, ubar);
-          gbar = gbar + cross(ubar, a);
-        } else {
-          // leaky rule: dC/dd = -alpha where the point does not penetrate
-          dbar = alpha * lb * iw;
-        }
-      }
-      if (first && m == kSims - 1 && valid && d < 0.0f) dbar = fmaf(pen_seed, d, dbar);
-      // second derivative only for penetrating samples
-      V3 rbar;
-      {
-        const V3 nbar = mul_t(o.R, gbar);
-        rbar = dbar * s.n;
-        if (pen) rbar = rbar + hess_mul(S, s, nbar);
-        abar = abar + mul(o.R, rbar);
-        if (pose_adj && valid) {
-          V3 thb = v3(0.0f, 0.0f, 0.0f);
-          if (pen) thb = rot_vjp(o, 1.0f, s.n, gbar);
-          thb = thb - rot_vjp(o, -1.0f, a, rbar);
-          XB[m][0] -= abar.x; XB[m][1] -= abar.y; XB[m][2] -= abar.z;
-          XB[m][3] += thb.x; XB[m][4] += thb.y; XB[m][5] += thb.z;
-        }
-      }
-      pbar = pbar + abar;
-    }
-    // scatter p_bar into link wrenches (force, torque about the world origin)
-    const V3 tau = cross(p, pbar);
-    const float v6[6] = {pbar.x, pbar.y, pbar.z, tau.x, tau.y, tau.z};
-    const int lk = H.chunk_lk[ch];
-    const int lf = lk & 0xffff, ll = lk >> 16;
-    if (lf == ll) {
-      if (lf != cur) {
-        if (cur >= 0) flush_link(c, cur, acc);
-        for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
-        cur = lf;
-      }
-      for (int j = 0; j < 6; ++j) acc[j] += v6[j];
-    } else {
-      if (cur >= 0) flush_link(c, cur, acc);
-      for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
-      cur = -1;
-      for (int l = lf; l <= ll; ++l) {
-        float mv[6];
-        for (int j = 0; j < 6; ++j) mv[j] = (link == l && valid) ? v6[j] : 0.0f;
-        flush_link(c, l, mv);
-      }
-    }
-  }
-  if (cur >= 0) flush_link(c, cur, acc);
   // pose adjoint of the previous iteration: running adjoint += this pass's sums
-  if (pose_adj)
-    for (int m = M0; m < M1; ++m)
-      for (int j = 0; j < 6; ++j) {
-        const float t = wave_sum(XB[m][j]);
-        if (c.lane == 0) c.lds[kOffU + kUStride * m + 25 + j] += t;
-      }
+  if (ROT && pose_adj) test_sums<6>(c, XB, c.lds + kOffU + 25, kUStride, true);
   wave_lds_sync();
 }
 
-// One backward iteration over all contacts (the adjoint of forward_pass at
-// iteration k). The per-test seeds (adjoints of the summed corrections) are
-// in LDS. Adds p_bar and p x p_bar to the link wrench table and, when
-// pose_adj, returns the pose adjoint sums (-sum a_bar, sum theta_bar).
 template <bool KONE>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
-  if constexpr (KONE) {
-    backward_k1(c, pen_seed);
-  } else {
-    backward_tests<0, 1>(c, first, pen_seed, pose_adj);
-    backward_tests<1, 2>(c, first, pen_seed, pose_adj);
-    backward_tests<2, 3>(c, first, pen_seed, pose_adj);
-    backward_tests<3, 4>(c, first, pen_seed, pose_adj);
-    backward_tests<4, 5>(c, first, pen_seed, pose_adj);
-    backward_tests<5, 6>(c, first, pen_seed, pose_adj);
-    backward_tests<6, 7>(c, first, pen_seed, pose_adj);
-  }
+  backward_lanes<!KONE>(c, first, pen_seed, pose_adj);
 }
 
 __device__ __forceinline__ float* pose_slot(float* lds, int s) { return lds + kOffPose + s * kSims * 6; }
 
-// Writes pose_new = pose_old + (omega W_lin, omega/(I/m) W_ang) for all tests
-// from the last forward pass's sums (in LDS).
-__device__ __forceinline__ void advance_pose(const Ctx& c, const float* pold, float* pnew) {
-  const float om = c.P.omega, omi = c.P.omega * c.S.inv_Im;
+// Relaxation of iteration k's corrections for test m: omega over the number
+// of active constraints (at least 1), as recorded in the counts table.
+__device__ __forceinline__ float avg_factor(const Ctx& c, int k, int m) {
+  const float n = c.lds[counts_offset(c.P.K, c.P.ckpt) + k * kSims + m];
+  return c.P.omega / fmaxf(n, 1.0f);
+}
+
+// Writes pose_new = pose_old + (a W_lin, a/(I/m) W_ang), a = omega / n_active,
+// for all tests from the last forward pass's sums (in LDS), and records that
+// pass's counts as iteration k's.
+__device__ __forceinline__ void advance_pose(const Ctx& c, const float* pold, float* pnew, int k) {
+  if (c.lane < kSims) c.lds[counts_offset(c.P.K, c.P.ckpt) + k * kSims + c.lane] = c.lds[kOffCnt + c.lane];
+  wave_lds_sync();
   if (c.lane < kSims * 6) {
     const int j = c.lane % 6;
-    pnew[c.lane] = fmaf(j < 3 ? om : omi, c.lds[kOffWS + c.lane], pold[c.lane]);
+    const float a = avg_factor(c, k, c.lane / 6);
+    pnew[c.lane] = fmaf(j < 3 ? a : a * c.S.inv_Im, c.lds[kOffWS + c.lane], pold[c.lane]);
   }
   wave_lds_sync();
 }
@@ -530,6 +403,9 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
   const bool do_fwd = (kind != STEP_BWD) || A.poses == nullptr;
   const bool do_bwd = kind != STEP_FWD;
   float* gpose = A.poses ? A.poses + static_cast<size_t>(b) * kSims * nslots * 6 : nullptr;
+  float* gcnt = A.poses ? A.poses + static_cast<size_t>(A.B) * kSims * nslots * 6 + static_cast<size_t>(b) * K * kSims
+                        : nullptr;
+  const size_t cnt_off = counts_offset(K, ck);
 
   forward_kinematics(c, qb);
 
@@ -560,7 +436,7 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
       float* ts = A.trace_samples ? A.trace_samples + static_cast<size_t>(b) * kSims * K * H.Nc * 6 : nullptr;
       forward_pass<KONE>(c, k == 0, lp, ts, K, k);
       if (k == 0) lpen = lp;
-      advance_pose(c, cur, cur);
+      advance_pose(c, cur, cur, k);
       if ((k + 1) % ck == 0) {
         float* dst = pose_slot(lds, (k + 1) / ck);
         if (lane < kSims * 6) dst[lane] = cur[lane];
@@ -569,10 +445,13 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
     }
     if (A.trace_poses && lane < kSims * 6)
       A.trace_poses[((static_cast<size_t>(b) * kSims + lane / 6) * (K + 1) + K) * 6 + lane % 6] = cur[lane];
-    if (gpose && kind == STEP_FWD)
+    if (gpose && kind == STEP_FWD) {
       for (int t = lane; t < nslots * kSims * 6; t += kWave) gpose[t] = lds[kOffPose + t];
+      for (int t = lane; t < K * kSims; t += kWave) gcnt[t] = lds[cnt_off + t];
+    }
   } else {
     for (int t = lane; t < nslots * kSims * 6; t += kWave) lds[kOffPose + t] = gpose[t];
+    for (int t = lane; t < K * kSims; t += kWave) lds[cnt_off + t] = gcnt[t];
     wave_lds_sync();
   }
 
@@ -645,7 +524,7 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
         load_test_consts(c, segbuf + (j - 1) * kSims * 6);
         float lp;
         forward_pass<KONE>(c, false, lp, nullptr, K, seg * ck + j - 1);
-        advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6);
+        advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6, seg * ck + j - 1);
       }
     }
     for (int j = ck - 1; j >= 0; --j) {
@@ -654,7 +533,7 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
       // seeds of this iteration's correction sums from the running adjoint
       if (lane < kSims) {
         float* U = lds + kOffU + kUStride * lane;
-        const float om = P.omega, omi = P.omega * c.S.inv_Im;
+        const float om = avg_factor(c, k, lane), omi = om * c.S.inv_Im;
         U[19] = om * U[25]; U[20] = om * U[26]; U[21] = om * U[27];
         U[22] = omi * U[28]; U[23] = omi * U[29]; U[24] = omi * U[30];
       }
