@@ -120,10 +120,19 @@ typedef struct {
   const float* values;       /* host [n][n][n], x fastest: index (k n + j) n + i; negative inside */
   float inertia_over_mass;   /* I/m of the isotropic object; <= 0 selects 2/5 R_eq^2 with
                                 R_eq^3 = 3 V / (4 pi), V = h^3 #{vertices with value < 0} */
+  int32_t layout;            /* GRASP_LAYOUT_*: the device gather copy of the grid */
 } grasp_sdf_desc;
 
-/* Copies the grid to the device (and a corner-packed copy for gathers).
- * EINVAL when the object has no interior and inertia_over_mass <= 0. */
+enum {
+  GRASP_LAYOUT_AUTO = 0,    /* z-pairs while they take at most 48 MiB (n <= 183), else corner records */
+  GRASP_LAYOUT_CELLS = 1,   /* 32 bytes per cell, its 8 corners: one cache line per sample, 8x the grid */
+  GRASP_LAYOUT_ZPAIRS = 2   /* (phi(i,j,k), phi(i,j,k+1)) per vertex: two lines per sample, 2x the grid */
+};
+
+/* Copies the grid to the device with a gather copy in the chosen layout.
+ * Samples are identical in every layout; only speed differs.
+ * EINVAL when the object has no interior and inertia_over_mass <= 0, or for
+ * an unknown layout. */
 grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* desc, grasp_sdf_id* out);
 /* EBUSY while a live job uses the grid. */
 grasp_status grasp_unload_sdf(grasp_ctx* ctx, grasp_sdf_id sdf);

@@ -35,7 +35,10 @@ class HandDesc(C.Structure):
 
 class SdfDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("lo", C.c_float * 3), ("h", C.c_float),
-                ("values", C.POINTER(C.c_float)), ("inertia_over_mass", C.c_float)]
+                ("values", C.POINTER(C.c_float)), ("inertia_over_mass", C.c_float), ("layout", C.c_int32)]
+
+
+LAYOUT_AUTO, LAYOUT_CELLS, LAYOUT_ZPAIRS = 0, 1, 2
 
 
 class TileC(C.Structure):

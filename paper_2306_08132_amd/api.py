@@ -64,8 +64,8 @@ class Context:
     def hand(self, hand) -> "Hand":
         return Hand(self, hand)
 
-    def sdf(self, grid, inertia_over_mass: float = 0.0) -> "Sdf":
-        return Sdf(self, grid, inertia_over_mass)
+    def sdf(self, grid, inertia_over_mass: float = 0.0, layout: int = 0) -> "Sdf":
+        return Sdf(self, grid, inertia_over_mass, layout)
 
     # -- steps -----------------------------------------------------------------
     def workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
@@ -212,11 +212,11 @@ class Hand:
 class Sdf:
     """An SDF grid resident in a context (grasp_load_sdf)."""
 
-    def __init__(self, ctx: Context, grid, inertia_over_mass: float = 0.0):
+    def __init__(self, ctx: Context, grid, inertia_over_mass: float = 0.0, layout: int = 0):
         self.ctx = ctx
         vals = _f32(grid.values)
         d = SdfDesc(int(grid.n), (C.c_float * 3)(*[float(x) for x in grid.lo]), float(grid.h),
-                    vals.ctypes.data_as(C.POINTER(C.c_float)), float(inertia_over_mass))
+                    vals.ctypes.data_as(C.POINTER(C.c_float)), float(inertia_over_mass), int(layout))
         sid = C.c_uint64()
         ctx.lib.call("grasp_load_sdf", ctx.h, C.byref(d), C.byref(sid))
         self.id = sid.value

@@ -356,7 +356,13 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   }
   const size_t nc = n - 1;
   const size_t vbytes = round_up(n3 * sizeof(float), 256);
-  const size_t cbytes = nc * nc * nc * 8 * sizeof(float);
+  const size_t zbytes = n * n * nc * 2 * sizeof(float);
+  if (d->layout < GRASP_LAYOUT_AUTO || d->layout > GRASP_LAYOUT_ZPAIRS) return fail(GRASP_EINVAL, "unknown layout");
+  const int layout = d->layout == GRASP_LAYOUT_CELLS    ? kLayoutCells
+                     : d->layout == GRASP_LAYOUT_ZPAIRS ? kLayoutZPairs
+                     : zbytes <= kZPairMaxBytes         ? kLayoutZPairs
+                                                        : kLayoutCells;
+  const size_t cbytes = layout == kLayoutZPairs ? zbytes : nc * nc * nc * 8 * sizeof(float);
   DeviceGuard g(ctx->device);
   if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -365,7 +371,8 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   char* b = static_cast<char*>(blk);
   hipError_t e = hipMemcpy(b, d->values, n3 * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, reinterpret_cast<float4*>(b + vbytes), nullptr);
+    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, layout, reinterpret_cast<float4*>(b + vbytes),
+                           nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     ctx->arena.free(blk);
@@ -382,6 +389,7 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   s->view.values = reinterpret_cast<const float*>(b);
   s->view.cells = reinterpret_cast<const float4*>(b + vbytes);
   s->view.cells_bytes = static_cast<uint32_t>(cbytes);
+  s->view.layout = layout;
   s->block = blk;
   s->bytes = vbytes + cbytes;
   s->inertia_over_mass = static_cast<float>(Im);

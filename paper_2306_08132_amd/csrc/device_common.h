@@ -100,21 +100,46 @@ __device__ __forceinline__ Axis grid_axis(float r, float lo, const SdfView& S) {
   return a;
 }
 
-// Byte offset of the 32-byte corner record of the cell holding r.
-__device__ __forceinline__ int sdf_cell_byte(const SdfView& S, V3 r) {
+// Byte offset, in the gather copy of layout LAY, of the data of the cell
+// holding r: its 32-byte corner record, or the z-pair of its lower corner
+// (unsigned: at most 511^3 * 32 bytes, below 2^32).
+template <int LAY>
+__device__ __forceinline__ uint32_t sdf_cell_byte(const SdfView& S, V3 r) {
   const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
-  const int nc = S.n - 1;
-  return ((static_cast<int>(az.i) * nc + static_cast<int>(ay.i)) * nc + static_cast<int>(ax.i)) * 32;
+  const uint32_t ix = static_cast<uint32_t>(ax.i), iy = static_cast<uint32_t>(ay.i), iz = static_cast<uint32_t>(az.i);
+  if constexpr (LAY == kLayoutCells) {
+    const uint32_t nc = static_cast<uint32_t>(S.n - 1);
+    return ((iz * nc + iy) * nc + ix) * 32u;
+  } else {
+    const uint32_t n = static_cast<uint32_t>(S.n);
+    return ((iz * n + iy) * n + ix) * 8u;
+  }
 }
 
 // The cell's 8 corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
 // (32-bit buffer offsets; an offset past cells_bytes reads zeros, never faults).
-__device__ __forceinline__ void sdf_corners(const SdfView& S, int off, float4& lo4, float4& hi4) {
+// Corner records: two 16-byte loads. Z-pairs: two 8-byte loads in row (j, k)
+// and two in row (j + 1, k).
+template <int LAY>
+__device__ __forceinline__ void sdf_corners(const SdfView& S, uint32_t off, float4& lo4, float4& hi4) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(S.cells), static_cast<short>(0),
                                         static_cast<int>(S.cells_bytes), 0x00020000);
-  lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-  hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+  if constexpr (LAY == kLayoutCells) {
+    lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0));
+    hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off + 16u), 0, 0));
+  } else {
+    const uint32_t row = static_cast<uint32_t>(S.n) * 8u;
+    const float2 a0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0));
+    const float2 a1 =
+        __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off + 8u), 0, 0));
+    const float2 b0 =
+        __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off + row), 0, 0));
+    const float2 b1 =
+        __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off + row + 8u), 0, 0));
+    lo4 = make_float4(a0.x, a1.x, b0.x, b1.x);
+    hi4 = make_float4(a0.y, a1.y, b0.y, b1.y);
+  }
 }
 
 // Trilinear value and analytic gradient at r from its cell's corners.
@@ -160,7 +185,8 @@ __device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 l
 
 __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   float4 lo4, hi4;
-  sdf_corners(S, sdf_cell_byte(S, r), lo4, hi4);
+  if (S.layout == kLayoutZPairs) sdf_corners<kLayoutZPairs>(S, sdf_cell_byte<kLayoutZPairs>(S, r), lo4, hi4);
+  else sdf_corners<kLayoutCells>(S, sdf_cell_byte<kLayoutCells>(S, r), lo4, hi4);
   sample_sdf_from(S, r, lo4, hi4, s);
 }
 

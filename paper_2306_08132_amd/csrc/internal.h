@@ -48,9 +48,21 @@ struct SdfView {
   float inv_h;
   float inv_Im;            // 1 / (I/m)
   const float* values;     // [N^3], x fastest
-  const float4* cells;     // [(N-1)^3][2]: corners (000,100,010,110), (001,101,011,111)
+  // Gather copy of the grid, one of two layouts:
+  //  kLayoutCells: [(N-1)^3][2] float4 per cell, corners (000,100,010,110), (001,101,011,111)
+  //  kLayoutZPairs: [N-1][N][N] float2 per vertex, (phi(i,j,k), phi(i,j,k+1))
+  const float4* cells;
   uint32_t cells_bytes;    // size of cells (< 4 GiB: buffer loads use 32-bit offsets)
+  int layout;
 };
+
+// Layouts of the gather copy. Corner records cost one cache line per sample
+// but 8x the grid's memory; z-pairs cost two lines per sample at 2x. The
+// smaller copy wins while it stays close to L2 (measured crossover between
+// 160^3 and 192^3); grids up to kZPairMaxBytes of z-pairs use them.
+constexpr int kLayoutCells = 0;
+constexpr int kLayoutZPairs = 1;
+constexpr size_t kZPairMaxBytes = size_t(48) << 20;
 
 // Device copy of the step parameters.
 struct StepConsts {
@@ -167,7 +179,7 @@ hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int 
 
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);
-hipError_t launch_build_cells(const float* values, int n, float4* cells, hipStream_t stream);
+hipError_t launch_build_cells(const float* values, int n, int layout, float4* cells, hipStream_t stream);
 hipError_t launch_sample_points(const SdfView& s, int n, const float* r, float* out4, float* hess9,
                                 hipStream_t stream);
 

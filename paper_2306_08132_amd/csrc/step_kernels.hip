@@ -138,7 +138,7 @@ __device__ __forceinline__ const float* test_consts(const Ctx& c, const LaneTest
   return c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
 }
 
-template <bool ROT, bool TRACE>
+template <bool ROT, bool TRACE, int LAY>
 __device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
@@ -163,13 +163,13 @@ __device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trac
     float4 lo[2], hi[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
+      sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
+        sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
                     hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
@@ -209,11 +209,11 @@ __device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trac
 // One forward projection iteration over all contacts: the 7 x 6 correction
 // sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
 // on the rest test of the first iteration, the penetration energy.
-template <bool KONE>
+template <bool KONE, int LAY>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
-  if (trace_s) forward_lanes<!KONE, true>(c, first, lpen, trace_s, K, k);
-  else forward_lanes<!KONE, false>(c, first, lpen, nullptr, K, k);
+  if (trace_s) forward_lanes<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
+  else forward_lanes<!KONE, false, LAY>(c, first, lpen, nullptr, K, k);
   wave_lds_sync();
 }
 
@@ -233,7 +233,7 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
 // sums of the current link, flushed (wave reductions) where the link changes;
 // with pose_adj the lanes also sum the adjoint of their test's pose (-sum
 // a_bar, sum theta_bar), which is added to the running pose adjoint.
-template <bool ROT>
+template <bool ROT, int LAY>
 __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
@@ -264,13 +264,13 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
     float4 lo[2], hi[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
+      sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners(S, sdf_cell_byte(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
+        sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
                     hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
@@ -348,9 +348,9 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
   wave_lds_sync();
 }
 
-template <bool KONE>
+template <bool KONE, int LAY>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
-  backward_lanes<!KONE>(c, first, pen_seed, pose_adj);
+  backward_lanes<!KONE, LAY>(c, first, pen_seed, pose_adj);
 }
 
 __device__ __forceinline__ float* pose_slot(float* lds, int s) { return lds + kOffPose + s * kSims * 6; }
@@ -389,8 +389,8 @@ __device__ __forceinline__ void init_pose(const Ctx& c, float* p0) {
 // ---------------------------------------------------------------------------
 // the per-candidate step
 // ---------------------------------------------------------------------------
-template <bool KONE>
-__device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
+template <bool KONE, int LAY>
+__device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
   const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id()};
@@ -434,7 +434,7 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
       if constexpr (!KONE) load_test_consts(c, cur);
       float lp;
       float* ts = A.trace_samples ? A.trace_samples + static_cast<size_t>(b) * kSims * K * H.Nc * 6 : nullptr;
-      forward_pass<KONE>(c, k == 0, lp, ts, K, k);
+      forward_pass<KONE, LAY>(c, k == 0, lp, ts, K, k);
       if (k == 0) lpen = lp;
       advance_pose(c, cur, cur, k);
       if ((k + 1) % ck == 0) {
@@ -523,7 +523,7 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
       for (int j = 1; j < ck; ++j) {
         load_test_consts(c, segbuf + (j - 1) * kSims * 6);
         float lp;
-        forward_pass<KONE>(c, false, lp, nullptr, K, seg * ck + j - 1);
+        forward_pass<KONE, LAY>(c, false, lp, nullptr, K, seg * ck + j - 1);
         advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6, seg * ck + j - 1);
       }
     }
@@ -538,8 +538,8 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
         U[22] = omi * U[28]; U[23] = omi * U[29]; U[24] = omi * U[30];
       }
       wave_lds_sync();
-      if constexpr (KONE) backward_pass<KONE>(c, true, pen_seed, false);
-      else backward_pass<KONE>(c, k == 0, pen_seed, k > 0);
+      if constexpr (KONE) backward_pass<KONE, LAY>(c, true, pen_seed, false);
+      else backward_pass<KONE, LAY>(c, k == 0, pen_seed, k > 0);
     }
   }
 
@@ -579,6 +579,14 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
       A.q_out[o] = qj - ad.lr * (mm / ad.c1) / (sqrtf(vv / ad.c2) + ad.eps);
     }
   }
+}
+
+// The gather layout of the candidate's grid selects the code path (uniform
+// over the wavefront).
+template <bool KONE>
+__device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
+  if (A.sdf.layout == kLayoutZPairs) candidate_step_lay<KONE, kLayoutZPairs>(A, b, kind, adam, lds);
+  else candidate_step_lay<KONE, kLayoutCells>(A, b, kind, adam, lds);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block i to XCD i mod
@@ -744,6 +752,15 @@ __global__ void k_build_cells(const float* __restrict__ vals, int n, float4* __r
   cells[2 * id + 1] = make_float4(V(0, 0, 1), V(1, 0, 1), V(0, 1, 1), V(1, 1, 1));
 }
 
+// z-pairs: P[k][j][i] = (phi(i,j,k), phi(i,j,k+1)) for k < n - 1
+__global__ void k_build_zpairs(const float* __restrict__ vals, int n, float2* __restrict__ P) {
+  const long long plane = static_cast<long long>(n) * n;
+  const long long total = plane * (n - 1);
+  const long long id = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  P[id] = make_float2(vals[id], vals[id + plane]);
+}
+
 __global__ void k_sample_points(SdfView S, int n, const float* __restrict__ r, float* __restrict__ out4,
                                 float* __restrict__ hess9) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -847,10 +864,16 @@ hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, Adam
   return hipGetLastError();
 }
 
-hipError_t launch_build_cells(const float* values, int n, float4* cells, hipStream_t stream) {
-  const long long total = static_cast<long long>(n - 1) * (n - 1) * (n - 1);
-  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-  hipLaunchKernelGGL(k_build_cells, dim3(blocks), dim3(256), 0, stream, values, n, cells);
+hipError_t launch_build_cells(const float* values, int n, int layout, float4* cells, hipStream_t stream) {
+  if (layout == kLayoutZPairs) {
+    const long long total = static_cast<long long>(n) * n * (n - 1);
+    hipLaunchKernelGGL(k_build_zpairs, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, values,
+                       n, reinterpret_cast<float2*>(cells));
+  } else {
+    const long long total = static_cast<long long>(n - 1) * (n - 1) * (n - 1);
+    hipLaunchKernelGGL(k_build_cells, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, values,
+                       n, cells);
+  }
   return hipGetLastError();
 }
 

@@ -70,16 +70,20 @@ def test_contact_links_exact(ctx, fj):
     assert np.array_equal(h.contact_links(), hand.contact_link)
 
 
+LAYOUTS = {"cells": 1, "zpairs": 2}
+
+
+@pytest.mark.parametrize("layout", ["cells", "zpairs"])
 @pytest.mark.parametrize("which", ["sphere64", "ellipsoids48", "mixed33"])
-def test_sdf_sampler_parity(ctx, which):
-    say("sampler", which)
+def test_sdf_sampler_parity(ctx, which, layout):
+    say("sampler", which, layout)
     if which == "sphere64":
         g = S.make_grid(S.make_object("sphere", seed=0), 64)
     elif which == "ellipsoids48":
         g = S.make_grid(S.make_object("ellipsoids", seed=2), 48)
     else:
         g = S.make_grid(S.make_object("mixed", seed=3, n_prims=5), 33)
-    sd = ctx.sdf(g)
+    sd = ctx.sdf(g, layout=LAYOUTS[layout])
     r = S.random_points(g, 20000, seed=7).astype(np.float32)
     out, H = ctx.debug_sdf_sample(sd, dev(r), hess=True)
     torch.cuda.synchronize()
@@ -135,8 +139,8 @@ def test_fk_and_trace_parity(ctx, tiny):
         assert np.all(err[:, :3] <= 1e-5 * lin + 1e-9) and np.all(err[:, 3:] <= 1e-5 * ang + 1e-9)
 
 
-def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05):
-    h, sd = ctx.hand(hand), ctx.sdf(grid)
+def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05, layout=0):
+    h, sd = ctx.hand(hand), ctx.sdf(grid, layout=layout)
     B = q.shape[0]
     qd = dev(q)
     loss = torch.empty(B, device=DEV)
@@ -382,6 +386,33 @@ def test_locality_order_changes_nothing(ctx, tiny):
         parts = [np.concatenate([o[k] for o in outs[1:]]) for k in range(3)]
         say("K", K, "ordered vs sliced max |diff| loss", float(np.nanmax(np.abs(whole[0] - parts[0]))))
         assert all(np.array_equal(a, b) for a, b in zip(whole, parts))
+
+
+def test_gather_layouts_bit_identical(ctx, tiny):
+    """Corner records and z-pairs hold the same corner values: every step
+    (K = 1 and K = 2, fused and split) and every sample agree bit for bit;
+    the corner-record path also meets the oracle on its own."""
+    hand, grid, q = tiny
+    h = ctx.hand(hand)
+    sds = {name: ctx.sdf(grid, layout=code) for name, code in LAYOUTS.items()}
+    r = dev(S.random_points(grid, 4096, seed=9).astype(np.float32))
+    samples = {name: ctx.debug_sdf_sample(sd, r, hess=True) for name, sd in sds.items()}
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(samples["cells"], samples["zpairs"]))
+    for K in (1, 2):
+        sp, _ = prm_pair(r_dil=0.004, K=K)
+        outs = {}
+        for name, sd in sds.items():
+            qd = dev(q)
+            m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+            loss = torch.empty(q.shape[0], device=DEV)
+            dq = torch.empty_like(qd)
+            ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+            outs[name] = (loss.cpu().numpy(), dq.cpu().numpy(), qd.cpu().numpy())
+        say("layouts K", K, "max |loss diff|", float(np.abs(outs["cells"][0] - outs["zpairs"][0]).max()))
+        assert all(np.array_equal(a, b) for a, b in zip(outs["cells"], outs["zpairs"]))
+    sp, op = prm_pair(r_dil=0.005)
+    compare_step(ctx, hand, grid, q, sp, op, "tiny r=5mm, corner records", layout=LAYOUTS["cells"])
 
 
 def test_plain_form_parity(ctx, tiny):
