@@ -8,7 +8,11 @@ with 2048 contacts, a 128^3 SDF of a union of ellipsoids, 4096 candidates,
 synthetic inputs already resident in HBM.
 
 Prints one JSON line: contact-evaluations per second (forward + backward),
-the roofline of the step kernel, and the FP64 oracle timed on the host.
+the roofline of the step kernel and the FP64 oracle timed on the host, with
+the other workloads beside them: the plain per-job form on the same
+candidates, a Poisson stream of jobs through the serving loop, 16 uneven
+jobs in one batched launch per step, and K = 16 projection iterations on
+65536 candidates (256^3 grid).
 """
 from __future__ import annotations
 
@@ -140,10 +144,11 @@ def batched_run(ctx, S, args):
     import numpy as np
     import torch
     from paper_2306_08132_amd.api import Batch, BatchJob, StepParams
+    print("bench: batched jobs", file=sys.stderr, flush=True)
     rng = np.random.default_rng(2)
     hand = S.make_hand(5, 4, 4096, seed=2)
     h = ctx.hand(hand)
-    jobs, evals = [], 0
+    jobs, evals, abytes = [], 0, 0
     for k in range(16):
         n = int(rng.choice([64, 96, 128, 192, 256]))
         grid = S.make_grid(S.make_object("mixed", seed=400 + k, n_range=(3, 8)), n, device="cuda:0")
@@ -151,6 +156,7 @@ def batched_run(ctx, S, args):
         q = S.make_candidates(hand, B, seed=500 + k, shell_radius=grid.bound_radius + 0.06)
         jobs.append((ctx.sdf(grid), torch.tensor(q, dtype=torch.float32, device="cuda:0")))
         evals += B * hand.n_contacts * M_SIMS
+        abytes += algorithmic_bytes(B, hand.n_contacts, 1, hand.n_dof, n)
     cap = sum(q.shape[0] for _, q in jobs)
     stream = torch.cuda.Stream()
     bj = [BatchJob(h, sd, StepParams(), q.clone(), T=300) for sd, q in jobs]
@@ -178,7 +184,8 @@ def batched_run(ctx, S, args):
     b.close()
     return {"jobs": 16, "candidates": cap, "contact_evals_per_step": evals, "ms_per_step": tb * 1e3,
             "contact_evals_per_s": evals / tb, "per_job_launches_ms_per_step": ts * 1e3,
-            "batched_over_per_job": ts / tb}
+            "batched_over_per_job": ts / tb, "algorithmic_bytes_per_step": abytes,
+            "roofline_frac": abytes / tb / (HBM_PEAK_GBS * 1e9)}
 
 
 def large_run(ctx, S, args):
@@ -186,8 +193,10 @@ def large_run(ctx, S, args):
     grid; pose checkpoints every 4 iterations with replay in the backward."""
     import torch
     from paper_2306_08132_amd.api import StepParams
+    print("bench: K = 16 workload", file=sys.stderr, flush=True)
     hand, grid, q0 = S.config_workload("large", device="cuda:0")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
+    abytes = algorithmic_bytes(q0.shape[0], hand.n_contacts, 16, hand.n_dof, grid.n)
     q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
     m, v = torch.zeros_like(q), torch.zeros_like(q)
     out = {}
@@ -201,8 +210,11 @@ def large_run(ctx, S, args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 2
         evals = q.shape[0] * hand.n_contacts * M_SIMS * 16
-        out[f"ckpt{ck}"] = {"s_per_iteration": dt, "contact_evals_per_s": evals / dt}
+        out[f"ckpt{ck}"] = {"s_per_iteration": dt, "contact_evals_per_s": evals / dt,
+                            "roofline_frac": abytes / dt / (HBM_PEAK_GBS * 1e9)}
+        print(f"bench: K = 16, checkpoints every {ck}: {dt:.3f} s per step", file=sys.stderr, flush=True)
     out["contact_evals_per_iteration"] = q.shape[0] * hand.n_contacts * M_SIMS * 16
+    out["algorithmic_bytes_per_iteration"] = abytes
     return out
 
 
@@ -217,8 +229,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-steps", type=int, default=60, help="optimizer steps per served job")
-    ap.add_argument("--batched", action="store_true", help="also run 16 uneven jobs in one launch per step")
-    ap.add_argument("--large", action="store_true", help="also run the K = 16 workload (65536 candidates)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
+    ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
                          "the reference that scales HBM counters")
@@ -315,8 +327,8 @@ def main():
     if not args.no_serving:
         print("bench: serving stream", file=sys.stderr, flush=True)
         serving = serving_run(ctx, S, n_jobs=args.serve_jobs, rate=args.serve_rate, steps=args.serve_steps)
-    batched = batched_run(ctx, S, args) if args.batched else None
-    large = large_run(ctx, S, args) if args.large else None
+    batched = None if args.no_batched else batched_run(ctx, S, args)
+    large = None if args.no_large else large_run(ctx, S, args)
 
     cpu = None
     if not args.no_cpu:
