@@ -50,7 +50,7 @@ grasp_status batch_fill(grasp_batch* bt, const grasp_batch_job* jobs, int32_t n,
   std::stable_sort(order.begin(), order.end());
   BatchHeader* hdr = reinterpret_cast<BatchHeader*>(bt->host + (group_kone ? 0 : bt->half));
   BatchJob* tab = reinterpret_cast<BatchJob*>(hdr + 1);
-  int total = 0, lds = 0;
+  int total = 0, total8 = 0, lds = 0;
   for (size_t k = 0; k < order.size(); ++k) {
     const int i = order[k].second;
     const grasp_batch_job& j = jobs[i];
@@ -71,11 +71,15 @@ grasp_status batch_fill(grasp_batch* bt, const grasp_batch_job* jobs, int32_t n,
     e.args.nonfinite = bt->flags_dev + i;
     e.args.order = j.B >= kOrderMinB ? bt->order_dev + total : nullptr;
     e.begin = total;
+    e.slice = (j.B + 7) / 8;
+    e.begin8 = total8;
     total += j.B;
+    total8 += e.slice;
     lds = std::max<int>(lds, static_cast<int>(wave_lds_floats(e.args.prm.K, e.args.prm.ckpt)));
   }
   hdr->n_jobs = static_cast<int>(order.size());
   hdr->total = total;
+  hdr->total8 = total8;
   *out_jobs = static_cast<int>(order.size());
   *out_total = total;
   *out_lds = lds;
@@ -185,7 +189,9 @@ grasp_status grasp_batch_step(grasp_batch* bt, grasp_batch_job* jobs, int32_t n,
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(bt->dev + off);
     const BatchJob* tab = reinterpret_cast<const BatchJob*>(hdr + 1);
     const TileCfg tc = bt->tile;
-    const int blocks = (bt->capacity + tc.wpb - 1) / tc.wpb;
+    // every XCD's list holds at most capacity / 8 + max_jobs candidates
+    const int per_xcd = (bt->capacity + 7) / 8 + bt->max_jobs;
+    const int blocks = 8 * ((per_xcd + tc.wpb - 1) / tc.wpb);
     if (!bt->use_graph || s == nullptr) {
       e = launch_order_batch(hdr, tab, bt->max_jobs, s);
       if (e == hipSuccess) e = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);

@@ -160,17 +160,20 @@ hipError_t launch_plain_step(const HandView& H, const SdfView& S, const StepCons
 // its B candidates; items [begin, begin + B) of the shared work range.
 struct BatchJob {
   StepArgs args;
-  int begin;
-  int pad[3];
+  int begin;   // first item of the job in the table (sum of the earlier jobs' B)
+  int slice;   // ceil(B / 8): the candidates of the job each XCD takes
+  int begin8;  // sum of the earlier jobs' slices: the job's place in every XCD's list
+  int pad;
 };
 struct BatchHeader {
   int n_jobs;
-  int total;  // sum of B over the table
-  int pad[2];
+  int total;   // sum of B over the table
+  int total8;  // sum of the slices
+  int pad;
 };
-// Launches `blocks` workgroups over the table's items (waves past the total
-// exit); kone selects the one-iteration kernel (every job in the table must
-// agree on it).
+// Launches `blocks` workgroups (a multiple of 8) over the table; XCD x takes
+// candidates [x slice, (x + 1) slice) of every job. Waves past the table exit;
+// kone selects the one-iteration kernel (every job in the table must agree on it).
 hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
                         int lds_floats, hipStream_t stream);
 

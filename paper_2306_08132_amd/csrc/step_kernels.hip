@@ -692,36 +692,35 @@ k_step(StepArgs A, int kind, int adam) {
   candidate_step<KONE>(A, b, kind, adam != 0, lds);
 }
 
-// Batched step: one launch covers every job of a device table. Wave w of the
-// grid takes work item w; items [begin, begin + B) of a job are its
-// candidates, each one fused forward, backward and Adam computed exactly as
-// the single-job launch computes it. Jobs are ordered most expensive first
-// so the dispatcher starts the long candidates early. The header and table
-// are read from device memory, so a graph captured for a grid of `capacity`
-// waves serves any job set up to that many candidates; waves past the
-// table's total exit at once.
+// Batched step: one launch covers every job of a device table, each
+// candidate's fused forward, backward and Adam computed exactly as the
+// single-job launch computes it. Workgroups go to the 8 XCDs round-robin;
+// XCD x takes the x-th eighth of every job (in the job's locality order), so
+// every XCD carries the same share of each job's work and sees one compact
+// part of each job's grid. The header and table are read from device memory,
+// so a graph captured for a grid of the batch's capacity serves any job set
+// up to that many candidates; waves past the table exit at once.
 template <bool KONE, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(OCC, 8)))
 k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, int lds_per_wave) {
   extern __shared__ float smem[];
   const int wpb = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
+  const int x = static_cast<int>(blockIdx.x) & 7;
   // wave-uniform by construction; readfirstlane lets the compiler see it
-  // the grid is sized for the batch capacity: spread only the blocks that hold items
-  const int total = hdr->total;
-  const int item = __builtin_amdgcn_readfirstlane(xcd_block((total + wpb - 1) / wpb) * wpb + w);
-  const int n_jobs = hdr->n_jobs;
-  if (item >= total) return;
-  int lo = 0, hi = n_jobs - 1;  // last job with begin <= item
+  const int t = __builtin_amdgcn_readfirstlane((static_cast<int>(blockIdx.x) >> 3) * wpb + w);
+  if (t >= hdr->total8) return;
+  int lo = 0, hi = hdr->n_jobs - 1;  // last job with begin8 <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].begin <= item) lo = mid;
+    if (jobs[mid].begin8 <= t) lo = mid;
     else hi = mid - 1;
   }
   lo = __builtin_amdgcn_readfirstlane(lo);
-  float* lds = smem + static_cast<size_t>(w) * lds_per_wave;
+  const int local = x * jobs[lo].slice + (t - jobs[lo].begin8);
   const StepArgs A = jobs[lo].args;  // one uniform copy, like a kernel argument
-  const int local = item - jobs[lo].begin;
+  if (local >= A.B) return;
+  float* lds = smem + static_cast<size_t>(w) * lds_per_wave;
   const int b = A.order ? __builtin_amdgcn_readfirstlane(A.order[local]) : local;
   candidate_step<KONE>(A, b, STEP_FUSED, true, lds);
 }
