@@ -47,3 +47,40 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     p = lib.StepParamsC()
     L.grasp_default_params(C.byref(p))
     assert (p.dt, p.K, p.ckpt_every, p.alpha_leak) == (C.c_float(1e-3).value, 1, 1, C.c_float(0.1).value)
+
+
+def _c_layout(structs):
+    """sizeof and offsetof of each struct member as the C compiler lays them
+    out, from a small program built against include/grasp.h."""
+    import subprocess
+    import tempfile
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "grasp.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    return got
+
+
+def test_binding_structs_match_the_c_layout(lib):
+    """Every ctypes struct of the binding has the C header's size and field
+    offsets (a field added on one side only would shift the others)."""
+    pairs = [("grasp_hand_desc", lib.HandDesc), ("grasp_sdf_desc", lib.SdfDesc), ("grasp_step_params", lib.StepParamsC),
+             ("grasp_tile", lib.TileC), ("grasp_batch_job", lib.BatchJobC), ("grasp_job_desc", lib.JobDescC),
+             ("grasp_job_result", lib.JobResultC), ("grasp_serve_stats", lib.ServeStatsC)]
+    structs = [(cname, [f for f, *_ in py._fields_]) for cname, py in pairs]
+    got = _c_layout(structs)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, *_ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
