@@ -363,16 +363,20 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
                      : zbytes <= kZPairMaxBytes         ? kLayoutZPairs
                                                         : kLayoutCells;
   const size_t cbytes = layout == kLayoutZPairs ? zbytes : nc * nc * nc * 8 * sizeof(float);
+  const int nb = static_cast<int>((nc + kBlockCells - 1) / kBlockCells);
+  const size_t bbytes = round_up(static_cast<size_t>(nb) * nb * nb * sizeof(float), 256);
   DeviceGuard g(ctx->device);
   if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  void* blk = ctx->arena.alloc(vbytes + cbytes);
+  void* blk = ctx->arena.alloc(vbytes + bbytes + cbytes);
   if (!blk) return fail(GRASP_ENOMEM, "arena full (SDF grid)");
   char* b = static_cast<char*>(blk);
   hipError_t e = hipMemcpy(b, d->values, n3 * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, layout, reinterpret_cast<float4*>(b + vbytes),
-                           nullptr);
+    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, layout,
+                           reinterpret_cast<float4*>(b + vbytes + bbytes), nullptr);
+  if (e == hipSuccess)
+    e = launch_build_bmin(reinterpret_cast<const float*>(b), d->n, reinterpret_cast<float*>(b + vbytes), nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     ctx->arena.free(blk);
@@ -387,11 +391,13 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   s->view.inv_h = 1.0f / d->h;
   s->view.inv_Im = static_cast<float>(1.0 / Im);
   s->view.values = reinterpret_cast<const float*>(b);
-  s->view.cells = reinterpret_cast<const float4*>(b + vbytes);
+  s->view.cells = reinterpret_cast<const float4*>(b + vbytes + bbytes);
   s->view.cells_bytes = static_cast<uint32_t>(cbytes);
   s->view.layout = layout;
+  s->view.bmin = reinterpret_cast<const float*>(b + vbytes);
+  s->view.nb = nb;
   s->block = blk;
-  s->bytes = vbytes + cbytes;
+  s->bytes = vbytes + bbytes + cbytes;
   s->inertia_over_mass = static_cast<float>(Im);
   const uint64_t id = ctx->next_id++;
   ctx->sdfs[id] = std::move(s);

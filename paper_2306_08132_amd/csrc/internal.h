@@ -54,7 +54,14 @@ struct SdfView {
   const float4* cells;
   uint32_t cells_bytes;    // size of cells (< 4 GiB: buffer loads use 32-bit offsets)
   int layout;
+  // Lower bounds for culling: the minimum over the corners of every block of
+  // kBlockCells^3 cells, [nb][nb][nb] with nb = ceil((N-1) / kBlockCells).
+  const float* bmin;
+  int nb;
 };
+
+constexpr int kBlockShift = 2;
+constexpr int kBlockCells = 1 << kBlockShift;
 
 // Layouts of the gather copy. Corner records cost one cache line per sample
 // but 8x the grid's memory; z-pairs cost two lines per sample at 2x. The
@@ -183,6 +190,7 @@ hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int 
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);
 hipError_t launch_build_cells(const float* values, int n, int layout, float4* cells, hipStream_t stream);
+hipError_t launch_build_bmin(const float* values, int n, float* bmin, hipStream_t stream);
 hipError_t launch_sample_points(const SdfView& s, int n, const float* r, float* out4, float* hess9,
                                 hipStream_t stream);
 

@@ -138,8 +138,23 @@ __device__ __forceinline__ const float* test_consts(const Ctx& c, const LaneTest
   return c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
 }
 
+// Whether the sample at grid-frame point r is provably clear of the dilated
+// surface (d > 0, with a margin far above the FP32 rounding of the sample):
+// the trilinear value is at least the minimum of its block's corners, and
+// outside the box the distance to the box adds on.
+__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float rd) {
+  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
+  const int bx = static_cast<int>(ax.i) >> kBlockShift;
+  const int by = static_cast<int>(ay.i) >> kBlockShift;
+  const int bz = static_cast<int>(az.i) >> kBlockShift;
+  const float bm = S.bmin[(bz * S.nb + by) * S.nb + bx];
+  const float ex = (ax.u - ax.b) * S.h, ey = (ay.u - ay.b) * S.h, ez = (az.u - az.b) * S.h;
+  const float e = __builtin_sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+  return fmaf(0.999999f, e, bm - rd) > 1e-6f;
+}
+
 template <bool ROT, bool TRACE, int LAY>
-__device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
+__device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
@@ -206,14 +221,93 @@ __device__ void forward_lanes(const Ctx& c, bool first, float& lpen, float* trac
   lpen = wave_sum(lp);
 }
 
+// The untraced forward pass: a group of samples whose every lane is provably
+// clear of the surface contributes exactly nothing (lambda = 0, no active
+// constraint, no penetration energy), so its gathers are skipped. The live
+// groups of a chunk are found first from the block minima; the corners of
+// the next live group are requested before the current one is blended. The
+// sums are bit-identical to the full pass's.
+template <bool ROT, int LAY>
+__device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
+  const HandView& H = c.H;
+  const SdfView& S = c.S;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
+  const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
+  const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
+  float R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  V3 x = v3(0.0f, 0.0f, 0.0f);
+  if constexpr (ROT) {
+    const float* U = test_consts(c, lt);
+    x = v3(U[0], U[1], U[2]);
+    for (int j = 0; j < 9; ++j) R[j] = U[3 + j];
+  }
+  auto frame_of = [&](float4 P4) {
+    const V3 p = v3(P4.x, P4.y, P4.z);
+    const V3 a = ROT ? p - x : p + lt.off;
+    return ROT ? mul_t(R, a) : a;
+  };
+  float W[6] = {0, 0, 0, 0, 0, 0};
+  float lp = 0.0f, na = 0.0f;
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    stage_chunk(c, ch);
+    uint32_t live = 0;
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+      const float4 P4 = P[kGroup * g + lt.sub];
+      const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
+      const bool needed = valid && !provably_clear(S, frame_of(P4), rd);
+      if (__builtin_amdgcn_ballot_w64(needed) != 0) live |= 1u << g;
+    }
+    live = __builtin_amdgcn_readfirstlane(live);
+    if (live == 0) continue;
+    int g = __builtin_ctz(live);
+    float4 lo, hi, lo_n, hi_n;
+    sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_of(P[kGroup * g + lt.sub])), lo, hi);
+    for (;;) {
+      live &= live - 1;
+      const int gn = live ? __builtin_ctz(live) : -1;
+      if (gn >= 0) sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_of(P[kGroup * gn + lt.sub])), lo_n, hi_n);
+      const float4 P4 = P[kGroup * g + lt.sub];
+      const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
+      const V3 p = v3(P4.x, P4.y, P4.z);
+      const V3 a = ROT ? p - x : p + lt.off;
+      Sample s;
+      sample_sdf_from(S, ROT ? mul_t(R, a) : a, lo, hi, s);
+      const V3 gn_ = ROT ? mul(R, s.n) : s.n;
+      const float d = s.phi - rd;
+      const bool act = valid && d < 0.0f;
+      lp = (first && act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      const V3 u = cross(a, gn_);
+      const float w = fmaf(dot(u, u), inv_Im, dot(gn_, gn_));
+      const bool on = act && w > wmin;
+      const float lam = on ? d * rcp(w) : 0.0f;
+      na += on ? 1.0f : 0.0f;
+      W[0] = fmaf(lam, gn_.x, W[0]);
+      W[1] = fmaf(lam, gn_.y, W[1]);
+      W[2] = fmaf(lam, gn_.z, W[2]);
+      W[3] = fmaf(lam, u.x, W[3]);
+      W[4] = fmaf(lam, u.y, W[4]);
+      W[5] = fmaf(lam, u.z, W[5]);
+      if (gn < 0) break;
+      g = gn;
+      lo = lo_n;
+      hi = hi_n;
+    }
+  }
+  test_sums<6>(c, W, c.lds + kOffWS, 6, false);
+  test_sums<1>(c, &na, c.lds + kOffCnt, 1, false);
+  lpen = wave_sum(lp);
+}
+
 // One forward projection iteration over all contacts: the 7 x 6 correction
 // sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
 // on the rest test of the first iteration, the penetration energy.
 template <bool KONE, int LAY>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
-  if (trace_s) forward_lanes<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
-  else forward_lanes<!KONE, false, LAY>(c, first, lpen, nullptr, K, k);
+  if (trace_s) forward_full<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
+  else forward_culled<!KONE, LAY>(c, first, lpen);
   wave_lds_sync();
 }
 
@@ -760,6 +854,22 @@ __global__ void k_build_zpairs(const float* __restrict__ vals, int n, float2* __
   P[id] = make_float2(vals[id], vals[id + plane]);
 }
 
+// Minimum over the corners of each block of kBlockCells^3 cells (vertices
+// [b B, b B + B] per axis, clipped to the grid): a lower bound of the
+// trilinear value anywhere in the block.
+__global__ void k_build_bmin(const float* __restrict__ vals, int n, float* __restrict__ bmin) {
+  const int nb = (n - 1 + kBlockCells - 1) / kBlockCells;
+  const int id = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= nb * nb * nb) return;
+  const int bx = id % nb, by = (id / nb) % nb, bz = id / (nb * nb);
+  float m = INFINITY;
+  for (int k = bz * kBlockCells; k <= min(bz * kBlockCells + kBlockCells, n - 1); ++k)
+    for (int j = by * kBlockCells; j <= min(by * kBlockCells + kBlockCells, n - 1); ++j)
+      for (int i = bx * kBlockCells; i <= min(bx * kBlockCells + kBlockCells, n - 1); ++i)
+        m = fminf(m, vals[(static_cast<long long>(k) * n + j) * n + i]);
+  bmin[id] = m;
+}
+
 __global__ void k_sample_points(SdfView S, int n, const float* __restrict__ r, float* __restrict__ out4,
                                 float* __restrict__ hess9) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -873,6 +983,13 @@ hipError_t launch_build_cells(const float* values, int n, int layout, float4* ce
     hipLaunchKernelGGL(k_build_cells, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, values,
                        n, cells);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_bmin(const float* values, int n, float* bmin, hipStream_t stream) {
+  const int nb = (n - 1 + kBlockCells - 1) / kBlockCells;
+  const int total = nb * nb * nb;
+  hipLaunchKernelGGL(k_build_bmin, dim3((total + 255) / 256), dim3(256), 0, stream, values, n, bmin);
   return hipGetLastError();
 }
 
