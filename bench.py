@@ -31,12 +31,24 @@ HBM_PEAK_GBS = 8000.0
 M_SIMS = 7
 
 
-def algorithmic_bytes(B, Nc, K, n_dof, n):
-    """Bytes one step must move at least once: 8 FP32 corners per contact
-    evaluation in the forward and again in the backward, each contact's
-    link-local coordinates per candidate (forward and backward), q/m/v read
-    and written plus dq, and the grid once."""
-    return 64 * B * Nc * M_SIMS * K + 24 * B * Nc + 28 * B * n_dof + 4 * n ** 3
+def algorithmic_bytes(B, Nc, K, n_dof, n, live):
+    """Bytes one step must move at least once. Per contact evaluation: the 8
+    FP32 corners (32 B) in the backward; in the forward the same 32 B only for
+    samples in groups the block bound cannot clear (fraction `live` of the
+    groups), plus the 4-byte bound itself, read once per contact when K = 1
+    (the seven tests share it) and once per evaluation otherwise. Per
+    candidate: each contact's link-local coordinates (forward and backward),
+    q/m/v read and written plus dq. The grid and its block table once."""
+    evals = B * Nc * M_SIMS * K
+    bound = 4 * B * Nc if K == 1 else 4 * evals
+    nb = -(-(n - 1) // 4)
+    return int(32 * evals * (1.0 + live) + bound + 24 * B * Nc + 28 * B * n_dof + 4 * n ** 3 + 4 * nb ** 3)
+
+
+def live_fraction(ctx, h, sd, prm, q):
+    """Fraction of the sample groups the forward passes of one step gather."""
+    live, total = ctx.debug_forward_groups(h, sd, prm, q)
+    return live / total if total else 0.0
 
 
 def kernel_source_hash():
@@ -154,9 +166,12 @@ def batched_run(ctx, S, args):
         grid = S.make_grid(S.make_object("mixed", seed=400 + k, n_range=(3, 8)), n, device="cuda:0")
         B = int(rng.integers(256, 4097))
         q = S.make_candidates(hand, B, seed=500 + k, shell_radius=grid.bound_radius + 0.06)
-        jobs.append((ctx.sdf(grid), torch.tensor(q, dtype=torch.float32, device="cuda:0")))
+        sd = ctx.sdf(grid)
+        qt = torch.tensor(q, dtype=torch.float32, device="cuda:0")
+        jobs.append((sd, qt))
         evals += B * hand.n_contacts * M_SIMS
-        abytes += algorithmic_bytes(B, hand.n_contacts, 1, hand.n_dof, n)
+        abytes += algorithmic_bytes(B, hand.n_contacts, 1, hand.n_dof, n,
+                                    live_fraction(ctx, h, sd, StepParams(r_dil=0.01), qt))
     cap = sum(q.shape[0] for _, q in jobs)
     stream = torch.cuda.Stream()
     bj = [BatchJob(h, sd, StepParams(), q.clone(), T=300) for sd, q in jobs]
@@ -196,10 +211,11 @@ def large_run(ctx, S, args):
     print("bench: K = 16 workload", file=sys.stderr, flush=True)
     hand, grid, q0 = S.config_workload("large", device="cuda:0")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
-    abytes = algorithmic_bytes(q0.shape[0], hand.n_contacts, 16, hand.n_dof, grid.n)
     q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
     m, v = torch.zeros_like(q), torch.zeros_like(q)
-    out = {}
+    live = live_fraction(ctx, h, sd, StepParams(K=16, ckpt_every=1, r_dil=0.01), q)
+    abytes = algorithmic_bytes(q0.shape[0], hand.n_contacts, 16, hand.n_dof, grid.n, live)
+    out = {"forward_live_fraction": live}
     for ck in (4, 1):
         prm = StepParams(K=16, ckpt_every=ck, r_dil=0.01)
         ctx.step_fused(h, sd, prm, q, m, v, 1)
@@ -279,6 +295,7 @@ def main():
     for t in range(args.warmup):
         step(t)
     torch.cuda.synchronize()
+    live = live_fraction(ctx, h, sd, StepParams(K=K, r_dil=r0 * (1.0 - args.warmup / (T_sched - 1))), q)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -292,7 +309,7 @@ def main():
     avg_ms = float(np.mean(kern_ms))
     evals = B * Nc * M_SIMS * K
     value = evals * args.steps / wall
-    abytes = algorithmic_bytes(B, Nc, K, nd, grid.n)
+    abytes = algorithmic_bytes(B, Nc, K, nd, grid.n, live)
     achieved = abytes / (avg_ms * 1e-3) / 1e9
     workload = "diff-step"
     traffic = measured_traffic("k_step", workload)
@@ -356,7 +373,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step<K=1> (fused)", "avg_launch_ms": avg_ms,
                      "tile": {"waves_per_block": tile[0], "min_waves_per_simd": tile[1]},
-                     "algorithmic_bytes_per_launch": abytes},
+                     "algorithmic_bytes_per_launch": abytes, "forward_live_fraction": live},
         "plain": plain,
         "serving": serving,
         "batched": batched,

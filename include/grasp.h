@@ -353,6 +353,16 @@ grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id 
                                const grasp_step_params* p, int32_t B, const float* q, float* p_world,
                                float* poses, float* samples, void* hip_stream);
 
+/* Runs one fused step without Adam (q, m, v untouched; no loss or dq written)
+ * and adds to groups (dev [2], uint64) the number of sample groups (9 contacts
+ * x 7 tests) its forward passes gathered, and the number of groups those
+ * passes hold. The rest were skipped as provably clear of the dilated surface
+ * (Eq. (1): they contribute no correction). Counts are exact and independent
+ * of the launch shape. Errors as grasp_step_fused. */
+grasp_status grasp_debug_forward_groups(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                        const grasp_step_params* p, int32_t B, const float* q,
+                                        uint64_t* groups, void* hip_stream);
+
 #pragma GCC visibility pop
 #ifdef __cplusplus
 }

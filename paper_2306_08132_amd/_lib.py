@@ -136,6 +136,7 @@ SIGNATURES = [
     ("grasp_serve_stats_get", _I32, [_VP, C.POINTER(ServeStatsC)]),
     ("grasp_debug_sdf_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP, _VP]),
     ("grasp_debug_trace", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _VP, _VP]),
+    ("grasp_debug_forward_groups", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP]),
 ]
 
 

@@ -178,6 +178,15 @@ class Context:
                       _ptr(sm), _stream(stream))
         return {"p": pw, "poses": ps, "samples": sm}
 
+    def debug_forward_groups(self, hand, sdf, prm: StepParams, q, stream=None):
+        """(groups gathered, groups) over the forward passes of one fused step at q."""
+        cnt = torch.zeros(2, dtype=torch.int64, device=q.device)
+        pc = prm.c()
+        self.lib.call("grasp_debug_forward_groups", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q),
+                      _ptr(cnt), _stream(stream))
+        g = cnt.cpu()
+        return int(g[0]), int(g[1])
+
 
 class Hand:
     """A hand resident in a context (grasp_create_hand)."""

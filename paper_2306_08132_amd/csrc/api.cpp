@@ -492,7 +492,7 @@ void save_tile(const std::string& key, TileCfg c) {
 }
 
 size_t pose_ws_bytes(const StepConsts& c, int32_t B) {
-  // pose checkpoints [B][7][slots][6], then active-constraint counts [B][K][7]
+  // pose checkpoints [B][slots][7][6], then active-constraint counts [B][K][7]
   return static_cast<size_t>(B) * kSims * (pose_slots(c.K, c.ckpt) * 6 + c.K) * sizeof(float);
 }
 
@@ -839,4 +839,25 @@ grasp_status grasp_debug_trace(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id 
   return GRASP_OK;
 }
 
+grasp_status grasp_debug_forward_groups(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                        const grasp_step_params* p, int32_t B, const float* q, uint64_t* groups,
+                                        void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  if (st != GRASP_OK) return st;
+  if (!groups) return fail(GRASP_EINVAL, "groups is NULL");
+  if (B > 0 && !q) return fail(GRASP_EINVAL, "q is NULL");
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.fwd_groups = reinterpret_cast<unsigned long long*>(groups);
+  const TileCfg tc = tile_for(ctx, r, B);
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_step(a, STEP_FUSED, false, tc, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_forward_groups launch");
+  return GRASP_OK;
+}
+
 }  // extern "C"
+

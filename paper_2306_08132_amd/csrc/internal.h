@@ -54,8 +54,9 @@ struct SdfView {
   const float4* cells;
   uint32_t cells_bytes;    // size of cells (< 4 GiB: buffer loads use 32-bit offsets)
   int layout;
-  // Lower bounds for culling: the minimum over the corners of every block of
-  // kBlockCells^3 cells, [nb][nb][nb] with nb = ceil((N-1) / kBlockCells).
+  // Lower bounds for culling: for every block of kBlockCells^3 cells, the
+  // minimum over the vertices of its cells widened by one cell on every side,
+  // [nb][nb][nb] with nb = ceil((N-1) / kBlockCells).
   const float* bmin;
   int nb;
 };
@@ -131,9 +132,11 @@ struct StepArgs {
   float* terms;         // [B][4] (or null)
   float* dq;            // [B][n_dof] (or null)
   const float* dloss;   // [B] (or null: 1)
-  float* poses;         // [B][7][slots][6] checkpoints, then [B][K][7] counts (or null)
+  float* poses;         // [B][slots][7][6] checkpoints, then [B][K][7] counts (or null)
   int* nonfinite;       // [1] set when any loss is not finite (or null)
   const int* order;     // [B] candidate taken by work item i (or null: i itself)
+  unsigned long long* fwd_groups;  // [2] += (sample groups gathered, sample groups) over
+                                   // every untraced forward pass (or null)
   // debug trace (caller order), all optional
   float* trace_p;       // [B][Nc][3]
   float* trace_poses;   // [B][7][K+1][6]

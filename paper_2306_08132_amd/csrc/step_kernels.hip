@@ -27,6 +27,7 @@ struct Ctx {
   const StepConsts& P;
   float* lds;
   int lane;
+  unsigned long long* groups;  // forward group counts (or null)
 };
 
 // Link transforms T_l (Sec. III-C, p = FK(q)): lane l composes its own
@@ -138,19 +139,37 @@ __device__ __forceinline__ const float* test_consts(const Ctx& c, const LaneTest
   return c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
 }
 
-// Whether the sample at grid-frame point r is provably clear of the dilated
-// surface (d > 0, with a margin far above the FP32 rounding of the sample):
-// the trilinear value is at least the minimum of its block's corners, and
-// outside the box the distance to the box adds on.
-__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float rd) {
+// Lower bounds for culling. The block table holds, for every block of 4^3
+// cells, the minimum over the grid vertices of the block widened by one cell
+// on every side. A trilinear value is at least the minimum of its cell's
+// corners, and the sample adds the distance to the grid box outside it; the
+// margins (relative 1e-6 on distances, absolute 1e-6 on the sum) lie far above
+// the FP32 rounding of the sample, so a bound above zero means d > 0 exactly
+// as the sample computes it: no active constraint, lambda = 0.
+__device__ __forceinline__ float bound_at(const SdfView& S, V3 r, float& e) {
   const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
   const int bx = static_cast<int>(ax.i) >> kBlockShift;
   const int by = static_cast<int>(ay.i) >> kBlockShift;
   const int bz = static_cast<int>(az.i) >> kBlockShift;
-  const float bm = S.bmin[(bz * S.nb + by) * S.nb + bx];
-  const float ex = (ax.u - ax.b) * S.h, ey = (ay.u - ay.b) * S.h, ez = (az.u - az.b) * S.h;
-  const float e = __builtin_sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+  // max-norm distance to the grid box (at most the Euclidean one the sample adds)
+  e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
+  return S.bmin[(bz * S.nb + by) * S.nb + bx];
+}
+
+// One sample at grid-frame point r: provably clear of the dilated surface.
+__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float rd) {
+  float e;
+  const float bm = bound_at(S, r, e);
   return fmaf(0.999999f, e, bm - rd) > 1e-6f;
+}
+
+// All seven test points p + o (|o| <= dv along one axis, dv below the cell
+// size) of a contact at p: each lies in a cell within one of p's cell per
+// axis, so inside p's widened block, and at most dv closer to the grid box.
+__device__ __forceinline__ bool contact_clear(const SdfView& S, V3 p, float rd, float dv) {
+  float e;
+  const float bm = bound_at(S, p, e);
+  return fmaxf(fmaf(0.999999f, e, -1.000001f * dv), 0.0f) + (bm - rd) > 1e-6f;
 }
 
 template <bool ROT, bool TRACE, int LAY>
@@ -249,17 +268,33 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
   };
   float W[6] = {0, 0, 0, 0, 0, 0};
   float lp = 0.0f, na = 0.0f;
+  uint32_t n_live = 0;
+  // without rotation the seven tests of a contact share one bound
+  const float dv = c.P.dt * c.P.v0;
+  const bool per_contact = !ROT && fabsf(dv) <= 0.99f * S.h;
   for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     uint32_t live = 0;
+    if (per_contact) {
+      // lane j bounds contact j of the chunk; group g holds contacts [9g, 9g + 9)
+      const float4 Pj = P[c.lane];
+      const bool needed = c.lane < kChunk && __float_as_int(Pj.w) >= 0 &&
+                          !contact_clear(S, v3(Pj.x, Pj.y, Pj.z), rd, fabsf(dv));
+      const uint64_t m = __builtin_amdgcn_ballot_w64(needed);
 #pragma unroll
-    for (int g = 0; g < kGroups; ++g) {
-      const float4 P4 = P[kGroup * g + lt.sub];
-      const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
-      const bool needed = valid && !provably_clear(S, frame_of(P4), rd);
-      if (__builtin_amdgcn_ballot_w64(needed) != 0) live |= 1u << g;
+      for (int g = 0; g < kGroups; ++g)
+        if ((m >> (kGroup * g)) & ((1ull << kGroup) - 1)) live |= 1u << g;
+    } else {
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        const float4 P4 = P[kGroup * g + lt.sub];
+        const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
+        const bool needed = valid && !provably_clear(S, frame_of(P4), rd);
+        if (__builtin_amdgcn_ballot_w64(needed) != 0) live |= 1u << g;
+      }
     }
     live = __builtin_amdgcn_readfirstlane(live);
+    n_live += __builtin_popcount(live);
     if (live == 0) continue;
     int g = __builtin_ctz(live);
     float4 lo, hi, lo_n, hi_n;
@@ -294,6 +329,10 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       lo = lo_n;
       hi = hi_n;
     }
+  }
+  if (c.groups && c.lane == 0) {
+    atomicAdd(c.groups, static_cast<unsigned long long>(n_live));
+    atomicAdd(c.groups + 1, static_cast<unsigned long long>((H.Nc + kGroup - 1) / kGroup));
   }
   test_sums<6>(c, W, c.lds + kOffWS, 6, false);
   test_sums<1>(c, &na, c.lds + kOffCnt, 1, false);
@@ -487,7 +526,7 @@ template <bool KONE, int LAY>
 __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
-  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id()};
+  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id(), A.fwd_groups};
   const int nd = H.n_dof;
   const int lane = c.lane;
   const float* qb = A.q + static_cast<size_t>(b) * nd;
@@ -862,10 +901,11 @@ __global__ void k_build_bmin(const float* __restrict__ vals, int n, float* __res
   const int id = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= nb * nb * nb) return;
   const int bx = id % nb, by = (id / nb) % nb, bz = id / (nb * nb);
+  // vertices of the block's cells widened by one cell on every side
   float m = INFINITY;
-  for (int k = bz * kBlockCells; k <= min(bz * kBlockCells + kBlockCells, n - 1); ++k)
-    for (int j = by * kBlockCells; j <= min(by * kBlockCells + kBlockCells, n - 1); ++j)
-      for (int i = bx * kBlockCells; i <= min(bx * kBlockCells + kBlockCells, n - 1); ++i)
+  for (int k = max(bz * kBlockCells - 1, 0); k <= min(bz * kBlockCells + kBlockCells + 1, n - 1); ++k)
+    for (int j = max(by * kBlockCells - 1, 0); j <= min(by * kBlockCells + kBlockCells + 1, n - 1); ++j)
+      for (int i = max(bx * kBlockCells - 1, 0); i <= min(bx * kBlockCells + kBlockCells + 1, n - 1); ++i)
         m = fminf(m, vals[(static_cast<long long>(k) * n + j) * n + i]);
   bmin[id] = m;
 }

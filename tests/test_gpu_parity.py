@@ -518,3 +518,48 @@ def test_step_captured_in_a_graph(ctx, tiny):
         torch.cuda.synchronize()
         _ = (qg * 2).sum().item()  # eager work between replays
         assert torch.equal(qg, ref[0][0]) and torch.equal(lg, ref[0][1]), rep
+
+
+@pytest.mark.parametrize("case", ["k1", "k1-wide-tests", "k1-outside", "k3", "k3-outside"])
+@pytest.mark.parametrize("layout", ["cells", "zpairs"])
+def test_culled_forward_matches_full_pass(ctx, tiny, case, layout):
+    """The untraced forward pass skips groups of samples whose block bound
+    proves them clear of the surface; the traced pass evaluates every sample.
+    Pose trajectories and active-constraint counts agree bit for bit, the
+    penetration energy agrees with the traced samples, and some groups are
+    skipped. Cases: one bound per contact (K = 1, dv below the cell size),
+    per-sample bounds (dv above it, and K > 1 with rotating tests), and hands
+    partly outside the grid box (distance term of the bound)."""
+    hand, grid, q = tiny
+    q = np.array(q[:48], dtype=np.float64)
+    if case.endswith("outside"):
+        q[:, 0] += 0.05  # wrist 5 cm along x: part of the hand leaves the 12 cm box
+    K = 3 if case.startswith("k3") else 1
+    dt = 2.5e-3 if case == "k1-wide-tests" else 1e-3  # dv = dt v0 above / below the 1.9 mm cell
+    assert (dt > grid.h) == (case == "k1-wide-tests")
+    say("culled vs full", case, layout)
+    h, sd = ctx.hand(hand), ctx.sdf(grid, layout=LAYOUTS[layout])
+    sp, _ = prm_pair(r_dil=0.006, K=K, ckpt_every=1, dt=dt)
+    qd = dev(q)
+    B = q.shape[0]
+    ws = torch.zeros(ctx.workspace_bytes(h, sd, sp, B) // 4, dtype=torch.float32, device=DEV)
+    loss = torch.empty(B, device=DEV)
+    terms = torch.empty((B, 4), device=DEV)
+    ctx.step_fwd(h, sd, sp, qd, loss, terms=terms, ws=ws)
+    tr = ctx.debug_trace(h, sd, sp, qd, p_world=False)
+    live, total = ctx.debug_forward_groups(h, sd, sp, qd)
+    torch.cuda.synchronize()
+    npose = B * 7 * (K + 1) * 6
+    poses = ws[:npose].view(B, K + 1, 7, 6).transpose(1, 2)  # checkpoints are slot-major per candidate
+    assert torch.equal(poses, tr["poses"]), float((poses - tr["poses"]).abs().max())
+    counts = ws[npose:npose + B * K * 7].view(B, K, 7).cpu().numpy()
+    sm = tr["samples"].cpu().numpy()  # [B][7][K][Nc][6]: d, g, w, lambda
+    assert np.array_equal(counts, (sm[..., 5] != 0).sum(axis=-1).transpose(0, 2, 1))
+    d0 = sm[:, 6, 0, :, 0].astype(np.float64)
+    lpen = 0.5 * np.where(d0 < 0, d0 * d0, 0.0).sum(axis=1)
+    got = terms[:, 1].cpu().numpy().astype(np.float64)
+    assert np.allclose(got, lpen, rtol=1e-5, atol=1e-12), np.abs(got - lpen).max()
+    passes = K  # forward passes of a fused step with a checkpoint every iteration
+    assert total == B * passes * -(-hand.n_contacts // 9)
+    say("  live groups", live, "of", total)
+    assert 0 < live < total
