@@ -100,20 +100,37 @@ __device__ __forceinline__ Axis grid_axis(float r, float lo, const SdfView& S) {
   return a;
 }
 
-// Byte offset, in the gather copy of layout LAY, of the data of the cell
-// holding r: its 32-byte corner record, or the z-pair of its lower corner
-// (unsigned: at most 511^3 * 32 bytes, below 2^32).
+// A sample point located in the grid: the byte offset, in the gather copy of
+// layout LAY, of its cell's data (its 32-byte corner record, or the z-pair of
+// its lower corner; unsigned: at most 511^3 * 32 bytes, below 2^32), its
+// position in the cell, and its offset from the clamped point in cells
+// (exactly 0 on axes where it lies inside the grid box). Computed once when
+// the corners are requested and kept until they arrive.
+struct Located {
+  uint32_t byte;
+  float fx, fy, fz;
+  float ox, oy, oz;
+};
+
 template <int LAY>
-__device__ __forceinline__ uint32_t sdf_cell_byte(const SdfView& S, V3 r) {
+__device__ __forceinline__ Located locate(const SdfView& S, V3 r) {
   const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
   const uint32_t ix = static_cast<uint32_t>(ax.i), iy = static_cast<uint32_t>(ay.i), iz = static_cast<uint32_t>(az.i);
+  Located L;
   if constexpr (LAY == kLayoutCells) {
     const uint32_t nc = static_cast<uint32_t>(S.n - 1);
-    return ((iz * nc + iy) * nc + ix) * 32u;
+    L.byte = ((iz * nc + iy) * nc + ix) * 32u;
   } else {
     const uint32_t n = static_cast<uint32_t>(S.n);
-    return ((iz * n + iy) * n + ix) * 8u;
+    L.byte = ((iz * n + iy) * n + ix) * 8u;
   }
+  L.fx = ax.b - ax.i;
+  L.fy = ay.b - ay.i;
+  L.fz = az.b - az.i;
+  L.ox = ax.u - ax.b;
+  L.oy = ay.u - ay.b;
+  L.oz = az.u - az.b;
+  return L;
 }
 
 // The cell's 8 corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
@@ -142,12 +159,13 @@ __device__ __forceinline__ void sdf_corners(const SdfView& S, uint32_t off, floa
   }
 }
 
-// Trilinear value and analytic gradient at r from its cell's corners.
-__device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 lo4, float4 hi4, Sample& s) {
-  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
-  s.fx = ax.b - ax.i;
-  s.fy = ay.b - ay.i;
-  s.fz = az.b - az.i;
+// Trilinear value and analytic gradient of the located sample from its
+// cell's corners.
+__device__ __forceinline__ void sample_sdf_from(const SdfView& S, const Located& L, float4 lo4, float4 hi4,
+                                                Sample& s) {
+  s.fx = L.fx;
+  s.fy = L.fy;
+  s.fz = L.fz;
   s.dx00 = lo4.y - lo4.x;
   s.dx10 = lo4.w - lo4.z;
   s.dx01 = hi4.y - hi4.x;
@@ -165,29 +183,34 @@ __device__ __forceinline__ void sample_sdf_from(const SdfView& S, V3 r, float4 l
   const float gx = fmaf(s.fz, gx1 - gx0, gx0);
   s.dyx0 = (hi4.z - hi4.x) - (lo4.z - lo4.x);
   s.dyx1 = (hi4.w - hi4.y) - (lo4.w - lo4.y);
-  s.clx = ax.u != ax.b;
-  s.cly = ay.u != ay.b;
-  s.clz = az.u != az.b;
+  s.clx = L.ox != 0.0f;
+  s.cly = L.oy != 0.0f;
+  s.clz = L.oz != 0.0f;
   s.phi = fmaf(s.fz, gz, c0);
   s.n = v3(s.clx ? 0.0f : gx * S.inv_h, s.cly ? 0.0f : gy * S.inv_h, s.clz ? 0.0f : gz * S.inv_h);
   // offset from the clamped point, exactly 0 on unclamped axes
-  s.e = v3((ax.u - ax.b) * S.h, (ay.u - ay.b) * S.h, (az.u - az.b) * S.h);
-  // outside the box: add the distance to the clamped point and its direction
-  // (selects rather than a branch keep the sample one basic block)
+  s.e = v3(L.ox * S.h, L.oy * S.h, L.oz * S.h);
+  // outside the box: add the distance to the clamped point and its direction.
+  // Inside, |e|^2 = 0 and the finite 1/|e| bound below adds exact zeros, so
+  // the sample needs no select (a -0 component becomes +0).
   const float ee = dot(s.e, s.e);
-  const bool outside = ee > 0.0f;
-  const float ine = rsq(ee);
-  s.inv_ne = outside ? ine : 0.0f;
-  s.phi = outside ? s.phi + ee * ine : s.phi;
-  const V3 nn = axpy(ine, s.e, s.n);
-  s.n = v3(outside ? nn.x : s.n.x, outside ? nn.y : s.n.y, outside ? nn.z : s.n.z);
+  const float ine = rsq(fmaxf(ee, 1.17549435e-38f));
+  s.inv_ne = ee > 0.0f ? ine : 0.0f;
+  s.phi = s.phi + ee * ine;
+  s.n = axpy(ine, s.e, s.n);
 }
 
 __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   float4 lo4, hi4;
-  if (S.layout == kLayoutZPairs) sdf_corners<kLayoutZPairs>(S, sdf_cell_byte<kLayoutZPairs>(S, r), lo4, hi4);
-  else sdf_corners<kLayoutCells>(S, sdf_cell_byte<kLayoutCells>(S, r), lo4, hi4);
-  sample_sdf_from(S, r, lo4, hi4, s);
+  if (S.layout == kLayoutZPairs) {
+    const Located L = locate<kLayoutZPairs>(S, r);
+    sdf_corners<kLayoutZPairs>(S, L.byte, lo4, hi4);
+    sample_sdf_from(S, L, lo4, hi4, s);
+  } else {
+    const Located L = locate<kLayoutCells>(S, r);
+    sdf_corners<kLayoutCells>(S, L.byte, lo4, hi4);
+    sample_sdf_from(S, L, lo4, hi4, s);
+  }
 }
 
 // H v with H = d(grad phi)/dr of the sample: mixed partials of the trilinear

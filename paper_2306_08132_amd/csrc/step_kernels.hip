@@ -195,22 +195,24 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
   for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     float4 lo[2], hi[2];
+    Located L[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
+      L[0] = locate<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z))));
+      sdf_corners<LAY>(S, L[0].byte, lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
-                    hi[(g + 1) & 1]);
+        L[(g + 1) & 1] = locate<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z))));
+        sdf_corners<LAY>(S, L[(g + 1) & 1].byte, lo[(g + 1) & 1], hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
       const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
       const V3 a = test_pt(v3(P4.x, P4.y, P4.z));
       Sample s;
-      sample_sdf_from(S, frame_pt(a), lo[g & 1], hi[g & 1], s);
+      sample_sdf_from(S, L[g & 1], lo[g & 1], hi[g & 1], s);
       const V3 gn = ROT ? mul(R, s.n) : s.n;
       const float d = s.phi - rd;
       const bool act = valid && d < 0.0f;
@@ -298,17 +300,21 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
     if (live == 0) continue;
     int g = __builtin_ctz(live);
     float4 lo, hi, lo_n, hi_n;
-    sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_of(P[kGroup * g + lt.sub])), lo, hi);
+    Located L = locate<LAY>(S, frame_of(P[kGroup * g + lt.sub])), L_n;
+    sdf_corners<LAY>(S, L.byte, lo, hi);
     for (;;) {
       live &= live - 1;
       const int gn = live ? __builtin_ctz(live) : -1;
-      if (gn >= 0) sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_of(P[kGroup * gn + lt.sub])), lo_n, hi_n);
+      if (gn >= 0) {
+        L_n = locate<LAY>(S, frame_of(P[kGroup * gn + lt.sub]));
+        sdf_corners<LAY>(S, L_n.byte, lo_n, hi_n);
+      }
       const float4 P4 = P[kGroup * g + lt.sub];
       const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
       const V3 p = v3(P4.x, P4.y, P4.z);
       const V3 a = ROT ? p - x : p + lt.off;
       Sample s;
-      sample_sdf_from(S, ROT ? mul_t(R, a) : a, lo, hi, s);
+      sample_sdf_from(S, L, lo, hi, s);
       const V3 gn_ = ROT ? mul(R, s.n) : s.n;
       const float d = s.phi - rd;
       const bool act = valid && d < 0.0f;
@@ -326,6 +332,7 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       W[5] = fmaf(lam, u.z, W[5]);
       if (gn < 0) break;
       g = gn;
+      L = L_n;
       lo = lo_n;
       hi = hi_n;
     }
@@ -395,16 +402,18 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
   for (int ch = 0; ch < n_chunks; ++ch) {
     stage_chunk(c, ch);
     float4 lo[2], hi[2];
+    Located L[2];
     {
       const float4 P4 = P[lt.sub];
-      sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z)))), lo[0], hi[0]);
+      L[0] = locate<LAY>(S, frame_pt(test_pt(v3(P4.x, P4.y, P4.z))));
+      sdf_corners<LAY>(S, L[0].byte, lo[0], hi[0]);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
       if (g + 1 < kGroups) {
         const float4 Pn = P[kGroup * (g + 1) + lt.sub];
-        sdf_corners<LAY>(S, sdf_cell_byte<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z)))), lo[(g + 1) & 1],
-                    hi[(g + 1) & 1]);
+        L[(g + 1) & 1] = locate<LAY>(S, frame_pt(test_pt(v3(Pn.x, Pn.y, Pn.z))));
+        sdf_corners<LAY>(S, L[(g + 1) & 1].byte, lo[(g + 1) & 1], hi[(g + 1) & 1]);
       }
       const float4 P4 = P[kGroup * g + lt.sub];
       const int link = __float_as_int(P4.w);
@@ -412,7 +421,7 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
       const V3 p = v3(P4.x, P4.y, P4.z);
       const V3 a = test_pt(p);
       Sample s;
-      sample_sdf_from(S, frame_pt(a), lo[g & 1], hi[g & 1], s);
+      sample_sdf_from(S, L[g & 1], lo[g & 1], hi[g & 1], s);
       const V3 gn = ROT ? mul(o.R, s.n) : s.n;
       const float d = s.phi - rd;
       const V3 u = cross(a, gn);
