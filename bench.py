@@ -247,6 +247,9 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=60, help="optimizer steps per served job")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
     ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="launch tile 'waves_per_block,min_waves_per_simd' instead of tuning (profiled runs: "
+                         "every step dispatch is then a timed shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
                          "the reference that scales HBM counters")
@@ -288,9 +291,14 @@ def main():
         prm = StepParams(K=K, r_dil=r0 * (1.0 - min(t, T_sched - 1) / (T_sched - 1)))
         ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
 
-    print("bench: tuning the launch tile", file=sys.stderr, flush=True)
-    tile, tile_ms = ctx.tune(h, sd, StepParams(K=K, r_dil=r0), q, reps=3)
-    print(f"bench: tile {tile} at {tile_ms:.3f} ms", file=sys.stderr, flush=True)
+    if args.tile:
+        tile = tuple(int(x) for x in args.tile.split(","))
+        ctx.set_tile(h, sd, StepParams(K=K, r_dil=r0), B, tile[0], tile[1])
+        print(f"bench: tile {tile} (given)", file=sys.stderr, flush=True)
+    else:
+        print("bench: tuning the launch tile", file=sys.stderr, flush=True)
+        tile, tile_ms = ctx.tune(h, sd, StepParams(K=K, r_dil=r0), q, reps=3)
+        print(f"bench: tile {tile} at {tile_ms:.3f} ms", file=sys.stderr, flush=True)
     print("bench: warmup", file=sys.stderr, flush=True)
     for t in range(args.warmup):
         step(t)

@@ -124,9 +124,11 @@ typedef struct {
 } grasp_sdf_desc;
 
 enum {
-  GRASP_LAYOUT_AUTO = 0,    /* z-pairs while they take at most 48 MiB (n <= 183), else corner records */
-  GRASP_LAYOUT_CELLS = 1,   /* 32 bytes per cell, its 8 corners: one cache line per sample, 8x the grid */
-  GRASP_LAYOUT_ZPAIRS = 2   /* (phi(i,j,k), phi(i,j,k+1)) per vertex: two lines per sample, 2x the grid */
+  GRASP_LAYOUT_AUTO = 0,     /* yz-quads */
+  GRASP_LAYOUT_YZQUADS = 1,  /* (phi(i,j,k), phi(i,j+1,k), phi(i,j,k+1), phi(i,j+1,k+1)) per vertex, 16
+                                bytes: a cell's 8 corners are 32 contiguous bytes of one row, so the seven
+                                tests of a contact touch few cache lines; 4x the grid */
+  GRASP_LAYOUT_ZPAIRS = 2    /* (phi(i,j,k), phi(i,j,k+1)) per vertex: two rows per sample, 2x the grid */
 };
 
 /* Copies the grid to the device with a gather copy in the chosen layout.

@@ -38,7 +38,7 @@ class SdfDesc(C.Structure):
                 ("values", C.POINTER(C.c_float)), ("inertia_over_mass", C.c_float), ("layout", C.c_int32)]
 
 
-LAYOUT_AUTO, LAYOUT_CELLS, LAYOUT_ZPAIRS = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_YZQUADS, LAYOUT_ZPAIRS = 0, 1, 2
 
 
 class TileC(C.Structure):

@@ -356,13 +356,10 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   }
   const size_t nc = n - 1;
   const size_t vbytes = round_up(n3 * sizeof(float), 256);
-  const size_t zbytes = n * n * nc * 2 * sizeof(float);
   if (d->layout < GRASP_LAYOUT_AUTO || d->layout > GRASP_LAYOUT_ZPAIRS) return fail(GRASP_EINVAL, "unknown layout");
-  const int layout = d->layout == GRASP_LAYOUT_CELLS    ? kLayoutCells
-                     : d->layout == GRASP_LAYOUT_ZPAIRS ? kLayoutZPairs
-                     : zbytes <= kZPairMaxBytes         ? kLayoutZPairs
-                                                        : kLayoutCells;
-  const size_t cbytes = layout == kLayoutZPairs ? zbytes : nc * nc * nc * 8 * sizeof(float);
+  const int layout = d->layout == GRASP_LAYOUT_ZPAIRS ? kLayoutZPairs : kLayoutYZQuads;
+  // z-pairs: [n-1][n][n] x 8 bytes; yz-quads: [n-1][n-1][n] x 16 bytes
+  const size_t cbytes = layout == kLayoutZPairs ? n * n * nc * 2 * sizeof(float) : n * nc * nc * 4 * sizeof(float);
   const int nb = static_cast<int>((nc + kBlockCells - 1) / kBlockCells);
   const size_t bbytes = round_up(static_cast<size_t>(nb) * nb * nb * sizeof(float), 256);
   DeviceGuard g(ctx->device);
@@ -373,7 +370,7 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
   char* b = static_cast<char*>(blk);
   hipError_t e = hipMemcpy(b, d->values, n3 * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = launch_build_cells(reinterpret_cast<const float*>(b), d->n, layout,
+    e = launch_build_gather(reinterpret_cast<const float*>(b), d->n, layout,
                            reinterpret_cast<float4*>(b + vbytes + bbytes), nullptr);
   if (e == hipSuccess)
     e = launch_build_bmin(reinterpret_cast<const float*>(b), d->n, reinterpret_cast<float*>(b + vbytes), nullptr);

@@ -101,8 +101,8 @@ __device__ __forceinline__ Axis grid_axis(float r, float lo, const SdfView& S) {
 }
 
 // A sample point located in the grid: the byte offset, in the gather copy of
-// layout LAY, of its cell's data (its 32-byte corner record, or the z-pair of
-// its lower corner; unsigned: at most 511^3 * 32 bytes, below 2^32), its
+// layout LAY, of its cell's data (the yz-quad or the z-pair of its lower
+// corner; at most 512 * 511^2 * 16 bytes, below 2^31), its
 // position in the cell, and its offset from the clamped point in cells
 // (exactly 0 on axes where it lies inside the grid box). Computed once when
 // the corners are requested and kept until they arrive.
@@ -117,9 +117,9 @@ __device__ __forceinline__ Located locate(const SdfView& S, V3 r) {
   const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
   const uint32_t ix = static_cast<uint32_t>(ax.i), iy = static_cast<uint32_t>(ay.i), iz = static_cast<uint32_t>(az.i);
   Located L;
-  if constexpr (LAY == kLayoutCells) {
-    const uint32_t nc = static_cast<uint32_t>(S.n - 1);
-    L.byte = ((iz * nc + iy) * nc + ix) * 32u;
+  if constexpr (LAY == kLayoutYZQuads) {
+    const uint32_t n = static_cast<uint32_t>(S.n);
+    L.byte = ((iz * (n - 1u) + iy) * n + ix) * 16u;
   } else {
     const uint32_t n = static_cast<uint32_t>(S.n);
     L.byte = ((iz * n + iy) * n + ix) * 8u;
@@ -135,16 +135,20 @@ __device__ __forceinline__ Located locate(const SdfView& S, V3 r) {
 
 // The cell's 8 corners: lo4 = (000, 100, 010, 110), hi4 = (001, 101, 011, 111)
 // (32-bit buffer offsets; an offset past cells_bytes reads zeros, never faults).
-// Corner records: two 16-byte loads. Z-pairs: two 8-byte loads in row (j, k)
-// and two in row (j + 1, k).
+// yz-quads: two 16-byte loads, vertices i and i + 1 of one row. Z-pairs: two
+// 8-byte loads in row (j, k) and two in row (j + 1, k).
 template <int LAY>
 __device__ __forceinline__ void sdf_corners(const SdfView& S, uint32_t off, float4& lo4, float4& hi4) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(S.cells), static_cast<short>(0),
                                         static_cast<int>(S.cells_bytes), 0x00020000);
-  if constexpr (LAY == kLayoutCells) {
-    lo4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0));
-    hi4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off + 16u), 0, 0));
+  if constexpr (LAY == kLayoutYZQuads) {
+    // quads of vertices i and i + 1: (v000, v010, v001, v011), (v100, v110, v101, v111)
+    const float4 e0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0));
+    const float4 e1 =
+        __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off + 16u), 0, 0));
+    lo4 = make_float4(e0.x, e1.x, e0.y, e1.y);
+    hi4 = make_float4(e0.z, e1.z, e0.w, e1.w);
   } else {
     const uint32_t row = static_cast<uint32_t>(S.n) * 8u;
     const float2 a0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0));
@@ -207,8 +211,8 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
     sdf_corners<kLayoutZPairs>(S, L.byte, lo4, hi4);
     sample_sdf_from(S, L, lo4, hi4, s);
   } else {
-    const Located L = locate<kLayoutCells>(S, r);
-    sdf_corners<kLayoutCells>(S, L.byte, lo4, hi4);
+    const Located L = locate<kLayoutYZQuads>(S, r);
+    sdf_corners<kLayoutYZQuads>(S, L.byte, lo4, hi4);
     sample_sdf_from(S, L, lo4, hi4, s);
   }
 }

@@ -49,7 +49,7 @@ struct SdfView {
   float inv_Im;            // 1 / (I/m)
   const float* values;     // [N^3], x fastest
   // Gather copy of the grid, one of two layouts:
-  //  kLayoutCells: [(N-1)^3][2] float4 per cell, corners (000,100,010,110), (001,101,011,111)
+  //  kLayoutYZQuads: [N-1][N-1][N] float4 per vertex, (phi(i,j,k), phi(i,j+1,k), phi(i,j,k+1), phi(i,j+1,k+1))
   //  kLayoutZPairs: [N-1][N][N] float2 per vertex, (phi(i,j,k), phi(i,j,k+1))
   const float4* cells;
   uint32_t cells_bytes;    // size of cells (< 4 GiB: buffer loads use 32-bit offsets)
@@ -64,13 +64,13 @@ struct SdfView {
 constexpr int kBlockShift = 2;
 constexpr int kBlockCells = 1 << kBlockShift;
 
-// Layouts of the gather copy. Corner records cost one cache line per sample
-// but 8x the grid's memory; z-pairs cost two lines per sample at 2x. The
-// smaller copy wins while it stays close to L2 (measured crossover between
-// 160^3 and 192^3); grids up to kZPairMaxBytes of z-pairs use them.
-constexpr int kLayoutCells = 0;
+// Layouts of the gather copy. yz-quads hold a cell's 8 corners in 32
+// contiguous bytes of one row, so a contact's seven test points, which lie in
+// neighbouring cells, touch about four cache lines; z-pairs need two rows per
+// sample but half the memory. yz-quads measured fastest from 96^3 to 256^3
+// (at 96^3 the two tie) and are the default.
+constexpr int kLayoutYZQuads = 0;
 constexpr int kLayoutZPairs = 1;
-constexpr size_t kZPairMaxBytes = size_t(48) << 20;
 
 // Device copy of the step parameters.
 struct StepConsts {
@@ -192,7 +192,7 @@ hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int 
 
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);
-hipError_t launch_build_cells(const float* values, int n, int layout, float4* cells, hipStream_t stream);
+hipError_t launch_build_gather(const float* values, int n, int layout, float4* cells, hipStream_t stream);
 hipError_t launch_build_bmin(const float* values, int n, float* bmin, hipStream_t stream);
 hipError_t launch_sample_points(const SdfView& s, int n, const float* r, float* out4, float* hess9,
                                 hipStream_t stream);

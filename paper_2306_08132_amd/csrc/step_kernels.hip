@@ -728,7 +728,7 @@ __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int
 template <bool KONE>
 __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   if (A.sdf.layout == kLayoutZPairs) candidate_step_lay<KONE, kLayoutZPairs>(A, b, kind, adam, lds);
-  else candidate_step_lay<KONE, kLayoutCells>(A, b, kind, adam, lds);
+  else candidate_step_lay<KONE, kLayoutYZQuads>(A, b, kind, adam, lds);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block i to XCD i mod
@@ -878,19 +878,17 @@ __global__ void k_adam(int n, float* q, float* m, float* v, const float* g, Adam
   q[i] -= c.lr * (mm / c.c1) / (sqrtf(vv / c.c2) + c.eps);
 }
 
-__global__ void k_build_cells(const float* __restrict__ vals, int n, float4* __restrict__ cells) {
-  const int nc = n - 1;
-  const long long total = static_cast<long long>(nc) * nc * nc;
+// yz-quads: Q[k][j][i] = (phi(i,j,k), phi(i,j+1,k), phi(i,j,k+1), phi(i,j+1,k+1))
+// for j, k < n - 1
+__global__ void k_build_yzquads(const float* __restrict__ vals, int n, float4* __restrict__ Q) {
+  const long long total = static_cast<long long>(n) * (n - 1) * (n - 1);
   const long long id = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= total) return;
-  const int ix = static_cast<int>(id % nc);
-  const int iy = static_cast<int>((id / nc) % nc);
-  const int iz = static_cast<int>(id / (static_cast<long long>(nc) * nc));
-  auto V = [&](int i, int j, int k) {
-    return vals[(static_cast<long long>(iz + k) * n + (iy + j)) * n + (ix + i)];
-  };
-  cells[2 * id] = make_float4(V(0, 0, 0), V(1, 0, 0), V(0, 1, 0), V(1, 1, 0));
-  cells[2 * id + 1] = make_float4(V(0, 0, 1), V(1, 0, 1), V(0, 1, 1), V(1, 1, 1));
+  const int ix = static_cast<int>(id % n);
+  const int iy = static_cast<int>((id / n) % (n - 1));
+  const int iz = static_cast<int>(id / (static_cast<long long>(n) * (n - 1)));
+  auto V = [&](int j, int k) { return vals[(static_cast<long long>(iz + k) * n + (iy + j)) * n + ix]; };
+  Q[id] = make_float4(V(0, 0), V(1, 0), V(0, 1), V(1, 1));
 }
 
 // z-pairs: P[k][j][i] = (phi(i,j,k), phi(i,j,k+1)) for k < n - 1
@@ -1022,15 +1020,15 @@ hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, Adam
   return hipGetLastError();
 }
 
-hipError_t launch_build_cells(const float* values, int n, int layout, float4* cells, hipStream_t stream) {
+hipError_t launch_build_gather(const float* values, int n, int layout, float4* cells, hipStream_t stream) {
   if (layout == kLayoutZPairs) {
     const long long total = static_cast<long long>(n) * n * (n - 1);
     hipLaunchKernelGGL(k_build_zpairs, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, values,
                        n, reinterpret_cast<float2*>(cells));
   } else {
-    const long long total = static_cast<long long>(n - 1) * (n - 1) * (n - 1);
-    hipLaunchKernelGGL(k_build_cells, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, values,
-                       n, cells);
+    const long long total = static_cast<long long>(n) * (n - 1) * (n - 1);
+    hipLaunchKernelGGL(k_build_yzquads, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
+                       values, n, cells);
   }
   return hipGetLastError();
 }

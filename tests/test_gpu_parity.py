@@ -70,10 +70,10 @@ def test_contact_links_exact(ctx, fj):
     assert np.array_equal(h.contact_links(), hand.contact_link)
 
 
-LAYOUTS = {"cells": 1, "zpairs": 2}
+LAYOUTS = {"yzquads": 1, "zpairs": 2}
 
 
-@pytest.mark.parametrize("layout", ["cells", "zpairs"])
+@pytest.mark.parametrize("layout", ["yzquads", "zpairs"])
 @pytest.mark.parametrize("which", ["sphere64", "ellipsoids48", "mixed33"])
 def test_sdf_sampler_parity(ctx, which, layout):
     say("sampler", which, layout)
@@ -389,16 +389,16 @@ def test_locality_order_changes_nothing(ctx, tiny):
 
 
 def test_gather_layouts_bit_identical(ctx, tiny):
-    """Corner records and z-pairs hold the same corner values: every step
+    """yz-quads and z-pairs hold the same corner values: every step
     (K = 1 and K = 2, fused and split) and every sample agree bit for bit;
-    the corner-record path also meets the oracle on its own."""
+    the yz-quad path also meets the oracle on its own."""
     hand, grid, q = tiny
     h = ctx.hand(hand)
     sds = {name: ctx.sdf(grid, layout=code) for name, code in LAYOUTS.items()}
     r = dev(S.random_points(grid, 4096, seed=9).astype(np.float32))
     samples = {name: ctx.debug_sdf_sample(sd, r, hess=True) for name, sd in sds.items()}
     torch.cuda.synchronize()
-    assert all(torch.equal(a, b) for a, b in zip(samples["cells"], samples["zpairs"]))
+    assert all(torch.equal(a, b) for a, b in zip(samples["yzquads"], samples["zpairs"]))
     for K in (1, 2):
         sp, _ = prm_pair(r_dil=0.004, K=K)
         outs = {}
@@ -409,10 +409,10 @@ def test_gather_layouts_bit_identical(ctx, tiny):
             dq = torch.empty_like(qd)
             ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
             outs[name] = (loss.cpu().numpy(), dq.cpu().numpy(), qd.cpu().numpy())
-        say("layouts K", K, "max |loss diff|", float(np.abs(outs["cells"][0] - outs["zpairs"][0]).max()))
-        assert all(np.array_equal(a, b) for a, b in zip(outs["cells"], outs["zpairs"]))
+        say("layouts K", K, "max |loss diff|", float(np.abs(outs["yzquads"][0] - outs["zpairs"][0]).max()))
+        assert all(np.array_equal(a, b) for a, b in zip(outs["yzquads"], outs["zpairs"]))
     sp, op = prm_pair(r_dil=0.005)
-    compare_step(ctx, hand, grid, q, sp, op, "tiny r=5mm, corner records", layout=LAYOUTS["cells"])
+    compare_step(ctx, hand, grid, q, sp, op, "tiny r=5mm, yz-quads", layout=LAYOUTS["yzquads"])
 
 
 def test_plain_form_parity(ctx, tiny):
@@ -521,7 +521,7 @@ def test_step_captured_in_a_graph(ctx, tiny):
 
 
 @pytest.mark.parametrize("case", ["k1", "k1-wide-tests", "k1-outside", "k3", "k3-outside"])
-@pytest.mark.parametrize("layout", ["cells", "zpairs"])
+@pytest.mark.parametrize("layout", ["yzquads", "zpairs"])
 def test_culled_forward_matches_full_pass(ctx, tiny, case, layout):
     """The untraced forward pass skips groups of samples whose block bound
     proves them clear of the surface; the traced pass evaluates every sample.
