@@ -563,3 +563,32 @@ def test_culled_forward_matches_full_pass(ctx, tiny, case, layout):
     assert total == B * passes * -(-hand.n_contacts // 9)
     say("  live groups", live, "of", total)
     assert 0 < live < total
+
+
+def test_stored_oracle_values(ctx, tiny):
+    """The HIP path against the oracle values stored under tests/golden (written
+    by make_oracle_tiny.py), with no oracle run: loss within 1e-4, gradient
+    within 1e-3 of its largest component, for one and three iterations."""
+    from test_golden import load_oracle_tiny
+    hand, grid, _ = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    for K, r_dil, rows in load_oracle_tiny():
+        sp, _ = prm_pair(r_dil=r_dil, K=K)
+        q = np.stack([r[1] for r in rows])
+        B = q.shape[0]
+        qd = dev(q)
+        loss = torch.empty(B, device=DEV)
+        terms = torch.empty((B, 4), device=DEV)
+        ws = torch.empty(max(ctx.workspace_bytes(h, sd, sp, B), 4), dtype=torch.uint8, device=DEV)
+        ctx.step_fwd(h, sd, sp, qd, loss, terms, ws=ws)
+        dq = torch.empty_like(qd)
+        ctx.step_bwd(h, sd, sp, qd, dq, ws=ws)
+        torch.cuda.synchronize()
+        loss, dq = loss.cpu().numpy().astype(np.float64), dq.cpu().numpy().astype(np.float64)
+        want_loss = np.array([r[2] for r in rows])
+        want_grad = np.stack([r[4] for r in rows])
+        lerr = np.abs(loss - want_loss) / np.maximum(np.abs(want_loss), sp.w_stable * sp.v0)
+        gerr = np.abs(dq - want_grad).max(axis=1) / np.abs(want_grad).max(axis=1)
+        say(f"stored oracle values K={K}: B={B} loss rel err {lerr.max():.2e}, grad rel err {gerr.max():.2e}")
+        assert np.all(lerr <= 1e-4), lerr
+        assert np.all(gerr <= 1e-3), gerr
