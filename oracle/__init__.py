@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SRC = [os.path.join(_HERE, "oracle.cpp")]
+SRC = [os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "mesh.cpp")]
 
 OBJ_GRID, OBJ_SPHERE, OBJ_PLANE, OBJ_BOX = 0, 1, 2, 3
 M_SIMS = 7
@@ -78,6 +78,49 @@ class Params:
 _lib = None
 
 
+class _Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int), ("vertices", C.POINTER(C.c_double)), ("normals", C.POINTER(C.c_double)),
+                ("n_faces", C.c_int), ("faces", C.POINTER(C.c_int)), ("alpha", C.c_double)]
+
+
+class Mesh:
+    """A closed triangle mesh (outward faces) with unit vertex normals for the
+    Phong surface (Sec. III-B), held in FP64 for the oracle."""
+
+    def __init__(self, vertices, faces, normals, alpha: float):
+        self.vertices = np.ascontiguousarray(vertices, np.float64).reshape(-1, 3)
+        self.faces = np.ascontiguousarray(faces, np.int32).reshape(-1, 3)
+        self.normals = np.ascontiguousarray(normals, np.float64).reshape(-1, 3)
+        self.alpha = float(alpha)
+        self.c = _Mesh(self.vertices.shape[0], _ptr(self.vertices), _ptr(self.normals), self.faces.shape[0],
+                       _ptr(self.faces, C.c_int), self.alpha)
+
+
+def mesh_sdf(mesh: Mesh, r):
+    """Phong signed distance and the paper's gradient at points r [n][3], with
+    the flat closest point, its face, the flat distance and the medial gap."""
+    r = np.ascontiguousarray(r, np.float64).reshape(-1, 3)
+    n = r.shape[0]
+    rho, grad, cl = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 3))
+    face, flat, gap = np.zeros(n, np.int32), np.zeros(n), np.zeros(n)
+    _check(lib().oracle_mesh_sdf(C.byref(mesh.c), n, _ptr(r), _ptr(rho), _ptr(grad), _ptr(cl), _ptr(face, C.c_int),
+                                 _ptr(flat), _ptr(gap)), "oracle_mesh_sdf")
+    return {"rho": rho, "grad": grad, "closest": cl, "face": face, "dist_flat": flat, "gap": gap}
+
+
+def winding_number(mesh: Mesh, r) -> float:
+    r = np.ascontiguousarray(r, np.float64).reshape(3)
+    return lib().oracle_winding_number(C.byref(mesh.c), _ptr(r))
+
+
+def closest_on_triangle(a, b, c, r):
+    a, b, c, r = (np.ascontiguousarray(x, np.float64).reshape(3) for x in (a, b, c, r))
+    out, bary = np.zeros(3), np.zeros(3)
+    _check(lib().oracle_closest_on_triangle(_ptr(a), _ptr(b), _ptr(c), _ptr(r), _ptr(out), _ptr(bary)),
+           "oracle_closest_on_triangle")
+    return out, bary
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -96,6 +139,11 @@ def lib():
         L.oracle_adam.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_double]
         L.oracle_rank.argtypes = [C.c_int, dp, ip]
+        mp = C.POINTER(_Mesh)
+        L.oracle_mesh_sdf.argtypes = [mp, C.c_int, dp, dp, dp, dp, ip, dp, dp]
+        L.oracle_winding_number.argtypes = [mp, dp]
+        L.oracle_winding_number.restype = C.c_double
+        L.oracle_closest_on_triangle.argtypes = [dp, dp, dp, dp, dp, dp]
         L.oracle_optimize.argtypes = [hp, op, pp, C.c_int, dp, C.c_int, C.c_double, C.c_double,
                                       C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, ip, dp,
                                       C.c_int]

@@ -72,6 +72,32 @@ typedef struct {
   double w_min;       /* a constraint with J M^-1 J^T <= w_min is skipped */
 } oparams;
 
+/* A closed triangle mesh with outward (counter-clockwise) faces and unit
+   vertex normals for the Phong surface (Sec. III-B). */
+typedef struct {
+  int n_vertices;
+  const double* vertices;  /* [n_vertices][3] */
+  const double* normals;   /* [n_vertices][3] */
+  int n_faces;
+  const int* faces;        /* [n_faces][3] */
+  double alpha;            /* Phong blend: 0 flat, 1 curved */
+} omesh;
+
+/* Phong signed distance at n points r [n][3] (mesh.cpp): rho [n], grad [n][3]
+   = (r - p) / rho, closest [n][3] = closest point of the flat mesh, face [n]
+   its face, dist_flat [n] = |r - closest|, gap [n] = how much farther the
+   nearest different surface point is (0 on the medial axis); each output but
+   rho may be NULL. */
+int oracle_mesh_sdf(const omesh* m, int n, const double* r, double* rho, double* grad, double* closest,
+                    int* face, double* dist_flat, double* gap);
+
+/* Generalized winding number of the mesh at r: 1 inside, 0 outside. */
+double oracle_winding_number(const omesh* m, const double* r);
+
+/* Closest point of triangle (a, b, c) to r and its barycentric weights [3]. */
+int oracle_closest_on_triangle(const double* a, const double* b, const double* c, const double* r, double* out,
+                               double* bary);
+
 /* Forward kinematics. p_out [B][Nc][3]; frames_out [B][L][12] or NULL. */
 int oracle_fk(const ohand* hand, int B, const double* q, double* p_out, double* frames_out);
 

@@ -535,3 +535,119 @@ def make_job_stream(n_jobs: int, rate: float, seed: int, B_range=(256, 8192),
             steps=steps,
         ))
     return jobs
+
+
+# ----------------------------------------------------------------------------
+# triangle meshes (the mesh object of Sec. III-B)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class TriMesh:
+    """A closed triangle mesh, faces counter-clockwise seen from outside,
+    with unit vertex normals for the Phong surface."""
+    vertices: np.ndarray  # [V][3] float64
+    faces: np.ndarray     # [F][3] int32
+    normals: np.ndarray   # [V][3] float64
+
+    def bound_radius(self) -> float:
+        return float(np.linalg.norm(self.vertices, axis=1).max())
+
+
+def icosphere(subdivisions: int) -> TriMesh:
+    """Unit sphere: an icosahedron whose faces are split in four
+    ``subdivisions`` times, new vertices pushed onto the sphere; normals are
+    the exact radial directions."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, float) / np.linalg.norm(p) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+             (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdivisions):
+        mid = {}
+
+        def midpoint(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                p = verts[i] + verts[j]
+                verts.append(p / np.linalg.norm(p))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    V = np.array(verts)
+    return TriMesh(V, np.array(faces, np.int32), V.copy())
+
+
+def mesh_ellipsoid(semi, rotation=None, center=(0.0, 0.0, 0.0), subdivisions: int = 3) -> TriMesh:
+    """An ellipsoid (semi-axes along the rotation's columns) from a scaled
+    icosphere; vertex normals are the exact surface normals there."""
+    s = icosphere(subdivisions)
+    e = np.asarray(semi, float)
+    R = np.eye(3) if rotation is None else np.asarray(rotation, float)
+    local = s.vertices * e
+    n = s.vertices / e  # gradient of sum (x_i / e_i)^2 at the surface point, up to a factor
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return TriMesh(local @ R.T + np.asarray(center, float), s.faces, n @ R.T)
+
+
+def mesh_box(half, splits: int = 1, center=(0.0, 0.0, 0.0)) -> TriMesh:
+    """An axis-aligned box whose six faces are each split into splits x splits
+    squares (two triangles each). Vertices inside a face get that face's
+    normal; vertices on box edges and corners the normalized mean of the
+    normals of the faces they touch."""
+    h = np.asarray(half, float)
+    verts, index = [], {}
+
+    def vid(p):
+        key = tuple(np.round(p, 12))
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(np.array(p, float))
+        return index[key]
+
+    faces = []
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            u, w = (axis + 1) % 3, (axis + 2) % 3
+            grid = {}
+            for a in range(splits + 1):
+                for b in range(splits + 1):
+                    p = np.zeros(3)
+                    p[axis] = sgn * h[axis]
+                    p[u] = -h[u] + 2.0 * h[u] * a / splits
+                    p[w] = -h[w] + 2.0 * h[w] * b / splits
+                    grid[a, b] = vid(p)
+            for a in range(splits):
+                for b in range(splits):
+                    q00, q10, q01, q11 = grid[a, b], grid[a + 1, b], grid[a, b + 1], grid[a + 1, b + 1]
+                    # (u, w, axis) is right-handed: u x w = axis direction, so
+                    # counter-clockwise in (u, w) faces +axis
+                    if sgn > 0:
+                        faces += [(q00, q10, q11), (q00, q11, q01)]
+                    else:
+                        faces += [(q00, q11, q10), (q00, q01, q11)]
+    V = np.array(verts)
+    N = np.zeros_like(V)
+    for i, p in enumerate(V):
+        for axis in range(3):
+            if abs(abs(p[axis]) - h[axis]) < 1e-12 * h.max():
+                N[i, axis] += np.sign(p[axis])
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    return TriMesh(V + np.asarray(center, float), np.array(faces, np.int32), N)
+
+
+def random_mesh_object(seed: int, n_prims: int = 1, subdivisions: int = 3) -> TriMesh:
+    """An ellipsoid mesh of the sizes the grid objects use (semi-axes
+    U[1.5, 5] cm, uniform orientation); n_prims > 1 is not a closed union and
+    is refused."""
+    if n_prims != 1:
+        raise ValueError("mesh objects are single closed surfaces")
+    rng = np.random.default_rng(seed)
+    semi = rng.uniform(1.5 * CM, 5.0 * CM, size=3)
+    rot = Rotation.random(random_state=rng.integers(1 << 31)).as_matrix()
+    return mesh_ellipsoid(semi, rot, (0.0, 0.0, 0.0), subdivisions)
