@@ -142,6 +142,55 @@ grasp_status grasp_unload_sdf(grasp_ctx* ctx, grasp_sdf_id sdf);
 grasp_status grasp_sdf_inertia(grasp_ctx* ctx, grasp_sdf_id sdf, float* out);
 
 /* ---------------------------------------------------------------------------
+ * Mesh objects (Sec. III-B): the Phong signed distance of a closed triangle
+ * mesh, rho(r) = s(r) |r - p| with p the closest point r* of the mesh moved
+ * towards the curved (Phong) triangle, p = (1 - alpha) r* + alpha sum_b w_b
+ * psi_b(r*) (w_b the barycentric weights of r*, psi_b the projection onto the
+ * tangent plane of vertex b), s = -1 inside; grad rho = (r - p) / rho.
+ * ------------------------------------------------------------------------- */
+typedef uint64_t grasp_mesh_id;
+
+typedef struct {
+  int32_t n_vertices;       /* 3 .. 2^24 */
+  const float* vertices;    /* host [n_vertices][3], object frame */
+  const float* normals;     /* host [n_vertices][3] unit vertex normals of the Phong surface, or NULL for
+                               the angle-weighted normals of the incident faces */
+  int32_t n_faces;          /* 4 .. 2^22 */
+  const int32_t* faces;     /* host [n_faces][3] vertex indices, counter-clockwise seen from outside; the
+                               mesh must be closed: every edge shared by exactly two faces, traversed in
+                               opposite directions; no face of zero area */
+  float alpha;              /* Phong blend in [0, 1]; 0 is the flat mesh */
+} grasp_mesh_desc;
+
+/* Builds a bounding-volume hierarchy on the host and copies it to the device.
+ * EINVAL for a mesh that is not closed and consistently oriented outward (its
+ * enclosed volume must be positive), a degenerate face, an index out of range,
+ * a non-finite coordinate or alpha outside [0, 1]; ENOMEM when the arena is
+ * full. */
+grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* desc, grasp_mesh_id* out);
+grasp_status grasp_unload_mesh(grasp_ctx* ctx, grasp_mesh_id mesh);
+
+/* Phong signed distance at n points r (dev [n][3], object frame): out (dev
+ * [n][4]) = rho, grad rho. A non-finite point gives NaN. Asynchronous on
+ * hip_stream. */
+grasp_status grasp_mesh_sample(grasp_ctx* ctx, grasp_mesh_id mesh, int32_t n, const float* r, float* out,
+                               void* hip_stream);
+
+typedef struct {
+  int32_t n;                /* vertices per axis, 2..512 */
+  float lo[3];              /* position of vertex (0,0,0) */
+  float h;                  /* vertex spacing, > 0 */
+  float inertia_over_mass;  /* <= 0: 2/5 R_eq^2 with R_eq^3 = 3 V / (4 pi), V the mesh's volume */
+  int32_t layout;           /* GRASP_LAYOUT_* of the gather copy */
+} grasp_mesh_grid_desc;
+
+/* Samples the mesh's Phong signed distance at the n^3 grid vertices on the
+ * device and loads the result as an SDF grid (the same object as
+ * grasp_load_sdf with those values), usable by every step form. */
+grasp_status grasp_load_sdf_from_mesh(grasp_ctx* ctx, grasp_mesh_id mesh, const grasp_mesh_grid_desc* desc,
+                                      grasp_sdf_id* out);
+
+/* ---------------------------------------------------------------------------
  * The step (Sec. III-C, Sec. IV-A)
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -153,7 +202,8 @@ typedef struct {
   float r_dil;       /* SDF dilation radius of this step (Sec. III-B), >= 0 */
   float alpha_leak;  /* leaky-gradient factor (Sec. III-C), 0.1 in the paper; 0 = exact */
   float w_stable, w_pen, w_range, w_limit; /* loss weights */
-  float w_min;       /* constraints with J M^-1 J^T <= w_min are skipped (1e-12) */
+  float w_min;       /* constraints with J M^-1 J^T <= w_min are skipped (1e-8: below it the trilinear
+                        gradient is single-precision rounding noise) */
   int32_t mode;      /* GRASP_MODE_*: how grasp_step_fwd/bwd share state */
 } grasp_step_params;
 
@@ -164,7 +214,7 @@ enum {
 };
 
 /* Fills p with the defaults above (dt 1e-3, v0 1, K 1, ckpt 1, omega 1, r_dil 0,
- * alpha 0.1, weights 1 / 1e4 / 1e-2 / 1, w_min 1e-12, AUTO). */
+ * alpha 0.1, weights 1 / 1e4 / 1e-2 / 1, w_min 1e-8, AUTO). */
 void grasp_default_params(grasp_step_params* p);
 
 /* Host out: workspace bytes grasp_step_fwd/bwd need for B candidates in SAVE

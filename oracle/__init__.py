@@ -68,7 +68,7 @@ class Params:
     w_pen: float = 1e4
     w_range: float = 1e-2
     w_limit: float = 1.0
-    w_min: float = 1e-12
+    w_min: float = 1e-8
 
     def _c(self):
         return _Params(self.dt, self.v0, self.K, self.omega, self.r_dil, self.alpha_leak,
@@ -98,14 +98,15 @@ class Mesh:
 
 def mesh_sdf(mesh: Mesh, r):
     """Phong signed distance and the paper's gradient at points r [n][3], with
-    the flat closest point, its face, the flat distance and the medial gap."""
+    the flat closest point, its face, the flat distance, the medial gap and
+    the spread of Phong distances over faces tied at FP32 resolution."""
     r = np.ascontiguousarray(r, np.float64).reshape(-1, 3)
     n = r.shape[0]
     rho, grad, cl = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 3))
-    face, flat, gap = np.zeros(n, np.int32), np.zeros(n), np.zeros(n)
+    face, flat, gap, spread = np.zeros(n, np.int32), np.zeros(n), np.zeros(n), np.zeros(n)
     _check(lib().oracle_mesh_sdf(C.byref(mesh.c), n, _ptr(r), _ptr(rho), _ptr(grad), _ptr(cl), _ptr(face, C.c_int),
-                                 _ptr(flat), _ptr(gap)), "oracle_mesh_sdf")
-    return {"rho": rho, "grad": grad, "closest": cl, "face": face, "dist_flat": flat, "gap": gap}
+                                 _ptr(flat), _ptr(gap), _ptr(spread)), "oracle_mesh_sdf")
+    return {"rho": rho, "grad": grad, "closest": cl, "face": face, "dist_flat": flat, "gap": gap, "spread": spread}
 
 
 def winding_number(mesh: Mesh, r) -> float:
@@ -140,7 +141,7 @@ def lib():
                                   C.c_double, C.c_double]
         L.oracle_rank.argtypes = [C.c_int, dp, ip]
         mp = C.POINTER(_Mesh)
-        L.oracle_mesh_sdf.argtypes = [mp, C.c_int, dp, dp, dp, dp, ip, dp, dp]
+        L.oracle_mesh_sdf.argtypes = [mp, C.c_int, dp, dp, dp, dp, ip, dp, dp, dp]
         L.oracle_winding_number.argtypes = [mp, dp]
         L.oracle_winding_number.restype = C.c_double
         L.oracle_closest_on_triangle.argtypes = [dp, dp, dp, dp, dp, dp]

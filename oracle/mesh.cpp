@@ -87,6 +87,19 @@ double solid_angle(D3 a, D3 b, D3 c, D3 r) {
   return 2.0 * std::atan2(num, den);
 }
 
+// Phong point of face f's point y with barycentric weights w: the blend of
+// y and its projections onto the tangent planes of the face's vertices.
+D3 phong_point(const omesh* m, int f, D3 y, const double w[3]) {
+  const int* t = m->faces + 3 * f;
+  D3 curved{0, 0, 0};
+  for (int j = 0; j < 3; ++j) {
+    const D3 v = load(m->vertices + 3 * t[j]);
+    const D3 nv = load(m->normals + 3 * t[j]);
+    curved = curved + w[j] * (y - dot(y - v, nv) * nv);
+  }
+  return (1.0 - m->alpha) * y + m->alpha * curved;
+}
+
 }  // namespace
 
 extern "C" {
@@ -113,7 +126,7 @@ int oracle_closest_on_triangle(const double* a, const double* b, const double* c
 }
 
 int oracle_mesh_sdf(const omesh* m, int n, const double* r, double* rho, double* grad, double* closest,
-                    int* face, double* dist_flat, double* gap) {
+                    int* face, double* dist_flat, double* gap, double* spread) {
   if (!m || n < 0 || (n > 0 && (!r || !rho)) || m->n_faces < 1) return -1;
   for (int k = 0; k < n; ++k) {
     const D3 x = load(r + 3 * k);
@@ -151,15 +164,22 @@ int oracle_mesh_sdf(const omesh* m, int n, const double* r, double* rho, double*
     // Phong point: blend of the flat closest point and its projections onto
     // the tangent planes of the face's three vertices
     const int* t = m->faces + 3 * bf;
-    D3 curved{0, 0, 0};
-    for (int j = 0; j < 3; ++j) {
-      const D3 v = load(m->vertices + 3 * t[j]);
-      const D3 nv = load(m->normals + 3 * t[j]);
-      const D3 psi = bx - dot(bx - v, nv) * nv;
-      curved = curved + bb[j] * psi;
-    }
-    const D3 p = (1.0 - m->alpha) * bx + m->alpha * curved;
+    const D3 p = phong_point(m, bf, bx, bb);
     const double dist = norm(x - p);
+    if (spread) {
+      // faces whose flat distance is within single-precision resolution of
+      // the best one: how far apart their Phong distances lie
+      const double eps = 4e-7 * (best + norm(x));
+      double sp = 0.0;
+      for (int f = 0; f < m->n_faces; ++f) {
+        const int* u = m->faces + 3 * f;
+        double w[3];
+        const D3 y = closest_on_triangle(load(m->vertices + 3 * u[0]), load(m->vertices + 3 * u[1]),
+                                         load(m->vertices + 3 * u[2]), x, w);
+        if (norm(x - y) <= best + eps) sp = std::fmax(sp, std::fabs(norm(x - phong_point(m, f, y, w)) - dist));
+      }
+      spread[k] = sp;
+    }
     rho[k] = s * dist;
     if (grad) {
       D3 g;

@@ -86,10 +86,12 @@ typedef struct {
 /* Phong signed distance at n points r [n][3] (mesh.cpp): rho [n], grad [n][3]
    = (r - p) / rho, closest [n][3] = closest point of the flat mesh, face [n]
    its face, dist_flat [n] = |r - closest|, gap [n] = how much farther the
-   nearest different surface point is (0 on the medial axis); each output but
-   rho may be NULL. */
+   nearest different surface point is (0 on the medial axis), spread [n] =
+   the largest difference of Phong distances over faces whose flat distance
+   is within single-precision resolution of the best (4e-7 (|r - closest| +
+   |r|)); each output but rho may be NULL. */
 int oracle_mesh_sdf(const omesh* m, int n, const double* r, double* rho, double* grad, double* closest,
-                    int* face, double* dist_flat, double* gap);
+                    int* face, double* dist_flat, double* gap, double* spread);
 
 /* Generalized winding number of the mesh at r: 1 inside, 0 outside. */
 double oracle_winding_number(const omesh* m, const double* r);

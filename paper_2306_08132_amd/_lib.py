@@ -41,6 +41,16 @@ class SdfDesc(C.Structure):
 LAYOUT_AUTO, LAYOUT_YZQUADS, LAYOUT_ZPAIRS = 0, 1, 2
 
 
+class MeshDescC(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("vertices", C.POINTER(C.c_float)), ("normals", C.POINTER(C.c_float)),
+                ("n_faces", C.c_int32), ("faces", C.POINTER(C.c_int32)), ("alpha", C.c_float)]
+
+
+class MeshGridDescC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("lo", C.c_float * 3), ("h", C.c_float), ("inertia_over_mass", C.c_float),
+                ("layout", C.c_int32)]
+
+
 class TileC(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("min_waves_per_simd", C.c_int32)]
 
@@ -90,7 +100,7 @@ class StepParams:
     w_pen: float = 1e4
     w_range: float = 1e-2
     w_limit: float = 1.0
-    w_min: float = 1e-12
+    w_min: float = 1e-8
     mode: int = MODE_AUTO
 
     def c(self) -> StepParamsC:
@@ -110,6 +120,10 @@ SIGNATURES = [
     ("grasp_destroy_hand", _I32, [_VP, _U64]),
     ("grasp_hand_contact_links", _I32, [_VP, _U64, _IP]),
     ("grasp_load_sdf", _I32, [_VP, C.POINTER(SdfDesc), C.POINTER(_U64)]),
+    ("grasp_load_mesh", _I32, [_VP, C.POINTER(MeshDescC), C.POINTER(_U64)]),
+    ("grasp_unload_mesh", _I32, [_VP, _U64]),
+    ("grasp_mesh_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP]),
+    ("grasp_load_sdf_from_mesh", _I32, [_VP, _U64, C.POINTER(MeshGridDescC), C.POINTER(_U64)]),
     ("grasp_unload_sdf", _I32, [_VP, _U64]),
     ("grasp_sdf_inertia", _I32, [_VP, _U64, _FP]),
     ("grasp_default_params", None, [C.POINTER(StepParamsC)]),

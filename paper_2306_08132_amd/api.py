@@ -11,7 +11,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (BatchJobC, HandDesc, JobDescC, JobResultC, Library, SdfDesc, ServeStatsC, StepParams,
+from ._lib import (BatchJobC, HandDesc, JobDescC, JobResultC, Library, MeshDescC, MeshGridDescC, SdfDesc,
+                   ServeStatsC, StepParams,
                    TileC, GRASP_EAGAIN, MODE_AUTO, MODE_RECOMPUTE, MODE_SAVE, GraspError)
 
 __all__ = ["Context", "Hand", "Sdf", "StepParams", "GraspStep", "GraspError", "Batch", "BatchJob",
@@ -66,6 +67,9 @@ class Context:
 
     def sdf(self, grid, inertia_over_mass: float = 0.0, layout: int = 0) -> "Sdf":
         return Sdf(self, grid, inertia_over_mass, layout)
+
+    def mesh(self, mesh, alpha: float, normals: bool = True) -> "Mesh":
+        return Mesh(self, mesh, alpha, normals)
 
     # -- steps -----------------------------------------------------------------
     def workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
@@ -231,6 +235,13 @@ class Sdf:
         self.id = sid.value
         self.n = int(grid.n)
 
+    @classmethod
+    def resident(cls, ctx: Context, sid: int, n: int) -> "Sdf":
+        """A grid the library already holds (e.g. built from a mesh)."""
+        s = cls.__new__(cls)
+        s.ctx, s.id, s.n = ctx, sid, n
+        return s
+
     def inertia_over_mass(self) -> float:
         out = C.c_float()
         self.ctx.lib.call("grasp_sdf_inertia", self.ctx.h, self.id, C.byref(out))
@@ -238,6 +249,41 @@ class Sdf:
 
     def unload(self):
         self.ctx.lib.call("grasp_unload_sdf", self.ctx.h, self.id)
+
+
+class Mesh:
+    """A closed triangle mesh resident in a context (grasp_load_mesh): its
+    Phong signed distance (Sec. III-B) on the device."""
+
+    def __init__(self, ctx: Context, mesh, alpha: float, normals: bool = True):
+        self.ctx = ctx
+        self._v = _f32(mesh.vertices)
+        self._n = _f32(mesh.normals) if normals else None
+        self._f = np.ascontiguousarray(mesh.faces, np.int32)
+        fp = C.POINTER(C.c_float)
+        d = MeshDescC(self._v.shape[0], self._v.ctypes.data_as(fp),
+                      self._n.ctypes.data_as(fp) if self._n is not None else None, self._f.shape[0],
+                      self._f.ctypes.data_as(C.POINTER(C.c_int32)), float(alpha))
+        mid = C.c_uint64()
+        ctx.lib.call("grasp_load_mesh", ctx.h, C.byref(d), C.byref(mid))
+        self.id = mid.value
+
+    def sample(self, r, stream=None):
+        """(rho, grad rho) [n][4] at device points r [n][3]."""
+        out = torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
+        self.ctx.lib.call("grasp_mesh_sample", self.ctx.h, self.id, r.shape[0], _ptr(r), _ptr(out), _stream(stream))
+        return out
+
+    def grid(self, n: int, lo, h: float, layout: int = 0, inertia_over_mass: float = 0.0) -> "Sdf":
+        """An SDF grid of the Phong distance sampled on the device at n^3 vertices."""
+        d = MeshGridDescC(int(n), (C.c_float * 3)(*[float(x) for x in lo]), float(h), float(inertia_over_mass),
+                          int(layout))
+        sid = C.c_uint64()
+        self.ctx.lib.call("grasp_load_sdf_from_mesh", self.ctx.h, self.id, C.byref(d), C.byref(sid))
+        return Sdf.resident(self.ctx, sid.value, int(n))
+
+    def unload(self):
+        self.ctx.lib.call("grasp_unload_mesh", self.ctx.h, self.id)
 
 
 class GraspStep(torch.autograd.Function):

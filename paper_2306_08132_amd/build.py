@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libgrasp.so")
-SOURCES = ["step_kernels.hip", "plain_kernels.hip", "api.cpp", "arena.cpp", "batch.cpp", "sched.cpp"]
+SOURCES = ["step_kernels.hip", "plain_kernels.hip", "mesh_kernels.hip", "api.cpp", "arena.cpp", "batch.cpp", "sched.cpp",
+           "mesh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -3,6 +3,7 @@
 // that kernels only ever see shapes they were written for.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -166,7 +167,7 @@ void grasp_default_params(grasp_step_params* p) {
   p->w_pen = 1e4f;
   p->w_range = 1e-2f;
   p->w_limit = 1.0f;
-  p->w_min = 1e-12f;
+  p->w_min = 1e-8f;
   p->mode = GRASP_MODE_AUTO;
 }
 
@@ -328,6 +329,66 @@ grasp_status grasp_hand_contact_links(grasp_ctx* ctx, grasp_hand_id id, int32_t*
   return GRASP_OK;
 }
 
+}  // extern "C"
+
+namespace grasp {
+
+grasp_status install_grid(grasp_ctx* ctx, int n_, const float lo[3], float h, double Im, int layout_req,
+                          const std::function<hipError_t(float*)>& fill, grasp_sdf_id* out) {
+  const size_t n = static_cast<size_t>(n_);
+  const size_t n3 = n * n * n;
+  const size_t nc = n - 1;
+  const size_t vbytes = round_up(n3 * sizeof(float), 256);
+  if (layout_req < GRASP_LAYOUT_AUTO || layout_req > GRASP_LAYOUT_ZPAIRS) return fail(GRASP_EINVAL, "unknown layout");
+  const int layout = layout_req == GRASP_LAYOUT_ZPAIRS ? kLayoutZPairs : kLayoutYZQuads;
+  // z-pairs: [n-1][n][n] x 8 bytes; yz-quads: [n-1][n-1][n] x 16 bytes
+  const size_t cbytes = layout == kLayoutZPairs ? n * n * nc * 2 * sizeof(float) : n * nc * nc * 4 * sizeof(float);
+  const int nb = static_cast<int>((nc + kBlockCells - 1) / kBlockCells);
+  const size_t bbytes = round_up(static_cast<size_t>(nb) * nb * nb * sizeof(float), 256);
+  DeviceGuard g(ctx->device);
+  if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  void* blk = ctx->arena.alloc(vbytes + bbytes + cbytes);
+  if (!blk) return fail(GRASP_ENOMEM, "arena full (SDF grid)");
+  char* b = static_cast<char*>(blk);
+  hipError_t e = fill(reinterpret_cast<float*>(b));
+  if (e == hipSuccess)
+    e = launch_build_gather(reinterpret_cast<const float*>(b), n_, layout,
+                            reinterpret_cast<float4*>(b + vbytes + bbytes), nullptr);
+  if (e == hipSuccess)
+    e = launch_build_bmin(reinterpret_cast<const float*>(b), n_, reinterpret_cast<float*>(b + vbytes), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ctx->arena.free(blk);
+    return device_fail(ctx, e, "SDF upload");
+  }
+  auto s = std::make_unique<DevSdf>();
+  s->view.n = n_;
+  s->view.lo[0] = lo[0];
+  s->view.lo[1] = lo[1];
+  s->view.lo[2] = lo[2];
+  s->view.h = h;
+  s->view.inv_h = 1.0f / h;
+  s->view.inv_Im = static_cast<float>(1.0 / Im);
+  s->view.values = reinterpret_cast<const float*>(b);
+  s->view.cells = reinterpret_cast<const float4*>(b + vbytes + bbytes);
+  s->view.cells_bytes = static_cast<uint32_t>(cbytes);
+  s->view.layout = layout;
+  s->view.bmin = reinterpret_cast<const float*>(b + vbytes);
+  s->view.nb = nb;
+  s->block = blk;
+  s->bytes = vbytes + bbytes + cbytes;
+  s->inertia_over_mass = static_cast<float>(Im);
+  const uint64_t id = ctx->next_id++;
+  ctx->sdfs[id] = std::move(s);
+  *out = id;
+  return GRASP_OK;
+}
+
+}  // namespace grasp
+
+extern "C" {
+
 // ---------------------------------------------------------------------------
 // SDF grids
 // ---------------------------------------------------------------------------
@@ -354,52 +415,10 @@ grasp_status grasp_load_sdf(grasp_ctx* ctx, const grasp_sdf_desc* d, grasp_sdf_i
     const double Req = std::cbrt(3.0 * V / (4.0 * M_PI));
     Im = 0.4 * Req * Req;
   }
-  const size_t nc = n - 1;
-  const size_t vbytes = round_up(n3 * sizeof(float), 256);
-  if (d->layout < GRASP_LAYOUT_AUTO || d->layout > GRASP_LAYOUT_ZPAIRS) return fail(GRASP_EINVAL, "unknown layout");
-  const int layout = d->layout == GRASP_LAYOUT_ZPAIRS ? kLayoutZPairs : kLayoutYZQuads;
-  // z-pairs: [n-1][n][n] x 8 bytes; yz-quads: [n-1][n-1][n] x 16 bytes
-  const size_t cbytes = layout == kLayoutZPairs ? n * n * nc * 2 * sizeof(float) : n * nc * nc * 4 * sizeof(float);
-  const int nb = static_cast<int>((nc + kBlockCells - 1) / kBlockCells);
-  const size_t bbytes = round_up(static_cast<size_t>(nb) * nb * nb * sizeof(float), 256);
-  DeviceGuard g(ctx->device);
-  if (!g.ok()) return fail(GRASP_EDEVICE, "hipSetDevice failed");
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  void* blk = ctx->arena.alloc(vbytes + bbytes + cbytes);
-  if (!blk) return fail(GRASP_ENOMEM, "arena full (SDF grid)");
-  char* b = static_cast<char*>(blk);
-  hipError_t e = hipMemcpy(b, d->values, n3 * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = launch_build_gather(reinterpret_cast<const float*>(b), d->n, layout,
-                           reinterpret_cast<float4*>(b + vbytes + bbytes), nullptr);
-  if (e == hipSuccess)
-    e = launch_build_bmin(reinterpret_cast<const float*>(b), d->n, reinterpret_cast<float*>(b + vbytes), nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    ctx->arena.free(blk);
-    return device_fail(ctx, e, "SDF upload");
-  }
-  auto s = std::make_unique<DevSdf>();
-  s->view.n = d->n;
-  s->view.lo[0] = d->lo[0];
-  s->view.lo[1] = d->lo[1];
-  s->view.lo[2] = d->lo[2];
-  s->view.h = d->h;
-  s->view.inv_h = 1.0f / d->h;
-  s->view.inv_Im = static_cast<float>(1.0 / Im);
-  s->view.values = reinterpret_cast<const float*>(b);
-  s->view.cells = reinterpret_cast<const float4*>(b + vbytes + bbytes);
-  s->view.cells_bytes = static_cast<uint32_t>(cbytes);
-  s->view.layout = layout;
-  s->view.bmin = reinterpret_cast<const float*>(b + vbytes);
-  s->view.nb = nb;
-  s->block = blk;
-  s->bytes = vbytes + bbytes + cbytes;
-  s->inertia_over_mass = static_cast<float>(Im);
-  const uint64_t id = ctx->next_id++;
-  ctx->sdfs[id] = std::move(s);
-  *out = id;
-  return GRASP_OK;
+  const float* host = d->values;
+  return install_grid(ctx, d->n, d->lo, d->h, Im, d->layout,
+                      [&](float* dev) { return hipMemcpy(dev, host, n3 * sizeof(float), hipMemcpyHostToDevice); },
+                      out);
 }
 
 grasp_status grasp_unload_sdf(grasp_ctx* ctx, grasp_sdf_id id) {

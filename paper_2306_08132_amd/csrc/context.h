@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <functional>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -39,6 +40,13 @@ struct DevSdf {
   int live_jobs = 0;
 };
 
+struct DevMesh {
+  MeshView view{};
+  void* block = nullptr;
+  size_t bytes = 0;
+  double volume = 0.0;  // enclosed volume (divergence theorem)
+};
+
 struct Scheduler;  // serving loop (sched.cpp)
 
 }  // namespace grasp
@@ -51,6 +59,7 @@ struct grasp_ctx {
   std::mutex mu;  // guards the arena and the object tables
   std::map<uint64_t, std::unique_ptr<grasp::DevHand>> hands;
   std::map<uint64_t, std::unique_ptr<grasp::DevSdf>> sdfs;
+  std::map<uint64_t, std::unique_ptr<grasp::DevMesh>> meshes;
   uint64_t next_id = 1;
   std::atomic<bool> poisoned{false};
   std::map<std::string, grasp::TileCfg> tiles;  // tuned launch shapes per problem shape
@@ -85,6 +94,12 @@ grasp_status device_fail(grasp_ctx* ctx, hipError_t e, const char* where);
 // Looks up resident objects (caller holds ctx->mu).
 DevHand* find_hand(grasp_ctx* ctx, grasp_hand_id id);
 DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id);
+
+// Allocates a grid block (values, block table, gather copy), lets fill write
+// the n^3 values at its start (on the device), builds the rest and registers
+// the grid. Validation of n, lo, h and the values is the caller's.
+grasp_status install_grid(grasp_ctx* ctx, int n, const float lo[3], float h, double Im, int layout,
+                          const std::function<hipError_t(float*)>& fill, grasp_sdf_id* out);
 
 // Checks one batch job and resolves its hand, grid and constants.
 grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c);

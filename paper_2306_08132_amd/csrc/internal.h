@@ -190,6 +190,28 @@ hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone,
 // The same for every job of a batch table whose order pointer is set.
 hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int max_jobs, hipStream_t stream);
 
+// A triangle mesh resident on the device (Sec. III-B): a bounding-volume
+// hierarchy in depth-first order and per-face records.
+//  nodes: [n_nodes][2] float4 (lo.xyz, a), (hi.xyz, count): a leaf (count > 0)
+//         holds faces [a, a + count); an internal node (count = 0) has its
+//         children at node + 1 and a
+//  tri:   [n_faces][3] float4 vertex positions (xyz), faces in leaf order
+//  info:  [n_faces][kMeshInfo] floats: Phong normals of the three vertices,
+//         face normal, pseudonormals of edges ab, bc, ca and of vertices a, b, c
+struct MeshView {
+  const float4* nodes;
+  const float4* tri;
+  const float* info;
+  int n_nodes;
+  int n_faces;
+  float alpha;  // Phong blend
+};
+constexpr int kMeshInfo = 32;
+constexpr int kMeshStack = 32;  // traversal stack entries; the hierarchy is kept shallower
+hipError_t launch_mesh_sample(const MeshView& M, int n, const float* r, float* out4, hipStream_t stream);
+hipError_t launch_mesh_fill_grid(const MeshView& M, int n, const float lo[3], float h, float* values,
+                                 hipStream_t stream);
+
 hipError_t launch_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c,
                        hipStream_t stream);
 hipError_t launch_build_gather(const float* values, int n, int layout, float4* cells, hipStream_t stream);

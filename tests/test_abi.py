@@ -77,7 +77,8 @@ def test_binding_structs_match_the_c_layout(lib):
     offsets (a field added on one side only would shift the others)."""
     pairs = [("grasp_hand_desc", lib.HandDesc), ("grasp_sdf_desc", lib.SdfDesc), ("grasp_step_params", lib.StepParamsC),
              ("grasp_tile", lib.TileC), ("grasp_batch_job", lib.BatchJobC), ("grasp_job_desc", lib.JobDescC),
-             ("grasp_job_result", lib.JobResultC), ("grasp_serve_stats", lib.ServeStatsC)]
+             ("grasp_job_result", lib.JobResultC), ("grasp_serve_stats", lib.ServeStatsC),
+             ("grasp_mesh_desc", lib.MeshDescC), ("grasp_mesh_grid_desc", lib.MeshGridDescC)]
     structs = [(cname, [f for f, *_ in py._fields_]) for cname, py in pairs]
     got = _c_layout(structs)
     for cname, py in pairs:
