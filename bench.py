@@ -11,8 +11,8 @@ Prints one JSON line: contact-evaluations per second (forward + backward),
 the roofline of the step kernel and the FP64 oracle timed on the host, with
 the other workloads beside them: the plain per-job form on the same
 candidates, a Poisson stream of jobs through the serving loop, 16 uneven
-jobs in one batched launch per step, and K = 16 projection iterations on
-65536 candidates (256^3 grid).
+jobs in one batched launch per step, K = 16 projection iterations on 65536
+candidates (256^3 grid), and Phong signed-distance queries on mesh objects.
 """
 from __future__ import annotations
 
@@ -234,6 +234,41 @@ def large_run(ctx, S, args):
     return out
 
 
+def mesh_run(ctx, S, args):
+    """The mesh object of Sec. III-B: Phong signed-distance queries through the
+    bounding-volume hierarchy (one lane per point) on ellipsoid meshes of
+    5120 and 81920 faces, and a 128^3 grid filled from a mesh on the device."""
+    import numpy as np
+    import torch
+    print("bench: mesh objects", file=sys.stderr, flush=True)
+    out = {}
+    rng = np.random.default_rng(11)
+    for sub in (4, 6):
+        m = S.mesh_ellipsoid([0.04, 0.025, 0.035], subdivisions=sub)
+        gm = ctx.mesh(m, 0.75)
+        R = m.bound_radius()
+        r = torch.as_tensor(rng.uniform(-1.5 * R, 1.5 * R, size=(1 << 20, 3)).astype(np.float32), device="cuda:0")
+        gm.sample(r)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gm.sample(r)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[f"faces_{m.faces.shape[0]}"] = {"queries_per_s": r.shape[0] / dt, "ms_per_million": dt * 1e3 / (r.shape[0] / 1e6)}
+        if sub == 4:
+            n = 128
+            t0 = time.perf_counter()
+            sd = gm.grid(n, (-0.06, -0.06, -0.06), 0.12 / (n - 1))
+            torch.cuda.synchronize()
+            out["grid_128_from_5120_faces_s"] = time.perf_counter() - t0
+            sd.unload()
+        gm.unload()
+    print(f"bench: mesh queries {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +282,7 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=60, help="optimizer steps per served job")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
     ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh-object queries")
     ap.add_argument("--tile", type=str, default=None,
                     help="launch tile 'waves_per_block,min_waves_per_simd' instead of tuning (profiled runs: "
                          "every step dispatch is then a timed shape)")
@@ -354,6 +390,7 @@ def main():
         serving = serving_run(ctx, S, n_jobs=args.serve_jobs, rate=args.serve_rate, steps=args.serve_steps)
     batched = None if args.no_batched else batched_run(ctx, S, args)
     large = None if args.no_large else large_run(ctx, S, args)
+    mesh = None if args.no_mesh else mesh_run(ctx, S, args)
 
     cpu = None
     if not args.no_cpu:
@@ -386,6 +423,7 @@ def main():
         "serving": serving,
         "batched": batched,
         "large": large,
+        "mesh": mesh,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
