@@ -196,11 +196,29 @@ def batched_run(ctx, S, args):
             ctx.step_fused(h, sd, StepParams(r_dil=0.01), q, m, v, t + 2)
     torch.cuda.synchronize()
     ts = (time.perf_counter() - t0) / (args.steps // 5 + 3)
+    # the same jobs in the plain per-job form: unfused stages, HBM
+    # intermediates, one set of launches per job per step
+    ws = ctx.plain_workspace(h, jobs[0][0], StepParams(r_dil=0.01), max(q.shape[0] for _, q in jobs))
+    pj = [(sd, q.clone(), torch.zeros_like(q), torch.zeros_like(q), torch.empty(q.shape[0], device=q.device))
+          for sd, q in jobs]
+    for sd, q, m, v, lp in pj:
+        ctx.plain_step(h, sd, StepParams(r_dil=0.01), q, m, v, 1, ws, loss=lp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_plain = max(3, args.steps // 10)
+    for t in range(n_plain):
+        for sd, q, m, v, lp in pj:
+            ctx.plain_step(h, sd, StepParams(r_dil=0.01), q, m, v, t + 2, ws, loss=lp)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / n_plain
+    del ws
     b.close()
+    print(f"bench: batched {tb * 1e3:.2f} ms/step, per-job fused {ts * 1e3:.2f}, per-job plain {tp * 1e3:.2f}",
+          file=sys.stderr, flush=True)
     return {"jobs": 16, "candidates": cap, "contact_evals_per_step": evals, "ms_per_step": tb * 1e3,
             "contact_evals_per_s": evals / tb, "per_job_launches_ms_per_step": ts * 1e3,
-            "batched_over_per_job": ts / tb, "algorithmic_bytes_per_step": abytes,
-            "roofline_frac": abytes / tb / (HBM_PEAK_GBS * 1e9)}
+            "batched_over_per_job": ts / tb, "plain_per_job_ms_per_step": tp * 1e3, "batched_over_plain": tp / tb,
+            "algorithmic_bytes_per_step": abytes, "roofline_frac": abytes / tb / (HBM_PEAK_GBS * 1e9)}
 
 
 def large_run(ctx, S, args):
