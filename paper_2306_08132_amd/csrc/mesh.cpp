@@ -7,7 +7,6 @@
 #include <array>
 #include <cmath>
 #include <cstring>
-#include <map>
 #include <numeric>
 #include <utility>
 #include <vector>
@@ -152,15 +151,24 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
     }
   }
   if (!(volume > 0.0)) return fail(GRASP_EINVAL, "mesh must enclose a positive volume (faces counter-clockwise from outside)");
-  // every directed edge once, and its reverse exactly once
-  std::map<std::pair<int, int>, int> edge_face;
+  // every directed edge once, and its reverse exactly once: directed edges
+  // as (u V + v, face) sorted by key
+  std::vector<std::pair<uint64_t, int>> edges;
+  edges.reserve(3 * static_cast<size_t>(F));
+  auto key = [V](int u, int v) { return static_cast<uint64_t>(u) * static_cast<uint64_t>(V) + static_cast<uint64_t>(v); };
   for (int f = 0; f < F; ++f)
-    for (int j = 0; j < 3; ++j) {
-      const std::pair<int, int> e{d->faces[3 * f + j], d->faces[3 * f + (j + 1) % 3]};
-      if (!edge_face.emplace(e, f).second) return fail(GRASP_EINVAL, "mesh is not consistently oriented");
-    }
-  for (const auto& kv : edge_face)
-    if (!edge_face.count({kv.first.second, kv.first.first}))
+    for (int j = 0; j < 3; ++j) edges.emplace_back(key(d->faces[3 * f + j], d->faces[3 * f + (j + 1) % 3]), f);
+  std::sort(edges.begin(), edges.end());
+  for (size_t i = 1; i < edges.size(); ++i)
+    if (edges[i].first == edges[i - 1].first) return fail(GRASP_EINVAL, "mesh is not consistently oriented");
+  // the face across directed edge (u, v): the one holding (v, u), or -1
+  auto across = [&](int u, int v) {
+    const uint64_t k = key(v, u);
+    const auto it = std::lower_bound(edges.begin(), edges.end(), std::make_pair(k, -1));
+    return it != edges.end() && it->first == k ? it->second : -1;
+  };
+  for (const auto& e : edges)
+    if (across(static_cast<int>(e.first / V), static_cast<int>(e.first % V)) < 0)
       return fail(GRASP_EINVAL, "mesh is not closed (an edge has one face)");
   // angle-weighted vertex pseudonormals
   std::vector<D3> vn(V, D3{0, 0, 0});
@@ -210,7 +218,7 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
     put(3, fn[f]);
     for (int j = 0; j < 3; ++j) {
       // edge (t[j], t[j+1]) and the face across it
-      const int g = edge_face.at({t[(j + 1) % 3], t[j]});
+      const int g = across(t[j], t[(j + 1) % 3]);
       put(4 + j, unit(add(fn[f], fn[g])));
       put(7 + j, vn[t[j]]);
     }
