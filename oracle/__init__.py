@@ -140,6 +140,9 @@ def lib():
         L.oracle_adam.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_double]
         L.oracle_rank.argtypes = [C.c_int, dp, ip]
+        L.oracle_evaluate.argtypes = [hp, op, C.c_int, dp, C.POINTER(_Eval), C.c_int, dp, C.c_double, dp, dp,
+                                      C.c_int]
+        L.oracle_select_top.argtypes = [C.c_int, dp, C.c_int, C.c_int, C.c_int, dp, ip, dp]
         mp = C.POINTER(_Mesh)
         L.oracle_mesh_sdf.argtypes = [mp, C.c_int, dp, dp, dp, dp, ip, dp, dp, dp]
         L.oracle_winding_number.argtypes = [mp, dp]
@@ -287,6 +290,53 @@ def rank(loss):
     r = np.zeros(loss.shape[0], np.int32)
     _check(lib().oracle_rank(loss.shape[0], _ptr(loss), _ptr(r, C.c_int)), "oracle_rank")
     return r
+
+
+class _Eval(C.Structure):
+    _fields_ = [("n_surface", C.c_int), ("surface_link", C.POINTER(C.c_int)),
+                ("surface_local", C.POINTER(C.c_double)), ("surface_area", C.POINTER(C.c_double)),
+                ("n_volume", C.c_int), ("volume_link", C.POINTER(C.c_int)),
+                ("volume_local", C.POINTER(C.c_double)), ("volume_weight", C.POINTER(C.c_double))]
+
+
+class EvalPoints:
+    """Oracle view of weighted hand samples (any object with the
+    synth.EvalPoints fields)."""
+
+    def __init__(self, e):
+        self.sl = np.ascontiguousarray(e.surface_link, dtype=np.int32)
+        self.sp = _d(e.surface_local).reshape(-1, 3)
+        self.sa = _d(e.surface_area)
+        self.vl = np.ascontiguousarray(e.volume_link, dtype=np.int32)
+        self.vp = _d(e.volume_local).reshape(-1, 3)
+        self.vw = _d(e.volume_weight)
+        self.c = _Eval(self.sl.shape[0], _ptr(self.sl, C.c_int), _ptr(self.sp), _ptr(self.sa),
+                       self.vl.shape[0], _ptr(self.vl, C.c_int), _ptr(self.vp), _ptr(self.vw))
+
+
+def evaluate(hand: Hand, obj: Obj, q, ev: EvalPoints, thresholds, delta: float = 0.0, threads: int = 0):
+    """Contact area at each threshold and intersection volume [B][T + 1], and
+    the weight of samples within delta of each threshold [B][T + 1]."""
+    q = _d(q).reshape(-1, hand.n_dof)
+    thr = _d(thresholds).reshape(-1)
+    B, M = q.shape[0], thr.shape[0] + 1
+    out, slack = np.zeros((B, M)), np.zeros((B, M))
+    _check(lib().oracle_evaluate(C.byref(hand.c), C.byref(obj.c), B, _ptr(q), C.byref(ev.c), thr.shape[0],
+                                 _ptr(thr), delta, _ptr(out), _ptr(slack), threads), "oracle_evaluate")
+    return out, slack
+
+
+def select_top(key, k: int, higher_is_better: bool = False, metrics=None):
+    """Indices of the k best keys (NaN last, ties by index) and the mean of
+    metrics [B][M] over them."""
+    key = _d(key).reshape(-1)
+    B = key.shape[0]
+    met = _d(np.zeros((B, 0)) if metrics is None else metrics).reshape(B, -1)
+    top = np.zeros(k, np.int32)
+    mean = np.zeros(met.shape[1])
+    _check(lib().oracle_select_top(B, _ptr(key), int(higher_is_better), k, met.shape[1], _ptr(met),
+                                   _ptr(top, C.c_int), _ptr(mean)), "oracle_select_top")
+    return top, mean
 
 
 def optimize(hand: Hand, obj: Obj, prm: Params, q0, T: int, r0: float = 0.01, lr=1e-3, b1=0.9,

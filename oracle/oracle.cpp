@@ -706,6 +706,91 @@ int oracle_rank(int B, const double* loss, int* rank) {
   return 0;
 }
 
+// Post-synthesis metrics (Sec. V-A). The paper names contact area and
+// intersection volume without formulas; read here as integrals over the
+// hand: CA(tau) = area of the hand surface whose signed distance to the
+// object is below tau (penetrating surface is in contact), IV = volume of the
+// hand whose signed distance is below 0, each estimated by the caller's
+// weighted samples placed by forward kinematics at the candidate's q.
+int oracle_evaluate(const ohand* hand, const oobject* obj, int B, const double* q, const oeval* ev, int n_thr,
+                    const double* thr, double delta, double* out, double* slack, int n_threads) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !ev || B < 0 || n_thr < 0 || (B > 0 && (!q || !out)) ||
+      (n_thr > 0 && !thr) || ev->n_surface < 0 || ev->n_volume < 0 || !(delta >= 0.0))
+    return -1;
+  if ((ev->n_surface > 0 && (!ev->surface_link || !ev->surface_local || !ev->surface_area)) ||
+      (ev->n_volume > 0 && (!ev->volume_link || !ev->volume_local || !ev->volume_weight)))
+    return -1;
+  for (int i = 0; i < ev->n_surface; ++i)
+    if (ev->surface_link[i] < 0 || ev->surface_link[i] >= hand->n_links) return -1;
+  for (int i = 0; i < ev->n_volume; ++i)
+    if (ev->volume_link[i] < 0 || ev->volume_link[i] >= hand->n_links) return -1;
+  const int nd = 6 + hand->n_links - 1, M = n_thr + 1;
+  const int nt = set_threads(n_threads);
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int b = 0; b < B; ++b) {
+    const double* qb = q + static_cast<size_t>(b) * nd;
+    double* o = out + static_cast<size_t>(b) * M;
+    double* s = slack ? slack + static_cast<size_t>(b) * M : nullptr;
+    for (int t = 0; t < M; ++t) {
+      o[t] = 0.0;
+      if (s) s[t] = 0.0;
+    }
+    bool finite = true;
+    for (int j = 0; j < nd; ++j) finite = finite && std::isfinite(qb[j]);
+    if (!finite) {
+      for (int t = 0; t < M; ++t) o[t] = std::nan("");
+      continue;
+    }
+    std::vector<Xf<double>> T;
+    forward_kinematics(*hand, qb, T);
+    auto phi_at = [&](int link, const double* local) {
+      double p[3], n3[3], phi;
+      apply_xf(T[link], local, p);
+      sample_object(*obj, p, phi, n3, nullptr);
+      return phi;
+    };
+    for (int i = 0; i < ev->n_surface; ++i) {
+      const double phi = phi_at(ev->surface_link[i], ev->surface_local + 3 * i);
+      const double a = ev->surface_area[i];
+      for (int t = 0; t < n_thr; ++t) {
+        if (phi < thr[t]) o[t] += a;
+        if (s && std::fabs(phi - thr[t]) < delta) s[t] += a;
+      }
+    }
+    for (int i = 0; i < ev->n_volume; ++i) {
+      const double phi = phi_at(ev->volume_link[i], ev->volume_local + 3 * i);
+      const double v = ev->volume_weight[i];
+      if (phi < 0.0) o[n_thr] += v;
+      if (s && std::fabs(phi) < delta) s[n_thr] += v;
+    }
+  }
+  return 0;
+}
+
+// Top-k selection behind the paper's top-10 figures (Sec. V-A): the paper
+// ranks by the epsilon metric; here the caller supplies the key.
+int oracle_select_top(int B, const double* key, int higher_is_better, int k, int M, const double* metrics,
+                      int* top, double* mean) {
+  if (B < 0 || k < 0 || k > B || M < 0 || (B > 0 && !key) || (k > 0 && !top) || (M > 0 && k > 0 && (!metrics || !mean)))
+    return -1;
+  auto better = [&](int a, int b) {
+    const bool na = std::isnan(key[a]), nb = std::isnan(key[b]);
+    if (na || nb) return !na && nb;
+    return higher_is_better ? key[a] > key[b] : key[a] < key[b];
+  };
+  std::vector<int> idx(B);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), better);
+  for (int j = 0; j < k; ++j) top[j] = idx[j];
+  for (int m = 0; m < M && k > 0; ++m) {
+    double sum = 0.0;
+    for (int j = 0; j < k; ++j) sum += metrics[static_cast<size_t>(top[j]) * M + m];
+    mean[m] = sum / k;
+  }
+  return 0;
+}
+
 int oracle_optimize(const ohand* hand, const oobject* obj, const oparams* prm, int B, double* q, int T, double r0,
                     double lr, double b1, double b2, double eps, int use_gd, double* final_loss, double* final_terms,
                     int* rank, double* loss_hist, int n_threads) {

@@ -147,6 +147,37 @@ int oracle_optimize(const ohand* hand, const oobject* obj, const oparams* prm, i
                     double* final_loss, double* final_terms, int* rank, double* loss_hist,
                     int n_threads);
 
+/* Weighted samples of the hand for the evaluation metrics: surface samples
+   with the area each stands for, volume samples with their volume; link-local
+   coordinates. */
+typedef struct {
+  int n_surface;
+  const int* surface_link;       /* [n_surface] */
+  const double* surface_local;   /* [n_surface][3] */
+  const double* surface_area;    /* [n_surface] */
+  int n_volume;
+  const int* volume_link;        /* [n_volume] */
+  const double* volume_local;    /* [n_volume][3] */
+  const double* volume_weight;   /* [n_volume] */
+} oeval;
+
+/* Post-synthesis metrics of B candidates q [B][n_dof] against the object at
+   rest (Sec. V-A): out [B][n_thr + 1] = contact area at each threshold
+   thr[t] (total area of surface samples whose signed distance is below
+   thr[t]) and the intersection volume (total volume of volume samples whose
+   signed distance is below 0). slack [B][n_thr + 1] (or NULL) = the weight of
+   the samples whose signed distance lies within delta of the threshold (of 0
+   for the volume). A candidate with a non-finite coordinate gets NaN. */
+int oracle_evaluate(const ohand* hand, const oobject* obj, int B, const double* q, const oeval* ev, int n_thr,
+                    const double* thr, double delta, double* out, double* slack, int n_threads);
+
+/* The k best of B candidates by key (ascending, or descending when
+   higher_is_better), NaN keys after all others, equal keys by index:
+   top [k]; mean [M] = the average of metrics [B][M] over them, summed in
+   rank order. */
+int oracle_select_top(int B, const double* key, int higher_is_better, int k, int M, const double* metrics,
+                      int* top, double* mean);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,7 @@ class Hand:
     joint_world_axis: np.ndarray     # [L][3] joint axes in the world at q = 0
     n_fingers: int = 0
     joints_per_finger: int = 0
+    capsules: np.ndarray | None = None  # [L][7] world capsule of each link at q = 0: a, b, radius
 
     @property
     def n_links(self) -> int:
@@ -203,7 +204,116 @@ def make_hand(n_fingers: int, joints_per_finger: int, n_contacts: int, seed: int
                 q_low=np.array(lim_lo), q_up=np.array(lim_up), contact_local=local,
                 contact_link=link.astype(np.int32), contact_rest_world=world,
                 link_rest_R=rest_R, link_rest_o=rest_o, joint_world_axis=waxis,
-                n_fingers=F, joints_per_finger=J)
+                n_fingers=F, joints_per_finger=J,
+                capsules=np.array([np.concatenate([a, b, [r]]) for a, b, r in caps]))
+
+
+@dataclasses.dataclass
+class EvalPoints:
+    """Weighted samples of a hand's surface and volume for the evaluation
+    metrics: surface samples carry the area they stand for (m^2), volume
+    samples the volume (m^3); coordinates in the frame of their link."""
+    surface_link: np.ndarray    # [Ns] int32
+    surface_local: np.ndarray   # [Ns][3]
+    surface_area: np.ndarray    # [Ns]
+    volume_link: np.ndarray     # [Nv] int32
+    volume_local: np.ndarray    # [Nv][3]
+    volume_weight: np.ndarray   # [Nv]
+    surface_rest: np.ndarray    # [Ns][3] world positions at q = 0 (for tests)
+    volume_rest: np.ndarray     # [Nv][3]
+
+    def as_f32(self) -> "EvalPoints":
+        f = lambda a: a.astype(np.float32).astype(np.float64)
+        return dataclasses.replace(self, surface_local=f(self.surface_local), surface_area=f(self.surface_area),
+                                   volume_local=f(self.volume_local), volume_weight=f(self.volume_weight))
+
+
+def _segment_distance(p, a, b):
+    ab = b - a
+    t = np.clip(((p - a) @ ab) / (ab @ ab), 0.0, 1.0)
+    return np.linalg.norm(p - (a + t[:, None] * ab), axis=1)
+
+
+def _cap_height(v, radius):
+    """Height h in [0, r] of the spherical cap of volume v (pi h^2 (3r - h) / 3,
+    increasing in h), by bisection."""
+    lo = np.zeros_like(v)
+    hi = np.full_like(v, radius)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        below = math.pi * mid * mid * (3.0 * radius - mid) / 3.0 < v
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def _capsule_volume_points(rng, a, b, radius, n):
+    """n points inside the capsule a->b, stratified by volume along the axis
+    (cap, cylinder, cap), uniform over the disc at each axial position."""
+    axis = b - a
+    length = float(np.linalg.norm(axis))
+    z = axis / length
+    tmp = np.array([1.0, 0.0, 0.0]) if abs(z[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    x = np.cross(z, tmp)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    cap = 2.0 * math.pi * radius ** 3 / 3.0
+    cyl = math.pi * radius * radius * length
+    total = 2.0 * cap + cyl
+    v = (np.arange(n) + rng.random(n)) / n * total
+    t = np.empty(n)  # axial coordinate from a
+    m0 = v < cap
+    m2 = v >= cap + cyl
+    m1 = ~(m0 | m2)
+    t[m0] = -radius + _cap_height(v[m0], radius)
+    t[m1] = (v[m1] - cap) / (math.pi * radius * radius)
+    t[m2] = length + radius - _cap_height(total - v[m2], radius)
+    off = np.clip(np.where(t < 0.0, -t, np.where(t > length, t - length, 0.0)), 0.0, radius)
+    disc = np.sqrt(radius * radius - off * off)
+    s = disc * np.sqrt(rng.random(n))
+    az = rng.random(n) * 2.0 * math.pi
+    return a + t[:, None] * z + (s * np.cos(az))[:, None] * x + (s * np.sin(az))[:, None] * y
+
+
+def make_eval_points(hand: Hand, n_surface: int, n_volume: int, seed: int) -> EvalPoints:
+    """Surface and volume samples of the capsule hand for contact area and
+    intersection volume (Sec. V-A metrics).
+
+    Each link's capsule gets a share of the samples proportional to its area
+    (volume), stratified along its axis; a sample weighs the capsule's area
+    (volume) over its share. A surface sample strictly inside another link's
+    capsule, and a volume sample strictly inside a lower-numbered link's
+    capsule, is dropped, so the weights cover the union of the capsules at
+    q = 0 once (collinear links of a straight finger form one capsule)."""
+    rng = np.random.default_rng(seed)
+    caps = [(c[0:3], c[3:6], float(c[6])) for c in hand.capsules]
+    L = len(caps)
+    areas = [2 * math.pi * r * np.linalg.norm(b - a) + 4 * math.pi * r * r for a, b, r in caps]
+    vols = [math.pi * r * r * np.linalg.norm(b - a) + 4.0 * math.pi * r ** 3 / 3.0 for a, b, r in caps]
+    ns = _split_counts(areas, n_surface)
+    nv = _split_counts(vols, n_volume) if n_volume > 0 else np.zeros(L, np.int64)
+    out = {}
+    for kind, counts, size, gen in (("surface", ns, areas, _capsule_points), ("volume", nv, vols, _capsule_volume_points)):
+        pts, links, wts = [], [], []
+        for l, ((a, b, r), n) in enumerate(zip(caps, counts)):
+            if n == 0:
+                continue
+            p = gen(rng, a, b, r, int(n))
+            others = [k for k in range(L) if k != l] if kind == "surface" else list(range(l))
+            keep = np.ones(len(p), bool)
+            for k in others:
+                keep &= _segment_distance(p, caps[k][0], caps[k][1]) >= caps[k][2]
+            pts.append(p[keep])
+            links.append(np.full(int(keep.sum()), l, np.int32))
+            wts.append(np.full(int(keep.sum()), size[l] / n))
+        world = np.concatenate(pts) if pts else np.zeros((0, 3))
+        link = np.concatenate(links) if links else np.zeros(0, np.int32)
+        w = np.concatenate(wts) if wts else np.zeros(0)
+        local = np.einsum("nji,nj->ni", hand.link_rest_R[link], world - hand.link_rest_o[link])
+        out[kind] = (link, local, w, world)
+    s, v = out["surface"], out["volume"]
+    return EvalPoints(surface_link=s[0], surface_local=s[1], surface_area=s[2], volume_link=v[0],
+                      volume_local=v[1], volume_weight=v[2], surface_rest=s[3], volume_rest=v[3])
 
 
 # ----------------------------------------------------------------------------

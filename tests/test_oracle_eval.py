@@ -1,0 +1,162 @@
+"""Pins of the oracle's post-synthesis metrics (Sec. V-A: contact area at a
+distance threshold, intersection volume, top-k selection) against what
+geometry fixes. A hand whose straight fingers point into a planar object has
+closed-form contact area and intersection volume: each finger is one long
+capsule whose area (Archimedes' zones and the cylinder) and volume
+(spherical caps and the cylinder) below a height are known; a plane is exact
+under trilinear interpolation, so only the sample stratification separates
+the oracle from the closed form, by at most two samples per link. The same
+holds under any rotation of plane and hand together. Special cases: an
+object holding the whole hand (the sums of all weights), an object clear of
+it (zero), a non-finite configuration (NaN). Top-k against a brute-force
+sort. No GPU needed."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle as O
+from paper_2306_08132_amd import synth as S
+
+THR = [0.002, 0.005, 0.009]  # the thresholds the paper's figures span (2 mm, 5 mm, 9 mm)
+
+
+def plane_grid(normal, offset, n=41, lo=(-0.2, -0.2, -0.2), side=0.4):
+    """A grid of the plane's signed distance normal . p - offset (FP32)."""
+    normal = np.asarray(normal, float) / np.linalg.norm(normal)
+    h = side / (n - 1)
+    i = np.arange(n) * h
+    z, y, x = np.meshgrid(lo[2] + i, lo[1] + i, lo[0] + i, indexing="ij")
+    vals = (x * normal[0] + y * normal[1] + z * normal[2] - offset).astype(np.float32).reshape(-1)
+    return S.Grid(n, np.asarray(lo, float), h, vals, [], side)
+
+
+def area_below(depth, r):
+    """Area of a long capsule of radius r (axis along the plane normal) within
+    `depth` of its lowest point: a zone of the end sphere, then cylinder."""
+    if depth <= 0.0:
+        return 0.0
+    if depth <= r:
+        return 2.0 * math.pi * r * depth
+    return 2.0 * math.pi * r * r + 2.0 * math.pi * r * (depth - r)
+
+
+def volume_below(depth, r):
+    if depth <= 0.0:
+        return 0.0
+    if depth <= r:
+        return math.pi * depth * depth * (3.0 * r - depth) / 3.0
+    return 2.0 * math.pi * r ** 3 / 3.0 + math.pi * r * r * (depth - r)
+
+
+def pointing_pose(hand, normal, yaw, dip):
+    """q with straight fingers (joint angles 0) pointing along -normal and the
+    lowest fingertip `dip` below the plane normal . p = 0; also the depth of
+    every finger's tip below the plane."""
+    normal = np.asarray(normal, float) / np.linalg.norm(normal)
+    # rotate the palm's +z (the fingers' direction) onto -normal, then spin about it
+    R = Rotation.align_vectors([-normal], [[0.0, 0.0, 1.0]])[0].as_matrix()
+    R = Rotation.from_rotvec(yaw * -normal).as_matrix() @ R
+    caps = hand.capsules
+    F, J = hand.n_fingers, hand.joints_per_finger
+    # height along the normal of each finger's tip pole, before translation
+    tips = []
+    for f in range(F):
+        links = 1 + f * J + np.arange(J)
+        e = np.concatenate([caps[links, 0:3], caps[links, 3:6]]) @ R.T
+        tips.append(float((e @ normal).min()) - float(caps[links[0], 6]))
+    shift = -(min(tips)) - dip  # lowest tip ends at -dip
+    t = shift * normal
+    q = np.zeros(hand.n_dof)
+    q[0:3] = t
+    q[3:6] = Rotation.from_matrix(R).as_euler("ZYX")
+    depths = [-(tp + shift) for tp in tips]
+    return q, depths
+
+
+def stratification_bound(hand, ev, links):
+    """Two samples' weight per link: the most a stratified count can miss in
+    one interval of a link's axis."""
+    sa = sum(2.0 * ev.surface_area[ev.surface_link == l].max() for l in links)
+    vw = sum(2.0 * ev.volume_weight[ev.volume_link == l].max() for l in links)
+    return sa, vw
+
+
+@pytest.fixture(scope="module")
+def hand_and_points():
+    hand = S.make_hand(3, 3, 256, seed=3)
+    ev = S.make_eval_points(hand, 40000, 40000, seed=4)
+    return hand, ev
+
+
+@pytest.mark.parametrize("normal,yaw,dip", [((0, 0, 1), 0.0, 0.012), ((0, 0, 1), 1.1, 0.006),
+                                            ((0.3, -0.5, 0.8), 2.3, 0.010)])
+def test_fingers_in_a_plane_closed_form(hand_and_points, normal, yaw, dip):
+    hand, ev = hand_and_points
+    normal = np.asarray(normal, float) / np.linalg.norm(normal)
+    q, depths = pointing_pose(hand, normal, yaw, dip)
+    grid = plane_grid(normal, 0.0)
+    out, slack = O.evaluate(O.Hand(hand), O.Obj(grid), q, O.EvalPoints(ev), THR, delta=1e-7)
+    r = 0.8 * S.CM
+    finger_links = range(1, hand.n_links)
+    sb, vb = stratification_bound(hand, ev, finger_links)
+    for t, tau in enumerate(THR):
+        exact = sum(area_below(d + tau, r) for d in depths)
+        assert abs(out[0, t] - exact) <= sb + slack[0, t], (tau, out[0, t], exact, sb)
+        assert exact > 10.0 * sb  # the pin can tell a wrong threshold from a right one
+    exact_iv = sum(volume_below(d, r) for d in depths)
+    assert abs(out[0, 3] - exact_iv) <= vb + slack[0, 3], (out[0, 3], exact_iv, vb)
+    assert exact_iv > 10.0 * vb
+    # the palm stays clear of the 9 mm band: only finger links contribute
+    assert np.all(np.diff(out[0, :3]) > 0.0)
+
+
+def test_object_holding_the_whole_hand(hand_and_points):
+    hand, ev = hand_and_points
+    grid = plane_grid((0, 0, 1), 0.5)  # phi = z - 0.5 < 0 over the grid box
+    q = np.zeros(hand.n_dof)
+    out, _ = O.evaluate(O.Hand(hand), O.Obj(grid), q, O.EvalPoints(ev), THR + [0.0])
+    assert np.allclose(out[0, :4], ev.surface_area.sum(), rtol=1e-12)
+    assert out[0, 4] == pytest.approx(ev.volume_weight.sum(), rel=1e-12)
+
+
+def test_object_clear_of_the_hand_and_nonfinite(hand_and_points):
+    hand, ev = hand_and_points
+    grid = plane_grid((0, 0, 1), -0.19)  # the hand at q = 0 lies far above
+    q = np.zeros((2, hand.n_dof))
+    q[1, 7] = np.nan
+    out, _ = O.evaluate(O.Hand(hand), O.Obj(grid), q, O.EvalPoints(ev), THR)
+    assert np.all(out[0] == 0.0)
+    assert np.all(np.isnan(out[1]))
+
+
+def test_contact_area_grows_with_the_threshold():
+    hand, grid, q = S.config_workload("tiny", B=16)
+    ev = S.make_eval_points(hand, 2000, 2000, seed=9)
+    q = q.copy()
+    q[:, 0:3] *= 0.45  # bring the wrists in to touch the sphere
+    out, _ = O.evaluate(O.Hand(hand), O.Obj(grid), q, O.EvalPoints(ev), [0.0] + THR)
+    assert np.all(np.diff(out[:, :4], axis=1) >= 0.0)
+    assert np.all(out[:, 4] <= ev.volume_weight.sum()) and (out[:, 4] > 0).sum() >= 4
+
+
+def brute_top(key, k, higher):
+    idx = list(range(len(key)))
+    nanfree = [i for i in idx if not math.isnan(key[i])]
+    nans = [i for i in idx if math.isnan(key[i])]
+    nanfree.sort(key=lambda i: (-key[i] if higher else key[i], i))
+    return (nanfree + nans)[:k]
+
+
+@pytest.mark.parametrize("higher", [False, True])
+def test_select_top_matches_brute_force(higher):
+    rng = np.random.default_rng(11)
+    for B, k in ((1, 1), (10, 10), (300, 10), (1000, 64)):
+        key = np.round(rng.normal(size=B), 1)  # plenty of ties
+        key[rng.random(B) < 0.05] = np.nan
+        key[rng.random(B) < 0.05] = -0.0
+        met = rng.random((B, 4))
+        top, mean = O.select_top(key, k, higher, met)
+        assert top.tolist() == brute_top(key.tolist(), k, higher)
+        assert np.allclose(mean, met[top].mean(axis=0), rtol=1e-14)
