@@ -191,6 +191,58 @@ grasp_status grasp_load_sdf_from_mesh(grasp_ctx* ctx, grasp_mesh_id mesh, const 
                                       grasp_sdf_id* out);
 
 /* ---------------------------------------------------------------------------
+ * Post-synthesis evaluation (Sec. V-A metrics). The paper reports contact area
+ * (CA) at a distance threshold (2, 5 and 9 mm in its figures) and
+ * intersection volume (IV) of the top-10 grasps. Read as integrals over the
+ * hand estimated from weighted samples: CA(tau) = total area of the surface
+ * samples whose signed distance to the object (at rest) is below tau,
+ * penetrating ones included; IV = total volume of the volume samples whose
+ * signed distance is below 0. Samples are placed by the hand's forward
+ * kinematics and read through the grid's trilinear value, as in the step.
+ * ------------------------------------------------------------------------- */
+typedef uint64_t grasp_eval_id;
+
+#define GRASP_MAX_THRESHOLDS 8
+#define GRASP_MAX_TOP 64
+
+typedef struct {
+  int32_t n_surface;            /* surface samples, 0 .. 2^24 */
+  const int32_t* surface_link;  /* host [n_surface], each in [0, n_links) */
+  const float* surface_local;   /* host [n_surface][3] in the frame of the link */
+  const float* surface_area;    /* host [n_surface] area each stands for (m^2), finite, >= 0 */
+  int32_t n_volume;             /* volume samples, 0 .. 2^24; n_surface + n_volume >= 1 */
+  const int32_t* volume_link;   /* host [n_volume] */
+  const float* volume_local;    /* host [n_volume][3] */
+  const float* volume_weight;   /* host [n_volume] volume each stands for (m^3), finite, >= 0 */
+} grasp_eval_desc;
+
+/* Copies a hand's weighted samples to the device (each set sorted by link;
+ * the sums do not depend on the order). The set belongs to the hand: it is
+ * usable while the hand exists. EINVAL on a bad count, link, coordinate or
+ * weight; ENOMEM when the arena is full. */
+grasp_status grasp_load_eval_points(grasp_ctx* ctx, grasp_hand_id hand, const grasp_eval_desc* desc,
+                                    grasp_eval_id* out);
+grasp_status grasp_unload_eval_points(grasp_ctx* ctx, grasp_eval_id ev);
+
+/* Metrics of B candidates q (dev [B][n_dof]) against the grid: out (dev
+ * [B][n_thr + 1]) = CA at thresholds[0 .. n_thr) (host, metres, finite,
+ * 1 <= n_thr <= GRASP_MAX_THRESHOLDS), then IV. A candidate with a
+ * non-finite coordinate gets NaN in every column. Asynchronous on hip_stream. */
+grasp_status grasp_evaluate(grasp_ctx* ctx, grasp_eval_id ev, grasp_sdf_id sdf, int32_t B, const float* q,
+                            int32_t n_thr, const float* thresholds, float* out, void* hip_stream);
+
+/* The k best of B candidates by key (dev [B]): ascending, or descending when
+ * higher_is_better; NaN keys after every other; equal keys (-0 equal to +0) in
+ * index order. top (dev [k]) gets their indices, best first; mean (dev [M], or
+ * NULL when M = 0) the average of metrics (dev [B][M]) over them, summed in
+ * FP64 in rank order. 1 <= k <= min(B, GRASP_MAX_TOP), B <= 2^24, M >= 0. The
+ * paper ranks by the epsilon metric, which is not computed here: any key can
+ * be given, for instance the final loss. Asynchronous on hip_stream; one
+ * workgroup, k passes over the keys. */
+grasp_status grasp_select_top(grasp_ctx* ctx, int32_t B, const float* key, int32_t higher_is_better, int32_t k,
+                              int32_t M, const float* metrics, int32_t* top, float* mean, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * The step (Sec. III-C, Sec. IV-A)
  * ------------------------------------------------------------------------- */
 typedef struct {

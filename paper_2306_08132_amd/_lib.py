@@ -51,6 +51,16 @@ class MeshGridDescC(C.Structure):
                 ("layout", C.c_int32)]
 
 
+class EvalDescC(C.Structure):
+    _fields_ = [("n_surface", C.c_int32), ("surface_link", C.POINTER(C.c_int32)),
+                ("surface_local", C.POINTER(C.c_float)), ("surface_area", C.POINTER(C.c_float)),
+                ("n_volume", C.c_int32), ("volume_link", C.POINTER(C.c_int32)),
+                ("volume_local", C.POINTER(C.c_float)), ("volume_weight", C.POINTER(C.c_float))]
+
+
+MAX_THRESHOLDS, MAX_TOP = 8, 64
+
+
 class TileC(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("min_waves_per_simd", C.c_int32)]
 
@@ -125,6 +135,10 @@ SIGNATURES = [
     ("grasp_mesh_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP]),
     ("grasp_load_sdf_from_mesh", _I32, [_VP, _U64, C.POINTER(MeshGridDescC), C.POINTER(_U64)]),
     ("grasp_unload_sdf", _I32, [_VP, _U64]),
+    ("grasp_load_eval_points", _I32, [_VP, _U64, C.POINTER(EvalDescC), C.POINTER(_U64)]),
+    ("grasp_unload_eval_points", _I32, [_VP, _U64]),
+    ("grasp_evaluate", _I32, [_VP, _U64, _U64, _I32, _VP, _I32, _FP, _VP, _VP]),
+    ("grasp_select_top", _I32, [_VP, _I32, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
     ("grasp_sdf_inertia", _I32, [_VP, _U64, _FP]),
     ("grasp_default_params", None, [C.POINTER(StepParamsC)]),
     ("grasp_step_workspace_bytes", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(_SZ)]),

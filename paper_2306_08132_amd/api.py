@@ -11,7 +11,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (BatchJobC, HandDesc, JobDescC, JobResultC, Library, MeshDescC, MeshGridDescC, SdfDesc,
+from ._lib import (BatchJobC, EvalDescC, HandDesc, JobDescC, JobResultC, Library, MeshDescC, MeshGridDescC, SdfDesc,
                    ServeStatsC, StepParams,
                    TileC, GRASP_EAGAIN, MODE_AUTO, MODE_RECOMPUTE, MODE_SAVE, GraspError)
 
@@ -70,6 +70,28 @@ class Context:
 
     def mesh(self, mesh, alpha: float, normals: bool = True) -> "Mesh":
         return Mesh(self, mesh, alpha, normals)
+
+    def eval_points(self, hand: "Hand", points) -> "EvalPoints":
+        return EvalPoints(self, hand, points)
+
+    # -- post-synthesis evaluation (Sec. V-A metrics) -------------------------
+    def evaluate(self, ev: "EvalPoints", sdf, q, thresholds, out=None, stream=None):
+        """[B][T + 1]: contact area at each threshold (m), then intersection volume."""
+        thr = np.ascontiguousarray(thresholds, np.float32).reshape(-1)
+        if out is None:
+            out = torch.empty((q.shape[0], thr.shape[0] + 1), dtype=torch.float32, device=q.device)
+        self.lib.call("grasp_evaluate", self.h, ev.id, sdf.id, q.shape[0], _ptr(q), thr.shape[0],
+                      thr.ctypes.data_as(C.POINTER(C.c_float)), _ptr(out), _stream(stream))
+        return out
+
+    def select_top(self, key, k: int, higher_is_better: bool = False, metrics=None, stream=None):
+        """(indices [k] best first, mean of metrics [B][M] over them or None)."""
+        top = torch.empty(k, dtype=torch.int32, device=key.device)
+        M = 0 if metrics is None else metrics.shape[1]
+        mean = torch.empty(M, dtype=torch.float32, device=key.device) if M else None
+        self.lib.call("grasp_select_top", self.h, key.shape[0], _ptr(key), int(higher_is_better), k, M,
+                      _ptr(metrics) if M else None, _ptr(top), _ptr(mean), _stream(stream))
+        return top, mean
 
     # -- steps -----------------------------------------------------------------
     def workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
@@ -284,6 +306,25 @@ class Mesh:
 
     def unload(self):
         self.ctx.lib.call("grasp_unload_mesh", self.ctx.h, self.id)
+
+
+class EvalPoints:
+    """A hand's weighted surface and volume samples resident in a context
+    (grasp_load_eval_points)."""
+
+    def __init__(self, ctx: Context, hand: Hand, points):
+        self.ctx = ctx
+        sl, sp, sa = _i32(points.surface_link), _f32(points.surface_local), _f32(points.surface_area)
+        vl, vp, vw = _i32(points.volume_link), _f32(points.volume_local), _f32(points.volume_weight)
+        fp, ip = C.POINTER(C.c_float), C.POINTER(C.c_int32)
+        d = EvalDescC(sl.shape[0], sl.ctypes.data_as(ip), sp.ctypes.data_as(fp), sa.ctypes.data_as(fp),
+                      vl.shape[0], vl.ctypes.data_as(ip), vp.ctypes.data_as(fp), vw.ctypes.data_as(fp))
+        eid = C.c_uint64()
+        ctx.lib.call("grasp_load_eval_points", ctx.h, hand.id, C.byref(d), C.byref(eid))
+        self.id = eid.value
+
+    def unload(self):
+        self.ctx.lib.call("grasp_unload_eval_points", self.ctx.h, self.id)
 
 
 class GraspStep(torch.autograd.Function):

@@ -16,6 +16,7 @@
 
 #include "../../include/grasp.h"
 #include "arena.h"
+#include "eval.h"
 #include "internal.h"
 
 namespace grasp {
@@ -47,6 +48,13 @@ struct DevMesh {
   double volume = 0.0;  // enclosed volume (divergence theorem)
 };
 
+struct DevEval {
+  EvalView view{};
+  void* block = nullptr;
+  size_t bytes = 0;
+  grasp_hand_id hand = 0;  // the hand whose links the samples hang from
+};
+
 struct Scheduler;  // serving loop (sched.cpp)
 
 }  // namespace grasp
@@ -60,6 +68,7 @@ struct grasp_ctx {
   std::map<uint64_t, std::unique_ptr<grasp::DevHand>> hands;
   std::map<uint64_t, std::unique_ptr<grasp::DevSdf>> sdfs;
   std::map<uint64_t, std::unique_ptr<grasp::DevMesh>> meshes;
+  std::map<uint64_t, std::unique_ptr<grasp::DevEval>> evals;
   uint64_t next_id = 1;
   std::atomic<bool> poisoned{false};
   std::map<std::string, grasp::TileCfg> tiles;  // tuned launch shapes per problem shape

@@ -1,0 +1,238 @@
+// Post-synthesis evaluation on gfx950 (Sec. V-A metrics): contact area at
+// distance thresholds and intersection volume of final grasps, and the
+// top-k selection behind the paper's top-10 figures.
+//
+// Contact area CA(tau) sums the areas of the hand's surface samples whose
+// signed distance to the object (at rest) lies below tau; intersection
+// volume sums the volumes of the hand's volume samples below 0. The samples
+// are placed by the same forward kinematics and read through the same grid
+// gather and trilinear value as the grasp step.
+//
+// Execution model: one wavefront takes four candidates. Lanes hold
+// consecutive samples (their link-local points read once for all four
+// candidates); each lane transforms its sample by the four candidates' link
+// frames, drops the placements that the block-minimum table proves to lie
+// above the largest threshold (or above 0 for volume samples), and gathers
+// the rest with all eight loads issued before any is used. Per-candidate
+// sums are lane-local, then a wavefront reduction in a fixed order: a
+// candidate's metrics are the same bits whatever else runs.
+#include "device_common.h"
+#include "eval.h"
+
+namespace grasp {
+namespace {
+
+using namespace dev;
+
+constexpr int kCpw = kEvalCandidatesPerWave;
+constexpr int kEvalWaves = 4;
+constexpr int kLdsPerWave = kCpw * kMaxLinks * 12;
+// a byte offset past every gather copy (at most 512 * 511^2 * 16 < 0x7F900000
+// bytes) whose loads read zeros without a memory request
+constexpr uint32_t kNoCell = 0x7FFF0000u;
+
+// Proven lower bound of the sample at r: the block-minimum table entry plus
+// the max-norm distance to the grid box (as the step's culling, with the same
+// margins over FP32 rounding). True when the sample is provably above t.
+__device__ __forceinline__ bool provably_above(const SdfView& S, V3 r, float t) {
+  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
+  const int bx = static_cast<int>(ax.i) >> kBlockShift;
+  const int by = static_cast<int>(ay.i) >> kBlockShift;
+  const int bz = static_cast<int>(az.i) >> kBlockShift;
+  const float e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
+  const float bm = S.bmin[(bz * S.nb + by) * S.nb + bx];
+  return fmaf(0.999999f, e, bm - t) > 1e-6f;
+}
+
+// Trilinear value of a located sample (the grasp step's arithmetic, without
+// the gradient): the same bits as the step's sample at the same point.
+__device__ __forceinline__ float sample_value(const SdfView& S, const Located& L, float4 lo4, float4 hi4) {
+  const float c00 = fmaf(L.fx, lo4.y - lo4.x, lo4.x);
+  const float c10 = fmaf(L.fx, lo4.w - lo4.z, lo4.z);
+  const float c01 = fmaf(L.fx, hi4.y - hi4.x, hi4.x);
+  const float c11 = fmaf(L.fx, hi4.w - hi4.z, hi4.z);
+  const float dy0 = c10 - c00, dy1 = c11 - c01;
+  const float c0 = fmaf(L.fy, dy0, c00), c1 = fmaf(L.fy, dy1, c01);
+  const float phi = fmaf(L.fz, c1 - c0, c0);
+  const V3 e = v3(L.ox * S.h, L.oy * S.h, L.oz * S.h);
+  const float ee = dot(e, e);
+  const float ine = rsq(fmaxf(ee, 1.17549435e-38f));
+  return phi + ee * ine;
+}
+
+template <int LAY, bool SURFACE>
+__device__ __forceinline__ void eval_set(const SdfView& S, const EvalView& E, const EvalConsts& C, const float* T,
+                                         const bool bad[kCpw], int lane, float acc[kCpw][kMaxThresholds + 1]) {
+  const int begin = SURFACE ? 0 : E.ns, end = SURFACE ? E.ns : E.ns + E.nv;
+  const float cut = SURFACE ? C.tmax : 0.0f;
+  for (int base = begin; base < end; base += kWave) {
+    const int i = base + lane;
+    const bool valid = i < end;
+    const float4 P = valid ? E.pts[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int l = valid ? E.link[i] : 0;
+    V3 r[kCpw];
+    bool live[kCpw];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < kCpw; ++c) {
+      const float4* T4 = reinterpret_cast<const float4*>(T + (c * kMaxLinks + l) * 12);
+      r[c] = xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z);
+      live[c] = valid && !bad[c] && !provably_above(S, r[c], cut);
+      any = any || live[c];
+    }
+    if (__builtin_amdgcn_ballot_w64(any) == 0) continue;
+    Located L[kCpw];
+    float4 lo4[kCpw], hi4[kCpw];
+#pragma unroll
+    for (int c = 0; c < kCpw; ++c) {
+      L[c] = locate<LAY>(S, r[c]);
+      sdf_corners<LAY>(S, live[c] ? L[c].byte : kNoCell, lo4[c], hi4[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kCpw; ++c) {
+      if (!live[c]) continue;
+      const float phi = sample_value(S, L[c], lo4[c], hi4[c]);
+      if constexpr (SURFACE) {
+#pragma unroll
+        for (int t = 0; t < kMaxThresholds; ++t)
+          if (t < C.n_thr && phi < C.thr[t]) acc[c][t] += P.w;
+      } else {
+        if (phi < 0.0f) acc[c][kMaxThresholds] += P.w;
+      }
+    }
+  }
+}
+
+template <int LAY>
+__global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate(HandView H, SdfView S, EvalView E, EvalConsts C,
+                                                                  int B, const float* __restrict__ q,
+                                                                  float* __restrict__ out) {
+  __shared__ float lds_all[kEvalWaves * kLdsPerWave];
+  const int lane = lane_id();
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  const int b0 = (static_cast<int>(blockIdx.x) * kEvalWaves + wave) * kCpw;
+  if (b0 >= B) return;
+  float* T = lds_all + wave * kLdsPerWave;
+  const int nd = H.n_dof;
+  // link frames of the wave's candidates; a candidate past B or with a
+  // non-finite coordinate is skipped (its metrics are NaN)
+  bool bad[kCpw];
+#pragma unroll
+  for (int c = 0; c < kCpw; ++c) {
+    const int b = b0 + c;
+    const bool in = b < B;
+    const float qj = (in && lane < nd) ? q[static_cast<size_t>(b) * nd + lane] : 0.0f;
+    bad[c] = !in || __builtin_amdgcn_ballot_w64(!isfinite(qj)) != 0;
+  }
+  for (int t = lane; t < kCpw * H.L; t += kWave) {
+    const int c = t / H.L, l = t - c * H.L;
+    const int b = min(b0 + c, B - 1);
+    float Jw[6];
+    link_transform(H, q + static_cast<size_t>(b) * nd, l, T + (c * kMaxLinks + l) * 12, Jw);
+  }
+  wave_lds_sync();
+  float acc[kCpw][kMaxThresholds + 1];
+#pragma unroll
+  for (int c = 0; c < kCpw; ++c)
+#pragma unroll
+    for (int t = 0; t <= kMaxThresholds; ++t) acc[c][t] = 0.0f;
+  eval_set<LAY, true>(S, E, C, T, bad, lane, acc);
+  eval_set<LAY, false>(S, E, C, T, bad, lane, acc);
+  const int M = C.n_thr + 1;
+#pragma unroll
+  for (int c = 0; c < kCpw; ++c) {
+    const int b = b0 + c;
+#pragma unroll
+    for (int t = 0; t <= kMaxThresholds; ++t) {
+      if (t < C.n_thr || t == kMaxThresholds) {
+        const float s = wave_sum(acc[c][t]);
+        if (lane == 0 && b < B) {
+          const int col = t == kMaxThresholds ? C.n_thr : t;
+          out[static_cast<size_t>(b) * M + col] = bad[c] ? __builtin_nanf("") : s;
+        }
+      }
+    }
+  }
+}
+
+// Key of candidate i as one 64-bit word whose unsigned order is the ranking:
+// the key mapped to an order-preserving 32-bit code (negated when higher is
+// better, -0 taken as +0, NaN after everything), then the index.
+__device__ __forceinline__ unsigned long long rank_word(const float* key, int i, bool higher) {
+  float k = key[i];
+  uint32_t u;
+  if (isnan(k)) {
+    u = 0xFFFFFFFFu;
+  } else {
+    k = higher ? -k : k;
+    k = k == 0.0f ? 0.0f : k;
+    const uint32_t bits = __float_as_uint(k);
+    u = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+  }
+  return (static_cast<unsigned long long>(u) << 32) | static_cast<uint32_t>(i);
+}
+
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long x) {
+  for (int s = 32; s >= 1; s >>= 1) {
+    const unsigned long long o = __shfl_xor(x, s);
+    x = o < x ? o : x;
+  }
+  return x;
+}
+
+// k rounds, each the smallest rank word above the previous winner: the k
+// best in order, with no scratch memory.
+__global__ void __launch_bounds__(kTopThreads) k_select_top(int B, const float* __restrict__ key, int higher, int k,
+                                                             int M, const float* __restrict__ metrics,
+                                                             int* __restrict__ top, float* __restrict__ mean) {
+  __shared__ unsigned long long part[kTopThreads / kWave];
+  __shared__ int chosen[kMaxTop];
+  const int tid = static_cast<int>(threadIdx.x);
+  unsigned long long last = 0ull;  // below every rank word (the smallest has a non-zero high half)
+  for (int j = 0; j < k; ++j) {
+    unsigned long long m = ~0ull;
+    for (int i = tid; i < B; i += kTopThreads) {
+      const unsigned long long w = rank_word(key, i, higher != 0);
+      if (w > last && w < m) m = w;
+    }
+    m = wave_min64(m);
+    if ((tid & (kWave - 1)) == 0) part[tid / kWave] = m;
+    __syncthreads();
+    unsigned long long best = part[0];
+    for (int w = 1; w < kTopThreads / kWave; ++w) best = part[w] < best ? part[w] : best;
+    last = best;
+    // k <= B leaves a word for every round; the clamp only keeps the index valid
+    if (tid == 0) chosen[j] = best == ~0ull ? 0 : static_cast<int>(best & 0xFFFFFFFFull);
+    __syncthreads();
+  }
+  for (int j = tid; j < k; j += kTopThreads) top[j] = chosen[j];
+  for (int m = tid; m < M; m += kTopThreads) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += static_cast<double>(metrics[static_cast<size_t>(chosen[j]) * M + m]);
+    mean[m] = static_cast<float>(s / k);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_evaluate(const HandView& H, const SdfView& S, const EvalView& E, const EvalConsts& c, int B,
+                           const float* q, float* out, hipStream_t stream) {
+  if (B <= 0) return hipSuccess;
+  const int per_block = kEvalWaves * kCpw;
+  const dim3 grid((B + per_block - 1) / per_block), block(kEvalWaves * kWave);
+  if (S.layout == kLayoutZPairs)
+    hipLaunchKernelGGL(k_evaluate<kLayoutZPairs>, grid, block, 0, stream, H, S, E, c, B, q, out);
+  else
+    hipLaunchKernelGGL(k_evaluate<kLayoutYZQuads>, grid, block, 0, stream, H, S, E, c, B, q, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_top(int B, const float* key, int higher_is_better, int k, int M, const float* metrics,
+                             int* top, float* mean, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select_top, dim3(1), dim3(kTopThreads), 0, stream, B, key, higher_is_better, k, M, metrics,
+                     top, mean);
+  return hipGetLastError();
+}
+
+}  // namespace grasp

@@ -624,6 +624,13 @@ def config_workload(name: str, seed: int | None = None, B: int | None = None,
     return hand, grid, q
 
 
+def config_eval_points(name: str, hand: Hand) -> EvalPoints:
+    """The evaluation samples of a named workload's hand: tiny 1024 + 1024,
+    diff 4096 + 4096, large 8192 + 8192 surface + volume samples."""
+    n, seed = {"tiny": (1024, 20), "diff": (4096, 21), "large": (8192, 24)}[name]
+    return make_eval_points(hand, n, n, seed=seed)
+
+
 def make_job_stream(n_jobs: int, rate: float, seed: int, B_range=(256, 8192),
                     res_choices=(64, 96, 128, 192, 256), steps: int = 300):
     """Poisson arrivals (mean ``rate`` jobs/s) of grasp jobs with random hands

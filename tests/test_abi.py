@@ -44,6 +44,9 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert b"NULL" in L.grasp_last_error()
     assert L.grasp_step_fwd(None, 0, 0, None, 0, None, None, None, None, 0, None) == lib.GRASP_EINVAL
     assert L.grasp_init(0, None, 1 << 20, None) == lib.GRASP_EINVAL
+    assert L.grasp_evaluate(None, 0, 0, 0, None, 1, None, None, None) == lib.GRASP_EINVAL
+    assert L.grasp_select_top(None, 1, None, 0, 1, 0, None, None, None, None) == lib.GRASP_EINVAL
+    assert L.grasp_load_eval_points(None, 0, None, None) == lib.GRASP_EINVAL
     p = lib.StepParamsC()
     L.grasp_default_params(C.byref(p))
     assert (p.dt, p.K, p.ckpt_every, p.alpha_leak) == (C.c_float(1e-3).value, 1, 1, C.c_float(0.1).value)
@@ -78,7 +81,8 @@ def test_binding_structs_match_the_c_layout(lib):
     pairs = [("grasp_hand_desc", lib.HandDesc), ("grasp_sdf_desc", lib.SdfDesc), ("grasp_step_params", lib.StepParamsC),
              ("grasp_tile", lib.TileC), ("grasp_batch_job", lib.BatchJobC), ("grasp_job_desc", lib.JobDescC),
              ("grasp_job_result", lib.JobResultC), ("grasp_serve_stats", lib.ServeStatsC),
-             ("grasp_mesh_desc", lib.MeshDescC), ("grasp_mesh_grid_desc", lib.MeshGridDescC)]
+             ("grasp_mesh_desc", lib.MeshDescC), ("grasp_mesh_grid_desc", lib.MeshGridDescC),
+             ("grasp_eval_desc", lib.EvalDescC)]
     structs = [(cname, [f for f, *_ in py._fields_]) for cname, py in pairs]
     got = _c_layout(structs)
     for cname, py in pairs:
