@@ -93,6 +93,26 @@ def cpu_baseline(hand, grid, q, prm_kw, budget_s=12.0):
             "sample": f"{done} of {q.shape[0]} candidates, 1 step, forward + gradient, FP64, {dt:.1f} s"}
 
 
+def cpu_eval_baseline(hand, grid, q, S, budget_s=4.0):
+    """The oracle's post-synthesis metrics on the host's cores over a bounded
+    sample of the evaluation workload's candidates."""
+    import numpy as np
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    evp = S.config_eval_points("diff", hand)
+    H, ob, E = O.Hand(hand.rounded()), O.Obj(grid), O.EvalPoints(evp.as_f32())
+    chunk = max(threads, 8)
+    done, t0 = 0, time.perf_counter()
+    while done < q.shape[0] and time.perf_counter() - t0 < budget_s:
+        O.evaluate(H, ob, q[done:done + chunk].astype(np.float32).astype(np.float64), E, EVAL_THRESHOLDS,
+                   threads=threads)
+        done += chunk
+    dt = time.perf_counter() - t0
+    n = len(evp.surface_link) + len(evp.volume_link)
+    return {"value": done * n / dt, "unit": "candidate-samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of {q.shape[0]} candidates, FP64, {dt:.1f} s"}
+
+
 def serving_pool(S, device):
     """A few hands and objects for the served jobs (geometry is built once
     and stays resident; jobs draw from it)."""
@@ -287,6 +307,53 @@ def mesh_run(ctx, S, args):
     return out
 
 
+EVAL_THRESHOLDS = (0.002, 0.005, 0.009)  # contact thresholds of the paper's metric figures (m)
+
+
+def eval_run(ctx, S, hand, grid, q0, h, sd, key, args):
+    """Post-synthesis evaluation (Sec. V-A metrics) of the 4096 candidates of
+    the differentiable-step workload at their synthetic poses: contact area at
+    2/5/9 mm and intersection volume from 4096 surface + 4096 volume samples
+    per hand, then the top-10 by a key (the final loss) and their means."""
+    import numpy as np
+    import torch
+    print("bench: post-synthesis evaluation", file=sys.stderr, flush=True)
+    evp = S.config_eval_points("diff", hand)
+    gev = ctx.eval_points(h, evp)
+    q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    out = torch.empty((q.shape[0], len(EVAL_THRESHOLDS) + 1), device="cuda:0")
+    for _ in range(3):
+        ctx.evaluate(gev, sd, q, EVAL_THRESHOLDS, out=out, stream=stream)
+    reps = 20
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        ctx.evaluate(gev, sd, q, EVAL_THRESHOLDS, out=out, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    sel = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        top, mean = ctx.select_top(key, 10, False, out, stream=stream)
+        b.record(stream)
+        sel.append((a, b))
+    torch.cuda.synchronize()
+    top_ms = float(np.mean([a.elapsed_time(b) for a, b in sel]))
+    n = len(evp.surface_link) + len(evp.volume_link)
+    res = {"candidates": q.shape[0], "surface_samples": len(evp.surface_link), "volume_samples": len(evp.volume_link),
+           "thresholds_m": list(EVAL_THRESHOLDS), "kernel": "k_evaluate", "avg_launch_ms": ms,
+           "candidate_samples_per_s": q.shape[0] * n / (ms * 1e-3), "top10_ms": top_ms,
+           "top10_mean_ca_cm2": [float(x) * 1e4 for x in mean[:3].cpu()], "top10_mean_iv_cm3": float(mean[3]) * 1e6,
+           "all_mean_ca5_cm2": float(out[:, 1].mean()) * 1e4, "all_mean_iv_cm3": float(out[:, 3].mean()) * 1e6}
+    gev.unload()
+    print(f"bench: evaluation {ms:.3f} ms/launch ({res['candidate_samples_per_s']:.3e} candidate-samples/s), "
+          f"top-10 {top_ms:.3f} ms", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +368,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
     ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh-object queries")
+    ap.add_argument("--no-eval", action="store_true", help="skip the post-synthesis evaluation")
     ap.add_argument("--tile", type=str, default=None,
                     help="launch tile 'waves_per_block,min_waves_per_simd' instead of tuning (profiled runs: "
                          "every step dispatch is then a timed shape)")
@@ -409,11 +477,13 @@ def main():
     batched = None if args.no_batched else batched_run(ctx, S, args)
     large = None if args.no_large else large_run(ctx, S, args)
     mesh = None if args.no_mesh else mesh_run(ctx, S, args)
+    evaluation = None if args.no_eval else eval_run(ctx, S, hand, grid, q0, h, sd, loss, args)
 
     cpu = None
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(hand, grid, q0, {"K": K, "r_dil": r0})
+        cpu["evaluation"] = cpu_eval_baseline(hand, grid, q0, S)
 
     out = {
         "metric": METRIC,
@@ -442,6 +512,7 @@ def main():
         "batched": batched,
         "large": large,
         "mesh": mesh,
+        "evaluation": evaluation,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -10,7 +10,16 @@
 namespace grasp {
 
 constexpr int kMaxThresholds = 8;
-constexpr int kEvalCandidatesPerWave = 4;  // one sample load serves four candidates
+// Launch shape of the evaluation: a workgroup of kEvalWaves wavefronts takes
+// kEvalCandidates candidates and splits their samples between its waves.
+#ifndef GRASP_EVAL_CANDIDATES
+#define GRASP_EVAL_CANDIDATES 2
+#endif
+#ifndef GRASP_EVAL_WAVES
+#define GRASP_EVAL_WAVES 4
+#endif
+constexpr int kEvalCandidates = GRASP_EVAL_CANDIDATES;  // one sample load serves them all
+constexpr int kEvalWaves = GRASP_EVAL_WAVES;
 constexpr int kTopThreads = 1024;
 constexpr int kMaxTop = 64;
 

@@ -8,14 +8,15 @@
 // are placed by the same forward kinematics and read through the same grid
 // gather and trilinear value as the grasp step.
 //
-// Execution model: one wavefront takes four candidates. Lanes hold
-// consecutive samples (their link-local points read once for all four
-// candidates); each lane transforms its sample by the four candidates' link
-// frames, drops the placements that the block-minimum table proves to lie
-// above the largest threshold (or above 0 for volume samples), and gathers
-// the rest with all eight loads issued before any is used. Per-candidate
-// sums are lane-local, then a wavefront reduction in a fixed order: a
-// candidate's metrics are the same bits whatever else runs.
+// Execution model: a workgroup takes a few candidates and its wavefronts
+// split their samples (wave w takes 64-sample chunks w, w + W, ...). Lanes
+// hold consecutive samples, each read once for all the workgroup's
+// candidates; a lane transforms its sample by every candidate's link frames,
+// drops the placements that the block-minimum table proves to lie above the
+// largest threshold (or above 0 for volume samples), and gathers the rest
+// with all their loads issued before any is used. Sums are lane-local, then
+// a wavefront reduction, then the waves' partial sums added in wave order:
+// a candidate's metrics are the same bits whatever else runs.
 #include "device_common.h"
 #include "eval.h"
 
@@ -24,9 +25,8 @@ namespace {
 
 using namespace dev;
 
-constexpr int kCpw = kEvalCandidatesPerWave;
-constexpr int kEvalWaves = 4;
-constexpr int kLdsPerWave = kCpw * kMaxLinks * 12;
+constexpr int kCpw = kEvalCandidates;
+constexpr int kAcc = kMaxThresholds + 1;  // thresholds, then the volume
 // a byte offset past every gather copy (at most 512 * 511^2 * 16 < 0x7F900000
 // bytes) whose loads read zeros without a memory request
 constexpr uint32_t kNoCell = 0x7FFF0000u;
@@ -62,10 +62,10 @@ __device__ __forceinline__ float sample_value(const SdfView& S, const Located& L
 
 template <int LAY, bool SURFACE>
 __device__ __forceinline__ void eval_set(const SdfView& S, const EvalView& E, const EvalConsts& C, const float* T,
-                                         const bool bad[kCpw], int lane, float acc[kCpw][kMaxThresholds + 1]) {
+                                         const bool bad[kCpw], int lane, int wave, float acc[kCpw][kAcc]) {
   const int begin = SURFACE ? 0 : E.ns, end = SURFACE ? E.ns : E.ns + E.nv;
   const float cut = SURFACE ? C.tmax : 0.0f;
-  for (int base = begin; base < end; base += kWave) {
+  for (int base = begin + wave * kWave; base < end; base += kEvalWaves * kWave) {
     const int i = base + lane;
     const bool valid = i < end;
     const float4 P = valid ? E.pts[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -107,50 +107,60 @@ template <int LAY>
 __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate(HandView H, SdfView S, EvalView E, EvalConsts C,
                                                                   int B, const float* __restrict__ q,
                                                                   float* __restrict__ out) {
-  __shared__ float lds_all[kEvalWaves * kLdsPerWave];
+  __shared__ float T[kCpw * kMaxLinks * 12];
+  __shared__ float part[kEvalWaves][kCpw][kAcc];
+  __shared__ int bad_s[kCpw];
+  const int tid = static_cast<int>(threadIdx.x);
   const int lane = lane_id();
-  const int wave = static_cast<int>(threadIdx.x) / kWave;
-  const int b0 = (static_cast<int>(blockIdx.x) * kEvalWaves + wave) * kCpw;
-  if (b0 >= B) return;
-  float* T = lds_all + wave * kLdsPerWave;
+  const int wave = tid / kWave;
+  const int b0 = static_cast<int>(blockIdx.x) * kCpw;  // < B: the grid has ceil(B / kCpw) workgroups
   const int nd = H.n_dof;
-  // link frames of the wave's candidates; a candidate past B or with a
-  // non-finite coordinate is skipped (its metrics are NaN)
-  bool bad[kCpw];
+  // a candidate past B or with a non-finite coordinate is skipped (its
+  // metrics are NaN); link frames of the workgroup's candidates
+  if (wave == 0) {
 #pragma unroll
-  for (int c = 0; c < kCpw; ++c) {
-    const int b = b0 + c;
-    const bool in = b < B;
-    const float qj = (in && lane < nd) ? q[static_cast<size_t>(b) * nd + lane] : 0.0f;
-    bad[c] = !in || __builtin_amdgcn_ballot_w64(!isfinite(qj)) != 0;
+    for (int c = 0; c < kCpw; ++c) {
+      const int b = b0 + c;
+      const bool in = b < B;
+      const float qj = (in && lane < nd) ? q[static_cast<size_t>(b) * nd + lane] : 0.0f;
+      const bool bad = !in || __builtin_amdgcn_ballot_w64(!isfinite(qj)) != 0;
+      if (lane == 0) bad_s[c] = bad;
+    }
   }
-  for (int t = lane; t < kCpw * H.L; t += kWave) {
+  for (int t = tid; t < kCpw * H.L; t += kEvalWaves * kWave) {
     const int c = t / H.L, l = t - c * H.L;
     const int b = min(b0 + c, B - 1);
     float Jw[6];
     link_transform(H, q + static_cast<size_t>(b) * nd, l, T + (c * kMaxLinks + l) * 12, Jw);
   }
-  wave_lds_sync();
-  float acc[kCpw][kMaxThresholds + 1];
+  __syncthreads();
+  bool bad[kCpw];
+#pragma unroll
+  for (int c = 0; c < kCpw; ++c) bad[c] = bad_s[c] != 0;
+  float acc[kCpw][kAcc];
 #pragma unroll
   for (int c = 0; c < kCpw; ++c)
 #pragma unroll
-    for (int t = 0; t <= kMaxThresholds; ++t) acc[c][t] = 0.0f;
-  eval_set<LAY, true>(S, E, C, T, bad, lane, acc);
-  eval_set<LAY, false>(S, E, C, T, bad, lane, acc);
-  const int M = C.n_thr + 1;
+    for (int t = 0; t < kAcc; ++t) acc[c][t] = 0.0f;
+  eval_set<LAY, true>(S, E, C, T, bad, lane, wave, acc);
+  eval_set<LAY, false>(S, E, C, T, bad, lane, wave, acc);
 #pragma unroll
-  for (int c = 0; c < kCpw; ++c) {
-    const int b = b0 + c;
+  for (int c = 0; c < kCpw; ++c)
 #pragma unroll
-    for (int t = 0; t <= kMaxThresholds; ++t) {
+    for (int t = 0; t < kAcc; ++t)
       if (t < C.n_thr || t == kMaxThresholds) {
         const float s = wave_sum(acc[c][t]);
-        if (lane == 0 && b < B) {
-          const int col = t == kMaxThresholds ? C.n_thr : t;
-          out[static_cast<size_t>(b) * M + col] = bad[c] ? __builtin_nanf("") : s;
-        }
+        if (lane == 0) part[wave][c][t] = s;
       }
+  __syncthreads();
+  if (tid < kCpw * kAcc) {
+    const int c = tid / kAcc, t = tid - c * kAcc;
+    const int b = b0 + c;
+    if (b < B && (t < C.n_thr || t == kMaxThresholds)) {
+      float s = part[0][c][t];
+      for (int w = 1; w < kEvalWaves; ++w) s += part[w][c][t];
+      out[static_cast<size_t>(b) * (C.n_thr + 1) + (t == kMaxThresholds ? C.n_thr : t)] =
+          bad[c] ? __builtin_nanf("") : s;
     }
   }
 }
@@ -218,8 +228,7 @@ __global__ void __launch_bounds__(kTopThreads) k_select_top(int B, const float* 
 hipError_t launch_evaluate(const HandView& H, const SdfView& S, const EvalView& E, const EvalConsts& c, int B,
                            const float* q, float* out, hipStream_t stream) {
   if (B <= 0) return hipSuccess;
-  const int per_block = kEvalWaves * kCpw;
-  const dim3 grid((B + per_block - 1) / per_block), block(kEvalWaves * kWave);
+  const dim3 grid((B + kCpw - 1) / kCpw), block(kEvalWaves * kWave);
   if (S.layout == kLayoutZPairs)
     hipLaunchKernelGGL(k_evaluate<kLayoutZPairs>, grid, block, 0, stream, H, S, E, c, B, q, out);
   else
