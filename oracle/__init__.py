@@ -52,7 +52,7 @@ class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("v0", C.c_double), ("K", C.c_int), ("omega", C.c_double),
                 ("r_dil", C.c_double), ("alpha_leak", C.c_double), ("w_stable", C.c_double),
                 ("w_pen", C.c_double), ("w_range", C.c_double), ("w_limit", C.c_double),
-                ("w_min", C.c_double)]
+                ("w_min", C.c_double), ("projection", C.c_int)]
 
 
 @dataclasses.dataclass
@@ -69,10 +69,11 @@ class Params:
     w_range: float = 1e-2
     w_limit: float = 1.0
     w_min: float = 1e-8
+    projection: int = 0  # 0 averaged corrections, 1 Gauss-Seidel sweep
 
     def _c(self):
         return _Params(self.dt, self.v0, self.K, self.omega, self.r_dil, self.alpha_leak,
-                       self.w_stable, self.w_pen, self.w_range, self.w_limit, self.w_min)
+                       self.w_stable, self.w_pen, self.w_range, self.w_limit, self.w_min, int(self.projection))
 
 
 _lib = None

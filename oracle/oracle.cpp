@@ -15,7 +15,10 @@
 //  * object representation: dense grid, trilinear value, analytic gradient;
 //    outside the box, clamp to the box and add the Euclidean distance to it;
 //  * the paper's Gauss-Seidel step over the contact constraints (Sec. III-C)
-//    is replaced by its parallel form with constraint averaging: every
+//    is taken literally with projection = 1: one constraint after another,
+//    each at the pose the previous ones left, in link-major order (the paper
+//    gives no order); by default (projection = 0) it is replaced by its
+//    parallel form with constraint averaging: every
 //    correction of Eq. (1) is computed at the same pose and their sum is
 //    divided by the number n of active (penetrating, w > w_min) constraints
 //    of that test, then added with relaxation omega; K such iterations in one
@@ -413,6 +416,10 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
   // 3. M velocity-test simulations (Sec. IV-A), each one PBD step (Sec. III-C)
   const double dirs[kSims][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
                                  {0, 0, 1}, {0, 0, -1}, {0, 0, 0}};
+  // Gauss-Seidel order: contacts stable-sorted by link
+  std::vector<int> order(Nc);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h.contact_link[a] < h.contact_link[b]; });
   S Lstable = konst<S>(0.0);
   for (int m = 0; m < kSims; ++m) {
     // symplectic-Euler prediction from the canonical pose with velocity v0_m
@@ -424,6 +431,52 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           tr->poses[(m * (P.K + 1) + k) * 6 + a] = val(x[a]);
           tr->poses[(m * (P.K + 1) + k) * 6 + 3 + a] = val(th[a]);
         }
+      if (P.projection == 1) {
+        // Gauss-Seidel: each constraint's Eq. (1) update applied at once, so
+        // the next constraint sees the pose the previous ones left
+        for (int oi = 0; oi < Nc; ++oi) {
+          const int i = order[oi];
+          S R[9];
+          rotation_matrix(th, R);
+          S a[3], r[3];
+          for (int j = 0; j < 3; ++j) a[j] = p[3 * i + j] - x[j];
+          for (int j = 0; j < 3; ++j) r[j] = R[j] * a[0] + R[3 + j] * a[1] + R[6 + j] * a[2];
+          S phi, nrm[3];
+          SampleInfo info;
+          sample_object(o, r, phi, nrm, &info);
+          S d = phi - P.r_dil;
+          S g[3], u[3];
+          for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
+          S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak);
+          u[0] = a[1] * g[2] - a[2] * g[1];
+          u[1] = a[2] * g[0] - a[0] * g[2];
+          u[2] = a[0] * g[1] - a[1] * g[0];
+          S w = (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / Im;
+          S lam = konst<S>(0.0);
+          const bool active = val(w) > P.w_min;
+          if (active) {
+            lam = -C / w;
+            for (int j = 0; j < 3; ++j) {
+              x[j] = x[j] + P.omega * (lam * g[j]);
+              th[j] = th[j] + (P.omega / Im) * (lam * u[j]);
+            }
+          }
+          if (tr) {
+            if (tr->samples) {
+              double* s = tr->samples + ((static_cast<size_t>(m) * P.K + k) * Nc + i) * 6;
+              s[0] = val(d); s[1] = val(g[0]); s[2] = val(g[1]); s[3] = val(g[2]);
+              s[4] = val(w); s[5] = val(lam);
+            }
+            if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
+            tr->min_face = std::min(tr->min_face, info.face_margin);
+            tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
+                    (static_cast<uint64_t>(info.cell[2]) << 32) |
+                    (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
+                    (static_cast<uint64_t>(val(d) < 0.0) << 52) | (static_cast<uint64_t>(active) << 53));
+          }
+        }
+        continue;
+      }
       S R[9];
       rotation_matrix(th, R);
       S Wl[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};

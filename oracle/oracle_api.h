@@ -70,6 +70,10 @@ typedef struct {
   double alpha_leak;  /* leaky gradient factor */
   double w_stable, w_pen, w_range, w_limit;
   double w_min;       /* a constraint with J M^-1 J^T <= w_min is skipped */
+  int projection;     /* 0: all corrections at one pose, averaged over the active
+                         constraints; 1: Gauss-Seidel, one constraint after another
+                         in link-major order (stable by link), each at the pose the
+                         previous ones left */
 } oparams;
 
 /* A closed triangle mesh with outward (counter-clockwise) faces and unit
