@@ -257,7 +257,18 @@ typedef struct {
   float w_min;       /* constraints with J M^-1 J^T <= w_min are skipped (1e-8: below it the trilinear
                         gradient is single-precision rounding noise) */
   int32_t mode;      /* GRASP_MODE_*: how grasp_step_fwd/bwd share state */
+  int32_t projection;/* GRASP_PROJECTION_*: how the constraint corrections combine */
 } grasp_step_params;
+
+/* Projection of the contact constraints (Sec. III-C). AVERAGED (default): every
+ * Eq. (1) correction at the same pose, their sum divided by the number of
+ * active constraints of the test; every step form. GAUSS_SEIDEL: the paper's
+ * serial form, each constraint at the pose the previous ones left, in
+ * link-major order (contacts stable-sorted by link); grasp_step_fwd, _bwd and
+ * _fused only, with K = 1 and at most 8192 contacts; no workspace (the
+ * backward replays the sweeps). */
+#define GRASP_PROJECTION_AVERAGED 0
+#define GRASP_PROJECTION_GAUSS_SEIDEL 1
 
 enum {
   GRASP_MODE_AUTO = 0,      /* SAVE when a workspace is given, else RECOMPUTE */

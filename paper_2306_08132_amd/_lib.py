@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgrasp.so")
 GRASP_OK, GRASP_EINVAL, GRASP_ENOMEM, GRASP_EDEVICE = 0, -1, -2, -3
 GRASP_EBUSY, GRASP_EAGAIN, GRASP_ENONFINITE, GRASP_ECANCELED = -4, -5, -6, -7
 MODE_AUTO, MODE_SAVE, MODE_RECOMPUTE = 0, 1, 2
+PROJECTION_AVERAGED, PROJECTION_GAUSS_SEIDEL = 0, 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY", -5: "EAGAIN",
                 -6: "ENONFINITE", -7: "ECANCELED"}
 
@@ -69,7 +70,7 @@ class StepParamsC(C.Structure):
     _fields_ = [("dt", C.c_float), ("v0", C.c_float), ("K", C.c_int32), ("ckpt_every", C.c_int32),
                 ("omega", C.c_float), ("r_dil", C.c_float), ("alpha_leak", C.c_float),
                 ("w_stable", C.c_float), ("w_pen", C.c_float), ("w_range", C.c_float),
-                ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32)]
+                ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32), ("projection", C.c_int32)]
 
 
 class BatchJobC(C.Structure):
@@ -112,11 +113,12 @@ class StepParams:
     w_limit: float = 1.0
     w_min: float = 1e-8
     mode: int = MODE_AUTO
+    projection: int = 0  # PROJECTION_AVERAGED or PROJECTION_GAUSS_SEIDEL
 
     def c(self) -> StepParamsC:
         return StepParamsC(self.dt, self.v0, self.K, self.ckpt_every, self.omega, self.r_dil,
                            self.alpha_leak, self.w_stable, self.w_pen, self.w_range, self.w_limit,
-                           self.w_min, self.mode)
+                           self.w_min, self.mode, self.projection)
 
 
 # (name, restype, argtypes) of every exported entry point in include/grasp.h

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "context.h"
+#include "gs.h"
 
 namespace grasp {
 
@@ -67,6 +68,8 @@ grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
       !finite(p->w_min) || p->w_min < 0.0f)
     return fail(GRASP_EINVAL, "params must be finite (r_dil, w_min >= 0)");
   if (p->mode < GRASP_MODE_AUTO || p->mode > GRASP_MODE_RECOMPUTE) return fail(GRASP_EINVAL, "bad mode");
+  if (p->projection != GRASP_PROJECTION_AVERAGED && p->projection != GRASP_PROJECTION_GAUSS_SEIDEL)
+    return fail(GRASP_EINVAL, "bad projection");
   // LDS of one wave must fit comfortably: K/ckpt + 1 + ckpt pose slots
   if (wave_lds_floats(p->K, p->ckpt_every) * sizeof(float) > 16 * 1024)
     return fail(GRASP_EINVAL, "K / ckpt_every too large for the pose checkpoint buffer");
@@ -169,6 +172,7 @@ void grasp_default_params(grasp_step_params* p) {
   p->w_limit = 1.0f;
   p->w_min = 1e-8f;
   p->mode = GRASP_MODE_AUTO;
+  p->projection = GRASP_PROJECTION_AVERAGED;
 }
 
 // ---------------------------------------------------------------------------
@@ -459,14 +463,23 @@ struct Resolved {
   StepConsts prm;
 };
 
+// gs_ok: the entry point also runs the Gauss-Seidel projection (single-job
+// fwd, bwd and fused steps with K = 1).
 grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const grasp_step_params* p, int32_t B,
-                     Resolved* r) {
+                     Resolved* r, bool gs_ok = false) {
   if (B < 0) return fail(GRASP_EINVAL, "B must be >= 0");
   grasp_status st = check_params(p, &r->prm);
   if (st != GRASP_OK) return st;
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
+    if (!gs_ok)
+      return fail(GRASP_EINVAL, "Gauss-Seidel projection runs in grasp_step_fwd, grasp_step_bwd and grasp_step_fused");
+    if (p->K != 1) return fail(GRASP_EINVAL, "Gauss-Seidel projection runs with K = 1");
+  }
   std::lock_guard<std::mutex> lk(ctx->mu);
   DevHand* h = find_hand(ctx, hid);
   if (!h) return fail(GRASP_EINVAL, "unknown hand id");
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL && h->view.Nc > kGsMaxContacts)
+    return fail(GRASP_EINVAL, "Gauss-Seidel projection takes at most 8192 contacts");
   DevSdf* s = find_sdf(ctx, sid);
   if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
   r->hand = h->view;
@@ -580,9 +593,9 @@ grasp_status grasp_step_workspace_bytes(grasp_ctx* ctx, grasp_hand_id hand, gras
   GRASP_CHECK_CTX(ctx);
   if (!out) return fail(GRASP_EINVAL, "out is NULL");
   Resolved r;
-  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
   if (st != GRASP_OK) return st;
-  *out = pose_ws_bytes(r.prm, B);
+  *out = p->projection == GRASP_PROJECTION_GAUSS_SEIDEL ? 0 : pose_ws_bytes(r.prm, B);
   return GRASP_OK;
 }
 
@@ -592,9 +605,19 @@ grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   set_error("");
   GRASP_CHECK_CTX(ctx);
   Resolved r;
-  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
   if (st != GRASP_OK) return st;
   if (B > 0 && (!q || !loss)) return fail(GRASP_EINVAL, "q/loss is NULL");
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
+    StepArgs a = base_args(r, B);
+    a.q = q;
+    a.loss = loss;
+    a.terms = terms;
+    DeviceGuard g(ctx->device);
+    const hipError_t e = launch_gs_step(a, STEP_FWD, false, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fwd launch");
+    return GRASP_OK;
+  }
   const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
   if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
     return fail(GRASP_ENOMEM, "workspace too small for SAVE mode");
@@ -616,9 +639,19 @@ grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
   set_error("");
   GRASP_CHECK_CTX(ctx);
   Resolved r;
-  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
   if (st != GRASP_OK) return st;
   if (B > 0 && (!q || !dq)) return fail(GRASP_EINVAL, "q/dq is NULL");
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
+    StepArgs a = base_args(r, B);
+    a.q = q;
+    a.dloss = dloss;
+    a.dq = dq;
+    DeviceGuard g(ctx->device);
+    const hipError_t e = launch_gs_step(a, STEP_BWD, false, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_bwd launch");
+    return GRASP_OK;
+  }
   const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
   if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
     return fail(GRASP_ENOMEM, "workspace too small for SAVE mode");
@@ -654,7 +687,7 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   set_error("");
   GRASP_CHECK_CTX(ctx);
   Resolved r;
-  grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
   if (st != GRASP_OK) return st;
   if (B > 0 && (!q || !m || !v)) return fail(GRASP_EINVAL, "q/m/v is NULL");
   st = check_adam(t, lr, b1, b2, eps);
@@ -668,9 +701,14 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   a.terms = terms;
   a.dq = dq;
   a.adam = adam_consts(t, lr, b1, b2, eps);
-  const TileCfg tc = tile_for(ctx, r, B);
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
+  hipError_t e;
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
+    e = launch_gs_step(a, STEP_FUSED, true, static_cast<hipStream_t>(hip_stream));
+  } else {
+    const TileCfg tc = tile_for(ctx, r, B);
+    e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
+  }
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
   return GRASP_OK;
 }

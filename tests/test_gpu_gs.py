@@ -1,0 +1,174 @@
+"""GPU parity of the Gauss-Seidel projection (Sec. III-C: the constraint
+updates applied one after another) against the oracle's literal sweep in the
+same link-major order, through the C ABI: losses within 1e-4, gradients within
+1e-3 per candidate. The sweep carries the pose from one constraint to the
+next, so FP32 and FP64 poses drift apart by a few 1e-8 m over a sweep; a
+constraint closer than 1e-6 m to d = 0 may then switch sides, and candidates
+holding one are reported and capped. Also: the fused step with Adam equals
+the forward, backward and Adam launches; the sweep differs from the averaged
+form; refusals of the forms it does not run in."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2306_08132_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+GS = 1
+KINK_GS = 1e-6  # metres
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2306_08132_amd.api import Context
+    c = Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def prm_pair(**kw):
+    from paper_2306_08132_amd.api import StepParams
+    sp = StepParams(**kw)
+    op = O.Params()
+    for k in vars(op):
+        v = getattr(sp, k)
+        setattr(op, k, float(np.float32(v)) if isinstance(v, float) else v)
+    return sp, op
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def compare_gs(ctx, hand, grid, q, label, max_flagged=0.2, layout=0, **kw):
+    sp, op = prm_pair(projection=GS, **kw)
+    h, sd = ctx.hand(hand), ctx.sdf(grid, layout=layout)
+    B = q.shape[0]
+    qd = dev(q)
+    loss = torch.empty(B, device=DEV)
+    terms = torch.empty((B, 4), device=DEV)
+    ctx.step_fwd(h, sd, sp, qd, loss, terms)
+    dq = torch.empty_like(qd)
+    ctx.step_bwd(h, sd, sp, qd, dq)
+    torch.cuda.synchronize()
+    loss, terms, dq = loss.cpu().numpy(), terms.cpu().numpy(), dq.cpu().numpy()
+    q32 = q.astype(np.float32).astype(np.float64)
+    ref = O.step(O.Hand(hand.rounded()), O.Obj(grid), op, q32, grad=True, margins=True)
+    floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
+    lerr = np.abs(loss - ref["loss"]) / floor
+    gscale = np.abs(ref["grad"]).max(axis=1)
+    gerr = np.abs(dq - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30)
+    flagged = ref["min_abs_d"] < KINK_GS
+    say(f"{label}: B={B} loss rel err max(unflagged) {lerr[~flagged].max() if (~flagged).any() else 0:.2e}, "
+        f"grad rel err max(unflagged) {gerr[~flagged].max() if (~flagged).any() else 0:.2e}, "
+        f"median {np.median(gerr):.2e}, flagged {flagged.mean():.3f} "
+        f"(their loss errs {np.round(lerr[flagged], 5).tolist()[:8]})")
+    assert np.all(lerr[~flagged] <= 1e-4), (np.argmax(lerr), lerr.max())
+    assert np.all(gerr[~flagged] <= 1e-3), (np.nonzero(gerr > 1e-3)[0], gerr.max())
+    assert flagged.mean() <= max_flagged
+    sd.unload()
+    h.destroy()
+    return loss, dq, ref
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+def test_gs_step_parity_tiny(ctx, layout):
+    hand, grid, q = S.config_workload("tiny")
+    compare_gs(ctx, hand, grid, q, f"GS tiny r=5mm layout {layout}", layout=layout, r_dil=0.005)
+    compare_gs(ctx, hand, grid, q, f"GS tiny exact layout {layout}", layout=layout, r_dil=0.0, alpha_leak=0.0)
+
+
+def test_gs_step_parity_ragged(ctx):
+    """Contact counts off the 64-lane chunk, several links per chunk."""
+    for F, J, n, N, B in [(3, 3, 65, 16, 5), (4, 4, 1000, 40, 9), (5, 4, 777, 33, 7)]:
+        hand = S.make_hand(F, J, n, seed=F + n)
+        grid = S.make_grid(S.make_object("ellipsoids", seed=n), N)
+        q = S.make_candidates(hand, B, seed=n, shell_radius=grid.bound_radius + 0.06)
+        compare_gs(ctx, hand, grid, q, f"GS ragged {F}x{J} Nc={n}", max_flagged=0.3, r_dil=0.003)
+
+
+def test_gs_full_size_diff_sampled(ctx):
+    """The differentiable-step workload (4096 candidates, 2048 contacts,
+    128^3) in one launch; 48 candidates checked against the oracle."""
+    hand, grid, q = S.config_workload("diff")
+    sp, op = prm_pair(projection=GS, r_dil=0.005)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    qd = dev(q)
+    B = q.shape[0]
+    loss = torch.empty(B, device=DEV)
+    dq = torch.empty_like(qd)
+    ctx.step_fwd(h, sd, sp, qd, loss)
+    ctx.step_bwd(h, sd, sp, qd, dq)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(2).choice(B, 48, replace=False)
+    ref = O.step(O.Hand(hand.rounded()), O.Obj(grid), op, q[idx].astype(np.float32).astype(np.float64),
+                 grad=True, margins=True)
+    lerr = np.abs(loss.cpu().numpy()[idx] - ref["loss"]) / np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
+    gerr = np.abs(dq.cpu().numpy()[idx] - ref["grad"]).max(axis=1) / np.abs(ref["grad"]).max(axis=1)
+    flagged = ref["min_abs_d"] < KINK_GS
+    say(f"GS diff full (sampled): loss err {lerr[~flagged].max():.2e}, grad err {gerr[~flagged].max():.2e}, "
+        f"flagged {flagged.mean():.3f}")
+    assert np.all(lerr[~flagged] <= 1e-4) and np.all(gerr[~flagged] <= 1e-3)
+    assert flagged.mean() <= 0.3
+    assert np.all(np.isfinite(loss.cpu().numpy()))
+    sd.unload()
+    h.destroy()
+
+
+def test_gs_fused_equals_fwd_bwd_adam(ctx):
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny", B=37)
+    sp = StepParams(projection=GS, r_dil=0.004)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    q1 = dev(q)
+    m1, v1 = torch.zeros_like(q1), torch.zeros_like(q1)
+    loss1 = torch.empty(q.shape[0], device=DEV)
+    dq1 = torch.empty_like(q1)
+    ctx.step_fused(h, sd, sp, q1, m1, v1, 1, loss=loss1, dq=dq1)
+    q2 = dev(q)
+    m2, v2 = torch.zeros_like(q2), torch.zeros_like(q2)
+    loss2 = torch.empty(q.shape[0], device=DEV)
+    dq2 = torch.empty_like(q2)
+    ctx.step_fwd(h, sd, sp, q2, loss2)
+    ctx.step_bwd(h, sd, sp, q2, dq2)
+    ctx.adam(q2, m2, v2, dq2, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(loss1, loss2) and torch.equal(dq1, dq2)
+    assert torch.allclose(q1, q2, rtol=0, atol=1e-7)
+    # the sweep is not the averaged step
+    loss3 = torch.empty(q.shape[0], device=DEV)
+    ctx.step_fwd(h, sd, StepParams(r_dil=0.004), dev(q), loss3)
+    assert (loss3 - loss2).abs().max() > 1e-3 * loss2.abs().max()
+    sd.unload()
+    h.destroy()
+
+
+def test_gs_refusals(ctx):
+    from paper_2306_08132_amd._lib import GraspError
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny", B=8)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    qd = dev(q)
+    loss = torch.empty(8, device=DEV)
+    with pytest.raises(GraspError, match="K = 1"):
+        ctx.step_fwd(h, sd, StepParams(projection=GS, K=2), qd, loss)
+    with pytest.raises(GraspError, match="projection"):
+        ctx.step_fwd(h, sd, StepParams(projection=7), qd, loss)
+    with pytest.raises(GraspError, match="Gauss-Seidel"):
+        ctx.plain_step(h, sd, StepParams(projection=GS), qd, torch.zeros_like(qd), torch.zeros_like(qd), 1,
+                       torch.empty(4, dtype=torch.uint8, device=DEV), loss=loss)
+    big = S.make_hand(3, 3, 8193, seed=1)
+    hb = ctx.hand(big)
+    with pytest.raises(GraspError, match="8192"):
+        ctx.step_fwd(hb, sd, StepParams(projection=GS), dev(S.make_candidates(big, 2, 0, 0.1)),
+                     torch.empty(2, device=DEV))
+    hb.destroy()
+    sd.unload()
+    h.destroy()
