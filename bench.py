@@ -307,6 +307,60 @@ def mesh_run(ctx, S, args):
     return out
 
 
+def gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args):
+    """The Gauss-Seidel projection (Sec. III-C, constraints swept one after
+    another) as a fused step with Adam on the same 4096 candidates, 2048
+    contacts and 128^3 grid, with the same dilation schedule."""
+    import numpy as np
+    import torch
+    from paper_2306_08132_amd.api import StepParams
+    print("bench: Gauss-Seidel projection", file=sys.stderr, flush=True)
+    q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
+    m, v = torch.zeros_like(q), torch.zeros_like(q)
+    loss = torch.empty(q.shape[0], device="cuda:0")
+    stream = torch.cuda.current_stream()
+    T = 500
+
+    def step(t):
+        prm = StepParams(K=1, projection=1, r_dil=r0 * (1.0 - min(t, T - 1) / (T - 1)))
+        ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
+
+    for t in range(2):
+        step(t)
+    n = max(3, args.steps // 5)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for i, (a, b) in enumerate(evs):
+        a.record(stream)
+        step(2 + i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    evals = q.shape[0] * hand.n_contacts * 7
+    res = {"kernel": "k_gs_step", "ms_per_step": ms, "contact_evals_per_s": evals / (ms * 1e-3), "steps": n,
+           "averaged_ms_per_step": avg_ms, "gs_over_averaged_time": ms / avg_ms,
+           "final_loss_mean": float(loss.mean())}
+    print(f"bench: Gauss-Seidel {ms:.3f} ms/step ({ms / avg_ms:.1f}x the averaged step)", file=sys.stderr,
+          flush=True)
+    return res
+
+
+def cpu_gs_baseline(hand, grid, q, r0, budget_s=4.0):
+    """The oracle's Gauss-Seidel step (forward + dual gradient) over a bounded
+    sample of the same candidates."""
+    import numpy as np
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    H, ob, P = O.Hand(hand.rounded()), O.Obj(grid), O.Params(K=1, r_dil=r0, projection=1)
+    chunk = max(threads, 8)
+    done, t0 = 0, time.perf_counter()
+    while done < q.shape[0] and time.perf_counter() - t0 < budget_s:
+        O.step(H, ob, P, q[done:done + chunk].astype(np.float32).astype(np.float64), grad=True, threads=threads)
+        done += chunk
+    dt = time.perf_counter() - t0
+    return {"value": done * hand.n_contacts * 7 / dt, "unit": "contact-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of {q.shape[0]} candidates, 1 Gauss-Seidel step, forward + gradient, FP64, {dt:.1f} s"}
+
+
 EVAL_THRESHOLDS = (0.002, 0.005, 0.009)  # contact thresholds of the paper's metric figures (m)
 
 
@@ -369,6 +423,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh-object queries")
     ap.add_argument("--no-eval", action="store_true", help="skip the post-synthesis evaluation")
+    ap.add_argument("--no-gs", action="store_true", help="skip the Gauss-Seidel projection")
     ap.add_argument("--tile", type=str, default=None,
                     help="launch tile 'waves_per_block,min_waves_per_simd' instead of tuning (profiled runs: "
                          "every step dispatch is then a timed shape)")
@@ -478,12 +533,14 @@ def main():
     large = None if args.no_large else large_run(ctx, S, args)
     mesh = None if args.no_mesh else mesh_run(ctx, S, args)
     evaluation = None if args.no_eval else eval_run(ctx, S, hand, grid, q0, h, sd, loss, args)
+    gauss_seidel = None if args.no_gs else gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args)
 
     cpu = None
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(hand, grid, q0, {"K": K, "r_dil": r0})
         cpu["evaluation"] = cpu_eval_baseline(hand, grid, q0, S)
+        cpu["gauss_seidel"] = cpu_gs_baseline(hand, grid, q0, r0)
 
     out = {
         "metric": METRIC,
@@ -513,6 +570,7 @@ def main():
         "large": large,
         "mesh": mesh,
         "evaluation": evaluation,
+        "gauss_seidel": gauss_seidel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
