@@ -152,6 +152,7 @@ void grasp_shutdown(grasp_ctx* ctx) {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
+    if (ctx->gs_ev) (void)hipEventDestroy(ctx->gs_ev);
     if (ctx->arena_owned) (void)hipFree(ctx->arena_base);
   }
   delete ctx;
@@ -557,6 +558,36 @@ grasp_status check_adam(int32_t t, float lr, float b1, float b2, float eps) {
 // not under stream capture): the order kernel and the step run on stream s
 // after the previous user of the context's order buffer, on any stream, has
 // finished with it. Without memory for the buffer the step runs unordered.
+// The Gauss-Seidel step. A launch with a backward records where every chunk's
+// sweep starts, in an arena buffer of the context shared by every stream:
+// each use waits (on the device) for the previous one.
+grasp_status launch_gs(grasp_ctx* ctx, const StepArgs& a, StepKind kind, bool adam, hipStream_t s,
+                       const char* where) {
+  if (a.B <= 0) return GRASP_OK;
+  hipError_t e = hipSuccess;
+  if (kind == STEP_FWD) {
+    e = launch_gs_step(a, kind, adam, nullptr, s);
+    return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, where);
+  }
+  const size_t need = gs_scratch_floats(a.B, a.hand.n_chunks);
+  std::lock_guard<std::mutex> lk(ctx->gs_mu);
+  if (ctx->gs_cap < need) {
+    // the old buffer may still be read by a launch on another stream
+    if (ctx->gs_ev) e = hipEventSynchronize(ctx->gs_ev);
+    if (e != hipSuccess) return device_fail(ctx, e, where);
+    std::lock_guard<std::mutex> lka(ctx->mu);
+    if (ctx->gs_buf) ctx->arena.free(ctx->gs_buf);
+    ctx->gs_buf = static_cast<float*>(ctx->arena.alloc(need * sizeof(float)));
+    ctx->gs_cap = ctx->gs_buf ? need : 0;
+    if (!ctx->gs_buf) return fail(GRASP_ENOMEM, "arena full (Gauss-Seidel start poses)");
+  }
+  if (!ctx->gs_ev) e = hipEventCreateWithFlags(&ctx->gs_ev, hipEventDisableTiming);
+  else e = hipStreamWaitEvent(s, ctx->gs_ev, 0);
+  if (e == hipSuccess) e = launch_gs_step(a, kind, adam, ctx->gs_buf, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->gs_ev, s);
+  return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, where);
+}
+
 hipError_t launch_ordered_step(grasp_ctx* ctx, StepArgs a, StepKind kind, bool adam, TileCfg tc, hipStream_t s) {
   a.order = nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -614,9 +645,7 @@ grasp_status grasp_step_fwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
     a.loss = loss;
     a.terms = terms;
     DeviceGuard g(ctx->device);
-    const hipError_t e = launch_gs_step(a, STEP_FWD, false, static_cast<hipStream_t>(hip_stream));
-    if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fwd launch");
-    return GRASP_OK;
+    return launch_gs(ctx, a, STEP_FWD, false, static_cast<hipStream_t>(hip_stream), "grasp_step_fwd launch");
   }
   const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
   if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
@@ -648,9 +677,7 @@ grasp_status grasp_step_bwd(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf
     a.dloss = dloss;
     a.dq = dq;
     DeviceGuard g(ctx->device);
-    const hipError_t e = launch_gs_step(a, STEP_BWD, false, static_cast<hipStream_t>(hip_stream));
-    if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_bwd launch");
-    return GRASP_OK;
+    return launch_gs(ctx, a, STEP_BWD, false, static_cast<hipStream_t>(hip_stream), "grasp_step_bwd launch");
   }
   const bool save = p->mode == GRASP_MODE_SAVE || (p->mode == GRASP_MODE_AUTO && ws);
   if (save && (!ws || ws_bytes < pose_ws_bytes(r.prm, B)))
@@ -702,13 +729,10 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   a.dq = dq;
   a.adam = adam_consts(t, lr, b1, b2, eps);
   DeviceGuard g(ctx->device);
-  hipError_t e;
-  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
-    e = launch_gs_step(a, STEP_FUSED, true, static_cast<hipStream_t>(hip_stream));
-  } else {
-    const TileCfg tc = tile_for(ctx, r, B);
-    e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
-  }
+  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL)
+    return launch_gs(ctx, a, STEP_FUSED, true, static_cast<hipStream_t>(hip_stream), "grasp_step_fused launch");
+  const TileCfg tc = tile_for(ctx, r, B);
+  hipError_t e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
   return GRASP_OK;
 }

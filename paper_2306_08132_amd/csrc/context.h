@@ -79,6 +79,12 @@ struct grasp_ctx {
   int* order_buf = nullptr;
   int order_cap = 0;
   hipEvent_t order_ev = nullptr;
+  // start poses of the Gauss-Seidel sweeps (launches with a backward), shared
+  // the same way
+  std::mutex gs_mu;
+  float* gs_buf = nullptr;
+  size_t gs_cap = 0;  // floats
+  hipEvent_t gs_ev = nullptr;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 

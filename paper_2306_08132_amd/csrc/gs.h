@@ -9,13 +9,16 @@
 namespace grasp {
 
 constexpr int kGsWaves = 2;             // candidates (waves) per workgroup
-constexpr int kGsMaxContacts = 8192;    // chunk start poses of every test stay in LDS
+constexpr int kGsMaxContacts = 8192;
 
-// LDS floats of one wave for a hand of n_chunks 64-contact chunks.
-size_t gs_lds_floats(int n_chunks);
+// Floats of the start-pose table a launch with a backward needs: the pose of
+// every (candidate, 64-contact chunk, test) where the chunk's sweep begins.
+size_t gs_scratch_floats(int B, int n_chunks);
 
 // One step with K = 1 and the constraints swept one after another: loss and
 // terms (kind != STEP_BWD), dq and Adam as the averaged step's launch.
-hipError_t launch_gs_step(const StepArgs& a, StepKind kind, bool adam, hipStream_t stream);
+// starts: the start-pose table (device, gs_scratch_floats) unless kind is
+// STEP_FWD, where it may be null.
+hipError_t launch_gs_step(const StepArgs& a, StepKind kind, bool adam, float* starts, hipStream_t stream);
 
 }  // namespace grasp

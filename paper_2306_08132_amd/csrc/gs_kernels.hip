@@ -42,7 +42,9 @@ constexpr int kGScr = kGBar + kSims * 6;     // [6] replay pose
 constexpr int kGZ = kGScr + 8;               // [65][6] poses of a replayed chunk sweep
 constexpr int kGZB = kGZ + (kWave + 1) * 6;  // [65][6] their adjoints
 constexpr int kGAct = kGZB + (kWave + 1) * 6;  // [64] applied lanes (ints)
-constexpr int kGStart = kGAct + kWave;       // [n_chunks][7][6] chunk start poses
+constexpr int kGFloats = kGAct + kWave;
+// The start pose of every (chunk, test) goes to a global table
+// [B][n_chunks][7][6] (written by the forward, read by the backward's replays).
 
 struct GsCtx {
   const HandView& H;
@@ -132,7 +134,7 @@ __device__ unsigned long long gs_sweep(const GsCtx& c, V3 p, bool valid, float* 
 }
 
 template <int LAY>
-__device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, float* lds) {
+__device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, float* lds, float* starts) {
   const HandView& H = A.hand;
   const SdfView& S = A.sdf;
   const StepConsts& P = A.prm;
@@ -143,6 +145,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
   const bool do_bwd = kind != STEP_FWD;
   const float rd = P.r_dil, wmin = P.w_min, inv_Im = S.inv_Im, om = P.omega;
   const int n_chunks = H.n_chunks;
+  float* start_tab = starts ? starts + static_cast<size_t>(b) * n_chunks * kSims * 6 : nullptr;
 
   if (lane < H.L) link_transform(H, qb, lane, lds + kGT + 12 * lane, lds + kGJ + 6 * lane);
   const float dv = P.dt * P.v0;
@@ -171,7 +174,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
     }
     for (int m = 0; m < kSims; ++m) {
       float* Pm = lds + kGPose + 6 * m;
-      if (do_bwd && lane < 6) lds[kGStart + (ch * kSims + m) * 6 + lane] = Pm[lane];
+      if (do_bwd && lane < 6) start_tab[(ch * kSims + m) * 6 + lane] = Pm[lane];
       gs_sweep<LAY>(c, p, valid, Pm, nullptr, nullptr);
     }
   }
@@ -240,7 +243,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
     V3 pacc = v3(0.0f, 0.0f, 0.0f);
     for (int m = 0; m < kSims; ++m) {
       // replay the chunk's sweep of test m
-      if (lane < 6) Scr[lane] = lds[kGStart + (ch * kSims + m) * 6 + lane];
+      if (lane < 6) Scr[lane] = start_tab[(ch * kSims + m) * 6 + lane];
       wave_lds_sync();
       const unsigned long long applied = gs_sweep<LAY>(c, p, valid, Scr, Z, act);
       const int n = __popcll(applied);
@@ -353,26 +356,27 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
   }
 }
 
-__global__ void __launch_bounds__(kGsWaves * kWave) k_gs_step(StepArgs A, int kind, int adam, int lds_floats) {
-  extern __shared__ float lds_all[];
+__global__ void __launch_bounds__(kGsWaves * kWave) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_gs_step(StepArgs A, int kind, int adam, float* starts) {
+  __shared__ float lds_all[kGsWaves * kGFloats];
   const int wave = static_cast<int>(threadIdx.x) / kWave;
   const int b = static_cast<int>(blockIdx.x) * kGsWaves + wave;
   if (b >= A.B) return;
-  float* lds = lds_all + static_cast<size_t>(wave) * lds_floats;
-  if (A.sdf.layout == kLayoutZPairs) gs_candidate<kLayoutZPairs>(A, b, kind, adam != 0, lds);
-  else gs_candidate<kLayoutYZQuads>(A, b, kind, adam != 0, lds);
+  float* lds = lds_all + wave * kGFloats;
+  if (A.sdf.layout == kLayoutZPairs) gs_candidate<kLayoutZPairs>(A, b, kind, adam != 0, lds, starts);
+  else gs_candidate<kLayoutYZQuads>(A, b, kind, adam != 0, lds, starts);
 }
 
 }  // namespace
 
-size_t gs_lds_floats(int n_chunks) { return static_cast<size_t>(kGStart) + static_cast<size_t>(n_chunks) * kSims * 6; }
+size_t gs_scratch_floats(int B, int n_chunks) {
+  return static_cast<size_t>(B) * static_cast<size_t>(n_chunks) * kSims * 6;
+}
 
-hipError_t launch_gs_step(const StepArgs& a, StepKind kind, bool adam, hipStream_t stream) {
+hipError_t launch_gs_step(const StepArgs& a, StepKind kind, bool adam, float* starts, hipStream_t stream) {
   if (a.B <= 0) return hipSuccess;
-  const int lf = static_cast<int>(gs_lds_floats(a.hand.n_chunks));
-  const size_t bytes = static_cast<size_t>(lf) * sizeof(float) * kGsWaves;
   const dim3 grid((a.B + kGsWaves - 1) / kGsWaves), block(kGsWaves * kWave);
-  hipLaunchKernelGGL(k_gs_step, grid, block, bytes, stream, a, static_cast<int>(kind), adam ? 1 : 0, lf);
+  hipLaunchKernelGGL(k_gs_step, grid, block, 0, stream, a, static_cast<int>(kind), adam ? 1 : 0, starts);
   return hipGetLastError();
 }
 
