@@ -265,7 +265,7 @@ typedef struct {
  * active constraints of the test; every step form. GAUSS_SEIDEL: the paper's
  * serial form, each constraint at the pose the previous ones left, in
  * link-major order (contacts stable-sorted by link); grasp_step_fwd, _bwd and
- * _fused only, with K = 1 and at most 8192 contacts; no workspace (the
+ * _fused only, with K = 1; no workspace (the
  * backward replays the sweeps from their start poses, 168 bytes per candidate
  * and 64-contact chunk, which the context keeps in its arena: ENOMEM when it
  * does not fit). */

@@ -479,8 +479,6 @@ grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const 
   std::lock_guard<std::mutex> lk(ctx->mu);
   DevHand* h = find_hand(ctx, hid);
   if (!h) return fail(GRASP_EINVAL, "unknown hand id");
-  if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL && h->view.Nc > kGsMaxContacts)
-    return fail(GRASP_EINVAL, "Gauss-Seidel projection takes at most 8192 contacts");
   DevSdf* s = find_sdf(ctx, sid);
   if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
   r->hand = h->view;

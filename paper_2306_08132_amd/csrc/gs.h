@@ -9,7 +9,6 @@
 namespace grasp {
 
 constexpr int kGsWaves = 2;             // candidates (waves) per workgroup
-constexpr int kGsMaxContacts = 8192;
 
 // Floats of the start-pose table a launch with a backward needs: the pose of
 // every (candidate, 64-contact chunk, test) where the chunk's sweep begins.
