@@ -106,6 +106,16 @@ class DeviceGuard {
 // HIP failure: poison the context and report EDEVICE.
 grasp_status device_fail(grasp_ctx* ctx, hipError_t e, const char* where);
 
+// A usable context: set and not poisoned by an earlier device error.
+inline grasp_status check_ctx(grasp_ctx* ctx) {
+  if (!ctx) return fail(GRASP_EINVAL, "context is NULL");
+  if (ctx->poisoned) return fail(GRASP_EDEVICE, "context poisoned by an earlier device error");
+  return GRASP_OK;
+}
+
+// Arena sub-allocations inside one block start on 256-byte boundaries.
+inline size_t round_up_bytes(size_t x) { return (x + 255) / 256 * 256; }
+
 // Looks up resident objects (caller holds ctx->mu).
 DevHand* find_hand(grasp_ctx* ctx, grasp_hand_id id);
 DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id);

@@ -217,6 +217,36 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   }
 }
 
+// A byte offset past every gather copy (at most 512 * 511^2 * 16 < 0x7F900000
+// bytes, plus a row): loads there read zeros and make no memory request, so a
+// lane that needs no sample can still issue its gather unconditionally.
+constexpr uint32_t kNoCell = 0x7FFF0000u;
+
+// Lower bounds for culling. The block table holds, for every block of 4^3
+// cells, the minimum over the grid vertices of the block widened by one cell
+// on every side. A trilinear value is at least the minimum of its cell's
+// corners, and the sample adds the distance to the grid box outside it; the
+// margins (relative 1e-6 on distances, absolute 1e-6 on the sum) lie far above
+// the FP32 rounding of the sample, so a bound above t means the sample's value
+// exceeds t exactly as the sample computes it (for t = r_dil: d > 0, no
+// active constraint, lambda = 0).
+__device__ __forceinline__ float bound_at(const SdfView& S, V3 r, float& e) {
+  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
+  const int bx = static_cast<int>(ax.i) >> kBlockShift;
+  const int by = static_cast<int>(ay.i) >> kBlockShift;
+  const int bz = static_cast<int>(az.i) >> kBlockShift;
+  // max-norm distance to the grid box (at most the Euclidean one the sample adds)
+  e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
+  return S.bmin[(bz * S.nb + by) * S.nb + bx];
+}
+
+// One sample at grid-frame point r: provably above t.
+__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float t) {
+  float e;
+  const float bm = bound_at(S, r, e);
+  return fmaf(0.999999f, e, bm - t) > 1e-6f;
+}
+
 // H v with H = d(grad phi)/dr of the sample: mixed partials of the trilinear
 // blend on unclamped axes, plus (I - e e^T/|e|^2)/|e| on clamped axes.
 __device__ __forceinline__ V3 hess_mul(const SdfView& S, const Sample& s, V3 v) {

@@ -16,14 +16,6 @@ using namespace grasp;
 
 namespace {
 
-grasp_status check_ctx(grasp_ctx* ctx) {
-  if (!ctx) return fail(GRASP_EINVAL, "context is NULL");
-  if (ctx->poisoned) return fail(GRASP_EDEVICE, "context poisoned by an earlier device error");
-  return GRASP_OK;
-}
-
-size_t round_up_bytes(size_t x) { return (x + 255) / 256 * 256; }
-
 // One sample set checked and appended in link order (stable within a link).
 grasp_status append_set(int n, const int32_t* link, const float* local, const float* w, int L, const char* what,
                         std::vector<float4>& pts, std::vector<int>& links) {

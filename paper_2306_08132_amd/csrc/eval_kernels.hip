@@ -27,23 +27,6 @@ using namespace dev;
 
 constexpr int kCpw = kEvalCandidates;
 constexpr int kAcc = kMaxThresholds + 1;  // thresholds, then the volume
-// a byte offset past every gather copy (at most 512 * 511^2 * 16 < 0x7F900000
-// bytes) whose loads read zeros without a memory request
-constexpr uint32_t kNoCell = 0x7FFF0000u;
-
-// Proven lower bound of the sample at r: the block-minimum table entry plus
-// the max-norm distance to the grid box (as the step's culling, with the same
-// margins over FP32 rounding). True when the sample is provably above t.
-__device__ __forceinline__ bool provably_above(const SdfView& S, V3 r, float t) {
-  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
-  const int bx = static_cast<int>(ax.i) >> kBlockShift;
-  const int by = static_cast<int>(ay.i) >> kBlockShift;
-  const int bz = static_cast<int>(az.i) >> kBlockShift;
-  const float e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
-  const float bm = S.bmin[(bz * S.nb + by) * S.nb + bx];
-  return fmaf(0.999999f, e, bm - t) > 1e-6f;
-}
-
 // Trilinear value of a located sample (the grasp step's arithmetic, without
 // the gradient): the same bits as the step's sample at the same point.
 __device__ __forceinline__ float sample_value(const SdfView& S, const Located& L, float4 lo4, float4 hi4) {
@@ -77,7 +60,7 @@ __device__ __forceinline__ void eval_set(const SdfView& S, const EvalView& E, co
     for (int c = 0; c < kCpw; ++c) {
       const float4* T4 = reinterpret_cast<const float4*>(T + (c * kMaxLinks + l) * 12);
       r[c] = xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z);
-      live[c] = valid && !bad[c] && !provably_above(S, r[c], cut);
+      live[c] = valid && !bad[c] && !provably_clear(S, r[c], cut);
       any = any || live[c];
     }
     if (__builtin_amdgcn_ballot_w64(any) == 0) continue;

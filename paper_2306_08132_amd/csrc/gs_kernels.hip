@@ -29,9 +29,6 @@ namespace {
 
 using namespace dev;
 
-// a byte offset past every gather copy: its loads read zeros, no request
-constexpr uint32_t kNoCell = 0x7FFF0000u;
-
 // per-wave LDS layout (floats)
 constexpr int kGT = 0;                       // [kMaxLinks][12] link transforms
 constexpr int kGJ = kGT + kMaxLinks * 12;    // [kMaxLinks][6] joint world origin, axis
@@ -53,16 +50,6 @@ struct GsCtx {
   float* lds;
   int lane;
 };
-
-__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float rd) {
-  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
-  const int bx = static_cast<int>(ax.i) >> kBlockShift;
-  const int by = static_cast<int>(ay.i) >> kBlockShift;
-  const int bz = static_cast<int>(az.i) >> kBlockShift;
-  const float e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
-  const float bm = S.bmin[(bz * S.nb + by) * S.nb + bx];
-  return fmaf(0.999999f, e, bm - rd) > 1e-6f;
-}
 
 // World position of sorted contact i (0 for padding).
 __device__ __forceinline__ V3 contact_world(const GsCtx& c, int i, int& link) {

@@ -94,19 +94,10 @@ struct Builder {
   }
 };
 
-size_t round_up_bytes(size_t x) { return (x + 255) / 256 * 256; }
-
 float bits_as_float(int i) {
   float f;
   std::memcpy(&f, &i, sizeof f);
   return f;
-}
-
-// A usable context: set and not poisoned by an earlier device error.
-grasp_status check_ctx(grasp_ctx* ctx) {
-  if (!ctx) return fail(GRASP_EINVAL, "context is NULL");
-  if (ctx->poisoned) return fail(GRASP_EDEVICE, "context poisoned by an earlier device error");
-  return GRASP_OK;
 }
 
 DevMesh* find_mesh(grasp_ctx* ctx, grasp_mesh_id id) {

@@ -139,30 +139,6 @@ __device__ __forceinline__ const float* test_consts(const Ctx& c, const LaneTest
   return c.lds + kOffU + kUStride * (lt.m < kSims ? lt.m : kSims - 1);
 }
 
-// Lower bounds for culling. The block table holds, for every block of 4^3
-// cells, the minimum over the grid vertices of the block widened by one cell
-// on every side. A trilinear value is at least the minimum of its cell's
-// corners, and the sample adds the distance to the grid box outside it; the
-// margins (relative 1e-6 on distances, absolute 1e-6 on the sum) lie far above
-// the FP32 rounding of the sample, so a bound above zero means d > 0 exactly
-// as the sample computes it: no active constraint, lambda = 0.
-__device__ __forceinline__ float bound_at(const SdfView& S, V3 r, float& e) {
-  const Axis ax = grid_axis(r.x, S.lo[0], S), ay = grid_axis(r.y, S.lo[1], S), az = grid_axis(r.z, S.lo[2], S);
-  const int bx = static_cast<int>(ax.i) >> kBlockShift;
-  const int by = static_cast<int>(ay.i) >> kBlockShift;
-  const int bz = static_cast<int>(az.i) >> kBlockShift;
-  // max-norm distance to the grid box (at most the Euclidean one the sample adds)
-  e = fmaxf(fabsf(ax.u - ax.b), fmaxf(fabsf(ay.u - ay.b), fabsf(az.u - az.b))) * S.h;
-  return S.bmin[(bz * S.nb + by) * S.nb + bx];
-}
-
-// One sample at grid-frame point r: provably clear of the dilated surface.
-__device__ __forceinline__ bool provably_clear(const SdfView& S, V3 r, float rd) {
-  float e;
-  const float bm = bound_at(S, r, e);
-  return fmaf(0.999999f, e, bm - rd) > 1e-6f;
-}
-
 // All seven test points p + o (|o| <= dv along one axis, dv below the cell
 // size) of a contact at p: each lies in a cell within one of p's cell per
 // axis, so inside p's widened block, and at most dv closer to the grid box.
