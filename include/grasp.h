@@ -265,10 +265,9 @@ typedef struct {
  * active constraints of the test; every step form. GAUSS_SEIDEL: the paper's
  * serial form, each constraint at the pose the previous ones left, in
  * link-major order (contacts stable-sorted by link); grasp_step_fwd, _bwd and
- * _fused only, with K = 1; no workspace (the
- * backward replays the sweeps from their start poses, 168 bytes per candidate
- * and 64-contact chunk, which the context keeps in its arena: ENOMEM when it
- * does not fit). */
+ * _fused only; K iterations are K sweeps. No workspace: the backward replays
+ * the sweeps from their start poses, 168 K bytes per candidate and 64-contact
+ * chunk, which the context keeps in its arena (ENOMEM when they do not fit). */
 #define GRASP_PROJECTION_AVERAGED 0
 #define GRASP_PROJECTION_GAUSS_SEIDEL 1
 

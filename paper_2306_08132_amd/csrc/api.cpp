@@ -465,7 +465,7 @@ struct Resolved {
 };
 
 // gs_ok: the entry point also runs the Gauss-Seidel projection (single-job
-// fwd, bwd and fused steps with K = 1).
+// fwd, bwd and fused steps).
 grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const grasp_step_params* p, int32_t B,
                      Resolved* r, bool gs_ok = false) {
   if (B < 0) return fail(GRASP_EINVAL, "B must be >= 0");
@@ -474,7 +474,6 @@ grasp_status resolve(grasp_ctx* ctx, grasp_hand_id hid, grasp_sdf_id sid, const 
   if (p->projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
     if (!gs_ok)
       return fail(GRASP_EINVAL, "Gauss-Seidel projection runs in grasp_step_fwd, grasp_step_bwd and grasp_step_fused");
-    if (p->K != 1) return fail(GRASP_EINVAL, "Gauss-Seidel projection runs with K = 1");
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   DevHand* h = find_hand(ctx, hid);
@@ -567,7 +566,7 @@ grasp_status launch_gs(grasp_ctx* ctx, const StepArgs& a, StepKind kind, bool ad
     e = launch_gs_step(a, kind, adam, nullptr, s);
     return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, where);
   }
-  const size_t need = gs_scratch_floats(a.B, a.hand.n_chunks);
+  const size_t need = gs_scratch_floats(a.B, a.hand.n_chunks, a.prm.K);
   std::lock_guard<std::mutex> lk(ctx->gs_mu);
   if (ctx->gs_cap < need) {
     // the old buffer may still be read by a launch on another stream

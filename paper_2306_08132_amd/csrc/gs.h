@@ -11,10 +11,11 @@ namespace grasp {
 constexpr int kGsWaves = 2;             // candidates (waves) per workgroup
 
 // Floats of the start-pose table a launch with a backward needs: the pose of
-// every (candidate, 64-contact chunk, test) where the chunk's sweep begins.
-size_t gs_scratch_floats(int B, int n_chunks);
+// every (candidate, iteration, 64-contact chunk, test) where a chunk's sweep
+// begins.
+size_t gs_scratch_floats(int B, int n_chunks, int K);
 
-// One step with K = 1 and the constraints swept one after another: loss and
+// One step with the constraints swept one after another: loss and
 // terms (kind != STEP_BWD), dq and Adam as the averaged step's launch.
 // starts: the start-pose table (device, gs_scratch_floats) unless kind is
 // STEP_FWD, where it may be null.

@@ -2,7 +2,8 @@
 // Eq. (1) updates of the contact constraints applied one after another, each
 // at the pose the previous ones left), with one projection iteration, its
 // hand-written adjoint with the leaky contact gradient, the losses of
-// Sec. IV-A and Adam.
+// Sec. IV-A and Adam; K projection iterations are K sweeps, each continuing
+// from the pose the previous one left.
 //
 // Execution model: one wavefront per candidate; lanes hold 64 consecutive
 // contacts of the link-sorted order (the sweep order). For each chunk and
@@ -40,8 +41,9 @@ constexpr int kGZ = kGScr + 8;               // [65][6] poses of a replayed chun
 constexpr int kGZB = kGZ + (kWave + 1) * 6;  // [65][6] their adjoints
 constexpr int kGAct = kGZB + (kWave + 1) * 6;  // [64] applied lanes (ints)
 constexpr int kGFloats = kGAct + kWave;
-// The start pose of every (chunk, test) goes to a global table
-// [B][n_chunks][7][6] (written by the forward, read by the backward's replays).
+// The start pose of every (iteration, chunk, test) sweep goes to a global
+// table [B][K][n_chunks][7][6] (written by the forward, read by the
+// backward's replays).
 
 struct GsCtx {
   const HandView& H;
@@ -132,7 +134,8 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
   const bool do_bwd = kind != STEP_FWD;
   const float rd = P.r_dil, wmin = P.w_min, inv_Im = S.inv_Im, om = P.omega;
   const int n_chunks = H.n_chunks;
-  float* start_tab = starts ? starts + static_cast<size_t>(b) * n_chunks * kSims * 6 : nullptr;
+  const int nk = P.K * n_chunks;  // sweeps of every test: K iterations over the chunks
+  float* start_tab = starts ? starts + static_cast<size_t>(b) * nk * kSims * 6 : nullptr;
 
   if (lane < H.L) link_transform(H, qb, lane, lds + kGT + 12 * lane, lds + kGJ + 6 * lane);
   const float dv = P.dt * P.v0;
@@ -143,14 +146,16 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
   }
   wave_lds_sync();
 
-  // ---- forward: rest-pose penetration, then the sweeps of every test ----
+  // ---- forward: rest-pose penetration, then the sweeps of every test, K
+  // iterations each continuing from the pose the last one left ----
   float lp = 0.0f;
-  for (int ch = 0; ch < n_chunks; ++ch) {
+  for (int kc = 0; kc < nk; ++kc) {
+    const int ch = kc % n_chunks;
     const int i = ch * kWave + lane;
     const bool valid = i < H.Nc;
     int link;
     const V3 p = contact_world(c, i, link);
-    {
+    if (kc < n_chunks) {
       const bool live = valid && !provably_clear(S, p, rd);
       if (__builtin_amdgcn_ballot_w64(live) != 0) {
         Sample s;
@@ -161,7 +166,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
     }
     for (int m = 0; m < kSims; ++m) {
       float* Pm = lds + kGPose + 6 * m;
-      if (do_bwd && lane < 6) start_tab[(ch * kSims + m) * 6 + lane] = Pm[lane];
+      if (do_bwd && lane < 6) start_tab[(kc * kSims + m) * 6 + lane] = Pm[lane];
       gs_sweep<LAY>(c, p, valid, Pm, nullptr, nullptr);
     }
   }
@@ -222,7 +227,8 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
   float* Z = lds + kGZ;
   float* ZB = lds + kGZB;
   int* act = reinterpret_cast<int*>(lds + kGAct);
-  for (int ch = n_chunks - 1; ch >= 0; --ch) {
+  for (int kc = nk - 1; kc >= 0; --kc) {
+    const int ch = kc % n_chunks;
     const int i = ch * kWave + lane;
     const bool valid = i < H.Nc;
     int link;
@@ -230,7 +236,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
     V3 pacc = v3(0.0f, 0.0f, 0.0f);
     for (int m = 0; m < kSims; ++m) {
       // replay the chunk's sweep of test m
-      if (lane < 6) Scr[lane] = start_tab[(ch * kSims + m) * 6 + lane];
+      if (lane < 6) Scr[lane] = start_tab[(kc * kSims + m) * 6 + lane];
       wave_lds_sync();
       const unsigned long long applied = gs_sweep<LAY>(c, p, valid, Scr, Z, act);
       const int n = __popcll(applied);
@@ -288,8 +294,8 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
       pacc = pacc + pb;
       wave_lds_sync();
     }
-    // rest-pose penetration
-    {
+    // rest-pose penetration (once per chunk)
+    if (kc < n_chunks) {
       Sample s;
       sample_at<LAY>(S, p, valid, s);
       const float d = s.phi - rd;
@@ -356,8 +362,8 @@ k_gs_step(StepArgs A, int kind, int adam, float* starts) {
 
 }  // namespace
 
-size_t gs_scratch_floats(int B, int n_chunks) {
-  return static_cast<size_t>(B) * static_cast<size_t>(n_chunks) * kSims * 6;
+size_t gs_scratch_floats(int B, int n_chunks, int K) {
+  return static_cast<size_t>(B) * static_cast<size_t>(K) * static_cast<size_t>(n_chunks) * kSims * 6;
 }
 
 hipError_t launch_gs_step(const StepArgs& a, StepKind kind, bool adam, float* starts, hipStream_t stream) {
