@@ -56,6 +56,39 @@ int main() {
   if (oracle_optimize(&h, &o, &p, B, qq, 3, 0.01, 1e-3, 0.9, 0.999, 1e-8, 0, fl, ft, rank, nullptr, 2)) return 4;
   for (int b = 0; b < B; ++b)
     if (!std::isfinite(loss[b]) || !std::isfinite(fl[b])) return 5;
+  // the literal Gauss-Seidel sweep
+  oparams pg = p;
+  pg.projection = 1;
+  double lgs[B], ggs[B * nd];
+  if (oracle_step(&h, &o, &pg, B, q, lgs, nullptr, ggs, nullptr, 2)) return 6;
+  // evaluation metrics of weighted samples, then the best two by loss
+  double sa[Nc], sv[Nc];
+  for (int i = 0; i < Nc; ++i) { sa[i] = 1e-5 * (i + 1); sv[i] = 1e-7 * (i + 1); }
+  oeval ev{Nc, lk, cl, sa, Nc, lk, cl, sv};
+  const double thr[3] = {0.002, 0.005, 0.009};
+  double met[B * 4], slack[B * 4], mean[4];
+  int top[2];
+  if (oracle_evaluate(&h, &o, B, q, &ev, 3, thr, 1e-6, met, slack, 2)) return 7;
+  if (oracle_select_top(B, loss, 0, 2, 4, met, top, mean)) return 8;
+  // a tetrahedron mesh, flat and curved
+  const double tv[12] = {0, 0, 0, 0.05, 0, 0, 0, 0.05, 0, 0, 0, 0.05};
+  const int tf[12] = {0, 2, 1, 0, 1, 3, 0, 3, 2, 1, 2, 3};
+  double tn[12];
+  for (int i = 0; i < 4; ++i) {
+    double c[3], len = 0.0;
+    for (int k = 0; k < 3; ++k) { c[k] = tv[3 * i + k] - 0.0125; len += c[k] * c[k]; }
+    for (int k = 0; k < 3; ++k) tn[3 * i + k] = c[k] / std::sqrt(len);
+  }
+  const double pts[9] = {0.01, 0.01, 0.01, 0.1, -0.02, 0.03, 0.02, 0.02, -0.01};
+  double rho[3], grd[9], clo[9], dfl[3], gap[3], spr[3];
+  int face[3];
+  for (double alpha : {0.0, 0.75}) {
+    omesh msh{4, tv, tn, 4, tf, alpha};
+    if (oracle_mesh_sdf(&msh, 3, pts, rho, grd, clo, face, dfl, gap, spr)) return 9;
+    if (!(rho[0] < 0.0) || !(rho[1] > 0.0)) return 10;
+  }
+  int top3[3];
+  if (oracle_select_top(B, loss, 1, 3, 0, nullptr, top3, nullptr)) return 11;
   std::printf("oracle ok %g %g %g\n", loss[0], loss[1], loss[2]);
   (void)m; (void)v;
   return 0;

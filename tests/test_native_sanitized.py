@@ -1,5 +1,6 @@
 """Host code under AddressSanitizer and UBSan (CPU only): the context arena
-allocator against a byte-map model, and the oracle on a small problem."""
+allocator against a byte-map model, and the oracle on a small problem (both
+projection forms, the evaluation metrics and top-k, a tetrahedron mesh)."""
 import os
 import subprocess
 
@@ -29,5 +30,6 @@ def test_arena_under_sanitizers(tmp_path):
 def test_oracle_under_sanitizers(tmp_path):
     od = os.path.join(ROOT, "oracle")
     out = build_and_run(tmp_path, "oracle_check", [os.path.join(ROOT, "tests", "native", "oracle_check.cpp"),
-                                                    os.path.join(od, "oracle.cpp")], [od], extra=["-fopenmp"])
+                                                    os.path.join(od, "oracle.cpp"), os.path.join(od, "mesh.cpp")],
+                        [od], extra=["-fopenmp"])
     assert "oracle ok" in out
