@@ -585,30 +585,44 @@ grasp_status launch_gs(grasp_ctx* ctx, const StepArgs& a, StepKind kind, bool ad
   return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, where);
 }
 
-hipError_t launch_ordered_step(grasp_ctx* ctx, StepArgs a, StepKind kind, bool adam, TileCfg tc, hipStream_t s) {
-  a.order = nullptr;
+}  // namespace
+
+// Runs launch(order) with the candidates of q in locality order (order =
+// null when there are too few, the stream is being captured or the arena
+// has no room): one arena buffer of the context shared by every stream,
+// each use waiting (on the device) for the previous one.
+hipError_t grasp::launch_with_order(grasp_ctx* ctx, const float* q, int n_dof, int B, const SdfView& S,
+                                    hipStream_t s, const std::function<hipError_t(const int*)>& launch) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return e;
-  if (a.B < kOrderMinB || cap != hipStreamCaptureStatusNone) return launch_step(a, kind, adam, tc, s);
+  if (B < kOrderMinB || cap != hipStreamCaptureStatusNone) return launch(nullptr);
   std::lock_guard<std::mutex> lk(ctx->order_mu);
-  if (ctx->order_cap < a.B) {
+  if (ctx->order_cap < B) {
     // the old buffer may still be read by a launch on another stream
     if (ctx->order_ev) e = hipEventSynchronize(ctx->order_ev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lka(ctx->mu);
     if (ctx->order_buf) ctx->arena.free(ctx->order_buf);
-    ctx->order_buf = static_cast<int*>(ctx->arena.alloc(static_cast<size_t>(a.B) * sizeof(int)));
-    ctx->order_cap = ctx->order_buf ? a.B : 0;
+    ctx->order_buf = static_cast<int*>(ctx->arena.alloc(static_cast<size_t>(B) * sizeof(int)));
+    ctx->order_cap = ctx->order_buf ? B : 0;
   }
-  if (!ctx->order_buf) return launch_step(a, kind, adam, tc, s);
+  if (!ctx->order_buf) return launch(nullptr);
   if (!ctx->order_ev) e = hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming);
   else e = hipStreamWaitEvent(s, ctx->order_ev, 0);
-  if (e == hipSuccess) e = launch_order(a.q, a.hand.n_dof, a.B, a.sdf, ctx->order_buf, s);
-  a.order = ctx->order_buf;
-  if (e == hipSuccess) e = launch_step(a, kind, adam, tc, s);
+  if (e == hipSuccess) e = launch_order(q, n_dof, B, S, ctx->order_buf, s);
+  if (e == hipSuccess) e = launch(ctx->order_buf);
   if (e == hipSuccess) e = hipEventRecord(ctx->order_ev, s);
   return e;
+}
+
+namespace {
+
+hipError_t launch_ordered_step(grasp_ctx* ctx, StepArgs a, StepKind kind, bool adam, TileCfg tc, hipStream_t s) {
+  return launch_with_order(ctx, a.q, a.hand.n_dof, a.B, a.sdf, s, [&](const int* order) {
+    a.order = order;
+    return launch_step(a, kind, adam, tc, s);
+  });
 }
 
 }  // namespace

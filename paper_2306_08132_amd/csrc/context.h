@@ -126,6 +126,11 @@ DevSdf* find_sdf(grasp_ctx* ctx, grasp_sdf_id id);
 grasp_status install_grid(grasp_ctx* ctx, int n, const float lo[3], float h, double Im, int layout,
                           const std::function<hipError_t(float*)>& fill, grasp_sdf_id* out);
 
+// Runs launch(order) with the candidates of q in locality order, or with
+// order = null (few candidates, stream capture, no arena room).
+hipError_t launch_with_order(grasp_ctx* ctx, const float* q, int n_dof, int B, const SdfView& S, hipStream_t s,
+                             const std::function<hipError_t(const int*)>& launch);
+
 // Checks one batch job and resolves its hand, grid and constants.
 grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c);
 

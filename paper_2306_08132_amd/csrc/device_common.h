@@ -217,6 +217,19 @@ __device__ __forceinline__ void sample_sdf(const SdfView& S, V3 r, Sample& s) {
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block i to XCD i mod
+// 8). This maps them so that each XCD works on one contiguous range of work
+// items, and with a locality order on candidates whose contacts touch
+// neighbouring grid cells: each XCD's L2 then holds a compact part of the
+// grid. A bijection on [0, nblk) for the first nblk blocks (those holding
+// work); blocks past nblk keep their index. Results never depend on it.
+__device__ __forceinline__ int xcd_block(int nblk) {
+  const int blk = static_cast<int>(blockIdx.x);
+  if (blk >= nblk) return blk;
+  const int per = nblk >> 3, rem = nblk & 7, x = blk & 7;
+  return x * per + min(x, rem) + (blk >> 3);
+}
+
 // A byte offset past every gather copy (at most 512 * 511^2 * 16 < 0x7F900000
 // bytes, plus a row): loads there read zeros and make no memory request, so a
 // lane that needs no sample can still issue its gather unconditionally.

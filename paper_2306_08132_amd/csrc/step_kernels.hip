@@ -707,18 +707,6 @@ __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kin
   else candidate_step_lay<KONE, kLayoutYZQuads>(A, b, kind, adam, lds);
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block i to XCD i mod
-// 8). This maps them so that each XCD works on one contiguous range of work
-// items, and with a locality order on candidates whose contacts touch
-// neighbouring grid cells: each XCD's L2 then holds a compact part of the
-// grid. A bijection on [0, nblk) for the first nblk blocks (those holding
-// work); blocks past nblk keep their index. Results never depend on it.
-__device__ __forceinline__ int xcd_block(int nblk) {
-  const int blk = static_cast<int>(blockIdx.x);
-  if (blk >= nblk) return blk;
-  const int per = nblk >> 3, rem = nblk & 7, x = blk & 7;
-  return x * per + min(x, rem) + (blk >> 3);
-}
 
 // Locality order: candidates bucketed by the direction of the wrist from
 // the grid's centre (a 4-bit-per-axis Morton code of the unit direction),
