@@ -325,6 +325,14 @@ def gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args):
         prm = StepParams(K=1, projection=1, r_dil=r0 * (1.0 - min(t, T - 1) / (T - 1)))
         ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
 
+    # forward only (loss), at the initial candidates: its share of the step
+    fwd_prm = StepParams(K=1, projection=1, r_dil=r0)
+    ctx.step_fwd(h, sd, fwd_prm, q, loss, stream=stream)
+    fe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    for a, b in fe:
+        a.record(stream)
+        ctx.step_fwd(h, sd, fwd_prm, q, loss, stream=stream)
+        b.record(stream)
     for t in range(2):
         step(t)
     n = max(3, args.steps // 5)
@@ -335,8 +343,9 @@ def gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args):
         b.record(stream)
     torch.cuda.synchronize()
     ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in fe]))
     evals = q.shape[0] * hand.n_contacts * 7
-    res = {"kernel": "k_gs_step", "ms_per_step": ms, "contact_evals_per_s": evals / (ms * 1e-3), "steps": n,
+    res = {"kernel": "k_gs_step", "ms_per_step": ms, "forward_only_ms": fwd_ms, "contact_evals_per_s": evals / (ms * 1e-3), "steps": n,
            "averaged_ms_per_step": avg_ms, "gs_over_averaged_time": ms / avg_ms,
            "final_loss_mean": float(loss.mean())}
     print(f"bench: Gauss-Seidel {ms:.3f} ms/step ({ms / avg_ms:.1f}x the averaged step)", file=sys.stderr,
