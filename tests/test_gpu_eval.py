@@ -115,6 +115,26 @@ def test_unit_weights_count_exactly(ctx):
     h.destroy()
 
 
+def test_eight_thresholds_and_a_large_top_k(ctx):
+    """The most thresholds one call takes (8, negative ones included), and
+    the top 64 of 2^20 keys."""
+    hand, grid, q, ev = small_case(seed=9)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    gev = ctx.eval_points(h, ev)
+    thr = np.float32([-0.004, -0.001, 0.0, 0.001, 0.002, 0.005, 0.009, 0.02])
+    got = ctx.evaluate(gev, sd, dev(q), thr).cpu().numpy().astype(np.float64)
+    ref, slack = oracle_metrics(hand, grid, q, ev, thr)
+    check(got, ref, slack, ev, "eight thresholds")
+    rng = np.random.default_rng(12)
+    key = keys(rng, 1 << 20)
+    top, _ = ctx.select_top(dev(key), 64, False)
+    rt, _ = O.select_top(key.astype(np.float64), 64, False)
+    assert np.array_equal(top.cpu().numpy(), rt)
+    gev.unload()
+    sd.unload()
+    h.destroy()
+
+
 def test_volume_only_and_surface_only_sets(ctx):
     hand, grid, q, ev = small_case(seed=4)
     h, sd = ctx.hand(hand), ctx.sdf(grid)

@@ -176,6 +176,12 @@ def test_gs_refusals(ctx):
     with pytest.raises(GraspError, match="Gauss-Seidel"):
         ctx.plain_step(h, sd, StepParams(projection=GS), qd, torch.zeros_like(qd), torch.zeros_like(qd), 1,
                        torch.empty(4, dtype=torch.uint8, device=DEV), loss=loss)
+    # no candidates: every form returns without launching
+    q0 = torch.empty((0, hand.n_dof), device=DEV)
+    ctx.step_fwd(h, sd, StepParams(projection=GS), q0, torch.empty(0, device=DEV))
+    ctx.step_bwd(h, sd, StepParams(projection=GS), q0, torch.empty_like(q0))
+    ctx.step_fused(h, sd, StepParams(projection=GS), q0, torch.empty_like(q0), torch.empty_like(q0), 1)
+    torch.cuda.synchronize()
     sd.unload()
     h.destroy()
 
