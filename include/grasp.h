@@ -408,7 +408,13 @@ grasp_status grasp_batch_flags(grasp_batch* batch, int32_t n, int32_t* out);
  * fits the arena and the candidate capacity; advances every resident job by
  * one optimizer step per batched launch; and retires a job after its T steps
  * with one forward at r_dil = 0 (final loss, terms) and the ranking, freeing
- * its memory. Hands and grids stay resident and are shared between jobs.
+ * its memory. Hands and grids stay resident and are shared between jobs. A
+ * job may also name an evaluation set of its hand: it then retires with the
+ * post-synthesis metrics of every candidate at its final configuration and,
+ * with top_k > 0, the top_k best by final loss and their mean metrics (the
+ * paper's top-10 figures); the set must stay loaded until the job ends (else
+ * the job ends with EINVAL), and its footprint grows by 4 (n_thr + 1) bytes
+ * per candidate.
  * ------------------------------------------------------------------------- */
 typedef struct {
   grasp_hand_id hand;
@@ -419,6 +425,10 @@ typedef struct {
   float r0;              /* initial dilation; r(t) = r0 (1 - t/(T-1)) */
   grasp_step_params p;   /* p.r_dil is ignored */
   float lr, b1, b2, eps; /* Adam */
+  grasp_eval_id eval;    /* evaluation set of the job's hand (grasp_load_eval_points), or 0 for none */
+  int32_t n_thr;         /* with eval: contact-area thresholds in thresholds[], 1..GRASP_MAX_THRESHOLDS */
+  float thresholds[GRASP_MAX_THRESHOLDS]; /* metres, finite */
+  int32_t top_k;         /* with eval: 0..min(B, GRASP_MAX_TOP); without: 0 */
 } grasp_job_desc;
 
 typedef struct {
@@ -429,6 +439,10 @@ typedef struct {
   int32_t* rank;         /* host [B]: candidate indices by ascending final loss (ties by index), or NULL */
   double t_submit, t_admit, t_done; /* seconds since grasp_init */
   int32_t steps;         /* optimizer steps the job took */
+  float* metrics;        /* host [B][n_thr + 1]: contact areas and intersection volume at the final q (jobs
+                            with an evaluation set), or NULL */
+  int32_t* top;          /* host [top_k]: the best candidates by final loss, best first, or NULL */
+  float* top_mean;       /* host [n_thr + 1]: their mean metrics, or NULL */
 } grasp_job_result;
 
 /* Sets the scheduler's candidate capacity per step (default 65536) and job

@@ -154,29 +154,41 @@ class Context:
         self.lib.call("grasp_serve_config", self.h, capacity, max_jobs)
 
     def submit(self, hand, sdf, q0, T: int, r0: float = 0.01, prm: StepParams | None = None, lr=1e-3, b1=0.9,
-               b2=0.999, eps=1e-8) -> int:
-        """Queues a grasp job (host q0 [B][n_dof]); returns its id."""
+               b2=0.999, eps=1e-8, eval_points=None, thresholds=(), top_k: int = 0) -> int:
+        """Queues a grasp job (host q0 [B][n_dof]); returns its id. With an
+        evaluation set the job retires with its metrics at the given
+        thresholds and, with top_k, the best candidates and their means."""
         q0 = _f32(q0)
         prm = prm or StepParams()
-        d = JobDescC(hand.id, sdf.id, q0.shape[0], q0.ctypes.data, T, r0, prm.c(), lr, b1, b2, eps)
+        thr = [float(x) for x in thresholds]
+        d = JobDescC(hand.id, sdf.id, q0.shape[0], q0.ctypes.data, T, r0, prm.c(), lr, b1, b2, eps,
+                     eval_points.id if eval_points is not None else 0, len(thr),
+                     (C.c_float * 8)(*(thr + [0.0] * (8 - len(thr)))[:8]), top_k)
         out = C.c_uint64()
         self.lib.call("grasp_submit", self.h, C.byref(d), C.byref(out))
         return out.value
 
-    def poll(self, job: int, B: int, n_dof: int):
-        """None while the job runs; then a dict of its results (status, q, loss, terms, rank, times)."""
+    def poll(self, job: int, B: int, n_dof: int, n_metrics: int = 0, top_k: int = 0):
+        """None while the job runs; then a dict of its results (status, q, loss, terms, rank, times, and
+        for jobs with an evaluation set: metrics [B][n_metrics], top [top_k], top_mean [n_metrics])."""
         q = np.zeros((B, n_dof), np.float32)
         loss = np.zeros(B, np.float32)
         terms = np.zeros((B, 4), np.float32)
         rank = np.zeros(B, np.int32)
-        r = JobResultC(0, q.ctypes.data, loss.ctypes.data, terms.ctypes.data, rank.ctypes.data, 0, 0, 0, 0)
+        met = np.zeros((B, n_metrics), np.float32) if n_metrics else None
+        top = np.zeros(top_k, np.int32) if top_k else None
+        mean = np.zeros(n_metrics, np.float32) if top_k else None
+        ptr = lambda a: None if a is None else a.ctypes.data
+        r = JobResultC(0, q.ctypes.data, loss.ctypes.data, terms.ctypes.data, rank.ctypes.data, 0, 0, 0, 0,
+                       ptr(met), ptr(top), ptr(mean))
         code = self.lib.grasp_poll(self.h, job, C.byref(r))
         if code == GRASP_EAGAIN:
             return None
         if code not in (0, -6, -7):
             self.lib.check(code, "grasp_poll")
         return {"status": r.status, "q": q, "loss": loss, "terms": terms, "rank": rank, "t_submit": r.t_submit,
-                "t_admit": r.t_admit, "t_done": r.t_done, "steps": r.steps}
+                "t_admit": r.t_admit, "t_done": r.t_done, "steps": r.steps, "metrics": met, "top": top,
+                "top_mean": mean}
 
     def cancel(self, job: int):
         self.lib.call("grasp_cancel", self.h, job)

@@ -49,17 +49,25 @@ struct Job {
   size_t footprint = 0;
   void* block = nullptr;
   float *q = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr, *terms = nullptr;
+  float *metrics = nullptr, *mean = nullptr;  // evaluation at retirement (jobs with an evaluation set)
+  int32_t* top = nullptr;
   int t = 0;
-  std::vector<float> out_q, out_loss, out_terms;
-  std::vector<int32_t> rank;
+  std::vector<float> out_q, out_loss, out_terms, out_metrics, out_mean;
+  std::vector<int32_t> rank, out_top;
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
-size_t job_footprint(int B, int n_dof) {
+// q, m, v, loss, terms; with an evaluation set, the metrics [B][M], the top
+// indices and their mean metrics.
+size_t job_footprint(int B, int n_dof, int M, int top_k) {
   const size_t b = static_cast<size_t>(B);
   auto r = [](size_t x) { return (x + 255) / 256 * 256; };
-  return 3 * r(b * n_dof * 4) + r(b * 4) + r(b * 16);
+  size_t f = 3 * r(b * n_dof * 4) + r(b * 4) + r(b * 16);
+  if (M > 0) f += r(b * M * 4) + r(static_cast<size_t>(top_k) * 4) + r(static_cast<size_t>(M) * 4);
+  return f;
 }
+
+int job_metrics(const grasp_job_desc& d) { return d.eval ? d.n_thr + 1 : 0; }
 
 }  // namespace
 
@@ -119,6 +127,12 @@ bool Scheduler::admit_one(Job& j) {
   j.v = reinterpret_cast<float*>(p + 2 * nq);
   j.loss = reinterpret_cast<float*>(p + 3 * nq);
   j.terms = reinterpret_cast<float*>(p + 3 * nq + r(b * 4));
+  if (const int M = job_metrics(j.desc); M > 0) {
+    char* e = p + 3 * nq + r(b * 4) + r(b * 16);
+    j.metrics = reinterpret_cast<float*>(e);
+    j.top = reinterpret_cast<int32_t*>(e + r(b * M * 4));
+    j.mean = reinterpret_cast<float*>(e + r(b * M * 4) + r(static_cast<size_t>(j.desc.top_k) * 4));
+  }
   hipError_t e = hipMemcpyAsync(j.q, j.q0.data(), b * j.n_dof * 4, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemsetAsync(j.m, 0, 2 * nq, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -141,6 +155,11 @@ void Scheduler::finish(Job& j) {
     p.r_dil = 0.0f;
     p.mode = GRASP_MODE_RECOMPUTE;
     grasp_status st = grasp_step_fwd(ctx, j.desc.hand, j.desc.sdf, &p, B, j.q, j.loss, j.terms, nullptr, 0, stream);
+    // post-synthesis evaluation at the final configurations, then the best by final loss
+    if (st == GRASP_OK && j.metrics)
+      st = grasp_evaluate(ctx, j.desc.eval, j.desc.sdf, B, j.q, j.desc.n_thr, j.desc.thresholds, j.metrics, stream);
+    if (st == GRASP_OK && j.metrics && j.desc.top_k > 0)
+      st = grasp_select_top(ctx, B, j.loss, 0, j.desc.top_k, j.desc.n_thr + 1, j.metrics, j.top, j.mean, stream);
     if (st != GRASP_OK) j.status = st;
   }
   if (j.state == JobState::Resident) {
@@ -151,6 +170,17 @@ void Scheduler::finish(Job& j) {
     if (e == hipSuccess) e = hipMemcpy(j.out_q.data(), j.q, j.out_q.size() * 4, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(j.out_loss.data(), j.loss, j.out_loss.size() * 4, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(j.out_terms.data(), j.terms, j.out_terms.size() * 4, hipMemcpyDeviceToHost);
+    if (j.metrics && j.status == GRASP_OK) {
+      const size_t M = static_cast<size_t>(j.desc.n_thr) + 1;
+      j.out_metrics.resize(static_cast<size_t>(B) * M);
+      if (e == hipSuccess) e = hipMemcpy(j.out_metrics.data(), j.metrics, j.out_metrics.size() * 4, hipMemcpyDeviceToHost);
+      if (j.desc.top_k > 0) {
+        j.out_top.resize(j.desc.top_k);
+        j.out_mean.resize(M);
+        if (e == hipSuccess) e = hipMemcpy(j.out_top.data(), j.top, j.out_top.size() * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(j.out_mean.data(), j.mean, M * 4, hipMemcpyDeviceToHost);
+      }
+    }
     if (e != hipSuccess) {
       fatal = device_fail(ctx, e, "scheduler results");
       j.status = GRASP_EDEVICE;
@@ -391,13 +421,27 @@ grasp_status grasp_submit(grasp_ctx* ctx, const grasp_job_desc* d, grasp_job_id*
   StepConsts sc;
   grasp_status st = resolve_job(ctx, probe, &hv, &sv, &sc);
   if (st != GRASP_OK) return st;
+  if (d->eval) {
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      auto it = ctx->evals.find(d->eval);
+      if (it == ctx->evals.end()) return fail(GRASP_EINVAL, "unknown evaluation set id");
+      if (it->second->hand != d->hand) return fail(GRASP_EINVAL, "the evaluation set belongs to another hand");
+    }
+    if (d->n_thr < 1 || d->n_thr > GRASP_MAX_THRESHOLDS) return fail(GRASP_EINVAL, "n_thr must be in [1, 8]");
+    for (int t = 0; t < d->n_thr; ++t)
+      if (!std::isfinite(d->thresholds[t])) return fail(GRASP_EINVAL, "thresholds must be finite");
+    if (d->top_k < 0 || d->top_k > std::min(d->B, GRASP_MAX_TOP)) return fail(GRASP_EINVAL, "top_k must be in [0, min(B, 64)]");
+  } else if (d->top_k != 0) {
+    return fail(GRASP_EINVAL, "top_k needs an evaluation set");
+  }
   st = GRASP_OK;
   Scheduler* s = sched_of(ctx, true, &st);
   auto j = std::make_unique<Job>();
   j->desc = *d;
   j->n_dof = n_dof;
   j->n_contacts = nc;
-  j->footprint = job_footprint(d->B, n_dof);
+  j->footprint = job_footprint(d->B, n_dof, job_metrics(*d), d->eval ? d->top_k : 0);
   j->q0.assign(d->q0, d->q0 + static_cast<size_t>(d->B) * n_dof);
   j->desc.q0 = nullptr;
   {
@@ -437,6 +481,9 @@ grasp_status grasp_poll(grasp_ctx* ctx, grasp_job_id id, grasp_job_result* r) {
     if (r->loss) std::memcpy(r->loss, j.out_loss.data(), static_cast<size_t>(B) * 4);
     if (r->terms) std::memcpy(r->terms, j.out_terms.data(), static_cast<size_t>(B) * 16);
     if (r->rank) std::memcpy(r->rank, j.rank.data(), static_cast<size_t>(B) * 4);
+    if (r->metrics && !j.out_metrics.empty()) std::memcpy(r->metrics, j.out_metrics.data(), j.out_metrics.size() * 4);
+    if (r->top && !j.out_top.empty()) std::memcpy(r->top, j.out_top.data(), j.out_top.size() * 4);
+    if (r->top_mean && !j.out_mean.empty()) std::memcpy(r->top_mean, j.out_mean.data(), j.out_mean.size() * 4);
   }
   r->status = j.status;
   r->t_submit = j.t_submit;

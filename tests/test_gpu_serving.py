@@ -1,6 +1,7 @@
 """GPU: the serving loop. A job's results are the same alone and in a mix
 of overlapping jobs (bit-exact), cancelled and non-finite jobs end without
-disturbing the others, and jobs that can never fit are refused."""
+disturbing the others, jobs that can never fit are refused, and a job with an
+evaluation set retires with its metrics and top 10."""
 import time
 
 import numpy as np
@@ -111,3 +112,43 @@ def test_refusals(setup):
         ctx.poll(123456789, 1, h.n_dof)
     st = ctx.serve_stats()
     assert st["steps"] > 0 and st["contact_evals"] > 0
+
+
+def test_job_with_evaluation(setup):
+    """A job that names an evaluation set retires with the metrics of every
+    candidate at its final configuration and the top 10 by final loss: the
+    same bits as evaluating and selecting on the job's returned q and loss."""
+    from paper_2306_08132_amd._lib import GraspError
+    ctx, _ = setup
+    dev = "cuda:0"
+    hand = S.make_hand(3, 3, 256, seed=70)
+    grid = S.make_grid(S.make_object("ellipsoids", seed=71, n_range=(2, 3)), 32)
+    q = S.make_candidates(hand, 48, seed=72, shell_radius=grid.bound_radius + 0.04).astype(np.float32)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    ev = ctx.eval_points(h, S.make_eval_points(hand, 700, 500, seed=73))
+    thr = [0.002, 0.005, 0.009]
+    say("serving: job with evaluation")
+    jid = ctx.submit(h, sd, q, T=6, eval_points=ev, thresholds=thr, top_k=10)
+    t0 = time.time()
+    r = None
+    while r is None and time.time() - t0 < 120.0:
+        r = ctx.poll(jid, q.shape[0], h.n_dof, n_metrics=4, top_k=10)
+        time.sleep(0.005)
+    assert r is not None and r["status"] == 0
+    met = ctx.evaluate(ev, sd, torch.as_tensor(r["q"], device=dev), thr)
+    top, mean = ctx.select_top(torch.as_tensor(r["loss"], device=dev), 10, metrics=met)
+    assert np.array_equal(r["metrics"], met.cpu().numpy())
+    assert np.array_equal(r["top"], top.cpu().numpy()) and np.array_equal(r["top_mean"], mean.cpu().numpy())
+    assert np.array_equal(r["top"], r["rank"][:10])
+    assert (r["metrics"][:, 2] > 0).any()
+    other = S.make_hand(3, 3, 128, seed=74)
+    ho = ctx.hand(other)
+    qo = S.make_candidates(other, 4, seed=75, shell_radius=0.1).astype(np.float32)
+    with pytest.raises(GraspError, match="another hand"):
+        ctx.submit(ho, sd, qo, T=2, eval_points=ev, thresholds=thr)
+    with pytest.raises(GraspError, match="evaluation set"):
+        ctx.submit(h, sd, q, T=2, top_k=3)
+    with pytest.raises(GraspError, match="top_k"):
+        ctx.submit(h, sd, q, T=2, eval_points=ev, thresholds=thr, top_k=65)
+    ev.unload()
+    ho.destroy()
