@@ -327,6 +327,42 @@ def evaluate(hand: Hand, obj: Obj, q, ev: EvalPoints, thresholds, delta: float =
     return out, slack
 
 
+def evaluate_mesh(hand, mesh: Mesh, q, ev, thresholds):
+    """Contact area at each threshold and intersection volume [B][T + 1]
+    against a mesh object's Phong signed distance (Sec. III-B, Sec. V-A),
+    from the same weighted samples: placed by the oracle's forward kinematics
+    (each sample set as the contact set of the hand) and queried through
+    mesh_sdf. Also the per-sample query outputs [B][N] of both sets ("surface",
+    "volume": rho, gap, spread, dist_flat) for tolerances. A configuration
+    with a non-finite coordinate gets NaN."""
+    import types
+    q = _d(q).reshape(-1, 6 + len(hand.parent) - 1)
+    thr = _d(thresholds).reshape(-1)
+    B = q.shape[0]
+    out = np.zeros((B, thr.shape[0] + 1))
+    per = {}
+    for kind, link, local, w in (("surface", ev.surface_link, ev.surface_local, ev.surface_area),
+                                 ("volume", ev.volume_link, ev.volume_local, ev.volume_weight)):
+        w = _d(w)
+        n = w.shape[0]
+        if n == 0:
+            per[kind] = {k: np.zeros((B, 0)) for k in ("rho", "gap", "spread", "dist_flat")}
+            continue
+        view = types.SimpleNamespace(parent=hand.parent, joint_origin=hand.joint_origin, joint_axis=hand.joint_axis,
+                                     q_low=hand.q_low, q_up=hand.q_up, contact_local=local, contact_link=link)
+        p = fk(Hand(view), np.nan_to_num(q))
+        res = mesh_sdf(mesh, p.reshape(-1, 3))
+        per[kind] = {k: res[k].reshape(B, n) for k in ("rho", "gap", "spread", "dist_flat")}
+        rho = per[kind]["rho"]
+        if kind == "surface":
+            for t, tau in enumerate(thr):
+                out[:, t] = ((rho < tau) * w).sum(axis=1)
+        else:
+            out[:, -1] = ((rho < 0.0) * w).sum(axis=1)
+    out[~np.isfinite(q).all(axis=1)] = np.nan
+    return out, per
+
+
 def select_top(key, k: int, higher_is_better: bool = False, metrics=None):
     """Indices of the k best keys (NaN last, ties by index) and the mean of
     metrics [B][M] over them."""

@@ -160,3 +160,28 @@ def test_select_top_matches_brute_force(higher):
         top, mean = O.select_top(key, k, higher, met)
         assert top.tolist() == brute_top(key.tolist(), k, higher)
         assert np.allclose(mean, met[top].mean(axis=0), rtol=1e-14)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.75])
+def test_mesh_evaluation_box_top_face_closed_form(hand_and_points, alpha):
+    """The same closed forms against a box mesh whose top face is the plane
+    z = 0: near the face's centre the box's signed distance is z, and the
+    Phong blend leaves its planar faces unchanged."""
+    from paper_2306_08132_amd import synth as S2
+    hand, ev = hand_and_points
+    ev = S2.make_eval_points(hand, 12000, 12000, seed=4)
+    box = S2.mesh_box([0.25, 0.25, 0.1], splits=4, center=(0.0, 0.0, -0.1))
+    M = O.Mesh(box.vertices, box.faces, box.normals, alpha)
+    normal = np.array([0.0, 0.0, 1.0])
+    q, depths = pointing_pose(hand, normal, 0.7, 0.009)
+    out, per = O.evaluate_mesh(hand, M, q, ev, THR)
+    r = 0.8 * S.CM
+    sb, vb = stratification_bound(hand, ev, range(1, hand.n_links))
+    for t, tau in enumerate(THR):
+        exact = sum(area_below(d + tau, r) for d in depths)
+        assert abs(out[0, t] - exact) <= sb + 1e-12, (tau, out[0, t], exact, sb)
+    exact_iv = sum(volume_below(d, r) for d in depths)
+    assert abs(out[0, 3] - exact_iv) <= vb + 1e-12
+    # the grid of the same plane gives the same metrics on the same samples
+    g, _ = O.evaluate(O.Hand(hand), O.Obj(plane_grid(normal, 0.0)), q, O.EvalPoints(ev), THR)
+    np.testing.assert_allclose(out, g, rtol=0, atol=3e-7 * np.abs(g).max())
