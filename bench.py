@@ -406,14 +406,26 @@ def eval_run(ctx, S, hand, grid, q0, h, sd, key, args):
     torch.cuda.synchronize()
     top_ms = float(np.mean([a.elapsed_time(b) for a, b in sel]))
     n = len(evp.surface_link) + len(evp.volume_link)
+    # the same samples against a mesh object (5120-face ellipsoid, Phong alpha 0.75) instead of the grid
+    gm = ctx.mesh(S.mesh_ellipsoid([0.05, 0.035, 0.04], subdivisions=4), 0.75)
+    mout = ctx.evaluate_mesh(gev, gm, q, EVAL_THRESHOLDS)
+    me = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in me:
+        a.record(stream)
+        ctx.evaluate_mesh(gev, gm, q, EVAL_THRESHOLDS, out=mout, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    mesh_ms = float(np.mean([a.elapsed_time(b) for a, b in me]))
+    gm.unload()
     res = {"candidates": q.shape[0], "surface_samples": len(evp.surface_link), "volume_samples": len(evp.volume_link),
+           "mesh_5120_faces_ms_per_launch": mesh_ms,
            "thresholds_m": list(EVAL_THRESHOLDS), "kernel": "k_evaluate", "avg_launch_ms": ms,
            "candidate_samples_per_s": q.shape[0] * n / (ms * 1e-3), "top10_ms": top_ms,
            "top10_mean_ca_cm2": [float(x) * 1e4 for x in mean[:3].cpu()], "top10_mean_iv_cm3": float(mean[3]) * 1e6,
            "all_mean_ca5_cm2": float(out[:, 1].mean()) * 1e4, "all_mean_iv_cm3": float(out[:, 3].mean()) * 1e6}
     gev.unload()
     print(f"bench: evaluation {ms:.3f} ms/launch ({res['candidate_samples_per_s']:.3e} candidate-samples/s), "
-          f"top-10 {top_ms:.3f} ms", file=sys.stderr, flush=True)
+          f"top-10 {top_ms:.3f} ms, against a 5120-face mesh {mesh_ms:.2f} ms", file=sys.stderr, flush=True)
     return res
 
 

@@ -231,6 +231,12 @@ grasp_status grasp_unload_eval_points(grasp_ctx* ctx, grasp_eval_id ev);
 grasp_status grasp_evaluate(grasp_ctx* ctx, grasp_eval_id ev, grasp_sdf_id sdf, int32_t B, const float* q,
                             int32_t n_thr, const float* thresholds, float* out, void* hip_stream);
 
+/* The same metrics against a mesh object's Phong signed distance (Sec. III-B;
+ * the mesh as loaded by grasp_load_mesh, at rest) instead of a grid: each
+ * sample through the hierarchy query. Errors and layouts as grasp_evaluate. */
+grasp_status grasp_evaluate_mesh(grasp_ctx* ctx, grasp_eval_id ev, grasp_mesh_id mesh, int32_t B, const float* q,
+                                 int32_t n_thr, const float* thresholds, float* out, void* hip_stream);
+
 /* The k best of B candidates by key (dev [B]): ascending, or descending when
  * higher_is_better; NaN keys after every other; equal keys (-0 equal to +0) in
  * index order. top (dev [k]) gets their indices, best first; mean (dev [M], or

@@ -141,6 +141,7 @@ SIGNATURES = [
     ("grasp_load_eval_points", _I32, [_VP, _U64, C.POINTER(EvalDescC), C.POINTER(_U64)]),
     ("grasp_unload_eval_points", _I32, [_VP, _U64]),
     ("grasp_evaluate", _I32, [_VP, _U64, _U64, _I32, _VP, _I32, _FP, _VP, _VP]),
+    ("grasp_evaluate_mesh", _I32, [_VP, _U64, _U64, _I32, _VP, _I32, _FP, _VP, _VP]),
     ("grasp_select_top", _I32, [_VP, _I32, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
     ("grasp_sdf_inertia", _I32, [_VP, _U64, _FP]),
     ("grasp_default_params", None, [C.POINTER(StepParamsC)]),

@@ -84,6 +84,15 @@ class Context:
                       thr.ctypes.data_as(C.POINTER(C.c_float)), _ptr(out), _stream(stream))
         return out
 
+    def evaluate_mesh(self, ev: "EvalPoints", mesh: "Mesh", q, thresholds, out=None, stream=None):
+        """As evaluate, against a mesh object's Phong signed distance."""
+        thr = np.ascontiguousarray(thresholds, np.float32).reshape(-1)
+        if out is None:
+            out = torch.empty((q.shape[0], thr.shape[0] + 1), dtype=torch.float32, device=q.device)
+        self.lib.call("grasp_evaluate_mesh", self.h, ev.id, mesh.id, q.shape[0], _ptr(q), thr.shape[0],
+                      thr.ctypes.data_as(C.POINTER(C.c_float)), _ptr(out), _stream(stream))
+        return out
+
     def select_top(self, key, k: int, higher_is_better: bool = False, metrics=None, stream=None):
         """(indices [k] best first, mean of metrics [B][M] over them or None)."""
         top = torch.empty(k, dtype=torch.int32, device=key.device)

@@ -103,40 +103,80 @@ grasp_status grasp_unload_eval_points(grasp_ctx* ctx, grasp_eval_id id) {
   return GRASP_OK;
 }
 
-grasp_status grasp_evaluate(grasp_ctx* ctx, grasp_eval_id id, grasp_sdf_id sdf, int32_t B, const float* q,
-                            int32_t n_thr, const float* thresholds, float* out, void* hip_stream) {
-  set_error("");
+}  // extern "C"
+
+namespace {
+
+// Checks the call and the thresholds; resolves the set and its hand.
+grasp_status eval_args(grasp_ctx* ctx, grasp_eval_id id, int32_t B, const float* q, int32_t n_thr,
+                       const float* thresholds, float* out, EvalConsts* c, HandView* hv, EvalView* ev) {
   if (const grasp_status st = check_ctx(ctx); st != GRASP_OK) return st;
   if (B < 0 || B > (1 << 26)) return fail(GRASP_EINVAL, "B must be in [0, 2^26]");
   if (n_thr < 1 || n_thr > kMaxThresholds) return fail(GRASP_EINVAL, "n_thr must be in [1, 8]");
   if (!thresholds) return fail(GRASP_EINVAL, "thresholds is NULL");
   if (B > 0 && (!q || !out)) return fail(GRASP_EINVAL, "q/out is NULL");
-  EvalConsts c{};
-  c.n_thr = n_thr;
-  c.tmax = -INFINITY;
+  *c = EvalConsts{};
+  c->n_thr = n_thr;
+  c->tmax = -INFINITY;
   for (int t = 0; t < n_thr; ++t) {
     if (!std::isfinite(thresholds[t])) return fail(GRASP_EINVAL, "thresholds must be finite");
-    c.thr[t] = thresholds[t];
-    c.tmax = std::max(c.tmax, thresholds[t]);
+    c->thr[t] = thresholds[t];
+    c->tmax = std::max(c->tmax, thresholds[t]);
   }
+  auto it = ctx->evals.find(id);
+  if (it == ctx->evals.end()) return fail(GRASP_EINVAL, "unknown evaluation set id");
+  DevHand* h = find_hand(ctx, it->second->hand);
+  if (!h) return fail(GRASP_EINVAL, "the evaluation set's hand no longer exists");
+  *hv = h->view;
+  *ev = it->second->view;
+  return GRASP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+grasp_status grasp_evaluate(grasp_ctx* ctx, grasp_eval_id id, grasp_sdf_id sdf, int32_t B, const float* q,
+                            int32_t n_thr, const float* thresholds, float* out, void* hip_stream) {
+  set_error("");
+  EvalConsts c;
   HandView hv;
   SdfView sv;
   EvalView ev;
   {
+    if (const grasp_status st = check_ctx(ctx); st != GRASP_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    auto it = ctx->evals.find(id);
-    if (it == ctx->evals.end()) return fail(GRASP_EINVAL, "unknown evaluation set id");
-    DevHand* h = find_hand(ctx, it->second->hand);
-    if (!h) return fail(GRASP_EINVAL, "the evaluation set's hand no longer exists");
+    if (const grasp_status st = eval_args(ctx, id, B, q, n_thr, thresholds, out, &c, &hv, &ev); st != GRASP_OK)
+      return st;
     DevSdf* s = find_sdf(ctx, sdf);
     if (!s) return fail(GRASP_EINVAL, "unknown sdf id");
-    hv = h->view;
     sv = s->view;
-    ev = it->second->view;
   }
   DeviceGuard g(ctx->device);
   const hipError_t e = launch_evaluate(hv, sv, ev, c, B, q, out, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_evaluate launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_evaluate_mesh(grasp_ctx* ctx, grasp_eval_id id, grasp_mesh_id mesh, int32_t B, const float* q,
+                                 int32_t n_thr, const float* thresholds, float* out, void* hip_stream) {
+  set_error("");
+  EvalConsts c;
+  HandView hv;
+  MeshView mv;
+  EvalView ev;
+  {
+    if (const grasp_status st = check_ctx(ctx); st != GRASP_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (const grasp_status st = eval_args(ctx, id, B, q, n_thr, thresholds, out, &c, &hv, &ev); st != GRASP_OK)
+      return st;
+    auto it = ctx->meshes.find(mesh);
+    if (it == ctx->meshes.end()) return fail(GRASP_EINVAL, "unknown mesh id");
+    mv = it->second->view;
+  }
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_evaluate_mesh(hv, mv, ev, c, B, q, out, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_evaluate_mesh launch");
   return GRASP_OK;
 }
 

@@ -19,6 +19,7 @@
 // a candidate's metrics are the same bits whatever else runs.
 #include "device_common.h"
 #include "eval.h"
+#include "mesh_device.h"
 
 namespace grasp {
 namespace {
@@ -148,6 +149,66 @@ __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate(HandView H, Sdf
   }
 }
 
+// The same metrics against a mesh object's Phong signed distance: one
+// workgroup per candidate, its link frames in LDS, one sample per lane
+// through the hierarchy query (no table bound: the query is the cost).
+// Sums as above: lane-sequential, wave butterfly, waves in order.
+__global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate_mesh(HandView H, MeshView M, EvalView E,
+                                                                       EvalConsts C, int B,
+                                                                       const float* __restrict__ q,
+                                                                       float* __restrict__ out) {
+  __shared__ float T[kMaxLinks * 12];
+  __shared__ float part[kEvalWaves][kAcc];
+  __shared__ int bad_s;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int lane = lane_id();
+  const int wave = tid / kWave;
+  const int b = static_cast<int>(blockIdx.x);  // < B: one workgroup per candidate
+  const int nd = H.n_dof;
+  const float* qb = q + static_cast<size_t>(b) * nd;
+  if (wave == 0) {
+    const float qj = lane < nd ? qb[lane] : 0.0f;
+    const bool bad = __builtin_amdgcn_ballot_w64(!isfinite(qj)) != 0;
+    if (lane == 0) bad_s = bad;
+  }
+  if (tid < H.L) {
+    float Jw[6];
+    link_transform(H, qb, tid, T + 12 * tid, Jw);
+  }
+  __syncthreads();
+  float acc[kAcc];
+#pragma unroll
+  for (int t = 0; t < kAcc; ++t) acc[t] = 0.0f;
+  const int n = E.ns + E.nv;
+  for (int i = tid; i < n; i += kEvalWaves * kWave) {
+    const float4 P = E.pts[i];
+    const float4* T4 = reinterpret_cast<const float4*>(T + 12 * E.link[i]);
+    float rho;
+    V3 g;
+    meshdev::mesh_sdf(M, xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z), rho, g);
+    if (i < E.ns) {
+#pragma unroll
+      for (int t = 0; t < kMaxThresholds; ++t)
+        if (t < C.n_thr && rho < C.thr[t]) acc[t] += P.w;
+    } else if (rho < 0.0f) {
+      acc[kMaxThresholds] += P.w;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kAcc; ++t)
+    if (t < C.n_thr || t == kMaxThresholds) {
+      const float s = wave_sum(acc[t]);
+      if (lane == 0) part[wave][t] = s;
+    }
+  __syncthreads();
+  if (tid < kAcc && (tid < C.n_thr || tid == kMaxThresholds)) {
+    float s = part[0][tid];
+    for (int w = 1; w < kEvalWaves; ++w) s += part[w][tid];
+    out[static_cast<size_t>(b) * (C.n_thr + 1) + (tid == kMaxThresholds ? C.n_thr : tid)] =
+        bad_s ? __builtin_nanf("") : s;
+  }
+}
+
 // Key of candidate i as one 64-bit word whose unsigned order is the ranking:
 // the key mapped to an order-preserving 32-bit code (negated when higher is
 // better, -0 taken as +0, NaN after everything), then the index.
@@ -216,6 +277,13 @@ hipError_t launch_evaluate(const HandView& H, const SdfView& S, const EvalView& 
     hipLaunchKernelGGL(k_evaluate<kLayoutZPairs>, grid, block, 0, stream, H, S, E, c, B, q, out);
   else
     hipLaunchKernelGGL(k_evaluate<kLayoutYZQuads>, grid, block, 0, stream, H, S, E, c, B, q, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_evaluate_mesh(const HandView& H, const MeshView& M, const EvalView& E, const EvalConsts& c,
+                                int B, const float* q, float* out, hipStream_t stream) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_evaluate_mesh, dim3(B), dim3(kEvalWaves * kWave), 0, stream, H, M, E, c, B, q, out);
   return hipGetLastError();
 }
 

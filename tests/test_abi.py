@@ -45,6 +45,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert L.grasp_step_fwd(None, 0, 0, None, 0, None, None, None, None, 0, None) == lib.GRASP_EINVAL
     assert L.grasp_init(0, None, 1 << 20, None) == lib.GRASP_EINVAL
     assert L.grasp_evaluate(None, 0, 0, 0, None, 1, None, None, None) == lib.GRASP_EINVAL
+    assert L.grasp_evaluate_mesh(None, 0, 0, 0, None, 1, None, None, None) == lib.GRASP_EINVAL
     assert L.grasp_select_top(None, 1, None, 0, 1, 0, None, None, None, None) == lib.GRASP_EINVAL
     assert L.grasp_load_eval_points(None, 0, None, None) == lib.GRASP_EINVAL
     p = lib.StepParamsC()

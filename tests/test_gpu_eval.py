@@ -244,3 +244,44 @@ def test_refusals(ctx):
         ctx.evaluate(gev, sd, dev(q), THR)
     gev.unload()
     sd.unload()
+
+
+def test_mesh_metrics_match_oracle(ctx):
+    """The metrics against a mesh object's Phong distance (ellipsoid mesh,
+    alpha 0.75) against the oracle's mesh evaluation. A sample may fall on
+    either side of a threshold where its distance is within the mesh query's
+    own tolerance of it: 1e-5 of max(|rho|, edge), plus the medial gap and the
+    spread of FP32-tied faces, plus 2 |rho| within 1e-6 m of the flat surface
+    (the sign jump), plus 1e-7 m of FP32 forward kinematics."""
+    hand = S.make_hand(3, 3, 256, seed=21)
+    m0 = S.mesh_ellipsoid([0.035, 0.025, 0.03], subdivisions=3)
+    m = S.TriMesh(m0.vertices.astype(np.float32).astype(np.float64), m0.faces,
+                  m0.normals.astype(np.float32).astype(np.float64))
+    alpha = float(np.float32(0.75))
+    q = S.make_candidates(hand, 37, seed=22, shell_radius=m.bound_radius() + 0.05).astype(np.float32)
+    q[5, 8] = np.nan
+    ev = S.make_eval_points(hand, 1500, 1200, seed=23)
+    h, gm = ctx.hand(hand), ctx.mesh(m, alpha)
+    gev = ctx.eval_points(h, ev)
+    got = ctx.evaluate_mesh(gev, gm, dev(q), THR).cpu().numpy().astype(np.float64)
+    e32 = ev.as_f32()
+    ref, per = O.evaluate_mesh(hand.rounded(), O.Mesh(m.vertices, m.faces, m.normals, alpha),
+                               q.astype(np.float64), e32, THR.astype(np.float64))
+    v = m.vertices[m.faces]
+    edge = float(np.linalg.norm(v[:, 1] - v[:, 0], axis=1).mean())
+
+    def ambiguous(d, target):
+        tol = (1e-5 * np.maximum(np.abs(d["rho"]), edge) + d["gap"] + d["spread"] + 1e-7
+               + np.where(d["dist_flat"] < 1e-6, 2.0 * np.abs(d["rho"]), 0.0))
+        return np.abs(d["rho"] - target) <= tol
+
+    slack = np.zeros_like(ref)
+    for t, tau in enumerate(THR.astype(np.float64)):
+        slack[:, t] = (ambiguous(per["surface"], tau) * e32.surface_area).sum(axis=1)
+    slack[:, -1] = (ambiguous(per["volume"], 0.0) * e32.volume_weight).sum(axis=1)
+    check(got, ref, slack, ev, "mesh metrics")
+    fin = np.isfinite(ref[:, 0])
+    assert (ref[fin, 2] > 0).mean() > 0.3 and (ref[fin, 3] > 0).any()
+    gev.unload()
+    gm.unload()
+    h.destroy()
