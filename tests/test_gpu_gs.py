@@ -192,3 +192,31 @@ def test_gs_many_contacts(ctx):
     grid = S.make_grid(S.make_object("sphere", seed=1), 48)
     q = S.make_candidates(hand, 3, seed=5, shell_radius=grid.bound_radius + 0.06)
     compare_gs(ctx, hand, grid, q, "GS 8193 contacts", max_flagged=0.34, r_dil=0.004)
+
+
+def test_gs_two_streams_share_the_start_pose_table(ctx):
+    """Backward launches of different sizes on two streams share the
+    context's start-pose table (each use waits on the device for the
+    previous one): the results equal the same launches one after another."""
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny", B=64)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp = StepParams(projection=GS, r_dil=0.004)
+    qa, qb = dev(q[:24]), dev(q)
+    ref = []
+    for qq in (qa, qb):
+        dq = torch.empty_like(qq)
+        ctx.step_bwd(h, sd, sp, qq, dq)
+        torch.cuda.synchronize()
+        ref.append(dq.clone())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [torch.empty_like(qa), torch.empty_like(qb)]
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ctx.step_bwd(h, sd, sp, qa, outs[0], stream=s1)
+        with torch.cuda.stream(s2):
+            ctx.step_bwd(h, sd, sp, qb, outs[1], stream=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], ref[0]) and torch.equal(outs[1], ref[1])
+    sd.unload()
+    h.destroy()
