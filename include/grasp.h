@@ -222,6 +222,7 @@ typedef struct {
  * weight; ENOMEM when the arena is full. */
 grasp_status grasp_load_eval_points(grasp_ctx* ctx, grasp_hand_id hand, const grasp_eval_desc* desc,
                                     grasp_eval_id* out);
+/* EBUSY while a served job that names the set has not ended. */
 grasp_status grasp_unload_eval_points(grasp_ctx* ctx, grasp_eval_id ev);
 
 /* Metrics of B candidates q (dev [B][n_dof]) against the grid: out (dev
@@ -418,9 +419,9 @@ grasp_status grasp_batch_flags(grasp_batch* batch, int32_t n, int32_t* out);
  * job may also name an evaluation set of its hand: it then retires with the
  * post-synthesis metrics of every candidate at its final configuration and,
  * with top_k > 0, the top_k best by final loss and their mean metrics (the
- * paper's top-10 figures); the set must stay loaded until the job ends (else
- * the job ends with EINVAL), and its footprint grows by 4 (n_thr + 1) bytes
- * per candidate.
+ * paper's top-10 figures); the set cannot be unloaded while such a job lives
+ * (EBUSY, as for its hand and grid), and the job's footprint grows by
+ * 4 (n_thr + 1) bytes per candidate.
  * ------------------------------------------------------------------------- */
 typedef struct {
   grasp_hand_id hand;

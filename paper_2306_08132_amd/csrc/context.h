@@ -53,6 +53,7 @@ struct DevEval {
   void* block = nullptr;
   size_t bytes = 0;
   grasp_hand_id hand = 0;  // the hand whose links the samples hang from
+  int live_jobs = 0;       // served jobs that will evaluate with it
 };
 
 struct Scheduler;  // serving loop (sched.cpp)

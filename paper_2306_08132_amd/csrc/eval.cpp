@@ -96,6 +96,7 @@ grasp_status grasp_unload_eval_points(grasp_ctx* ctx, grasp_eval_id id) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->evals.find(id);
   if (it == ctx->evals.end()) return fail(GRASP_EINVAL, "unknown evaluation set id");
+  if (it->second->live_jobs > 0) return fail(GRASP_EBUSY, "evaluation set in use by a live job");
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
   ctx->arena.free(it->second->block);

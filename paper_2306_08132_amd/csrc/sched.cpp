@@ -108,6 +108,10 @@ void Scheduler::release(Job& j) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (DevHand* h = find_hand(ctx, j.desc.hand)) h->live_jobs--;
   if (DevSdf* s = find_sdf(ctx, j.desc.sdf)) s->live_jobs--;
+  if (j.desc.eval) {
+    auto it = ctx->evals.find(j.desc.eval);
+    if (it != ctx->evals.end()) it->second->live_jobs--;
+  }
 }
 
 bool Scheduler::admit_one(Job& j) {
@@ -452,8 +456,15 @@ grasp_status grasp_submit(grasp_ctx* ctx, const grasp_job_desc* d, grasp_job_id*
     if (st != GRASP_OK) return st;
     {
       std::lock_guard<std::mutex> lk2(ctx->mu);
+      DevEval* ev = nullptr;
+      if (d->eval) {
+        auto it = ctx->evals.find(d->eval);
+        if (it == ctx->evals.end()) return fail(GRASP_EINVAL, "unknown evaluation set id");
+        ev = it->second.get();
+      }
       find_hand(ctx, d->hand)->live_jobs++;
       find_sdf(ctx, d->sdf)->live_jobs++;
+      if (ev) ev->live_jobs++;
     }
     j->id = s->next_id++;
     j->t_submit = s->now();

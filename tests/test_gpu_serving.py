@@ -129,6 +129,8 @@ def test_job_with_evaluation(setup):
     thr = [0.002, 0.005, 0.009]
     say("serving: job with evaluation")
     jid = ctx.submit(h, sd, q, T=6, eval_points=ev, thresholds=thr, top_k=10)
+    with pytest.raises(GraspError, match="live job"):
+        ev.unload()  # the job still needs it
     t0 = time.time()
     r = None
     while r is None and time.time() - t0 < 120.0:
