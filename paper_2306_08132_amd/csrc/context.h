@@ -46,6 +46,7 @@ struct DevMesh {
   void* block = nullptr;
   size_t bytes = 0;
   double volume = 0.0;  // enclosed volume (divergence theorem)
+  double max_edge = 0.0;  // longest edge: the Phong point is within alpha times it of the flat one
 };
 
 struct DevEval {

@@ -166,6 +166,7 @@ grasp_status grasp_evaluate_mesh(grasp_ctx* ctx, grasp_eval_id id, grasp_mesh_id
   HandView hv;
   MeshView mv;
   EvalView ev;
+  float bulge;
   {
     if (const grasp_status st = check_ctx(ctx); st != GRASP_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -174,9 +175,10 @@ grasp_status grasp_evaluate_mesh(grasp_ctx* ctx, grasp_eval_id id, grasp_mesh_id
     auto it = ctx->meshes.find(mesh);
     if (it == ctx->meshes.end()) return fail(GRASP_EINVAL, "unknown mesh id");
     mv = it->second->view;
+    bulge = static_cast<float>(mv.alpha * it->second->max_edge * (1.0 + 1e-6));
   }
   DeviceGuard g(ctx->device);
-  const hipError_t e = launch_evaluate_mesh(hv, mv, ev, c, B, q, out, static_cast<hipStream_t>(hip_stream));
+  const hipError_t e = launch_evaluate_mesh(hv, mv, ev, c, bulge, B, q, out, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_evaluate_mesh launch");
   return GRASP_OK;
 }

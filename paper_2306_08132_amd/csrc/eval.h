@@ -41,9 +41,10 @@ struct EvalConsts {
 hipError_t launch_evaluate(const HandView& H, const SdfView& S, const EvalView& E, const EvalConsts& c, int B,
                            const float* q, float* out, hipStream_t stream);
 
-// The same metrics against a mesh object's Phong signed distance.
+// The same metrics against a mesh object's Phong signed distance; bulge: how
+// far the Phong surface can lie from the flat one (alpha times the longest edge).
 hipError_t launch_evaluate_mesh(const HandView& H, const MeshView& M, const EvalView& E, const EvalConsts& c,
-                                int B, const float* q, float* out, hipStream_t stream);
+                                float bulge, int B, const float* q, float* out, hipStream_t stream);
 
 // top [k] (k <= kMaxTop) and mean [M] of metrics [B][M] over them.
 hipError_t launch_select_top(int B, const float* key, int higher_is_better, int k, int M, const float* metrics,

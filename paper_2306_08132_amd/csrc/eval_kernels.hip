@@ -151,10 +151,14 @@ __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate(HandView H, Sdf
 
 // The same metrics against a mesh object's Phong signed distance: one
 // workgroup per candidate, its link frames in LDS, one sample per lane
-// through the hierarchy query (no table bound: the query is the cost).
+// through the hierarchy query. A sample outside the mesh's bounding box is
+// at least its distance to the box from the flat surface, and the Phong
+// point lies within `bulge` (alpha times the longest edge) of the flat one,
+// so a sample whose box distance exceeds the cut by more than the bulge
+// (with margins far above FP32 rounding) adds nothing and skips the query.
 // Sums as above: lane-sequential, wave butterfly, waves in order.
 __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate_mesh(HandView H, MeshView M, EvalView E,
-                                                                       EvalConsts C, int B,
+                                                                       EvalConsts C, float bulge, int B,
                                                                        const float* __restrict__ q,
                                                                        float* __restrict__ out) {
   __shared__ float T[kMaxLinks * 12];
@@ -183,9 +187,13 @@ __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate_mesh(HandView H
   for (int i = tid; i < n; i += kEvalWaves * kWave) {
     const float4 P = E.pts[i];
     const float4* T4 = reinterpret_cast<const float4*>(T + 12 * E.link[i]);
+    const V3 r = xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z);
+    const float cut = i < E.ns ? C.tmax : 0.0f;
+    const float db = sqrtf(meshdev::box_d2(M.nodes[0], M.nodes[1], r));
+    if (fmaf(0.999999f, db, -bulge) - cut > 1e-6f) continue;
     float rho;
     V3 g;
-    meshdev::mesh_sdf(M, xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z), rho, g);
+    meshdev::mesh_sdf(M, r, rho, g);
     if (i < E.ns) {
 #pragma unroll
       for (int t = 0; t < kMaxThresholds; ++t)
@@ -281,9 +289,9 @@ hipError_t launch_evaluate(const HandView& H, const SdfView& S, const EvalView& 
 }
 
 hipError_t launch_evaluate_mesh(const HandView& H, const MeshView& M, const EvalView& E, const EvalConsts& c,
-                                int B, const float* q, float* out, hipStream_t stream) {
+                                float bulge, int B, const float* q, float* out, hipStream_t stream) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_evaluate_mesh, dim3(B), dim3(kEvalWaves * kWave), 0, stream, H, M, E, c, B, q, out);
+  hipLaunchKernelGGL(k_evaluate_mesh, dim3(B), dim3(kEvalWaves * kWave), 0, stream, H, M, E, c, bulge, B, q, out);
   return hipGetLastError();
 }
 

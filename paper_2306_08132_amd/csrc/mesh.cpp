@@ -126,7 +126,7 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
   // faces, their unit normals and the angle of each corner
   std::vector<D3> fn(F);
   std::vector<std::array<double, 3>> corner(F);
-  double volume = 0.0;
+  double volume = 0.0, max_edge = 0.0;
   for (int f = 0; f < F; ++f) {
     const int* t = d->faces + 3 * f;
     for (int j = 0; j < 3; ++j)
@@ -136,6 +136,7 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
     if (!(norm(n) > 0.0)) return fail(GRASP_EINVAL, "face of zero area");
     fn[f] = unit(n);
     volume += dot(P[t[0]], cross(P[t[1]], P[t[2]])) / 6.0;
+    for (int j = 0; j < 3; ++j) max_edge = std::max(max_edge, norm(sub(P[t[(j + 1) % 3]], P[t[j]])));
     for (int j = 0; j < 3; ++j) {
       const D3 e1 = unit(sub(P[t[(j + 1) % 3]], P[t[j]])), e2 = unit(sub(P[t[(j + 2) % 3]], P[t[j]]));
       corner[f][j] = std::acos(std::max(-1.0, std::min(1.0, dot(e1, e2))));
@@ -239,6 +240,7 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
   m->block = blk;
   m->bytes = bn + bt + bi;
   m->volume = volume;
+  m->max_edge = max_edge;
   const uint64_t id = ctx->next_id++;
   ctx->meshes[id] = std::move(m);
   *out = id;
