@@ -272,9 +272,11 @@ typedef struct {
  * active constraints of the test; every step form. GAUSS_SEIDEL: the paper's
  * serial form, each constraint at the pose the previous ones left, in
  * link-major order (contacts stable-sorted by link); grasp_step_fwd, _bwd and
- * _fused only; K iterations are K sweeps. No workspace: the backward replays
- * the sweeps from their start poses, 168 K bytes per candidate and 64-contact
- * chunk, which the context keeps in its arena (ENOMEM when they do not fit). */
+ * _fused, and served jobs (each stepped by a fused launch of its own; the
+ * batched launch refuses it); K iterations are K sweeps. No workspace: the
+ * backward replays the sweeps from their start poses, 168 K bytes per
+ * candidate and 64-contact chunk, which the context keeps in its arena
+ * (ENOMEM when they do not fit; a served job then ends with that status). */
 #define GRASP_PROJECTION_AVERAGED 0
 #define GRASP_PROJECTION_GAUSS_SEIDEL 1
 

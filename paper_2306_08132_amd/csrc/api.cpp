@@ -551,10 +551,6 @@ grasp_status check_adam(int32_t t, float lr, float b1, float b2, float eps) {
   return GRASP_OK;
 }
 
-// One single-job step launch with the candidate locality order (B >= kOrderMinB,
-// not under stream capture): the order kernel and the step run on stream s
-// after the previous user of the context's order buffer, on any stream, has
-// finished with it. Without memory for the buffer the step runs unordered.
 // The Gauss-Seidel step. A launch with a backward records where every chunk's
 // sweep starts, in an arena buffer of the context shared by every stream:
 // each use waits (on the device) for the previous one.
@@ -618,6 +614,10 @@ hipError_t grasp::launch_with_order(grasp_ctx* ctx, const float* q, int n_dof, i
 
 namespace {
 
+// One single-job step launch with the candidate locality order (B >= kOrderMinB,
+// not under stream capture): the order kernel and the step run on stream s
+// after the previous user of the context's order buffer, on any stream, has
+// finished with it. Without memory for the buffer the step runs unordered.
 hipError_t launch_ordered_step(grasp_ctx* ctx, StepArgs a, StepKind kind, bool adam, TileCfg tc, hipStream_t s) {
   return launch_with_order(ctx, a.q, a.hand.n_dof, a.B, a.sdf, s, [&](const int* order) {
     a.order = order;
@@ -789,13 +789,14 @@ grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
 
 namespace grasp {
 // Checks one batch job and resolves its hand and grid (used by batch.cpp).
-grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c) {
+grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c,
+                         bool gs_ok) {
   if (j.B < 1 || !j.q || !j.m || !j.v) return fail(GRASP_EINVAL, "batch job needs B >= 1 and q, m, v");
   if (j.t < 0 || j.T < 1 || !(j.r0 >= 0.0f) || !std::isfinite(j.r0)) return fail(GRASP_EINVAL, "bad job schedule");
   grasp_status st = check_adam(j.t + 1, j.lr, j.b1, j.b2, j.eps);
   if (st != GRASP_OK) return st;
   Resolved r;
-  st = resolve(ctx, j.hand, j.sdf, &j.p, j.B, &r);
+  st = resolve(ctx, j.hand, j.sdf, &j.p, j.B, &r, gs_ok);
   if (st != GRASP_OK) return st;
   *h = r.hand;
   *s = r.sdf;

@@ -134,7 +134,10 @@ hipError_t launch_with_order(grasp_ctx* ctx, const float* q, int n_dof, int B, c
                              const std::function<hipError_t(const int*)>& launch);
 
 // Checks one batch job and resolves its hand, grid and constants.
-grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c);
+// gs_ok: the caller also runs Gauss-Seidel jobs (the serving loop does, with
+// a launch of their own; the batched launch does not).
+grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, SdfView* s, StepConsts* c,
+                         bool gs_ok = false);
 
 // Checks step parameters and fills the device constants.
 grasp_status check_params(const grasp_step_params* p, StepConsts* out);

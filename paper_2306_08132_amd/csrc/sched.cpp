@@ -204,8 +204,9 @@ void Scheduler::finish(Job& j) {
 void Scheduler::run() {
   (void)hipSetDevice(ctx->device);
   std::vector<grasp_batch_job> bj;
-  std::vector<Job*> bjob;
+  std::vector<Job*> bjob, gsjob;
   std::vector<int32_t> flags;
+  std::vector<grasp_status> gs_st;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
@@ -276,8 +277,13 @@ void Scheduler::run() {
       }
       bj.clear();
       bjob.clear();
+      gsjob.clear();
       for (uint64_t id : resident) {
         Job& j = *jobs[id];
+        if (j.desc.p.projection == GRASP_PROJECTION_GAUSS_SEIDEL) {
+          gsjob.push_back(&j);  // stepped by a launch of its own
+          continue;
+        }
         grasp_batch_job b{};
         b.hand = j.desc.hand;
         b.sdf = j.desc.sdf;
@@ -299,10 +305,25 @@ void Scheduler::run() {
         bjob.push_back(&j);
       }
     }
-    // 3. one batched step for every resident job (outside the lock)
-    grasp_status st = grasp_batch_step(batch, bj.data(), static_cast<int32_t>(bj.size()), stream);
+    // 3. one batched step for every resident job (outside the lock); a
+    // Gauss-Seidel job's sweep is its own fused launch on the same stream,
+    // with the same dilation schedule
+    grasp_status st = GRASP_OK;
     flags.assign(bj.size(), 0);
-    if (st == GRASP_OK) st = grasp_batch_flags(batch, static_cast<int32_t>(bj.size()), flags.data());
+    if (!bj.empty()) {
+      st = grasp_batch_step(batch, bj.data(), static_cast<int32_t>(bj.size()), stream);
+      if (st == GRASP_OK) st = grasp_batch_flags(batch, static_cast<int32_t>(bj.size()), flags.data());
+    }
+    gs_st.assign(gsjob.size(), GRASP_OK);
+    for (size_t k = 0; k < gsjob.size() && st == GRASP_OK; ++k) {
+      Job* j = gsjob[k];
+      grasp_step_params p = j->desc.p;
+      p.r_dil = dilation_at(j->desc.r0, j->t, j->desc.T);
+      // a refusal (say, no room left for the sweep's start poses) ends this job only
+      gs_st[k] = grasp_step_fused(ctx, j->desc.hand, j->desc.sdf, &p, j->desc.B, j->q, j->m, j->v, j->t + 1,
+                                  j->desc.lr, j->desc.b1, j->desc.b2, j->desc.eps, j->loss, nullptr, nullptr, stream);
+      if (gs_st[k] == GRASP_EDEVICE) st = GRASP_EDEVICE;
+    }
     {
       std::lock_guard<std::mutex> lk(mu);
       if (st != GRASP_OK) {
@@ -315,6 +336,15 @@ void Scheduler::run() {
         j.t = bj[k].t;
         evals += static_cast<int64_t>(j.desc.B) * j.n_contacts * 7 * j.desc.p.K;
         if (flags[k]) j.status = GRASP_ENONFINITE;
+      }
+      for (size_t k = 0; k < gsjob.size(); ++k) {
+        Job& j = *gsjob[k];
+        if (gs_st[k] != GRASP_OK) {
+          j.status = gs_st[k];
+          continue;
+        }
+        ++j.t;
+        evals += static_cast<int64_t>(j.desc.B) * j.n_contacts * 7 * j.desc.p.K;
       }
       // 4. retire finished jobs
       for (auto it = resident.begin(); it != resident.end();) {
@@ -423,7 +453,7 @@ grasp_status grasp_submit(grasp_ctx* ctx, const grasp_job_desc* d, grasp_job_id*
   HandView hv;
   SdfView sv;
   StepConsts sc;
-  grasp_status st = resolve_job(ctx, probe, &hv, &sv, &sc);
+  grasp_status st = resolve_job(ctx, probe, &hv, &sv, &sc, true);
   if (st != GRASP_OK) return st;
   if (d->eval) {
     {

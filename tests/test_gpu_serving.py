@@ -1,7 +1,8 @@
 """GPU: the serving loop. A job's results are the same alone and in a mix
 of overlapping jobs (bit-exact), cancelled and non-finite jobs end without
-disturbing the others, jobs that can never fit are refused, and a job with an
-evaluation set retires with its metrics and top 10."""
+disturbing the others, jobs that can never fit are refused, a job with an
+evaluation set retires with its metrics and top 10, and a Gauss-Seidel job
+equals its fused steps launched directly."""
 import time
 
 import numpy as np
@@ -154,3 +155,35 @@ def test_job_with_evaluation(setup):
         ctx.submit(h, sd, q, T=2, eval_points=ev, thresholds=thr, top_k=65)
     ev.unload()
     ho.destroy()
+
+
+def test_gauss_seidel_job(setup):
+    """A served job with the Gauss-Seidel projection, running beside an
+    averaged job, gives the same bits as its fused steps launched directly on
+    the same dilation schedule followed by the forward at zero dilation."""
+    from paper_2306_08132_amd.api import StepParams
+    from paper_2306_08132_amd._lib import PROJECTION_GAUSS_SEIDEL as GS
+    ctx, objs = setup
+    dev = "cuda:0"
+    h, sd, q = objs[1]
+    T, r0 = 6, 0.01
+    say("serving: Gauss-Seidel job beside an averaged job")
+    other = ctx.submit(objs[0][0], objs[0][1], objs[0][2], T=9)
+    jid = ctx.submit(h, sd, q, T=T, r0=r0, prm=StepParams(projection=GS))
+    r = wait(ctx, jid, q.shape[0], h.n_dof)
+    assert r["status"] == 0 and r["steps"] == T
+    assert wait(ctx, other, objs[0][2].shape[0], objs[0][0].n_dof)["status"] == 0
+    say("serving: the same Gauss-Seidel steps launched directly")
+    qd = torch.as_tensor(q, device=dev).clone()
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    loss = torch.empty(q.shape[0], device=dev)
+    terms = torch.empty(q.shape[0], 4, device=dev)
+    for t in range(T):
+        r_dil = float(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1))
+        ctx.step_fused(h, sd, StepParams(projection=GS, r_dil=r_dil), qd, m, v, t + 1, loss=loss)
+    ctx.step_fwd(h, sd, StepParams(projection=GS, r_dil=0.0), qd, loss, terms)
+    torch.cuda.synchronize()
+    assert np.array_equal(r["q"], qd.cpu().numpy())
+    assert np.array_equal(r["loss"], loss.cpu().numpy())
+    assert np.array_equal(r["terms"], terms.cpu().numpy())
+    assert not np.array_equal(r["q"], q)  # the job moved its candidates
