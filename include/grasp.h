@@ -276,7 +276,8 @@ typedef struct {
  * batched launch refuses it); K iterations are K sweeps. No workspace: the
  * backward replays the sweeps from their start poses, 168 K bytes per
  * candidate and 64-contact chunk, which the context keeps in its arena
- * (ENOMEM when they do not fit; a served job then ends with that status). */
+ * (ENOMEM when they do not fit); a served job keeps its own table in its
+ * arena block, counted in its footprint at admission. */
 #define GRASP_PROJECTION_AVERAGED 0
 #define GRASP_PROJECTION_GAUSS_SEIDEL 1
 

@@ -803,6 +803,29 @@ grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, 
   *c = r.prm;
   return GRASP_OK;
 }
+
+grasp_status step_fused_gs(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
+                           int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2, float eps,
+                           float* loss, float* starts, hipStream_t s) {
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
+  if (st != GRASP_OK) return st;
+  if (p->projection != GRASP_PROJECTION_GAUSS_SEIDEL) return fail(GRASP_EINVAL, "not a Gauss-Seidel step");
+  if (B > 0 && (!q || !m || !v || !starts)) return fail(GRASP_EINVAL, "q/m/v/starts is NULL");
+  st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.q_out = q;
+  a.m = m;
+  a.v = v;
+  a.loss = loss;
+  a.adam = adam_consts(t, lr, b1, b2, eps);
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_gs_step(a, STEP_FUSED, true, starts, s);
+  return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, "Gauss-Seidel job step");
+}
 }  // namespace grasp
 
 extern "C" {

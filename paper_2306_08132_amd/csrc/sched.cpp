@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "gs.h"
 
 using namespace grasp;
 
@@ -51,6 +52,8 @@ struct Job {
   float *q = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr, *terms = nullptr;
   float *metrics = nullptr, *mean = nullptr;  // evaluation at retirement (jobs with an evaluation set)
   int32_t* top = nullptr;
+  float* starts = nullptr;  // Gauss-Seidel jobs: the sweep start-pose table
+  size_t start_floats = 0;
   int t = 0;
   std::vector<float> out_q, out_loss, out_terms, out_metrics, out_mean;
   std::vector<int32_t> rank, out_top;
@@ -58,13 +61,13 @@ struct Job {
 };
 
 // q, m, v, loss, terms; with an evaluation set, the metrics [B][M], the top
-// indices and their mean metrics.
-size_t job_footprint(int B, int n_dof, int M, int top_k) {
+// indices and their mean metrics; last, a Gauss-Seidel job's start poses.
+size_t job_footprint(int B, int n_dof, int M, int top_k, size_t start_floats) {
   const size_t b = static_cast<size_t>(B);
   auto r = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t f = 3 * r(b * n_dof * 4) + r(b * 4) + r(b * 16);
   if (M > 0) f += r(b * M * 4) + r(static_cast<size_t>(top_k) * 4) + r(static_cast<size_t>(M) * 4);
-  return f;
+  return f + r(start_floats * 4);
 }
 
 int job_metrics(const grasp_job_desc& d) { return d.eval ? d.n_thr + 1 : 0; }
@@ -137,6 +140,9 @@ bool Scheduler::admit_one(Job& j) {
     j.top = reinterpret_cast<int32_t*>(e + r(b * M * 4));
     j.mean = reinterpret_cast<float*>(e + r(b * M * 4) + r(static_cast<size_t>(j.desc.top_k) * 4));
   }
+  if (j.start_floats)
+    j.starts = reinterpret_cast<float*>(
+        p + job_footprint(j.desc.B, j.n_dof, job_metrics(j.desc), j.desc.eval ? j.desc.top_k : 0, 0));
   hipError_t e = hipMemcpyAsync(j.q, j.q0.data(), b * j.n_dof * 4, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemsetAsync(j.m, 0, 2 * nq, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -307,7 +313,7 @@ void Scheduler::run() {
     }
     // 3. one batched step for every resident job (outside the lock); a
     // Gauss-Seidel job's sweep is its own fused launch on the same stream,
-    // with the same dilation schedule
+    // with the same dilation schedule and its own start-pose table
     grasp_status st = GRASP_OK;
     flags.assign(bj.size(), 0);
     if (!bj.empty()) {
@@ -319,9 +325,9 @@ void Scheduler::run() {
       Job* j = gsjob[k];
       grasp_step_params p = j->desc.p;
       p.r_dil = dilation_at(j->desc.r0, j->t, j->desc.T);
-      // a refusal (say, no room left for the sweep's start poses) ends this job only
-      gs_st[k] = grasp_step_fused(ctx, j->desc.hand, j->desc.sdf, &p, j->desc.B, j->q, j->m, j->v, j->t + 1,
-                                  j->desc.lr, j->desc.b1, j->desc.b2, j->desc.eps, j->loss, nullptr, nullptr, stream);
+      // a refusal ends this job only
+      gs_st[k] = step_fused_gs(ctx, j->desc.hand, j->desc.sdf, &p, j->desc.B, j->q, j->m, j->v, j->t + 1, j->desc.lr,
+                               j->desc.b1, j->desc.b2, j->desc.eps, j->loss, j->starts, stream);
       if (gs_st[k] == GRASP_EDEVICE) st = GRASP_EDEVICE;
     }
     {
@@ -475,7 +481,9 @@ grasp_status grasp_submit(grasp_ctx* ctx, const grasp_job_desc* d, grasp_job_id*
   j->desc = *d;
   j->n_dof = n_dof;
   j->n_contacts = nc;
-  j->footprint = job_footprint(d->B, n_dof, job_metrics(*d), d->eval ? d->top_k : 0);
+  // a Gauss-Seidel job keeps its own start-pose table, reserved at admission
+  j->start_floats = d->p.projection == GRASP_PROJECTION_GAUSS_SEIDEL ? gs_scratch_floats(d->B, hv.n_chunks, d->p.K) : 0;
+  j->footprint = job_footprint(d->B, n_dof, job_metrics(*d), d->eval ? d->top_k : 0, j->start_floats);
   j->q0.assign(d->q0, d->q0 + static_cast<size_t>(d->B) * n_dof);
   j->desc.q0 = nullptr;
   {

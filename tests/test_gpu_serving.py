@@ -187,3 +187,27 @@ def test_gauss_seidel_job(setup):
     assert np.array_equal(r["loss"], loss.cpu().numpy())
     assert np.array_equal(r["terms"], terms.cpu().numpy())
     assert not np.array_equal(r["q"], q)  # the job moved its candidates
+
+
+def test_gauss_seidel_job_reserves_its_start_poses(gpu):
+    """A Gauss-Seidel job's footprint holds its sweep start-pose table (168 K
+    bytes per candidate and 64-contact chunk): in a 16 MiB arena a job of 4096
+    candidates, 8 chunks and K = 4 (22 MB of start poses) can never fit and is
+    refused at submission, while the same job with the averaged projection
+    is admitted and runs."""
+    from paper_2306_08132_amd.api import Context, GraspError, StepParams
+    from paper_2306_08132_amd._lib import PROJECTION_GAUSS_SEIDEL as GS
+    ctx = Context(0, arena_bytes=16 << 20)
+    try:
+        ctx.serve_config(capacity=4096, max_jobs=4)
+        hand = S.make_hand(3, 3, 512, seed=80)
+        grid = S.make_grid(S.make_object("ellipsoids", seed=81, n_range=(2, 3)), 24)
+        q = S.make_candidates(hand, 4096, seed=82, shell_radius=grid.bound_radius + 0.06).astype(np.float32)
+        h, sd = ctx.hand(hand), ctx.sdf(grid)
+        say("serving: a Gauss-Seidel job larger than the arena is refused")
+        with pytest.raises(GraspError, match="never fit"):
+            ctx.submit(h, sd, q, T=2, prm=StepParams(projection=GS, K=4))
+        r = wait(ctx, ctx.submit(h, sd, q, T=2, prm=StepParams(K=4)), q.shape[0], h.n_dof)
+        assert r["status"] == 0 and r["steps"] == 2
+    finally:
+        ctx.close()
