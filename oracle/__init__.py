@@ -45,7 +45,7 @@ class _Obj(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("lo", C.c_double * 3), ("h", C.c_double),
                 ("values", C.POINTER(C.c_float)), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("half", C.c_double * 3), ("normal", C.c_double * 3), ("offset", C.c_double),
-                ("inertia_over_mass", C.c_double)]
+                ("inertia_over_mass", C.c_double), ("fd_normal", C.c_int)]
 
 
 class _Params(C.Structure):
@@ -187,7 +187,7 @@ class Obj:
     """Oracle view of an object: a grid (synth.Grid) or an analytic shape."""
 
     def __init__(self, grid=None, kind=OBJ_GRID, center=(0, 0, 0), radius=0.0, half=(0, 0, 0),
-                 normal=(0, 0, 1), offset=0.0, inertia_over_mass=0.0):
+                 normal=(0, 0, 1), offset=0.0, inertia_over_mass=0.0, fd_normal=False):
         self.values = None
         c = _Obj()
         c.kind = kind
@@ -206,6 +206,7 @@ class Obj:
         c.normal = (C.c_double * 3)(*n)
         c.offset = offset
         c.inertia_over_mass = inertia_over_mass
+        c.fd_normal = int(bool(fd_normal))  # grid: central-difference normal (seven queries)
         self.c = c
 
     def inertia_over_mass(self) -> float:

@@ -264,11 +264,32 @@ void sample_grid(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* inf
   }
 }
 
+// Grid normal by central differences (Sec. III-A: finite differencing costs
+// seven queries per sample against one): the value and cell at r, then the
+// value at r +- h along each axis. A face of the grid is crossed by r + h e_a
+// exactly when it is crossed by r, so the centre's face margin still flags
+// every kink.
+template <class S>
+void sample_grid_fd(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
+  S unused[3];
+  sample_grid(o, r, phi, unused, info);
+  for (int a = 0; a < 3; ++a) {
+    S rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]};
+    rp[a] = rp[a] + o.h;
+    rm[a] = rm[a] - o.h;
+    S vp, vm;
+    sample_grid(o, rp, vp, unused, nullptr);
+    sample_grid(o, rm, vm, unused, nullptr);
+    n[a] = (vp - vm) / (2.0 * o.h);
+  }
+}
+
 template <class S>
 void sample_object(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
   switch (o.kind) {
     case OBJ_GRID:
-      sample_grid(o, r, phi, n, info);
+      if (o.fd_normal) sample_grid_fd(o, r, phi, n, info);
+      else sample_grid(o, r, phi, n, info);
       return;
     case OBJ_SPHERE: {
       S a[3];
@@ -576,7 +597,7 @@ bool valid_hand(const ohand* h) {
 
 bool valid_obj(const oobject* o) {
   if (!o) return false;
-  if (o->kind == OBJ_GRID) return o->n >= 2 && o->h > 0.0 && o->values;
+  if (o->kind == OBJ_GRID) return o->n >= 2 && o->h > 0.0 && o->values && (o->fd_normal == 0 || o->fd_normal == 1);
   return o->kind >= OBJ_SPHERE && o->kind <= OBJ_BOX;
 }
 

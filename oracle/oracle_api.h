@@ -59,6 +59,11 @@ typedef struct {
   /* I/m of the isotropic object; <= 0 for a grid means 0.4 R_eq^2 with
      R_eq^3 = 3 V / (4 pi), V = h^3 * #{vertices with value < 0} */
   double inertia_over_mass;
+  /* grid only: 0 = the analytic gradient of the trilinear blend; 1 = the
+     normal by central differences of the sampled value at +-h along each
+     axis, seven queries per sample (the earlier method's normal that
+     Sec. III-A contrasts with, kept for comparison) */
+  int fd_normal;
 } oobject;
 
 typedef struct {

@@ -89,6 +89,12 @@ int main() {
   }
   int top3[3];
   if (oracle_select_top(B, loss, 1, 3, 0, nullptr, top3, nullptr)) return 11;
+  // the seven-query central-difference normal, in the step and the sampler
+  oobject ofd = o;
+  ofd.fd_normal = 1;
+  double lfd[B], gfd[B * nd], sphi[3], sgrad[9], shess[27], smarg[3];
+  if (oracle_step(&h, &ofd, &p, B, q, lfd, nullptr, gfd, nullptr, 2)) return 12;
+  if (oracle_sample(&ofd, 3, pts, sphi, sgrad, shess, smarg)) return 13;
   std::printf("oracle ok %g %g %g\n", loss[0], loss[1], loss[2]);
   (void)m; (void)v;
   return 0;

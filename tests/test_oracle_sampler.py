@@ -1,5 +1,7 @@
 """Pins of the oracle's grid SDF sampler (trilinear grid of Sec. III-A, with
-the analytic gradient and the out-of-box extension) against closed forms."""
+the analytic gradient and the out-of-box extension) against closed forms, and
+of its seven-query central-difference normal (the finite differencing that
+Sec. III-A contrasts with, an oracle option for comparison)."""
 import numpy as np
 import pytest
 
@@ -160,3 +162,71 @@ def test_inertia_from_vertex_count(oracle_lib):
     g2.values = vals
     Req = (3 * 37 * g2.h ** 3 / (4 * np.pi)) ** (1 / 3)
     assert O.Obj(g2).inertia_over_mass() == pytest.approx(0.4 * Req ** 2, rel=1e-14)
+
+
+def _quadratic_grid(n=33, lo=-0.5, h=1.0 / 32):
+    """Grid of |r|^2 - 1/16 on dyadic vertices, whose values FP32 holds exactly."""
+    from paper_2306_08132_amd.synth import Grid
+    g = Grid(n=n, lo=np.full(3, lo), h=h, values=np.empty(0, np.float32), prims=[], bound_radius=0.0)
+    P = g.vertex_positions()
+    vals = (P * P).sum(axis=1) - 1.0 / 16
+    assert np.array_equal(vals.astype(np.float32).astype(np.float64), vals)
+    g.values = vals.astype(np.float32)
+    return g
+
+
+def test_central_difference_normal_closed_forms(oracle_lib):
+    """The seven-query normal (Sec. III-A's finite differencing, an oracle
+    option for comparison) against closed forms. On an affine field it equals
+    the field's gradient, like the analytic one. On |r|^2 the trilinear blend
+    is piecewise linear along each axis with knots at the vertices, and its
+    central difference over +-h is exactly 2r at every point whose offsets
+    stay in the box, while the analytic gradient of the blend is constant
+    within a cell (the sum of the cell's two vertex coordinates); the value
+    is the same blend either way."""
+    O = oracle_lib
+    rng = np.random.default_rng(7)
+    coef = np.array([0.5, 0.25, -0.125])
+    ga = dyadic_plane_grid(coef=coef, off=0.0625)
+    ra = ga.lo + ga.h + rng.random((3000, 3)) * ga.h * (ga.n - 3)
+    _, gfd, _ = O.sample(O.Obj(ga, fd_normal=True), ra)
+    np.testing.assert_allclose(gfd, np.broadcast_to(coef, gfd.shape), atol=1e-13, rtol=0)
+    gq = _quadratic_grid()
+    rq = gq.lo + gq.h + rng.random((3000, 3)) * gq.h * (gq.n - 3)
+    phi_fd, n_fd, _ = O.sample(O.Obj(gq, fd_normal=True), rq)
+    phi_an, n_an, _ = O.sample(O.Obj(gq), rq)
+    np.testing.assert_allclose(n_fd, 2.0 * rq, atol=1e-12, rtol=0)
+    np.testing.assert_array_equal(phi_fd, phi_an)
+    cell = np.floor((rq - gq.lo) / gq.h)
+    np.testing.assert_allclose(n_an, 2.0 * (gq.lo + cell * gq.h) + gq.h, atol=1e-12, rtol=0)
+    assert np.abs(n_an - n_fd).max() > 0.5 * gq.h  # the two normals differ inside a cell
+
+
+def test_central_difference_normal_gradient_and_accuracy(oracle_lib):
+    """With the seven-query normal the dual gradient of the loss still equals
+    central differences of the loss outside kinks. On a sphere's grid the
+    seven-query normal is second-order accurate and the analytic gradient of
+    the trilinear blend first-order (constant along an axis within a cell),
+    so near the surface the former lies closer to the exact normal r/|r|."""
+    O = oracle_lib
+    hand, grid, q = S.config_workload("tiny", B=8)
+    H = O.Hand(hand)
+    ob = O.Obj(grid, fd_normal=True)
+    P = O.Params(alpha_leak=0.0)
+    g = O.step(H, ob, P, q)["grad"]
+    fd, ex = O.fd_grad(H, ob, P, q, h=1e-6)
+    assert ex.mean() < 0.6
+    tol = 1e-5 * np.abs(g).max(axis=1, keepdims=True)
+    bad = (np.abs(fd - g) > tol) & ~ex
+    assert not bad.any(), np.argwhere(bad)[:5]
+    sph = S.make_grid(S.make_object("sphere", seed=0), 64)
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=(4000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    radius = float(sph.prims[0][2])  # the grid holds |r| - radius about the origin
+    pts = d * (radius + rng.uniform(-0.5, 0.5, (4000, 1)) * sph.h * 4)
+    _, n_an, _ = O.sample(O.Obj(sph), pts)
+    _, n_fd, _ = O.sample(O.Obj(sph, fd_normal=True), pts)
+    e_an = np.linalg.norm(n_an - d, axis=1)
+    e_fd = np.linalg.norm(n_fd - d, axis=1)
+    assert np.median(e_fd) < 0.5 * np.median(e_an), (np.median(e_fd), np.median(e_an))
