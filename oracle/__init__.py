@@ -246,7 +246,7 @@ def step(hand: Hand, obj: Obj, prm: Params, q, grad: bool = True, margins: bool 
     loss = np.zeros(B)
     terms = np.zeros((B, 4))
     g = np.zeros((B, hand.n_dof)) if grad else None
-    mg = np.zeros((B, 2)) if margins else None
+    mg = np.zeros((B, 3)) if margins else None
     pc = prm._c()
     _check(lib().oracle_step(C.byref(hand.c), C.byref(obj.c), C.byref(pc), B, _ptr(q), _ptr(loss),
                              _ptr(terms), _ptr(g), _ptr(mg), threads), "oracle_step")
@@ -256,6 +256,7 @@ def step(hand: Hand, obj: Obj, prm: Params, q, grad: bool = True, margins: bool 
     if margins:
         out["min_abs_d"] = mg[:, 0]
         out["min_face"] = mg[:, 1]
+        out["min_face_all"] = mg[:, 2]
     return out
 
 

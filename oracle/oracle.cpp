@@ -381,7 +381,8 @@ struct Trace {
   double* samples = nullptr;  // [M][K][Nc][6]
   double* p_world = nullptr;  // [Nc][3]
   double min_abs_d = 1e30;
-  double min_face = 1e30;
+  double min_face = 1e30;      // penetrating samples: their gradient sets a correction
+  double min_face_all = 1e30;  // every sample with w > w_min: the leak reaches its gradient
   uint64_t signature = 1469598103934665603ull;  // FNV-1a over discrete decisions
   void mix(uint64_t x) {
     for (int i = 0; i < 8; ++i) { signature ^= (x >> (8 * i)) & 0xff; signature *= 1099511628211ull; }
@@ -489,7 +490,8 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
               s[4] = val(w); s[5] = val(lam);
             }
             if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
-            tr->min_face = std::min(tr->min_face, info.face_margin);
+            if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
+            if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
             tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                     (static_cast<uint64_t>(info.cell[2]) << 32) |
                     (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
@@ -537,7 +539,8 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
             s[4] = val(w); s[5] = val(lam);
           }
           if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
-          tr->min_face = std::min(tr->min_face, info.face_margin);
+          if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
+          if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
           tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                   (static_cast<uint64_t>(info.cell[2]) << 32) |
                   (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
@@ -613,7 +616,7 @@ void step_dual(const ohand& h, const oobject& o, double Im, const oparams& P, co
   *loss = L.v;
   if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i].v;
   for (int j = 0; j < nd; ++j) grad[j] = L.d[j];
-  if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; }
+  if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; margins[2] = tr.min_face_all; }
 }
 
 void step_one(const ohand& h, const oobject& o, double Im, const oparams& P, const double* q,
@@ -625,7 +628,7 @@ void step_one(const ohand& h, const oobject& o, double Im, const oparams& P, con
     candidate_step(h, o, Im, P, q, L, t4, margins ? &tr : nullptr);
     *loss = L;
     if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i];
-    if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; }
+    if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; margins[2] = tr.min_face_all; }
     return;
   }
   if (nd <= 8) step_dual<8>(h, o, Im, P, q, loss, terms, grad, margins);
@@ -707,7 +710,7 @@ int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
   for (int b = 0; b < B; ++b)
     step_one(*hand, *obj, Im, *prm, q + static_cast<size_t>(b) * nd, loss + b, terms ? terms + 4 * b : nullptr,
-             grad ? grad + static_cast<size_t>(b) * nd : nullptr, margins ? margins + 2 * b : nullptr);
+             grad ? grad + static_cast<size_t>(b) * nd : nullptr, margins ? margins + 3 * b : nullptr);
   return 0;
 }
 

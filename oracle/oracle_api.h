@@ -122,8 +122,10 @@ double oracle_inertia_over_mass(const oobject* obj);
 
 /* One grasp step for B candidates q [B][n_dof].
    loss [B]; terms [B][4] = (L_stable, L_pen, L_range, L_limit) or NULL;
-   grad [B][n_dof] or NULL; margins [B][2] = (min |d| over samples,
-   min face margin over samples) or NULL. */
+   grad [B][n_dof] or NULL; margins [B][3] = (min |d| over samples with
+   w > w_min; min face margin in cell units over the penetrating ones, d < 0,
+   whose gradient sets a correction; the same over every sample with
+   w > w_min, whose gradient the leaky rule reaches) or NULL. */
 int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B,
                 const double* q, double* loss, double* terms, double* grad, double* margins,
                 int n_threads);

@@ -44,7 +44,7 @@ int main() {
     q[b * nd + 0] = 0.01 * b - 0.01; q[b * nd + 2] = 0.02; q[b * nd + 3] = 0.3 * b;
     for (int j = 6; j < nd; ++j) q[b * nd + j] = 0.2 * j - 1.0 + 0.1 * b;
   }
-  double loss[B], terms[4 * B], grad[B * nd], margins[2 * B], fd[B * nd];
+  double loss[B], terms[4 * B], grad[B * nd], margins[3 * B], fd[B * nd];
   int ex[B * nd];
   if (oracle_step(&h, &o, &p, B, q, loss, terms, grad, margins, 2)) return 1;
   if (oracle_fd_grad(&h, &o, &p, B, q, 1e-6, fd, ex, 2)) return 2;
