@@ -6,7 +6,8 @@ next, so FP32 and FP64 poses drift apart by a few 1e-8 m over a sweep; a
 constraint closer than 1e-6 m to d = 0 may then switch sides, and candidates
 holding one are reported and capped. Also: the fused step with Adam equals
 the forward, backward and Adam launches; the sweep differs from the averaged
-form; refusals of the forms it does not run in; 8193 contacts; K = 3."""
+form; refusals of the forms it does not run in; 8193 contacts; K = 3; a
+teacher-forced 30-step trajectory."""
 import numpy as np
 import pytest
 import torch
@@ -218,5 +219,74 @@ def test_gs_two_streams_share_the_start_pose_table(ctx):
             ctx.step_bwd(h, sd, sp, qb, outs[1], stream=s2)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], ref[0]) and torch.equal(outs[1], ref[1])
+    sd.unload()
+    h.destroy()
+
+
+def test_gs_trajectory_teacher_forced(ctx):
+    """30 fused Gauss-Seidel steps on the small workload along the dilation
+    schedule from 1 cm, each checked from the GPU's own state: the loss within
+    1e-4 and the gradient within 1e-3 of the oracle's sweep at that q, and the
+    Adam update within 1e-6 of its operands' magnitudes. Set aside, reported:
+    for the loss, candidates holding a constraint within 1e-6 m of d = 0 or a
+    penetrating sample within 1e-5 cell units of a cell face (FP32 may take
+    the other side or the neighbouring cell's gradient); for the gradient,
+    also any sample that close to a face, since the leak reaches every
+    sample's gradient. Where the FP64 gradient itself moves under changes of
+    q at FP32 resolution (|v| near 0), the gradient tolerance is four times
+    that movement."""
+    hand, grid, q0 = S.config_workload("tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    H, ob = O.Hand(hand.rounded()), O.Obj(grid)
+    B, T, r0 = q0.shape[0], 30, 0.01
+    qd = dev(q0)
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    loss = torch.empty(B, device=DEV)
+    dq = torch.empty_like(qd)
+    lr, b1, b2, eps = (float(np.float32(x)) for x in (1e-3, 0.9, 0.999, 1e-8))
+    fl, gfl, worst_l, worst_g = [], [], 0.0, 0.0
+    for t in range(T):
+        r = float(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1))
+        sp, op = prm_pair(projection=GS, r_dil=r)
+        q_prev, m_prev, v_prev = (x.cpu().numpy().astype(np.float64) for x in (qd, m, v))
+        ctx.step_fused(h, sd, sp, qd, m, v, t + 1, loss=loss, dq=dq)
+        torch.cuda.synchronize()
+        lg, gg = loss.cpu().numpy(), dq.cpu().numpy()
+        ref = O.step(H, ob, op, q_prev, grad=True, margins=True)
+        floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
+        lerr = np.abs(lg - ref["loss"]) / floor
+        flagged = (ref["min_abs_d"] < KINK_GS) | (ref["min_face"] < 1e-5)
+        gflag = flagged | (ref["min_face_all"] < 1e-5)
+        assert np.all(lerr[~flagged] <= 1e-4), (t, np.argmax(np.where(flagged, 0, lerr)), lerr[~flagged].max())
+        gscale = np.maximum(np.abs(ref["grad"]).max(axis=1), 1e-30)
+        gerr = np.abs(gg - ref["grad"]).max(axis=1) / gscale
+        over = np.nonzero(~gflag & (gerr > 1e-3))[0]
+        if over.size:
+            cond = np.zeros(over.size)
+            rng = np.random.default_rng(t)
+            for _ in range(3):
+                qp = q_prev[over] * (1.0 + rng.normal(size=q_prev[over].shape) * 6e-8)
+                gp = O.step(H, ob, op, qp)["grad"]
+                cond = np.maximum(cond, np.abs(gp - ref["grad"][over]).max(axis=1) / gscale[over])
+            bad = gerr[over] > np.maximum(1e-3, 4.0 * cond)
+            assert not bad.any(), (t, over[bad], gerr[over][bad])
+        fl.append(flagged.mean())
+        gfl.append(gflag.mean())
+        worst_l = max(worst_l, lerr[~flagged].max() if (~flagged).any() else 0.0)
+        worst_g = max(worst_g, gerr[~gflag].max() if (~gflag).any() else 0.0)
+        g64 = gg.astype(np.float64)
+        qa, ma, va = O.adam(q_prev, m_prev, v_prev, g64, t + 1, lr=lr, b1=b1, b2=b2, eps=eps)
+        sm = b1 * np.abs(m_prev) + (1.0 - b1) * np.abs(g64)
+        sv = b2 * v_prev + (1.0 - b2) * g64 * g64
+        vhat = va / (1.0 - b2 ** (t + 1))
+        sq = np.abs(q_prev) + lr * (sm / (1.0 - b1 ** (t + 1))) / (np.sqrt(vhat) + eps)
+        for name, got, want, scale in (("q", qd, qa, sq), ("m", m, ma, sm), ("v", v, va, sv)):
+            err = np.abs(got.cpu().numpy() - want)
+            assert np.all(err <= 1e-6 * scale + 1e-7), (t, name, err.max())
+    say(f"GS trajectory: {T} steps, B={B}: worst loss rel err {worst_l:.2e}, worst grad rel err {worst_g:.2e}, "
+        f"set aside for the loss mean {np.mean(fl):.3f} max {np.max(fl):.3f}, for the gradient mean "
+        f"{np.mean(gfl):.3f} max {np.max(gfl):.3f}")
+    assert np.max(fl) <= 0.25 and np.mean(fl) <= 0.1
+    assert np.max(gfl) <= 0.5 and np.mean(gfl) <= 0.3
     sd.unload()
     h.destroy()
