@@ -386,6 +386,7 @@ typedef struct {
   float* v;
   float* loss;           /* dev [B] or NULL: loss at the start of the step */
   float* terms;          /* dev [B][4] or NULL */
+  float* dq;             /* dev [B][n_dof] or NULL: the gradient the step's Adam update used */
   int32_t t;             /* optimizer steps already taken; the call runs Adam step t + 1
                             and increments t */
   int32_t T;             /* schedule length (dilation reaches 0 at t = T - 1) */
@@ -439,6 +440,8 @@ typedef struct {
   int32_t n_thr;         /* with eval: contact-area thresholds in thresholds[], 1..GRASP_MAX_THRESHOLDS */
   float thresholds[GRASP_MAX_THRESHOLDS]; /* metres, finite */
   int32_t top_k;         /* with eval: 0..min(B, GRASP_MAX_TOP); without: 0 */
+  int32_t record_history;/* 1: keep q before and the loss at every step (host memory, 4 B (n_dof + 1)
+                            per candidate and step), returned through hist_q / hist_loss */
 } grasp_job_desc;
 
 typedef struct {
@@ -453,6 +456,10 @@ typedef struct {
                             with an evaluation set), or NULL */
   int32_t* top;          /* host [top_k]: the best candidates by final loss, best first, or NULL */
   float* top_mean;       /* host [n_thr + 1]: their mean metrics, or NULL */
+  float* hist_q;         /* host [T][B][n_dof] or NULL: with record_history, q before each step taken (rows
+                            past `steps` untouched) */
+  float* hist_loss;      /* host [T][B] or NULL: with record_history, the loss at the start of each step
+                            (at that step's dilation) */
 } grasp_job_result;
 
 /* Sets the scheduler's candidate capacity per step (default 65536) and job

@@ -76,21 +76,22 @@ class StepParamsC(C.Structure):
 class BatchJobC(C.Structure):
     _fields_ = [("hand", C.c_uint64), ("sdf", C.c_uint64), ("p", StepParamsC), ("B", C.c_int32),
                 ("q", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("loss", C.c_void_p),
-                ("terms", C.c_void_p), ("t", C.c_int32), ("T", C.c_int32), ("r0", C.c_float),
-                ("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float)]
+                ("terms", C.c_void_p), ("dq", C.c_void_p), ("t", C.c_int32), ("T", C.c_int32),
+                ("r0", C.c_float), ("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float)]
 
 
 class JobDescC(C.Structure):
     _fields_ = [("hand", C.c_uint64), ("sdf", C.c_uint64), ("B", C.c_int32), ("q0", C.c_void_p),
                 ("T", C.c_int32), ("r0", C.c_float), ("p", StepParamsC), ("lr", C.c_float), ("b1", C.c_float),
                 ("b2", C.c_float), ("eps", C.c_float), ("eval", C.c_uint64), ("n_thr", C.c_int32),
-                ("thresholds", C.c_float * 8), ("top_k", C.c_int32)]
+                ("thresholds", C.c_float * 8), ("top_k", C.c_int32), ("record_history", C.c_int32)]
 
 
 class JobResultC(C.Structure):
     _fields_ = [("status", C.c_int32), ("q", C.c_void_p), ("loss", C.c_void_p), ("terms", C.c_void_p),
                 ("rank", C.c_void_p), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
-                ("steps", C.c_int32), ("metrics", C.c_void_p), ("top", C.c_void_p), ("top_mean", C.c_void_p)]
+                ("steps", C.c_int32), ("metrics", C.c_void_p), ("top", C.c_void_p), ("top_mean", C.c_void_p),
+                ("hist_q", C.c_void_p), ("hist_loss", C.c_void_p)]
 
 
 class ServeStatsC(C.Structure):

@@ -163,23 +163,25 @@ class Context:
         self.lib.call("grasp_serve_config", self.h, capacity, max_jobs)
 
     def submit(self, hand, sdf, q0, T: int, r0: float = 0.01, prm: StepParams | None = None, lr=1e-3, b1=0.9,
-               b2=0.999, eps=1e-8, eval_points=None, thresholds=(), top_k: int = 0) -> int:
+               b2=0.999, eps=1e-8, eval_points=None, thresholds=(), top_k: int = 0, record_history: bool = False) -> int:
         """Queues a grasp job (host q0 [B][n_dof]); returns its id. With an
         evaluation set the job retires with its metrics at the given
-        thresholds and, with top_k, the best candidates and their means."""
+        thresholds and, with top_k, the best candidates and their means.
+        record_history keeps q before and the loss at every step."""
         q0 = _f32(q0)
         prm = prm or StepParams()
         thr = [float(x) for x in thresholds]
         d = JobDescC(hand.id, sdf.id, q0.shape[0], q0.ctypes.data, T, r0, prm.c(), lr, b1, b2, eps,
                      eval_points.id if eval_points is not None else 0, len(thr),
-                     (C.c_float * 8)(*(thr + [0.0] * (8 - len(thr)))[:8]), top_k)
+                     (C.c_float * 8)(*(thr + [0.0] * (8 - len(thr)))[:8]), top_k, int(record_history))
         out = C.c_uint64()
         self.lib.call("grasp_submit", self.h, C.byref(d), C.byref(out))
         return out.value
 
-    def poll(self, job: int, B: int, n_dof: int, n_metrics: int = 0, top_k: int = 0):
+    def poll(self, job: int, B: int, n_dof: int, n_metrics: int = 0, top_k: int = 0, T: int = 0):
         """None while the job runs; then a dict of its results (status, q, loss, terms, rank, times, and
-        for jobs with an evaluation set: metrics [B][n_metrics], top [top_k], top_mean [n_metrics])."""
+        for jobs with an evaluation set: metrics [B][n_metrics], top [top_k], top_mean [n_metrics]; with
+        T > 0, for a job that recorded its history, hist_q [steps][B][n_dof] and hist_loss [steps][B])."""
         q = np.zeros((B, n_dof), np.float32)
         loss = np.zeros(B, np.float32)
         terms = np.zeros((B, 4), np.float32)
@@ -187,9 +189,11 @@ class Context:
         met = np.zeros((B, n_metrics), np.float32) if n_metrics else None
         top = np.zeros(top_k, np.int32) if top_k else None
         mean = np.zeros(n_metrics, np.float32) if top_k else None
+        hq = np.zeros((T, B, n_dof), np.float32) if T else None
+        hl = np.zeros((T, B), np.float32) if T else None
         ptr = lambda a: None if a is None else a.ctypes.data
         r = JobResultC(0, q.ctypes.data, loss.ctypes.data, terms.ctypes.data, rank.ctypes.data, 0, 0, 0, 0,
-                       ptr(met), ptr(top), ptr(mean))
+                       ptr(met), ptr(top), ptr(mean), ptr(hq), ptr(hl))
         code = self.lib.grasp_poll(self.h, job, C.byref(r))
         if code == GRASP_EAGAIN:
             return None
@@ -197,7 +201,8 @@ class Context:
             self.lib.check(code, "grasp_poll")
         return {"status": r.status, "q": q, "loss": loss, "terms": terms, "rank": rank, "t_submit": r.t_submit,
                 "t_admit": r.t_admit, "t_done": r.t_done, "steps": r.steps, "metrics": met, "top": top,
-                "top_mean": mean}
+                "top_mean": mean, "hist_q": None if hq is None else hq[:r.steps],
+                "hist_loss": None if hl is None else hl[:r.steps]}
 
     def cancel(self, job: int):
         self.lib.call("grasp_cancel", self.h, job)
@@ -349,13 +354,16 @@ class EvalPoints:
 
 
 class GraspStep(torch.autograd.Function):
-    """loss = GraspStep.apply(q, ctx, hand, sdf, params): the grasp loss of
-    each candidate (grasp_step_fwd); backward is the hand-written adjoint
-    (grasp_step_bwd). In SAVE/AUTO mode a workspace tensor carries the pose
-    checkpoints from forward to backward; RECOMPUTE needs none."""
+    """loss = GraspStep.apply(q, ctx, hand, sdf, params[, ws_budget]): the grasp
+    loss of each candidate (grasp_step_fwd); backward is the hand-written
+    adjoint (grasp_step_bwd). In SAVE mode a workspace tensor carries the pose
+    checkpoints from forward to backward; RECOMPUTE needs none and the
+    backward recomputes FK and the samples. AUTO saves only when the workspace
+    fits ws_budget bytes (default: half of the device's free memory), so a
+    batch too large for memory recomputes instead of failing."""
 
     @staticmethod
-    def forward(fctx, q, ctx: Context, hand: Hand, sdf: Sdf, prm: StepParams):
+    def forward(fctx, q, ctx: Context, hand: Hand, sdf: Sdf, prm: StepParams, ws_budget=None):
         q = q.detach().contiguous()
         if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != hand.n_dof:
             raise ValueError("q must be float32 [B][n_dof]")
@@ -364,7 +372,12 @@ class GraspStep(torch.autograd.Function):
         ws = None
         if prm.mode != MODE_RECOMPUTE:
             nb = ctx.workspace_bytes(hand, sdf, prm, B)
-            ws = torch.empty(max(nb, 4), dtype=torch.uint8, device=q.device)
+            if prm.mode == MODE_AUTO:
+                budget = ws_budget if ws_budget is not None else torch.cuda.mem_get_info(q.device)[0] // 2
+                if nb > budget:
+                    nb = -1  # recompute in the backward
+            if nb >= 0:
+                ws = torch.empty(max(nb, 4), dtype=torch.uint8, device=q.device)
         ctx.step_fwd(hand, sdf, prm, q, loss, ws=ws)
         fctx.save_for_backward(q)
         fctx.extra = (ctx, hand, sdf, prm, ws)
@@ -376,7 +389,7 @@ class GraspStep(torch.autograd.Function):
         ctx, hand, sdf, prm, ws = fctx.extra
         dq = torch.empty_like(q)
         ctx.step_bwd(hand, sdf, prm, q, dq, dloss=dloss.contiguous().to(torch.float32), ws=ws)
-        return dq, None, None, None, None
+        return dq, None, None, None, None, None
 
 
 class BatchJob:
@@ -384,20 +397,22 @@ class BatchJob:
     device tensors q, m, v (updated in place) and schedule position."""
 
     def __init__(self, hand: Hand, sdf: Sdf, prm: StepParams, q, m=None, v=None, loss=None, terms=None,
-                 t: int = 0, T: int = 300, r0: float = 0.01, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+                 t: int = 0, T: int = 300, r0: float = 0.01, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, dq=None):
         self.hand, self.sdf, self.prm = hand, sdf, prm
         self.q = q
         self.m = torch.zeros_like(q) if m is None else m
         self.v = torch.zeros_like(q) if v is None else v
         self.loss = torch.empty(q.shape[0], dtype=torch.float32, device=q.device) if loss is None else loss
         self.terms = terms
+        self.dq = dq
         self.t, self.T, self.r0 = t, T, r0
         self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
 
     def c(self) -> BatchJobC:
         return BatchJobC(self.hand.id, self.sdf.id, self.prm.c(), self.q.shape[0], self.q.data_ptr(),
                          self.m.data_ptr(), self.v.data_ptr(), self.loss.data_ptr(),
-                         None if self.terms is None else self.terms.data_ptr(), self.t, self.T, self.r0,
+                         None if self.terms is None else self.terms.data_ptr(),
+                         None if self.dq is None else self.dq.data_ptr(), self.t, self.T, self.r0,
                          self.lr, self.b1, self.b2, self.eps)
 
 

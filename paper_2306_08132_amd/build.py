@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libgrasp.so")
-SOURCES = ["step_kernels.hip", "plain_kernels.hip", "mesh_kernels.hip", "api.cpp", "arena.cpp", "batch.cpp", "sched.cpp",
+SOURCES = ["step_kernels.hip", "plain_kernels.hip", "mesh_kernels.hip", "api.cpp", "arena.cpp", "batch.cpp", "serve_core.cpp", "sched.cpp",
            "mesh.cpp", "eval_kernels.hip", "eval.cpp", "gs_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -562,6 +562,13 @@ grasp_status launch_gs(grasp_ctx* ctx, const StepArgs& a, StepKind kind, bool ad
     e = launch_gs_step(a, kind, adam, nullptr, s);
     return e == hipSuccess ? GRASP_OK : device_fail(ctx, e, where);
   }
+  // the start-pose table is a context buffer that a later, larger step may
+  // move: a captured graph would keep its old address
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return device_fail(ctx, e, where);
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(GRASP_EINVAL, "a Gauss-Seidel step with a backward cannot be captured into a graph");
   const size_t need = gs_scratch_floats(a.B, a.hand.n_chunks, a.prm.K);
   std::lock_guard<std::mutex> lk(ctx->gs_mu);
   if (ctx->gs_cap < need) {
@@ -806,7 +813,7 @@ grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, 
 
 grasp_status step_fused_gs(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
                            int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2, float eps,
-                           float* loss, float* starts, hipStream_t s) {
+                           float* loss, float* starts, int* nonfinite, hipStream_t s) {
   GRASP_CHECK_CTX(ctx);
   Resolved r;
   grasp_status st = resolve(ctx, hand, sdf, p, B, &r, true);
@@ -821,6 +828,7 @@ grasp_status step_fused_gs(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
   a.m = m;
   a.v = v;
   a.loss = loss;
+  a.nonfinite = nonfinite;
   a.adam = adam_consts(t, lr, b1, b2, eps);
   DeviceGuard g(ctx->device);
   const hipError_t e = launch_gs_step(a, STEP_FUSED, true, starts, s);

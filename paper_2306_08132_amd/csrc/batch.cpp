@@ -68,6 +68,7 @@ grasp_status batch_fill(grasp_batch* bt, const grasp_batch_job* jobs, int32_t n,
     e.args.v = j.v;
     e.args.loss = j.loss;
     e.args.terms = j.terms;
+    e.args.dq = j.dq;
     e.args.nonfinite = bt->flags_dev + i;
     e.args.order = j.B >= kOrderMinB ? bt->order_dev + total : nullptr;
     e.begin = total;

@@ -141,10 +141,11 @@ grasp_status resolve_job(grasp_ctx* ctx, const grasp_batch_job& j, HandView* h, 
 
 // The serving loop's Gauss-Seidel step: grasp_step_fused without terms or dq,
 // its start-pose table at `starts` (gs_scratch_floats(B, n_chunks, K) device
-// floats that only stream s uses) instead of the context's shared table.
+// floats that only stream s uses) instead of the context's shared table;
+// *nonfinite (device int) is set when a loss is not finite.
 grasp_status step_fused_gs(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf, const grasp_step_params* p,
                            int32_t B, float* q, float* m, float* v, int32_t t, float lr, float b1, float b2, float eps,
-                           float* loss, float* starts, hipStream_t s);
+                           float* loss, float* starts, int* nonfinite, hipStream_t s);
 
 // Checks step parameters and fills the device constants.
 grasp_status check_params(const grasp_step_params* p, StepConsts* out);

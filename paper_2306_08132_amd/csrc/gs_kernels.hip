@@ -202,6 +202,7 @@ __device__ void gs_candidate(const StepArgs& A, int b, int kind, bool adam, floa
       if (A.terms) {
         A.terms[4 * b] = Lstable; A.terms[4 * b + 1] = lpen; A.terms[4 * b + 2] = Lrange; A.terms[4 * b + 3] = Llimit;
       }
+      if (A.nonfinite && !isfinite(L)) atomicOr(A.nonfinite, 1);
     }
   }
   if (!do_bwd) return;
