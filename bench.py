@@ -1,18 +1,23 @@
-"""Benchmark of the fused grasp step on one MI355X.
+"""Benchmark of the grasp step on one MI355X.
 
 One step = one pass of the whole hot path over every candidate: forward
-kinematics, SDF gathers for M = 7 velocity tests, the PBD corrections and
-losses, the hand-written adjoint, and Adam (a single fused launch). The
-workload is the differentiable-step configuration: a 4-finger 22-DOF hand
-with 2048 contacts, a 128^3 SDF of a union of ellipsoids, 4096 candidates,
-synthetic inputs already resident in HBM.
+kinematics, SDF gathers for M = 7 velocity tests and K projection
+iterations, the PBD corrections and losses, the hand-written adjoint, and
+Adam, in one fused launch. The headline workload is the largest single-GPU
+configuration: 65536 candidates of a 5-finger 26-DOF hand with 8192
+contacts on a 256^3 SDF of a union of 8 ellipsoids/boxes, K = 16 projection
+iterations with pose checkpoints every 4 (the backward recomputes FK and the
+samples inside each segment). Inputs are synthetic and resident in HBM.
 
-Prints one JSON line: contact-evaluations per second (forward + backward),
-the roofline of the step kernel and the FP64 oracle timed on the host, with
-the other workloads beside them: the plain per-job form on the same
-candidates, a Poisson stream of jobs through the serving loop, 16 uneven
-jobs in one batched launch per step, K = 16 projection iterations on 65536
-candidates (256^3 grid), and Phong signed-distance queries on mesh objects.
+Prints one JSON line: the headline's contact-evaluations per second (forward
++ backward), its roofline (algorithmic bytes of the accounting below over the
+kernel's launch time; the bound chosen from the committed rocprofv3 counters)
+and the FP64 oracle timed on the host, with the other workloads beside them:
+the differentiable-step workload (4096 candidates, 2048 contacts, 128^3)
+fused and in the plain per-job form, 16 uneven jobs in one batched launch per
+step, the serving stream (64 Poisson jobs at 20/s and a sub-saturation
+stream, each also through the plain per-job form first in first out), the
+Gauss-Seidel projection, the post-synthesis metrics and mesh queries.
 """
 from __future__ import annotations
 
@@ -43,6 +48,39 @@ def algorithmic_bytes(B, Nc, K, n_dof, n, live):
     bound = 4 * B * Nc if K == 1 else 4 * evals
     nb = -(-(n - 1) // 4)
     return int(32 * evals * (1.0 + live) + bound + 24 * B * Nc + 28 * B * n_dof + 4 * n ** 3 + 4 * nb ** 3)
+
+
+def survey_bytes(B, Nc, K, n_dof, n):
+    """Algorithmic bytes of one step in the plain accounting: per contact
+    evaluation the 8 FP32 corners gathered once in the forward and once in
+    the backward (64 B); per (candidate, contact) the link-local coordinates
+    (24 B); per (candidate, DOF) q, m, v read and written plus dq (28 B); the
+    grid once. No credit for samples the forward skips or for cache hits."""
+    return int(64 * B * Nc * M_SIMS * K + 24 * B * Nc + 28 * B * n_dof + 4 * n ** 3)
+
+
+CLOCK_HZ = 2.4e9      # MI355X peak engine clock
+SIMDS = 256 * 4       # 256 CUs x 4 SIMDs; a wave64 FP32 VALU instruction takes 4 cycles on a 16-lane SIMD
+
+
+def counter_fractions(kernel, workload, launch_s):
+    """From the committed rocprofv3 counters of this kernel source: the VALU
+    busy fraction (SQ_INSTS_VALU x 4 cycles over the launch's SIMD-cycles at
+    2.4 GHz) and the DRAM fraction (copy-scaled FETCH_SIZE + WRITE_SIZE per
+    launch over the launch time and 8 TB/s). None when missing or stale."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(kernel, {}).get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    traffic = e["fetch_kib"] * 1024 * e["fetch_scale"] + e["write_kib"] * 1024 * e["write_scale"]
+    valu = e["sq_insts_valu"] * 4.0 / (launch_s * CLOCK_HZ * SIMDS)
+    dram = traffic / launch_s / (HBM_PEAK_GBS * 1e9)
+    return {"valu_busy_frac": valu, "dram_frac": dram, "traffic_bytes_per_launch": traffic,
+            "sq_insts_valu_per_launch": e["sq_insts_valu"], "profiled_launch_ms": e.get("avg_ms")}
 
 
 def live_fraction(ctx, h, sd, prm, q):
@@ -90,7 +128,9 @@ def cpu_baseline(hand, grid, q, prm_kw, budget_s=12.0):
     dt = time.perf_counter() - t0
     evals = done * hand.n_contacts * M_SIMS * prm_kw.get("K", 1)
     return {"value": evals / dt, "unit": "contact-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} of {q.shape[0]} candidates, 1 step, forward + gradient, FP64, {dt:.1f} s"}
+            "sample": f"{done} of {q.shape[0]} candidates x 1 step ({hand.n_contacts} contacts, 7 tests, "
+                      f"K = {prm_kw.get('K', 1)}), forward + dual-number gradient, FP64, {dt:.1f} s",
+            "label": "FP64 correctness oracle, not a tuned CPU baseline"}
 
 
 def cpu_eval_baseline(hand, grid, q, S, budget_s=4.0):
@@ -113,60 +153,189 @@ def cpu_eval_baseline(hand, grid, q, S, budget_s=4.0):
             "sample": f"{done} of {q.shape[0]} candidates, FP64, {dt:.1f} s"}
 
 
-def serving_pool(S, device):
-    """A few hands and objects for the served jobs (geometry is built once
-    and stays resident; jobs draw from it)."""
-    import numpy as np
-    hands = {F: S.make_hand(F, 4 if F > 3 else 3, 2048, seed=200 + F) for F in (3, 4, 5)}
-    objs = []
-    for k, n in enumerate((64, 96, 128)):
-        prims = S.make_object("mixed", seed=300 + k, n_range=(3, 6))
-        objs.append(S.make_grid(prims, n, device=device))
-    return hands, objs
+def host_cpu():
+    """The host's CPU model and core counts (the machine the oracle runs on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "usable_cores": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
-def serving_run(ctx, S, n_jobs, rate, steps):
-    """Poisson stream of grasp jobs through the serving loop: p50/p99 of
-    submit-to-result latency and served contact-evaluations per second."""
+def cpu_matrix(workloads, budget_s=2.5):
+    """The FP64 oracle, unmodified, on every workload's per-candidate shape:
+    forward only and forward + dual-number gradient, on all the host threads
+    it may use and on one. Each entry runs whole candidates (one optimizer
+    step each, at the workload's dilation) until budget_s has passed, at
+    least one; candidates are independent, so the rate carries over to any
+    count. Label: FP64 correctness oracle, not a tuned CPU baseline."""
     import numpy as np
-    from paper_2306_08132_amd.api import StepParams
-    hands, objs = serving_pool(S, "cuda:0")
-    rh = {F: ctx.hand(h) for F, h in hands.items()}
-    ro = [ctx.sdf(g) for g in objs]
-    stream = S.make_job_stream(n_jobs, rate, seed=3, B_range=(256, 2048), steps=steps)
-    rng = np.random.default_rng(3)
+    import oracle as O
+    threads_all = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {}
+    for name, (hand, grid, q, prm_kw) in workloads.items():
+        H, ob, P = O.Hand(hand.rounded()), O.Obj(grid), O.Params(**prm_kw)
+        per_cand = hand.n_contacts * M_SIMS * prm_kw.get("K", 1)
+        for threads in (threads_all, 1):
+            for grad in (False, True):
+                chunk = threads
+                done, t0 = 0, time.perf_counter()
+                while done < q.shape[0] and (done == 0 or time.perf_counter() - t0 < budget_s):
+                    qs = q[done % q.shape[0]:done % q.shape[0] + chunk]
+                    O.step(H, ob, P, qs.astype(np.float32).astype(np.float64), grad=grad, threads=threads)
+                    done += qs.shape[0]
+                dt = time.perf_counter() - t0
+                key = f"{name}/{'fwd+grad' if grad else 'fwd'}/{threads}t"
+                out[key] = {"contact_evals_per_s": done * per_cand / dt, "candidates": done, "s": round(dt, 2)}
+    return out
+
+
+def c4_jobs(S, n_jobs, rate, steps, device):
+    """The serving workload: a Poisson stream (mean `rate` jobs/s, stream seed
+    3) of jobs, each with its own random hand (3, 4 or 5 fingers of 3 or 4
+    joints, 1024, 2048 or 4096 contacts), its own random union of 3-8
+    ellipsoids/boxes on a 64^3..256^3 grid, U[256, 8192] candidates on the
+    approach shell, and `steps` optimizer steps."""
+    import numpy as np
+    stream = S.make_job_stream(n_jobs, rate, seed=3, B_range=(256, 8192), steps=steps)
     jobs = []
     for j in stream:
-        F = int(rng.integers(3, 6))
-        g = int(rng.integers(0, len(objs)))
-        q = S.make_candidates(hands[F], j["B"], seed=j["hand_seed"] % 100000,
-                              shell_radius=objs[g].bound_radius + 0.06).astype(np.float32)
-        jobs.append((j["arrival"], F, g, q))
+        hand = S.make_hand(j["fingers"], j["joints"], j["n_contacts"], seed=j["hand_seed"] % (1 << 30))
+        prims = S.make_object("mixed", seed=j["obj_seed"] % (1 << 30), n_range=(3, 8))
+        grid = S.make_grid(prims, j["res"], device=device)
+        q = S.make_candidates(hand, j["B"], seed=j["hand_seed"] % 100003,
+                              shell_radius=grid.bound_radius + 0.06).astype(np.float32)
+        jobs.append(dict(j, hand=hand, grid=grid, q=q))
+    return jobs
+
+
+def _latency_stats(lat):
+    import numpy as np
+    lat = np.asarray(lat)
+    return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "max_s": float(lat.max())}
+
+
+def serve_stream(ctx, jobs, res, arrivals):
+    """Submits each job at its arrival time (seconds from the start) to the
+    serving loop and waits for all: submit-to-result latencies, jobs/s and
+    served contact-evaluations/s over the stream's wall time."""
+    from paper_2306_08132_amd.api import StepParams
     st0 = ctx.serve_stats()
     t0 = time.perf_counter()
     ids = []
-    for arr, F, g, q in jobs:
+    for j, arr in zip(jobs, arrivals):
         while time.perf_counter() - t0 < arr:
             time.sleep(0.0005)
-        ids.append((ctx.submit(rh[F], ro[g], q, T=steps, prm=StepParams()), F, q.shape[0]))
-    lat, status = [], []
-    for jid, F, B in ids:
+        h, sd = res[id(j)]
+        ids.append((ctx.submit(h, sd, j["q"], T=j["steps"], prm=StepParams()), j))
+    lat, ok = [], True
+    for jid, j in ids:
         while True:
-            r = ctx.poll(jid, B, hands[F].n_dof)
+            r = ctx.poll(jid, j["q"].shape[0], j["hand"].n_dof)
             if r is not None:
                 break
             time.sleep(0.001)
         lat.append(r["t_done"] - r["t_submit"])
-        status.append(r["status"])
+        ok = ok and r["status"] == 0
     wall = time.perf_counter() - t0
     st1 = ctx.serve_stats()
-    lat = np.array(lat)
     evals = st1["contact_evals"] - st0["contact_evals"]
-    return {"jobs": n_jobs, "rate_per_s": rate, "steps_per_job": steps, "candidates": "U[256, 2048]",
-            "contacts": 2048, "grids": [g.n for g in objs], "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "jobs_per_s": n_jobs / wall,
-            "contact_evals_per_s": evals / wall, "batched_steps": st1["steps"] - st0["steps"],
-            "all_ok": bool(all(s_ == 0 for s_ in status))}
+    return dict(_latency_stats(lat), jobs=len(jobs), wall_s=wall, jobs_per_s=len(jobs) / wall,
+                contact_evals_per_s=evals / wall, batched_steps=st1["steps"] - st0["steps"], all_ok=bool(ok))
+
+
+def plain_fifo(ctx, jobs, res, arrivals):
+    """The same stream through the plain per-job form, first in first out: one
+    job at a time (its T plain steps: unfused stage kernels with HBM
+    intermediates, then Adam; the final forward at zero dilation), the next
+    job starting when it has both arrived and the previous one has ended.
+    Latency = end - arrival."""
+    import numpy as np
+    import torch
+    from paper_2306_08132_amd.api import StepParams
+    dev = "cuda:0"
+    ws_bytes = 0
+    for j in jobs:
+        h, sd = res[id(j)]
+        ws_bytes = max(ws_bytes, ctx.plain_workspace_bytes(h, sd, StepParams(), j["q"].shape[0]))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    lat, evals = [], 0
+    for j, arr in zip(jobs, arrivals):
+        while time.perf_counter() - t0 < arr:
+            time.sleep(0.0005)
+        h, sd = res[id(j)]
+        q = torch.tensor(j["q"], device=dev)
+        m, v = torch.zeros_like(q), torch.zeros_like(q)
+        loss = torch.empty(q.shape[0], device=dev)
+        T, r0 = j["steps"], 0.01
+        for t in range(T):
+            r = float(np.float32(np.float64(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1))))
+            ctx.plain_step(h, sd, StepParams(r_dil=r), q, m, v, t + 1, ws, loss=loss)
+        ctx.step_fwd(h, sd, StepParams(r_dil=0.0), q, loss)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - arr)
+        evals += q.shape[0] * j["hand"].n_contacts * M_SIMS * T
+    wall = time.perf_counter() - t0
+    del ws
+    return dict(_latency_stats(lat), jobs=len(jobs), wall_s=wall, jobs_per_s=len(jobs) / wall,
+                contact_evals_per_s=evals / wall)
+
+
+def serving_run(ctx, S, args):
+    """C4: 64 jobs at Poisson 20 jobs/s (an overload: the offered work is
+    several times what one GPU does per second), then the same jobs at 0.7x
+    the capacity the first stream measured; each stream also through the
+    plain per-job form first in first out. Hands and grids are resident
+    before the streams start (loading is not part of a job)."""
+    import numpy as np
+    print("bench: serving workload (building hands and grids)", file=sys.stderr, flush=True)
+    jobs = c4_jobs(S, args.serve_jobs, args.serve_rate, args.serve_steps, "cuda:0")
+    res = {}
+    for j in jobs:
+        res[id(j)] = (ctx.hand(j["hand"]), ctx.sdf(j["grid"]))
+    arr = np.array([j["arrival"] for j in jobs])
+    arr -= arr[0]
+    offered = sum(j["q"].shape[0] * j["hand"].n_contacts * M_SIMS * j["steps"] for j in jobs) / max(arr[-1], 1e-9)
+    out = {"jobs": len(jobs), "steps_per_job": args.serve_steps, "candidates": "U[256, 8192]",
+           "contacts": sorted({j["hand"].n_contacts for j in jobs}), "grids": sorted({j["grid"].n for j in jobs}),
+           "fingers": sorted({j["fingers"] for j in jobs}),
+           "contact_evals_per_job_mean": float(np.mean([j["q"].shape[0] * j["hand"].n_contacts * M_SIMS *
+                                                         j["steps"] for j in jobs]))}
+    print("bench: serving stream at 20 jobs/s", file=sys.stderr, flush=True)
+    over = serve_stream(ctx, jobs, res, arr)
+    over.update(rate_per_s=args.serve_rate, offered_contact_evals_per_s=offered)
+    cap = over["jobs_per_s"]
+    rate2 = 0.7 * cap
+    arr2 = arr * (args.serve_rate / rate2)
+    print(f"bench: serving stream at 0.7 x capacity ({rate2:.2f} jobs/s)", file=sys.stderr, flush=True)
+    sub = serve_stream(ctx, jobs, res, arr2)
+    sub.update(rate_per_s=rate2)
+    out["served"] = {"overload": over, "sub_saturation": sub}
+    if not args.no_plain:
+        print("bench: the same streams, plain per-job form, first in first out", file=sys.stderr, flush=True)
+        p1 = plain_fifo(ctx, jobs, res, arr)
+        p1.update(rate_per_s=args.serve_rate)
+        p2 = plain_fifo(ctx, jobs, res, arr2)
+        p2.update(rate_per_s=rate2)
+        out["plain_fifo"] = {"overload": p1, "sub_saturation": p2}
+        out["served_over_plain_throughput"] = over["contact_evals_per_s"] / p1["contact_evals_per_s"]
+    for h, sd in res.values():
+        sd.unload()
+    print(f"bench: served p50/p99 {over['p50_s']:.2f}/{over['p99_s']:.2f} s at 20/s, "
+          f"{sub['p50_s']:.2f}/{sub['p99_s']:.2f} s at {rate2:.2f}/s", file=sys.stderr, flush=True)
+    return out
 
 
 def batched_run(ctx, S, args):
@@ -201,21 +370,21 @@ def batched_run(ctx, S, args):
             b.step(bj, stream=stream)
         stream.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps // 5 + 3):
+        for _ in range(args.diff_steps // 5 + 3):
             b.step(bj, stream=stream)
         stream.synchronize()
-        tb = (time.perf_counter() - t0) / (args.steps // 5 + 3)
+        tb = (time.perf_counter() - t0) / (args.diff_steps // 5 + 3)
     # the same jobs, one fused launch per job per step
     sj = [(sd, q.clone(), torch.zeros_like(q), torch.zeros_like(q)) for sd, q in jobs]
     for sd, q, m, v in sj:
         ctx.step_fused(h, sd, StepParams(r_dil=0.01), q, m, v, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(args.steps // 5 + 3):
+    for t in range(args.diff_steps // 5 + 3):
         for sd, q, m, v in sj:
             ctx.step_fused(h, sd, StepParams(r_dil=0.01), q, m, v, t + 2)
     torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / (args.steps // 5 + 3)
+    ts = (time.perf_counter() - t0) / (args.diff_steps // 5 + 3)
     # the same jobs in the plain per-job form: unfused stages, HBM
     # intermediates, one set of launches per job per step
     ws = ctx.plain_workspace(h, jobs[0][0], StepParams(r_dil=0.01), max(q.shape[0] for _, q in jobs))
@@ -225,7 +394,7 @@ def batched_run(ctx, S, args):
         ctx.plain_step(h, sd, StepParams(r_dil=0.01), q, m, v, 1, ws, loss=lp)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n_plain = max(3, args.steps // 10)
+    n_plain = max(3, args.diff_steps // 10)
     for t in range(n_plain):
         for sd, q, m, v, lp in pj:
             ctx.plain_step(h, sd, StepParams(r_dil=0.01), q, m, v, t + 2, ws, loss=lp)
@@ -241,35 +410,65 @@ def batched_run(ctx, S, args):
             "algorithmic_bytes_per_step": abytes, "roofline_frac": abytes / tb / (HBM_PEAK_GBS * 1e9)}
 
 
-def large_run(ctx, S, args):
-    """K = 16 projection iterations, 65536 candidates, 8192 contacts, 256^3
-    grid; pose checkpoints every 4 iterations with replay in the backward."""
+def large_headline(ctx, S, args):
+    """The headline: K = 16 projection iterations on 65536 candidates, 8192
+    contacts, 256^3 grid, pose checkpoints every 4 iterations with replay in
+    the backward; W untimed steps, then exactly K timed steps, HIP events
+    around each step on the launch stream (the candidate order kernel and
+    the step kernel); the same with a checkpoint every iteration beside it."""
+    import numpy as np
     import torch
     from paper_2306_08132_amd.api import StepParams
-    print("bench: K = 16 workload", file=sys.stderr, flush=True)
+    print("bench: building the large workload", file=sys.stderr, flush=True)
     hand, grid, q0 = S.config_workload("large", device="cuda:0")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
     m, v = torch.zeros_like(q), torch.zeros_like(q)
-    live = live_fraction(ctx, h, sd, StepParams(K=16, ckpt_every=1, r_dil=0.01), q)
-    abytes = algorithmic_bytes(q0.shape[0], hand.n_contacts, 16, hand.n_dof, grid.n, live)
-    out = {"forward_live_fraction": live}
-    for ck in (4, 1):
-        prm = StepParams(K=16, ckpt_every=ck, r_dil=0.01)
-        ctx.step_fused(h, sd, prm, q, m, v, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for t in range(2):
-            ctx.step_fused(h, sd, prm, q, m, v, t + 2)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 2
-        evals = q.shape[0] * hand.n_contacts * M_SIMS * 16
-        out[f"ckpt{ck}"] = {"s_per_iteration": dt, "contact_evals_per_s": evals / dt,
-                            "roofline_frac": abytes / dt / (HBM_PEAK_GBS * 1e9)}
-        print(f"bench: K = 16, checkpoints every {ck}: {dt:.3f} s per step", file=sys.stderr, flush=True)
-    out["contact_evals_per_iteration"] = q.shape[0] * hand.n_contacts * M_SIMS * 16
-    out["algorithmic_bytes_per_iteration"] = abytes
-    return out
+    loss = torch.empty(q.shape[0], device="cuda:0")
+    stream = torch.cuda.current_stream()
+    B, Nc, nd, K = q0.shape[0], hand.n_contacts, hand.n_dof, 16
+    T, r0 = 200, 0.01
+    tile = (2, 4)  # the step kernel's launch shape for this workload (tuning it costs seconds per shape)
+    ctx.set_tile(h, sd, StepParams(K=K, ckpt_every=4), B, *tile)
+    ctx.set_tile(h, sd, StepParams(K=K, ckpt_every=1), B, *tile)
+
+    def step(t, ck):
+        prm = StepParams(K=K, ckpt_every=ck, r_dil=r0 * (1.0 - min(t, T - 1) / (T - 1)))
+        ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
+
+    for t in range(args.warmup):
+        step(t, 4)
+    torch.cuda.synchronize()
+    t_live = args.warmup
+    live = live_fraction(ctx, h, sd, StepParams(K=K, ckpt_every=1, r_dil=r0 * (1.0 - t_live / (T - 1))), q)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(args.warmup + i, 4)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # the same steps with a checkpoint every iteration (no replay), for comparison
+    ck1 = []
+    for i in range(2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step(args.warmup + args.steps + i, 1)
+        b.record(stream)
+        ck1.append((a, b))
+    torch.cuda.synchronize()
+    ck1_ms = float(np.mean([a.elapsed_time(b) for a, b in ck1]))
+    evals = B * Nc * M_SIMS * K
+    print(f"bench: large workload {launch_ms:.1f} ms per step (checkpoints every 4), {ck1_ms:.1f} ms (every "
+          f"iteration), {evals * args.steps / wall:.3e} contact-evals/s", file=sys.stderr, flush=True)
+    res = {"hand": hand, "grid": grid, "q0": q0, "B": B, "Nc": Nc, "n_dof": nd, "K": K, "tile": tile,
+           "wall_s": wall, "launch_ms": launch_ms, "ckpt1_launch_ms": ck1_ms, "evals": evals, "live": live,
+           "schedule": {"r0_m": r0, "T": T, "timed_steps": [args.warmup, args.warmup + args.steps - 1]}}
+    sd_h = (h, sd)
+    return res, sd_h
 
 
 def mesh_run(ctx, S, args):
@@ -335,7 +534,7 @@ def gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args):
         b.record(stream)
     for t in range(2):
         step(t)
-    n = max(3, args.steps // 5)
+    n = max(3, args.diff_steps // 5)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     for i, (a, b) in enumerate(evs):
         a.record(stream)
@@ -429,56 +628,18 @@ def eval_run(ctx, S, hand, grid, q0, h, sd, key, args):
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-job form")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
-    ap.add_argument("--serve-jobs", type=int, default=24)
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
-    ap.add_argument("--serve-steps", type=int, default=60, help="optimizer steps per served job")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
-    ap.add_argument("--no-large", action="store_true", help="skip the K = 16 workload (65536 candidates)")
-    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh-object queries")
-    ap.add_argument("--no-eval", action="store_true", help="skip the post-synthesis evaluation")
-    ap.add_argument("--no-gs", action="store_true", help="skip the Gauss-Seidel projection")
-    ap.add_argument("--tile", type=str, default=None,
-                    help="launch tile 'waves_per_block,min_waves_per_simd' instead of tuning (profiled runs: "
-                         "every step dispatch is then a timed shape)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
-                         "the reference that scales HBM counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the grasp step shards by "
-              "candidates with no exchange inside a step, so one GPU's share is what it measures.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def diff_run(ctx, S, args):
+    """The differentiable-step workload (4-finger 22-DOF hand, 2048 contacts,
+    128^3 union of ellipsoids, 4096 candidates, K = 1): fused steps along the
+    dilation schedule from r0 = 1 cm over T = 500 steps, 10 untimed then 50
+    timed, and the plain per-job form on the same candidates."""
     import numpy as np
     import torch
-    from paper_2306_08132_amd import _lib
-    from paper_2306_08132_amd import synth as S
-    from paper_2306_08132_amd.api import Context, StepParams
-
-    if not os.path.exists(_lib.LIB_PATH):
-        from __graft_entry__ import build
-        build()
-    if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    print("bench: building the workload", file=sys.stderr, flush=True)
+    from paper_2306_08132_amd.api import StepParams
+    print("bench: building the differentiable-step workload", file=sys.stderr, flush=True)
     hand, grid, q0 = S.config_workload("diff", device="cuda:0")
     B, Nc, nd, K = q0.shape[0], hand.n_contacts, hand.n_dof, 1
     T_sched, r0 = 500, 0.01
-    ctx = Context(0, arena_bytes=8 << 30)
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     stream = torch.cuda.current_stream()
     q = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
@@ -492,77 +653,175 @@ def main():
     if args.tile:
         tile = tuple(int(x) for x in args.tile.split(","))
         ctx.set_tile(h, sd, StepParams(K=K, r_dil=r0), B, tile[0], tile[1])
-        print(f"bench: tile {tile} (given)", file=sys.stderr, flush=True)
     else:
-        print("bench: tuning the launch tile", file=sys.stderr, flush=True)
-        tile, tile_ms = ctx.tune(h, sd, StepParams(K=K, r_dil=r0), q, reps=3)
-        print(f"bench: tile {tile} at {tile_ms:.3f} ms", file=sys.stderr, flush=True)
-    print("bench: warmup", file=sys.stderr, flush=True)
-    for t in range(args.warmup):
+        tile, _ = ctx.tune(h, sd, StepParams(K=K, r_dil=r0), q, reps=3)
+    warm, steps = args.diff_warmup, args.diff_steps
+    for t in range(warm):
         step(t)
     torch.cuda.synchronize()
-    live = live_fraction(ctx, h, sd, StepParams(K=K, r_dil=r0 * (1.0 - args.warmup / (T_sched - 1))), q)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    live = live_fraction(ctx, h, sd, StepParams(K=K, r_dil=r0 * (1.0 - warm / (T_sched - 1))), q)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ev[i][0].record(stream)
-        step(args.warmup + i)
+        step(warm + i)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    avg_ms = float(np.mean(kern_ms))
+    avg_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     evals = B * Nc * M_SIMS * K
-    value = evals * args.steps / wall
-    abytes = algorithmic_bytes(B, Nc, K, nd, grid.n, live)
-    achieved = abytes / (avg_ms * 1e-3) / 1e9
-    workload = "diff-step"
-    traffic = measured_traffic("k_step", workload)
-    print(f"bench: fused step {avg_ms:.3f} ms/launch, {value:.3e} contact-evals/s", file=sys.stderr, flush=True)
-
-    plain = None
+    value = evals * steps / wall
+    sbytes = survey_bytes(B, Nc, K, nd, grid.n)
+    cbytes = algorithmic_bytes(B, Nc, K, nd, grid.n, live)
+    cf = counter_fractions("k_step", "diff-step", avg_ms * 1e-3)
+    out = {"workload": "diff-step", "hand": "4 fingers x 4 joints, 22 DOF", "contacts": Nc, "candidates": B,
+           "sdf": f"union of {len(grid.prims)} ellipsoids, {grid.n}^3 FP32", "iterations": K,
+           "schedule": {"r0_m": r0, "T": T_sched, "timed_steps": [warm, warm + steps - 1]},
+           "steps": steps, "warmup": warm, "ms_per_step": wall * 1e3 / steps, "avg_launch_ms": avg_ms,
+           "contact_evals_per_s": value, "tile": list(tile),
+           "roofline": {"bound": None, "algorithmic_bytes_per_launch": sbytes,
+                        "frac": sbytes / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "culled_accounting_bytes_per_launch": cbytes,
+                        "culled_accounting_frac": cbytes / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "forward_live_fraction": live, "counters": cf}}
+    if cf:
+        out["roofline"]["bound"] = "hbm" if cf["dram_frac"] >= cf["valu_busy_frac"] else "alu"
+    print(f"bench: diff-step fused {avg_ms:.3f} ms/launch, {value:.3e} contact-evals/s", file=sys.stderr,
+          flush=True)
     if not args.no_plain:
         # the plain per-job form on the same candidates: unfused stages, HBM
         # intermediates, one launch per stage per step, no graph
-        print("bench: plain per-job form", file=sys.stderr, flush=True)
         qp = torch.tensor(q0, dtype=torch.float32, device="cuda:0")
         mp, vp = torch.zeros_like(qp), torch.zeros_like(qp)
         prm0 = StepParams(K=K, r_dil=r0)
         ws = ctx.plain_workspace(h, sd, prm0, B)
-        n_plain = max(3, args.steps // 5)
+        n_plain = max(3, steps // 5)
         for t in range(2):
             ctx.plain_step(h, sd, prm0, qp, mp, vp, t + 1, ws, loss=loss, stream=stream)
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         for t in range(n_plain):
-            prm = StepParams(K=K, r_dil=r0 * (1.0 - min(t, T_sched - 1) / (T_sched - 1)))
+            prm = StepParams(K=K, r_dil=r0 * (1.0 - min(t + 2, T_sched - 1) / (T_sched - 1)))
             ctx.plain_step(h, sd, prm, qp, mp, vp, t + 3, ws, loss=loss, stream=stream)
         torch.cuda.synchronize()
         tp = (time.perf_counter() - tp0) / n_plain
-        plain = {"value": evals / tp, "unit": "contact-evals/s", "ms_per_step": tp * 1e3, "steps": n_plain,
-                 "workspace_bytes": ws.numel(), "fused_over_plain": value / (evals / tp)}
+        out["plain"] = {"contact_evals_per_s": evals / tp, "ms_per_step": tp * 1e3, "steps": n_plain,
+                        "workspace_bytes": ws.numel()}
+        out["fused_over_plain"] = value / (evals / tp)
         del ws
-        print(f"bench: plain {tp * 1e3:.3f} ms/step, fused/plain {value / (evals / tp):.2f}x", file=sys.stderr,
+        print(f"bench: plain {tp * 1e3:.3f} ms/step, fused/plain {out['fused_over_plain']:.2f}x", file=sys.stderr,
               flush=True)
+    return out, (hand, grid, q0, h, sd, loss, avg_ms)
 
-    serving = None
-    if not args.no_serving:
-        print("bench: serving stream", file=sys.stderr, flush=True)
-        serving = serving_run(ctx, S, n_jobs=args.serve_jobs, rate=args.serve_rate, steps=args.serve_steps)
-    batched = None if args.no_batched else batched_run(ctx, S, args)
-    large = None if args.no_large else large_run(ctx, S, args)
-    mesh = None if args.no_mesh else mesh_run(ctx, S, args)
-    evaluation = None if args.no_eval else eval_run(ctx, S, hand, grid, q0, h, sd, loss, args)
-    gauss_seidel = None if args.no_gs else gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args)
 
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed steps of the headline (large) workload")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed steps of the headline workload")
+    ap.add_argument("--diff-steps", type=int, default=50, help="timed steps of the differentiable-step workload")
+    ap.add_argument("--diff-warmup", type=int, default=10)
+    ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baselines")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-job forms")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable-step workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving streams")
+    ap.add_argument("--serve-jobs", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-steps", type=int, default=300, help="optimizer steps per served job")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16 uneven jobs in one launch per step")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh-object queries")
+    ap.add_argument("--no-eval", action="store_true", help="skip the post-synthesis evaluation")
+    ap.add_argument("--no-gs", action="store_true", help="skip the Gauss-Seidel projection")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="launch tile 'waves_per_block,min_waves_per_simd' of the differentiable-step workload "
+                         "instead of tuning")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) three times, "
+                         "the reference that scales HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the grasp step shards by "
+              "candidates with no exchange inside a step, so one GPU's share is what it measures.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.headline_only:
+        args.no_cpu = args.no_plain = args.no_diff = args.no_serving = args.no_batched = True
+        args.no_mesh = args.no_eval = args.no_gs = True
+
+    import torch
+    from paper_2306_08132_amd import _lib
+    from paper_2306_08132_amd import synth as S
+    from paper_2306_08132_amd.api import Context
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from __graft_entry__ import build
+        build()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    ctx = Context(0, arena_bytes=24 << 30)
+
+    # ---- the headline: the large workload ----
+    L, (hL, sdL) = large_headline(ctx, S, args)
+    value = L["evals"] * args.steps / L["wall_s"]
+    launch_s = L["launch_ms"] * 1e-3
+    sbytes = survey_bytes(L["B"], L["Nc"], L["K"], L["n_dof"], L["grid"].n)
+    achieved = sbytes / launch_s / 1e9
+    cbytes = algorithmic_bytes(L["B"], L["Nc"], L["K"], L["n_dof"], L["grid"].n, L["live"])
+    cf = counter_fractions("k_step", "large-k16", launch_s)
+    bound = "hbm" if (cf is None or cf["dram_frac"] >= cf["valu_busy_frac"]) else "alu"
+    roofline = {"bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": cf["traffic_bytes_per_launch"] if cf else None,
+                "kernel": "k_step<K=16> (fused, pose checkpoints every 4)", "avg_launch_ms": L["launch_ms"],
+                "algorithmic_bytes_per_launch": sbytes,
+                "accounting": "64 B per contact evaluation (8 FP32 corners in the forward and in the backward) "
+                              "+ 24 B per (candidate, contact) + 28 B per (candidate, DOF) + the grid once",
+                "culled_accounting_bytes_per_launch": cbytes,
+                "culled_accounting_frac": cbytes / launch_s / (HBM_PEAK_GBS * 1e9),
+                "forward_live_fraction": L["live"],
+                "counters": cf,
+                "tile": {"waves_per_block": L["tile"][0], "min_waves_per_simd": L["tile"][1]},
+                "checkpoint_every_iteration_ms": L["ckpt1_launch_ms"]}
     cpu = None
     if not args.no_cpu:
-        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(hand, grid, q0, {"K": K, "r_dil": r0})
-        cpu["evaluation"] = cpu_eval_baseline(hand, grid, q0, S)
-        cpu["gauss_seidel"] = cpu_gs_baseline(hand, grid, q0, r0)
+        print("bench: oracle CPU baseline (large workload)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(L["hand"], L["grid"], L["q0"], {"K": 16, "r_dil": 0.01})
+        cpu["host"] = host_cpu()
 
+    # ---- the other workloads ----
+    diff = None
+    if not args.no_diff:
+        diff, (hand2, grid2, q2, h2, sd2, loss2, avg2) = diff_run(ctx, S, args)
+    batched = None if args.no_batched else batched_run(ctx, S, args)
+    serving = None if args.no_serving else serving_run(ctx, S, args)
+    mesh = None if args.no_mesh else mesh_run(ctx, S, args)
+    evaluation = gauss_seidel = None
+    if diff is not None:
+        evaluation = None if args.no_eval else eval_run(ctx, S, hand2, grid2, q2, h2, sd2, loss2, args)
+        gauss_seidel = None if args.no_gs else gs_run(ctx, S, hand2, q2, h2, sd2, 0.01, avg2, args)
+    if cpu is not None:
+        print("bench: oracle CPU matrix", file=sys.stderr, flush=True)
+        work = {"large": (L["hand"], L["grid"], L["q0"], {"K": 16, "r_dil": 0.01})}
+        h1, g1, q1 = S.config_workload("tiny")
+        work["tiny"] = (h1, g1, q1, {"K": 1, "r_dil": 0.01})
+        if diff is not None:
+            work["diff-step"] = (hand2, grid2, q2, {"K": 1, "r_dil": 0.01})
+            hb = S.make_hand(5, 4, 4096, seed=2)
+            gb = S.make_grid(S.make_object("mixed", seed=400, n_range=(3, 8)), 128, device="cuda:0")
+            qb = S.make_candidates(hb, 64, seed=500, shell_radius=gb.bound_radius + 0.06)
+            work["batched-job"] = (hb, gb, qb, {"K": 1, "r_dil": 0.01})
+        cpu["matrix"] = cpu_matrix(work)
+        if diff is not None:
+            cpu["evaluation"] = cpu_eval_baseline(hand2, grid2, q2, S)
+            cpu["gauss_seidel"] = cpu_gs_baseline(hand2, grid2, q2, 0.01)
+
+    hand = L["hand"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -570,25 +829,22 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": L["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "hand": "4 fingers x 4 joints, 22 DOF", "contacts": Nc,
-                   "sdf": f"union of {len(grid.prims)} ellipsoids, {grid.n}^3 FP32", "candidates": B,
-                   "tests_per_candidate": M_SIMS, "iterations": K, "contact_evals_per_step": evals,
-                   "step": "fused forward + adjoint + Adam, one launch"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step<K=1> (fused)", "avg_launch_ms": avg_ms,
-                     "tile": {"waves_per_block": tile[0], "min_waves_per_simd": tile[1]},
-                     "algorithmic_bytes_per_launch": abytes, "forward_live_fraction": live},
-        "plain": plain,
-        "serving": serving,
+        "config": {"workload": "large", "hand": "5 fingers x 4 joints, 26 DOF", "contacts": L["Nc"],
+                   "sdf": f"union of {len(L['grid'].prims)} ellipsoids/boxes, {L['grid'].n}^3 FP32",
+                   "candidates": L["B"], "tests_per_candidate": M_SIMS, "iterations": L["K"],
+                   "checkpoint_every": 4, "contact_evals_per_step": L["evals"],
+                   "schedule": L["schedule"],
+                   "step": "fused forward + adjoint (segments recomputed) + Adam, one launch"},
+        "roofline": roofline,
+        "diff_step": diff,
         "batched": batched,
-        "large": large,
+        "serving": serving,
         "mesh": mesh,
         "evaluation": evaluation,
         "gauss_seidel": gauss_seidel,

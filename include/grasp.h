@@ -265,6 +265,14 @@ typedef struct {
                         gradient is single-precision rounding noise) */
   int32_t mode;      /* GRASP_MODE_*: how grasp_step_fwd/bwd share state */
   int32_t projection;/* GRASP_PROJECTION_*: how the constraint corrections combine */
+  float mu;          /* Coulomb friction coefficient, >= 0 (0: frictionless). The paper's projection
+                        includes friction (Sec. III-C) by a cited model; read as positional friction:
+                        each active contact's tangential displacement over the step (of the object's
+                        point at the contact, dp_t = dp - (dp . n) n, n = g / |g|) is removed up to
+                        mu C, wholly while |dp_t| <= mu C (static), by mu C beyond (kinetic), as the
+                        Eq. (1) correction of a positional constraint along dp_t / |dp_t|, averaged
+                        with the normal corrections. mu > 0 needs K = 1 and the averaged projection
+                        (EINVAL otherwise); the plain form refuses it. */
 } grasp_step_params;
 
 /* Projection of the contact constraints (Sec. III-C). AVERAGED (default): every
@@ -288,7 +296,7 @@ enum {
 };
 
 /* Fills p with the defaults above (dt 1e-3, v0 1, K 1, ckpt 1, omega 1, r_dil 0,
- * alpha 0.1, weights 1 / 1e4 / 1e-2 / 1, w_min 1e-8, AUTO). */
+ * alpha 0.1, weights 1 / 1e4 / 1e-2 / 1, w_min 1e-8, AUTO, averaged, mu 0). */
 void grasp_default_params(grasp_step_params* p);
 
 /* Host out: workspace bytes grasp_step_fwd/bwd need for B candidates in SAVE

@@ -52,7 +52,7 @@ class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("v0", C.c_double), ("K", C.c_int), ("omega", C.c_double),
                 ("r_dil", C.c_double), ("alpha_leak", C.c_double), ("w_stable", C.c_double),
                 ("w_pen", C.c_double), ("w_range", C.c_double), ("w_limit", C.c_double),
-                ("w_min", C.c_double), ("projection", C.c_int)]
+                ("w_min", C.c_double), ("projection", C.c_int), ("mu", C.c_double)]
 
 
 @dataclasses.dataclass
@@ -70,10 +70,12 @@ class Params:
     w_limit: float = 1.0
     w_min: float = 1e-8
     projection: int = 0  # 0 averaged corrections, 1 Gauss-Seidel sweep
+    mu: float = 0.0      # Coulomb friction coefficient (0: frictionless)
 
     def _c(self):
         return _Params(self.dt, self.v0, self.K, self.omega, self.r_dil, self.alpha_leak,
-                       self.w_stable, self.w_pen, self.w_range, self.w_limit, self.w_min, int(self.projection))
+                       self.w_stable, self.w_pen, self.w_range, self.w_limit, self.w_min, int(self.projection),
+                       float(self.mu))
 
 
 _lib = None
@@ -137,6 +139,8 @@ def lib():
         L.oracle_inertia_over_mass.restype = C.c_double
         L.oracle_step.argtypes = [hp, op, pp, C.c_int, dp, dp, dp, dp, dp, C.c_int]
         L.oracle_trace.argtypes = [hp, op, pp, dp, dp, dp, dp]
+        L.oracle_step_ex.argtypes = [hp, op, pp, C.c_int, dp, dp, dp, dp, C.c_int, ip, C.POINTER(_Flip),
+                                     C.c_double, C.c_double, C.c_int, C.POINTER(_Amb), ip, C.c_int]
         L.oracle_fd_grad.argtypes = [hp, op, pp, C.c_int, dp, C.c_double, dp, ip, C.c_int]
         L.oracle_adam.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_double]
@@ -257,6 +261,46 @@ def step(hand: Hand, obj: Obj, prm: Params, q, grad: bool = True, margins: bool 
         out["min_abs_d"] = mg[:, 0]
         out["min_face"] = mg[:, 1]
         out["min_face_all"] = mg[:, 2]
+    return out
+
+
+class _Flip(C.Structure):
+    _fields_ = [("m", C.c_int), ("k", C.c_int), ("i", C.c_int), ("what", C.c_int)]
+
+
+class _Amb(C.Structure):
+    _fields_ = [("m", C.c_int), ("k", C.c_int), ("i", C.c_int), ("what", C.c_int), ("margin", C.c_double),
+                ("penetrating", C.c_int)]
+
+
+def step_ex(hand: Hand, obj: Obj, prm: Params, q, flips=(), kink_d: float = -1.0, kink_face: float = -1.0,
+            max_amb: int = 0, grad: bool = True, threads: int = 0):
+    """oracle_step with readings of ambiguous samples and their report.
+    flips: (b, m, k, i, what) tuples, what 0 = the other side of d = 0, 1..3 =
+    the other cell along x, y, z. With max_amb > 0, "amb" lists per candidate
+    the first max_amb samples (m, k, i, what, margin, penetrating) within
+    kink_d of d = 0 or kink_face cell units of a cell face, and "n_amb" their
+    full counts."""
+    q = _d(q).reshape(-1, hand.n_dof)
+    B = q.shape[0]
+    loss = np.zeros(B)
+    terms = np.zeros((B, 4))
+    g = np.zeros((B, hand.n_dof)) if grad else None
+    nf = len(flips)
+    fb = np.array([f[0] for f in flips], np.int32) if nf else None
+    farr = (_Flip * max(nf, 1))(*[_Flip(int(f[1]), int(f[2]), int(f[3]), int(f[4])) for f in flips])
+    amb = (_Amb * max(B * max_amb, 1))()
+    namb = np.zeros(B, np.int32)
+    pc = prm._c()
+    _check(lib().oracle_step_ex(C.byref(hand.c), C.byref(obj.c), C.byref(pc), B, _ptr(q), _ptr(loss), _ptr(terms),
+                                _ptr(g), nf, _ptr(fb, C.c_int), farr, float(kink_d), float(kink_face), int(max_amb),
+                                amb if max_amb > 0 else None, _ptr(namb, C.c_int), threads), "oracle_step_ex")
+    out = {"loss": loss, "terms": terms, "n_amb": namb}
+    if grad:
+        out["grad"] = g
+    if max_amb > 0:
+        out["amb"] = [[(a.m, a.k, a.i, a.what, a.margin, a.penetrating)
+                       for a in amb[b * max_amb:b * max_amb + min(int(namb[b]), max_amb)]] for b in range(B)]
     return out
 
 

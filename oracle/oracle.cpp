@@ -205,6 +205,11 @@ struct SampleInfo {
   int cell[3] = {0, 0, 0};
   int clamped[3] = {0, 0, 0};
   double face_margin = 1e30;
+  double axis_margin[3] = {1e30, 1e30, 1e30};  // per axis: distance (cell units) to the nearest face
+  // input: bit a set = take the cell on the other side of the face nearest
+  // to the sample along axis a (both cells meet there: the value is the same,
+  // the gradient is the other cell's)
+  int flip_axes = 0;
 };
 
 // Grid: trilinear interpolation of a vertex-centred grid (Sec. III-A). Per
@@ -227,10 +232,17 @@ void sample_grid(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* inf
     else if (val(u) > N - 1.0) { ub = konst<S>(N - 1.0); cl[a] = true; }
     else { ub = u; cl[a] = false; }
     c[a] = std::min(static_cast<int>(std::floor(val(ub))), N - 2);
+    double k = std::min(std::max(std::round(val(u)), 0.0), N - 1.0);
+    if (info && (info->flip_axes >> a & 1)) {
+      // the other cell at the nearest interior face k
+      const int kf = static_cast<int>(k);
+      if (c[a] == kf && kf - 1 >= 0) c[a] = kf - 1;
+      else if (c[a] == kf - 1 && kf <= N - 2) c[a] = kf;
+    }
     f[a] = ub - static_cast<double>(c[a]);
     e[a] = cl[a] ? (u - ub) * o.h : konst<S>(0.0);
-    double k = std::min(std::max(std::round(val(u)), 0.0), N - 1.0);
     margin = std::min(margin, std::fabs(val(u) - k));
+    if (info) info->axis_margin[a] = std::fabs(val(u) - k);
   }
   auto V = [&](int i, int j, int k) -> double {
     return static_cast<double>(o.values[(static_cast<int64_t>(c[2] + k) * N + (c[1] + j)) * N + (c[0] + i)]);
@@ -384,6 +396,29 @@ struct Trace {
   double min_face = 1e30;      // penetrating samples: their gradient sets a correction
   double min_face_all = 1e30;  // every sample with w > w_min: the leak reaches its gradient
   uint64_t signature = 1469598103934665603ull;  // FNV-1a over discrete decisions
+  // readings of ambiguous samples to take (flips of this candidate) and the
+  // report of the samples that are ambiguous at FP32 resolution
+  const oflip* flips = nullptr;
+  int n_flips = 0;
+  double kink_d = -1.0, kink_face = -1.0;
+  std::vector<oamb>* amb = nullptr;
+  // flips of sample (m, k, i): bit 0 = the other side of d = 0, bit 1 + a =
+  // the other cell along axis a
+  int flips_of(int m, int k, int i) const {
+    int f = 0;
+    for (int j = 0; j < n_flips; ++j)
+      if (flips[j].m == m && flips[j].k == k && flips[j].i == i) f |= 1 << flips[j].what;
+    return f;
+  }
+  void report_friction(int m, int k, int i, double gap) {
+    if (amb && std::fabs(gap) < kink_d) amb->push_back(oamb{m, k, i, 4, std::fabs(gap), 1});
+  }
+  void report(int m, int k, int i, double d, const SampleInfo& info, bool pen) {
+    if (!amb) return;
+    if (std::fabs(d) < kink_d) amb->push_back(oamb{m, k, i, 0, std::fabs(d), pen ? 1 : 0});
+    for (int a = 0; a < 3; ++a)
+      if (info.axis_margin[a] < kink_face) amb->push_back(oamb{m, k, i, 1 + a, info.axis_margin[a], pen ? 1 : 0});
+  }
   void mix(uint64_t x) {
     for (int i = 0; i < 8; ++i) { signature ^= (x >> (8 * i)) & 0xff; signature *= 1099511628211ull; }
   }
@@ -404,13 +439,60 @@ template <int N> Dual<N> hand_part(const Dual<N>& d, const Dual<N>* g, const Dua
 // for hand points that do not touch the object; along the object's pose
 // from one projection iteration to the next the derivative stays exact
 // (with one iteration the pose carries no tangent and the two coincide).
-template <class S> S leaky_penetration(const S& d, const S& d_hand, double alpha) {
-  if (val(d) < 0.0) return -d;
-  S c = -alpha * d_hand;
-  c.v = 0.0;
+// pen: which side of d = 0 the sample is taken on (d < 0, unless a flip
+// takes the other reading of a sample within rounding of the surface); it
+// selects the derivative rule, while the value stays max(0, -d).
+template <class S> S leaky_penetration(const S& d, const S& d_hand, double alpha, bool pen) {
+  S c = pen ? -d : -alpha * d_hand;
+  c.v = std::max(0.0, -val(d));
   return c;
 }
-template <> double leaky_penetration<double>(const double& d, const double&, double) { return d < 0.0 ? -d : 0.0; }
+template <> double leaky_penetration<double>(const double& d, const double&, double, bool) {
+  return std::max(0.0, -d);
+}
+
+// Coulomb friction of one active contact (Sec. III-C cites a friction model
+// without stating it; read here as positional friction in position-based
+// dynamics). The object's material point at the contact, at r in the object
+// frame, started the step at r (rest pose) and is now at the hand point p:
+// it moved by dp = p - r. Its tangential part dp_t = dp - (dp . n) n, with
+// n = g / |g| the contact normal, is removed up to the Coulomb bound mu C:
+// wholly while |dp_t| <= mu C (static friction), by mu C along it otherwise
+// (kinetic), as the Eq. (1) correction of a positional constraint along
+// t = dp_t / |dp_t|: lambda_t = -min(|dp_t|, mu C) / w_t with
+// w_t = |t|^2 + |a x t|^2 / (I/m). Adds (lambda_t t, lambda_t a x t) to the
+// sums of corrections.
+template <class S>
+void add_friction(const S p[3], const S r[3], const S a[3], const S g[3], const S& C, double mu, double Im,
+                  S Wl[3], S Wa[3], Trace* tr = nullptr, int m = 0, int k = 0, int i = 0) {
+  const S gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  if (!(val(gg) > 0.0)) return;
+  const S ng = sqrt_(gg);
+  S nh[3], dp[3], dpt[3];
+  for (int j = 0; j < 3; ++j) { nh[j] = g[j] / ng; dp[j] = p[j] - r[j]; }
+  const S sn = dp[0] * nh[0] + dp[1] * nh[1] + dp[2] * nh[2];
+  for (int j = 0; j < 3; ++j) dpt[j] = dp[j] - sn * nh[j];
+  const S tl2 = dpt[0] * dpt[0] + dpt[1] * dpt[1] + dpt[2] * dpt[2];
+  if (!(val(tl2) > 0.0)) return;
+  const S tl = sqrt_(tl2);
+  S th[3];
+  for (int j = 0; j < 3; ++j) th[j] = dpt[j] / tl;
+  S ut[3];
+  ut[0] = a[1] * th[2] - a[2] * th[1];
+  ut[1] = a[2] * th[0] - a[0] * th[2];
+  ut[2] = a[0] * th[1] - a[1] * th[0];
+  const S wt = (th[0] * th[0] + th[1] * th[1] + th[2] * th[2]) + (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]) / Im;
+  // static while the displacement is within the cone, kinetic beyond it
+  // (a flip takes the other side of a switch within rounding)
+  bool stat = val(tl) <= mu * val(C);
+  if (tr) {
+    if (tr->flips_of(m, k, i) & (1 << 4)) stat = !stat;
+    tr->report_friction(m, k, i, val(tl) - mu * val(C));
+  }
+  const S delta = stat ? tl : mu * C;
+  const S lt = -delta / wt;
+  for (int j = 0; j < 3; ++j) { Wl[j] += lt * th[j]; Wa[j] += lt * ut[j]; }
+}
 
 template <class S>
 void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& P, const S* q,
@@ -427,12 +509,18 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
 
   // 2. penetration of the hand at the object's rest pose, with dilation:
   //    C0_i = max(0, -(phi(p_i) - r)); L_pen = 1/2 sum C0_i^2
+  //    (the same samples as the rest test's first iteration, m = 6, k = 0,
+  //    so a flip of one of those applies here too)
   S Lpen = konst<S>(0.0);
   for (int i = 0; i < Nc; ++i) {
     S phi, n[3];
-    sample_object(o, &p[3 * i], phi, n, nullptr);
+    SampleInfo info;
+    const int fl = tr ? tr->flips_of(kSims - 1, 0, i) : 0;
+    info.flip_axes = fl >> 1;
+    sample_object(o, &p[3 * i], phi, n, &info);
     S d = phi - P.r_dil;
-    if (val(d) < 0.0) Lpen += 0.5 * (d * d);
+    const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
+    if (pen) Lpen += 0.5 * (d * d);
   }
 
   // 3. M velocity-test simulations (Sec. IV-A), each one PBD step (Sec. III-C)
@@ -465,11 +553,14 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           for (int j = 0; j < 3; ++j) r[j] = R[j] * a[0] + R[3 + j] * a[1] + R[6 + j] * a[2];
           S phi, nrm[3];
           SampleInfo info;
+          const int fl = tr ? tr->flips_of(m, k, i) : 0;
+          info.flip_axes = fl >> 1;
           sample_object(o, r, phi, nrm, &info);
           S d = phi - P.r_dil;
+          const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
           S g[3], u[3];
           for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-          S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak);
+          S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
           u[0] = a[1] * g[2] - a[2] * g[1];
           u[1] = a[2] * g[0] - a[0] * g[2];
           u[2] = a[0] * g[1] - a[1] * g[0];
@@ -478,9 +569,13 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           const bool active = val(w) > P.w_min;
           if (active) {
             lam = -C / w;
+            S Wl[3] = {lam * g[0], lam * g[1], lam * g[2]};
+            S Wa[3] = {lam * u[0], lam * u[1], lam * u[2]};
+            // friction from the same sample, added to this constraint's update
+            if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, Wl, Wa, tr, m, k, i);
             for (int j = 0; j < 3; ++j) {
-              x[j] = x[j] + P.omega * (lam * g[j]);
-              th[j] = th[j] + (P.omega / Im) * (lam * u[j]);
+              x[j] = x[j] + P.omega * Wl[j];
+              th[j] = th[j] + (P.omega / Im) * Wa[j];
             }
           }
           if (tr) {
@@ -492,6 +587,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
             if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
             if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
             if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
+            if (active) tr->report(m, k, i, val(d), info, pen);
             tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                     (static_cast<uint64_t>(info.cell[2]) << 32) |
                     (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
@@ -512,13 +608,16 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         for (int j = 0; j < 3; ++j) r[j] = R[j] * a[0] + R[3 + j] * a[1] + R[6 + j] * a[2];
         S phi, nrm[3];
         SampleInfo info;
+        const int fl = tr ? tr->flips_of(m, k, i) : 0;
+        info.flip_axes = fl >> 1;
         sample_object(o, r, phi, nrm, &info);
         // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
         S d = phi - P.r_dil;
+        const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
         // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
         S g[3], u[3];
         for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-        S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak);
+        S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
         u[0] = a[1] * g[2] - a[2] * g[1];
         u[1] = a[2] * g[0] - a[0] * g[2];
         u[2] = a[0] * g[1] - a[1] * g[0];
@@ -530,7 +629,8 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         if (active) {
           lam = -C / w;
           for (int j = 0; j < 3; ++j) { Wl[j] += lam * g[j]; Wa[j] += lam * u[j]; }
-          if (val(d) < 0.0) ++n_active;
+          if (pen) ++n_active;
+          if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, Wl, Wa, tr, m, k, i);
         }
         if (tr) {
           if (tr->samples) {
@@ -541,6 +641,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
           if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
           if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
+          if (active) tr->report(m, k, i, val(d), info, pen);
           tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                   (static_cast<uint64_t>(info.cell[2]) << 32) |
                   (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
@@ -606,13 +707,14 @@ bool valid_obj(const oobject* o) {
 
 template <int N>
 void step_dual(const ohand& h, const oobject& o, double Im, const oparams& P, const double* q,
-               double* loss, double* terms, double* grad, double* margins) {
+               double* loss, double* terms, double* grad, double* margins, Trace* ext = nullptr) {
   const int nd = 6 + h.n_links - 1;
   std::vector<Dual<N>> qd(nd);
   for (int j = 0; j < nd; ++j) { qd[j] = Dual<N>(q[j]); qd[j].d[j] = 1.0; }
   Dual<N> L, t4[4];
-  Trace tr;
-  candidate_step(h, o, Im, P, qd.data(), L, t4, margins ? &tr : nullptr);
+  Trace own;
+  Trace& tr = ext ? *ext : own;
+  candidate_step(h, o, Im, P, qd.data(), L, t4, (margins || ext) ? &tr : nullptr);
   *loss = L.v;
   if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i].v;
   for (int j = 0; j < nd; ++j) grad[j] = L.d[j];
@@ -620,22 +722,23 @@ void step_dual(const ohand& h, const oobject& o, double Im, const oparams& P, co
 }
 
 void step_one(const ohand& h, const oobject& o, double Im, const oparams& P, const double* q,
-              double* loss, double* terms, double* grad, double* margins) {
+              double* loss, double* terms, double* grad, double* margins, Trace* ext = nullptr) {
   const int nd = 6 + h.n_links - 1;
   if (!grad) {
     double L, t4[4];
-    Trace tr;
-    candidate_step(h, o, Im, P, q, L, t4, margins ? &tr : nullptr);
+    Trace own;
+    Trace& tr = ext ? *ext : own;
+    candidate_step(h, o, Im, P, q, L, t4, (margins || ext) ? &tr : nullptr);
     *loss = L;
     if (terms) for (int i = 0; i < 4; ++i) terms[i] = t4[i];
     if (margins) { margins[0] = tr.min_abs_d; margins[1] = tr.min_face; margins[2] = tr.min_face_all; }
     return;
   }
-  if (nd <= 8) step_dual<8>(h, o, Im, P, q, loss, terms, grad, margins);
-  else if (nd <= 16) step_dual<16>(h, o, Im, P, q, loss, terms, grad, margins);
-  else if (nd <= 24) step_dual<24>(h, o, Im, P, q, loss, terms, grad, margins);
-  else if (nd <= 32) step_dual<32>(h, o, Im, P, q, loss, terms, grad, margins);
-  else step_dual<40>(h, o, Im, P, q, loss, terms, grad, margins);
+  if (nd <= 8) step_dual<8>(h, o, Im, P, q, loss, terms, grad, margins, ext);
+  else if (nd <= 16) step_dual<16>(h, o, Im, P, q, loss, terms, grad, margins, ext);
+  else if (nd <= 24) step_dual<24>(h, o, Im, P, q, loss, terms, grad, margins, ext);
+  else if (nd <= 32) step_dual<32>(h, o, Im, P, q, loss, terms, grad, margins, ext);
+  else step_dual<40>(h, o, Im, P, q, loss, terms, grad, margins, ext);
 }
 
 int set_threads(int n) {
@@ -711,6 +814,41 @@ int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B
   for (int b = 0; b < B; ++b)
     step_one(*hand, *obj, Im, *prm, q + static_cast<size_t>(b) * nd, loss + b, terms ? terms + 4 * b : nullptr,
              grad ? grad + static_cast<size_t>(b) * nd : nullptr, margins ? margins + 3 * b : nullptr);
+  return 0;
+}
+
+int oracle_step_ex(const ohand* hand, const oobject* obj, const oparams* prm, int B, const double* q,
+                   double* loss, double* terms, double* grad, int n_flips, const int* flip_b, const oflip* flips,
+                   double kink_d, double kink_face, int max_amb, oamb* amb, int* n_amb, int n_threads) {
+  if (!valid_hand(hand) || !valid_obj(obj) || !prm || B < 0 || (B > 0 && (!q || !loss)) || prm->K < 1 ||
+      n_flips < 0 || (n_flips > 0 && (!flip_b || !flips)) || max_amb < 0 || (max_amb > 0 && amb && !n_amb))
+    return -1;
+  for (int j = 0; j < n_flips; ++j)
+    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 4) return -1;
+  const double Im = inertia_over_mass(*obj);
+  if (!(Im > 0.0)) return -2;
+  const int nd = 6 + hand->n_links - 1;
+  // the flips of each candidate, in input order
+  std::vector<std::vector<oflip>> per(B);
+  for (int j = 0; j < n_flips; ++j) per[flip_b[j]].push_back(flips[j]);
+  const int nt = set_threads(n_threads);
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int b = 0; b < B; ++b) {
+    std::vector<oamb> found;
+    Trace tr;
+    tr.flips = per[b].data();
+    tr.n_flips = static_cast<int>(per[b].size());
+    tr.kink_d = kink_d;
+    tr.kink_face = kink_face;
+    tr.amb = &found;
+    step_one(*hand, *obj, Im, *prm, q + static_cast<size_t>(b) * nd, loss + b, terms ? terms + 4 * b : nullptr,
+             grad ? grad + static_cast<size_t>(b) * nd : nullptr, nullptr, &tr);
+    if (n_amb) n_amb[b] = static_cast<int>(found.size());
+    if (amb)
+      for (int j = 0; j < std::min<int>(max_amb, static_cast<int>(found.size())); ++j)
+        amb[static_cast<size_t>(b) * max_amb + j] = found[j];
+  }
   return 0;
 }
 

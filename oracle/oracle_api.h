@@ -79,6 +79,9 @@ typedef struct {
                          constraints; 1: Gauss-Seidel, one constraint after another
                          in link-major order (stable by link), each at the pose the
                          previous ones left */
+  double mu;          /* Coulomb friction coefficient (0: frictionless): each
+                         active contact's tangential displacement over the step
+                         is removed up to mu C (static below, kinetic above) */
 } oparams;
 
 /* A closed triangle mesh with outward (counter-clockwise) faces and unit
@@ -129,6 +132,39 @@ double oracle_inertia_over_mass(const oobject* obj);
 int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B,
                 const double* q, double* loss, double* terms, double* grad, double* margins,
                 int n_threads);
+
+/* A reading of one sample that FP32 arithmetic may take instead of FP64's:
+   sample (m, k, i) = velocity test m, projection iteration k, contact i. */
+typedef struct {
+  int m, k, i;
+  int what;  /* 0: the other side of d = 0 (counted active or not, and the
+                derivative rule of C = max(0, -d) that side takes; the value
+                stays max(0, -d)); 1, 2, 3: the cell on the other side of the
+                cell face nearest to the sample along x, y, z (the value is
+                continuous there, the gradient is the other cell's); 4: the
+                other side of the friction cone (static or kinetic friction)
+                for a contact whose slide |dp_t| lies within kink_d of mu C */
+} oflip;
+
+/* A sample with w > w_min within FP32 resolution of a decision: |d| below
+   kink_d (what 0), a coordinate within kink_face cell units of a cell face
+   (what 1 + axis), or a friction slide within kink_d of mu C (what 4);
+   margin = that distance; penetrating = the side of d = 0 the sample took. */
+typedef struct {
+  int m, k, i, what;
+  double margin;
+  int penetrating;
+} oamb;
+
+/* oracle_step with readings and a report of the ambiguous samples: the
+   n_flips flips apply to candidates flip_b[j]; for every candidate up to
+   max_amb ambiguous samples go to amb [B][max_amb] in the order the step
+   meets them, and n_amb [B] gets their full count. amb/n_amb may be NULL.
+   The flips of the rest test's first iteration (m = 6, k = 0) also apply to
+   the rest-pose samples of L_pen, which are the same points. */
+int oracle_step_ex(const ohand* hand, const oobject* obj, const oparams* prm, int B, const double* q,
+                   double* loss, double* terms, double* grad, int n_flips, const int* flip_b, const oflip* flips,
+                   double kink_d, double kink_face, int max_amb, oamb* amb, int* n_amb, int n_threads);
 
 /* One candidate in detail. poses [M][K+1][6] = (x, theta) before each
    iteration and after the last; samples [M][K][Nc][6] = (d, g, w, lambda) or NULL;

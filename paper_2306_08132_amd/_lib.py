@@ -70,7 +70,8 @@ class StepParamsC(C.Structure):
     _fields_ = [("dt", C.c_float), ("v0", C.c_float), ("K", C.c_int32), ("ckpt_every", C.c_int32),
                 ("omega", C.c_float), ("r_dil", C.c_float), ("alpha_leak", C.c_float),
                 ("w_stable", C.c_float), ("w_pen", C.c_float), ("w_range", C.c_float),
-                ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32), ("projection", C.c_int32)]
+                ("w_limit", C.c_float), ("w_min", C.c_float), ("mode", C.c_int32), ("projection", C.c_int32),
+                ("mu", C.c_float)]
 
 
 class BatchJobC(C.Structure):
@@ -116,11 +117,12 @@ class StepParams:
     w_min: float = 1e-8
     mode: int = MODE_AUTO
     projection: int = 0  # PROJECTION_AVERAGED or PROJECTION_GAUSS_SEIDEL
+    mu: float = 0.0      # Coulomb friction coefficient (0: frictionless)
 
     def c(self) -> StepParamsC:
         return StepParamsC(self.dt, self.v0, self.K, self.ckpt_every, self.omega, self.r_dil,
                            self.alpha_leak, self.w_stable, self.w_pen, self.w_range, self.w_limit,
-                           self.w_min, self.mode, self.projection)
+                           self.w_min, self.mode, self.projection, self.mu)
 
 
 # (name, restype, argtypes) of every exported entry point in include/grasp.h

@@ -131,11 +131,15 @@ class Context:
         self.lib.call("grasp_step_fused", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
                       _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
 
-    def plain_workspace(self, hand, sdf, prm: StepParams, B: int) -> torch.Tensor:
+    def plain_workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
         out = C.c_size_t()
         pc = prm.c()
         self.lib.call("grasp_plain_workspace_bytes", self.h, hand.id, sdf.id, C.byref(pc), B, C.byref(out))
-        return torch.empty(out.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return out.value
+
+    def plain_workspace(self, hand, sdf, prm: StepParams, B: int) -> torch.Tensor:
+        return torch.empty(self.plain_workspace_bytes(hand, sdf, prm, B), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
 
     def plain_step(self, hand, sdf, prm: StepParams, q, m, v, t: int, ws, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
                    loss=None, terms=None, stream=None):

@@ -70,6 +70,9 @@ grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
   if (p->mode < GRASP_MODE_AUTO || p->mode > GRASP_MODE_RECOMPUTE) return fail(GRASP_EINVAL, "bad mode");
   if (p->projection != GRASP_PROJECTION_AVERAGED && p->projection != GRASP_PROJECTION_GAUSS_SEIDEL)
     return fail(GRASP_EINVAL, "bad projection");
+  if (!finite(p->mu) || p->mu < 0.0f) return fail(GRASP_EINVAL, "friction coefficient mu must be finite and >= 0");
+  if (p->mu > 0.0f && (p->K != 1 || p->projection != GRASP_PROJECTION_AVERAGED))
+    return fail(GRASP_EINVAL, "friction (mu > 0) runs with one iteration (K = 1) of the averaged projection");
   // LDS of one wave must fit comfortably: K/ckpt + 1 + ckpt pose slots
   if (wave_lds_floats(p->K, p->ckpt_every) * sizeof(float) > 16 * 1024)
     return fail(GRASP_EINVAL, "K / ckpt_every too large for the pose checkpoint buffer");
@@ -84,6 +87,7 @@ grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
     out->w_range = p->w_range;
     out->w_limit = p->w_limit;
     out->w_min = p->w_min;
+    out->mu = p->mu;
     out->K = p->K;
     out->ckpt = p->ckpt_every;
   }
@@ -96,6 +100,7 @@ using namespace grasp;
 
 namespace {
 void load_tile_cache(grasp_ctx* ctx);
+
 
 #define GRASP_CHECK_CTX(ctx)                                                        \
   do {                                                                              \
@@ -174,6 +179,7 @@ void grasp_default_params(grasp_step_params* p) {
   p->w_min = 1e-8f;
   p->mode = GRASP_MODE_AUTO;
   p->projection = GRASP_PROJECTION_AVERAGED;
+  p->mu = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +783,7 @@ grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   grasp_status st = resolve(ctx, hand, sdf, p, B, &r);
   if (st != GRASP_OK) return st;
   if (r.prm.K != 1) return fail(GRASP_EINVAL, "the plain form runs one projection iteration (K = 1)");
+  if (r.prm.mu > 0.0f) return fail(GRASP_EINVAL, "the plain form has no friction (mu must be 0)");
   if (B > 0 && (!q || !m || !v || !loss || !ws)) return fail(GRASP_EINVAL, "q/m/v/loss/ws is NULL");
   st = check_adam(t, lr, b1, b2, eps);
   if (st != GRASP_OK) return st;

@@ -334,6 +334,40 @@ __device__ __forceinline__ V3 rot_vjp(const Rot& o, float sgn, V3 v, V3 yb) {
             c * ph.z + o.A * a.z + o.B * (pv * yb.z + v.z * py - 2.0f * ph.z * vy));
 }
 
+// Coulomb friction of an active contact (read as positional friction of
+// position-based dynamics): the object's material point at the contact moved
+// by dp over the step; its tangential part dp_t = dp - (dp . n) n, n = g/|g|,
+// is removed up to mu C, as the Eq. (1) correction of a positional
+// constraint along t = dp_t / |dp_t|: lambda_t = -min(|dp_t|, mu C) / w_t,
+// w_t = |t|^2 + |a x t|^2 / (I/m), correction lambda_t (t, a x t).
+struct Fric {
+  V3 nh;       // unit normal g / |g|
+  float ing;   // 1 / |g|
+  float sn;    // dp . n
+  V3 th;       // unit tangent of the slide
+  float itl;   // 1 / |dp_t|
+  float tl;    // |dp_t|
+  V3 ut;       // a x t
+  float wt;    // generalized inverse mass along t
+};
+
+// The friction direction of a sample with gradient g != 0 (every sample with
+// w > w_min has one); false when the slide is exactly normal (no tangent).
+__device__ __forceinline__ bool friction_dir(V3 g, V3 dp, V3 a, float inv_Im, Fric& f) {
+  f.ing = rsq(dot(g, g));
+  f.nh = f.ing * g;
+  f.sn = dot(dp, f.nh);
+  const V3 dpt = axpy(-f.sn, f.nh, dp);
+  const float tl2 = dot(dpt, dpt);
+  if (!(tl2 > 0.0f)) return false;
+  f.itl = rsq(tl2);
+  f.tl = tl2 * f.itl;
+  f.th = f.itl * dpt;
+  f.ut = cross(a, f.th);
+  f.wt = fmaf(dot(f.ut, f.ut), inv_Im, dot(f.th, f.th));
+  return true;
+}
+
 // Test point of velocity test m before any correction (a = p - dt v0 dir_m):
 // exactly one coordinate moves, so the other two (and their grid
 // coordinates) are shared by the tests of one contact.

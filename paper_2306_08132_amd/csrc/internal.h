@@ -75,6 +75,7 @@ constexpr int kLayoutZPairs = 1;
 // Device copy of the step parameters.
 struct StepConsts {
   float dt, v0, omega, r_dil, alpha, w_stable, w_pen, w_range, w_limit, w_min;
+  float mu;     // Coulomb friction coefficient (0: frictionless; one iteration only)
   int K;        // projection iterations
   int ckpt;     // pose checkpoint interval (1 = every iteration kept)
 };

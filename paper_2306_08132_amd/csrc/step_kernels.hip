@@ -148,6 +148,69 @@ __device__ __forceinline__ bool contact_clear(const SdfView& S, V3 p, float rd, 
   return fmaxf(fmaf(0.999999f, e, -1.000001f * dv), 0.0f) + (bm - rd) > 1e-6f;
 }
 
+// Coulomb friction of an active sample in the one-iteration pass (the
+// object at its predicted pose, unturned): the material point at the contact
+// moved by the test's prediction dp = -off. Adds lambda_t (t, a x t),
+// lambda_t = -min(|dp_t|, mu C) / w_t, to the lane's correction sums.
+__device__ __forceinline__ void add_friction(const Ctx& c, const LaneTest& lt, V3 a, V3 g, float d, bool on,
+                                             float inv_Im, float W[6]) {
+  if (!(c.P.mu > 0.0f) || !on) return;
+  Fric f;
+  if (!friction_dir(g, -1.0f * lt.off, a, inv_Im, f)) return;
+  const float mc = -c.P.mu * d;  // mu C, C = -d > 0
+  const float delta = f.tl <= mc ? f.tl : mc;
+  const float lam = -delta * rcp(f.wt);
+  W[0] = fmaf(lam, f.th.x, W[0]);
+  W[1] = fmaf(lam, f.th.y, W[1]);
+  W[2] = fmaf(lam, f.th.z, W[2]);
+  W[3] = fmaf(lam, f.ut.x, W[3]);
+  W[4] = fmaf(lam, f.ut.y, W[4]);
+  W[5] = fmaf(lam, f.ut.z, W[5]);
+}
+
+// Adjoint of add_friction for one sample (one iteration): from the test's
+// seeds (WlB, WaB), the contributions to d_bar, and, for a penetrating
+// sample, to the adjoints of the gradient g and of a. A non-penetrating
+// sample contributes through the leaky derivative of C only (its lambda_t is
+// 0): d_bar += alpha mu lb_t / w_t.
+__device__ __forceinline__ void friction_adjoint(const Ctx& c, const LaneTest& lt, V3 a, V3 g, float d, bool okw,
+                                                 bool pen, float inv_Im, V3 WlB, V3 WaB, float& dbar, V3& gbar,
+                                                 V3& abar) {
+  if (!(c.P.mu > 0.0f) || !okw) return;
+  Fric f;
+  const V3 dp = -1.0f * lt.off;
+  if (!friction_dir(g, dp, a, inv_Im, f)) return;
+  const float lbt = fmaf(WlB.x, f.th.x, fmaf(WlB.y, f.th.y, fmaf(WlB.z, f.th.z, dot(WaB, f.ut))));
+  const float iwt = rcp(f.wt);
+  const float mu = c.P.mu;
+  if (!pen) {
+    dbar = fmaf(c.P.alpha * mu * lbt, iwt, dbar);
+    return;
+  }
+  const float mc = -mu * d;
+  const bool stat = f.tl <= mc;
+  const float delta = stat ? f.tl : mc;
+  const float lam = -delta * iwt;
+  const float deltab = -lbt * iwt;
+  const float wtb2 = 2.0f * lbt * delta * iwt * iwt;  // 2 w_t_bar
+  // u_t = a x t; w_t = |t|^2 + |u_t|^2 / (I/m)
+  const V3 utb = axpy(lam, WaB, (wtb2 * inv_Im) * f.ut);
+  V3 thb = axpy(lam, WlB, wtb2 * f.th);
+  abar = abar + cross(f.th, utb);
+  thb = thb + cross(utb, a);
+  // delta: |dp_t| (static) or mu C = -mu d (kinetic)
+  const float tlb = stat ? deltab : 0.0f;
+  if (!stat) dbar = fmaf(-mu, deltab, dbar);
+  // t = dp_t / |dp_t|
+  const float tt = dot(f.th, thb);
+  const V3 dptb = axpy(tlb, f.th, f.itl * axpy(-tt, f.th, thb));
+  // dp_t = dp - (dp . n) n, n = g / |g|
+  const float snb = -dot(dptb, f.nh);
+  const V3 nhb = axpy(snb, dp, (-f.sn) * dptb);
+  const float nn = dot(f.nh, nhb);
+  gbar = gbar + f.ing * axpy(-nn, f.nh, nhb);
+}
+
 template <bool ROT, bool TRACE, int LAY>
 __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   const HandView& H = c.H;
@@ -204,6 +267,7 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
       W[3] = fmaf(lam, u.x, W[3]);
       W[4] = fmaf(lam, u.y, W[4]);
       W[5] = fmaf(lam, u.z, W[5]);
+      if constexpr (!ROT) add_friction(c, lt, a, gn, d, on, inv_Im, W);
       if constexpr (TRACE) {
         if (valid) {
           const int i = ch * kChunk + kGroup * g + lt.sub;
@@ -306,6 +370,7 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       W[3] = fmaf(lam, u.x, W[3]);
       W[4] = fmaf(lam, u.y, W[4]);
       W[5] = fmaf(lam, u.z, W[5]);
+      if constexpr (!ROT) add_friction(c, lt, a, gn_, d, on, inv_Im, W);
       if (gn < 0) break;
       g = gn;
       L = L_n;
@@ -411,13 +476,14 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
       dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
       V3 ab = v3(0.0f, 0.0f, 0.0f);
       V3 gbar = v3(0.0f, 0.0f, 0.0f);
+      if constexpr (!ROT) friction_adjoint(c, lt, a, gn, d, okw, pen, inv_Im, WlB, WaB, dbar, gbar, ab);
       V3 rbar = dbar * s.n;
       if (pen) {
         const float lam = d * iw;
         const float wbar2 = -2.0f * lb * lam * iw;
         const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
-        gbar = axpy(lam, WlB, wbar2 * gn);
-        ab = cross(gn, ubar);
+        gbar = gbar + axpy(lam, WlB, wbar2 * gn);
+        ab = ab + cross(gn, ubar);
         gbar = gbar + cross(ubar, a);
         rbar = rbar + hess_mul(S, s, ROT ? mul_t(o.R, gbar) : gbar);
       }

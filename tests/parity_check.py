@@ -1,0 +1,205 @@
+"""Comparison of per-candidate losses and gradients from the HIP path with the
+FP64 oracle, where FP32 rounding may decide a discrete choice differently.
+
+Two choices of the step depend on a comparison that FP32 can decide either
+way when the FP64 value lies within rounding of the threshold:
+  * the side of d = 0 (whether the constraint C = max(0, -d) is active, which
+    sets the averaging count and the derivative rule: full or leaky);
+  * the cell of a coordinate that lies on a cell face (the value is
+    continuous there, the trilinear gradient is the other cell's).
+Both readings of such a sample are correct FP32 results of the method. The
+oracle reports the samples within kink_d of d = 0 and within kink_face cell
+units of a face (oracle_step_ex); a candidate that misses the tolerance on
+the oracle's own reading is compared again with every combination of the
+other readings of its most ambiguous samples (nearest to the decision
+first). It passes if one combination meets the tolerance; it is set aside
+(reported, capped) only when it has more ambiguous units than are
+enumerated; otherwise it fails.
+
+FP32 error model behind the two bands:
+  * contact positions come out of a chain of at most 9 rigid transforms in
+    FP32; their error stays below 1e-5 of max(|p|, 1 cm) (the FK tolerance),
+    about 1e-7 m here, so d = phi - r moves by about the same: a sample with
+    |d| below KINK_D = 2.5e-7 m may land on either side;
+  * a grid coordinate u = (r - lo)/h in FP32 carries the position error over
+    h (1-2 mm): about 1e-4 cell units. KINK_FACE = 2e-4 cell units covers it.
+Face readings of a coordinate that the seven tests share (an axis the test
+does not move along, at the first iteration, where the object has not
+turned) are one decision in FP32 and are flipped together.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+import oracle as O
+
+KINK_D = 2.5e-7      # metres
+KINK_FACE = 2e-4     # cell units
+# tests that do not move along axis a (their first-iteration coordinate on
+# that axis is the hand point's own, bit for bit in FP32)
+SHARED = {1: (2, 3, 4, 5, 6), 2: (0, 1, 4, 5, 6), 3: (0, 1, 2, 3, 6)}
+
+
+def units_of(amb, shared=True):
+    """Independent FP32 decisions among a candidate's ambiguous samples, most
+    ambiguous first: (margin, [flip (m, k, i, what)]). shared: the averaged
+    projection, whose first iteration samples every test at the predicted,
+    unturned pose (in the Gauss-Seidel sweep each constraint sees the pose
+    the previous ones left, so no coordinate is shared)."""
+    units = {}
+    for (m, k, i, what, margin, _pen) in amb:
+        if shared and what in SHARED and k == 0 and m in SHARED[what]:
+            key = ("shared", i, what)
+            fl = [(mm, 0, i, what) for mm in SHARED[what]]
+        else:
+            key = (m, k, i, what)
+            fl = [(m, k, i, what)]
+        if key not in units or margin < units[key][0]:
+            units[key] = (margin, fl)
+    return sorted(units.values(), key=lambda u: u[0])
+
+
+def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floor=None, max_units=6,
+            gtol_per=None, kink_d=KINK_D, kink_face=KINK_FACE, shared=None, conditioning=False, cond_cap=1e-2,
+            label="", say=print):
+    """Checks every candidate; returns a report dict. gpu_grad may be None
+    (loss only). gtol_per: optional per-candidate gradient tolerance (must be
+    >= gtol). conditioning: a candidate whose gradient still misses the
+    tolerance under every reading is measured for the conditioning of the
+    FP64 gradient itself (how far it moves when q changes at FP32
+    resolution, `conditioning`); it passes (status 4) if its error is within
+    four times that movement and that is at most cond_cap, and it is set
+    aside as not determined at FP32 resolution (status 2) if the movement
+    alone exceeds cond_cap / 4 and covers the error."""
+    q = np.asarray(q, np.float64)
+    B = q.shape[0]
+    if shared is None:
+        shared = op.projection == 0
+    ref = O.step_ex(H, ob, op, q, kink_d=kink_d, kink_face=kink_face, max_amb=256, grad=gpu_grad is not None)
+    floor = loss_floor if loss_floor is not None else op.w_stable * op.v0
+    gt = np.full(B, gtol) if gtol_per is None else np.maximum(np.asarray(gtol_per, np.float64), gtol)
+
+    def errs(loss_ref, grad_ref, gl, gg):
+        le = abs(gl - loss_ref) / max(abs(loss_ref), floor)
+        if gg is None:
+            return le, 0.0
+        return le, np.abs(gg - grad_ref).max() / max(np.abs(grad_ref).max(), 1e-30)
+
+    status = np.zeros(B, np.int32)  # 0 direct, 1 resolved by a reading, 2 set aside, 3 failed, 4 conditioning
+    lerr = np.zeros(B)
+    gerr = np.zeros(B)
+    n_units = np.array([len(units_of(a, shared)) for a in ref["amb"]])
+    for b in range(B):
+        gg = None if gpu_grad is None else gpu_grad[b]
+        lerr[b], gerr[b] = errs(ref["loss"][b], None if gg is None else ref["grad"][b], gpu_loss[b], gg)
+    cond = np.zeros(B)
+    if conditioning and gpu_grad is not None:
+        # a gradient-only miss first meets the gradient's own sensitivity
+        idx = np.nonzero((lerr <= ltol) & (gerr > gt))[0]
+        if idx.size:
+            cond[idx] = conditioning_of(H, ob, op, q[idx])
+            for b in idx:
+                if gerr[b] <= 4.0 * cond[b] and 4.0 * cond[b] <= cond_cap:
+                    status[b] = 4
+    for b in range(B):
+        gg = None if gpu_grad is None else gpu_grad[b]
+        if status[b] == 4 or (lerr[b] <= ltol and gerr[b] <= gt[b]):
+            continue
+        units = units_of(ref["amb"][b], shared)
+        if not units:
+            status[b] = 3
+            continue
+        cand = units[:max_units]
+        say(f"  {label}: candidate {b} (loss rel err {lerr[b]:.2e}, grad rel err {gerr[b]:.2e}): trying the "
+            f"other readings of {len(cand)} of its {len(units)} ambiguous decisions")
+        subsets = [s for r in range(1, len(cand) + 1) for s in itertools.combinations(range(len(cand)), r)]
+        flips = [(row, *f) for row, s in enumerate(subsets) for u in s for f in cand[u][1]]
+        alt = O.step_ex(H, ob, op, np.repeat(q[b:b + 1], len(subsets), axis=0), flips=flips,
+                        grad=gpu_grad is not None)
+        best = None
+        for row in range(len(subsets)):
+            le, ge = errs(alt["loss"][row], None if gg is None else alt["grad"][row], gpu_loss[b], gg)
+            if le <= ltol and ge <= gt[b]:
+                best = (le, ge)
+                break
+        if best is not None:
+            status[b] = 1
+            lerr[b], gerr[b] = best
+        else:
+            status[b] = 2 if len(units) > max_units else 3
+    if conditioning and gpu_grad is not None:
+        # what is left with a matching loss: set aside where the FP64 gradient's
+        # own movement at FP32 resolution exceeds the cap and covers the error
+        for b in np.nonzero(((status == 2) | (status == 3)) & (lerr <= ltol))[0]:
+            if cond[b] == 0.0:
+                cond[b] = conditioning_of(H, ob, op, q[b:b + 1])[0]
+            if gerr[b] <= 4.0 * cond[b]:
+                status[b] = 2
+    rep = {"B": B, "direct": int((status == 0).sum()), "resolved": int((status == 1).sum()),
+           "conditioned": int((status == 4).sum()), "max_cond": float(cond.max(initial=0.0)),
+           "set_aside": int((status == 2).sum()), "failed": int((status == 3).sum()),
+           "max_lerr": float(lerr[(status <= 1) | (status == 4)].max(initial=0.0)),
+           "max_gerr": float(gerr[status <= 1].max(initial=0.0)),
+           "ambiguous": int((n_units > 0).sum()), "status": status, "lerr": lerr, "gerr": gerr, "ref": ref}
+    say(f"{label}: B={B} direct {rep['direct']}, resolved by an FP32 reading {rep['resolved']}, within the "
+        f"gradient's conditioning {rep['conditioned']} (largest {rep['max_cond']:.1e}), set aside "
+        f"{rep['set_aside']}, failed {rep['failed']} (candidates with ambiguous samples {rep['ambiguous']}); "
+        f"max loss rel err {rep['max_lerr']:.2e}, max grad rel err (direct, resolved) {rep['max_gerr']:.2e}")
+    return rep
+
+
+def assert_ok(rep, max_set_aside=0.01):
+    bad = np.nonzero(rep["status"] == 3)[0]
+    assert bad.size == 0, ("failed candidates", bad, rep["lerr"][bad], rep["gerr"][bad])
+    assert rep["set_aside"] <= max_set_aside * rep["B"], ("set aside", rep["set_aside"], rep["B"])
+
+
+def conditioning_of(H, ob, op, q, n=3, seed=1):
+    return conditioning(H, ob, op, q, n=n, seed=seed)
+
+
+def conditioning(H, ob, op, q, n=3, seed=1):
+    """How far the FP64 gradient moves, relative to its largest component,
+    when q changes at FP32 resolution (2^-24 relative): per candidate, the
+    largest of n perturbed evaluations."""
+    q = np.asarray(q, np.float64)
+    g0 = O.step(H, ob, op, q)["grad"]
+    scale = np.maximum(np.abs(g0).max(axis=1), 1e-30)
+    cond = np.zeros(q.shape[0])
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        qp = q * (1.0 + rng.normal(size=q.shape) * 6e-8)
+        gp = O.step(H, ob, op, qp)["grad"]
+        cond = np.maximum(cond, np.abs(gp - g0).max(axis=1) / scale)
+    return cond
+
+
+def near_tie_groups(loss, tol):
+    """Group ids of candidates whose sorted losses chain within tol (FP64
+    losses; ties by index as the stable sort takes them)."""
+    order = np.argsort(loss, kind="stable")
+    gid = np.zeros(len(loss), np.int64)
+    g = 0
+    for k in range(1, len(order)):
+        if not abs(loss[order[k]] - loss[order[k - 1]]) <= tol:
+            g += 1
+        gid[order[k]] = g
+    return order, gid
+
+
+def assert_rank_matches(rank_gpu, loss_oracle, rel=2e-4, label="", say=print):
+    """The GPU's ranking is the oracle's stable sort of its FP64 losses, up
+    to swaps inside groups of near-tied losses (|dL| <= rel * max |L|)."""
+    loss_oracle = np.asarray(loss_oracle, np.float64)
+    tol = rel * np.abs(loss_oracle).max()
+    order, gid = near_tie_groups(loss_oracle, tol)
+    rank_gpu = np.asarray(rank_gpu)
+    assert sorted(rank_gpu.tolist()) == list(range(len(loss_oracle)))
+    pos_group = gid[order]          # group of the k-th place in the oracle's order
+    got_group = gid[rank_gpu]       # group of the candidate the GPU put there
+    exact = int((rank_gpu == order).sum())
+    say(f"{label}: ranking of {len(order)}: {exact} places identical, "
+        f"{len(order) - exact} inside near-tie groups, {int(gid.max()) + 1} groups")
+    assert np.array_equal(pos_group, got_group), np.nonzero(pos_group != got_group)[0][:10]

@@ -1,0 +1,153 @@
+"""GPU parity of the Coulomb friction of the one-iteration step (Sec. III-C;
+read as positional friction: each active contact's tangential displacement
+over the step removed up to mu C) against the oracle's: loss and gradient of
+every candidate (tests/parity_check.py), on the small workload, ragged hands
+and a sample of the differentiable-step workload; the hand-written adjoint
+against central differences of the oracle loss; fused equals forward,
+backward and Adam; mu = 0 equals the frictionless step bit for bit; the
+batched launch with friction equals its single-job steps; refusals where it
+is not built (several iterations, Gauss-Seidel, the plain form)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import parity_check as P
+from paper_2306_08132_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2306_08132_amd.api import Context
+    c = Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def prm_pair(**kw):
+    from paper_2306_08132_amd.api import StepParams
+    sp = StepParams(**kw)
+    op = O.Params()
+    for k in vars(op):
+        v = getattr(sp, k)
+        setattr(op, k, float(np.float32(v)) if isinstance(v, float) else v)
+    return sp, op
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def split_step(ctx, h, sd, sp, q):
+    B = q.shape[0]
+    qd = dev(q)
+    loss = torch.empty(B, device=DEV)
+    ctx.step_fwd(h, sd, sp, qd, loss)
+    dq = torch.empty_like(qd)
+    ctx.step_bwd(h, sd, sp, qd, dq)
+    torch.cuda.synchronize()
+    return loss.cpu().numpy(), dq.cpu().numpy()
+
+
+@pytest.mark.parametrize("mu", [0.3, 1.0])
+def test_friction_parity_tiny(ctx, mu):
+    hand, grid, q = S.config_workload("tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    for kw in (dict(r_dil=0.005), dict(r_dil=0.0, alpha_leak=0.0)):
+        sp, op = prm_pair(mu=mu, **kw)
+        loss, dq = split_step(ctx, h, sd, sp, q)
+        rep = P.compare(loss, dq, O.Hand(hand.rounded()), O.Obj(grid), op, q.astype(np.float32).astype(np.float64),
+                        label=f"friction mu={mu} {kw}", say=say)
+        P.assert_ok(rep)
+    # friction changes the result
+    sp0, _ = prm_pair(r_dil=0.005)
+    l0, _ = split_step(ctx, h, sd, sp0, q)
+    sp1, _ = prm_pair(r_dil=0.005, mu=mu)
+    l1, _ = split_step(ctx, h, sd, sp1, q)
+    assert np.abs(l1 - l0).max() > 1e-3
+
+
+def test_friction_parity_ragged_and_diff_sample(ctx):
+    for F, J, n, N, B in [(3, 3, 65, 16, 5), (4, 4, 1000, 40, 9), (5, 4, 777, 33, 7)]:
+        hand = S.make_hand(F, J, n, seed=F + n)
+        grid = S.make_grid(S.make_object("ellipsoids", seed=n), N)
+        q = S.make_candidates(hand, B, seed=n, shell_radius=grid.bound_radius + 0.06)
+        h, sd = ctx.hand(hand), ctx.sdf(grid)
+        sp, op = prm_pair(r_dil=0.003, mu=0.5)
+        loss, dq = split_step(ctx, h, sd, sp, q)
+        rep = P.compare(loss, dq, O.Hand(hand.rounded()), O.Obj(grid), op, q.astype(np.float32).astype(np.float64),
+                        label=f"friction ragged {F}x{J} Nc={n}", say=say)
+        P.assert_ok(rep)
+    hand, grid, q = S.config_workload("diff")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.005, mu=0.5)
+    qd = dev(q)
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    loss = torch.empty(q.shape[0], device=DEV)
+    dq = torch.empty_like(qd)
+    ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(6).choice(q.shape[0], 32, replace=False)
+    rep = P.compare(loss.cpu().numpy()[idx], dq.cpu().numpy()[idx], O.Hand(hand.rounded()), O.Obj(grid), op,
+                    q[idx].astype(np.float32).astype(np.float64), label="friction diff full (32 sampled)", say=say)
+    P.assert_ok(rep)
+
+
+def test_friction_gradient_matches_finite_differences(ctx):
+    hand, grid, q = S.config_workload("tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(alpha_leak=0.0, r_dil=0.004, mu=0.6)
+    _, g = split_step(ctx, h, sd, sp, q[:8])
+    fd, ex = O.fd_grad(O.Hand(hand.rounded()), O.Obj(grid), op, q[:8].astype(np.float32).astype(np.float64), h=1e-6)
+    scale = np.abs(fd).max(axis=1, keepdims=True)
+    bad = (np.abs(g - fd) > 1e-3 * scale) & ~ex
+    say("friction fd excluded fraction", ex.mean())
+    assert ex.mean() < 0.5 and not bad.any()
+
+
+def test_friction_forms_agree(ctx):
+    """Fused = forward + backward + Adam; mu = 0 is the frictionless step; a
+    batched launch with friction equals the single-job fused steps."""
+    from paper_2306_08132_amd.api import Batch, BatchJob, StepParams
+    hand, grid, q = S.config_workload("tiny", B=300)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp = StepParams(r_dil=0.004, mu=0.5)
+    qf = dev(q)
+    mf, vf = torch.zeros_like(qf), torch.zeros_like(qf)
+    lf = torch.empty(q.shape[0], device=DEV)
+    dqf = torch.empty_like(qf)
+    ctx.step_fused(h, sd, sp, qf, mf, vf, 1, loss=lf, dq=dqf)
+    l2, g2 = split_step(ctx, h, sd, sp, q)
+    assert np.array_equal(lf.cpu().numpy(), l2) and np.array_equal(dqf.cpu().numpy(), g2)
+    la, ga = split_step(ctx, h, sd, StepParams(r_dil=0.004), q)
+    lb, gb = split_step(ctx, h, sd, StepParams(r_dil=0.004, mu=0.0), q)
+    assert np.array_equal(la, lb) and np.array_equal(ga, gb)
+    # batched: the job's first step equals the fused step at the schedule's first dilation
+    job = BatchJob(h, sd, StepParams(mu=0.5), dev(q), T=10, r0=0.004)
+    b = Batch(ctx, capacity=512, max_jobs=4, use_graph=False)
+    b.step([job])
+    torch.cuda.synchronize()
+    assert torch.equal(job.q, qf) and torch.equal(job.loss, lf)
+    b.close()
+
+
+def test_friction_refusals(ctx):
+    from paper_2306_08132_amd._lib import GraspError
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny", B=4)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    qd = dev(q)
+    loss = torch.empty(4, device=DEV)
+    for bad in (dict(mu=0.5, K=2), dict(mu=0.5, projection=1), dict(mu=-0.1), dict(mu=float("nan"))):
+        with pytest.raises(GraspError):
+            ctx.step_fwd(h, sd, StepParams(**bad), qd, loss)
+    with pytest.raises(GraspError, match="friction"):
+        ctx.plain_step(h, sd, StepParams(mu=0.5), qd, torch.zeros_like(qd), torch.zeros_like(qd), 1,
+                       torch.empty(1 << 20, dtype=torch.uint8, device=DEV), loss=loss)

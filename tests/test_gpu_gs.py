@@ -1,18 +1,19 @@
 """GPU parity of the Gauss-Seidel projection (Sec. III-C: the constraint
 updates applied one after another) against the oracle's literal sweep in the
 same link-major order, through the C ABI: losses within 1e-4, gradients within
-1e-3 per candidate. The sweep carries the pose from one constraint to the
+1e-3, every candidate. The sweep carries the pose from one constraint to the
 next, so FP32 and FP64 poses drift apart by a few 1e-8 m over a sweep; a
-constraint closer than 1e-6 m to d = 0 may then switch sides, and candidates
-holding one are reported and capped. Also: the fused step with Adam equals
-the forward, backward and Adam launches; the sweep differs from the averaged
-form; refusals of the forms it does not run in; 8193 contacts; K = 3; a
-teacher-forced 30-step trajectory."""
+constraint within 1e-6 m of d = 0 may take either side in FP32, and the check
+takes either reading (tests/parity_check.py). Also: the fused step with Adam
+equals the forward, backward and Adam launches; the sweep differs from the
+averaged form; refusals of the forms it does not run in (and of graph
+capture); 8193 contacts; K = 3; a teacher-forced 30-step trajectory."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
+import parity_check as P
 from paper_2306_08132_amd import synth as S
 
 pytestmark = pytest.mark.gpu
@@ -48,7 +49,10 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
 
 
-def compare_gs(ctx, hand, grid, q, label, max_flagged=0.2, layout=0, loss_all=False, min_unflagged=1, **kw):
+def compare_gs(ctx, hand, grid, q, label, layout=0, loss_only=False, max_units=6, conditioning=False, **kw):
+    """Split forward and backward at q against the oracle's sweep; every
+    candidate checked (tests/parity_check), with the band of FP32-ambiguous
+    constraints widened to KINK_GS for the pose drift along the sweep."""
     sp, op = prm_pair(projection=GS, **kw)
     h, sd = ctx.hand(hand), ctx.sdf(grid, layout=layout)
     B = q.shape[0]
@@ -61,24 +65,12 @@ def compare_gs(ctx, hand, grid, q, label, max_flagged=0.2, layout=0, loss_all=Fa
     torch.cuda.synchronize()
     loss, terms, dq = loss.cpu().numpy(), terms.cpu().numpy(), dq.cpu().numpy()
     q32 = q.astype(np.float32).astype(np.float64)
-    ref = O.step(O.Hand(hand.rounded()), O.Obj(grid), op, q32, grad=True, margins=True)
-    floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
-    lerr = np.abs(loss - ref["loss"]) / floor
-    gscale = np.abs(ref["grad"]).max(axis=1)
-    gerr = np.abs(dq - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30)
-    flagged = ref["min_abs_d"] < KINK_GS
-    say(f"{label}: B={B} loss rel err max(unflagged) {lerr[~flagged].max() if (~flagged).any() else 0:.2e}, "
-        f"grad rel err max(unflagged) {gerr[~flagged].max() if (~flagged).any() else 0:.2e}, "
-        f"median {np.median(gerr):.2e}, flagged {flagged.mean():.3f} "
-        f"(their loss errs {np.round(lerr[flagged], 5).tolist()[:8]})")
-    assert np.all(lerr[~flagged] <= 1e-4), (np.argmax(lerr), lerr.max())
-    if loss_all:
-        assert np.all(lerr <= 1e-4), (np.argmax(lerr), lerr.max())
-    assert np.all(gerr[~flagged] <= 1e-3), (np.nonzero(gerr > 1e-3)[0], gerr.max())
-    assert flagged.mean() <= max_flagged and (~flagged).sum() >= min_unflagged
+    rep = P.compare(loss, None if loss_only else dq, O.Hand(hand.rounded()), O.Obj(grid), op, q32,
+                    kink_d=KINK_GS, max_units=max_units, conditioning=conditioning, label=label, say=say)
+    P.assert_ok(rep)
     sd.unload()
     h.destroy()
-    return loss, dq, ref
+    return loss, dq, rep
 
 
 @pytest.mark.parametrize("layout", [1, 2])
@@ -89,15 +81,17 @@ def test_gs_step_parity_tiny(ctx, layout):
 
 
 def test_gs_step_parity_iterations(ctx):
-    """K = 3: three sweeps, each from the pose the last one left. A sweep
-    resolves each constraint it applies to d = 0 exactly, so the next sweep
-    decides those constraints' branch on rounding: the loss is continuous
-    there and must match for every candidate, but the gradient jumps between
-    the full and the leaky term (the leak reaches the hand point only), so it
-    is compared on the candidates with no constraint within 1e-6 m of d = 0."""
+    """K = 3: three sweeps, each from the pose the last one left. With omega =
+    1 a sweep leaves every constraint it applied at d = 0 up to rounding, so
+    the next sweep decides those constraints' derivative rule (full or
+    leaky) on rounding, for many constraints at once: the loss, continuous
+    there, is checked for every candidate; the gradient is checked with
+    under-relaxed sweeps (omega = 0.5), which leave each applied constraint
+    half resolved and clear of d = 0."""
     hand, grid, q = S.config_workload("tiny")
     for kw, label in ((dict(r_dil=0.005), "GS tiny K=3"), (dict(r_dil=0.0, alpha_leak=0.0), "GS tiny K=3 exact")):
-        compare_gs(ctx, hand, grid, q, label, max_flagged=1.0, loss_all=True, min_unflagged=4, K=3, **kw)
+        compare_gs(ctx, hand, grid, q, label + " (loss)", loss_only=True, K=3, **kw)
+        compare_gs(ctx, hand, grid, q, label + " omega=0.5", K=3, omega=0.5, max_units=8, conditioning=True, **kw)
 
 
 def test_gs_step_parity_ragged(ctx):
@@ -106,7 +100,7 @@ def test_gs_step_parity_ragged(ctx):
         hand = S.make_hand(F, J, n, seed=F + n)
         grid = S.make_grid(S.make_object("ellipsoids", seed=n), N)
         q = S.make_candidates(hand, B, seed=n, shell_radius=grid.bound_radius + 0.06)
-        compare_gs(ctx, hand, grid, q, f"GS ragged {F}x{J} Nc={n}", max_flagged=0.3, r_dil=0.003)
+        compare_gs(ctx, hand, grid, q, f"GS ragged {F}x{J} Nc={n}", r_dil=0.003)
 
 
 def test_gs_full_size_diff_sampled(ctx):
@@ -122,17 +116,12 @@ def test_gs_full_size_diff_sampled(ctx):
     ctx.step_fwd(h, sd, sp, qd, loss)
     ctx.step_bwd(h, sd, sp, qd, dq)
     torch.cuda.synchronize()
-    idx = np.random.default_rng(2).choice(B, 48, replace=False)
-    ref = O.step(O.Hand(hand.rounded()), O.Obj(grid), op, q[idx].astype(np.float32).astype(np.float64),
-                 grad=True, margins=True)
-    lerr = np.abs(loss.cpu().numpy()[idx] - ref["loss"]) / np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
-    gerr = np.abs(dq.cpu().numpy()[idx] - ref["grad"]).max(axis=1) / np.abs(ref["grad"]).max(axis=1)
-    flagged = ref["min_abs_d"] < KINK_GS
-    say(f"GS diff full (sampled): loss err {lerr[~flagged].max():.2e}, grad err {gerr[~flagged].max():.2e}, "
-        f"flagged {flagged.mean():.3f}")
-    assert np.all(lerr[~flagged] <= 1e-4) and np.all(gerr[~flagged] <= 1e-3)
-    assert flagged.mean() <= 0.3
     assert np.all(np.isfinite(loss.cpu().numpy()))
+    idx = np.random.default_rng(2).choice(B, 48, replace=False)
+    rep = P.compare(loss.cpu().numpy()[idx], dq.cpu().numpy()[idx], O.Hand(hand.rounded()), O.Obj(grid), op,
+                    q[idx].astype(np.float32).astype(np.float64), kink_d=KINK_GS, label="GS diff full (48 sampled)",
+                    say=say)
+    P.assert_ok(rep)
     sd.unload()
     h.destroy()
 
@@ -192,7 +181,7 @@ def test_gs_many_contacts(ctx):
     hand = S.make_hand(3, 3, 8193, seed=1)
     grid = S.make_grid(S.make_object("sphere", seed=1), 48)
     q = S.make_candidates(hand, 3, seed=5, shell_radius=grid.bound_radius + 0.06)
-    compare_gs(ctx, hand, grid, q, "GS 8193 contacts", max_flagged=0.34, r_dil=0.004)
+    compare_gs(ctx, hand, grid, q, "GS 8193 contacts", r_dil=0.004)
 
 
 def test_gs_two_streams_share_the_start_pose_table(ctx):
@@ -225,16 +214,11 @@ def test_gs_two_streams_share_the_start_pose_table(ctx):
 
 def test_gs_trajectory_teacher_forced(ctx):
     """30 fused Gauss-Seidel steps on the small workload along the dilation
-    schedule from 1 cm, each checked from the GPU's own state: the loss within
-    1e-4 and the gradient within 1e-3 of the oracle's sweep at that q, and the
-    Adam update within 1e-6 of its operands' magnitudes. Set aside, reported:
-    for the loss, candidates holding a constraint within 1e-6 m of d = 0 or a
-    penetrating sample within 1e-5 cell units of a cell face (FP32 may take
-    the other side or the neighbouring cell's gradient); for the gradient,
-    also any sample that close to a face, since the leak reaches every
-    sample's gradient. Where the FP64 gradient itself moves under changes of
-    q at FP32 resolution (|v| near 0), the gradient tolerance is four times
-    that movement."""
+    schedule from 1 cm, each checked from the GPU's own state: every
+    candidate's loss within 1e-4 and gradient within 1e-3 of the oracle's
+    sweep at that q (constraints within FP32 resolution of d = 0 or of a cell
+    face under either reading), and the Adam update within 1e-6 of its
+    operands' magnitudes."""
     hand, grid, q0 = S.config_workload("tiny")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     H, ob = O.Hand(hand.rounded()), O.Obj(grid)
@@ -244,7 +228,7 @@ def test_gs_trajectory_teacher_forced(ctx):
     loss = torch.empty(B, device=DEV)
     dq = torch.empty_like(qd)
     lr, b1, b2, eps = (float(np.float32(x)) for x in (1e-3, 0.9, 0.999, 1e-8))
-    fl, gfl, worst_l, worst_g = [], [], 0.0, 0.0
+    res, aside, worst_l, worst_g = [], [], 0.0, 0.0
     for t in range(T):
         r = float(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1))
         sp, op = prm_pair(projection=GS, r_dil=r)
@@ -252,28 +236,13 @@ def test_gs_trajectory_teacher_forced(ctx):
         ctx.step_fused(h, sd, sp, qd, m, v, t + 1, loss=loss, dq=dq)
         torch.cuda.synchronize()
         lg, gg = loss.cpu().numpy(), dq.cpu().numpy()
-        ref = O.step(H, ob, op, q_prev, grad=True, margins=True)
-        floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
-        lerr = np.abs(lg - ref["loss"]) / floor
-        flagged = (ref["min_abs_d"] < KINK_GS) | (ref["min_face"] < 1e-5)
-        gflag = flagged | (ref["min_face_all"] < 1e-5)
-        assert np.all(lerr[~flagged] <= 1e-4), (t, np.argmax(np.where(flagged, 0, lerr)), lerr[~flagged].max())
-        gscale = np.maximum(np.abs(ref["grad"]).max(axis=1), 1e-30)
-        gerr = np.abs(gg - ref["grad"]).max(axis=1) / gscale
-        over = np.nonzero(~gflag & (gerr > 1e-3))[0]
-        if over.size:
-            cond = np.zeros(over.size)
-            rng = np.random.default_rng(t)
-            for _ in range(3):
-                qp = q_prev[over] * (1.0 + rng.normal(size=q_prev[over].shape) * 6e-8)
-                gp = O.step(H, ob, op, qp)["grad"]
-                cond = np.maximum(cond, np.abs(gp - ref["grad"][over]).max(axis=1) / gscale[over])
-            bad = gerr[over] > np.maximum(1e-3, 4.0 * cond)
-            assert not bad.any(), (t, over[bad], gerr[over][bad])
-        fl.append(flagged.mean())
-        gfl.append(gflag.mean())
-        worst_l = max(worst_l, lerr[~flagged].max() if (~flagged).any() else 0.0)
-        worst_g = max(worst_g, gerr[~gflag].max() if (~gflag).any() else 0.0)
+        rep = P.compare(lg, gg, H, ob, op, q_prev, kink_d=KINK_GS, conditioning=True, label=f"GS step {t}",
+                        say=lambda *a: None)
+        P.assert_ok(rep, max_set_aside=2.0 / B)
+        res.append(rep["resolved"] / B)
+        aside.append(rep["set_aside"] / B)
+        worst_l = max(worst_l, rep["max_lerr"])
+        worst_g = max(worst_g, rep["max_gerr"])
         g64 = gg.astype(np.float64)
         qa, ma, va = O.adam(q_prev, m_prev, v_prev, g64, t + 1, lr=lr, b1=b1, b2=b2, eps=eps)
         sm = b1 * np.abs(m_prev) + (1.0 - b1) * np.abs(g64)
@@ -283,10 +252,48 @@ def test_gs_trajectory_teacher_forced(ctx):
         for name, got, want, scale in (("q", qd, qa, sq), ("m", m, ma, sm), ("v", v, va, sv)):
             err = np.abs(got.cpu().numpy() - want)
             assert np.all(err <= 1e-6 * scale + 1e-7), (t, name, err.max())
-    say(f"GS trajectory: {T} steps, B={B}: worst loss rel err {worst_l:.2e}, worst grad rel err {worst_g:.2e}, "
-        f"set aside for the loss mean {np.mean(fl):.3f} max {np.max(fl):.3f}, for the gradient mean "
-        f"{np.mean(gfl):.3f} max {np.max(gfl):.3f}")
-    assert np.max(fl) <= 0.25 and np.mean(fl) <= 0.1
-    assert np.max(gfl) <= 0.5 and np.mean(gfl) <= 0.3
+    say(f"GS trajectory: {T} steps, B={B}: worst loss rel err {worst_l:.2e}, worst grad rel err {worst_g:.2e}; "
+        f"resolved by an FP32 reading: mean {np.mean(res):.3f} max {np.max(res):.3f}; set aside mean "
+        f"{np.mean(aside):.4f} max {np.max(aside):.3f}")
+    assert np.mean(aside) <= 0.01
+    sd.unload()
+    h.destroy()
+
+
+def test_gs_backward_refuses_graph_capture(ctx):
+    """A Gauss-Seidel launch with a backward keeps its sweep start poses in a
+    context buffer that a later, larger launch may move, so it refuses to be
+    captured; its forward alone (no table) can be captured and replays to the
+    eager result."""
+    from paper_2306_08132_amd._lib import GraspError
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny", B=16)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp = StepParams(projection=GS, r_dil=0.004)
+    qd = dev(q)
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        g.capture_begin()
+        try:
+            with pytest.raises(GraspError, match="captured"):
+                ctx.step_fused(h, sd, sp, qd, m, v, 1, stream=s)
+        finally:
+            g.capture_end()
+    torch.cuda.synchronize()
+    ref = torch.empty(16, device=DEV)
+    ctx.step_fwd(h, sd, sp, qd, ref)
+    out = torch.empty(16, device=DEV)
+    g2 = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g2, stream=s):
+        ctx.step_fwd(h, sd, sp, qd, out, stream=s)
+    for _ in range(3):
+        out.zero_()
+        g2.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
     sd.unload()
     h.destroy()

@@ -1,24 +1,25 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs. Tolerances: relative 1e-5 on SDF samples and contact
 positions, 1e-4 on losses, 1e-3 on gradients; exact on contact-to-link
-indexing and ranking. A sample within 2.5e-7 m of d = 0 (about five times
-the FP32 error of d at these coordinates) may take the other branch of the
-leaky rule in FP32; candidates holding one are reported and may not exceed
-a small fraction. Where the FP64 gradient itself moves by more than a
-quarter of the tolerance under FP32-resolution changes of q (|v| near zero),
-the gradient tolerance is four times that movement."""
+indexing; rankings equal up to swaps inside near-tied groups. Every
+candidate is checked: a sample within FP32 resolution of d = 0 or of a cell
+face may take either reading (tests/parity_check.py), and a candidate is
+only set aside (at most 1%) when it has more such samples than are
+enumerated. Where the FP64 gradient itself moves by more than a quarter of
+the tolerance under FP32-resolution changes of q (|v| near zero after
+several projection iterations), the gradient tolerance is four times that
+movement, capped at 1e-2, for a stated share of the candidates."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
+import parity_check as P
 from paper_2306_08132_amd import synth as S
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-KINK_D = 2.5e-7  # metres: a sample this close to d = 0 may flip branch in FP32
-KINK_FACE = 1e-5  # cell units: a sample this close to a cell face may change cell in FP32
 
 
 def say(*a):
@@ -99,7 +100,8 @@ def test_sdf_sampler_parity(ctx, which, layout):
     scale = np.maximum(np.abs(Ho).reshape(-1, 9).max(axis=1), 1.0 / g.h)
     herr = np.abs(H - Ho).reshape(-1, 9).max(axis=1)
     assert np.all(herr[ok] <= 1e-4 * scale[ok]), np.max(herr[ok] / scale[ok])
-    say("  flagged near faces:", (~ok).mean())
+    say("  gradients not compared (within 1e-4 cell units of a face, where the gradient jumps):", (~ok).mean())
+    assert (~ok).mean() <= 0.01
     assert inertia_close(ctx, sd, g)
 
 
@@ -140,7 +142,14 @@ def test_fk_and_trace_parity(ctx, tiny):
         assert np.all(err[:, :3] <= 1e-5 * lin + 1e-9) and np.all(err[:, 3:] <= 1e-5 * ang + 1e-9)
 
 
-def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05, layout=0):
+def compare_step(ctx, hand, grid, q, sp, op, label, layout=0, conditioning=False, max_set_aside=0.01):
+    """Split forward and backward at q against the oracle (tests/parity_check:
+    every candidate checked, ambiguous samples under either FP32 reading).
+    conditioning: with several projection iterations the gradient of
+    L_stable = |v| near v = 0 is ill-conditioned; a candidate whose gradient
+    misses 1e-3 is held to four times the movement of the FP64 gradient under
+    FP32-resolution changes of q, capped at 1e-2, and set aside beyond the cap
+    (at most max_set_aside of the candidates)."""
     h, sd = ctx.hand(hand), ctx.sdf(grid, layout=layout)
     B = q.shape[0]
     qd = dev(q)
@@ -154,32 +163,9 @@ def compare_step(ctx, hand, grid, q, sp, op, label, max_flagged=0.05, layout=0):
     torch.cuda.synchronize()
     loss, terms, dq = loss.cpu().numpy(), terms.cpu().numpy(), dq.cpu().numpy()
     q32 = q.astype(np.float32).astype(np.float64)
-    ref = O.step(ohand(hand), O.Obj(grid), op, q32, grad=True, margins=True)
-    floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
-    lerr = np.abs(loss - ref["loss"]) / floor
-    gscale = np.abs(ref["grad"]).max(axis=1)
-    gerr = np.abs(dq - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30)
-    # conditioning: how far the FP64 gradient itself moves when q is perturbed
-    # at FP32 resolution (2^-24 relative). Near |v| = 0 the stable term's
-    # gradient v/|v| is ill-conditioned, and more so after several projection
-    # iterations; there the tolerance widens to four times that movement.
-    cond = np.zeros(B)
-    rng = np.random.default_rng(1)
-    for _ in range(3):
-        qp = q32 * (1.0 + rng.normal(size=q32.shape) * 6e-8)
-        gp = O.step(ohand(hand), O.Obj(grid), op, qp)["grad"]
-        cond = np.maximum(cond, np.abs(gp - ref["grad"]).max(axis=1) / np.maximum(gscale, 1e-30))
-    gtol = np.maximum(1e-3, 4.0 * cond)
-    flagged = ref["min_abs_d"] < KINK_D
-    say(f"{label}: B={B} max loss rel err {lerr.max():.2e}, grad rel err max(unflagged) "
-        f"{gerr[~flagged].max() if (~flagged).any() else 0:.2e}, median {np.median(gerr):.2e}, "
-        f"widened tol {(gtol > 1e-3).sum()} (max {gtol.max():.2e}), "
-        f"flagged {flagged.mean():.3f} (their grad errs {np.round(gerr[flagged], 5).tolist()})")
-    assert np.all(lerr <= 1e-4), (np.argmax(lerr), lerr.max())
-    bad = ~flagged & (gerr > gtol)
-    assert not bad.any(), (np.nonzero(bad)[0], gerr[bad], gtol[bad])
-    assert flagged.mean() <= max_flagged
-    return loss, dq, ref
+    rep = P.compare(loss, dq, ohand(hand), O.Obj(grid), op, q32, conditioning=conditioning, label=label, say=say)
+    P.assert_ok(rep, max_set_aside=max_set_aside)
+    return loss, dq, rep["ref"]
 
 
 def test_step_parity_tiny(ctx, tiny):
@@ -197,7 +183,7 @@ def test_step_parity_ragged_and_small(ctx):
         grid = S.make_grid(S.make_object("ellipsoids", seed=n), N)
         q = S.make_candidates(hand, B, seed=n, shell_radius=grid.bound_radius + 0.06)
         sp, op = prm_pair(r_dil=0.003)
-        compare_step(ctx, hand, grid, q, sp, op, f"ragged {F}x{J} Nc={n}", max_flagged=0.2)
+        compare_step(ctx, hand, grid, q, sp, op, f"ragged {F}x{J} Nc={n}")
 
 
 def test_step_parity_iterations(ctx, tiny):
@@ -206,7 +192,8 @@ def test_step_parity_iterations(ctx, tiny):
     outs = []
     for K, ck in [(4, 1), (4, 2), (4, 4)]:
         sp, op = prm_pair(K=K, ckpt_every=ck, r_dil=0.004)
-        loss, dq, _ = compare_step(ctx, hand, grid, q[:24], sp, op, f"K={K} ckpt={ck}", max_flagged=0.2)
+        loss, dq, _ = compare_step(ctx, hand, grid, q[:24], sp, op, f"K={K} ckpt={ck}", conditioning=True,
+                                   max_set_aside=0.1)
         outs.append((loss, dq))
     for loss, dq in outs[1:]:
         assert np.array_equal(loss, outs[0][0]) and np.array_equal(dq, outs[0][1])
@@ -317,7 +304,8 @@ def test_nonfinite_input_stays_in_bounds(ctx, tiny):
 
 def test_full_size_diff_sampled(ctx):
     """Full differentiable-step workload (4096 candidates, 2048 contacts,
-    128^3): fused launch as benchmarked, 8 sampled candidates vs the oracle."""
+    128^3): the fused launch as benchmarked, 48 sampled candidates against
+    the oracle (every one checked, ambiguous samples under either reading)."""
     hand, grid, q = S.config_workload("diff")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     sp, op = prm_pair(r_dil=0.005)
@@ -328,15 +316,10 @@ def test_full_size_diff_sampled(ctx):
     dq = torch.empty_like(qd)
     ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
     torch.cuda.synchronize()
-    idx = np.random.default_rng(0).choice(B, 8, replace=False)
-    ref = O.step(ohand(hand), O.Obj(grid), op, q[idx].astype(np.float32).astype(np.float64), margins=True)
-    l, g = loss.cpu().numpy()[idx], dq.cpu().numpy()[idx]
-    lerr = np.abs(l - ref["loss"]) / np.maximum(np.abs(ref["loss"]), 1.0)
-    gerr = np.abs(g - ref["grad"]).max(axis=1) / np.abs(ref["grad"]).max(axis=1)
-    flagged = ref["min_abs_d"] < KINK_D
-    say("diff full: loss err", lerr.max(), "grad err", gerr, "flagged", flagged)
-    assert np.all(lerr <= 1e-4)
-    assert np.all(gerr[~flagged] <= 1e-3)
+    idx = np.random.default_rng(0).choice(B, 48, replace=False)
+    rep = P.compare(loss.cpu().numpy()[idx], dq.cpu().numpy()[idx], ohand(hand), O.Obj(grid), op,
+                    q[idx].astype(np.float32).astype(np.float64), label="diff full (48 sampled)", say=say)
+    P.assert_ok(rep)
 
 
 def test_every_tile_bit_identical(ctx, tiny):
@@ -434,21 +417,18 @@ def test_plain_form_parity(ctx, tiny):
     dqf = torch.empty_like(qf)
     ctx.step_fused(h, sd, sp, qf, mf, vf, 1, loss=lf, dq=dqf)
     torch.cuda.synchronize()
-    ref = O.step(ohand(hand), O.Obj(grid), op, q.astype(np.float32).astype(np.float64), margins=True)
     lp = loss.cpu().numpy()
-    assert np.all(np.abs(lp - ref["loss"]) <= 1e-4 * np.maximum(np.abs(ref["loss"]), 1.0))
-    # Adam's first step is -lr sign(g): compare the update direction where |g| is not tiny
-    g = ref["grad"]
-    big = np.abs(g) > 1e-3 * np.abs(g).max(axis=1, keepdims=True)
-    upd = (qp.cpu().numpy() - q.astype(np.float32))
-    flagged = ref["min_abs_d"] < KINK_D
-    ok = big & ~flagged[:, None]
-    assert np.all(np.sign(upd[ok]) == -np.sign(g[ok]))
     # m after one step is (1 - b1) dq: the plain gradient against the oracle
     dq_plain = m.cpu().numpy() / np.float32(1 - np.float32(0.9))
-    err = np.abs(dq_plain - g).max(axis=1) / np.abs(g).max(axis=1)
-    say("plain grad rel err max(unflagged)", err[~flagged].max())
-    assert np.all(err[~flagged] <= 1e-3)
+    rep = P.compare(lp, dq_plain, ohand(hand), O.Obj(grid), op, q.astype(np.float32).astype(np.float64),
+                    label="plain form", say=say)
+    P.assert_ok(rep)
+    # Adam's first step is -lr sign(g): the update direction where |g| is not tiny
+    g = rep["ref"]["grad"]
+    big = np.abs(g) > 1e-3 * np.abs(g).max(axis=1, keepdims=True)
+    upd = (qp.cpu().numpy() - q.astype(np.float32))
+    ok = big & (rep["status"] == 0)[:, None]
+    assert np.all(np.sign(upd[ok]) == -np.sign(g[ok]))
     assert np.allclose(lp, lf.cpu().numpy(), rtol=1e-5, atol=1e-6)
 
 
@@ -598,15 +578,13 @@ def test_stored_oracle_values(ctx, tiny):
 def test_trajectory_teacher_forced(ctx, tiny):
     """100 fused steps on the small workload (64 candidates, 512 contacts,
     64^3 grid) along the dilation schedule from 1 cm, every step checked from
-    the GPU's own state: loss and gradient against the oracle at that q, to
-    the single-step tolerances (candidates holding a sample within KINK_D of
-    d = 0, or a penetrating one within KINK_FACE of a cell face, reported,
-    not failed; for the gradient, which the leak ties to every sample's
-    gradient, also those holding any sample within KINK_FACE of a face), and the Adam update against the oracle's Adam
+    the GPU's own state: loss and gradient of every candidate against the
+    oracle at that q (samples within FP32 resolution of d = 0 or of a cell
+    face under either reading), and the Adam update against the oracle's Adam
     fed the GPU's gradient and moments (1e-6 relative to the operands'
-    magnitudes). The free-running trajectories (each
-    side on its own state, final loss at zero dilation) are reported, not
-    asserted: FP32 and FP64 states drift apart over many steps."""
+    magnitudes). The free-running trajectories (each side on its own state,
+    final loss at zero dilation) are reported, not asserted: FP32 and FP64
+    states drift apart over many steps."""
     from paper_2306_08132_amd.api import StepParams
     hand, grid, q0 = tiny
     h, sd = ctx.hand(hand), ctx.sdf(grid)
@@ -617,7 +595,7 @@ def test_trajectory_teacher_forced(ctx, tiny):
     loss = torch.empty(B, device=DEV)
     dq = torch.empty_like(qd)
     worst_l = worst_g = 0.0
-    flagged_steps, gflagged_steps, flagged_lerr = [], [], []
+    resolved, set_aside = [], []
     for t in range(T):
         r = float(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1))
         sp, op = prm_pair(r_dil=r)
@@ -625,37 +603,15 @@ def test_trajectory_teacher_forced(ctx, tiny):
         ctx.step_fused(h, sd, sp, qd, m, v, t + 1, loss=loss, dq=dq)
         torch.cuda.synchronize()
         lg, gg = loss.cpu().numpy(), dq.cpu().numpy()
-        ref = O.step(H, ob, op, q_prev, grad=True, margins=True)
-        floor = np.maximum(np.abs(ref["loss"]), op.w_stable * op.v0)
-        lerr = np.abs(lg - ref["loss"]) / floor
-        # a sample within KINK_D of d = 0 may count as active on one side and
-        # not the other, and a penetrating sample within KINK_FACE cell units
-        # of a cell face may take the neighbouring cell's gradient: either
-        # moves a correction and so the loss; such candidates are reported,
-        # not failed
-        flagged = (ref["min_abs_d"] < KINK_D) | (ref["min_face"] < KINK_FACE)
-        assert np.all(lerr[~flagged] <= 1e-4), (t, np.argmax(np.where(flagged, 0, lerr)), lerr[~flagged].max())
-        gscale = np.maximum(np.abs(ref["grad"]).max(axis=1), 1e-30)
-        gerr = np.abs(gg - ref["grad"]).max(axis=1) / gscale
-        # the leak reaches every sample's gradient, so the gradient check also
-        # sets aside candidates with any sample within KINK_FACE of a face
-        gflag = flagged | (ref["min_face_all"] < KINK_FACE)
-        over = np.nonzero(~gflag & (gerr > 1e-3))[0]
-        if over.size:
-            # conditioning of the FP64 gradient at FP32 resolution, as in the single step
-            cond = np.zeros(over.size)
-            rng = np.random.default_rng(t)
-            for _ in range(3):
-                qp = q_prev[over] * (1.0 + rng.normal(size=q_prev[over].shape) * 6e-8)
-                gp = O.step(H, ob, op, qp)["grad"]
-                cond = np.maximum(cond, np.abs(gp - ref["grad"][over]).max(axis=1) / gscale[over])
-            bad = gerr[over] > np.maximum(1e-3, 4.0 * cond)
-            assert not bad.any(), (t, over[bad], gerr[over][bad])
-        flagged_steps.append(flagged.mean())
-        gflagged_steps.append(gflag.mean())
-        flagged_lerr.extend(lerr[flagged].tolist())
-        worst_l = max(worst_l, lerr[~flagged].max() if (~flagged).any() else 0.0)
-        worst_g = max(worst_g, gerr[~gflag].max() if (~gflag).any() else 0.0)
+        rep = P.compare(lg, gg, H, ob, op, q_prev, conditioning=True, label=f"step {t}", say=lambda *a: None)
+        P.assert_ok(rep, max_set_aside=2.0 / B)
+        if rep["resolved"] or rep["conditioned"] or rep["set_aside"]:
+            say(f"  step {t}: resolved {rep['resolved']}, within conditioning {rep['conditioned']} "
+                f"(largest {rep['max_cond']:.1e}), set aside {rep['set_aside']}")
+        resolved.append(rep["resolved"] / B)
+        set_aside.append(rep["set_aside"] / B)
+        worst_l = max(worst_l, rep["max_lerr"])
+        worst_g = max(worst_g, rep["max_gerr"])
         lr, b1, b2, eps = f32(1e-3), f32(0.9), f32(0.999), f32(1e-8)
         g64 = gg.astype(np.float64)
         qa, ma, va = O.adam(q_prev, m_prev, v_prev, g64, t + 1, lr=lr, b1=b1, b2=b2, eps=eps)
@@ -668,13 +624,10 @@ def test_trajectory_teacher_forced(ctx, tiny):
         for name, got, want, scale in (("q", qd, qa, sq), ("m", m, ma, sm), ("v", v, va, sv)):
             err = np.abs(got.cpu().numpy() - want)
             assert np.all(err <= 1e-6 * scale + 1e-7), (t, name, np.argmax(err - 1e-6 * scale), err.max())
-    say(f"trajectory: {T} steps, B={B}: worst loss rel err {worst_l:.2e}, worst unflagged grad rel err "
-        f"{worst_g:.2e}, flagged mean {np.mean(flagged_steps):.4f} max {np.max(flagged_steps):.4f} "
-        f"(their loss rel errs up to {max(flagged_lerr, default=0.0):.2e})")
-    say(f"trajectory: gradient checks set aside (any sample near a face) mean {np.mean(gflagged_steps):.4f} "
-        f"max {np.max(gflagged_steps):.4f}")
-    assert np.max(flagged_steps) <= 0.1 and np.mean(flagged_steps) <= 0.02
-    assert np.max(gflagged_steps) <= 0.25 and np.mean(gflagged_steps) <= 0.1
+    say(f"trajectory: {T} steps, B={B}: worst loss rel err {worst_l:.2e}, worst grad rel err {worst_g:.2e}; "
+        f"candidates resolved by an FP32 reading: mean {np.mean(resolved):.4f} max {np.max(resolved):.4f}; "
+        f"set aside: mean {np.mean(set_aside):.4f} max {np.max(set_aside):.4f}")
+    assert np.mean(set_aside) <= 0.01
     # free running: the GPU's final loss at zero dilation against the oracle's own optimisation
     fin = torch.empty(B, device=DEV)
     ctx.step_fwd(h, sd, StepParams(r_dil=0.0), qd, fin)
@@ -685,3 +638,48 @@ def test_trajectory_teacher_forced(ctx, tiny):
     rel = np.abs(fin.cpu().numpy() - own["loss"]) / np.maximum(np.abs(own["loss"]), op0.w_stable * op0.v0)
     say(f"trajectory free-running: final loss rel diff median {np.median(rel):.2e}, max {rel.max():.2e}; "
         f"median final loss GPU {np.median(fin.cpu().numpy()):.4f}, oracle {np.median(own['loss']):.4f}")
+
+
+def test_auto_mode_recomputes_when_the_workspace_exceeds_the_budget(ctx, tiny):
+    """GraspStep in AUTO mode keeps pose checkpoints only when the workspace
+    fits its budget; with a budget of 0 bytes the backward recomputes FK and
+    the samples, and the gradient is bit-identical to SAVE's."""
+    from paper_2306_08132_amd.api import MODE_AUTO, MODE_SAVE, GraspStep, StepParams
+    hand, grid, q = tiny
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    grads = {}
+    for name, mode, budget in (("save", MODE_SAVE, None), ("auto-fits", MODE_AUTO, 1 << 30),
+                               ("auto-recompute", MODE_AUTO, 0)):
+        sp = StepParams(r_dil=0.004, K=4, ckpt_every=2, mode=mode)
+        qd = dev(q[:32]).requires_grad_(True)
+        GraspStep.apply(qd, ctx, h, sd, sp, budget).sum().backward()
+        torch.cuda.synchronize()
+        grads[name] = qd.grad.cpu().numpy()
+    assert ctx.workspace_bytes(h, sd, StepParams(K=4, ckpt_every=2), 32) > 0
+    assert np.array_equal(grads["save"], grads["auto-fits"])
+    assert np.array_equal(grads["save"], grads["auto-recompute"])
+
+
+@pytest.mark.parametrize("which", ["tiny", "diff"])
+def test_ranking_matches_oracle(ctx, which):
+    """Candidates ranked by the GPU's loss at zero dilation (the served form's
+    final ranking: stable sort of the FP32 losses) against the oracle's
+    stable sort of its FP64 losses at the same q: the same permutation up to
+    swaps inside groups of near-tied losses (|dL| <= 2e-4 max |L|)."""
+    from paper_2306_08132_amd.api import StepParams
+    if which == "tiny":
+        hand, grid, q = S.config_workload("tiny")
+        idx = np.arange(q.shape[0])
+    else:
+        hand, grid, q = S.config_workload("diff")
+        idx = np.random.default_rng(4).choice(q.shape[0], 96, replace=False)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    qs = q[idx]
+    loss = torch.empty(len(idx), device=DEV)
+    ctx.step_fwd(h, sd, StepParams(r_dil=0.0), dev(qs), loss)
+    torch.cuda.synchronize()
+    lg = loss.cpu().numpy()
+    rank_gpu = np.argsort(lg, kind="stable")
+    _, op = prm_pair(r_dil=0.0)
+    ref = O.step(ohand(hand), O.Obj(grid), op, qs.astype(np.float32).astype(np.float64), grad=False)
+    P.assert_rank_matches(rank_gpu, ref["loss"], label=f"ranking {which}", say=say)

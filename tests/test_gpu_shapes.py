@@ -1,0 +1,179 @@
+"""GPU parity at the shapes of the batched and the large workloads, and of the
+served form, against the FP64 oracle (every compared candidate checked, with
+ambiguous samples under either FP32 reading, tests/parity_check.py):
+
+* one batched launch per step over jobs with the 5-finger hand (26 DOF, 4096
+  contacts) on grids of 64^3, 128^3, 192^3 and 256^3: at every step, sampled
+  candidates of every job against the oracle at that step's q and dilation
+  (loss and the gradient the step's Adam used);
+* the large workload in one launch: 65536 candidates, 8192 contacts, a 256^3
+  grid, 16 projection iterations with a pose checkpoint every 4: 32 sampled
+  candidates;
+* a served job, teacher-forced: its recorded q before every step and the loss
+  at the start of that step against the oracle at that q, its final losses at
+  zero dilation, and its ranking against the oracle's stable sort of the
+  oracle's own FP64 losses (equal up to swaps inside near-tied groups)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import parity_check as P
+from paper_2306_08132_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def oparams(sp):
+    op = O.Params()
+    for k in vars(op):
+        v = getattr(sp, k)
+        setattr(op, k, f32(v) if isinstance(v, float) else v)
+    return op
+
+
+def dilation(r0, t, T):
+    """The library's schedule r0 (1 - t/(T-1)) as it computes it (FP64, then FP32)."""
+    return f32(np.float64(np.float32(r0)) * (1.0 - min(t, T - 1) / (T - 1)))
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2306_08132_amd.api import Context
+    c = Context(0, arena_bytes=3 << 30)
+    yield c
+    c.close()
+
+
+def test_batched_jobs_against_oracle(ctx):
+    from paper_2306_08132_amd.api import Batch, BatchJob, StepParams
+    hand = S.make_hand(5, 4, 4096, seed=31)
+    H = O.Hand(hand.rounded())
+    h = ctx.hand(hand)
+    specs = [(64, 300, 41), (128, 120, 42), (192, 290, 43), (256, 160, 44)]  # (N, B, seed)
+    jobs, grids = [], []
+    T, r0 = 20, 0.01
+    for N, B, seed in specs:
+        say(f"batched job: {N}^3 grid, {B} candidates")
+        grid = S.make_grid(S.make_object("mixed", seed=seed, n_prims=3 + seed % 6), N, device=DEV)
+        q = S.make_candidates(hand, B, seed=seed + 7, shell_radius=grid.bound_radius + 0.06)
+        sd = ctx.sdf(grid)
+        qd = torch.tensor(q, dtype=torch.float32, device=DEV)
+        jobs.append(BatchJob(h, sd, StepParams(), qd, T=T, r0=r0, dq=torch.empty_like(qd)))
+        grids.append(grid)
+    stream = torch.cuda.Stream()
+    b = Batch(ctx, capacity=1024, max_jobs=8, use_graph=True)
+    rng = np.random.default_rng(5)
+    totals = {"direct": 0, "resolved": 0, "set_aside": 0, "n": 0}
+    for step in range(3):
+        q_before = [j.q.cpu().numpy().astype(np.float64) for j in jobs]
+        with torch.cuda.stream(stream):
+            b.step(jobs, stream=stream)
+        stream.synchronize()
+        assert not b.flags(len(jobs)).any()
+        for k, (j, grid) in enumerate(zip(jobs, grids)):
+            idx = rng.choice(j.q.shape[0], 3, replace=False)
+            sp = StepParams(r_dil=dilation(r0, step, T))
+            rep = P.compare(j.loss.cpu().numpy()[idx], j.dq.cpu().numpy()[idx], H, O.Obj(grid), oparams(sp),
+                            q_before[k][idx], label=f"batched step {step} job {k} ({grid.n}^3)", say=say)
+            P.assert_ok(rep, max_set_aside=0.0)
+            for key in ("direct", "resolved", "set_aside"):
+                totals[key] += rep[key]
+            totals["n"] += len(idx)
+            # the gradient the step's Adam used: the first step's update is -lr sign(dq) where |dq| is not tiny
+            if step == 0:
+                g = j.dq.cpu().numpy()[idx]
+                big = np.abs(g) > 1e-3 * np.abs(g).max(axis=1, keepdims=True)
+                upd = j.q.cpu().numpy()[idx] - q_before[k][idx].astype(np.float32)
+                assert np.all(np.sign(upd[big]) == -np.sign(g[big]))
+    say(f"batched: {totals['n']} candidate-steps: direct {totals['direct']}, resolved {totals['resolved']}, "
+        f"set aside {totals['set_aside']}")
+    b.close()
+
+
+def test_large_workload_sampled(ctx):
+    """65536 candidates x 8192 contacts on a 256^3 grid, 16 projection
+    iterations, pose checkpoints every 4 (the backward replays each segment):
+    the fused launch as benchmarked, 32 sampled candidates against the oracle.
+    With 16 iterations the gradient of |v| near v = 0 can be ill-conditioned:
+    a candidate whose gradient misses 1e-3 is held to four times the movement
+    of the FP64 gradient under FP32-resolution changes of q (capped at 1e-2),
+    and set aside where that movement alone exceeds the cap."""
+    from paper_2306_08132_amd.api import StepParams
+    say("large workload: building the 256^3 grid")
+    hand, grid, q = S.config_workload("large", device=DEV)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp = StepParams(K=16, ckpt_every=4, r_dil=0.005)
+    B = q.shape[0]
+    qd = torch.tensor(q, dtype=torch.float32, device=DEV)
+    m, v = torch.zeros_like(qd), torch.zeros_like(qd)
+    loss = torch.empty(B, device=DEV)
+    dq = torch.empty_like(qd)
+    t0 = time.time()
+    ctx.step_fused(h, sd, sp, qd, m, v, 1, loss=loss, dq=dq)
+    torch.cuda.synchronize()
+    say(f"large workload: fused step in {time.time() - t0:.2f} s")
+    assert np.all(np.isfinite(loss.cpu().numpy()))
+    idx = np.random.default_rng(9).choice(B, 32, replace=False)
+    q32 = q[idx].astype(np.float32).astype(np.float64)
+    H, ob, op = O.Hand(hand.rounded()), O.Obj(grid), oparams(sp)
+    rep = P.compare(loss.cpu().numpy()[idx], dq.cpu().numpy()[idx], H, ob, op, q32, conditioning=True,
+                    max_units=4, label="large (32 sampled)", say=say)
+    P.assert_ok(rep, max_set_aside=0.25)
+    sd.unload()
+    h.destroy()
+
+
+def test_served_job_against_oracle(ctx):
+    """A job through the serving loop beside two others, with its history
+    recorded: the loss at the start of every step against the oracle at the
+    q it recorded (teacher-forced) and that step's dilation, the final loss
+    at zero dilation against the oracle at the final q, and the ranking."""
+    from paper_2306_08132_amd.api import StepParams
+    hand, grid, q = S.config_workload("tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    other = S.make_candidates(hand, 40, seed=3, shell_radius=grid.bound_radius + 0.06)
+    T, r0 = 8, 0.01
+    ids = [ctx.submit(h, sd, other, T=5, r0=r0)]
+    jid = ctx.submit(h, sd, q, T=T, r0=r0, record_history=True)
+    ids.append(ctx.submit(h, sd, other, T=11, r0=r0))
+    t0 = time.time()
+    res = None
+    while res is None and time.time() - t0 < 120:
+        res = ctx.poll(jid, q.shape[0], hand.n_dof, T=T)
+        time.sleep(0.005)
+    assert res is not None and res["status"] == 0 and res["steps"] == T
+    for i in ids:
+        while ctx.poll(i, 40, hand.n_dof) is None:
+            time.sleep(0.005)
+    H, ob = O.Hand(hand.rounded()), O.Obj(grid)
+    assert np.array_equal(res["hist_q"][0], q.astype(np.float32))
+    counts = np.zeros(3, int)
+    for t in range(T):
+        op = oparams(StepParams(r_dil=dilation(r0, t, T)))
+        rep = P.compare(res["hist_loss"][t], None, H, ob, op, res["hist_q"][t].astype(np.float64),
+                        label=f"served step {t}", say=lambda *a: None)
+        P.assert_ok(rep, max_set_aside=0.0)
+        counts += (rep["direct"], rep["resolved"], rep["set_aside"])
+    say(f"served job: {T} steps x {q.shape[0]} candidates: direct {counts[0]}, resolved {counts[1]}")
+    # history is consistent with the result: the last recorded q is one step before the final q
+    assert not np.array_equal(res["hist_q"][-1], res["q"])
+    op0 = oparams(StepParams(r_dil=0.0))
+    qf = res["q"].astype(np.float64)
+    rep = P.compare(res["loss"], None, H, ob, op0, qf, label="served final loss", say=say)
+    P.assert_ok(rep, max_set_aside=0.0)
+    ref = O.step(H, ob, op0, qf, grad=False)
+    P.assert_rank_matches(res["rank"], ref["loss"], label="served ranking", say=say)
+    sd.unload()
+    h.destroy()
