@@ -334,6 +334,22 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
                               int32_t t, float lr, float b1, float b2, float eps, float* loss,
                               float* terms, float* dq, void* hip_stream);
 
+/* grasp_step_fused for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step, bit for bit, with the candidate locality order kept in a
+ * fixed device array of the library (1 MiB per GPU, held until the process
+ * ends) instead of the context's arena. It calls no hipMalloc, hipFree or
+ * allocating routine, and can be captured into a graph (the order is computed
+ * inside the captured work). Limits: B <= 262144 (EINVAL above), averaged
+ * projection only (EINVAL for Gauss-Seidel, whose start-pose table needs
+ * memory). Every call on one GPU shares that array: calls that overlap on one
+ * GPU (different streams, or concurrent graph replays) race and must be
+ * serialized by the caller. */
+grasp_status grasp_step_fused_static(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                     const grasp_step_params* p, int32_t B, float* q, float* m, float* v, int32_t t,
+                                     float lr, float b1, float b2, float eps, float* loss, float* terms, float* dq,
+                                     void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * The plain per-job form: the same step (K = 1) as one unfused kernel per
  * stage (link transforms, contact points, SDF samples, summed corrections,

@@ -154,6 +154,8 @@ SIGNATURES = [
     ("grasp_adam_step", _I32, [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _F, _F, _F, _F, _VP]),
     ("grasp_step_fused", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F,
                                 _F, _VP, _VP, _VP, _VP]),
+    ("grasp_step_fused_static", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F,
+                                _F, _VP, _VP, _VP, _VP]),
     ("grasp_plain_workspace_bytes", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(_SZ)]),
     ("grasp_plain_step", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F, _F,
                                 _VP, _VP, _VP, _SZ, _VP]),

@@ -131,6 +131,14 @@ class Context:
         self.lib.call("grasp_step_fused", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
                       _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
 
+    def step_fused_static(self, hand, sdf, prm: StepParams, q, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
+                          loss=None, terms=None, dq=None, stream=None):
+        """grasp_step_fused_static: the fused step with no allocation (its
+        candidate order in the library's fixed device array; B <= 262144)."""
+        pc = prm.c()
+        self.lib.call("grasp_step_fused_static", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q),
+                      _ptr(m), _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
+
     def plain_workspace_bytes(self, hand, sdf, prm: StepParams, B: int) -> int:
         out = C.c_size_t()
         pc = prm.c()

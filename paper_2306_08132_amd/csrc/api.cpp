@@ -101,6 +101,32 @@ using namespace grasp;
 namespace {
 void load_tile_cache(grasp_ctx* ctx);
 
+// Candidate locality order of grasp_step_fused_static: a fixed device array
+// (each GPU the library runs on holds its own copy until the process ends),
+// so that step allocates nothing. Host code uses only the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+constexpr int kStaticOrderMax = 262144;  // candidates: 1 MiB of ints
+static __device__ __align__(256) int scratch[kStaticOrderMax];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of scratch.
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<int*>(ptr);
+  return hipSuccess;
+}
+
+int* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 #define GRASP_CHECK_CTX(ctx)                                                        \
   do {                                                                              \
@@ -143,6 +169,12 @@ grasp_status grasp_init(int device, void* arena_dev, size_t arena_bytes, grasp_c
     ctx->arena_owned = true;
   }
   ctx->arena.reset(ctx->arena_base, arena_bytes);
+  e = scratch_setup(device);
+  if (e != hipSuccess) {
+    if (ctx->arena_owned) (void)hipFree(ctx->arena_base);
+    delete ctx;
+    return fail(GRASP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
   load_tile_cache(ctx);
   *out = ctx;
   return GRASP_OK;
@@ -758,6 +790,43 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   const TileCfg tc = tile_for(ctx, r, B);
   hipError_t e = launch_ordered_step(ctx, a, STEP_FUSED, true, tc, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_step_fused_static(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
+                                     const grasp_step_params* p, int32_t B, float* q, float* m, float* v, int32_t t,
+                                     float lr, float b1, float b2, float eps, float* loss, float* terms, float* dq,
+                                     void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  Resolved r;
+  grasp_status st = resolve(ctx, hand, sdf, p, B, &r, false);
+  if (st != GRASP_OK) return st;
+  if (B > kStaticOrderMax)
+    return fail(GRASP_EINVAL, "B exceeds the 262144 candidates of the static scratch (use grasp_step_fused)");
+  if (B > 0 && (!q || !m || !v)) return fail(GRASP_EINVAL, "q/m/v is NULL");
+  st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  int* order = scratch_of(ctx->device);
+  if (!order) return fail(GRASP_EDEVICE, "static scratch not set up for this device");
+  StepArgs a = base_args(r, B);
+  a.q = q;
+  a.q_out = q;
+  a.m = m;
+  a.v = v;
+  a.loss = loss;
+  a.terms = terms;
+  a.dq = dq;
+  a.adam = adam_consts(t, lr, b1, b2, eps);
+  if (B < kOrderMinB) order = nullptr;
+  a.order = order;
+  const TileCfg tc = tile_for(ctx, r, B);
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (order) e = launch_order(q, r.hand.n_dof, B, r.sdf, order, s);
+  if (e == hipSuccess) e = launch_step(a, STEP_FUSED, true, tc, s);
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_static launch");
   return GRASP_OK;
 }
 
