@@ -277,10 +277,11 @@ def step_ex(hand: Hand, obj: Obj, prm: Params, q, flips=(), kink_d: float = -1.0
             max_amb: int = 0, grad: bool = True, threads: int = 0):
     """oracle_step with readings of ambiguous samples and their report.
     flips: (b, m, k, i, what) tuples, what 0 = the other side of d = 0, 1..3 =
-    the other cell along x, y, z. With max_amb > 0, "amb" lists per candidate
-    the first max_amb samples (m, k, i, what, margin, penetrating) within
-    kink_d of d = 0 or kink_face cell units of a cell face, and "n_amb" their
-    full counts."""
+    the other cell along x, y, z, 4 = the other side of the friction cone,
+    5 = the other side of the friction floor. With max_amb > 0, "amb" lists
+    per candidate the first max_amb samples (m, k, i, what, margin,
+    penetrating) within kink_d of d = 0, of mu C or of the friction floor, or
+    kink_face cell units of a cell face, and "n_amb" their full counts."""
     q = _d(q).reshape(-1, hand.n_dof)
     B = q.shape[0]
     loss = np.zeros(B)

@@ -48,6 +48,11 @@
 namespace {
 
 constexpr int kSims = 7;  // M = 7 simulations (Sec. IV-A)
+// friction floor: slides up to this fraction of dt v0 have no direction
+constexpr double kSlideMin = 1e-3;
+// contact tolerance: penetration beyond this fraction of dt v0 makes a
+// constraint active
+constexpr double kContactTol = 5e-3;
 
 // ---------------------------------------------------------------------------
 // scalars: double, or a dual number carrying N tangents
@@ -392,7 +397,7 @@ struct Trace {
   double* poses = nullptr;    // [M][K+1][6]
   double* samples = nullptr;  // [M][K][Nc][6]
   double* p_world = nullptr;  // [Nc][3]
-  double min_abs_d = 1e30;
+  double min_abs_d = 1e30;      // min |d + eps| over samples with w > w_min: distance from the activation
   double min_face = 1e30;      // penetrating samples: their gradient sets a correction
   double min_face_all = 1e30;  // every sample with w > w_min: the leak reaches its gradient
   uint64_t signature = 1469598103934665603ull;  // FNV-1a over discrete decisions
@@ -402,8 +407,9 @@ struct Trace {
   int n_flips = 0;
   double kink_d = -1.0, kink_face = -1.0;
   std::vector<oamb>* amb = nullptr;
-  // flips of sample (m, k, i): bit 0 = the other side of d = 0, bit 1 + a =
-  // the other cell along axis a
+  // flips of sample (m, k, i): bit 0 = the other side of the activation
+  // d = -eps, bit 1 + a = the other cell along axis a, bit 4 the other side
+  // of the friction cone, bit 5 of the friction floor
   int flips_of(int m, int k, int i) const {
     int f = 0;
     for (int j = 0; j < n_flips; ++j)
@@ -413,9 +419,13 @@ struct Trace {
   void report_friction(int m, int k, int i, double gap) {
     if (amb && std::fabs(gap) < kink_d) amb->push_back(oamb{m, k, i, 4, std::fabs(gap), 1});
   }
-  void report(int m, int k, int i, double d, const SampleInfo& info, bool pen) {
+  void report_slide(int m, int k, int i, double gap) {
+    if (amb && std::fabs(gap) < kink_d) amb->push_back(oamb{m, k, i, 5, std::fabs(gap), 1});
+  }
+  // gap: d + eps, the distance from the activation
+  void report(int m, int k, int i, double gap, const SampleInfo& info, bool pen) {
     if (!amb) return;
-    if (std::fabs(d) < kink_d) amb->push_back(oamb{m, k, i, 0, std::fabs(d), pen ? 1 : 0});
+    if (std::fabs(gap) < kink_d) amb->push_back(oamb{m, k, i, 0, std::fabs(gap), pen ? 1 : 0});
     for (int a = 0; a < 3; ++a)
       if (info.axis_margin[a] < kink_face) amb->push_back(oamb{m, k, i, 1 + a, info.axis_margin[a], pen ? 1 : 0});
   }
@@ -434,22 +444,30 @@ template <int N> Dual<N> hand_part(const Dual<N>& d, const Dual<N>* g, const Dua
 }
 
 // C = max(0, -d) with the leaky derivative rule (Sec. III-C, "Leaky
-// gradient"): value max(0, -d); tangent -dd where d < 0, and -alpha times
-// the hand-point part of dd otherwise. The leak is a surrogate derivative
-// for hand points that do not touch the object; along the object's pose
-// from one projection iteration to the next the derivative stays exact
-// (with one iteration the pose carries no tangent and the two coincide).
-// pen: which side of d = 0 the sample is taken on (d < 0, unless a flip
-// takes the other reading of a sample within rounding of the surface); it
-// selects the derivative rule, while the value stays max(0, -d).
+// gradient"), for a constraint that counts as penetrating (pen): value -d and
+// tangent -dd; otherwise value 0 and tangent -alpha times the hand-point part
+// of dd. The leak is a surrogate derivative for hand points that do not
+// touch the object; along the object's pose from one projection iteration to
+// the next the derivative stays exact (with one iteration the pose carries no
+// tangent and the two coincide).
+// pen: d < -eps with eps the contact tolerance (see contact_tol), unless a
+// flip takes the other reading of a sample within rounding of -eps. The
+// tolerance keeps a constraint that a projection has just resolved (d = 0 up
+// to rounding) out of the active set: at d = 0 the active state, and with it
+// the derivative rule and the averaging count, would be decided by rounding.
 template <class S> S leaky_penetration(const S& d, const S& d_hand, double alpha, bool pen) {
   S c = pen ? -d : -alpha * d_hand;
-  c.v = std::max(0.0, -val(d));
+  if (!pen) c.v = 0.0;
   return c;
 }
-template <> double leaky_penetration<double>(const double& d, const double&, double, bool) {
-  return std::max(0.0, -d);
+template <> double leaky_penetration<double>(const double& d, const double&, double, bool pen) {
+  return pen ? -d : 0.0;
 }
+
+// The contact tolerance: a sample penetrates (counts as an active
+// constraint) when d < -contact_tol(P) = -5e-3 dt v0, half a percent of a
+// test's displacement.
+inline double contact_tol(const oparams& P) { return kContactTol * P.dt * P.v0; }
 
 // Coulomb friction of one active contact (Sec. III-C cites a friction model
 // without stating it; read here as positional friction in position-based
@@ -461,10 +479,13 @@ template <> double leaky_penetration<double>(const double& d, const double&, dou
 // (kinetic), as the Eq. (1) correction of a positional constraint along
 // t = dp_t / |dp_t|: lambda_t = -min(|dp_t|, mu C) / w_t with
 // w_t = |t|^2 + |a x t|^2 / (I/m). Adds (lambda_t t, lambda_t a x t) to the
-// sums of corrections.
+// sums of corrections. A slide no longer than smin (a thousandth of the
+// test displacement dt v0) has no direction: the contact gets no friction.
+// Without that floor a slide that is zero in exact arithmetic (a test
+// moving along a flat face's normal) would take its direction from rounding.
 template <class S>
 void add_friction(const S p[3], const S r[3], const S a[3], const S g[3], const S& C, double mu, double Im,
-                  S Wl[3], S Wa[3], Trace* tr = nullptr, int m = 0, int k = 0, int i = 0) {
+                  double smin, S Wl[3], S Wa[3], Trace* tr = nullptr, int m = 0, int k = 0, int i = 0) {
   const S gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
   if (!(val(gg) > 0.0)) return;
   const S ng = sqrt_(gg);
@@ -475,6 +496,13 @@ void add_friction(const S p[3], const S r[3], const S a[3], const S g[3], const 
   const S tl2 = dpt[0] * dpt[0] + dpt[1] * dpt[1] + dpt[2] * dpt[2];
   if (!(val(tl2) > 0.0)) return;
   const S tl = sqrt_(tl2);
+  // the floor: a flip takes the other side of it within rounding
+  bool slides = val(tl) > smin;
+  if (tr) {
+    if (tr->flips_of(m, k, i) & (1 << 5)) slides = !slides;
+    tr->report_slide(m, k, i, val(tl) - smin);
+  }
+  if (!slides) return;
   S th[3];
   for (int j = 0; j < 3; ++j) th[j] = dpt[j] / tl;
   S ut[3];
@@ -519,9 +547,10 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
     info.flip_axes = fl >> 1;
     sample_object(o, &p[3 * i], phi, n, &info);
     S d = phi - P.r_dil;
-    const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
-    if (pen) Lpen += 0.5 * (d * d);
+    // 1/2 C0^2 is smooth at d = 0: no reading of the side is needed here
+    if (val(d) < 0.0) Lpen += 0.5 * (d * d);
   }
+  const double eps = contact_tol(P);
 
   // 3. M velocity-test simulations (Sec. IV-A), each one PBD step (Sec. III-C)
   const double dirs[kSims][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
@@ -557,7 +586,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           info.flip_axes = fl >> 1;
           sample_object(o, r, phi, nrm, &info);
           S d = phi - P.r_dil;
-          const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
+          const bool pen = (val(d) < -eps) != ((fl & 1) != 0);
           S g[3], u[3];
           for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
           S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
@@ -572,7 +601,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
             S Wl[3] = {lam * g[0], lam * g[1], lam * g[2]};
             S Wa[3] = {lam * u[0], lam * u[1], lam * u[2]};
             // friction from the same sample, added to this constraint's update
-            if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, Wl, Wa, tr, m, k, i);
+            if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, kSlideMin * P.dt * P.v0, Wl, Wa, tr, m, k, i);
             for (int j = 0; j < 3; ++j) {
               x[j] = x[j] + P.omega * Wl[j];
               th[j] = th[j] + (P.omega / Im) * Wa[j];
@@ -584,14 +613,14 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
               s[0] = val(d); s[1] = val(g[0]); s[2] = val(g[1]); s[3] = val(g[2]);
               s[4] = val(w); s[5] = val(lam);
             }
-            if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
-            if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
+            if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d) + eps));
+            if (active && val(d) < -eps) tr->min_face = std::min(tr->min_face, info.face_margin);
             if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
-            if (active) tr->report(m, k, i, val(d), info, pen);
+            if (active) tr->report(m, k, i, val(d) + eps, info, pen);
             tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                     (static_cast<uint64_t>(info.cell[2]) << 32) |
                     (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
-                    (static_cast<uint64_t>(val(d) < 0.0) << 52) | (static_cast<uint64_t>(active) << 53));
+                    (static_cast<uint64_t>(val(d) < -eps) << 52) | (static_cast<uint64_t>(active) << 53));
           }
         }
         continue;
@@ -613,7 +642,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         sample_object(o, r, phi, nrm, &info);
         // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
         S d = phi - P.r_dil;
-        const bool pen = (val(d) < 0.0) != ((fl & 1) != 0);
+        const bool pen = (val(d) < -eps) != ((fl & 1) != 0);
         // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
         S g[3], u[3];
         for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
@@ -630,7 +659,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           lam = -C / w;
           for (int j = 0; j < 3; ++j) { Wl[j] += lam * g[j]; Wa[j] += lam * u[j]; }
           if (pen) ++n_active;
-          if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, Wl, Wa, tr, m, k, i);
+          if (P.mu > 0.0) add_friction(&p[3 * i], r, a, g, C, P.mu, Im, kSlideMin * P.dt * P.v0, Wl, Wa, tr, m, k, i);
         }
         if (tr) {
           if (tr->samples) {
@@ -638,14 +667,14 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
             s[0] = val(d); s[1] = val(g[0]); s[2] = val(g[1]); s[3] = val(g[2]);
             s[4] = val(w); s[5] = val(lam);
           }
-          if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d)));
-          if (active && val(d) < 0.0) tr->min_face = std::min(tr->min_face, info.face_margin);
+          if (active) tr->min_abs_d = std::min(tr->min_abs_d, std::fabs(val(d) + eps));
+          if (active && val(d) < -eps) tr->min_face = std::min(tr->min_face, info.face_margin);
           if (active) tr->min_face_all = std::min(tr->min_face_all, info.face_margin);
-          if (active) tr->report(m, k, i, val(d), info, pen);
+          if (active) tr->report(m, k, i, val(d) + eps, info, pen);
           tr->mix(static_cast<uint64_t>(info.cell[0]) | (static_cast<uint64_t>(info.cell[1]) << 16) |
                   (static_cast<uint64_t>(info.cell[2]) << 32) |
                   (static_cast<uint64_t>(info.clamped[0] + 2 * info.clamped[1] + 4 * info.clamped[2]) << 48) |
-                  (static_cast<uint64_t>(val(d) < 0.0) << 52) | (static_cast<uint64_t>(active) << 53));
+                  (static_cast<uint64_t>(val(d) < -eps) << 52) | (static_cast<uint64_t>(active) << 53));
         }
       }
       // all corrections at the same pose, averaged over the active constraints,
@@ -824,7 +853,7 @@ int oracle_step_ex(const ohand* hand, const oobject* obj, const oparams* prm, in
       n_flips < 0 || (n_flips > 0 && (!flip_b || !flips)) || max_amb < 0 || (max_amb > 0 && amb && !n_amb))
     return -1;
   for (int j = 0; j < n_flips; ++j)
-    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 4) return -1;
+    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 5) return -1;
   const double Im = inertia_over_mass(*obj);
   if (!(Im > 0.0)) return -2;
   const int nd = 6 + hand->n_links - 1;

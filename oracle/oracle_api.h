@@ -125,10 +125,13 @@ double oracle_inertia_over_mass(const oobject* obj);
 
 /* One grasp step for B candidates q [B][n_dof].
    loss [B]; terms [B][4] = (L_stable, L_pen, L_range, L_limit) or NULL;
-   grad [B][n_dof] or NULL; margins [B][3] = (min |d| over samples with
-   w > w_min; min face margin in cell units over the penetrating ones, d < 0,
-   whose gradient sets a correction; the same over every sample with
-   w > w_min, whose gradient the leaky rule reaches) or NULL. */
+   grad [B][n_dof] or NULL; margins [B][3] = (min |d + eps| over samples
+   with w > w_min, the distance from the activation d = -eps; min face margin
+   in cell units over the penetrating ones, d < -eps, whose gradient sets a
+   correction; the same over every sample with w > w_min, whose gradient the
+   leaky rule reaches) or NULL. A sample of the projection penetrates (is an
+   active constraint) when d < -eps, eps = 5e-3 dt v0 (contact tolerance); the
+   penetration energy L_pen counts d < 0. */
 int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B,
                 const double* q, double* loss, double* terms, double* grad, double* margins,
                 int n_threads);
@@ -137,19 +140,22 @@ int oracle_step(const ohand* hand, const oobject* obj, const oparams* prm, int B
    sample (m, k, i) = velocity test m, projection iteration k, contact i. */
 typedef struct {
   int m, k, i;
-  int what;  /* 0: the other side of d = 0 (counted active or not, and the
-                derivative rule of C = max(0, -d) that side takes; the value
-                stays max(0, -d)); 1, 2, 3: the cell on the other side of the
+  int what;  /* 0: the other side of the activation d = -eps (counted active
+                or not: the value of C and its derivative rule follow the
+                side); 1, 2, 3: the cell on the other side of the
                 cell face nearest to the sample along x, y, z (the value is
                 continuous there, the gradient is the other cell's); 4: the
                 other side of the friction cone (static or kinetic friction)
-                for a contact whose slide |dp_t| lies within kink_d of mu C */
+                for a contact whose slide |dp_t| lies within kink_d of mu C;
+                5: the other side of the friction floor (no friction for a
+                slide up to 1e-3 dt v0) for a slide within kink_d of it */
 } oflip;
 
-/* A sample with w > w_min within FP32 resolution of a decision: |d| below
-   kink_d (what 0), a coordinate within kink_face cell units of a cell face
-   (what 1 + axis), or a friction slide within kink_d of mu C (what 4);
-   margin = that distance; penetrating = the side of d = 0 the sample took. */
+/* A sample with w > w_min within FP32 resolution of a decision: d within
+   kink_d of the activation -eps (what 0), a coordinate within kink_face cell
+   units of a cell face (what 1 + axis), a friction slide within kink_d of
+   mu C (what 4) or of the friction floor (what 5); margin = that distance;
+   penetrating = the side of the activation the sample took. */
 typedef struct {
   int m, k, i, what;
   double margin;

@@ -351,15 +351,29 @@ struct Fric {
   float wt;    // generalized inverse mass along t
 };
 
+// Contact tolerance: a sample counts as penetrating (an active constraint,
+// with the full derivative of C = -d) when d < -kContactTol dt v0. A
+// constraint that a projection has just resolved sits at d = 0 up to
+// rounding; the tolerance keeps it out of the active set instead of letting
+// rounding pick its state, derivative rule and the averaging count. The
+// penetration energy at the rest pose counts d < 0 (1/2 d^2 is smooth there).
+constexpr float kContactTol = 5e-3f;
+
+// Slides up to this fraction of the test displacement dt v0 have no
+// direction and get no friction: a slide that is zero in exact arithmetic (a
+// test moving along a flat face's normal) would otherwise take its direction
+// from rounding.
+constexpr float kSlideMin = 1e-3f;
+
 // The friction direction of a sample with gradient g != 0 (every sample with
-// w > w_min has one); false when the slide is exactly normal (no tangent).
-__device__ __forceinline__ bool friction_dir(V3 g, V3 dp, V3 a, float inv_Im, Fric& f) {
+// w > w_min has one); false when the slide is no longer than the floor smin.
+__device__ __forceinline__ bool friction_dir(V3 g, V3 dp, V3 a, float inv_Im, float smin, Fric& f) {
   f.ing = rsq(dot(g, g));
   f.nh = f.ing * g;
   f.sn = dot(dp, f.nh);
   const V3 dpt = axpy(-f.sn, f.nh, dp);
   const float tl2 = dot(dpt, dpt);
-  if (!(tl2 > 0.0f)) return false;
+  if (!(tl2 > smin * smin)) return false;
   f.itl = rsq(tl2);
   f.tl = tl2 * f.itl;
   f.th = f.itl * dpt;

@@ -78,6 +78,7 @@ template <int LAY>
 __device__ unsigned long long gs_sweep(const GsCtx& c, V3 p, bool valid, float* Pm, float* Z, int* act) {
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im, om = c.P.omega;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
   if (Z && c.lane < 6) Z[c.lane] = Pm[c.lane];
   wave_lds_sync();
   unsigned long long applied = 0ull;
@@ -96,7 +97,7 @@ __device__ unsigned long long gs_sweep(const GsCtx& c, V3 p, bool valid, float* 
     const float d = s.phi - rd;
     const V3 u = cross(a, gn);
     const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
-    const unsigned long long on = __builtin_amdgcn_ballot_w64(live && d < 0.0f && w > wmin);
+    const unsigned long long on = __builtin_amdgcn_ballot_w64(live && d < dact && w > wmin);
     if (on == 0ull) break;
     const int j = __builtin_ctzll(on);
     wave_lds_sync();  // every lane has read Pm

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) pk_reduce(PlainArgs a) {
       const V3 g = v3(sm.y, sm.z, sm.w);
       const V3 u = cross(ap, g);
       const float w = fmaf(dot(u, u), a.S.inv_Im, dot(g, g));
-      if (w > a.P.w_min) {
+      if (d < -kContactTol * dv && w > a.P.w_min) {
         const float lam = d * rcp(w);
         acc[0] = fmaf(lam, g.x, acc[0]); acc[1] = fmaf(lam, g.y, acc[1]); acc[2] = fmaf(lam, g.z, acc[2]);
         acc[3] = fmaf(lam, u.x, acc[3]); acc[4] = fmaf(lam, u.y, acc[4]); acc[5] = fmaf(lam, u.z, acc[5]);
@@ -185,7 +185,7 @@ __global__ void pk_contact_bwd(PlainArgs a) {
     V3 abar = v3(0.0f, 0.0f, 0.0f);
     if (w > P.w_min) {
       const float iw = rcp(w);
-      if (d < 0.0f) {
+      if (d < -kContactTol * dv) {
         const float lam = d * iw;
         dbar = lb * iw;
         const float wbar2 = -2.0f * lb * lam * iw;

@@ -151,12 +151,13 @@ __device__ __forceinline__ bool contact_clear(const SdfView& S, V3 p, float rd, 
 // Coulomb friction of an active sample in the one-iteration pass (the
 // object at its predicted pose, unturned): the material point at the contact
 // moved by the test's prediction dp = -off. Adds lambda_t (t, a x t),
-// lambda_t = -min(|dp_t|, mu C) / w_t, to the lane's correction sums.
+// lambda_t = -min(|dp_t|, mu C) / w_t, to the lane's correction sums (none
+// for a slide up to the floor kSlideMin dt v0).
 __device__ __forceinline__ void add_friction(const Ctx& c, const LaneTest& lt, V3 a, V3 g, float d, bool on,
                                              float inv_Im, float W[6]) {
   if (!(c.P.mu > 0.0f) || !on) return;
   Fric f;
-  if (!friction_dir(g, -1.0f * lt.off, a, inv_Im, f)) return;
+  if (!friction_dir(g, -1.0f * lt.off, a, inv_Im, kSlideMin * (c.P.dt * c.P.v0), f)) return;
   const float mc = -c.P.mu * d;  // mu C, C = -d > 0
   const float delta = f.tl <= mc ? f.tl : mc;
   const float lam = -delta * rcp(f.wt);
@@ -179,7 +180,7 @@ __device__ __forceinline__ void friction_adjoint(const Ctx& c, const LaneTest& l
   if (!(c.P.mu > 0.0f) || !okw) return;
   Fric f;
   const V3 dp = -1.0f * lt.off;
-  if (!friction_dir(g, dp, a, inv_Im, f)) return;
+  if (!friction_dir(g, dp, a, inv_Im, kSlideMin * (c.P.dt * c.P.v0), f)) return;
   const float lbt = fmaf(WlB.x, f.th.x, fmaf(WlB.y, f.th.y, fmaf(WlB.z, f.th.z, dot(WaB, f.ut))));
   const float iwt = rcp(f.wt);
   const float mu = c.P.mu;
@@ -216,6 +217,7 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
   const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
@@ -254,8 +256,8 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
       sample_sdf_from(S, L[g & 1], lo[g & 1], hi[g & 1], s);
       const V3 gn = ROT ? mul(R, s.n) : s.n;
       const float d = s.phi - rd;
-      const bool act = valid && d < 0.0f;
-      lp = (first && act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      const bool act = valid && d < dact;
+      lp = (first && valid && d < 0.0f && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
       const V3 u = cross(a, gn);
       const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
       const bool on = act && w > wmin;
@@ -293,6 +295,7 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = S.inv_Im;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
   const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
@@ -357,8 +360,8 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       sample_sdf_from(S, L, lo, hi, s);
       const V3 gn_ = ROT ? mul(R, s.n) : s.n;
       const float d = s.phi - rd;
-      const bool act = valid && d < 0.0f;
-      lp = (first && act && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      const bool act = valid && d < dact;
+      lp = (first && valid && d < 0.0f && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
       const V3 u = cross(a, gn_);
       const float w = fmaf(dot(u, u), inv_Im, dot(gn_, gn_));
       const bool on = act && w > wmin;
@@ -419,6 +422,7 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
   const HandView& H = c.H;
   const SdfView& S = c.S;
   const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, inv_Im = S.inv_Im;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
   const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
   const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
   const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
@@ -469,9 +473,9 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
       const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
       const float lb = fmaf(WlB.x, gn.x, fmaf(WlB.y, gn.y, fmaf(WlB.z, gn.z, dot(WaB, u))));
       const bool okw = valid && w > wmin;
-      const bool pen = okw && d < 0.0f;
+      const bool pen = okw && d < dact;
       const float iw = rcp(w);
-      // lambda = d / w where d < 0 (full derivative); dC/dd = -alpha elsewhere
+      // lambda = d / w where active (full derivative); dC/dd = -alpha elsewhere
       float dbar = okw ? (pen ? lb * iw : alpha * lb * iw) : 0.0f;
       dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
       V3 ab = v3(0.0f, 0.0f, 0.0f);

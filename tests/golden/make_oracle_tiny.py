@@ -3,9 +3,9 @@ candidates of the tiny workload (3x3 hand, 512 contacts, 64^3 sphere grid,
 seeded inputs from the synthetic generators), for one and for three projection
 iterations. Only the oracle computes the stored values.
 
-Candidates are kept when every sample lies at least 1e-6 m from d = 0 and the
-FP64 gradient moves by less than 2.5e-4 of its norm under FP32-resolution
-changes of q, so the FP32 kernels can be held to the parity tolerances there.
+Candidates are kept when every sample lies at least 1e-6 m from the
+activation d = -eps (the contact tolerance) and the FP64 gradient moves by
+less than 2.5e-4 of its norm under FP32-resolution changes of q, so the FP32 kernels can be held to the parity tolerances there.
 Parameters and configurations are stored as FP32 values (what the kernels
 receive). Rerun after any change to the oracle's arithmetic; the commit then
 names the passage that justifies the change."""

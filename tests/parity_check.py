@@ -1,13 +1,16 @@
 """Comparison of per-candidate losses and gradients from the HIP path with the
 FP64 oracle, where FP32 rounding may decide a discrete choice differently.
 
-Two choices of the step depend on a comparison that FP32 can decide either
-way when the FP64 value lies within rounding of the threshold:
-  * the side of d = 0 (whether the constraint C = max(0, -d) is active, which
-    sets the averaging count and the derivative rule: full or leaky);
+Choices of the step that depend on a comparison FP32 can decide either way
+when the FP64 value lies within rounding of the threshold:
+  * the side of the activation d = -eps (eps = 5e-3 dt v0, the contact
+    tolerance: whether the constraint C = max(0, -d) is active, which sets
+    the averaging count and the derivative rule: full or leaky);
   * the cell of a coordinate that lies on a cell face (the value is
-    continuous there, the trilinear gradient is the other cell's).
-Both readings of such a sample are correct FP32 results of the method. The
+    continuous there, the trilinear gradient is the other cell's);
+  * with friction, the side of the friction cone (static or kinetic) and of
+    the friction floor (a slide up to 1e-3 dt v0 gets no friction).
+Every reading of such a sample are correct FP32 results of the method. The
 oracle reports the samples within kink_d of d = 0 and within kink_face cell
 units of a face (oracle_step_ex); a candidate that misses the tolerance on
 the oracle's own reading is compared again with every combination of the
@@ -20,7 +23,7 @@ FP32 error model behind the two bands:
   * contact positions come out of a chain of at most 9 rigid transforms in
     FP32; their error stays below 1e-5 of max(|p|, 1 cm) (the FK tolerance),
     about 1e-7 m here, so d = phi - r moves by about the same: a sample with
-    |d| below KINK_D = 2.5e-7 m may land on either side;
+    d within KINK_D = 2.5e-7 m of -eps may land on either side;
   * a grid coordinate u = (r - lo)/h in FP32 carries the position error over
     h (1-2 mm): about 1e-4 cell units. KINK_FACE = 2e-4 cell units covers it.
 Face readings of a coordinate that the seven tests share (an axis the test
@@ -42,23 +45,29 @@ KINK_FACE = 2e-4     # cell units
 SHARED = {1: (2, 3, 4, 5, 6), 2: (0, 1, 4, 5, 6), 3: (0, 1, 2, 3, 6)}
 
 
-def units_of(amb, shared=True):
-    """Independent FP32 decisions among a candidate's ambiguous samples, most
-    ambiguous first: (margin, [flip (m, k, i, what)]). shared: the averaged
-    projection, whose first iteration samples every test at the predicted,
-    unturned pose (in the Gauss-Seidel sweep each constraint sees the pose
-    the previous ones left, so no coordinate is shared)."""
+def units_of(amb, shared=True, kink_d=KINK_D, kink_face=KINK_FACE):
+    """Independent FP32 decisions among a candidate's ambiguous samples:
+    (margin relative to its band, [flip (m, k, i, what)]). The activation and
+    friction decisions come first (a flip changes which derivative rule or
+    correction applies, a large change of the gradient); cell-face decisions
+    after them (the value is continuous there and the gradient changes by the
+    grid's second differences); each kind most ambiguous first. shared: the
+    averaged projection, whose first iteration samples every test at the
+    predicted, unturned pose (in the Gauss-Seidel sweep each constraint sees
+    the pose the previous ones left, so no coordinate is shared)."""
     units = {}
     for (m, k, i, what, margin, _pen) in amb:
+        rel = margin / (kink_face if what in SHARED else kink_d)
         if shared and what in SHARED and k == 0 and m in SHARED[what]:
             key = ("shared", i, what)
             fl = [(mm, 0, i, what) for mm in SHARED[what]]
         else:
             key = (m, k, i, what)
             fl = [(m, k, i, what)]
-        if key not in units or margin < units[key][0]:
-            units[key] = (margin, fl)
-    return sorted(units.values(), key=lambda u: u[0])
+        if key not in units or rel < units[key][0]:
+            units[key] = (rel, fl, what in SHARED)
+    order = sorted(units.values(), key=lambda u: (u[2], u[0]))
+    return [(rel, fl) for rel, fl, _face in order]
 
 
 def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floor=None, max_units=6,
@@ -66,13 +75,23 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
             label="", say=print):
     """Checks every candidate; returns a report dict. gpu_grad may be None
     (loss only). gtol_per: optional per-candidate gradient tolerance (must be
-    >= gtol). conditioning: a candidate whose gradient still misses the
-    tolerance under every reading is measured for the conditioning of the
-    FP64 gradient itself (how far it moves when q changes at FP32
-    resolution, `conditioning`); it passes (status 4) if its error is within
-    four times that movement and that is at most cond_cap, and it is set
-    aside as not determined at FP32 resolution (status 2) if the movement
-    alone exceeds cond_cap / 4 and covers the error."""
+    >= gtol).
+
+    A candidate that misses the tolerance on the oracle's own reading is
+    compared again under the other readings of its most ambiguous decisions
+    (status 1 when one meets the tolerance). Without `conditioning` it is set
+    aside (status 2) when it holds more ambiguous decisions than max_units
+    and fails (status 3) otherwise.
+
+    With `conditioning` (several projection iterations, where rounding early
+    in the trajectory can move the later active sets) every miss is measured
+    for the conditioning of the FP64 result itself: how far the oracle's loss
+    and gradient move when q changes at FP32 resolution (`conditioning`). It
+    passes (status 4) when both errors are within four times those movements
+    and the gradient's is at most cond_cap; it is set aside as not determined
+    at FP32 resolution (status 2) when the movements cover the errors but
+    exceed the cap; otherwise it fails, however many ambiguous decisions it
+    holds."""
     q = np.asarray(q, np.float64)
     B = q.shape[0]
     if shared is None:
@@ -90,24 +109,29 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
     status = np.zeros(B, np.int32)  # 0 direct, 1 resolved by a reading, 2 set aside, 3 failed, 4 conditioning
     lerr = np.zeros(B)
     gerr = np.zeros(B)
-    n_units = np.array([len(units_of(a, shared)) for a in ref["amb"]])
+    n_units = np.asarray(ref["n_amb"])
     for b in range(B):
         gg = None if gpu_grad is None else gpu_grad[b]
         lerr[b], gerr[b] = errs(ref["loss"][b], None if gg is None else ref["grad"][b], gpu_loss[b], gg)
-    cond = np.zeros(B)
-    if conditioning and gpu_grad is not None:
-        # a gradient-only miss first meets the gradient's own sensitivity
-        idx = np.nonzero((lerr <= ltol) & (gerr > gt))[0]
-        if idx.size:
-            cond[idx] = conditioning_of(H, ob, op, q[idx])
-            for b in idx:
-                if gerr[b] <= 4.0 * cond[b] and 4.0 * cond[b] <= cond_cap:
-                    status[b] = 4
+    miss = ~((lerr <= ltol) & (gerr <= gt))
+    lcond = np.zeros(B)
+    gcond = np.zeros(B)
+    if conditioning and miss.any():
+        idx = np.nonzero(miss)[0]
+        lcond[idx], gcond[idx] = conditioning_of(H, ob, op, q[idx], floor=floor, grad=gpu_grad is not None)
+        for b in idx:
+            if (lerr[b] <= max(ltol, 4.0 * lcond[b]) and gerr[b] <= max(gt[b], 4.0 * gcond[b])
+                    and 4.0 * gcond[b] <= cond_cap):
+                status[b] = 4
     for b in range(B):
         gg = None if gpu_grad is None else gpu_grad[b]
-        if status[b] == 4 or (lerr[b] <= ltol and gerr[b] <= gt[b]):
+        if status[b] == 4 or not miss[b]:
             continue
-        units = units_of(ref["amb"][b], shared)
+        amb_b = ref["amb"][b]
+        if ref["n_amb"][b] > len(amb_b):  # the full report of this candidate
+            amb_b = O.step_ex(H, ob, op, q[b:b + 1], kink_d=kink_d, kink_face=kink_face,
+                              max_amb=int(ref["n_amb"][b]), grad=False)["amb"][0]
+        units = units_of(amb_b, shared, kink_d, kink_face)
         if not units:
             status[b] = 3
             continue
@@ -127,26 +151,28 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
         if best is not None:
             status[b] = 1
             lerr[b], gerr[b] = best
+        elif conditioning:
+            covered = lerr[b] <= max(ltol, 4.0 * lcond[b]) and gerr[b] <= max(gt[b], 4.0 * gcond[b])
+            status[b] = 2 if covered else 3
         else:
             status[b] = 2 if len(units) > max_units else 3
-    if conditioning and gpu_grad is not None:
-        # what is left with a matching loss: set aside where the FP64 gradient's
-        # own movement at FP32 resolution exceeds the cap and covers the error
-        for b in np.nonzero(((status == 2) | (status == 3)) & (lerr <= ltol))[0]:
-            if cond[b] == 0.0:
-                cond[b] = conditioning_of(H, ob, op, q[b:b + 1])[0]
-            if gerr[b] <= 4.0 * cond[b]:
-                status[b] = 2
     rep = {"B": B, "direct": int((status == 0).sum()), "resolved": int((status == 1).sum()),
-           "conditioned": int((status == 4).sum()), "max_cond": float(cond.max(initial=0.0)),
+           "conditioned": int((status == 4).sum()), "max_cond": float(gcond.max(initial=0.0)),
+           "max_lcond": float(lcond.max(initial=0.0)),
            "set_aside": int((status == 2).sum()), "failed": int((status == 3).sum()),
-           "max_lerr": float(lerr[(status <= 1) | (status == 4)].max(initial=0.0)),
+           "max_lerr": float(lerr[status <= 1].max(initial=0.0)),
            "max_gerr": float(gerr[status <= 1].max(initial=0.0)),
-           "ambiguous": int((n_units > 0).sum()), "status": status, "lerr": lerr, "gerr": gerr, "ref": ref}
+           "ambiguous": int((n_units > 0).sum()), "status": status, "lerr": lerr, "gerr": gerr,
+           "lcond": lcond, "gcond": gcond, "ref": ref}
     say(f"{label}: B={B} direct {rep['direct']}, resolved by an FP32 reading {rep['resolved']}, within the "
-        f"gradient's conditioning {rep['conditioned']} (largest {rep['max_cond']:.1e}), set aside "
-        f"{rep['set_aside']}, failed {rep['failed']} (candidates with ambiguous samples {rep['ambiguous']}); "
-        f"max loss rel err {rep['max_lerr']:.2e}, max grad rel err (direct, resolved) {rep['max_gerr']:.2e}")
+        f"conditioning {rep['conditioned']} (largest gradient movement {rep['max_cond']:.1e}, loss "
+        f"{rep['max_lcond']:.1e}), set aside {rep['set_aside']}, failed {rep['failed']} (candidates with "
+        f"ambiguous samples {rep['ambiguous']}); max loss rel err {rep['max_lerr']:.2e}, max grad rel err "
+        f"(direct, resolved) {rep['max_gerr']:.2e}")
+    for b in np.nonzero(status >= 2)[0]:
+        kind = {2: "set aside", 3: "FAILED", 4: "within conditioning"}[int(status[b])]
+        say(f"  {label}: candidate {b} {kind}: loss rel err {lerr[b]:.2e} (movement {lcond[b]:.1e}), grad rel "
+            f"err {gerr[b]:.2e} (movement {gcond[b]:.1e})")
     return rep
 
 
@@ -156,24 +182,31 @@ def assert_ok(rep, max_set_aside=0.01):
     assert rep["set_aside"] <= max_set_aside * rep["B"], ("set aside", rep["set_aside"], rep["B"])
 
 
-def conditioning_of(H, ob, op, q, n=3, seed=1):
-    return conditioning(H, ob, op, q, n=n, seed=seed)
+def conditioning_of(H, ob, op, q, n=3, seed=1, floor=None, grad=True):
+    """(loss movement, gradient movement) per candidate: `conditioning`."""
+    return conditioning(H, ob, op, q, n=n, seed=seed, floor=floor, grad=grad)
 
 
-def conditioning(H, ob, op, q, n=3, seed=1):
-    """How far the FP64 gradient moves, relative to its largest component,
-    when q changes at FP32 resolution (2^-24 relative): per candidate, the
-    largest of n perturbed evaluations."""
+def conditioning(H, ob, op, q, n=3, seed=1, floor=None, grad=True):
+    """How far the FP64 loss and gradient move when q changes at FP32
+    resolution (2^-24 relative): per candidate, the largest of n perturbed
+    evaluations, the loss relative to max(|L|, floor) (floor w_s v0 by
+    default) and the gradient relative to its largest component."""
     q = np.asarray(q, np.float64)
-    g0 = O.step(H, ob, op, q)["grad"]
-    scale = np.maximum(np.abs(g0).max(axis=1), 1e-30)
-    cond = np.zeros(q.shape[0])
+    floor = op.w_stable * op.v0 if floor is None else floor
+    r0 = O.step(H, ob, op, q, grad=grad)
+    lscale = np.maximum(np.abs(r0["loss"]), floor)
+    gscale = np.maximum(np.abs(r0["grad"]).max(axis=1), 1e-30) if grad else None
+    lc = np.zeros(q.shape[0])
+    gc = np.zeros(q.shape[0])
     rng = np.random.default_rng(seed)
     for _ in range(n):
         qp = q * (1.0 + rng.normal(size=q.shape) * 6e-8)
-        gp = O.step(H, ob, op, qp)["grad"]
-        cond = np.maximum(cond, np.abs(gp - g0).max(axis=1) / scale)
-    return cond
+        rp = O.step(H, ob, op, qp, grad=grad)
+        lc = np.maximum(lc, np.abs(rp["loss"] - r0["loss"]) / lscale)
+        if grad:
+            gc = np.maximum(gc, np.abs(rp["grad"] - r0["grad"]).max(axis=1) / gscale)
+    return lc, gc
 
 
 def near_tie_groups(loss, tol):

@@ -106,10 +106,14 @@ def test_large_workload_sampled(ctx):
     """65536 candidates x 8192 contacts on a 256^3 grid, 16 projection
     iterations, pose checkpoints every 4 (the backward replays each segment):
     the fused launch as benchmarked, 32 sampled candidates against the oracle.
-    With 16 iterations the gradient of |v| near v = 0 can be ill-conditioned:
-    a candidate whose gradient misses 1e-3 is held to four times the movement
-    of the FP64 gradient under FP32-resolution changes of q (capped at 1e-2),
-    and set aside where that movement alone exceeds the cap."""
+    Over 16 iterations of a deep penetration, rounding at the first
+    iterations (the gradient across a cell face, times a correction of
+    centimetres) can move later active sets: a candidate that misses is held
+    to four times the movement of the FP64 loss and gradient under
+    FP32-resolution changes of q (the gradient's capped at 1e-2), and set
+    aside only where that movement covers its error and exceeds the cap. One
+    of the 32 is (its FP64 gradient moves by 0.2 under such changes); the
+    test allows two."""
     from paper_2306_08132_amd.api import StepParams
     say("large workload: building the 256^3 grid")
     hand, grid, q = S.config_workload("large", device=DEV)
@@ -130,7 +134,7 @@ def test_large_workload_sampled(ctx):
     H, ob, op = O.Hand(hand.rounded()), O.Obj(grid), oparams(sp)
     rep = P.compare(loss.cpu().numpy()[idx], dq.cpu().numpy()[idx], H, ob, op, q32, conditioning=True,
                     max_units=4, label="large (32 sampled)", say=say)
-    P.assert_ok(rep, max_set_aside=0.25)
+    P.assert_ok(rep, max_set_aside=2.0 / 32)
     sd.unload()
     h.destroy()
 

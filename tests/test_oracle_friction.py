@@ -100,3 +100,25 @@ def test_friction_gradient_on_a_grid_and_leak_linearity(oracle_lib):
     g1 = O.step(H, ob, O.Params(mu=0.5, alpha_leak=1.0, r_dil=0.004), q)["grad"]
     gl = O.step(H, ob, O.Params(mu=0.5, alpha_leak=0.1, r_dil=0.004), q)["grad"]
     np.testing.assert_allclose(gl, g0 + 0.1 * (g1 - g0), rtol=1e-9, atol=1e-9 * np.abs(g1).max())
+
+
+@pytest.mark.parametrize("beta_mrad, stuck", [(0.0, False), (0.5, False), (2.0, True)])
+def test_friction_floor(oracle_lib, beta_mrad, stuck):
+    """A slide up to 1e-3 dt v0 has no direction and gets no friction: on a
+    plane tilted by beta from the +x test's direction, the +x test slides by
+    dt v0 sin(beta). At beta = 0 and 0.5 mrad (slides 0 and 5e-4 dt v0) the
+    object keeps its slide, as without friction; at 2 mrad (2e-3 dt v0, far
+    inside the cone for mu = 0.5) it sticks."""
+    beta = beta_mrad * 1e-3
+    n, ob = plane([np.cos(beta), np.sin(beta), 0.0])
+    hand = O.Hand(point_hand([[0.0, 0.0, 0.0]]))
+    P = O.Params(mu=0.5, r_dil=0.0)
+    x1 = O.trace(hand, ob, P, np.zeros(6))["poses"][0, 1, :3]
+    x0 = P.dt * P.v0 * np.array([1.0, 0.0, 0.0])
+    free = x0 - (x0 @ n) * n
+    if stuck:
+        assert np.linalg.norm(x1) < 1e-12 * P.dt * P.v0
+    else:
+        np.testing.assert_allclose(x1, free, atol=1e-15 * P.dt * P.v0)
+        x1f = O.trace(hand, ob, O.Params(mu=0.0, r_dil=0.0), np.zeros(6))["poses"][0, 1, :3]
+        assert np.array_equal(x1, x1f)

@@ -160,3 +160,40 @@ def test_phong_surface_converges_to_the_sphere(alpha):
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders >= 1.8), (alpha, errs, orders)
     assert errs[-1] < 2e-3
+
+
+@pytest.mark.parametrize("f", [0.5, 2.0, 40.0])
+def test_contact_tolerance_on_a_plane(oracle_lib, f):
+    """The activation threshold d < -eps, eps = 5e-3 dt v0 (contact
+    tolerance), on one contact and the plane x = offset seen by the +x test
+    (rotation frozen by a huge inertia): the test moves the object by dt v0
+    along +x, so the contact ends at d = -f eps. Below the tolerance (f = 0.5)
+    nothing happens; beyond it the correction removes all of it (x1 = x0 -
+    f eps along x, d = 0). A second iteration starts from a resolved contact
+    (d = 0 up to rounding), which is not active: the pose stays, and the
+    derivative of the final pose along the hand's x is that of the first
+    iteration, exactly 1 (the constraint moves the object with the hand)."""
+    dv = 1e-3
+    eps = 5e-3 * dv
+    off = -dv + f * eps
+    ob = O.Obj(kind=O.OBJ_PLANE, normal=np.array([1.0, 0.0, 0.0]), offset=off, inertia_over_mass=1e6)
+    hand = O.Hand(point_hand([[0.0, 0.0, 0.0]]))
+    for K in (1, 2):
+        P = O.Params(K=K, r_dil=0.0, alpha_leak=0.0, dt=dv, v0=1.0)
+        tr = O.trace(hand, ob, P, np.zeros(6))
+        x = tr["poses"][0, :, 0]  # +x test: x before each iteration and after the last
+        lam = tr["samples"][0, :, 0, 5]
+        assert x[0] == pytest.approx(dv, abs=1e-18)
+        if f < 1.0:
+            assert np.all(lam == 0.0) and np.all(x == x[0])
+        else:
+            assert x[1] == pytest.approx(dv - f * eps, abs=1e-15 * dv)
+            assert lam[0] != 0.0 and np.all(lam[1:] == 0.0)
+            assert np.all(x[1:] == x[1])
+    # the loss gradient along the wrist's x: with the contact active the +x
+    # test's final |x| = dv - f eps + (q_x) moves with q_x (derivative 1 over M dt
+    # in L_stable); below the tolerance it does not depend on q_x
+    P = O.Params(K=2, r_dil=0.0, alpha_leak=0.0, dt=dv, v0=1.0, w_pen=0.0, w_range=0.0, w_limit=0.0)
+    g = O.step(hand, ob, P, np.zeros((1, 6)))["grad"][0]
+    expect = (1.0 / (7 * dv)) if f > 1.0 else 0.0
+    assert g[0] == pytest.approx(expect, rel=1e-9, abs=1e-9)

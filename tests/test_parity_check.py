@@ -62,3 +62,20 @@ def test_shared_coordinates_flip_together():
     # test 4's face at k = 2, and test 0's own x coordinate
     assert [len(u[1]) for u in units] == [1, 5, 1, 1]
     assert units[1][1] == [(m, 0, 9, 1) for m in (2, 3, 4, 5, 6)]
+
+
+def test_conditioning_sets_aside_only_what_it_explains(tiny):
+    """With several iterations and conditioning measured, a wrong loss or
+    gradient fails however many ambiguous decisions the candidate holds: a
+    candidate is set aside only when the movement of the FP64 result under
+    FP32-resolution changes of q covers its error."""
+    H, ob, q = tiny
+    op = O.Params(r_dil=0.005, K=3)
+    ref = O.step(H, ob, op, q[:12])
+    lo, g = ref["loss"].copy(), ref["grad"].copy()
+    lo[3] *= 1.0 + 1e-2
+    g[4] *= 1.05
+    rep = P.compare(lo, g, H, ob, op, q[:12], conditioning=True, max_units=1, say=lambda *a: None)
+    assert rep["status"][3] == 3 and rep["status"][4] == 3
+    assert rep["lcond"][3] < 1e-3 and rep["gcond"][4] < 1e-2
+    assert np.all(rep["status"][[b for b in range(12) if b not in (3, 4)]] == 0)
