@@ -97,20 +97,6 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    e = d.get(kernel, {}).get(workload)
-    if not e or e.get("source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
-
-
 def cpu_baseline(hand, grid, q, prm_kw, budget_s=12.0):
     """The FP64 oracle (forward + dual-number gradient), unmodified, on the
     host's cores over a bounded sample of the same workload's candidates."""

@@ -72,7 +72,7 @@ def units_of(amb, shared=True, kink_d=KINK_D, kink_face=KINK_FACE):
 
 def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floor=None, max_units=6,
             gtol_per=None, kink_d=KINK_D, kink_face=KINK_FACE, shared=None, conditioning=False, cond_cap=1e-2,
-            label="", say=print):
+            drift=None, greedy=4, label="", say=print):
     """Checks every candidate; returns a report dict. gpu_grad may be None
     (loss only). gtol_per: optional per-candidate gradient tolerance (must be
     >= gtol).
@@ -91,12 +91,21 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
     and the gradient's is at most cond_cap; it is set aside as not determined
     at FP32 resolution (status 2) when the movements cover the errors but
     exceed the cap; otherwise it fails, however many ambiguous decisions it
-    holds."""
+    holds.
+
+    drift = (kink_d, kink_face): wider bands for a form whose FP32 state
+    drifts from FP64 inside the step (the Gauss-Seidel sweep, whose pose
+    carries every earlier constraint's rounding). A candidate that no
+    combination in the narrow bands resolves is then searched greedily over
+    the decisions inside the wide bands: up to `greedy` times the reading
+    that brings the result closest is added; it passes (status 5) when the
+    readings found meet the tolerance."""
     q = np.asarray(q, np.float64)
     B = q.shape[0]
     if shared is None:
         shared = op.projection == 0
-    ref = O.step_ex(H, ob, op, q, kink_d=kink_d, kink_face=kink_face, max_amb=256, grad=gpu_grad is not None)
+    want_grad = gpu_grad is not None
+    ref = O.step_ex(H, ob, op, q, kink_d=kink_d, kink_face=kink_face, max_amb=256, grad=want_grad)
     floor = loss_floor if loss_floor is not None else op.w_stable * op.v0
     gt = np.full(B, gtol) if gtol_per is None else np.maximum(np.asarray(gtol_per, np.float64), gtol)
 
@@ -106,7 +115,45 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
             return le, 0.0
         return le, np.abs(gg - grad_ref).max() / max(np.abs(grad_ref).max(), 1e-30)
 
-    status = np.zeros(B, np.int32)  # 0 direct, 1 resolved by a reading, 2 set aside, 3 failed, 4 conditioning
+    def under(b, flip_sets):
+        """(loss err, grad err) of candidate b under each set of readings."""
+        gg = None if gpu_grad is None else gpu_grad[b]
+        flips = [(row, *f) for row, fs in enumerate(flip_sets) for f in fs]
+        alt = O.step_ex(H, ob, op, np.repeat(q[b:b + 1], len(flip_sets), axis=0), flips=flips, grad=want_grad)
+        return [errs(alt["loss"][r], None if gg is None else alt["grad"][r], gpu_loss[b], gg)
+                for r in range(len(flip_sets))]
+
+    def enumerate_readings(b, cand, n_all):
+        # every combination of the other readings of the most ambiguous decisions
+        say(f"  {label}: candidate {b} (loss rel err {lerr[b]:.2e}, grad rel err {gerr[b]:.2e}): trying the "
+            f"other readings of {len(cand)} of its {n_all} ambiguous decisions")
+        subsets = [s for r in range(1, len(cand) + 1) for s in itertools.combinations(range(len(cand)), r)]
+        for le, ge in under(b, [[f for u in s for f in cand[u][1]] for s in subsets]):
+            if le <= ltol and ge <= gt[b]:
+                return le, ge
+        return None
+
+    def greedy_readings(b):
+        # readings inside the drift bands, added one at a time, closest first
+        wide = O.step_ex(H, ob, op, q[b:b + 1], kink_d=drift[0], kink_face=drift[1], max_amb=1 << 14, grad=False)
+        units = units_of(wide["amb"][0], shared, drift[0], drift[1])
+        say(f"  {label}: candidate {b}: greedy search over {len(units)} decisions in the drift bands")
+        chosen = []
+        for _ in range(greedy):
+            rest = [u for u in range(len(units)) if u not in chosen]
+            if not rest:
+                break
+            res = under(b, [[f for c in chosen + [u] for f in units[c][1]] for u in rest])
+            score = [max(le / ltol, ge / gt[b]) for le, ge in res]
+            k = int(np.argmin(score))
+            chosen.append(rest[k])
+            if score[k] <= 1.0:
+                return res[k]
+        return None
+
+    # 0 direct, 1 resolved by a reading, 2 set aside, 3 failed, 4 within conditioning,
+    # 5 resolved by readings in the drift bands
+    status = np.zeros(B, np.int32)
     lerr = np.zeros(B)
     gerr = np.zeros(B)
     n_units = np.asarray(ref["n_amb"])
@@ -118,58 +165,50 @@ def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floo
     gcond = np.zeros(B)
     if conditioning and miss.any():
         idx = np.nonzero(miss)[0]
-        lcond[idx], gcond[idx] = conditioning_of(H, ob, op, q[idx], floor=floor, grad=gpu_grad is not None)
+        lcond[idx], gcond[idx] = conditioning_of(H, ob, op, q[idx], floor=floor, grad=want_grad)
         for b in idx:
             if (lerr[b] <= max(ltol, 4.0 * lcond[b]) and gerr[b] <= max(gt[b], 4.0 * gcond[b])
                     and 4.0 * gcond[b] <= cond_cap):
                 status[b] = 4
-    for b in range(B):
-        gg = None if gpu_grad is None else gpu_grad[b]
-        if status[b] == 4 or not miss[b]:
-            continue
+    for b in np.nonzero(miss & (status != 4))[0]:
         amb_b = ref["amb"][b]
         if ref["n_amb"][b] > len(amb_b):  # the full report of this candidate
             amb_b = O.step_ex(H, ob, op, q[b:b + 1], kink_d=kink_d, kink_face=kink_face,
                               max_amb=int(ref["n_amb"][b]), grad=False)["amb"][0]
         units = units_of(amb_b, shared, kink_d, kink_face)
-        if not units:
-            status[b] = 3
-            continue
-        cand = units[:max_units]
-        say(f"  {label}: candidate {b} (loss rel err {lerr[b]:.2e}, grad rel err {gerr[b]:.2e}): trying the "
-            f"other readings of {len(cand)} of its {len(units)} ambiguous decisions")
-        subsets = [s for r in range(1, len(cand) + 1) for s in itertools.combinations(range(len(cand)), r)]
-        flips = [(row, *f) for row, s in enumerate(subsets) for u in s for f in cand[u][1]]
-        alt = O.step_ex(H, ob, op, np.repeat(q[b:b + 1], len(subsets), axis=0), flips=flips,
-                        grad=gpu_grad is not None)
-        best = None
-        for row in range(len(subsets)):
-            le, ge = errs(alt["loss"][row], None if gg is None else alt["grad"][row], gpu_loss[b], gg)
-            if le <= ltol and ge <= gt[b]:
-                best = (le, ge)
-                break
+        best = enumerate_readings(b, units[:max_units], len(units)) if units else None
         if best is not None:
             status[b] = 1
             lerr[b], gerr[b] = best
-        elif conditioning:
+            continue
+        if drift is not None:
+            best = greedy_readings(b)
+            if best is not None:
+                status[b] = 5
+                lerr[b], gerr[b] = best
+                continue
+        if conditioning:
             covered = lerr[b] <= max(ltol, 4.0 * lcond[b]) and gerr[b] <= max(gt[b], 4.0 * gcond[b])
             status[b] = 2 if covered else 3
         else:
             status[b] = 2 if len(units) > max_units else 3
+    ok = (status <= 1) | (status == 5)
     rep = {"B": B, "direct": int((status == 0).sum()), "resolved": int((status == 1).sum()),
+           "drift_resolved": int((status == 5).sum()),
            "conditioned": int((status == 4).sum()), "max_cond": float(gcond.max(initial=0.0)),
            "max_lcond": float(lcond.max(initial=0.0)),
            "set_aside": int((status == 2).sum()), "failed": int((status == 3).sum()),
-           "max_lerr": float(lerr[status <= 1].max(initial=0.0)),
-           "max_gerr": float(gerr[status <= 1].max(initial=0.0)),
+           "max_lerr": float(lerr[ok].max(initial=0.0)),
+           "max_gerr": float(gerr[ok].max(initial=0.0)),
            "ambiguous": int((n_units > 0).sum()), "status": status, "lerr": lerr, "gerr": gerr,
            "lcond": lcond, "gcond": gcond, "ref": ref}
-    say(f"{label}: B={B} direct {rep['direct']}, resolved by an FP32 reading {rep['resolved']}, within the "
-        f"conditioning {rep['conditioned']} (largest gradient movement {rep['max_cond']:.1e}, loss "
+    drift_note = f" (in the drift bands {rep['drift_resolved']})" if drift is not None else ""
+    say(f"{label}: B={B} direct {rep['direct']}, resolved by an FP32 reading {rep['resolved']}{drift_note}, within "
+        f"the conditioning {rep['conditioned']} (largest gradient movement {rep['max_cond']:.1e}, loss "
         f"{rep['max_lcond']:.1e}), set aside {rep['set_aside']}, failed {rep['failed']} (candidates with "
         f"ambiguous samples {rep['ambiguous']}); max loss rel err {rep['max_lerr']:.2e}, max grad rel err "
         f"(direct, resolved) {rep['max_gerr']:.2e}")
-    for b in np.nonzero(status >= 2)[0]:
+    for b in np.nonzero((status >= 2) & (status != 5))[0]:
         kind = {2: "set aside", 3: "FAILED", 4: "within conditioning"}[int(status[b])]
         say(f"  {label}: candidate {b} {kind}: loss rel err {lerr[b]:.2e} (movement {lcond[b]:.1e}), grad rel "
             f"err {gerr[b]:.2e} (movement {gcond[b]:.1e})")

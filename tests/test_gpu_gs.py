@@ -21,6 +21,11 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 GS = 1
 KINK_GS = 1e-6  # metres
+# The sweep's pose carries the rounding of every constraint applied before
+# (about 1e-7 m in each d, a random walk over up to a few hundred updates):
+# a few 1e-6 m. Readings inside these wider bands are searched greedily for
+# a candidate the narrow bands leave unresolved (tests/parity_check.py).
+DRIFT_GS = (4e-6, 2e-3)  # (metres, cell units: 3.8e-6 m at h = 1.9 mm)
 
 
 def say(*a):
@@ -66,7 +71,8 @@ def compare_gs(ctx, hand, grid, q, label, layout=0, loss_only=False, max_units=6
     loss, terms, dq = loss.cpu().numpy(), terms.cpu().numpy(), dq.cpu().numpy()
     q32 = q.astype(np.float32).astype(np.float64)
     rep = P.compare(loss, None if loss_only else dq, O.Hand(hand.rounded()), O.Obj(grid), op, q32,
-                    kink_d=KINK_GS, max_units=max_units, conditioning=conditioning, label=label, say=say)
+                    kink_d=KINK_GS, max_units=max_units, conditioning=conditioning, drift=DRIFT_GS, label=label,
+                    say=say)
     P.assert_ok(rep)
     sd.unload()
     h.destroy()
@@ -214,9 +220,10 @@ def test_gs_trajectory_teacher_forced(ctx):
     """30 fused Gauss-Seidel steps on the small workload along the dilation
     schedule from 1 cm, each checked from the GPU's own state: every
     candidate's loss within 1e-4 and gradient within 1e-3 of the oracle's
-    sweep at that q (constraints within FP32 resolution of d = 0 or of a cell
-    face under either reading), and the Adam update within 1e-6 of its
-    operands' magnitudes."""
+    sweep at that q (constraints within FP32 resolution of the activation or
+    of a cell face under either reading, readings in the sweep's drift bands
+    searched greedily, conditioning measured), and the Adam update within
+    1e-6 of its operands' magnitudes."""
     hand, grid, q0 = S.config_workload("tiny")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     H, ob = O.Hand(hand.rounded()), O.Obj(grid)
@@ -234,10 +241,10 @@ def test_gs_trajectory_teacher_forced(ctx):
         ctx.step_fused(h, sd, sp, qd, m, v, t + 1, loss=loss, dq=dq)
         torch.cuda.synchronize()
         lg, gg = loss.cpu().numpy(), dq.cpu().numpy()
-        rep = P.compare(lg, gg, H, ob, op, q_prev, kink_d=KINK_GS, conditioning=True, label=f"GS step {t}",
-                        say=lambda *a: None)
+        rep = P.compare(lg, gg, H, ob, op, q_prev, kink_d=KINK_GS, conditioning=True, drift=DRIFT_GS,
+                        label=f"GS step {t}", say=lambda *a: None)
         P.assert_ok(rep, max_set_aside=2.0 / B)
-        res.append(rep["resolved"] / B)
+        res.append((rep["resolved"] + rep["drift_resolved"]) / B)
         aside.append(rep["set_aside"] / B)
         worst_l = max(worst_l, rep["max_lerr"])
         worst_g = max(worst_g, rep["max_gerr"])
