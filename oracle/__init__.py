@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC = [os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "mesh.cpp")]
 
-OBJ_GRID, OBJ_SPHERE, OBJ_PLANE, OBJ_BOX = 0, 1, 2, 3
+OBJ_GRID, OBJ_SPHERE, OBJ_PLANE, OBJ_BOX, OBJ_MESH = 0, 1, 2, 3, 4
 M_SIMS = 7
 
 
@@ -45,7 +45,7 @@ class _Obj(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("lo", C.c_double * 3), ("h", C.c_double),
                 ("values", C.POINTER(C.c_float)), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("half", C.c_double * 3), ("normal", C.c_double * 3), ("offset", C.c_double),
-                ("inertia_over_mass", C.c_double), ("fd_normal", C.c_int)]
+                ("inertia_over_mass", C.c_double), ("fd_normal", C.c_int), ("mesh", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -191,10 +191,13 @@ class Obj:
     """Oracle view of an object: a grid (synth.Grid) or an analytic shape."""
 
     def __init__(self, grid=None, kind=OBJ_GRID, center=(0, 0, 0), radius=0.0, half=(0, 0, 0),
-                 normal=(0, 0, 1), offset=0.0, inertia_over_mass=0.0, fd_normal=False):
+                 normal=(0, 0, 1), offset=0.0, inertia_over_mass=0.0, fd_normal=False, mesh=None):
         self.values = None
+        self.mesh = mesh  # a Mesh: the Phong signed distance (inertia_over_mass must be given)
         c = _Obj()
-        c.kind = kind
+        c.kind = OBJ_MESH if mesh is not None else kind
+        if mesh is not None:
+            c.mesh = C.cast(C.pointer(mesh.c), C.c_void_p)
         if grid is not None:
             self.values = np.ascontiguousarray(grid.values, dtype=np.float32)
             c.kind = OBJ_GRID

@@ -215,6 +215,12 @@ struct SampleInfo {
   // to the sample along axis a (both cells meet there: the value is the same,
   // the gradient is the other cell's)
   int flip_axes = 0;
+  // mesh: input, take the other side of the flat surface; output, the flat
+  // distance (the sign's margin) and the exact gradient of the distance
+  int flip_sign = 0;
+  double sign_margin = 1e30;
+  bool has_grad_d = false;
+  double grad_d[3] = {0, 0, 0};
 };
 
 // Grid: trilinear interpolation of a vertex-centred grid (Sec. III-A). Per
@@ -301,9 +307,146 @@ void sample_grid_fd(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* 
   }
 }
 
+// Mesh object (Sec. III-B): Phong signed distance rho(r) = s |r - p|. The
+// closest point r* of the flat mesh is searched over every face in FP64; its
+// face and region (face interior, an edge or a vertex) and the sign s of the
+// flat mesh (winding number) are discrete and carry no derivative. r* is then
+// formed again in the scalar type from its region's formula (projection onto
+// the face plane or the edge line, or the vertex itself) with its
+// barycentric weights, and the Phong point follows:
+//   p = (1 - alpha) r* + alpha sum_b w_b psi_b(r*),
+//   psi_b(x) = x - ((x - v_b) . n_b) n_b (the tangent plane of vertex b).
+// The constraint normal is the gradient the paper states, (r - p) / rho
+// (the face normal at rho = 0). The exact gradient of rho, which the leaky
+// rule's hand-point part needs, is taken by forward-mode differentiation of
+// the same formula in r.
+struct MeshHit {
+  int face = -1;
+  int region = 0;  // 0 face interior, 1 edge (v0, v1), 2 vertex v0 (indices 0..2 within the face)
+  int v0 = 0, v1 = 0;
+  double s = 1.0;
+  double dist_flat = 0.0;
+};
+
+MeshHit mesh_closest(const omesh& m, const double r[3]) {
+  MeshHit h;
+  double best = INFINITY;
+  for (int f = 0; f < m.n_faces; ++f) {
+    const int* t = m.faces + 3 * f;
+    double y[3], w[3];
+    oracle_closest_on_triangle(m.vertices + 3 * t[0], m.vertices + 3 * t[1], m.vertices + 3 * t[2], r, y, w);
+    const double dd = std::sqrt((r[0] - y[0]) * (r[0] - y[0]) + (r[1] - y[1]) * (r[1] - y[1]) +
+                                (r[2] - y[2]) * (r[2] - y[2]));
+    if (dd < best) {
+      best = dd;
+      h.face = f;
+      int nz[3], k = 0;
+      for (int j = 0; j < 3; ++j)
+        if (w[j] != 0.0) nz[k++] = j;
+      h.region = k == 3 ? 0 : (k == 2 ? 1 : 2);
+      h.v0 = k >= 1 ? nz[0] : 0;
+      h.v1 = k >= 2 ? nz[1] : 0;
+    }
+  }
+  h.dist_flat = best;
+  h.s = oracle_winding_number(&m, r) > 0.5 ? -1.0 : 1.0;
+  return h;
+}
+
+template <class S> void phong_rho(const omesh& m, const MeshHit& h, const S r[3], S& rho, S n[3]) {
+  const int* t = m.faces + 3 * h.face;
+  const double* P[3] = {m.vertices + 3 * t[0], m.vertices + 3 * t[1], m.vertices + 3 * t[2]};
+  const double* Nv[3] = {m.normals + 3 * t[0], m.normals + 3 * t[1], m.normals + 3 * t[2]};
+  double e1[3], e2[3], N[3];
+  for (int i = 0; i < 3; ++i) { e1[i] = P[1][i] - P[0][i]; e2[i] = P[2][i] - P[0][i]; }
+  N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nn = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+  S x[3], w[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+  if (h.region == 0) {
+    // projection onto the face plane, weights from the sub-triangle areas
+    S off = konst<S>(0.0);
+    for (int i = 0; i < 3; ++i) off += (r[i] - P[0][i]) * N[i];
+    for (int i = 0; i < 3; ++i) x[i] = r[i] - (off / nn) * N[i];
+    for (int j = 0; j < 2; ++j) {
+      // w_j = ((P[j+2] - P[j+1]) x (x - P[j+1])) . N / |N|^2
+      const double* A = P[(j + 1) % 3];
+      const double* Bv = P[(j + 2) % 3];
+      const double u[3] = {Bv[0] - A[0], Bv[1] - A[1], Bv[2] - A[2]};
+      const S v[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};
+      const S c0 = u[1] * v[2] - u[2] * v[1], c1 = u[2] * v[0] - u[0] * v[2], c2 = u[0] * v[1] - u[1] * v[0];
+      w[j] = (c0 * N[0] + c1 * N[1] + c2 * N[2]) / nn;
+    }
+    w[2] = 1.0 - w[0] - w[1];
+  } else if (h.region == 1) {
+    // projection onto the edge's line
+    const double* A = P[h.v0];
+    const double* Bv = P[h.v1];
+    const double d[3] = {Bv[0] - A[0], Bv[1] - A[1], Bv[2] - A[2]};
+    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    S tp = konst<S>(0.0);
+    for (int i = 0; i < 3; ++i) tp += (r[i] - A[i]) * d[i];
+    tp = tp / dd;
+    for (int i = 0; i < 3; ++i) x[i] = A[i] + tp * d[i];
+    w[h.v0] = 1.0 - tp;
+    w[h.v1] = tp;
+  } else {
+    for (int i = 0; i < 3; ++i) x[i] = konst<S>(P[h.v0][i]);
+    w[h.v0] = konst<S>(1.0);
+  }
+  // Phong point
+  S curved[3] = {konst<S>(0.0), konst<S>(0.0), konst<S>(0.0)};
+  for (int b = 0; b < 3; ++b) {
+    S hb = konst<S>(0.0);
+    for (int i = 0; i < 3; ++i) hb += (x[i] - P[b][i]) * Nv[b][i];
+    for (int i = 0; i < 3; ++i) curved[i] += w[b] * (x[i] - hb * Nv[b][i]);
+  }
+  S dv[3];
+  for (int i = 0; i < 3; ++i) dv[i] = r[i] - ((1.0 - m.alpha) * x[i] + m.alpha * curved[i]);
+  const S d2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+  if (val(d2) > 0.0) {
+    const S dist = sqrt_(d2);
+    rho = h.s * dist;
+    for (int i = 0; i < 3; ++i) n[i] = dv[i] / rho;
+  } else {
+    rho = konst<S>(0.0);
+    const double l = std::sqrt(nn);
+    for (int i = 0; i < 3; ++i) n[i] = konst<S>(N[i] / l);
+  }
+}
+
+template <class S>
+void sample_mesh(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
+  const double rv[3] = {val(r[0]), val(r[1]), val(r[2])};
+  MeshHit h = mesh_closest(*o.mesh, rv);
+  if (info && info->flip_sign) h.s = -h.s;
+  phong_rho(*o.mesh, h, r, phi, n);
+  if (info) {
+    Dual<3> r3[3], rho3, n3[3];
+    for (int i = 0; i < 3; ++i) { r3[i] = Dual<3>(rv[i]); r3[i].d[i] = 1.0; }
+    phong_rho(*o.mesh, h, r3, rho3, n3);
+    info->has_grad_d = true;
+    for (int i = 0; i < 3; ++i) info->grad_d[i] = rho3.d[i];
+    info->sign_margin = h.dist_flat;
+    // the discrete state, for the signature: the closest feature (a face, an
+    // edge by its sorted vertices, a vertex; faces that share the feature
+    // give the same point) and the sign
+    const int* t = o.mesh->faces + 3 * h.face;
+    const int a = t[h.v0], b = t[h.v1];
+    info->cell[0] = h.region == 0 ? h.face : std::min(a, b);
+    info->cell[1] = h.region == 1 ? std::max(a, b) : 0;
+    info->cell[2] = h.region;
+    info->clamped[0] = h.s > 0.0 ? 1 : 0;
+  }
+}
+
 template <class S>
 void sample_object(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
   switch (o.kind) {
+    case OBJ_MESH:
+      sample_mesh(o, r, phi, n, info);
+      return;
     case OBJ_GRID:
       if (o.fd_normal) sample_grid_fd(o, r, phi, n, info);
       else sample_grid(o, r, phi, n, info);
@@ -409,7 +552,8 @@ struct Trace {
   std::vector<oamb>* amb = nullptr;
   // flips of sample (m, k, i): bit 0 = the other side of the activation
   // d = -eps, bit 1 + a = the other cell along axis a, bit 4 the other side
-  // of the friction cone, bit 5 of the friction floor
+  // of the friction cone, bit 5 of the friction floor, bit 6 of a mesh's
+  // flat surface
   int flips_of(int m, int k, int i) const {
     int f = 0;
     for (int j = 0; j < n_flips; ++j)
@@ -428,6 +572,7 @@ struct Trace {
     if (std::fabs(gap) < kink_d) amb->push_back(oamb{m, k, i, 0, std::fabs(gap), pen ? 1 : 0});
     for (int a = 0; a < 3; ++a)
       if (info.axis_margin[a] < kink_face) amb->push_back(oamb{m, k, i, 1 + a, info.axis_margin[a], pen ? 1 : 0});
+    if (info.sign_margin < kink_d) amb->push_back(oamb{m, k, i, 6, info.sign_margin, pen ? 1 : 0});
   }
   void mix(uint64_t x) {
     for (int i = 0; i < 8; ++i) { signature ^= (x >> (8 * i)) & 0xff; signature *= 1099511628211ull; }
@@ -440,6 +585,27 @@ inline double hand_part(const double& d, const double*, const double*) { return 
 template <int N> Dual<N> hand_part(const Dual<N>& d, const Dual<N>* g, const Dual<N>* p) {
   Dual<N> r(d.v);
   for (int t = 0; t < N; ++t) r.d[t] = g[0].v * p[0].d[t] + g[1].v * p[1].d[t] + g[2].v * p[2].d[t];
+  return r;
+}
+
+// The gradient of d in the hand point, world frame: the constraint normal g,
+// except for a mesh, whose stated normal (r - p) / rho is not the exact
+// gradient of rho; there R times the exact gradient the sampler reports.
+struct HandGrad {
+  double v[3];
+};
+template <class S> HandGrad hand_grad(const S g[3], const S R[9], const SampleInfo& info) {
+  HandGrad hg;
+  for (int j = 0; j < 3; ++j)
+    hg.v[j] = info.has_grad_d ? val(R[3 * j]) * info.grad_d[0] + val(R[3 * j + 1]) * info.grad_d[1] +
+                                    val(R[3 * j + 2]) * info.grad_d[2]
+                              : val(g[j]);
+  return hg;
+}
+inline double hand_part(const double& d, const HandGrad&, const double*) { return d; }
+template <int N> Dual<N> hand_part(const Dual<N>& d, const HandGrad& g, const Dual<N>* p) {
+  Dual<N> r(d.v);
+  for (int t = 0; t < N; ++t) r.d[t] = g.v[0] * p[0].d[t] + g.v[1] * p[1].d[t] + g.v[2] * p[2].d[t];
   return r;
 }
 
@@ -545,6 +711,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
     SampleInfo info;
     const int fl = tr ? tr->flips_of(kSims - 1, 0, i) : 0;
     info.flip_axes = fl >> 1;
+    info.flip_sign = (fl >> 6) & 1;
     sample_object(o, &p[3 * i], phi, n, &info);
     S d = phi - P.r_dil;
     // 1/2 C0^2 is smooth at d = 0: no reading of the side is needed here
@@ -584,12 +751,13 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           SampleInfo info;
           const int fl = tr ? tr->flips_of(m, k, i) : 0;
           info.flip_axes = fl >> 1;
+          info.flip_sign = (fl >> 6) & 1;
           sample_object(o, r, phi, nrm, &info);
           S d = phi - P.r_dil;
           const bool pen = (val(d) < -eps) != ((fl & 1) != 0);
           S g[3], u[3];
           for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-          S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
+          S C = leaky_penetration(d, hand_part(d, hand_grad(g, R, info), &p[3 * i]), P.alpha_leak, pen);
           u[0] = a[1] * g[2] - a[2] * g[1];
           u[1] = a[2] * g[0] - a[0] * g[2];
           u[2] = a[0] * g[1] - a[1] * g[0];
@@ -639,6 +807,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         SampleInfo info;
         const int fl = tr ? tr->flips_of(m, k, i) : 0;
         info.flip_axes = fl >> 1;
+        info.flip_sign = (fl >> 6) & 1;
         sample_object(o, r, phi, nrm, &info);
         // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
         S d = phi - P.r_dil;
@@ -646,7 +815,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
         S g[3], u[3];
         for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-        S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
+        S C = leaky_penetration(d, hand_part(d, hand_grad(g, R, info), &p[3 * i]), P.alpha_leak, pen);
         u[0] = a[1] * g[2] - a[2] * g[1];
         u[1] = a[2] * g[0] - a[0] * g[2];
         u[2] = a[0] * g[1] - a[1] * g[0];
@@ -731,6 +900,9 @@ bool valid_hand(const ohand* h) {
 bool valid_obj(const oobject* o) {
   if (!o) return false;
   if (o->kind == OBJ_GRID) return o->n >= 2 && o->h > 0.0 && o->values && (o->fd_normal == 0 || o->fd_normal == 1);
+  if (o->kind == OBJ_MESH)
+    return o->mesh && o->mesh->n_faces >= 1 && o->mesh->vertices && o->mesh->normals && o->mesh->faces &&
+           o->inertia_over_mass > 0.0;
   return o->kind >= OBJ_SPHERE && o->kind <= OBJ_BOX;
 }
 
@@ -853,7 +1025,7 @@ int oracle_step_ex(const ohand* hand, const oobject* obj, const oparams* prm, in
       n_flips < 0 || (n_flips > 0 && (!flip_b || !flips)) || max_amb < 0 || (max_amb > 0 && amb && !n_amb))
     return -1;
   for (int j = 0; j < n_flips; ++j)
-    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 5) return -1;
+    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 6) return -1;
   const double Im = inertia_over_mass(*obj);
   if (!(Im > 0.0)) return -2;
   const int nd = 6 + hand->n_links - 1;

@@ -40,7 +40,18 @@ typedef struct {
   const int* contact_link;     /* [n_contacts] */
 } ohand;
 
-enum { OBJ_GRID = 0, OBJ_SPHERE = 1, OBJ_PLANE = 2, OBJ_BOX = 3 };
+/* A closed triangle mesh with outward (counter-clockwise) faces and unit
+   vertex normals for the Phong surface (Sec. III-B). */
+typedef struct {
+  int n_vertices;
+  const double* vertices;  /* [n_vertices][3] */
+  const double* normals;   /* [n_vertices][3] */
+  int n_faces;
+  const int* faces;        /* [n_faces][3] */
+  double alpha;            /* Phong blend: 0 flat, 1 curved */
+} omesh;
+
+enum { OBJ_GRID = 0, OBJ_SPHERE = 1, OBJ_PLANE = 2, OBJ_BOX = 3, OBJ_MESH = 4 };
 
 typedef struct {
   int kind;
@@ -64,6 +75,10 @@ typedef struct {
      axis, seven queries per sample (the earlier method's normal that
      Sec. III-A contrasts with, kept for comparison) */
   int fd_normal;
+  /* mesh: the Phong signed distance of this mesh (Sec. III-B; brute force
+     over its faces, sign by the winding number); inertia_over_mass must be
+     given (> 0) */
+  const omesh* mesh;
 } oobject;
 
 typedef struct {
@@ -84,16 +99,6 @@ typedef struct {
                          is removed up to mu C (static below, kinetic above) */
 } oparams;
 
-/* A closed triangle mesh with outward (counter-clockwise) faces and unit
-   vertex normals for the Phong surface (Sec. III-B). */
-typedef struct {
-  int n_vertices;
-  const double* vertices;  /* [n_vertices][3] */
-  const double* normals;   /* [n_vertices][3] */
-  int n_faces;
-  const int* faces;        /* [n_faces][3] */
-  double alpha;            /* Phong blend: 0 flat, 1 curved */
-} omesh;
 
 /* Phong signed distance at n points r [n][3] (mesh.cpp): rho [n], grad [n][3]
    = (r - p) / rho, closest [n][3] = closest point of the flat mesh, face [n]
@@ -148,13 +153,16 @@ typedef struct {
                 other side of the friction cone (static or kinetic friction)
                 for a contact whose slide |dp_t| lies within kink_d of mu C;
                 5: the other side of the friction floor (no friction for a
-                slide up to 1e-3 dt v0) for a slide within kink_d of it */
+                slide up to 1e-3 dt v0) for a slide within kink_d of it;
+                6: the other side of a mesh's flat surface (the sign of the
+                Phong distance) for a sample within kink_d of it */
 } oflip;
 
 /* A sample with w > w_min within FP32 resolution of a decision: d within
    kink_d of the activation -eps (what 0), a coordinate within kink_face cell
    units of a cell face (what 1 + axis), a friction slide within kink_d of
-   mu C (what 4) or of the friction floor (what 5); margin = that distance;
+   mu C (what 4) or of the friction floor (what 5), a mesh sample within
+   kink_d of the flat surface (what 6); margin = that distance;
    penetrating = the side of the activation the sample took. */
 typedef struct {
   int m, k, i, what;
