@@ -176,6 +176,14 @@ grasp_status grasp_unload_mesh(grasp_ctx* ctx, grasp_mesh_id mesh);
 grasp_status grasp_mesh_sample(grasp_ctx* ctx, grasp_mesh_id mesh, int32_t n, const float* r, float* out,
                                void* hip_stream);
 
+/* Debugging and tests: the sample the mesh step (grasp_step_fused_mesh) takes
+ * at n points r (dev [n][3]): out (dev [n][8]) = rho, the stated normal
+ * (r - p) / rho, the exact gradient of rho through the closest point and the
+ * Phong point, and the closest feature's region (0 face interior, 1 edge,
+ * 2 vertex). Asynchronous on hip_stream. */
+grasp_status grasp_debug_mesh_step_sample(grasp_ctx* ctx, grasp_mesh_id mesh, int32_t n, const float* r,
+                                          float* out, void* hip_stream);
+
 typedef struct {
   int32_t n;                /* vertices per axis, 2..512 */
   float lo[3];              /* position of vertex (0,0,0) */
@@ -333,6 +341,28 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
                               const grasp_step_params* p, int32_t B, float* q, float* m, float* v,
                               int32_t t, float lr, float b1, float b2, float eps, float* loss,
                               float* terms, float* dq, void* hip_stream);
+
+/* The fused step on a mesh object (Sec. III-B's Phong signed distance as the
+ * constraint's rho, Sec. III-C): every sample of every iteration queries the
+ * mesh through its hierarchy instead of a grid, with the constraint normal
+ * (r - p) / rho the paper states and, in the adjoint, the exact derivative of
+ * rho and of that normal through the closest point (face interior, edge or
+ * vertex) and the Phong point. Arguments as grasp_step_fused, with the mesh
+ * of grasp_load_mesh and the object's I/m (<= 0: 2/5 R_eq^2 from the mesh's
+ * volume). The averaged projection only (EINVAL for Gauss-Seidel), mu = 0
+ * (EINVAL otherwise); no locality order or tile choice: two candidates per
+ * workgroup. Asynchronous on hip_stream. */
+grasp_status grasp_step_fused_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mesh_id mesh,
+                                   const grasp_step_params* p, float inertia_over_mass, int32_t B, float* q,
+                                   float* m, float* v, int32_t t, float lr, float b1, float b2, float eps,
+                                   float* loss, float* terms, float* dq, void* hip_stream);
+
+/* Debugging and tests: the forward pass of grasp_step_fused_mesh with the
+ * trace of grasp_debug_trace (contact points, poses, per-sample d, g, w,
+ * lambda), in the same layouts. */
+grasp_status grasp_debug_trace_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mesh_id mesh,
+                                    const grasp_step_params* p, float inertia_over_mass, int32_t B, const float* q,
+                                    float* p_world, float* poses, float* samples, void* hip_stream);
 
 /* grasp_step_fused for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

@@ -216,11 +216,17 @@ struct SampleInfo {
   // the gradient is the other cell's)
   int flip_axes = 0;
   // mesh: input, take the other side of the flat surface; output, the flat
-  // distance (the sign's margin) and the exact gradient of the distance
+  // distance (the sign's margin)
   int flip_sign = 0;
   double sign_margin = 1e30;
-  bool has_grad_d = false;
-  double grad_d[3] = {0, 0, 0};
+  // mesh: input, take the nearest different point of the surface; output,
+  // how much farther it is (0 on the medial axis)
+  int flip_alt = 0;
+  double alt_margin = 1e30;
+  // mesh: input, take the neighbouring region of the closest point (face
+  // interior, edge, vertex); output, its distance to that region
+  int flip_region = 0;
+  double region_margin = 1e30;
 };
 
 // Grid: trilinear interpolation of a vertex-centred grid (Sec. III-A). Per
@@ -317,40 +323,132 @@ void sample_grid_fd(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* 
 //   p = (1 - alpha) r* + alpha sum_b w_b psi_b(r*),
 //   psi_b(x) = x - ((x - v_b) . n_b) n_b (the tangent plane of vertex b).
 // The constraint normal is the gradient the paper states, (r - p) / rho
-// (the face normal at rho = 0). The exact gradient of rho, which the leaky
-// rule's hand-point part needs, is taken by forward-mode differentiation of
-// the same formula in r.
+// (the face normal at rho = 0); the dual numbers carry the exact derivative
+// of rho and of that normal through r*, the weights and the Phong point. The
+// leaky rule's hand-point part takes the stated normal as the direction, as
+// it takes the trilinear gradient on a grid.
 struct MeshHit {
   int face = -1;
   int region = 0;  // 0 face interior, 1 edge (v0, v1), 2 vertex v0 (indices 0..2 within the face)
   int v0 = 0, v1 = 0;
   double s = 1.0;
   double dist_flat = 0.0;
+  double y[3] = {0, 0, 0};  // the closest point
+  // the neighbouring region of the same face nearest to the closest point
+  // (interior <-> edge <-> vertex) and how far the closest point is from it
+  int alt_region = 0, alt_v0 = 0, alt_v1 = 0;
+  double region_margin = INFINITY;
 };
 
-MeshHit mesh_closest(const omesh& m, const double r[3]) {
+// The closest point of face f to r as a hit (region from its weights).
+MeshHit face_hit(const omesh& m, int f, const double r[3], double& dist) {
   MeshHit h;
-  double best = INFINITY;
-  for (int f = 0; f < m.n_faces; ++f) {
-    const int* t = m.faces + 3 * f;
-    double y[3], w[3];
-    oracle_closest_on_triangle(m.vertices + 3 * t[0], m.vertices + 3 * t[1], m.vertices + 3 * t[2], r, y, w);
-    const double dd = std::sqrt((r[0] - y[0]) * (r[0] - y[0]) + (r[1] - y[1]) * (r[1] - y[1]) +
-                                (r[2] - y[2]) * (r[2] - y[2]));
-    if (dd < best) {
-      best = dd;
-      h.face = f;
-      int nz[3], k = 0;
-      for (int j = 0; j < 3; ++j)
-        if (w[j] != 0.0) nz[k++] = j;
-      h.region = k == 3 ? 0 : (k == 2 ? 1 : 2);
-      h.v0 = k >= 1 ? nz[0] : 0;
-      h.v1 = k >= 2 ? nz[1] : 0;
+  const int* t = m.faces + 3 * f;
+  double w[3];
+  oracle_closest_on_triangle(m.vertices + 3 * t[0], m.vertices + 3 * t[1], m.vertices + 3 * t[2], r, h.y, w);
+  dist = std::sqrt((r[0] - h.y[0]) * (r[0] - h.y[0]) + (r[1] - h.y[1]) * (r[1] - h.y[1]) +
+                   (r[2] - h.y[2]) * (r[2] - h.y[2]));
+  h.face = f;
+  int nz[3], k = 0;
+  for (int j = 0; j < 3; ++j)
+    if (w[j] != 0.0) nz[k++] = j;
+  h.region = k == 3 ? 0 : (k == 2 ? 1 : 2);
+  h.v0 = k >= 1 ? nz[0] : 0;
+  h.v1 = k >= 2 ? nz[1] : 0;
+  h.dist_flat = dist;
+  // distance (metres) from the closest point to the nearest other region
+  const double* P[3] = {m.vertices + 3 * t[0], m.vertices + 3 * t[1], m.vertices + 3 * t[2]};
+  auto sub = [](const double* a, const double* b, double* o) { for (int i = 0; i < 3; ++i) o[i] = a[i] - b[i]; };
+  auto dot3 = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  auto edge_param = [&](int a, int b) {  // parameter of r's projection on the line P[a] -> P[b], and |e|
+    double e[3], ra[3];
+    sub(P[b], P[a], e);
+    sub(r, P[a], ra);
+    const double ee = dot3(e, e);
+    return std::make_pair(dot3(ra, e) / ee, std::sqrt(ee));
+  };
+  if (h.region == 0) {
+    // the edge opposite the smallest weight: distance = w * height over that edge
+    int j = 0;
+    for (int i = 1; i < 3; ++i)
+      if (w[i] < w[j]) j = i;
+    const int a = (j + 1) % 3, b = (j + 2) % 3;
+    double e1[3], e2[3], N[3];
+    sub(P[1], P[0], e1);
+    sub(P[2], P[0], e2);
+    N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double area2 = std::sqrt(dot3(N, N));
+    h.alt_region = 1;
+    h.alt_v0 = std::min(a, b);
+    h.alt_v1 = std::max(a, b);
+    h.region_margin = w[j] * area2 / edge_param(a, b).second;
+  } else if (h.region == 1) {
+    // the vertex at the nearer end, or the interior when r projects just inside
+    const auto tp = edge_param(h.v0, h.v1);
+    const double to_vertex = std::min(tp.first, 1.0 - tp.first) * tp.second;
+    const int c = 3 - h.v0 - h.v1;
+    double e[3], rc[3], ec[3];
+    sub(P[h.v1], P[h.v0], e);
+    sub(r, P[h.v0], rc);
+    sub(P[c], P[h.v0], ec);
+    // the in-plane direction from the edge towards the third vertex
+    double perp[3];
+    const double te = dot3(ec, e) / dot3(e, e);
+    for (int i = 0; i < 3; ++i) perp[i] = ec[i] - te * e[i];
+    const double lp = std::sqrt(dot3(perp, perp));
+    const double to_interior = -dot3(rc, perp) / lp;  // > 0: r projects outside the face
+    if (to_vertex <= to_interior) {
+      h.alt_region = 2;
+      h.alt_v0 = tp.first < 0.5 ? h.v0 : h.v1;
+      h.alt_v1 = 0;
+      h.region_margin = to_vertex;
+    } else {
+      h.alt_region = 0;
+      h.region_margin = to_interior;
     }
+  } else {
+    // the vertex's edge whose line r projects nearest past the vertex
+    double bestm = INFINITY;
+    for (int o = 0; o < 3; ++o) {
+      if (o == h.v0) continue;
+      const auto tp = edge_param(h.v0, o);
+      const double mg = -tp.first * tp.second;  // > 0: r projects before the vertex
+      if (mg < bestm) {
+        bestm = mg;
+        h.alt_region = 1;
+        h.alt_v0 = std::min(h.v0, o);
+        h.alt_v1 = std::max(h.v0, o);
+      }
+    }
+    h.region_margin = bestm;
   }
-  h.dist_flat = best;
-  h.s = oracle_winding_number(&m, r) > 0.5 ? -1.0 : 1.0;
   return h;
+}
+
+// The closest point of the flat mesh (first face of least distance), and the
+// nearest different point of the surface (faces that share the closest edge
+// or vertex give the same point and do not count): near the medial axis the
+// two are nearly equidistant and FP32 may take either.
+void mesh_closest(const omesh& m, const double r[3], MeshHit& best, MeshHit& second) {
+  double bd = INFINITY;
+  for (int f = 0; f < m.n_faces; ++f) {
+    double d;
+    const MeshHit h = face_hit(m, f, r, d);
+    if (d < bd) { bd = d; best = h; }
+  }
+  double sd = INFINITY;
+  second = best;
+  second.dist_flat = INFINITY;
+  for (int f = 0; f < m.n_faces; ++f) {
+    double d;
+    const MeshHit h = face_hit(m, f, r, d);
+    const double sep = std::sqrt((h.y[0] - best.y[0]) * (h.y[0] - best.y[0]) + (h.y[1] - best.y[1]) * (h.y[1] - best.y[1]) +
+                                 (h.y[2] - best.y[2]) * (h.y[2] - best.y[2]));
+    if (sep > 1e-9 && d < sd) { sd = d; second = h; }
+  }
+  best.s = second.s = oracle_winding_number(&m, r) > 0.5 ? -1.0 : 1.0;
 }
 
 template <class S> void phong_rho(const omesh& m, const MeshHit& h, const S r[3], S& rho, S n[3]) {
@@ -419,16 +517,21 @@ template <class S> void phong_rho(const omesh& m, const MeshHit& h, const S r[3]
 template <class S>
 void sample_mesh(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* info) {
   const double rv[3] = {val(r[0]), val(r[1]), val(r[2])};
-  MeshHit h = mesh_closest(*o.mesh, rv);
+  MeshHit best, second;
+  mesh_closest(*o.mesh, rv, best, second);
+  const double gap = second.dist_flat - best.dist_flat;
+  MeshHit h = (info && info->flip_alt && std::isfinite(gap)) ? second : best;
   if (info && info->flip_sign) h.s = -h.s;
+  if (info && info->flip_region) {
+    h.region = best.alt_region;
+    h.v0 = best.alt_v0;
+    h.v1 = best.alt_v1;
+  }
   phong_rho(*o.mesh, h, r, phi, n);
   if (info) {
-    Dual<3> r3[3], rho3, n3[3];
-    for (int i = 0; i < 3; ++i) { r3[i] = Dual<3>(rv[i]); r3[i].d[i] = 1.0; }
-    phong_rho(*o.mesh, h, r3, rho3, n3);
-    info->has_grad_d = true;
-    for (int i = 0; i < 3; ++i) info->grad_d[i] = rho3.d[i];
-    info->sign_margin = h.dist_flat;
+    info->sign_margin = best.dist_flat;
+    info->alt_margin = std::isfinite(gap) ? gap : 1e30;
+    info->region_margin = std::fabs(best.region_margin);
     // the discrete state, for the signature: the closest feature (a face, an
     // edge by its sorted vertices, a vertex; faces that share the feature
     // give the same point) and the sign
@@ -553,7 +656,8 @@ struct Trace {
   // flips of sample (m, k, i): bit 0 = the other side of the activation
   // d = -eps, bit 1 + a = the other cell along axis a, bit 4 the other side
   // of the friction cone, bit 5 of the friction floor, bit 6 of a mesh's
-  // flat surface
+  // flat surface, bit 7 the nearest different point of a mesh, bit 8 the
+  // neighbouring region of a mesh's closest point
   int flips_of(int m, int k, int i) const {
     int f = 0;
     for (int j = 0; j < n_flips; ++j)
@@ -573,6 +677,8 @@ struct Trace {
     for (int a = 0; a < 3; ++a)
       if (info.axis_margin[a] < kink_face) amb->push_back(oamb{m, k, i, 1 + a, info.axis_margin[a], pen ? 1 : 0});
     if (info.sign_margin < kink_d) amb->push_back(oamb{m, k, i, 6, info.sign_margin, pen ? 1 : 0});
+    if (info.alt_margin < kink_d) amb->push_back(oamb{m, k, i, 7, info.alt_margin, pen ? 1 : 0});
+    if (info.region_margin < kink_d) amb->push_back(oamb{m, k, i, 8, info.region_margin, pen ? 1 : 0});
   }
   void mix(uint64_t x) {
     for (int i = 0; i < 8; ++i) { signature ^= (x >> (8 * i)) & 0xff; signature *= 1099511628211ull; }
@@ -588,26 +694,6 @@ template <int N> Dual<N> hand_part(const Dual<N>& d, const Dual<N>* g, const Dua
   return r;
 }
 
-// The gradient of d in the hand point, world frame: the constraint normal g,
-// except for a mesh, whose stated normal (r - p) / rho is not the exact
-// gradient of rho; there R times the exact gradient the sampler reports.
-struct HandGrad {
-  double v[3];
-};
-template <class S> HandGrad hand_grad(const S g[3], const S R[9], const SampleInfo& info) {
-  HandGrad hg;
-  for (int j = 0; j < 3; ++j)
-    hg.v[j] = info.has_grad_d ? val(R[3 * j]) * info.grad_d[0] + val(R[3 * j + 1]) * info.grad_d[1] +
-                                    val(R[3 * j + 2]) * info.grad_d[2]
-                              : val(g[j]);
-  return hg;
-}
-inline double hand_part(const double& d, const HandGrad&, const double*) { return d; }
-template <int N> Dual<N> hand_part(const Dual<N>& d, const HandGrad& g, const Dual<N>* p) {
-  Dual<N> r(d.v);
-  for (int t = 0; t < N; ++t) r.d[t] = g.v[0] * p[0].d[t] + g.v[1] * p[1].d[t] + g.v[2] * p[2].d[t];
-  return r;
-}
 
 // C = max(0, -d) with the leaky derivative rule (Sec. III-C, "Leaky
 // gradient"), for a constraint that counts as penetrating (pen): value -d and
@@ -712,6 +798,8 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
     const int fl = tr ? tr->flips_of(kSims - 1, 0, i) : 0;
     info.flip_axes = fl >> 1;
     info.flip_sign = (fl >> 6) & 1;
+    info.flip_alt = (fl >> 7) & 1;
+    info.flip_region = (fl >> 8) & 1;
     sample_object(o, &p[3 * i], phi, n, &info);
     S d = phi - P.r_dil;
     // 1/2 C0^2 is smooth at d = 0: no reading of the side is needed here
@@ -752,12 +840,14 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
           const int fl = tr ? tr->flips_of(m, k, i) : 0;
           info.flip_axes = fl >> 1;
           info.flip_sign = (fl >> 6) & 1;
+          info.flip_alt = (fl >> 7) & 1;
+          info.flip_region = (fl >> 8) & 1;
           sample_object(o, r, phi, nrm, &info);
           S d = phi - P.r_dil;
           const bool pen = (val(d) < -eps) != ((fl & 1) != 0);
           S g[3], u[3];
           for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-          S C = leaky_penetration(d, hand_part(d, hand_grad(g, R, info), &p[3 * i]), P.alpha_leak, pen);
+          S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
           u[0] = a[1] * g[2] - a[2] * g[1];
           u[1] = a[2] * g[0] - a[0] * g[2];
           u[2] = a[0] * g[1] - a[1] * g[0];
@@ -808,6 +898,8 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         const int fl = tr ? tr->flips_of(m, k, i) : 0;
         info.flip_axes = fl >> 1;
         info.flip_sign = (fl >> 6) & 1;
+        info.flip_alt = (fl >> 7) & 1;
+        info.flip_region = (fl >> 8) & 1;
         sample_object(o, r, phi, nrm, &info);
         // dilated surface: the r_dil level set (Sec. III-B, "SDF dilation")
         S d = phi - P.r_dil;
@@ -815,7 +907,7 @@ void candidate_step(const ohand& h, const oobject& o, double Im, const oparams& 
         // constraint Jacobian J_C = (dC/dx, dC/dtheta) = (g, a x g), g = R grad(phi)
         S g[3], u[3];
         for (int j = 0; j < 3; ++j) g[j] = R[3 * j] * nrm[0] + R[3 * j + 1] * nrm[1] + R[3 * j + 2] * nrm[2];
-        S C = leaky_penetration(d, hand_part(d, hand_grad(g, R, info), &p[3 * i]), P.alpha_leak, pen);
+        S C = leaky_penetration(d, hand_part(d, g, &p[3 * i]), P.alpha_leak, pen);
         u[0] = a[1] * g[2] - a[2] * g[1];
         u[1] = a[2] * g[0] - a[0] * g[2];
         u[2] = a[0] * g[1] - a[1] * g[0];
@@ -1025,7 +1117,7 @@ int oracle_step_ex(const ohand* hand, const oobject* obj, const oparams* prm, in
       n_flips < 0 || (n_flips > 0 && (!flip_b || !flips)) || max_amb < 0 || (max_amb > 0 && amb && !n_amb))
     return -1;
   for (int j = 0; j < n_flips; ++j)
-    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 6) return -1;
+    if (flip_b[j] < 0 || flip_b[j] >= B || flips[j].what < 0 || flips[j].what > 8) return -1;
   const double Im = inertia_over_mass(*obj);
   if (!(Im > 0.0)) return -2;
   const int nd = 6 + hand->n_links - 1;

@@ -155,14 +155,21 @@ typedef struct {
                 5: the other side of the friction floor (no friction for a
                 slide up to 1e-3 dt v0) for a slide within kink_d of it;
                 6: the other side of a mesh's flat surface (the sign of the
-                Phong distance) for a sample within kink_d of it */
+                Phong distance) for a sample within kink_d of it; 7: the
+                nearest different point of a mesh for a sample whose two
+                nearest points lie within kink_d of each other's distance
+                (near the medial axis); 8: the neighbouring region (face
+                interior, edge, vertex) of a mesh's closest point lying
+                within kink_d of it */
 } oflip;
 
 /* A sample with w > w_min within FP32 resolution of a decision: d within
    kink_d of the activation -eps (what 0), a coordinate within kink_face cell
    units of a cell face (what 1 + axis), a friction slide within kink_d of
    mu C (what 4) or of the friction floor (what 5), a mesh sample within
-   kink_d of the flat surface (what 6); margin = that distance;
+   kink_d of the flat surface (what 6), of the medial axis (what 7) or of
+   another region of its closest point (what 8);
+   margin = that distance;
    penetrating = the side of the activation the sample took. */
 typedef struct {
   int m, k, i, what;

@@ -139,6 +139,7 @@ SIGNATURES = [
     ("grasp_load_mesh", _I32, [_VP, C.POINTER(MeshDescC), C.POINTER(_U64)]),
     ("grasp_unload_mesh", _I32, [_VP, _U64]),
     ("grasp_mesh_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP]),
+    ("grasp_debug_mesh_step_sample", _I32, [_VP, _U64, _I32, _VP, _VP, _VP]),
     ("grasp_load_sdf_from_mesh", _I32, [_VP, _U64, C.POINTER(MeshGridDescC), C.POINTER(_U64)]),
     ("grasp_unload_sdf", _I32, [_VP, _U64]),
     ("grasp_load_eval_points", _I32, [_VP, _U64, C.POINTER(EvalDescC), C.POINTER(_U64)]),
@@ -156,6 +157,9 @@ SIGNATURES = [
                                 _F, _VP, _VP, _VP, _VP]),
     ("grasp_step_fused_static", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F,
                                 _F, _VP, _VP, _VP, _VP]),
+    ("grasp_step_fused_mesh", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _F, _I32, _VP, _VP, _VP, _I32, _F, _F,
+                                      _F, _F, _VP, _VP, _VP, _VP]),
+    ("grasp_debug_trace_mesh", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _F, _I32, _VP, _VP, _VP, _VP, _VP]),
     ("grasp_plain_workspace_bytes", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, C.POINTER(_SZ)]),
     ("grasp_plain_step", _I32, [_VP, _U64, _U64, C.POINTER(StepParamsC), _I32, _VP, _VP, _VP, _I32, _F, _F, _F, _F,
                                 _VP, _VP, _VP, _SZ, _VP]),

@@ -131,6 +131,16 @@ class Context:
         self.lib.call("grasp_step_fused", self.h, hand.id, sdf.id, C.byref(pc), q.shape[0], _ptr(q), _ptr(m),
                       _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq), _stream(stream))
 
+    def step_fused_mesh(self, hand, mesh, prm: StepParams, q, m, v, t: int, inertia_over_mass: float = 0.0, lr=1e-3,
+                        b1=0.9, b2=0.999, eps=1e-8, loss=None, terms=None, dq=None, stream=None):
+        """grasp_step_fused_mesh: the fused step with the mesh's Phong signed
+        distance sampled at every contact (inertia_over_mass <= 0: from the
+        mesh's volume)."""
+        pc = prm.c()
+        self.lib.call("grasp_step_fused_mesh", self.h, hand.id, mesh.id, C.byref(pc), float(inertia_over_mass),
+                      q.shape[0], _ptr(q), _ptr(m), _ptr(v), t, lr, b1, b2, eps, _ptr(loss), _ptr(terms), _ptr(dq),
+                      _stream(stream))
+
     def step_fused_static(self, hand, sdf, prm: StepParams, q, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
                           loss=None, terms=None, dq=None, stream=None):
         """grasp_step_fused_static: the fused step with no allocation (its
@@ -242,6 +252,17 @@ class Context:
                       _ptr(sm), _stream(stream))
         return {"p": pw, "poses": ps, "samples": sm}
 
+    def debug_trace_mesh(self, hand, mesh, prm: StepParams, q, inertia_over_mass: float = 0.0, stream=None):
+        """The mesh step's forward with its trace (as debug_trace)."""
+        B, dev = q.shape[0], q.device
+        pw = torch.empty((B, hand.n_contacts, 3), dtype=torch.float32, device=dev)
+        ps = torch.empty((B, 7, prm.K + 1, 6), dtype=torch.float32, device=dev)
+        sm = torch.empty((B, 7, prm.K, hand.n_contacts, 6), dtype=torch.float32, device=dev)
+        pc = prm.c()
+        self.lib.call("grasp_debug_trace_mesh", self.h, hand.id, mesh.id, C.byref(pc), float(inertia_over_mass), B,
+                      _ptr(q), _ptr(pw), _ptr(ps), _ptr(sm), _stream(stream))
+        return {"p": pw, "poses": ps, "samples": sm}
+
     def debug_forward_groups(self, hand, sdf, prm: StepParams, q, stream=None):
         """(groups gathered, groups) over the forward passes of one fused step at q."""
         cnt = torch.zeros(2, dtype=torch.int64, device=q.device)
@@ -332,6 +353,14 @@ class Mesh:
         """(rho, grad rho) [n][4] at device points r [n][3]."""
         out = torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
         self.ctx.lib.call("grasp_mesh_sample", self.ctx.h, self.id, r.shape[0], _ptr(r), _ptr(out), _stream(stream))
+        return out
+
+    def step_sample(self, r, stream=None):
+        """(rho, stated normal, exact gradient of rho, region) [n][8] at device
+        points r [n][3]: the sample the mesh step takes."""
+        out = torch.empty((r.shape[0], 8), dtype=torch.float32, device=r.device)
+        self.ctx.lib.call("grasp_debug_mesh_step_sample", self.ctx.h, self.id, r.shape[0], _ptr(r), _ptr(out),
+                          _stream(stream))
         return out
 
     def grid(self, n: int, lo, h: float, layout: int = 0, inertia_over_mass: float = 0.0) -> "Sdf":

@@ -793,6 +793,84 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
   return GRASP_OK;
 }
 
+namespace {
+// The hand and the mesh of a mesh step, the parameters checked, and the I/m
+// (<= 0: from the mesh's volume) into a.sdf.inv_Im.
+grasp_status resolve_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mesh_id mesh, const grasp_step_params* p,
+                          float inertia_over_mass, int32_t B, StepArgs* a) {
+  if (B < 0) return fail(GRASP_EINVAL, "B must be >= 0");
+  StepConsts prm;
+  grasp_status st = check_params(p, &prm);
+  if (st != GRASP_OK) return st;
+  if (p->projection != GRASP_PROJECTION_AVERAGED)
+    return fail(GRASP_EINVAL, "the step on a mesh runs the averaged projection only");
+  if (p->mu != 0.0f) return fail(GRASP_EINVAL, "the step on a mesh is frictionless (mu = 0)");
+  if (std::isnan(inertia_over_mass) || std::isinf(inertia_over_mass))
+    return fail(GRASP_EINVAL, "inertia_over_mass must be finite");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DevHand* h = find_hand(ctx, hand);
+  if (!h) return fail(GRASP_EINVAL, "unknown hand id");
+  auto it = ctx->meshes.find(mesh);
+  if (it == ctx->meshes.end()) return fail(GRASP_EINVAL, "unknown mesh id");
+  a->hand = h->view;
+  a->mesh = it->second->view;
+  double Im = inertia_over_mass;
+  if (!(Im > 0.0)) {
+    const double Req = std::cbrt(3.0 * it->second->volume / (4.0 * M_PI));
+    Im = 0.4 * Req * Req;
+  }
+  a->sdf.inv_Im = static_cast<float>(1.0 / static_cast<double>(static_cast<float>(Im)));
+  a->prm = prm;
+  a->B = B;
+  return GRASP_OK;
+}
+}  // namespace
+
+grasp_status grasp_debug_trace_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mesh_id mesh,
+                                    const grasp_step_params* p, float inertia_over_mass, int32_t B, const float* q,
+                                    float* p_world, float* poses, float* samples, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  StepArgs a{};
+  grasp_status st = resolve_mesh(ctx, hand, mesh, p, inertia_over_mass, B, &a);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && !q) return fail(GRASP_EINVAL, "q is NULL");
+  a.q = q;
+  a.trace_p = p_world;
+  a.trace_poses = poses;
+  a.trace_samples = samples;
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_step_mesh(a, STEP_FWD, false, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_trace_mesh launch");
+  return GRASP_OK;
+}
+
+grasp_status grasp_step_fused_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mesh_id mesh,
+                                   const grasp_step_params* p, float inertia_over_mass, int32_t B, float* q, float* m,
+                                   float* v, int32_t t, float lr, float b1, float b2, float eps, float* loss,
+                                   float* terms, float* dq, void* hip_stream) {
+  set_error("");
+  GRASP_CHECK_CTX(ctx);
+  StepArgs a{};
+  grasp_status st = resolve_mesh(ctx, hand, mesh, p, inertia_over_mass, B, &a);
+  if (st != GRASP_OK) return st;
+  if (B > 0 && (!q || !m || !v)) return fail(GRASP_EINVAL, "q/m/v is NULL");
+  st = check_adam(t, lr, b1, b2, eps);
+  if (st != GRASP_OK) return st;
+  a.q = q;
+  a.q_out = q;
+  a.m = m;
+  a.v = v;
+  a.loss = loss;
+  a.terms = terms;
+  a.dq = dq;
+  a.adam = adam_consts(t, lr, b1, b2, eps);
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_step_mesh(a, STEP_FUSED, true, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_mesh launch");
+  return GRASP_OK;
+}
+
 grasp_status grasp_step_fused_static(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id sdf,
                                      const grasp_step_params* p, int32_t B, float* q, float* m, float* v, int32_t t,
                                      float lr, float b1, float b2, float eps, float* loss, float* terms, float* dq,

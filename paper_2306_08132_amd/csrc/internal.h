@@ -71,6 +71,26 @@ constexpr int kBlockCells = 1 << kBlockShift;
 // (at 96^3 the two tie) and are the default.
 constexpr int kLayoutYZQuads = 0;
 constexpr int kLayoutZPairs = 1;
+// Not a grid layout: the step's object is a triangle mesh (MeshView), its
+// Phong signed distance queried through the hierarchy at every sample.
+constexpr int kLayoutMesh = 2;
+
+// A triangle mesh resident on the device (Sec. III-B): a bounding-volume
+// hierarchy in depth-first order and per-face records.
+//  nodes: [n_nodes][2] float4 (lo.xyz, a), (hi.xyz, count): a leaf (count > 0)
+//         holds faces [a, a + count); an internal node (count = 0) has its
+//         children at node + 1 and a
+//  tri:   [n_faces][3] float4 vertex positions (xyz), faces in leaf order
+//  info:  [n_faces][kMeshInfo] floats: Phong normals of the three vertices,
+//         face normal, pseudonormals of edges ab, bc, ca and of vertices a, b, c
+struct MeshView {
+  const float4* nodes;
+  const float4* tri;
+  const float* info;
+  int n_nodes;
+  int n_faces;
+  float alpha;  // Phong blend
+};
 
 // Device copy of the step parameters.
 struct StepConsts {
@@ -138,6 +158,9 @@ struct StepArgs {
   const int* order;     // [B] candidate taken by work item i (or null: i itself)
   unsigned long long* fwd_groups;  // [2] += (sample groups gathered, sample groups) over
                                    // every untraced forward pass (or null)
+  // a mesh object (nodes set): the step samples its Phong signed distance
+  // instead of the grid; sdf then carries only inv_Im
+  MeshView mesh;
   // debug trace (caller order), all optional
   float* trace_p;       // [B][Nc][3]
   float* trace_poses;   // [B][7][K+1][6]
@@ -154,6 +177,9 @@ struct TileCfg {
 bool valid_tile(TileCfg c);
 
 hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream);
+// The same step on a mesh object (a.mesh): one projection form (averaged),
+// no culling, two candidates per workgroup.
+hipError_t launch_step_mesh(const StepArgs& a, StepKind kind, bool adam, hipStream_t stream);
 
 // Candidates of at least this many get a locality order before the step.
 constexpr int kOrderMinB = 256;
@@ -191,25 +217,10 @@ hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone,
 // The same for every job of a batch table whose order pointer is set.
 hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int max_jobs, hipStream_t stream);
 
-// A triangle mesh resident on the device (Sec. III-B): a bounding-volume
-// hierarchy in depth-first order and per-face records.
-//  nodes: [n_nodes][2] float4 (lo.xyz, a), (hi.xyz, count): a leaf (count > 0)
-//         holds faces [a, a + count); an internal node (count = 0) has its
-//         children at node + 1 and a
-//  tri:   [n_faces][3] float4 vertex positions (xyz), faces in leaf order
-//  info:  [n_faces][kMeshInfo] floats: Phong normals of the three vertices,
-//         face normal, pseudonormals of edges ab, bc, ca and of vertices a, b, c
-struct MeshView {
-  const float4* nodes;
-  const float4* tri;
-  const float* info;
-  int n_nodes;
-  int n_faces;
-  float alpha;  // Phong blend
-};
 constexpr int kMeshInfo = 32;
 constexpr int kMeshStack = 32;  // traversal stack entries; the hierarchy is kept shallower
 hipError_t launch_mesh_sample(const MeshView& M, int n, const float* r, float* out4, hipStream_t stream);
+hipError_t launch_mesh_step_sample(const MeshView& M, int n, const float* r, float* out8, hipStream_t stream);
 hipError_t launch_mesh_fill_grid(const MeshView& M, int n, const float lo[3], float h, float* values,
                                  hipStream_t stream);
 

@@ -279,6 +279,25 @@ grasp_status grasp_mesh_sample(grasp_ctx* ctx, grasp_mesh_id id, int32_t n, cons
   return GRASP_OK;
 }
 
+grasp_status grasp_debug_mesh_step_sample(grasp_ctx* ctx, grasp_mesh_id id, int32_t n, const float* r, float* out,
+                                          void* hip_stream) {
+  set_error("");
+  if (const grasp_status st = check_ctx(ctx); st != GRASP_OK) return st;
+  if (n < 0) return fail(GRASP_EINVAL, "n must be >= 0");
+  if (n > 0 && (!r || !out)) return fail(GRASP_EINVAL, "r/out is NULL");
+  MeshView v;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DevMesh* m = find_mesh(ctx, id);
+    if (!m) return fail(GRASP_EINVAL, "unknown mesh id");
+    v = m->view;
+  }
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_mesh_step_sample(v, n, r, out, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "grasp_debug_mesh_step_sample launch");
+  return GRASP_OK;
+}
+
 grasp_status grasp_load_sdf_from_mesh(grasp_ctx* ctx, grasp_mesh_id id, const grasp_mesh_grid_desc* d,
                                       grasp_sdf_id* out) {
   set_error("");

@@ -35,6 +35,20 @@ __global__ void k_mesh_sample(MeshView M, int n, const float* __restrict__ r, fl
   out4[4 * i + 3] = g.z;
 }
 
+// The sample the grasp step takes on a mesh: rho, the stated normal, the
+// exact gradient of rho and the closest feature's region, [n][8].
+__global__ void k_mesh_step_sample(MeshView M, int n, const float* __restrict__ r, float* __restrict__ out8) {
+  const int i = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  MeshSample s;
+  mesh_sample(M, v3(r[3 * i], r[3 * i + 1], r[3 * i + 2]), s);
+  float* o = out8 + 8 * static_cast<size_t>(i);
+  o[0] = s.rho;
+  o[1] = s.n.x; o[2] = s.n.y; o[3] = s.n.z;
+  o[4] = s.grad.x; o[5] = s.grad.y; o[6] = s.grad.z;
+  o[7] = static_cast<float>(s.region);
+}
+
 // The grid's vertex (i, j, k) at lo + (i, j, k) h gets rho there.
 __global__ void k_mesh_fill_grid(MeshView M, int n, float lox, float loy, float loz, float h,
                                  float* __restrict__ values) {
@@ -54,6 +68,12 @@ __global__ void k_mesh_fill_grid(MeshView M, int n, float lox, float loy, float 
 hipError_t launch_mesh_sample(const MeshView& M, int n, const float* r, float* out4, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mesh_sample, dim3((n + 127) / 128), dim3(128), 0, stream, M, n, r, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_step_sample(const MeshView& M, int n, const float* r, float* out8, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mesh_step_sample, dim3((n + 127) / 128), dim3(128), 0, stream, M, n, r, out8);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 // a candidate's result is bit-identical whatever else runs on the GPU. No
 // workgroup barrier is used: waves never wait on each other.
 #include "device_common.h"
+#include "mesh_device.h"
 
 namespace grasp {
 
@@ -28,6 +29,7 @@ struct Ctx {
   float* lds;
   int lane;
   unsigned long long* groups;  // forward group counts (or null)
+  const MeshView& M;           // the mesh object of a mesh step (unused on grids)
 };
 
 // Link transforms T_l (Sec. III-C, p = FK(q)): lane l composes its own
@@ -393,11 +395,73 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
 // One forward projection iteration over all contacts: the 7 x 6 correction
 // sums W_m = sum_i lambda_i (g_i, u_i) (Eq. (1) per constraint, summed) and,
 // on the rest test of the first iteration, the penetration energy.
+// The forward pass on a mesh object: every sample queries the Phong signed
+// distance through the hierarchy (no block bounds); the arithmetic after the
+// sample is forward_full's.
+template <bool ROT, bool TRACE>
+__device__ void forward_mesh(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
+  const HandView& H = c.H;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, inv_Im = c.S.inv_Im;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
+  const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
+  const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
+  float R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  V3 x = v3(0.0f, 0.0f, 0.0f);
+  if constexpr (ROT) {
+    const float* U = test_consts(c, lt);
+    x = v3(U[0], U[1], U[2]);
+    for (int j = 0; j < 9; ++j) R[j] = U[3 + j];
+  }
+  float W[6] = {0, 0, 0, 0, 0, 0};
+  float lp = 0.0f, na = 0.0f;
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    stage_chunk(c, ch);
+    for (int g = 0; g < kGroups; ++g) {
+      const float4 P4 = P[kGroup * g + lt.sub];
+      const bool valid = __float_as_int(P4.w) >= 0 && lt.m < kSims;
+      const V3 a = ROT ? v3(P4.x, P4.y, P4.z) - x : v3(P4.x, P4.y, P4.z) + lt.off;
+      meshdev::MeshSample s;
+      meshdev::mesh_sample(c.M, ROT ? mul_t(R, a) : a, s);
+      const V3 gn = ROT ? mul(R, s.n) : s.n;
+      const float d = s.rho - rd;
+      const bool act = valid && d < dact;
+      lp = (first && valid && d < 0.0f && lt.m == kSims - 1) ? fmaf(0.5f * d, d, lp) : lp;
+      const V3 u = cross(a, gn);
+      const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
+      const bool on = act && w > wmin;
+      const float lam = on ? d * rcp(w) : 0.0f;
+      na += on ? 1.0f : 0.0f;
+      W[0] = fmaf(lam, gn.x, W[0]);
+      W[1] = fmaf(lam, gn.y, W[1]);
+      W[2] = fmaf(lam, gn.z, W[2]);
+      W[3] = fmaf(lam, u.x, W[3]);
+      W[4] = fmaf(lam, u.y, W[4]);
+      W[5] = fmaf(lam, u.z, W[5]);
+      if constexpr (TRACE) {
+        if (valid) {
+          const int i = ch * kChunk + kGroup * g + lt.sub;
+          float* o6 = trace_s + ((static_cast<size_t>(lt.m) * K + k) * H.Nc + H.perm[i]) * 6;
+          o6[0] = d; o6[1] = gn.x; o6[2] = gn.y; o6[3] = gn.z; o6[4] = w; o6[5] = lam;
+        }
+      }
+    }
+  }
+  test_sums<6>(c, W, c.lds + kOffWS, 6, false);
+  test_sums<1>(c, &na, c.lds + kOffCnt, 1, false);
+  lpen = wave_sum(lp);
+}
+
 template <bool KONE, int LAY>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
-  if (trace_s) forward_full<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
-  else forward_culled<!KONE, LAY>(c, first, lpen);
+  if constexpr (LAY == kLayoutMesh) {
+    if (trace_s) forward_mesh<!KONE, true>(c, first, lpen, trace_s, K, k);
+    else forward_mesh<!KONE, false>(c, first, lpen, nullptr, K, k);
+  } else {
+    if (trace_s) forward_full<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
+    else forward_culled<!KONE, LAY>(c, first, lpen);
+  }
   wave_lds_sync();
 }
 
@@ -536,9 +600,122 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
   wave_lds_sync();
 }
 
+// The backward pass on a mesh object: backward_lanes with the sample's
+// Phong distance, its exact gradient (for d) and the action of the stated
+// normal's derivative (for the penetrating samples' corrections) in place of
+// the grid's value, gradient and Hessian. No friction.
+template <bool ROT>
+__device__ void backward_mesh(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
+  const HandView& H = c.H;
+  const float rd = c.P.r_dil, wmin = c.P.w_min, alpha = c.P.alpha, inv_Im = c.S.inv_Im;
+  const float dact = -kContactTol * (c.P.dt * c.P.v0);  // active below
+  const LaneTest lt = lane_test(c.lane, c.P.dt * c.P.v0);
+  const float4* P = reinterpret_cast<const float4*>(c.lds + kOffP);
+  const int n_chunks = (H.Nc + kChunk - 1) / kChunk;
+  // link of the last contact (contacts are sorted by link)
+  const int last_link = H.clink[H.Nc - 1];
+  const float* U = test_consts(c, lt);
+  // seeds of this lane's test
+  const V3 WlB = v3(U[19], U[20], U[21]);
+  const V3 WaB = v3(U[22], U[23], U[24]);
+  const float pseed = (first && lt.m == kSims - 1) ? pen_seed : 0.0f;
+  Rot o;
+  V3 x = v3(0.0f, 0.0f, 0.0f);
+  if constexpr (ROT) {
+    load_rot(U, o);
+    x = v3(U[0], U[1], U[2]);
+  }
+  auto test_pt = [&](V3 p) { return ROT ? p - x : p + lt.off; };
+  auto frame_pt = [&](V3 a) { return ROT ? mul_t(o.R, a) : a; };
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  float XB[6] = {0, 0, 0, 0, 0, 0};
+  int cur = -1;
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    stage_chunk(c, ch);
+    for (int g = 0; g < kGroups; ++g) {
+      const float4 P4 = P[kGroup * g + lt.sub];
+      const int link = __float_as_int(P4.w);
+      const bool valid = link >= 0 && lt.m < kSims;
+      const V3 p = v3(P4.x, P4.y, P4.z);
+      const V3 a = test_pt(p);
+      meshdev::MeshSample s;
+      meshdev::mesh_sample(c.M, frame_pt(a), s);
+      const V3 gn = ROT ? mul(o.R, s.n) : s.n;
+      const float d = s.rho - rd;
+      const V3 u = cross(a, gn);
+      const float w = fmaf(dot(u, u), inv_Im, dot(gn, gn));
+      const float lb = fmaf(WlB.x, gn.x, fmaf(WlB.y, gn.y, fmaf(WlB.z, gn.z, dot(WaB, u))));
+      const bool okw = valid && w > wmin;
+      const bool pen = okw && d < dact;
+      const float iw = rcp(w);
+      // lambda = d / w where active: the exact derivative of d (and the
+      // penetration energy's); elsewhere the leak, dC/dd = -alpha, along the
+      // stated normal as the hand point's direction
+      float dbar = (okw && pen) ? lb * iw : 0.0f;
+      dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
+      const float leak = (okw && !pen) ? alpha * lb * iw : 0.0f;
+      V3 ab = v3(0.0f, 0.0f, 0.0f);
+      V3 gbar = v3(0.0f, 0.0f, 0.0f);
+      V3 rbar = axpy(dbar, s.grad, leak * s.n);
+      if (pen) {
+        const float lam = d * iw;
+        const float wbar2 = -2.0f * lb * lam * iw;
+        const V3 ubar = axpy(lam, WaB, (wbar2 * inv_Im) * u);
+        gbar = gbar + axpy(lam, WlB, wbar2 * gn);
+        ab = ab + cross(gn, ubar);
+        gbar = gbar + cross(ubar, a);
+        rbar = rbar + meshdev::mesh_ngrad_t(s, c.M.alpha, ROT ? mul_t(o.R, gbar) : gbar);
+      }
+      // a_bar of the sample (exactly 0 on invalid lanes: dbar = 0, no penetration)
+      const V3 pb = ab + (ROT ? mul(o.R, rbar) : rbar);
+      if constexpr (ROT) {
+        // the leak acts on the hand point only: a non-penetrating sample adds
+        // nothing to the adjoint of the object's pose
+        if (pose_adj && pen) {
+          V3 thb = v3(0.0f, 0.0f, 0.0f);
+          if (pen) thb = rot_vjp(o, 1.0f, s.n, gbar);
+          thb = thb - rot_vjp(o, -1.0f, a, rbar);
+          XB[0] -= pb.x; XB[1] -= pb.y; XB[2] -= pb.z;
+          XB[3] += thb.x; XB[4] += thb.y; XB[5] += thb.z;
+        }
+      }
+      const V3 tau = cross(p, pb);
+      const float v6[6] = {pb.x, pb.y, pb.z, tau.x, tau.y, tau.z};
+      // links of the group's first and last contacts (wave-uniform)
+      const int lf = __builtin_amdgcn_readfirstlane(__float_as_int(P[kGroup * g].w));
+      const int lz = __builtin_amdgcn_readfirstlane(__float_as_int(P[kGroup * g + kGroup - 1].w));
+      if (lf < 0) continue;  // past the last contact
+      const int ll = lz >= 0 ? lz : last_link;
+      if (lf == ll) {
+        if (lf != cur) {
+          if (cur >= 0) flush_link(c, cur, acc);
+          for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
+          cur = lf;
+        }
+        for (int j = 0; j < 6; ++j) acc[j] += v6[j];
+      } else {
+        if (cur >= 0) flush_link(c, cur, acc);
+        for (int j = 0; j < 6; ++j) acc[j] = 0.0f;
+        cur = -1;
+        for (int l = lf; l <= ll; ++l) {
+          float mv[6];
+          for (int j = 0; j < 6; ++j) mv[j] = link == l ? v6[j] : 0.0f;
+          flush_link(c, l, mv);
+        }
+      }
+    }
+  }
+  if (cur >= 0) flush_link(c, cur, acc);
+  // pose adjoint of the previous iteration: running adjoint += this pass's sums
+  if (ROT && pose_adj) test_sums<6>(c, XB, c.lds + kOffU + 25, kUStride, true);
+  wave_lds_sync();
+}
+
+
 template <bool KONE, int LAY>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
-  backward_lanes<!KONE, LAY>(c, first, pen_seed, pose_adj);
+  if constexpr (LAY == kLayoutMesh) backward_mesh<!KONE>(c, first, pen_seed, pose_adj);
+  else backward_lanes<!KONE, LAY>(c, first, pen_seed, pose_adj);
 }
 
 __device__ __forceinline__ float* pose_slot(float* lds, int s) { return lds + kOffPose + s * kSims * 6; }
@@ -581,7 +758,7 @@ template <bool KONE, int LAY>
 __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
-  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id(), A.fwd_groups};
+  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id(), A.fwd_groups, A.mesh};
   const int nd = H.n_dof;
   const int lane = c.lane;
   const float* qb = A.q + static_cast<size_t>(b) * nd;
@@ -841,6 +1018,19 @@ __device__ void order_block(const float* q, int nd, int B, V3 centre, int* out) 
   }
 }
 
+// The step on a mesh object: one wave per candidate, the same per-candidate
+// code with the mesh's Phong distance sampled in place of the grid.
+template <bool KONE>
+__global__ void __launch_bounds__(256) k_step_mesh(StepArgs A, int kind, int adam) {
+  extern __shared__ float smem[];
+  const int wpb = blockDim.x / kWave;
+  const int w = threadIdx.x / kWave;
+  const int item = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
+  if (item >= A.B) return;
+  float* lds = smem + static_cast<size_t>(w) * wave_lds_floats(A.prm.K, A.prm.ckpt);
+  candidate_step_lay<KONE, kLayoutMesh>(A, item, kind, adam != 0, lds);
+}
+
 __global__ void __launch_bounds__(kOrderThreads) k_order(const float* q, int nd, int B, SdfView S, int* out) {
   order_block(q, nd, B, grid_centre(S), out);
 }
@@ -1003,6 +1193,20 @@ hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg,
     launch_occ<true>(a, static_cast<int>(kind), adam, cfg, lds, stream);
   else
     launch_occ<false>(a, static_cast<int>(kind), adam, cfg, lds, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_mesh(const StepArgs& a, StepKind kind, bool adam, hipStream_t stream) {
+  if (a.B <= 0) return hipSuccess;
+  constexpr int kWpb = 2;
+  const size_t lds = wave_lds_floats(a.prm.K, a.prm.ckpt) * kWpb * sizeof(float);
+  const int blocks = (a.B + kWpb - 1) / kWpb;
+  if (a.prm.K == 1)
+    hipLaunchKernelGGL(k_step_mesh<true>, dim3(blocks), dim3(kWpb * kWave), lds, stream, a, static_cast<int>(kind),
+                       adam ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_step_mesh<false>, dim3(blocks), dim3(kWpb * kWave), lds, stream, a, static_cast<int>(kind),
+                       adam ? 1 : 0);
   return hipGetLastError();
 }
 

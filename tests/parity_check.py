@@ -9,7 +9,11 @@ when the FP64 value lies within rounding of the threshold:
   * the cell of a coordinate that lies on a cell face (the value is
     continuous there, the trilinear gradient is the other cell's);
   * with friction, the side of the friction cone (static or kinetic) and of
-    the friction floor (a slide up to 1e-3 dt v0 gets no friction).
+    the friction floor (a slide up to 1e-3 dt v0 gets no friction);
+  * on a mesh, the side of the flat surface (the sign of the Phong distance),
+    near the medial axis which of two nearly equidistant points of the
+    surface is the closest, and the region (face interior, edge, vertex) of a
+    closest point near a region's border.
 Every reading of such a sample are correct FP32 results of the method. The
 oracle reports the samples within kink_d of d = 0 and within kink_face cell
 units of a face (oracle_step_ex); a candidate that misses the tolerance on
@@ -47,27 +51,33 @@ SHARED = {1: (2, 3, 4, 5, 6), 2: (0, 1, 4, 5, 6), 3: (0, 1, 2, 3, 6)}
 
 def units_of(amb, shared=True, kink_d=KINK_D, kink_face=KINK_FACE):
     """Independent FP32 decisions among a candidate's ambiguous samples:
-    (margin relative to its band, [flip (m, k, i, what)]). The activation and
-    friction decisions come first (a flip changes which derivative rule or
-    correction applies, a large change of the gradient); cell-face decisions
-    after them (the value is continuous there and the gradient changes by the
-    grid's second differences); each kind most ambiguous first. shared: the
+    (margin relative to its band, [flip (m, k, i, what)]). The activation,
+    friction and mesh decisions of samples that correct the pose come first (a
+    flip changes which derivative rule or correction applies, a large change
+    of the gradient); then a mesh's other nearest point for samples that only
+    leak; cell-face decisions last (the value is continuous there and the
+    gradient changes by the grid's second differences); each tier most
+    ambiguous first. shared: the
     averaged projection, whose first iteration samples every test at the
     predicted, unturned pose (in the Gauss-Seidel sweep each constraint sees
     the pose the previous ones left, so no coordinate is shared)."""
     units = {}
-    for (m, k, i, what, margin, _pen) in amb:
+    for (m, k, i, what, margin, pen) in amb:
         rel = margin / (kink_face if what in SHARED else kink_d)
+        # tiers: decisions that change a correction; a mesh sample's other
+        # nearest point when the sample only leaks (its normal turns by the
+        # points' separation over the distance); cell faces
+        tier = 2 if what in SHARED else (1 if what in (7, 8) and not pen else 0)
         if shared and what in SHARED and k == 0 and m in SHARED[what]:
             key = ("shared", i, what)
             fl = [(mm, 0, i, what) for mm in SHARED[what]]
         else:
             key = (m, k, i, what)
             fl = [(m, k, i, what)]
-        if key not in units or rel < units[key][0]:
-            units[key] = (rel, fl, what in SHARED)
-    order = sorted(units.values(), key=lambda u: (u[2], u[0]))
-    return [(rel, fl) for rel, fl, _face in order]
+        if key not in units or (tier, rel) < units[key][:2]:
+            units[key] = (tier, rel, fl)
+    order = sorted(units.values(), key=lambda u: (u[0], u[1]))
+    return [(rel, fl) for _tier, rel, fl in order]
 
 
 def compare(gpu_loss, gpu_grad, H, ob, op, q, *, ltol=1e-4, gtol=1e-3, loss_floor=None, max_units=6,
