@@ -250,14 +250,27 @@ void sample_grid(const oobject& o, const S r[3], S& phi, S n[3], SampleInfo* inf
     else { ub = u; cl[a] = false; }
     c[a] = std::min(static_cast<int>(std::floor(val(ub))), N - 2);
     double k = std::min(std::max(std::round(val(u)), 0.0), N - 1.0);
+    bool outward = false;  // clamped by the other reading at a boundary face
     if (info && (info->flip_axes >> a & 1)) {
-      // the other cell at the nearest interior face k
       const int kf = static_cast<int>(k);
-      if (c[a] == kf && kf - 1 >= 0) c[a] = kf - 1;
-      else if (c[a] == kf - 1 && kf <= N - 2) c[a] = kf;
+      if (kf == 0 || kf == N - 1) {
+        // the box's own face: the other reading of a point within FP32 of
+        // it is inside (the trilinear slope) or clamped (the direction to
+        // the face, from the outside)
+        ub = konst<S>(static_cast<double>(kf));
+        outward = !cl[a];
+        cl[a] = !cl[a];
+        c[a] = std::min(kf, N - 2);
+      } else if (c[a] == kf) {
+        // the other cell at the nearest interior face k
+        c[a] = kf - 1;
+      } else if (c[a] == kf - 1) {
+        c[a] = kf;
+      }
     }
     f[a] = ub - static_cast<double>(c[a]);
     e[a] = cl[a] ? (u - ub) * o.h : konst<S>(0.0);
+    if (outward && (k == 0.0) == (val(e[a]) > 0.0)) e[a] = -e[a];
     margin = std::min(margin, std::fabs(val(u) - k));
     if (info) info->axis_margin[a] = std::fabs(val(u) - k);
   }

@@ -79,3 +79,42 @@ def test_conditioning_sets_aside_only_what_it_explains(tiny):
     assert rep["status"][3] == 3 and rep["status"][4] == 3
     assert rep["lcond"][3] < 1e-3 and rep["gcond"][4] < 1e-2
     assert np.all(rep["status"][[b for b in range(12) if b not in (3, 4)]] == 0)
+
+
+def test_grid_boundary_face_reading(oracle_lib):
+    """A sample on the grid box's own face (u = 0 along y) with z beyond the
+    box is read inside (the trilinear y-slope plus the direction to the clamped
+    point) or, as the other reading of that face, clamped along y (no y part).
+    An affine grid phi = 0.5 x + 0.25 y - 0.125 z + 1/16 has slope (0.5, 0.25,
+    -0.125), so the +x test's normal is g = (0.5, 0.25, 1) or g' = (0.5, 0, 1);
+    nothing penetrates and w_pen = 0, so the x-gradient of the loss changes by
+    the leak term of that sample alone,
+      w_s / (7 dt) alpha (e . g') g'_x / w' - (same with g),
+    w = |g|^2 + |r x g|^2 / (I/m). The oracle reports the face and the other
+    reading reproduces this number."""
+    from tests.helpers import dyadic_plane_grid, point_hand
+    grid = dyadic_plane_grid()
+    Im = 0.25
+    ob = O.Obj(grid, inertia_over_mass=Im)
+    p = np.array([0.3, -1.0, 1.5])  # y on the box's face, z half a unit above the box
+    H = O.Hand(point_hand([p]))
+    op = O.Params(r_dil=0.0, w_pen=0.0, alpha_leak=0.3)
+    q = np.zeros((1, 6))
+    dv = op.dt * op.v0
+    ref = O.step_ex(H, ob, op, q, kink_d=P.KINK_D, kink_face=P.KINK_FACE, max_amb=64)
+    assert (0, 0, 0, 2) in [tuple(int(x) for x in a[:4]) for a in ref["amb"][0]]
+    alt = O.step_ex(H, ob, op, q, flips=[(0, 0, 0, 0, 2)])
+    r = p - dv * np.array([1.0, 0.0, 0.0])
+    phi, g, _ = O.sample(ob, r[None])
+    assert np.allclose(g[0], [0.5, 0.25, 1.0], rtol=0, atol=1e-12)
+
+    def term(gv):
+        u = np.cross(r, gv)
+        w = gv @ gv + (u @ u) / Im
+        return gv[0] * op.alpha_leak * gv[0] / w
+
+    want = op.w_stable / (7 * op.dt) * (term(np.array([0.5, 0.0, 1.0])) - term(np.array([0.5, 0.25, 1.0])))
+    got = alt["grad"][0, 0] - ref["grad"][0, 0]
+    assert abs(want) > 1e-3
+    assert got == pytest.approx(want, rel=1e-9)
+    assert np.array_equal(alt["loss"], ref["loss"])
