@@ -492,6 +492,51 @@ def mesh_run(ctx, S, args):
     return out
 
 
+def mesh_step_run(ctx, S, hand, q0, h, sd, args):
+    """The grasp step with the object as a mesh queried at every sample
+    (Sec. III-B's Phong distance in Sec. III-C's step, forward and adjoint
+    through the closest and Phong points), beside the grid step, on the
+    differentiable-step hand (2048 contacts) and its first 1024 candidates
+    against a 5120-face ellipsoid mesh (Phong alpha 0.75), r_dil = 5 mm, K = 1."""
+    import numpy as np
+    import torch
+    from paper_2306_08132_amd.api import StepParams
+    print("bench: grasp step on a mesh object", file=sys.stderr, flush=True)
+    B, Nc = 1024, hand.n_contacts
+    gm = ctx.mesh(S.mesh_ellipsoid([0.05, 0.035, 0.04], subdivisions=4), 0.75)
+    Im = float(np.float32(0.4 * 0.04 ** 2))
+    prm = StepParams(K=1, r_dil=0.005)
+    stream = torch.cuda.current_stream()
+    res = {"candidates": B, "contacts": Nc, "faces": 5120, "phong_alpha": 0.75, "r_dil_m": 0.005, "iterations": 1}
+    for name in ("mesh", "grid"):
+        q = torch.tensor(q0[:B], dtype=torch.float32, device="cuda:0")
+        m, v = torch.zeros_like(q), torch.zeros_like(q)
+        loss = torch.empty(B, device="cuda:0")
+
+        def step(t):
+            if name == "mesh":
+                ctx.step_fused_mesh(h, gm, prm, q, m, v, t + 1, inertia_over_mass=Im, loss=loss, stream=stream)
+            else:
+                ctx.step_fused(h, sd, prm, q, m, v, t + 1, loss=loss, stream=stream)
+
+        step(0)
+        torch.cuda.synchronize()
+        n = 3 if name == "mesh" else 20
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for i in range(n):
+            ev[i][0].record(stream)
+            step(1 + i)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        res[name] = {"ms_per_step": ms, "contact_evals_per_s": B * Nc * M_SIMS / (ms * 1e-3), "steps": n}
+    res["mesh_over_grid_time"] = res["mesh"]["ms_per_step"] / res["grid"]["ms_per_step"]
+    gm.unload()
+    print(f"bench: mesh step {res['mesh']['ms_per_step']:.2f} ms, grid step {res['grid']['ms_per_step']:.3f} ms "
+          f"on {B} candidates", file=sys.stderr, flush=True)
+    return res
+
+
 def gs_run(ctx, S, hand, q0, h, sd, r0, avg_ms, args):
     """The Gauss-Seidel projection (Sec. III-C, constraints swept one after
     another) as a fused step with Adam on the same 4096 candidates, 2048
@@ -791,6 +836,8 @@ def main():
     if diff is not None:
         evaluation = None if args.no_eval else eval_run(ctx, S, hand2, grid2, q2, h2, sd2, loss2, args)
         gauss_seidel = None if args.no_gs else gs_run(ctx, S, hand2, q2, h2, sd2, 0.01, avg2, args)
+        if mesh is not None:
+            mesh["step"] = mesh_step_run(ctx, S, hand2, q2, h2, sd2, args)
     if cpu is not None:
         print("bench: oracle CPU matrix", file=sys.stderr, flush=True)
         work = {"large": (L["hand"], L["grid"], L["q0"], {"K": 16, "r_dil": 0.01})}

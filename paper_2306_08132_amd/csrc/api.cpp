@@ -250,19 +250,57 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
     for (int j = 0; j < 3; ++j)
       if (!finite(d->contact_local[3 * i + j])) return fail(GRASP_EINVAL, "contact_local not finite");
   }
-  // stable sort of contacts by link: slot -> caller index
+  // Two orders of the contacts, both sorted by link (so slot s has the same
+  // link in both). The step's: within a link along a Morton curve of the
+  // link-frame coordinates (10 bits per axis over the link's box), so that
+  // the contacts sharing a wave instruction, and the next ones, sample
+  // neighbouring grid cells. The Gauss-Seidel sweep's: the caller's order
+  // within a link (the sweep order is part of that projection's result).
+  // Each maps slot -> caller index.
+  std::vector<float> blo(3 * static_cast<size_t>(L), INFINITY), bhi(3 * static_cast<size_t>(L), -INFINITY);
+  for (int i = 0; i < Nc; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int l = d->contact_link[i];
+      blo[3 * l + j] = std::min(blo[3 * l + j], d->contact_local[3 * i + j]);
+      bhi[3 * l + j] = std::max(bhi[3 * l + j], d->contact_local[3 * i + j]);
+    }
+  auto spread = [](uint64_t v) {  // 10 bits -> every third bit
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x30000ff;
+    v = (v | (v << 8)) & 0x300f00f;
+    v = (v | (v << 4)) & 0x30c30c3;
+    v = (v | (v << 2)) & 0x9249249;
+    return v;
+  };
+  std::vector<uint64_t> key(Nc);
+  for (int i = 0; i < Nc; ++i) {
+    const int l = d->contact_link[i];
+    uint64_t m = 0;
+    for (int j = 0; j < 3; ++j) {
+      const float ext = bhi[3 * l + j] - blo[3 * l + j];
+      const float u = ext > 0.0f ? (d->contact_local[3 * i + j] - blo[3 * l + j]) / ext : 0.0f;
+      m |= spread(static_cast<uint64_t>(std::min(1023.0f, std::max(0.0f, u * 1023.0f)))) << j;
+    }
+    key[i] = (static_cast<uint64_t>(l) << 32) | m;
+  }
   std::vector<int> perm(Nc);
   std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d->contact_link[a] < d->contact_link[b]; });
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  std::vector<int> gperm(Nc);
+  std::iota(gperm.begin(), gperm.end(), 0);
+  std::stable_sort(gperm.begin(), gperm.end(), [&](int a, int b) { return d->contact_link[a] < d->contact_link[b]; });
   const int nch = (Nc + kWave - 1) / kWave;
   const int npad = nch * kWave;
-  std::vector<float> cx(npad, 0.0f), cy(npad, 0.0f), cz(npad, 0.0f);
+  std::vector<float> cx(npad, 0.0f), cy(npad, 0.0f), cz(npad, 0.0f), gx(npad, 0.0f), gy(npad, 0.0f), gz(npad, 0.0f);
   std::vector<int> clink(npad, 0), chunk(nch, 0), link_start(L + 1, 0);
   for (int s = 0; s < Nc; ++s) {
-    const int i = perm[s];
+    const int i = perm[s], k = gperm[s];
     cx[s] = d->contact_local[3 * i];
     cy[s] = d->contact_local[3 * i + 1];
     cz[s] = d->contact_local[3 * i + 2];
+    gx[s] = d->contact_local[3 * k];
+    gy[s] = d->contact_local[3 * k + 1];
+    gz[s] = d->contact_local[3 * k + 2];
     clink[s] = d->contact_link[i];
   }
   for (int s = 0; s < Nc; ++s) link_start[clink[s] + 1] = s + 1;
@@ -288,7 +326,9 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
       {cz.data(), cz.size() * 4, 0},         {parent.data(), parent.size() * 4, 0},
       {chain.data(), chain.size() * 4, 0},   {depth.data(), depth.size() * 4, 0},
       {clink.data(), clink.size() * 4, 0},   {chunk.data(), chunk.size() * 4, 0},
-      {perm.data(), perm.size() * 4, 0},     {link_start.data(), link_start.size() * 4, 0}};
+      {perm.data(), perm.size() * 4, 0},     {link_start.data(), link_start.size() * 4, 0},
+      {gx.data(), gx.size() * 4, 0},         {gy.data(), gy.size() * 4, 0},
+      {gz.data(), gz.size() * 4, 0}};
   size_t total = 0;
   for (auto& p : parts) { p.off = total; total += round_up(p.bytes, 256); }
   std::vector<char> host(total, 0);
@@ -326,6 +366,9 @@ grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* d, grasp_h
   h->view.chunk_lk = I(11);
   h->view.perm = I(12);
   h->view.link_start = I(13);
+  h->view.gcx = F(14);
+  h->view.gcy = F(15);
+  h->view.gcz = F(16);
   h->block = blk;
   h->bytes = total;
   h->contact_link.assign(d->contact_link, d->contact_link + Nc);

@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/grasp.h"
+#include "grasp.h"
 #include "arena.h"
 #include "eval.h"
 #include "internal.h"

@@ -8,7 +8,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/grasp.h"
+#include "grasp.h"
 #include "context.h"
 #include "eval.h"
 

@@ -53,11 +53,11 @@ struct GsCtx {
   int lane;
 };
 
-// World position of sorted contact i (0 for padding).
+// World position of the contact at sweep position i (0 for padding).
 __device__ __forceinline__ V3 contact_world(const GsCtx& c, int i, int& link) {
   link = c.H.clink[i];
   const float4* T4 = reinterpret_cast<const float4*>(c.lds + kGT + 12 * link);
-  return xform_point(T4[0], T4[1], T4[2], c.H.cx[i], c.H.cy[i], c.H.cz[i]);
+  return xform_point(T4[0], T4[1], T4[2], c.H.gcx[i], c.H.gcy[i], c.H.gcz[i]);
 }
 
 // Sample at object-frame point r (gathered only where live).

@@ -30,13 +30,16 @@ struct HandView {
   const int* depth;       // [L] number of valid chain entries
   const float* qlo;       // [n_dof]
   const float* qup;       // [n_dof]
-  const float* cx;        // [n_chunks * 64] link-local contact coordinates, sorted by link
-  const float* cy;
+  const float* cx;        // [n_chunks * 64] link-local contact coordinates, sorted by link and
+  const float* cy;        //   within a link along a Morton curve of these coordinates
   const float* cz;
   const int* clink;       // [n_chunks * 64] link of each sorted contact (0 in padding)
   const int* chunk_lk;    // [n_chunks] first link | (last link << 16) of the chunk's valid contacts
   const int* link_start;  // [L + 1] first sorted contact of each link
   const int* perm;        // [Nc] sorted slot -> caller index
+  const float* gcx;       // [n_chunks * 64] the same contacts in the Gauss-Seidel sweep order:
+  const float* gcy;       //   sorted by link, the caller's order within a link (slot s has the
+  const float* gcz;       //   same link in both orders)
 };
 
 // An object SDF resident on the device: vertex-centred N^3 grid, and the

@@ -11,7 +11,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/grasp.h"
+#include "grasp.h"
 #include "context.h"
 #include "internal.h"
 

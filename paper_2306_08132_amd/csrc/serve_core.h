@@ -16,7 +16,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/grasp.h"
+#include "grasp.h"
 
 namespace grasp {
 

@@ -45,7 +45,8 @@ def test_serving_loop_under_thread_sanitizer(tmp_path):
     exe = str(tmp_path / "sched_check")
     srcs = [os.path.join(ROOT, "tests", "native", "sched_check.cpp"), os.path.join(csrc, "serve_core.cpp"),
             os.path.join(csrc, "arena.cpp"), os.path.join(od, "oracle.cpp"), os.path.join(od, "mesh.cpp")]
-    cmd = ["g++", "-std=c++17", "-fsanitize=thread", "-g", "-O1", "-Wno-unknown-pragmas", f"-I{csrc}", f"-I{od}"] + \
+    cmd = ["g++", "-std=c++17", "-fsanitize=thread", "-g", "-O1", "-Wno-unknown-pragmas", f"-I{csrc}", f"-I{od}",
+           f"-I{os.path.join(ROOT, 'include')}"] + \
         srcs + ["-o", exe, "-lpthread"]
     subprocess.run(cmd, check=True)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 second_deadlock_stack=1")
