@@ -624,6 +624,27 @@ def cpu_gs_baseline(hand, grid, q, r0, budget_s=4.0):
             "sample": f"{done} of {q.shape[0]} candidates, 1 Gauss-Seidel step, forward + gradient, FP64, {dt:.1f} s"}
 
 
+def cpu_mesh_step_baseline(hand, q, S, budget_s=10.0):
+    """The oracle's grasp step on the mesh object of the mesh-step leg
+    (forward + dual gradient, every face tested per sample in FP64) over a
+    bounded sample of the same candidates, one candidate per thread."""
+    import numpy as np
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    m = S.mesh_ellipsoid([0.05, 0.035, 0.04], subdivisions=4)
+    f32 = lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+    M = O.Mesh(f32(m.vertices), m.faces, f32(m.normals), float(np.float32(0.75)))
+    ob = O.Obj(mesh=M, inertia_over_mass=float(np.float32(0.4 * 0.04 ** 2)))
+    H, P = O.Hand(hand.rounded()), O.Params(K=1, r_dil=float(np.float32(0.005)))
+    done, t0 = 0, time.perf_counter()
+    while done < q.shape[0] and time.perf_counter() - t0 < budget_s:
+        O.step(H, ob, P, f32(q[done:done + threads]), grad=True, threads=threads)
+        done += threads
+    dt = time.perf_counter() - t0
+    return {"value": done * hand.n_contacts * 7 / dt, "unit": "contact-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of 1024 candidates, 1 step on the 5120-face mesh, forward + gradient, FP64, {dt:.1f} s"}
+
+
 EVAL_THRESHOLDS = (0.002, 0.005, 0.009)  # contact thresholds of the paper's metric figures (m)
 
 
@@ -870,6 +891,8 @@ def main():
         if diff is not None:
             cpu["evaluation"] = cpu_eval_baseline(hand2, grid2, q2, S)
             cpu["gauss_seidel"] = cpu_gs_baseline(hand2, grid2, q2, 0.01)
+            if mesh is not None:
+                cpu["mesh_step"] = cpu_mesh_step_baseline(hand2, q2[:1024], S)
 
     hand = L["hand"]
     out = {

@@ -93,6 +93,8 @@ struct MeshView {
   int n_nodes;
   int n_faces;
   float alpha;  // Phong blend
+  float bulge;  // alpha times the longest edge (widened by 1e-6): the Phong point's largest offset
+                // from the flat closest point, so rho >= (distance to the root box) - bulge
 };
 
 // Device copy of the step parameters.

@@ -237,6 +237,7 @@ grasp_status grasp_load_mesh(grasp_ctx* ctx, const grasp_mesh_desc* d, grasp_mes
   m->view.n_nodes = static_cast<int>(nn);
   m->view.n_faces = F;
   m->view.alpha = d->alpha;
+  m->view.bulge = static_cast<float>(d->alpha * max_edge * (1.0 + 1e-6));
   m->block = blk;
   m->bytes = bn + bt + bi;
   m->volume = volume;
