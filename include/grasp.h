@@ -99,8 +99,11 @@ typedef struct {
 
 /* The wrist is Trans(q0, q1, q2) Rz(q3) Ry(q4) Rx(q5); link l >= 1 has pose
  * T_parent * joint_origin[l] * Rot(joint_axis[l], q[5 + l]). The library
- * copies the description, re-lays the contacts out sorted by link, and
- * returns results indexed by contact in the caller's order.
+ * copies the description and re-lays the contacts out sorted by link, within
+ * a link along a Morton curve of their link-frame coordinates (sums over
+ * contacts run in that order); the Gauss-Seidel sweep takes the contacts of
+ * a link in the caller's order. Results indexed by contact come back in the
+ * caller's order.
  * EINVAL on a malformed description (e.g. a non-unit axis, |1 - |a|| > 1e-3). */
 grasp_status grasp_create_hand(grasp_ctx* ctx, const grasp_hand_desc* desc, grasp_hand_id* out);
 /* EBUSY while a live job uses the hand. */
@@ -343,8 +346,10 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
                               float* terms, float* dq, void* hip_stream);
 
 /* The fused step on a mesh object (Sec. III-B's Phong signed distance as the
- * constraint's rho, Sec. III-C): every sample of every iteration queries the
- * mesh through its hierarchy instead of a grid, with the constraint normal
+ * constraint's rho, Sec. III-C): the samples query the mesh through its
+ * hierarchy instead of a grid (the forward skips a sample whose distance to
+ * the mesh's box, less alpha times the longest edge, clears r_dil: it adds
+ * exactly nothing there), with the constraint normal
  * (r - p) / rho the paper states and, in the adjoint, the exact derivative of
  * rho and of that normal through the closest point (face interior, edge or
  * vertex) and the Phong point. Arguments as grasp_step_fused, with the mesh
