@@ -118,3 +118,67 @@ def test_grid_boundary_face_reading(oracle_lib):
     assert abs(want) > 1e-3
     assert got == pytest.approx(want, rel=1e-9)
     assert np.array_equal(alt["loss"], ref["loss"])
+
+
+def quadratic_dyadic_grid(n=33, lo=-1.0, h=1.0 / 16):
+    """Vertex values 0.5 x^2 + 0.25 y - 0.125 z + 1/16, exact in FP32: the
+    trilinear x-slope jumps across every x cell face."""
+    from paper_2306_08132_amd.synth import Grid
+    g = Grid(n=n, lo=np.full(3, lo), h=h, values=np.empty(0, np.float32), prims=[], bound_radius=0.0)
+    X = g.vertex_positions()
+    vals = 0.5 * X[:, 0] ** 2 + 0.25 * X[:, 1] - 0.125 * X[:, 2] + 0.0625
+    assert np.array_equal(vals.astype(np.float32).astype(np.float64), vals)
+    g.values = vals.astype(np.float32)
+    return g
+
+
+def two_sided(ob, p, op, what, nudges):
+    """The oracle reports a sample of kind `what` at p; the default and the
+    other reading of the reported samples are the step at p + nudges[0] and
+    p + nudges[1], in some order."""
+    from tests.helpers import point_hand
+    H = O.Hand(point_hand([p]))
+    q = np.zeros((1, 6))
+    ref = O.step_ex(H, ob, op, q, kink_d=P.KINK_D, kink_face=P.KINK_FACE, max_amb=64)
+    amb = [tuple(int(x) for x in a[:4]) for a in ref["amb"][0] if int(a[3]) == what]
+    assert amb
+    alt = O.step_ex(H, ob, op, q, flips=[(0, *f) for f in amb])
+    lo = O.step(O.Hand(point_hand([p + nudges[0]])), ob, op, q)
+    hi = O.step(O.Hand(point_hand([p + nudges[1]])), ob, op, q)
+
+    def close(a, b):
+        g = max(np.abs(a["grad"]).max(), np.abs(b["grad"]).max())
+        return (abs(a["loss"][0] - b["loss"][0]) <= 1e-6 * abs(b["loss"][0])
+                and np.abs(a["grad"] - b["grad"]).max() <= 1e-5 * g)
+
+    assert not close(lo, hi)
+    assert (close(ref, lo) and close(alt, hi)) or (close(ref, hi) and close(alt, lo))
+    return amb
+
+
+def test_cell_face_reading_is_the_other_side(oracle_lib):
+    """A point on an interior x cell face of a grid whose x-slope jumps
+    there, inside the dilated surface: reading the other cell is the step
+    1e-10 m to the other side (the rest test and the y and z tests share the
+    face)."""
+    ob = O.Obj(quadratic_dyadic_grid(), inertia_over_mass=0.25)
+    p = np.array([0.25, 0.125, -0.5])  # u_x = 20: the face between cells 19 and 20
+    phi = 0.5 * p[0] ** 2 + 0.25 * p[1] - 0.125 * p[2] + 0.0625
+    amb = two_sided(ob, p, O.Params(r_dil=phi + 0.01), 1,
+                    (np.array([-1e-10, 0.0, 0.0]), np.array([1e-10, 0.0, 0.0])))
+    assert {a[0] for a in amb} == {2, 3, 4, 5, 6}
+
+
+def test_activation_reading_is_the_other_side(oracle_lib):
+    """A sample at the activation d = -eps exactly (eps the contact tolerance)
+    on an affine grid: reading it active or not is the step with the point
+    moved 1e-10 m along the gradient to either side."""
+    from tests.helpers import dyadic_plane_grid
+    ob = O.Obj(dyadic_plane_grid(), inertia_over_mass=0.25)
+    p = np.array([0.25, 0.125, -0.5])
+    phi = 0.5 * p[0] + 0.25 * p[1] - 0.125 * p[2] + 0.0625
+    op = O.Params()
+    eps = 5e-3 * op.dt * op.v0
+    op.r_dil = phi + eps  # the rest test's d = phi - r_dil = -eps
+    g = np.array([0.5, 0.25, -0.125])
+    two_sided(ob, p, op, 0, (-1e-10 * g / np.linalg.norm(g), 1e-10 * g / np.linalg.norm(g)))
