@@ -579,7 +579,7 @@ std::string shape_key(const Resolved& r, int32_t B) {
 TileCfg tile_for(grasp_ctx* ctx, const Resolved& r, int32_t B) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->tiles.find(shape_key(r, B));
-  return it == ctx->tiles.end() ? TileCfg{} : it->second;
+  return it == ctx->tiles.end() ? default_tile(r.prm.K == 1) : it->second;
 }
 
 void load_tile_cache(grasp_ctx* ctx) {

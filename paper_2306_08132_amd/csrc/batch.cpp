@@ -127,7 +127,7 @@ grasp_status grasp_batch_create(grasp_ctx* ctx, int32_t capacity, int32_t max_jo
     return device_fail(ctx, e, "grasp_batch_create");
   }
   std::memset(bt->host, 0, 2 * bt->half);
-  bt->tile = TileCfg{};
+  bt->tile = TileCfg{0, 0};  // unset: each form's default shape
   *out = bt;
   return GRASP_OK;
 }
@@ -189,7 +189,7 @@ grasp_status grasp_batch_step(grasp_batch* bt, grasp_batch_job* jobs, int32_t n,
     if (e != hipSuccess) break;
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(bt->dev + off);
     const BatchJob* tab = reinterpret_cast<const BatchJob*>(hdr + 1);
-    const TileCfg tc = bt->tile;
+    const TileCfg tc = valid_tile(bt->tile) ? bt->tile : default_tile(group != 0);
     // every XCD's list holds at most capacity / 8 + max_jobs candidates
     const int per_xcd = (bt->capacity + 7) / 8 + bt->max_jobs;
     const int blocks = 8 * ((per_xcd + tc.wpb - 1) / tc.wpb);
