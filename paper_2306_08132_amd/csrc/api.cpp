@@ -190,6 +190,7 @@ void grasp_shutdown(grasp_ctx* ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
     if (ctx->gs_ev) (void)hipEventDestroy(ctx->gs_ev);
+    if (ctx->face_ev) (void)hipEventDestroy(ctx->face_ev);
     if (ctx->arena_owned) (void)hipFree(ctx->arena_base);
   }
   delete ctx;
@@ -909,7 +910,40 @@ grasp_status grasp_step_fused_mesh(grasp_ctx* ctx, grasp_hand_id hand, grasp_mes
   a.dq = dq;
   a.adam = adam_consts(t, lr, b1, b2, eps);
   DeviceGuard g(ctx->device);
-  const hipError_t e = launch_step_mesh(a, STEP_FUSED, true, static_cast<hipStream_t>(hip_stream));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (a.prm.K == 1 && B > 0) {
+    // One iteration: the forward records each sample's nearest face in a
+    // context buffer and the adjoint reuses it instead of walking the
+    // hierarchy again. Not under stream capture (a later, larger step may
+    // move the buffer) and not without room in the arena: then both walk.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_mesh");
+    if (cap == hipStreamCaptureStatusNone) {
+      const size_t need = static_cast<size_t>(B) * kSims * static_cast<size_t>(a.hand.Nc);
+      std::lock_guard<std::mutex> lk(ctx->face_mu);
+      if (ctx->face_cap < need) {
+        // the old buffer may still be in use by a launch on another stream
+        if (ctx->face_ev) e = hipEventSynchronize(ctx->face_ev);
+        if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_mesh");
+        std::lock_guard<std::mutex> lka(ctx->mu);
+        if (ctx->face_buf) ctx->arena.free(ctx->face_buf);
+        ctx->face_buf = static_cast<int*>(ctx->arena.alloc(need * sizeof(int)));
+        ctx->face_cap = ctx->face_buf ? need : 0;
+      }
+      if (ctx->face_buf) {
+        if (!ctx->face_ev) e = hipEventCreateWithFlags(&ctx->face_ev, hipEventDisableTiming);
+        else e = hipStreamWaitEvent(s, ctx->face_ev, 0);
+        a.mesh_face = ctx->face_buf;
+        if (e == hipSuccess) e = launch_step_mesh(a, STEP_FUSED, true, s);
+        if (e == hipSuccess) e = hipEventRecord(ctx->face_ev, s);
+        if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_mesh launch");
+        return GRASP_OK;
+      }
+    }
+  }
+  e = launch_step_mesh(a, STEP_FUSED, true, s);
   if (e != hipSuccess) return device_fail(ctx, e, "grasp_step_fused_mesh launch");
   return GRASP_OK;
 }

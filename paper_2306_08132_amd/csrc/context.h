@@ -87,6 +87,12 @@ struct grasp_ctx {
   float* gs_buf = nullptr;
   size_t gs_cap = 0;  // floats
   hipEvent_t gs_ev = nullptr;
+  // nearest faces of a one-iteration mesh step's samples (forward to
+  // adjoint), shared the same way
+  std::mutex face_mu;
+  int* face_buf = nullptr;
+  size_t face_cap = 0;  // ints
+  hipEvent_t face_ev = nullptr;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 

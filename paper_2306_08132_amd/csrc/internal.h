@@ -166,6 +166,8 @@ struct StepArgs {
   // a mesh object (nodes set): the step samples its Phong signed distance
   // instead of the grid; sdf then carries only inv_Im
   MeshView mesh;
+  int* mesh_face;       // [B][7][Nc] nearest face of every sample of a one-iteration mesh step,
+                        // written by the forward and read by the adjoint (or null: both walk)
   // debug trace (caller order), all optional
   float* trace_p;       // [B][Nc][3]
   float* trace_poses;   // [B][7][K+1][6]

@@ -260,9 +260,9 @@ __device__ __forceinline__ V3 mesh_ngrad_t(const MeshSample& s, float alpha, V3 
   return s.inv_rho * (fpv * f + at);
 }
 
-__device__ __forceinline__ void mesh_sample(const MeshView& M, V3 p, MeshSample& s) {
-  float best;
-  const int f = nearest_triangle(M, p, best);
+// The sample at p given its nearest face f (from nearest_triangle; < 0: p
+// not finite).
+__device__ __forceinline__ void mesh_sample_face(const MeshView& M, int f, V3 p, MeshSample& s) {
   if (f < 0) {
     const float nan = __builtin_nanf("");
     s.rho = nan;
@@ -313,6 +313,11 @@ __device__ __forceinline__ void mesh_sample(const MeshView& M, V3 p, MeshSample&
     s.n = I3(3);
     s.grad = s.n;
   }
+}
+
+__device__ __forceinline__ void mesh_sample(const MeshView& M, V3 p, MeshSample& s) {
+  float best;
+  mesh_sample_face(M, nearest_triangle(M, p, best), p, s);
 }
 
 }  // namespace meshdev

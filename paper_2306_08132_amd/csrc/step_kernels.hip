@@ -30,6 +30,7 @@ struct Ctx {
   int lane;
   unsigned long long* groups;  // forward group counts (or null)
   const MeshView& M;           // the mesh object of a mesh step (unused on grids)
+  int* face;                   // this candidate's [7][Nc] nearest faces (one-iteration mesh step, or null)
 };
 
 // Link transforms T_l (Sec. III-C, p = FK(q)): lane l composes its own
@@ -429,11 +430,17 @@ __device__ void forward_mesh(const Ctx& c, bool first, float& lpen, float* trace
       bool query = true;
       if constexpr (!TRACE) {
         const float db = sqrtf(meshdev::box_d2(c.M.nodes[0], c.M.nodes[1], r));
-        query = !(fmaf(0.999999f, db, -c.M.bulge) - rd > 1e-6f);
+        query = c.face || !(fmaf(0.999999f, db, -c.M.bulge) - rd > 1e-6f);
       }
       meshdev::MeshSample s;
       if (query) {
-        meshdev::mesh_sample(c.M, r, s);
+        float best;
+        const int f = meshdev::nearest_triangle(c.M, r, best);
+        if constexpr (!TRACE && !ROT) {
+          // the adjoint takes the same face instead of walking again
+          if (c.face && valid) c.face[lt.m * H.Nc + ch * kChunk + kGroup * g + lt.sub] = f;
+        }
+        meshdev::mesh_sample_face(c.M, f, r, s);
       } else {
         s.rho = 1e30f;  // inactive, not penetrating: lambda = 0 with a zero normal
         s.n = v3(0.0f, 0.0f, 0.0f);
@@ -654,7 +661,14 @@ __device__ void backward_mesh(const Ctx& c, bool first, float pen_seed, bool pos
       const V3 p = v3(P4.x, P4.y, P4.z);
       const V3 a = test_pt(p);
       meshdev::MeshSample s;
-      meshdev::mesh_sample(c.M, frame_pt(a), s);
+      if (!ROT && c.face) {
+        // the face the forward found at this same point (any finite face on
+        // lanes without a sample, whose results are multiplied by zero)
+        const int f = valid ? c.face[lt.m * H.Nc + ch * kChunk + kGroup * g + lt.sub] : 0;
+        meshdev::mesh_sample_face(c.M, f, frame_pt(a), s);
+      } else {
+        meshdev::mesh_sample(c.M, frame_pt(a), s);
+      }
       const V3 gn = ROT ? mul(o.R, s.n) : s.n;
       const float d = s.rho - rd;
       const V3 u = cross(a, gn);
@@ -773,7 +787,9 @@ template <bool KONE, int LAY>
 __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
-  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id(), A.fwd_groups, A.mesh};
+  int* face = (KONE && LAY == kLayoutMesh && A.mesh_face)
+                  ? A.mesh_face + static_cast<size_t>(b) * kSims * A.hand.Nc : nullptr;
+  const Ctx c{A.hand, A.sdf, A.prm, lds, lane_id(), A.fwd_groups, A.mesh, face};
   const int nd = H.n_dof;
   const int lane = c.lane;
   const float* qb = A.q + static_cast<size_t>(b) * nd;

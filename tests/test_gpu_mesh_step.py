@@ -161,3 +161,41 @@ def test_mesh_step_sample_exact_gradient(ctx):
     # it differs from the stated normal where alpha moves the Phong point with r
     assert np.abs(out[ok, 4:7] - out[ok, 1:4]).max() > 1e-2
     dm.unload()
+
+
+def test_face_cache_is_the_walk(ctx):
+    """The one-iteration mesh step records each sample's nearest face in the
+    forward and the adjoint reuses it; captured into a graph it walks the
+    hierarchy again instead (a later step may move the context's buffer).
+    Both give the same bits: the same face at the same point. Replayed twice
+    with eager work in between."""
+    from paper_2306_08132_amd.api import StepParams
+    hand, _, q = S.config_workload("tiny")
+    Im = float(np.float32(0.4 * 0.04 ** 2))
+    dm, _, _ = mesh_pair(ctx, S.mesh_ellipsoid((0.045, 0.035, 0.04), subdivisions=2), 0.75, Im)
+    h = ctx.hand(hand)
+    sp = StepParams(r_dil=0.005)
+    qa = torch.tensor(q, dtype=torch.float32, device=DEV)
+    la, ga = torch.empty(q.shape[0], device=DEV), torch.empty_like(qa)
+    ctx.step_fused_mesh(h, dm, sp, qa, torch.zeros_like(qa), torch.zeros_like(qa), 1, inertia_over_mass=Im,
+                        loss=la, dq=ga)
+    torch.cuda.synchronize()
+    qb = torch.tensor(q, dtype=torch.float32, device=DEV)
+    mb, vb = torch.zeros_like(qb), torch.zeros_like(qb)
+    lb, gb = torch.empty_like(la), torch.empty_like(ga)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.step_fused_mesh(h, dm, sp, qb, mb, vb, 1, inertia_over_mass=Im, loss=lb, dq=gb, stream=s)
+    q0 = torch.tensor(q, dtype=torch.float32, device=DEV)
+    for _ in range(2):
+        qb.copy_(q0)
+        mb.zero_()
+        vb.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (qb * 2).sum().item()
+        assert torch.equal(la, lb) and torch.equal(ga, gb) and torch.equal(qa, qb)
+    h.destroy()
+    dm.unload()
