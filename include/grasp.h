@@ -347,9 +347,13 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
 
 /* The fused step on a mesh object (Sec. III-B's Phong signed distance as the
  * constraint's rho, Sec. III-C): the samples query the mesh through its
- * hierarchy instead of a grid (the forward skips a sample whose distance to
- * the mesh's box, less alpha times the longest edge, clears r_dil: it adds
- * exactly nothing there), with the constraint normal
+ * hierarchy instead of a grid. With one iteration the forward records every
+ * sample's nearest face in a context buffer (B x 7 x n_contacts ints from the
+ * arena, kept and reused, shared by streams in launch order) and the adjoint
+ * reuses it; under stream capture or without room in the arena both passes
+ * walk, and the forward skips a sample whose distance to the mesh's box, less
+ * alpha times the longest edge, clears r_dil (it adds exactly nothing there).
+ * The results are the same bits either way. The constraint normal is
  * (r - p) / rho the paper states and, in the adjoint, the exact derivative of
  * rho and of that normal through the closest point (face interior, edge or
  * vertex) and the Phong point. Arguments as grasp_step_fused, with the mesh
