@@ -282,8 +282,9 @@ typedef struct {
                         point at the contact, dp_t = dp - (dp . n) n, n = g / |g|) is removed up to
                         mu C, wholly while |dp_t| <= mu C (static), by mu C beyond (kinetic), as the
                         Eq. (1) correction of a positional constraint along dp_t / |dp_t|, averaged
-                        with the normal corrections. mu > 0 needs K = 1 and the averaged projection
-                        (EINVAL otherwise); the plain form refuses it. */
+                        with the normal corrections; dp = p - r, the hand point minus its
+                        object-frame coordinates at the iteration's pose. mu > 0 needs the averaged
+                        projection (EINVAL otherwise); the plain form and the mesh step refuse it. */
 } grasp_step_params;
 
 /* Projection of the contact constraints (Sec. III-C). AVERAGED (default): every

@@ -71,8 +71,8 @@ grasp_status check_params(const grasp_step_params* p, StepConsts* out) {
   if (p->projection != GRASP_PROJECTION_AVERAGED && p->projection != GRASP_PROJECTION_GAUSS_SEIDEL)
     return fail(GRASP_EINVAL, "bad projection");
   if (!finite(p->mu) || p->mu < 0.0f) return fail(GRASP_EINVAL, "friction coefficient mu must be finite and >= 0");
-  if (p->mu > 0.0f && (p->K != 1 || p->projection != GRASP_PROJECTION_AVERAGED))
-    return fail(GRASP_EINVAL, "friction (mu > 0) runs with one iteration (K = 1) of the averaged projection");
+  if (p->mu > 0.0f && p->projection != GRASP_PROJECTION_AVERAGED)
+    return fail(GRASP_EINVAL, "friction (mu > 0) runs with the averaged projection");
   // LDS of one wave must fit comfortably: K/ckpt + 1 + ckpt pose slots
   if (wave_lds_floats(p->K, p->ckpt_every) * sizeof(float) > 16 * 1024)
     return fail(GRASP_EINVAL, "K / ckpt_every too large for the pose checkpoint buffer");

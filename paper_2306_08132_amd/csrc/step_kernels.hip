@@ -151,16 +151,18 @@ __device__ __forceinline__ bool contact_clear(const SdfView& S, V3 p, float rd, 
   return fmaxf(fmaf(0.999999f, e, -1.000001f * dv), 0.0f) + (bm - rd) > 1e-6f;
 }
 
-// Coulomb friction of an active sample in the one-iteration pass (the
-// object at its predicted pose, unturned): the material point at the contact
-// moved by the test's prediction dp = -off. Adds lambda_t (t, a x t),
+// Coulomb friction of an active sample: dp is the displacement over the step
+// of the object's material point at the contact, p - r (p the hand point, r
+// its object-frame coordinates, the point's rest position); in the
+// one-iteration pass (the object at its predicted pose, unturned) it is the
+// test's prediction -off. Adds lambda_t (t, a x t),
 // lambda_t = -min(|dp_t|, mu C) / w_t, to the lane's correction sums (none
 // for a slide up to the floor kSlideMin dt v0).
-__device__ __forceinline__ void add_friction(const Ctx& c, const LaneTest& lt, V3 a, V3 g, float d, bool on,
-                                             float inv_Im, float W[6]) {
-  if (!(c.P.mu > 0.0f) || !on) return;
+__device__ __forceinline__ void add_friction(const Ctx& c, V3 dp, V3 a, V3 g, float d, bool on, float inv_Im,
+                                             float W[6]) {
+  if (!on) return;
   Fric f;
-  if (!friction_dir(g, -1.0f * lt.off, a, inv_Im, kSlideMin * (c.P.dt * c.P.v0), f)) return;
+  if (!friction_dir(g, dp, a, inv_Im, kSlideMin * (c.P.dt * c.P.v0), f)) return;
   const float mc = -c.P.mu * d;  // mu C, C = -d > 0
   const float delta = f.tl <= mc ? f.tl : mc;
   const float lam = -delta * rcp(f.wt);
@@ -172,17 +174,16 @@ __device__ __forceinline__ void add_friction(const Ctx& c, const LaneTest& lt, V
   W[5] = fmaf(lam, f.ut.z, W[5]);
 }
 
-// Adjoint of add_friction for one sample (one iteration): from the test's
-// seeds (WlB, WaB), the contributions to d_bar, and, for a penetrating
-// sample, to the adjoints of the gradient g and of a. A non-penetrating
-// sample contributes through the leaky derivative of C only (its lambda_t is
-// 0): d_bar += alpha mu lb_t / w_t.
-__device__ __forceinline__ void friction_adjoint(const Ctx& c, const LaneTest& lt, V3 a, V3 g, float d, bool okw,
-                                                 bool pen, float inv_Im, V3 WlB, V3 WaB, float& dbar, V3& gbar,
-                                                 V3& abar) {
-  if (!(c.P.mu > 0.0f) || !okw) return;
+// Adjoint of add_friction for one sample: from the test's seeds (WlB, WaB),
+// the contributions to d_bar, and, for a penetrating sample, to the
+// adjoints of the gradient g, of a and of dp. A non-penetrating sample
+// contributes through the leaky derivative of C only (its lambda_t is 0):
+// d_bar += alpha mu lb_t / w_t.
+__device__ __forceinline__ void friction_adjoint(const Ctx& c, V3 dp, V3 a, V3 g, float d, bool okw, bool pen,
+                                                 float inv_Im, V3 WlB, V3 WaB, float& dbar, V3& gbar, V3& abar,
+                                                 V3& dpbar) {
+  if (!okw) return;
   Fric f;
-  const V3 dp = -1.0f * lt.off;
   if (!friction_dir(g, dp, a, inv_Im, kSlideMin * (c.P.dt * c.P.v0), f)) return;
   const float lbt = fmaf(WlB.x, f.th.x, fmaf(WlB.y, f.th.y, fmaf(WlB.z, f.th.z, dot(WaB, f.ut))));
   const float iwt = rcp(f.wt);
@@ -213,6 +214,7 @@ __device__ __forceinline__ void friction_adjoint(const Ctx& c, const LaneTest& l
   const V3 nhb = axpy(snb, dp, (-f.sn) * dptb);
   const float nn = dot(f.nh, nhb);
   gbar = gbar + f.ing * axpy(-nn, f.nh, nhb);
+  dpbar = dpbar + axpy(snb, f.nh, dptb);
 }
 
 template <bool ROT, bool TRACE, int LAY>
@@ -272,7 +274,11 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
       W[3] = fmaf(lam, u.x, W[3]);
       W[4] = fmaf(lam, u.y, W[4]);
       W[5] = fmaf(lam, u.z, W[5]);
-      if constexpr (!ROT) add_friction(c, lt, a, gn, d, on, inv_Im, W);
+      if (c.P.mu > 0.0f) {
+        // the material point's displacement: the test's prediction, or p - r
+        const V3 dp = ROT ? v3(P4.x, P4.y, P4.z) - mul_t(R, a) : -1.0f * lt.off;
+        add_friction(c, dp, a, gn, d, on, inv_Im, W);
+      }
       if constexpr (TRACE) {
         if (valid) {
           const int i = ch * kChunk + kGroup * g + lt.sub;
@@ -376,7 +382,7 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       W[3] = fmaf(lam, u.x, W[3]);
       W[4] = fmaf(lam, u.y, W[4]);
       W[5] = fmaf(lam, u.z, W[5]);
-      if constexpr (!ROT) add_friction(c, lt, a, gn_, d, on, inv_Im, W);
+      if (c.P.mu > 0.0f) add_friction(c, ROT ? p - mul_t(R, a) : -1.0f * lt.off, a, gn_, d, on, inv_Im, W);
       if (gn < 0) break;
       g = gn;
       L = L_n;
@@ -566,8 +572,13 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
       dbar = (valid && d < 0.0f) ? fmaf(pseed, d, dbar) : dbar;
       V3 ab = v3(0.0f, 0.0f, 0.0f);
       V3 gbar = v3(0.0f, 0.0f, 0.0f);
-      if constexpr (!ROT) friction_adjoint(c, lt, a, gn, d, okw, pen, inv_Im, WlB, WaB, dbar, gbar, ab);
+      V3 dpb = v3(0.0f, 0.0f, 0.0f);
+      const bool fric = c.P.mu > 0.0f;
+      if (fric)
+        friction_adjoint(c, ROT ? p - mul_t(o.R, a) : -1.0f * lt.off, a, gn, d, okw, pen, inv_Im, WlB, WaB, dbar,
+                         gbar, ab, dpb);
       V3 rbar = dbar * s.n;
+      if (ROT && fric) rbar = rbar - dpb;  // dp = p - r: r_bar gets -dp_bar
       if (pen) {
         const float lam = d * iw;
         const float wbar2 = -2.0f * lb * lam * iw;
@@ -578,7 +589,7 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
         rbar = rbar + hess_mul(S, s, ROT ? mul_t(o.R, gbar) : gbar);
       }
       // a_bar of the sample (exactly 0 on invalid lanes: dbar = 0, no penetration)
-      const V3 pb = ab + (ROT ? mul(o.R, rbar) : rbar);
+      const V3 pa = ab + (ROT ? mul(o.R, rbar) : rbar);
       if constexpr (ROT) {
         // the leak acts on the hand point only: a non-penetrating sample adds
         // nothing to the adjoint of the object's pose
@@ -586,10 +597,12 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
           V3 thb = v3(0.0f, 0.0f, 0.0f);
           if (pen) thb = rot_vjp(o, 1.0f, s.n, gbar);
           thb = thb - rot_vjp(o, -1.0f, a, rbar);
-          XB[0] -= pb.x; XB[1] -= pb.y; XB[2] -= pb.z;
+          XB[0] -= pa.x; XB[1] -= pa.y; XB[2] -= pa.z;
           XB[3] += thb.x; XB[4] += thb.y; XB[5] += thb.z;
         }
       }
+      // the hand point: through a = p - x and, with friction, through dp
+      const V3 pb = (ROT && fric) ? pa + dpb : pa;
       const V3 tau = cross(p, pb);
       const float v6[6] = {pb.x, pb.y, pb.z, tau.x, tau.y, tau.z};
       // links of the group's first and last contacts (wave-uniform)

@@ -1,12 +1,13 @@
-"""GPU parity of the Coulomb friction of the one-iteration step (Sec. III-C;
-read as positional friction: each active contact's tangential displacement
-over the step removed up to mu C) against the oracle's: loss and gradient of
-every candidate (tests/parity_check.py), on the small workload, ragged hands
-and a sample of the differentiable-step workload; the hand-written adjoint
-against central differences of the oracle loss; fused equals forward,
-backward and Adam; mu = 0 equals the frictionless step bit for bit; the
-batched launch with friction equals its single-job steps; refusals where it
-is not built (several iterations, Gauss-Seidel, the plain form)."""
+"""GPU parity of the Coulomb friction of the step (Sec. III-C; read as
+positional friction: each active contact's tangential displacement over the
+step removed up to mu C) against the oracle's: loss and gradient of every
+candidate (tests/parity_check.py), on the small workload, ragged hands and a
+sample of the differentiable-step workload, with one and with several
+projection iterations (the displacement p - r at each iteration's pose); the
+hand-written adjoint against central differences of the oracle loss; fused
+equals forward, backward and Adam; mu = 0 equals the frictionless step bit
+for bit; the batched launch with friction equals its single-job steps;
+refusals where it is not built (Gauss-Seidel, the plain form)."""
 import numpy as np
 import pytest
 import torch
@@ -100,6 +101,28 @@ def test_friction_parity_ragged_and_diff_sample(ctx):
     P.assert_ok(rep)
 
 
+@pytest.mark.parametrize("K,ck", [(3, 1), (3, 3), (4, 2)])
+def test_friction_parity_iterations(ctx, K, ck):
+    """Friction in every one of K projection iterations (the material
+    point's displacement p - r at the iteration's pose, the object rotating),
+    with pose checkpoints every ck iterations (the backward replays each
+    segment): every candidate of the small workload against the oracle, and
+    the checkpoint interval changes no bit."""
+    hand, grid, q = S.config_workload("tiny")
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    sp, op = prm_pair(r_dil=0.005, mu=0.5, K=K, ckpt_every=ck)
+    loss, dq = split_step(ctx, h, sd, sp, q)
+    rep = P.compare(loss, dq, O.Hand(hand.rounded()), O.Obj(grid), op, q.astype(np.float32).astype(np.float64),
+                    conditioning=True, label=f"friction K={K} ckpt={ck}", say=say)
+    P.assert_ok(rep, max_set_aside=2.0 / q.shape[0])
+    sp1, _ = prm_pair(r_dil=0.005, mu=0.5, K=K, ckpt_every=1)
+    l1, g1 = split_step(ctx, h, sd, sp1, q)
+    assert np.array_equal(l1, loss) and np.array_equal(g1, dq)
+    sp0, _ = prm_pair(r_dil=0.005, K=K, ckpt_every=ck)
+    l0, _ = split_step(ctx, h, sd, sp0, q)
+    assert np.abs(l0 - loss).max() > 1e-3
+
+
 def test_friction_gradient_matches_finite_differences(ctx):
     hand, grid, q = S.config_workload("tiny")
     h, sd = ctx.hand(hand), ctx.sdf(grid)
@@ -145,7 +168,7 @@ def test_friction_refusals(ctx):
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     qd = dev(q)
     loss = torch.empty(4, device=DEV)
-    for bad in (dict(mu=0.5, K=2), dict(mu=0.5, projection=1), dict(mu=-0.1), dict(mu=float("nan"))):
+    for bad in (dict(mu=0.5, projection=1), dict(mu=-0.1), dict(mu=float("nan"))):
         with pytest.raises(GraspError):
             ctx.step_fwd(h, sd, StepParams(**bad), qd, loss)
     with pytest.raises(GraspError, match="friction"):
