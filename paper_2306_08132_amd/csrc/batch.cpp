@@ -190,22 +190,25 @@ grasp_status grasp_batch_step(grasp_batch* bt, grasp_batch_job* jobs, int32_t n,
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(bt->dev + off);
     const BatchJob* tab = reinterpret_cast<const BatchJob*>(hdr + 1);
     const TileCfg tc = valid_tile(bt->tile) ? bt->tile : default_tile(group != 0);
+    bool fric = false;  // a job of this group with friction
+    for (int i = 0; i < n; ++i)
+      if ((bt->views[i].prm.K == 1) == (group != 0) && bt->views[i].prm.mu > 0.0f) fric = true;
     // every XCD's list holds at most capacity / 8 + max_jobs candidates
     const int per_xcd = (bt->capacity + 7) / 8 + bt->max_jobs;
     const int blocks = 8 * ((per_xcd + tc.wpb - 1) / tc.wpb);
     if (!bt->use_graph || s == nullptr) {
       e = launch_order_batch(hdr, tab, bt->max_jobs, s);
-      if (e == hipSuccess) e = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
+      if (e == hipSuccess) e = launch_batch(hdr, tab, group != 0, fric, tc, blocks, lds, s);
       continue;
     }
-    const auto key = std::make_tuple(group, tc.wpb, tc.occ, lds);
+    const auto key = std::make_tuple(group + (fric ? 2 : 0), tc.wpb, tc.occ, lds);
     auto it = bt->graphs.find(key);
     if (it == bt->graphs.end()) {
       BatchGraph bg{};
       e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
       if (e == hipSuccess) {
         hipError_t le = launch_order_batch(hdr, tab, bt->max_jobs, s);
-        if (le == hipSuccess) le = launch_batch(hdr, tab, group != 0, tc, blocks, lds, s);
+        if (le == hipSuccess) le = launch_batch(hdr, tab, group != 0, fric, tc, blocks, lds, s);
         e = hipStreamEndCapture(s, &bg.graph);
         if (e == hipSuccess) e = le;
       }

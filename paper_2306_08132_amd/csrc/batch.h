@@ -36,6 +36,6 @@ struct grasp_batch {
   int* order_dev = nullptr;   // per-job candidate locality orders, capacity ints
   grasp::TileCfg tile{};
   std::vector<grasp::BatchView> views;
-  std::map<std::tuple<int, int, int, int>, grasp::BatchGraph> graphs;  // (group, wpb, occ, lds)
+  std::map<std::tuple<int, int, int, int>, grasp::BatchGraph> graphs;  // (group + 2 fric, wpb, occ, lds)
   hipEvent_t last = nullptr;  // completion of the previous step (table reuse)
 };

@@ -225,8 +225,9 @@ struct BatchHeader {
 };
 // Launches `blocks` workgroups (a multiple of 8) over the table; XCD x takes
 // candidates [x slice, (x + 1) slice) of every job. Waves past the table exit;
-// kone selects the one-iteration kernel (every job in the table must agree on it).
-hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
+// kone selects the one-iteration kernel (every job in the table must agree on it);
+// fric, the several-iteration kernel with friction compiled in (needed when a job has mu > 0).
+hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, bool fric, TileCfg cfg, int blocks,
                         int lds_floats, hipStream_t stream);
 
 // The same for every job of a batch table whose order pointer is set.

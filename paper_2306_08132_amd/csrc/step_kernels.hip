@@ -299,7 +299,7 @@ __device__ void forward_full(const Ctx& c, bool first, float& lpen, float* trace
 // groups of a chunk are found first from the block minima; the corners of
 // the next live group are requested before the current one is blended. The
 // sums are bit-identical to the full pass's.
-template <bool ROT, int LAY>
+template <bool ROT, int LAY, bool FRIC>
 __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
@@ -382,7 +382,7 @@ __device__ void forward_culled(const Ctx& c, bool first, float& lpen) {
       W[3] = fmaf(lam, u.x, W[3]);
       W[4] = fmaf(lam, u.y, W[4]);
       W[5] = fmaf(lam, u.z, W[5]);
-      if (c.P.mu > 0.0f) add_friction(c, ROT ? p - mul_t(R, a) : -1.0f * lt.off, a, gn_, d, on, inv_Im, W);
+      if (FRIC && c.P.mu > 0.0f) add_friction(c, ROT ? p - mul_t(R, a) : -1.0f * lt.off, a, gn_, d, on, inv_Im, W);
       if (gn < 0) break;
       g = gn;
       L = L_n;
@@ -480,7 +480,7 @@ __device__ void forward_mesh(const Ctx& c, bool first, float& lpen, float* trace
   lpen = wave_sum(lp);
 }
 
-template <bool KONE, int LAY>
+template <bool KONE, int LAY, bool FRIC>
 __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace_s, int K, int k) {
   lpen = 0.0f;
   if constexpr (LAY == kLayoutMesh) {
@@ -488,7 +488,7 @@ __device__ void forward_pass(const Ctx& c, bool first, float& lpen, float* trace
     else forward_mesh<!KONE, false>(c, first, lpen, nullptr, K, k);
   } else {
     if (trace_s) forward_full<!KONE, true, LAY>(c, first, lpen, trace_s, K, k);
-    else forward_culled<!KONE, LAY>(c, first, lpen);
+    else forward_culled<!KONE, LAY, FRIC>(c, first, lpen);
   }
   wave_lds_sync();
 }
@@ -509,7 +509,7 @@ __device__ __forceinline__ void flush_link(const Ctx& c, int l, const float v[6]
 // sums of the current link, flushed (wave reductions) where the link changes;
 // with pose_adj the lanes also sum the adjoint of their test's pose (-sum
 // a_bar, sum theta_bar), which is added to the running pose adjoint.
-template <bool ROT, int LAY>
+template <bool ROT, int LAY, bool FRIC>
 __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   const HandView& H = c.H;
   const SdfView& S = c.S;
@@ -573,7 +573,7 @@ __device__ void backward_lanes(const Ctx& c, bool first, float pen_seed, bool po
       V3 ab = v3(0.0f, 0.0f, 0.0f);
       V3 gbar = v3(0.0f, 0.0f, 0.0f);
       V3 dpb = v3(0.0f, 0.0f, 0.0f);
-      const bool fric = c.P.mu > 0.0f;
+      const bool fric = FRIC && c.P.mu > 0.0f;
       if (fric)
         friction_adjoint(c, ROT ? p - mul_t(o.R, a) : -1.0f * lt.off, a, gn, d, okw, pen, inv_Im, WlB, WaB, dbar,
                          gbar, ab, dpb);
@@ -754,10 +754,10 @@ __device__ void backward_mesh(const Ctx& c, bool first, float pen_seed, bool pos
 }
 
 
-template <bool KONE, int LAY>
+template <bool KONE, int LAY, bool FRIC>
 __device__ void backward_pass(const Ctx& c, bool first, float pen_seed, bool pose_adj) {
   if constexpr (LAY == kLayoutMesh) backward_mesh<!KONE>(c, first, pen_seed, pose_adj);
-  else backward_lanes<!KONE, LAY>(c, first, pen_seed, pose_adj);
+  else backward_lanes<!KONE, LAY, FRIC>(c, first, pen_seed, pose_adj);
 }
 
 __device__ __forceinline__ float* pose_slot(float* lds, int s) { return lds + kOffPose + s * kSims * 6; }
@@ -796,7 +796,7 @@ __device__ __forceinline__ void init_pose(const Ctx& c, float* p0) {
 // ---------------------------------------------------------------------------
 // the per-candidate step
 // ---------------------------------------------------------------------------
-template <bool KONE, int LAY>
+template <bool KONE, int LAY, bool FRIC>
 __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int kind, bool adam, float* lds) {
   const HandView& H = A.hand;
   const StepConsts& P = A.prm;
@@ -843,7 +843,7 @@ __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int
       if constexpr (!KONE) load_test_consts(c, cur);
       float lp;
       float* ts = A.trace_samples ? A.trace_samples + static_cast<size_t>(b) * kSims * K * H.Nc * 6 : nullptr;
-      forward_pass<KONE, LAY>(c, k == 0, lp, ts, K, k);
+      forward_pass<KONE, LAY, FRIC>(c, k == 0, lp, ts, K, k);
       if (k == 0) lpen = lp;
       advance_pose(c, cur, cur, k);
       if ((k + 1) % ck == 0) {
@@ -932,7 +932,7 @@ __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int
       for (int j = 1; j < ck; ++j) {
         load_test_consts(c, segbuf + (j - 1) * kSims * 6);
         float lp;
-        forward_pass<KONE, LAY>(c, false, lp, nullptr, K, seg * ck + j - 1);
+        forward_pass<KONE, LAY, FRIC>(c, false, lp, nullptr, K, seg * ck + j - 1);
         advance_pose(c, segbuf + (j - 1) * kSims * 6, segbuf + j * kSims * 6, seg * ck + j - 1);
       }
     }
@@ -947,8 +947,8 @@ __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int
         U[22] = omi * U[28]; U[23] = omi * U[29]; U[24] = omi * U[30];
       }
       wave_lds_sync();
-      if constexpr (KONE) backward_pass<KONE, LAY>(c, true, pen_seed, false);
-      else backward_pass<KONE, LAY>(c, k == 0, pen_seed, k > 0);
+      if constexpr (KONE) backward_pass<KONE, LAY, FRIC>(c, true, pen_seed, false);
+      else backward_pass<KONE, LAY, FRIC>(c, k == 0, pen_seed, k > 0);
     }
   }
 
@@ -992,10 +992,10 @@ __device__ __forceinline__ void candidate_step_lay(const StepArgs& A, int b, int
 
 // The gather layout of the candidate's grid selects the code path (uniform
 // over the wavefront).
-template <bool KONE>
+template <bool KONE, bool FRIC>
 __device__ __forceinline__ void candidate_step(const StepArgs& A, int b, int kind, bool adam, float* lds) {
-  if (A.sdf.layout == kLayoutZPairs) candidate_step_lay<KONE, kLayoutZPairs>(A, b, kind, adam, lds);
-  else candidate_step_lay<KONE, kLayoutYZQuads>(A, b, kind, adam, lds);
+  if (A.sdf.layout == kLayoutZPairs) candidate_step_lay<KONE, kLayoutZPairs, FRIC>(A, b, kind, adam, lds);
+  else candidate_step_lay<KONE, kLayoutYZQuads, FRIC>(A, b, kind, adam, lds);
 }
 
 
@@ -1076,7 +1076,7 @@ k_step_mesh(StepArgs A, int kind, int adam) {
   const int item = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * wpb + w);
   if (item >= A.B) return;
   float* lds = smem + static_cast<size_t>(w) * wave_lds_floats(A.prm.K, A.prm.ckpt);
-  candidate_step_lay<KONE, kLayoutMesh>(A, item, kind, adam != 0, lds);
+  candidate_step_lay<KONE, kLayoutMesh, false>(A, item, kind, adam != 0, lds);
 }
 
 __global__ void __launch_bounds__(kOrderThreads) k_order(const float* q, int nd, int B, SdfView S, int* out) {
@@ -1093,7 +1093,9 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_batch(const BatchHeader
 
 // OCC is the minimum number of waves per SIMD the register allocation must
 // allow (1 = the compiler's choice); it is the occupancy knob of the tuner.
-template <bool KONE, int OCC>
+// FRIC compiles the friction correction in (always with one iteration; with
+// several, only when mu > 0: its registers cost a wave per SIMD there).
+template <bool KONE, int OCC, bool FRIC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(OCC, 8)))
 k_step(StepArgs A, int kind, int adam) {
   extern __shared__ float smem[];
@@ -1103,7 +1105,7 @@ k_step(StepArgs A, int kind, int adam) {
   if (item >= A.B) return;
   const int b = A.order ? __builtin_amdgcn_readfirstlane(A.order[item]) : item;
   float* lds = smem + static_cast<size_t>(w) * wave_lds_floats(A.prm.K, A.prm.ckpt);
-  candidate_step<KONE>(A, b, kind, adam != 0, lds);
+  candidate_step<KONE, FRIC>(A, b, kind, adam != 0, lds);
 }
 
 // Batched step: one launch covers every job of a device table, each
@@ -1114,7 +1116,7 @@ k_step(StepArgs A, int kind, int adam) {
 // part of each job's grid. The header and table are read from device memory,
 // so a graph captured for a grid of the batch's capacity serves any job set
 // up to that many candidates; waves past the table exit at once.
-template <bool KONE, int OCC>
+template <bool KONE, int OCC, bool FRIC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(OCC, 8)))
 k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, int lds_per_wave) {
   extern __shared__ float smem[];
@@ -1136,7 +1138,7 @@ k_batch(const BatchHeader* __restrict__ hdr, const BatchJob* __restrict__ jobs, 
   if (local >= A.B) return;
   float* lds = smem + static_cast<size_t>(w) * lds_per_wave;
   const int b = A.order ? __builtin_amdgcn_readfirstlane(A.order[local]) : local;
-  candidate_step<KONE>(A, b, STEP_FUSED, true, lds);
+  candidate_step<KONE, FRIC>(A, b, STEP_FUSED, true, lds);
 }
 
 __global__ void k_adam(int n, float* q, float* m, float* v, const float* g, AdamConsts c) {
@@ -1214,7 +1216,11 @@ namespace {
 template <bool KONE, int OCC>
 void launch_variant(const StepArgs& a, int kind, bool adam, int wpb, size_t lds, hipStream_t stream) {
   const int blocks = (a.B + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_step<KONE, OCC>), dim3(blocks), dim3(wpb * kWave), lds, stream, a, kind, adam ? 1 : 0);
+  if (KONE || a.prm.mu > 0.0f)
+    hipLaunchKernelGGL((k_step<KONE, OCC, true>), dim3(blocks), dim3(wpb * kWave), lds, stream, a, kind, adam ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_step<false, OCC, false>), dim3(blocks), dim3(wpb * kWave), lds, stream, a, kind,
+                       adam ? 1 : 0);
 }
 template <bool KONE>
 void launch_occ(const StepArgs& a, int kind, bool adam, TileCfg cfg, size_t lds, hipStream_t stream) {
@@ -1273,29 +1279,34 @@ hipError_t launch_order_batch(const BatchHeader* hdr, const BatchJob* jobs, int 
 namespace {
 template <bool KONE, int OCC>
 void launch_batch_variant(const BatchHeader* hdr, const BatchJob* jobs, int blocks, int wpb, int lds_floats,
-                          hipStream_t stream) {
-  hipLaunchKernelGGL((k_batch<KONE, OCC>), dim3(blocks), dim3(wpb * kWave),
-                     static_cast<size_t>(lds_floats) * wpb * sizeof(float), stream, hdr, jobs, lds_floats);
+                          bool fric, hipStream_t stream) {
+  const size_t lds = static_cast<size_t>(lds_floats) * wpb * sizeof(float);
+  if (KONE || fric)
+    hipLaunchKernelGGL((k_batch<KONE, OCC, true>), dim3(blocks), dim3(wpb * kWave), lds, stream, hdr, jobs,
+                       lds_floats);
+  else
+    hipLaunchKernelGGL((k_batch<false, OCC, false>), dim3(blocks), dim3(wpb * kWave), lds, stream, hdr, jobs,
+                       lds_floats);
 }
 }  // namespace
 
-hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, TileCfg cfg, int blocks,
+hipError_t launch_batch(const BatchHeader* hdr, const BatchJob* jobs, bool kone, bool fric, TileCfg cfg, int blocks,
                         int lds_floats, hipStream_t stream) {
   if (!valid_tile(cfg)) cfg = TileCfg{};
   switch ((kone ? 10 : 0) + cfg.occ) {
-    case 12: launch_batch_variant<true, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 13: launch_batch_variant<true, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 14: launch_batch_variant<true, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 15: launch_batch_variant<true, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 16: launch_batch_variant<true, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 2: launch_batch_variant<false, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 3: launch_batch_variant<false, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 4: launch_batch_variant<false, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 5: launch_batch_variant<false, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
-    case 6: launch_batch_variant<false, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream); break;
+    case 12: launch_batch_variant<true, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 13: launch_batch_variant<true, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 14: launch_batch_variant<true, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 15: launch_batch_variant<true, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 16: launch_batch_variant<true, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 2: launch_batch_variant<false, 2>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 3: launch_batch_variant<false, 3>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 4: launch_batch_variant<false, 4>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 5: launch_batch_variant<false, 5>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
+    case 6: launch_batch_variant<false, 6>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream); break;
     default:
-      if (kone) launch_batch_variant<true, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);
-      else launch_batch_variant<false, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, stream);
+      if (kone) launch_batch_variant<true, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream);
+      else launch_batch_variant<false, 1>(hdr, jobs, blocks, cfg.wpb, lds_floats, fric, stream);
   }
   return hipGetLastError();
 }
