@@ -161,6 +161,30 @@ def test_friction_forms_agree(ctx):
     b.close()
 
 
+def test_friction_iterations_batched_equals_fused(ctx):
+    """A batched launch of several-iteration jobs with and without friction
+    (the friction kernel is picked for the group) equals their single-job
+    fused steps bit for bit."""
+    from paper_2306_08132_amd.api import Batch, BatchJob, StepParams
+    hand, grid, q = S.config_workload("tiny", B=200)
+    h, sd = ctx.hand(hand), ctx.sdf(grid)
+    want = []
+    for mu in (0.5, 0.0):
+        qf = dev(q)
+        mf, vf = torch.zeros_like(qf), torch.zeros_like(qf)
+        lf = torch.empty(q.shape[0], device=DEV)
+        ctx.step_fused(h, sd, StepParams(r_dil=0.004, mu=mu, K=2), qf, mf, vf, 1, loss=lf)
+        want.append((qf, lf))
+    jobs = [BatchJob(h, sd, StepParams(mu=mu, K=2), dev(q), T=10, r0=0.004) for mu in (0.5, 0.0)]
+    b = Batch(ctx, capacity=512, max_jobs=4, use_graph=False)
+    b.step(jobs)
+    torch.cuda.synchronize()
+    for job, (qf, lf) in zip(jobs, want):
+        assert torch.equal(job.q, qf) and torch.equal(job.loss, lf)
+    assert not torch.equal(want[0][1], want[1][1])
+    b.close()
+
+
 def test_friction_refusals(ctx):
     from paper_2306_08132_amd._lib import GraspError
     from paper_2306_08132_amd.api import StepParams
