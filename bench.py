@@ -438,7 +438,7 @@ def large_headline(ctx, S, args):
     stream = torch.cuda.current_stream()
     B, Nc, nd, K = q0.shape[0], hand.n_contacts, hand.n_dof, 16
     T, r0 = 200, 0.01
-    tile = (1, 2)  # the step kernel's launch shape for this workload (tuning it costs seconds per shape)
+    tile = (1, 4)  # the step kernel's launch shape for this workload (tuning it costs seconds per shape)
     ctx.set_tile(h, sd, StepParams(K=K, ckpt_every=4), B, *tile)
     ctx.set_tile(h, sd, StepParams(K=K, ckpt_every=1), B, *tile)
 

@@ -416,7 +416,7 @@ grasp_status grasp_plain_step(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
  * ------------------------------------------------------------------------- */
 /* Launch shape of the step kernels. Where none is tuned or set: two
  * candidates per workgroup at four waves per SIMD for one projection
- * iteration, one at two for several. Every shape gives the same bits. */
+ * iteration, one at four for several. Every shape gives the same bits. */
 typedef struct {
   int32_t waves_per_block;     /* candidates per workgroup: 1, 2 or 4 */
   int32_t min_waves_per_simd;  /* register budget: 1 (compiler's choice) .. 6 */

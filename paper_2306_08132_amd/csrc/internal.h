@@ -186,10 +186,11 @@ bool valid_tile(TileCfg c);
 // The shape used where none was set or tuned. One iteration (128 VGPRs with
 // 12 bytes of spills): two waves per workgroup at four per SIMD (16 uneven
 // batched jobs 5.89 -> 5.52 ms against one wave per SIMD's minimum; the tuner
-// picks it on the 4096-candidate step). Several iterations (152 VGPRs): one
-// wave per workgroup, two per SIMD (the 65536-candidate K = 16 step 578 ->
-// 565 ms against two waves at three).
-inline TileCfg default_tile(bool kone) { return kone ? TileCfg{2, 4} : TileCfg{1, 2}; }
+// picks it on the 4096-candidate step). Several iterations: one wave per
+// workgroup at four per SIMD (128 VGPRs, 80 bytes of spills per lane; the
+// 65536-candidate K = 16 step 568 -> 519 ms against two or three per SIMD at
+// 152 VGPRs without spills; five per SIMD spill 252 bytes and take 1012 ms).
+inline TileCfg default_tile(bool kone) { return kone ? TileCfg{2, 4} : TileCfg{1, 4}; }
 
 hipError_t launch_step(const StepArgs& a, StepKind kind, bool adam, TileCfg cfg, hipStream_t stream);
 // The same step on a mesh object (a.mesh): one projection form (averaged),

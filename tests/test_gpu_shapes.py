@@ -120,7 +120,7 @@ def test_large_workload_sampled(ctx):
     h, sd = ctx.hand(hand), ctx.sdf(grid)
     sp = StepParams(K=16, ckpt_every=4, r_dil=0.005)
     B = q.shape[0]
-    ctx.set_tile(h, sd, sp, B, 1, 2)  # the launch shape the benchmark times
+    ctx.set_tile(h, sd, sp, B, 1, 4)  # the launch shape the benchmark times
     qd = torch.tensor(q, dtype=torch.float32, device=DEV)
     m, v = torch.zeros_like(qd), torch.zeros_like(qd)
     loss = torch.empty(B, device=DEV)
