@@ -155,12 +155,13 @@ k_evaluate(HandView H, SdfView S, EvalView E, EvalConsts C, int B, const float* 
 }
 
 // The same metrics against a mesh object's Phong signed distance: one
-// workgroup per candidate, its link frames in LDS, one sample per lane
-// through the hierarchy query. A sample outside the mesh's bounding box is
-// at least its distance to the box from the flat surface, and the Phong
-// point lies within `bulge` (alpha times the longest edge) of the flat one,
-// so a sample whose box distance exceeds the cut by more than the bulge
-// (with margins far above FP32 rounding) adds nothing and skips the query.
+// workgroup per candidate, its link frames in LDS, one sample per lane,
+// each wave walking the hierarchy once for its 64 samples. A sample outside
+// the mesh's bounding box is at least its distance to the box from the flat
+// surface, and the Phong point lies within `bulge` (alpha times the longest
+// edge) of the flat one, so a sample whose box distance exceeds the cut by
+// more than the bulge (with margins far above FP32 rounding) adds nothing and
+// skips the query.
 // Sums as above: lane-sequential, wave butterfly, waves in order.
 __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate_mesh(HandView H, MeshView M, EvalView E,
                                                                        EvalConsts C, float bulge, int B,
@@ -189,16 +190,27 @@ __global__ void __launch_bounds__(kEvalWaves * kWave) k_evaluate_mesh(HandView H
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) acc[t] = 0.0f;
   const int n = E.ns + E.nv;
-  for (int i = tid; i < n; i += kEvalWaves * kWave) {
-    const float4 P = E.pts[i];
-    const float4* T4 = reinterpret_cast<const float4*>(T + 12 * E.link[i]);
-    const V3 r = xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z);
-    const float cut = i < E.ns ? C.tmax : 0.0f;
-    const float db = sqrtf(meshdev::box_d2(M.nodes[0], M.nodes[1], r));
-    if (fmaf(0.999999f, db, -bulge) - cut > 1e-6f) continue;
+  // the wave's lanes take consecutive samples and walk the hierarchy together
+  for (int i0 = tid - lane; i0 < n; i0 += kEvalWaves * kWave) {
+    const int i = i0 + lane;
+    float4 P = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    V3 r = v3(0.0f, 0.0f, 0.0f);
+    bool query = false;
+    if (i < n) {
+      P = E.pts[i];
+      const float4* T4 = reinterpret_cast<const float4*>(T + 12 * E.link[i]);
+      r = xform_point(T4[0], T4[1], T4[2], P.x, P.y, P.z);
+      const float cut = i < E.ns ? C.tmax : 0.0f;
+      const float db = sqrtf(meshdev::box_d2(M.nodes[0], M.nodes[1], r));
+      query = !(fmaf(0.999999f, db, -bulge) - cut > 1e-6f);
+    }
+    if (__builtin_amdgcn_ballot_w64(query) == 0) continue;
+    float best;
+    const int f = meshdev::nearest_triangle_wave(M, r, best, query);
+    if (!query) continue;
     float rho;
     V3 g;
-    meshdev::mesh_sdf(M, r, rho, g);
+    meshdev::mesh_sdf_face(M, f, r, rho, g);
     if (i < E.ns) {
 #pragma unroll
       for (int t = 0; t < kMaxThresholds; ++t)

@@ -166,10 +166,82 @@ __device__ __forceinline__ int nearest_triangle(const MeshView& M, V3 p, float& 
   return bestf;
 }
 
+// nearest_triangle for the lanes of one wave at once, called by every lane of
+// the wave together (active: the lane wants its point's face; the others
+// return -1). The wave walks one path, the union of what its lanes need: a
+// node is entered when some lane's reach covers its box, and every lane tests
+// the faces of each leaf entered, keeping its own best under the same tie
+// rule. The node and face records are read at a wave-uniform index. The
+// stack holds one entry per level in one register across the lanes (entry k
+// in lane k).
+__device__ __forceinline__ int nearest_triangle_wave(const MeshView& M, V3 p, float& best, bool active) {
+  const int lane = __lane_id();
+  int stk = 0;
+  int sp = 0;
+  int bestf = -1;
+  int brank = 3;
+  best = INFINITY;
+  // inactive lanes never reach a box (box_d2 >= 0) and take no face
+  float reach = active ? INFINITY : -1.0f;
+  if (__builtin_amdgcn_ballot_w64(box_d2(M.nodes[0], M.nodes[1], p) < reach) == 0) return -1;
+  int node = 0;
+  for (;;) {
+    const float4 lo = M.nodes[2 * node], hi = M.nodes[2 * node + 1];
+    const int a = __float_as_int(lo.w), cnt = __float_as_int(hi.w);
+    if (cnt > 0) {
+      for (int f = a; f < a + cnt; ++f) {
+        const TriPoint t = closest_on_tri(ld3(M.tri[3 * f]), ld3(M.tri[3 * f + 1]), ld3(M.tri[3 * f + 2]), p);
+        const V3 d = p - t.x;
+        const float d2 = dot(d, d);
+        const int rank = t.feature == 0 ? 0 : (t.feature >= 4 ? 1 : 2);
+        const float band = kTieBand * best;
+        const bool take =
+            active && (rank < brank ? d2 <= best + band : (rank == brank ? d2 < best : d2 < best - band));
+        if (take) {
+          best = d2;
+          bestf = f;
+          brank = rank;
+          reach = fmaf(kTieBand, d2, d2);
+        }
+      }
+    } else {
+      const int l = node + 1, r = a;
+      const float dl = box_d2(M.nodes[2 * l], M.nodes[2 * l + 1], p);
+      const float dr = box_d2(M.nodes[2 * r], M.nodes[2 * r + 1], p);
+      const uint64_t bl = __builtin_amdgcn_ballot_w64(dl <= reach);
+      const uint64_t br = __builtin_amdgcn_ballot_w64(dr <= reach);
+      if (bl != 0 && br != 0) {
+        // nearer child first by the lanes' majority
+        const int nl = __builtin_popcountll(__builtin_amdgcn_ballot_w64(dl <= reach && dl <= dr));
+        const int nr = __builtin_popcountll(__builtin_amdgcn_ballot_w64(dr <= reach && dr < dl));
+        const bool left_first = nl >= nr;
+        stk = lane == sp ? (left_first ? r : l) : stk;
+        ++sp;
+        node = left_first ? l : r;
+        continue;
+      }
+      if (bl != 0 || br != 0) {
+        node = bl != 0 ? l : r;
+        continue;
+      }
+    }
+    bool found = false;
+    while (sp > 0) {
+      --sp;
+      node = __builtin_amdgcn_readlane(stk, sp);
+      if (__builtin_amdgcn_ballot_w64(box_d2(M.nodes[2 * node], M.nodes[2 * node + 1], p) <= reach) != 0) {
+        found = true;
+        break;
+      }
+    }
+    if (!found) break;
+  }
+  return bestf;
+}
+
 // Phong signed distance and its stated gradient at p.
-__device__ __forceinline__ void mesh_sdf(const MeshView& M, V3 p, float& rho, V3& g) {
-  float best;
-  const int f = nearest_triangle(M, p, best);
+// (mesh_sdf_face: the same given p's nearest face f from either walk.)
+__device__ __forceinline__ void mesh_sdf_face(const MeshView& M, int f, V3 p, float& rho, V3& g) {
   if (f < 0) {
     rho = __builtin_nanf("");
     g = v3(rho, rho, rho);
@@ -198,6 +270,11 @@ __device__ __forceinline__ void mesh_sdf(const MeshView& M, V3 p, float& rho, V3
   const float dist = sqrtf(dot(d, d));
   rho = s * dist;
   g = dist > 0.0f ? (1.0f / rho) * d : I3(3);
+}
+
+__device__ __forceinline__ void mesh_sdf(const MeshView& M, V3 p, float& rho, V3& g) {
+  float best;
+  mesh_sdf_face(M, nearest_triangle(M, p, best), p, rho, g);
 }
 
 // The Phong distance at a sample of the grasp step, with what its adjoint
@@ -318,6 +395,12 @@ __device__ __forceinline__ void mesh_sample_face(const MeshView& M, int f, V3 p,
 __device__ __forceinline__ void mesh_sample(const MeshView& M, V3 p, MeshSample& s) {
   float best;
   mesh_sample_face(M, nearest_triangle(M, p, best), p, s);
+}
+
+// mesh_sample through nearest_triangle_wave: every lane of the wave calls it.
+__device__ __forceinline__ void mesh_sample_wave(const MeshView& M, V3 p, MeshSample& s) {
+  float best;
+  mesh_sample_face(M, nearest_triangle_wave(M, p, best, true), p, s);
 }
 
 }  // namespace meshdev

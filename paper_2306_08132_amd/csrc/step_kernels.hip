@@ -438,10 +438,16 @@ __device__ void forward_mesh(const Ctx& c, bool first, float& lpen, float* trace
         const float db = sqrtf(meshdev::box_d2(c.M.nodes[0], c.M.nodes[1], r));
         query = c.face || !(fmaf(0.999999f, db, -c.M.bulge) - rd > 1e-6f);
       }
+      // the wave walks the hierarchy for all its lanes when one of them needs
+      // it, so that a lane's face does not depend on which others are culled
+      // (the adjoint's walk, without the face buffer, takes every lane)
+      int f = -1;
+      if (__builtin_amdgcn_ballot_w64(query) != 0) {
+        float best;
+        f = meshdev::nearest_triangle_wave(c.M, r, best, true);
+      }
       meshdev::MeshSample s;
       if (query) {
-        float best;
-        const int f = meshdev::nearest_triangle(c.M, r, best);
         if constexpr (!TRACE && !ROT) {
           // the adjoint takes the same face instead of walking again
           if (c.face && valid) c.face[lt.m * H.Nc + ch * kChunk + kGroup * g + lt.sub] = f;
@@ -680,7 +686,7 @@ __device__ void backward_mesh(const Ctx& c, bool first, float pen_seed, bool pos
         const int f = valid ? c.face[lt.m * H.Nc + ch * kChunk + kGroup * g + lt.sub] : 0;
         meshdev::mesh_sample_face(c.M, f, frame_pt(a), s);
       } else {
-        meshdev::mesh_sample(c.M, frame_pt(a), s);
+        meshdev::mesh_sample_wave(c.M, frame_pt(a), s);
       }
       const V3 gn = ROT ? mul(o.R, s.n) : s.n;
       const float d = s.rho - rd;
