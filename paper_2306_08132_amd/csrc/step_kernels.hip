@@ -1070,9 +1070,8 @@ __device__ void order_block(const float* q, int nd, int B, V3 centre, int* out) 
 
 // The step on a mesh object: one wave per candidate, the same per-candidate
 // code with the mesh's Phong distance sampled in place of the grid. The
-// hierarchy walk is latency-bound, so the one-iteration form is held to
-// 128 VGPRs for four waves per SIMD (8 bytes per lane spill; 415 -> 342 ms on
-// 4096 candidates of a 5120-face mesh).
+// hierarchy walk is latency-bound, so the one-iteration form asks for four
+// waves per SIMD (114 VGPRs, no spills; five, at 96 VGPRs, are slower).
 template <bool KONE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(KONE ? 4 : 3, 8)))
 k_step_mesh(StepArgs A, int kind, int adam) {
