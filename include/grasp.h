@@ -245,7 +245,8 @@ grasp_status grasp_evaluate(grasp_ctx* ctx, grasp_eval_id ev, grasp_sdf_id sdf, 
 
 /* The same metrics against a mesh object's Phong signed distance (Sec. III-B;
  * the mesh as loaded by grasp_load_mesh, at rest) instead of a grid: each
- * sample through the hierarchy query. Errors and layouts as grasp_evaluate. */
+ * sample through the hierarchy query, walked once per wave for 64 samples of
+ * one candidate. Errors and layouts as grasp_evaluate. */
 grasp_status grasp_evaluate_mesh(grasp_ctx* ctx, grasp_eval_id ev, grasp_mesh_id mesh, int32_t B, const float* q,
                                  int32_t n_thr, const float* thresholds, float* out, void* hip_stream);
 
@@ -354,7 +355,9 @@ grasp_status grasp_step_fused(grasp_ctx* ctx, grasp_hand_id hand, grasp_sdf_id s
  * reuses it; under stream capture or without room in the arena both passes
  * walk, and the forward skips a sample whose distance to the mesh's box, less
  * alpha times the longest edge, clears r_dil (it adds exactly nothing there).
- * The results are the same bits either way. The constraint normal is
+ * The results are the same bits either way. Each wave walks the hierarchy
+ * once for its 63 samples, all of one candidate, so a candidate's result
+ * depends on its own inputs only. The constraint normal is
  * (r - p) / rho the paper states and, in the adjoint, the exact derivative of
  * rho and of that normal through the closest point (face interior, edge or
  * vertex) and the Phong point. Arguments as grasp_step_fused, with the mesh
