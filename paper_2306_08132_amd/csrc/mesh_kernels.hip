@@ -1,7 +1,8 @@
 // The mesh object of Sec. III-B on gfx950: the Phong signed distance of a
 // closed triangle mesh, queried through a bounding-volume hierarchy.
 //
-// One lane per query point. The lane walks the hierarchy nearest child
+// One lane per query point (the grid fill: one wave per brick of grid
+// vertices, walking together). The lane walks the hierarchy nearest child
 // first with a private stack, pruning every box farther than the best
 // triangle so far; the closest point of a triangle comes from its Voronoi
 // regions (vertices, edges, interior). The sign is taken from the
@@ -49,18 +50,29 @@ __global__ void k_mesh_step_sample(MeshView M, int n, const float* __restrict__ 
   o[7] = static_cast<float>(s.region);
 }
 
-// The grid's vertex (i, j, k) at lo + (i, j, k) h gets rho there.
+// The grid's vertex (i, j, k) at lo + (i, j, k) h gets rho there. Each wave
+// takes a 4 x 4 x 4 brick of vertices (lane = di + 4 dj + 16 dk), whose 64
+// points walk the hierarchy together; lanes past the grid's edge only ride
+// along.
 __global__ void k_mesh_fill_grid(MeshView M, int n, float lox, float loy, float loz, float h,
                                  float* __restrict__ values) {
-  const long long id = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long long total = static_cast<long long>(n) * n * n;
-  if (id >= total) return;
-  const int i = static_cast<int>(id % n), j = static_cast<int>((id / n) % n), k = static_cast<int>(id / (static_cast<long long>(n) * n));
+  const int nb = (n + 3) / 4;
+  const long long brick = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  if (brick >= static_cast<long long>(nb) * nb * nb) return;  // whole waves
+  const int lane = static_cast<int>(threadIdx.x) % kWave;
+  const int i = 4 * static_cast<int>(brick % nb) + (lane & 3);
+  const int j = 4 * static_cast<int>((brick / nb) % nb) + ((lane >> 2) & 3);
+  const int k = 4 * static_cast<int>(brick / (static_cast<long long>(nb) * nb)) + (lane >> 4);
+  const bool in = i < n && j < n && k < n;
+  const V3 p = v3(fmaf(static_cast<float>(i), h, lox), fmaf(static_cast<float>(j), h, loy),
+                  fmaf(static_cast<float>(k), h, loz));
+  float best;
+  const int f = nearest_triangle_wave(M, p, best, in);
+  if (!in) return;
   float rho;
   V3 g;
-  mesh_sdf(M, v3(fmaf(static_cast<float>(i), h, lox), fmaf(static_cast<float>(j), h, loy),
-                 fmaf(static_cast<float>(k), h, loz)), rho, g);
-  values[id] = rho;
+  mesh_sdf_face(M, f, p, rho, g);
+  values[(static_cast<long long>(k) * n + j) * n + i] = rho;
 }
 
 }  // namespace
@@ -79,8 +91,9 @@ hipError_t launch_mesh_step_sample(const MeshView& M, int n, const float* r, flo
 
 hipError_t launch_mesh_fill_grid(const MeshView& M, int n, const float lo[3], float h, float* values,
                                  hipStream_t stream) {
-  const long long total = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(k_mesh_fill_grid, dim3(static_cast<unsigned>((total + 127) / 128)), dim3(128), 0, stream, M,
+  // one wave per 4^3 brick, two waves per workgroup
+  const long long nb = (n + 3) / 4, waves = nb * nb * nb;
+  hipLaunchKernelGGL(k_mesh_fill_grid, dim3(static_cast<unsigned>((waves + 1) / 2)), dim3(2 * kWave), 0, stream, M,
                      n, lo[0], lo[1], lo[2], h, values);
   return hipGetLastError();
 }

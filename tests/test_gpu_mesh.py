@@ -142,7 +142,7 @@ def test_grid_from_mesh_and_step(ctx):
     from paper_2306_08132_amd.api import StepParams
     m = f32mesh(S.mesh_ellipsoid([0.035, 0.025, 0.03], subdivisions=3))
     alpha = float(np.float32(0.75))
-    n = 48
+    n = 50  # 4^3 bricks of the fill with a ragged edge
     lo = np.float32([-0.06, -0.06, -0.06]).astype(np.float64)
     h = float(np.float32(0.12 / (n - 1)))
     gm = ctx.mesh(m, alpha)
