@@ -173,7 +173,8 @@ __device__ __forceinline__ int nearest_triangle(const MeshView& M, V3 p, float& 
 // the faces of each leaf entered, keeping its own best under the same tie
 // rule. The node and face records are read at a wave-uniform index. The
 // stack holds one entry per level in one register across the lanes (entry k
-// in lane k).
+// in lane k): the loader keeps the depth below kMeshStack, which fits a wave.
+static_assert(kMeshStack <= kWave, "the wave's stack has one entry per lane");
 __device__ __forceinline__ int nearest_triangle_wave(const MeshView& M, V3 p, float& best, bool active) {
   const int lane = __lane_id();
   int stk = 0;
