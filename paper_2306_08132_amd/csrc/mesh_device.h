@@ -182,9 +182,12 @@ __device__ __forceinline__ int nearest_triangle_wave(const MeshView& M, V3 p, fl
   int bestf = -1;
   int brank = 3;
   best = INFINITY;
-  // inactive lanes never reach a box (box_d2 >= 0) and take no face
-  float reach = active ? INFINITY : -1.0f;
-  if (__builtin_amdgcn_ballot_w64(box_d2(M.nodes[0], M.nodes[1], p) < reach) == 0) return -1;
+  // as in nearest_triangle, a point whose distance to the root box is not
+  // below infinity (not finite, or too far for FP32) gets -1; such lanes and
+  // the inactive ones never reach a box (box_d2 >= 0) and take no face
+  const bool live = active && box_d2(M.nodes[0], M.nodes[1], p) < INFINITY;
+  float reach = live ? INFINITY : -1.0f;
+  if (__builtin_amdgcn_ballot_w64(live) == 0) return -1;
   int node = 0;
   for (;;) {
     const float4 lo = M.nodes[2 * node], hi = M.nodes[2 * node + 1];
@@ -197,7 +200,7 @@ __device__ __forceinline__ int nearest_triangle_wave(const MeshView& M, V3 p, fl
         const int rank = t.feature == 0 ? 0 : (t.feature >= 4 ? 1 : 2);
         const float band = kTieBand * best;
         const bool take =
-            active && (rank < brank ? d2 <= best + band : (rank == brank ? d2 < best : d2 < best - band));
+            live && (rank < brank ? d2 <= best + band : (rank == brank ? d2 < best : d2 < best - band));
         if (take) {
           best = d2;
           bestf = f;
