@@ -157,6 +157,14 @@ def test_grid_from_mesh_and_step(ctx):
     say(f"grid from mesh: max err {err.max():.2e}, off the flat surface {err[~near].max():.2e}, "
         f"on it {near.sum()} of {near.size}")
     assert np.all(err <= 1e-5 * np.maximum(np.abs(want), h) + gap + np.where(near, 2.0 * np.abs(want), 0.0))
+    # the fill walks the hierarchy once per 4^3 brick of vertices, the point
+    # query once per point: at the vertices they agree up to the grid's own
+    # interpolation rounding and faces tied within FP32 (either sign on the
+    # flat surface)
+    lane = gm.sample(r).cpu().numpy()[:, 0].astype(np.float64)
+    dl = np.abs(got - lane)
+    say(f"fill against the point query: max diff {dl.max():.2e}, bit-equal {np.mean(dl == 0):.4f}")
+    assert np.all(dl <= 4e-6 * np.maximum(np.abs(lane), h) + np.where(near, 2.0 * np.abs(lane), 0.0))
     # a step on each side's own grid
     hand, _, q = S.config_workload("tiny")
     hd = ctx.hand(hand)
